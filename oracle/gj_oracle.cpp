@@ -1,0 +1,581 @@
+// CPU oracle for Generic Join subgraph queries -- TEST INFRASTRUCTURE ONLY.
+//
+// A plain, slow, obviously-correct implementation of what the GPU library
+// computes.  Only the test suite, the smoke check and the CPU-baseline leg of
+// the benchmark may load it; the GPU library never does.  It shares no code,
+// headers or tables with the GPU library.
+//
+// Paper: Ammar, McSherry, Salihoglu, Joglekar, "Distributed Evaluation of
+// Subgraph Queries Using Worst-case Optimal Low-Memory Dataflows" (VLDB 2018).
+//
+//  * A subgraph query is a multiway self-join of the edge relation: one
+//    attribute per query vertex, one atom edge(a_i, a_j) per query edge
+//    (Sec. 1.1; Sec. 2.1 notation).  Join semantics: a match is any tuple of
+//    vertices that satisfies every atom (no distinctness requirement).
+//  * Generic Join (Sec. 2.2, Fig. 1): attributes are bound one at a time in a
+//    global order; a prefix is extended by the values present in every
+//    extension set Ext^i_j(p) of the relations that bind the next attribute,
+//    proposing from the smallest set and checking the proposals against the
+//    others.
+//  * The evaluated implementation seeds P_2 from the edges of an atom over the
+//    first two attributes (Sec. 4.2) and runs count-minimisation, proposal and
+//    intersection per stage (Sec. 3.1, Sec. 4.1); extension sets are the
+//    out- and in-neighbour lists (forward and reverse indices, Sec. 4.1).
+//  * Delta-GJ (Sec. 3.3.1): dQ_i = R'_1..R'_{i-1}, dR_i, R_{i+1}..R_n, each
+//    ordered starting with R_i's attributes; the signed union of the dQ_i is
+//    the change of the output.
+//
+// Readings where the paper is silent (each is listed with its reason in the
+// design notes): count-minimisation ties go to the lowest atom index; the
+// remaining attributes of dQ_i follow the global order, taking next the
+// earliest attribute that shares an atom with a bound one; update batches drop
+// self-loops, collapse repeats, ignore no-op operations and reject a batch
+// that inserts and deletes one edge; output rows are in attribute-index order,
+// sorted ascending as unsigned tuples.
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <map>
+#include <set>
+#include <thread>
+#include <utility>
+#include <vector>
+
+namespace {
+
+constexpr int kMaxAttrs = 8;
+constexpr int kMaxAtoms = 16;
+
+enum { OR_OK = 0, OR_EINVAL = 1, OR_EOVERFLOW = 4 };
+
+// Edge relation held as per-vertex sorted neighbour vectors (out and in).
+struct Graph {
+  uint32_t n = 0;
+  std::vector<std::vector<uint32_t>> out, in;
+  // the edge set in (src, dst) order and in (dst, src) order; position in
+  // these is the "edge index" of the forward / reverse direction
+  std::vector<std::pair<uint32_t, uint32_t>> fwd_edges, rev_edges;
+  uint64_t noop_inserts = 0, noop_deletes = 0, dropped_loops = 0;
+
+  bool has(uint32_t u, uint32_t v) const {
+    const auto& l = out[u];
+    return std::binary_search(l.begin(), l.end(), v);
+  }
+  void rebuild_lists(const std::set<std::pair<uint32_t, uint32_t>>& s) {
+    out.assign(n, {});
+    in.assign(n, {});
+    fwd_edges.assign(s.begin(), s.end());
+    rev_edges.clear();
+    for (auto& e : s) {
+      out[e.first].push_back(e.second);
+      in[e.second].push_back(e.first);
+      rev_edges.push_back({e.second, e.first});
+    }
+    for (auto& l : out) std::sort(l.begin(), l.end());
+    for (auto& l : in) std::sort(l.begin(), l.end());
+    std::sort(rev_edges.begin(), rev_edges.end());
+  }
+};
+
+struct Atom {
+  int s, d;
+};
+
+struct Query {
+  int m = 0;
+  std::vector<Atom> atoms;
+  std::vector<int> order;  // order[j] = attribute bound at position j
+};
+
+// An extension set reference: the neighbour list of the value in prefix
+// column `col`, outgoing (`out_dir`) or incoming, in the old or new version.
+struct Binding {
+  int atom;
+  int col;
+  bool out_dir;
+};
+
+bool valid_query(const Query& q) {
+  if (q.m < 2 || q.m > kMaxAttrs) return false;
+  if (q.atoms.empty() || (int)q.atoms.size() > kMaxAtoms) return false;
+  if ((int)q.order.size() != q.m) return false;
+  std::vector<int> seen(q.m, 0);
+  for (int a : q.order) {
+    if (a < 0 || a >= q.m || seen[a]) return false;
+    seen[a] = 1;
+  }
+  for (auto& at : q.atoms) {
+    if (at.s < 0 || at.s >= q.m || at.d < 0 || at.d >= q.m) return false;
+    if (at.s == at.d) return false;
+  }
+  std::vector<int> pos(q.m);
+  for (int j = 0; j < q.m; ++j) pos[q.order[j]] = j;
+  // the first two attributes must share an atom (P_2 is seeded from edges)
+  bool seed = false;
+  for (auto& at : q.atoms)
+    if (std::max(pos[at.s], pos[at.d]) == 1) seed = true;
+  if (!seed) return false;
+  // every later attribute needs an atom to an earlier one
+  for (int j = 2; j < q.m; ++j) {
+    bool any = false;
+    for (auto& at : q.atoms)
+      if (std::max(pos[at.s], pos[at.d]) == j) any = true;
+    if (!any) return false;
+  }
+  return true;
+}
+
+// Per-query plan derived from the order: the seed atom (lowest index over the
+// first two attributes), filter atoms over the same two, and for every later
+// position j the atoms binding order[j] with their bound column.
+struct Plan {
+  int seed_atom = -1;
+  bool seed_fwd = true;  // P_2 = (u, v) with u -> v (true) or v -> u (false)
+  std::vector<int> filters;
+  std::vector<std::vector<Binding>> bind;  // bind[j], j = 2..m-1
+};
+
+Plan make_plan(const Query& q) {
+  Plan p;
+  std::vector<int> pos(q.m);
+  for (int j = 0; j < q.m; ++j) pos[q.order[j]] = j;
+  for (int i = 0; i < (int)q.atoms.size(); ++i) {
+    const Atom& at = q.atoms[i];
+    if (std::max(pos[at.s], pos[at.d]) == 1) {
+      if (p.seed_atom < 0) {
+        p.seed_atom = i;
+        p.seed_fwd = pos[at.s] == 0;
+      } else {
+        p.filters.push_back(i);
+      }
+    }
+  }
+  p.bind.assign(q.m, {});
+  for (int i = 0; i < (int)q.atoms.size(); ++i) {
+    const Atom& at = q.atoms[i];
+    int j = std::max(pos[at.s], pos[at.d]);
+    if (j < 2) continue;
+    // the atom binds attribute order[j]; its other end is already bound
+    if (pos[at.d] == j)  // edge(y, x): x ranges over out(y)
+      p.bind[j].push_back({i, pos[at.s], true});
+    else  // edge(x, y): x ranges over in(y)
+      p.bind[j].push_back({i, pos[at.d], false});
+  }
+  return p;
+}
+
+// Which version of the relation an atom reads: for delta query dQ_i, atoms
+// before i read the new graph, atoms after i the old one (Sec. 3.3.1).
+struct Views {
+  const Graph* g_old;
+  const Graph* g_new;
+  int delta_atom;  // -1: every atom reads g_old
+  const Graph& of(int atom) const {
+    return (delta_atom >= 0 && atom < delta_atom) ? *g_new : *g_old;
+  }
+};
+
+const std::vector<uint32_t>& ext_list(const Views& v, const Binding& b,
+                                      uint32_t key) {
+  const Graph& g = v.of(b.atom);
+  return b.out_dir ? g.out[key] : g.in[key];
+}
+
+struct Counters {
+  uint64_t prefixes[kMaxAttrs + 1] = {0};
+  uint64_t extensions[kMaxAttrs + 1] = {0};
+  uint64_t matches = 0;
+  bool overflow = false;
+  void add(uint64_t& slot, uint64_t x) {
+    if (__builtin_add_overflow(slot, x, &slot)) overflow = true;
+  }
+  void merge(const Counters& o) {
+    for (int j = 0; j <= kMaxAttrs; ++j) {
+      add(prefixes[j], o.prefixes[j]);
+      add(extensions[j], o.extensions[j]);
+    }
+    add(matches, o.matches);
+    overflow = overflow || o.overflow;
+  }
+};
+
+// Extends one prefix (in position order) through stages j..m-1, depth first.
+// Count-minimisation picks the smallest extension set (ties: lowest atom
+// index), proposes its values in ascending order and keeps a value only if
+// every other binding set contains it (Sec. 3.1 steps; Sec. 4.1 operators).
+void extend(const Query& q, const Plan& plan, const Views& views, int j,
+            std::vector<uint32_t>& prefix, Counters& c, bool collect,
+            std::vector<uint32_t>& rows) {
+  c.add(c.prefixes[j], 1);
+  if (j == q.m) {
+    c.add(c.matches, 1);
+    if (collect) {
+      // store in attribute-index order
+      uint32_t row[kMaxAttrs];
+      for (int k = 0; k < q.m; ++k) row[q.order[k]] = prefix[k];
+      rows.insert(rows.end(), row, row + q.m);
+    }
+    return;
+  }
+  const std::vector<Binding>& B = plan.bind[j];
+  size_t best = 0;
+  for (size_t i = 1; i < B.size(); ++i) {
+    size_t ci = ext_list(views, B[i], prefix[B[i].col]).size();
+    size_t cb = ext_list(views, B[best], prefix[B[best].col]).size();
+    if (ci < cb) best = i;  // strict: ties keep the lower atom
+  }
+  const std::vector<uint32_t>& prop = ext_list(views, B[best], prefix[B[best].col]);
+  c.add(c.extensions[j], prop.size());
+  for (uint32_t e : prop) {
+    bool keep = true;
+    for (size_t i = 0; i < B.size() && keep; ++i) {
+      if (i == best) continue;
+      const std::vector<uint32_t>& l = ext_list(views, B[i], prefix[B[i].col]);
+      keep = std::binary_search(l.begin(), l.end(), e);
+    }
+    if (!keep) continue;
+    prefix.push_back(e);
+    extend(q, plan, views, j + 1, prefix, c, collect, rows);
+    prefix.pop_back();
+  }
+}
+
+// Does seed pair (x0, x1) (values of order[0], order[1]) satisfy atom i?
+bool pair_ok(const Query& q, const Views& v, int atom, uint32_t x0, uint32_t x1) {
+  const Atom& at = q.atoms[atom];
+  uint32_t s = at.s == q.order[0] ? x0 : x1;
+  uint32_t d = at.s == q.order[0] ? x1 : x0;
+  return v.of(atom).has(s, d);
+}
+
+// Runs the edge-seeded Generic Join on seed edges [lo, hi) of the seed
+// atom's edge list, in the seed atom's version.
+void run_seeds(const Query& q, const Plan& plan, const Views& views,
+               uint64_t lo, uint64_t hi, Counters& c, bool collect,
+               std::vector<uint32_t>& rows) {
+  const Graph& g = views.of(plan.seed_atom);
+  const auto& E = plan.seed_fwd ? g.fwd_edges : g.rev_edges;
+  std::vector<uint32_t> prefix;
+  prefix.reserve(q.m);
+  for (uint64_t k = lo; k < hi && k < E.size(); ++k) {
+    uint32_t x0 = E[k].first, x1 = E[k].second;
+    bool ok = true;
+    for (int f : plan.filters) ok = ok && pair_ok(q, views, f, x0, x1);
+    if (!ok) continue;
+    prefix.assign({x0, x1});
+    extend(q, plan, views, 2, prefix, c, collect, rows);
+  }
+}
+
+void sort_rows(std::vector<uint32_t>& rows, int m) {
+  size_t n = rows.size() / m;
+  std::vector<std::vector<uint32_t>> t(n);
+  for (size_t i = 0; i < n; ++i) t[i].assign(rows.begin() + i * m, rows.begin() + (i + 1) * m);
+  std::sort(t.begin(), t.end());
+  for (size_t i = 0; i < n; ++i) std::copy(t[i].begin(), t[i].end(), rows.begin() + i * m);
+}
+
+struct Result {
+  int m = 0;
+  Counters c;
+  std::vector<uint32_t> rows;   // attribute-index order, sorted
+  std::vector<int8_t> signs;    // delta results only
+  int64_t count_delta = 0;
+  uint64_t raw_emissions = 0;   // delta: signed outputs before consolidation
+};
+
+bool parse_query(int num_attrs, const uint8_t* as, const uint8_t* ad, int num_atoms,
+                 const uint8_t* order, Query& q) {
+  if (num_attrs < 0 || num_attrs > kMaxAttrs || num_atoms < 0 || num_atoms > kMaxAtoms)
+    return false;
+  q.m = num_attrs;
+  q.atoms.clear();
+  for (int i = 0; i < num_atoms; ++i) q.atoms.push_back({as[i], ad[i]});
+  q.order.assign(order, order + num_attrs);
+  return valid_query(q);
+}
+
+// Order of dQ_i: the atom's (src, dst), then repeatedly the earliest attribute
+// in the global order that shares an atom with an already-bound attribute.
+std::vector<int> delta_order(const Query& q, int i) {
+  std::vector<int> ord = {q.atoms[i].s, q.atoms[i].d};
+  std::vector<int> bound(q.m, 0);
+  bound[ord[0]] = bound[ord[1]] = 1;
+  while ((int)ord.size() < q.m) {
+    int pick = -1;
+    for (int a : q.order) {
+      if (bound[a]) continue;
+      bool adj = false;
+      for (auto& at : q.atoms)
+        if ((at.s == a && bound[at.d]) || (at.d == a && bound[at.s])) adj = true;
+      if (adj) { pick = a; break; }
+    }
+    if (pick < 0) return {};
+    ord.push_back(pick);
+    bound[pick] = 1;
+  }
+  return ord;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Graph: drops self-loops and repeated edges.  Vertex ids must be < n.
+void* or_graph_new(uint32_t n, const uint32_t* src, const uint32_t* dst, uint64_t m) {
+  std::set<std::pair<uint32_t, uint32_t>> s;
+  Graph* g = new Graph();
+  g->n = n;
+  for (uint64_t i = 0; i < m; ++i) {
+    if (src[i] >= n || dst[i] >= n) { delete g; return nullptr; }
+    if (src[i] == dst[i]) { ++g->dropped_loops; continue; }
+    s.insert({src[i], dst[i]});
+  }
+  g->rebuild_lists(s);
+  return g;
+}
+
+void* or_graph_copy(const void* g) { return new Graph(*(const Graph*)g); }
+void or_graph_free(void* g) { delete (Graph*)g; }
+uint64_t or_graph_edges(const void* g) { return ((const Graph*)g)->fwd_edges.size(); }
+uint32_t or_graph_vertices(const void* g) { return ((const Graph*)g)->n; }
+void or_graph_edge_list(const void* gp, uint32_t* src, uint32_t* dst) {
+  const Graph* g = (const Graph*)gp;
+  for (size_t i = 0; i < g->fwd_edges.size(); ++i) {
+    src[i] = g->fwd_edges[i].first;
+    dst[i] = g->fwd_edges[i].second;
+  }
+}
+
+int or_query_valid(int num_attrs, const uint8_t* as, const uint8_t* ad, int num_atoms,
+                   const uint8_t* order) {
+  Query q;
+  return parse_query(num_attrs, as, ad, num_atoms, order, q) ? 1 : 0;
+}
+
+// Edge-seeded Generic Join over seed edges [seed_lo, seed_hi) of the seed
+// atom (clamped to the edge count).  collect != 0 keeps the matching rows.
+// Seeds are split over `threads` std::threads in contiguous chunks; the
+// result does not depend on the thread count.
+void* or_run(const void* gp, int num_attrs, const uint8_t* as, const uint8_t* ad,
+             int num_atoms, const uint8_t* order, int collect, uint64_t seed_lo,
+             uint64_t seed_hi, int threads, int* status) {
+  const Graph* g = (const Graph*)gp;
+  Query q;
+  if (!parse_query(num_attrs, as, ad, num_atoms, order, q)) {
+    *status = OR_EINVAL;
+    return nullptr;
+  }
+  Plan plan = make_plan(q);
+  Views views{g, g, -1};
+  const auto& E = plan.seed_fwd ? g->fwd_edges : g->rev_edges;
+  uint64_t hi = std::min<uint64_t>(seed_hi, E.size());
+  uint64_t lo = std::min<uint64_t>(seed_lo, hi);
+  if (threads < 1) threads = 1;
+  uint64_t span = hi - lo;
+  if ((uint64_t)threads > span) threads = span ? (int)span : 1;
+  std::vector<Counters> cs(threads);
+  std::vector<std::vector<uint32_t>> rs(threads);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < threads; ++t) {
+    uint64_t a = lo + span * t / threads, b = lo + span * (t + 1) / threads;
+    pool.emplace_back([&, t, a, b] { run_seeds(q, plan, views, a, b, cs[t], collect != 0, rs[t]); });
+  }
+  for (auto& th : pool) th.join();
+  Result* r = new Result();
+  r->m = q.m;
+  for (int t = 0; t < threads; ++t) {
+    r->c.merge(cs[t]);
+    r->rows.insert(r->rows.end(), rs[t].begin(), rs[t].end());
+  }
+  // P_2 counts seeds that passed the filters; prefixes[m] == matches
+  if (collect) sort_rows(r->rows, q.m);
+  *status = r->c.overflow ? OR_EOVERFLOW : OR_OK;
+  return r;
+}
+
+// Textbook Generic Join (Fig. 1): starts from P_0 = {()}; an atom whose other
+// attribute is not yet bound contributes the projection of the relation on
+// the new attribute ({v : out(v) nonempty} or {v : in(v) nonempty}).
+// Returns every P_j, j = 1..m, concatenated (position order); sizes[j] = |P_j|.
+void* or_run_textbook(const void* gp, int num_attrs, const uint8_t* as, const uint8_t* ad,
+                      int num_atoms, const uint8_t* order, uint64_t* sizes, int* status) {
+  const Graph* g = (const Graph*)gp;
+  Query q;
+  q.m = num_attrs;
+  for (int i = 0; i < num_atoms; ++i) q.atoms.push_back({as[i], ad[i]});
+  q.order.assign(order, order + num_attrs);
+  if (num_attrs < 1 || num_attrs > kMaxAttrs) { *status = OR_EINVAL; return nullptr; }
+  std::vector<int> pos(q.m);
+  for (int j = 0; j < q.m; ++j) pos[q.order[j]] = j;
+  std::vector<uint32_t> has_out, has_in;
+  for (uint32_t v = 0; v < g->n; ++v) {
+    if (!g->out[v].empty()) has_out.push_back(v);
+    if (!g->in[v].empty()) has_in.push_back(v);
+  }
+  Result* r = new Result();
+  r->m = q.m;
+  std::vector<std::vector<uint32_t>> P = {{}};  // P_0 = {()}
+  for (int j = 0; j < q.m; ++j) {
+    int x = q.order[j];
+    std::vector<std::vector<uint32_t>> next;
+    for (auto& p : P) {
+      std::vector<const std::vector<uint32_t>*> sets;
+      for (auto& at : q.atoms) {
+        if (at.s == x && at.d != x) {
+          if (pos[at.d] < j) sets.push_back(&g->in[p[pos[at.d]]]);
+          else sets.push_back(&has_out);
+        } else if (at.d == x && at.s != x) {
+          if (pos[at.s] < j) sets.push_back(&g->out[p[pos[at.s]]]);
+          else sets.push_back(&has_in);
+        }
+      }
+      if (sets.empty()) { *status = OR_EINVAL; delete r; return nullptr; }
+      size_t best = 0;
+      for (size_t i = 1; i < sets.size(); ++i)
+        if (sets[i]->size() < sets[best]->size()) best = i;
+      for (uint32_t e : *sets[best]) {
+        bool keep = true;
+        for (size_t i = 0; i < sets.size() && keep; ++i)
+          if (i != best) keep = std::binary_search(sets[i]->begin(), sets[i]->end(), e);
+        if (!keep) continue;
+        auto np = p;
+        np.push_back(e);
+        next.push_back(np);
+      }
+    }
+    P.swap(next);
+    sizes[j + 1] = P.size();
+    for (auto& p : P) r->rows.insert(r->rows.end(), p.begin(), p.end());
+  }
+  *status = OR_OK;
+  return r;
+}
+
+// Applies a signed update batch to the graph (in place) and returns, for the
+// given query, the consolidated change of its output (Delta-GJ, Sec. 3.3.1).
+// Normalisation: self-loops dropped, repeated rows collapse, an insertion of
+// a present edge and a deletion of an absent edge are no-ops (counted); a
+// batch that both inserts and deletes one edge is rejected (status EINVAL,
+// graph unchanged).  Pass num_atoms = 0 to only apply the batch.
+void* or_delta(void* gp, const uint32_t* src, const uint32_t* dst, const int8_t* sign,
+               uint64_t b, int num_attrs, const uint8_t* as, const uint8_t* ad,
+               int num_atoms, const uint8_t* order, int* status) {
+  Graph* g = (Graph*)gp;
+  Query q;
+  bool have_query = num_atoms > 0;
+  if (have_query && !parse_query(num_attrs, as, ad, num_atoms, order, q)) {
+    *status = OR_EINVAL;
+    return nullptr;
+  }
+  std::set<std::pair<uint32_t, uint32_t>> ins, del;
+  for (uint64_t i = 0; i < b; ++i) {
+    if (src[i] >= g->n || dst[i] >= g->n || (sign[i] != 1 && sign[i] != -1)) {
+      *status = OR_EINVAL;
+      return nullptr;
+    }
+    if (src[i] == dst[i]) continue;
+    (sign[i] > 0 ? ins : del).insert({src[i], dst[i]});
+  }
+  for (auto& e : ins)
+    if (del.count(e)) { *status = OR_EINVAL; return nullptr; }
+  // the signed change dE: inserted edges absent before, deleted edges present
+  std::vector<std::pair<std::pair<uint32_t, uint32_t>, int>> dE;
+  uint64_t noop_i = 0, noop_d = 0;
+  for (auto& e : ins) {
+    if (g->has(e.first, e.second)) ++noop_i;
+    else dE.push_back({e, +1});
+  }
+  for (auto& e : del) {
+    if (!g->has(e.first, e.second)) ++noop_d;
+    else dE.push_back({e, -1});
+  }
+  std::set<std::pair<uint32_t, uint32_t>> s(g->fwd_edges.begin(), g->fwd_edges.end());
+  for (auto& x : dE) {
+    if (x.second > 0) s.insert(x.first);
+    else s.erase(x.first);
+  }
+  Graph g_new;
+  g_new.n = g->n;
+  g_new.rebuild_lists(s);
+  Result* r = new Result();
+  r->m = q.m;
+  if (have_query) {
+    std::map<std::vector<uint32_t>, int64_t> acc;
+    for (int i = 0; i < (int)q.atoms.size(); ++i) {
+      Query qi = q;
+      qi.order = delta_order(q, i);
+      if ((int)qi.order.size() != q.m) { *status = OR_EINVAL; delete r; return nullptr; }
+      Plan plan = make_plan(qi);
+      // the seed atom of dQ_i must be atom i itself: other atoms over the
+      // same two attributes become filters in their own version
+      plan.filters.clear();
+      for (int k = 0; k < (int)q.atoms.size(); ++k) {
+        if (k == i) continue;
+        const Atom& at = q.atoms[k];
+        bool same = (at.s == q.atoms[i].s && at.d == q.atoms[i].d) ||
+                    (at.s == q.atoms[i].d && at.d == q.atoms[i].s);
+        if (same) plan.filters.push_back(k);
+      }
+      plan.seed_atom = i;
+      plan.seed_fwd = true;
+      Views views{g, &g_new, i};
+      for (auto& x : dE) {
+        uint32_t x0 = x.first.first, x1 = x.first.second;
+        bool ok = true;
+        for (int f : plan.filters) ok = ok && pair_ok(qi, views, f, x0, x1);
+        if (!ok) continue;
+        std::vector<uint32_t> prefix = {x0, x1}, rows;
+        Counters c;
+        extend(qi, plan, views, 2, prefix, c, true, rows);
+        r->c.merge(c);
+        for (size_t k = 0; k + q.m <= rows.size(); k += q.m) {
+          std::vector<uint32_t> t(rows.begin() + k, rows.begin() + k + q.m);
+          acc[t] += x.second;
+          ++r->raw_emissions;
+        }
+      }
+    }
+    for (auto& kv : acc) {
+      if (kv.second == 0) continue;
+      r->rows.insert(r->rows.end(), kv.first.begin(), kv.first.end());
+      r->signs.push_back((int8_t)kv.second);
+      r->count_delta += kv.second;
+    }
+  }
+  g->rebuild_lists(s);
+  g->noop_inserts += noop_i;
+  g->noop_deletes += noop_d;
+  *status = OR_OK;
+  return r;
+}
+
+uint64_t or_result_matches(const void* r) { return ((const Result*)r)->c.matches; }
+void or_result_counters(const void* rp, uint64_t* prefixes, uint64_t* extensions) {
+  const Result* r = (const Result*)rp;
+  for (int j = 0; j <= kMaxAttrs; ++j) {
+    prefixes[j] = r->c.prefixes[j];
+    extensions[j] = r->c.extensions[j];
+  }
+}
+uint64_t or_result_num_rows(const void* r) {
+  const Result* x = (const Result*)r;
+  return x->m ? x->rows.size() / x->m : 0;
+}
+void or_result_rows(const void* r, uint32_t* out) {
+  const Result* x = (const Result*)r;
+  std::copy(x->rows.begin(), x->rows.end(), out);
+}
+void or_result_signs(const void* r, int8_t* out) {
+  const Result* x = (const Result*)r;
+  std::copy(x->signs.begin(), x->signs.end(), out);
+}
+int64_t or_result_count_delta(const void* r) { return ((const Result*)r)->count_delta; }
+uint64_t or_result_raw_emissions(const void* r) { return ((const Result*)r)->raw_emissions; }
+void or_graph_noops(const void* gp, uint64_t* ins, uint64_t* del) {
+  *ins = ((const Graph*)gp)->noop_inserts;
+  *del = ((const Graph*)gp)->noop_deletes;
+}
+void or_result_free(void* r) { delete (Result*)r; }
+
+}  // extern "C"

@@ -1,0 +1,27 @@
+"""Brute-force subgraph matching by the definition: every vertex tuple that
+satisfies every atom (join semantics).  Independent of the oracle: numpy over
+all n^m tuples, for tiny graphs only."""
+import numpy as np
+
+
+def adjacency(n, src, dst):
+    A = np.zeros((n, n), dtype=bool)
+    src = np.asarray(src, dtype=np.int64)
+    dst = np.asarray(dst, dtype=np.int64)
+    keep = src != dst
+    A[src[keep], dst[keep]] = True
+    return A
+
+
+def matches(A, query):
+    m, atoms, _ = query
+    n = A.shape[0]
+    T = np.indices((n,) * m).reshape(m, -1)  # lexicographic order
+    ok = np.ones(T.shape[1], dtype=bool)
+    for s, d in atoms:
+        ok &= A[T[s], T[d]]
+    return T[:, ok].T.astype(np.uint32)
+
+
+def as_set(rows):
+    return set(map(tuple, np.asarray(rows).tolist()))

@@ -1,0 +1,56 @@
+"""Subgraph queries used by the tests: (num_attrs, atoms, global order).
+
+An atom (s, d) is edge(a_s, a_d).  Attributes are 0-based (a1 -> 0).
+"""
+# transitive triangle e(a1,a2), e(a2,a3), e(a1,a3)   (evaluation query list, Sec. 5)
+TRIANGLE = (3, [(0, 1), (1, 2), (0, 2)], [0, 1, 2])
+# cyclic triangle e(a1,a2), e(a2,a3), e(a3,a1)        (Sec. 1.1, Appendix A)
+CYCLIC_TRIANGLE = (3, [(0, 1), (1, 2), (2, 0)], [0, 1, 2])
+# 4-clique: all six pairs i < j                        (evaluation query list, Sec. 5)
+CLIQUE4 = (4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)], [0, 1, 2, 3])
+# diamond as two 2-paths a1->a2->a4, a1->a3->a4
+DIAMOND = (4, [(0, 1), (0, 2), (1, 3), (2, 3)], [0, 1, 2, 3])
+# diamond as printed in the evaluation query list: e(a1,a2), e(a2,a3), e(a4,a1), e(a4,a3)
+PAPER_DIAMOND = (4, [(0, 1), (1, 2), (3, 0), (3, 2)], [0, 1, 2, 3])
+# directed 4-cycle a1->a2->a3->a4->a1
+CYCLE4 = (4, [(0, 1), (1, 2), (2, 3), (3, 0)], [0, 1, 2, 3])
+# house (evaluation query list, Sec. 5)
+HOUSE = (5, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3), (1, 4), (2, 4)],
+         [0, 1, 2, 3, 4])
+# 5-clique
+CLIQUE5 = (5, [(i, j) for i in range(5) for j in range(i + 1, 5)], [0, 1, 2, 3, 4])
+# a query with a second atom over the first two attributes (a P_2 filter):
+# reciprocal pair a1<->a2 closed by a3
+RECIPROCAL = (3, [(0, 1), (1, 0), (1, 2), (2, 0)], [0, 1, 2])
+
+ALL = {
+    "triangle": TRIANGLE,
+    "cyclic_triangle": CYCLIC_TRIANGLE,
+    "clique4": CLIQUE4,
+    "diamond": DIAMOND,
+    "paper_diamond": PAPER_DIAMOND,
+    "cycle4": CYCLE4,
+    "house": HOUSE,
+    "clique5": CLIQUE5,
+    "reciprocal": RECIPROCAL,
+}
+
+
+def with_order(q, order):
+    return (q[0], q[1], list(order))
+
+
+def valid_orders(q):
+    """Every global order whose first two attributes share an atom and whose
+    later attributes each have an atom to an earlier one."""
+    import itertools
+    m, atoms, _ = q
+    out = []
+    for perm in itertools.permutations(range(m)):
+        pos = {a: i for i, a in enumerate(perm)}
+        ok = any(max(pos[s], pos[d]) == 1 for s, d in atoms)
+        for j in range(2, m):
+            ok = ok and any(max(pos[s], pos[d]) == j for s, d in atoms)
+        if ok:
+            out.append(list(perm))
+    return out

@@ -1,0 +1,284 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics:
+the paper's worked example, brute force over all vertex tuples, closed forms
+on structured graphs, dense matrix identities, the delta-query identity and
+order independence.  CPU only."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import brute
+from tests import queries as Q
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rand_graph(n, m, seed, loops=True):
+    rng = np.random.default_rng(seed)
+    s = rng.integers(0, n, m).astype(np.uint32)
+    d = rng.integers(0, n, m).astype(np.uint32)
+    if not loops:
+        keep = s != d
+        s, d = s[keep], d[keep]
+    return s, d
+
+
+# ---------------------------------------------------------------- Appendix A
+def test_appendix_a_worked_example():
+    g = json.load(open(os.path.join(GOLDEN, "appendix_a.json")))
+    e = np.array(g["edges"], dtype=np.uint32)
+    G = oracle.Graph(g["num_vertices"], e[:, 0], e[:, 1])
+    q = (g["query"]["num_attrs"], [tuple(a) for a in g["query"]["atoms"]], g["query"]["order"])
+    pr = g["printed"]
+    # the printed extension sets follow from the graph
+    out_ne = sorted(set(e[:, 0].tolist()))
+    in_ne = sorted(set(e[:, 1].tolist()))
+    assert out_ne == pr["Ext1_1_projection_out_nonempty"] == pr["Ext2_2_projection_out_nonempty"]
+    assert in_ne == pr["Ext3_1_projection_in_nonempty"]
+    assert sorted(e[e[:, 0] == 1, 1].tolist()) == pr["Ext1_2_of_1"]
+    assert sorted(e[e[:, 0] == 6, 1].tolist()) == pr["Ext2_3_of_1_6"]
+    assert sorted(e[e[:, 1] == 1, 0].tolist()) == pr["Ext3_3_of_1_6"]
+    P = oracle.textbook(G, q)
+    assert P[0].tolist() == pr["P1"]
+    assert P[1].tolist() == pr["P2"]
+    assert P[2].tolist() == pr["P3"]
+    # the edge-seeded form reaches the same P_3
+    r = oracle.run(G, q, collect=True)
+    assert r["rows"].tolist() == pr["P3"]
+    assert r["matches"] == 3
+
+
+# ---------------------------------------------------------------- brute force
+@pytest.mark.parametrize("name", ["triangle", "cyclic_triangle", "clique4", "diamond",
+                                  "paper_diamond", "cycle4", "reciprocal"])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_brute_force_small(name, seed):
+    q = Q.ALL[name]
+    n = 24 if q[0] == 3 else 14
+    s, d = rand_graph(n, n * 5, seed)
+    A = brute.adjacency(n, s, d)
+    want = brute.matches(A, q)
+    G = oracle.Graph(n, s, d)
+    for order in Q.valid_orders(q):
+        r = oracle.run(G, Q.with_order(q, order), collect=True)
+        assert r["matches"] == len(want)
+        assert np.array_equal(r["rows"], want), order
+
+
+@pytest.mark.parametrize("name", ["house", "clique5"])
+def test_brute_force_five_attrs(name):
+    q = Q.ALL[name]
+    n = 10
+    s, d = rand_graph(n, 70, 7)
+    A = brute.adjacency(n, s, d)
+    want = brute.matches(A, q)
+    G = oracle.Graph(n, s, d)
+    r = oracle.run(G, q, collect=True)
+    assert np.array_equal(r["rows"], want)
+    assert len(want) > 0
+
+
+def test_brute_force_n50_triangle():
+    n = 50
+    s, d = rand_graph(n, 600, 11)
+    A = brute.adjacency(n, s, d)
+    for q in (Q.TRIANGLE, Q.CYCLIC_TRIANGLE):
+        want = brute.matches(A, q)
+        r = oracle.run(oracle.Graph(n, s, d), q, collect=True)
+        assert np.array_equal(r["rows"], want)
+
+
+def test_textbook_equals_edge_seeded():
+    n = 16
+    s, d = rand_graph(n, 90, 3)
+    G = oracle.Graph(n, s, d)
+    for name in ["triangle", "cyclic_triangle", "clique4", "diamond", "cycle4"]:
+        q = Q.ALL[name]
+        P = oracle.textbook(G, q)
+        r = oracle.run(G, q, collect=True)
+        # textbook rows are in position order == attribute order here
+        assert np.array_equal(P[-1][np.lexsort(P[-1].T[::-1])], r["rows"])
+
+
+# ---------------------------------------------------------------- closed forms
+def complete(n):
+    s, d = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    keep = s != d
+    return s[keep].astype(np.uint32), d[keep].astype(np.uint32)
+
+
+def tournament(n):
+    s, d = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    keep = s < d
+    return s[keep].astype(np.uint32), d[keep].astype(np.uint32)
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 9])
+def test_complete_digraph(n):
+    G = oracle.Graph(n, *complete(n))
+    assert oracle.run(G, Q.TRIANGLE)["matches"] == n * (n - 1) * (n - 2)
+    assert oracle.run(G, Q.CYCLIC_TRIANGLE)["matches"] == n * (n - 1) * (n - 2)
+    assert oracle.run(G, Q.CLIQUE4)["matches"] == n * (n - 1) * (n - 2) * (n - 3)
+    assert oracle.run(G, Q.DIAMOND)["matches"] == (n - 1) ** 4 + (n - 1)
+    assert oracle.run(G, Q.CYCLE4)["matches"] == (n - 1) ** 4 + (n - 1)
+
+
+@pytest.mark.parametrize("n", [3, 6, 11])
+def test_transitive_tournament(n):
+    G = oracle.Graph(n, *tournament(n))
+    assert oracle.run(G, Q.TRIANGLE)["matches"] == math.comb(n, 3)
+    assert oracle.run(G, Q.CLIQUE4)["matches"] == math.comb(n, 4)
+    assert oracle.run(G, Q.CYCLIC_TRIANGLE)["matches"] == 0
+    assert oracle.run(G, Q.CYCLE4)["matches"] == 0
+    want = sum((n - d) * (d - 1) ** 2 for d in range(1, n))
+    assert oracle.run(G, Q.DIAMOND)["matches"] == want
+
+
+def test_bipartite_odd_cycles_vanish():
+    rng = np.random.default_rng(5)
+    L, R = 40, 35
+    s = rng.integers(0, L, 900)
+    d = rng.integers(L, L + R, 900)
+    flip = rng.random(900) < 0.5  # arcs in both directions across the cut
+    s2 = np.where(flip, d, s).astype(np.uint32)
+    d2 = np.where(flip, s, d).astype(np.uint32)
+    G = oracle.Graph(L + R, s2, d2)
+    for q in (Q.TRIANGLE, Q.CYCLIC_TRIANGLE, Q.CLIQUE4):
+        assert oracle.run(G, q)["matches"] == 0
+    # even cycles are bipartite patterns and do occur
+    assert oracle.run(G, Q.CYCLE4)["matches"] > 0
+    assert oracle.run(G, Q.DIAMOND)["matches"] > 0
+
+
+def test_er2000_dense_identities():
+    """Workload: ER digraph, n = 2,000, 20,000 distinct arcs, seed 0.
+    Counts equal dense matrix forms: transitive triangle = sum(A o A^2),
+    cyclic triangle = tr(A^3), two-2-path diamond = sum((A^2)^2),
+    4-cycle = tr(A^4) (exact in float64 below 2^53)."""
+    s, d = synth.er_edges(2000, 20000, 0)
+    A = brute.adjacency(2000, s, d).astype(np.float64)
+    A2 = A @ A
+    G = oracle.Graph(2000, s, d)
+    r = oracle.run(G, Q.TRIANGLE, collect=True)
+    assert r["matches"] == int((A * A2).sum())
+    assert r["prefixes"][2] == 20000
+    # the stage-3 extension counter: sum over arcs of min(out(a1), out(a2))
+    outd = np.bincount(s, minlength=2000)
+    assert r["extensions"][2] == int(np.minimum(outd[s], outd[d]).sum())
+    # every row is a triangle
+    rows = r["rows"].astype(np.int64)
+    assert A[rows[:, 0], rows[:, 1]].all() and A[rows[:, 1], rows[:, 2]].all()
+    assert A[rows[:, 0], rows[:, 2]].all()
+    assert oracle.run(G, Q.CYCLIC_TRIANGLE)["matches"] == int(np.trace(A2 @ A))
+    assert oracle.run(G, Q.DIAMOND)["matches"] == int((A2 * A2).sum())
+    assert oracle.run(G, Q.CYCLE4)["matches"] == int(np.trace(A2 @ A2))
+
+
+def test_agm_bound_triangle():
+    s, d = synth.rmat_draws(10, seed=3)
+    G = oracle.Graph(1 << 10, s, d)
+    E = G.num_edges
+    r = oracle.run(G, Q.TRIANGLE)
+    assert r["matches"] <= E ** 1.5
+    assert r["prefixes"][3] == r["matches"]
+
+
+# ---------------------------------------------------------------- orders, threads, slices
+def test_order_and_thread_independence():
+    s, d = synth.rmat_draws(9, seed=4)
+    G = oracle.Graph(1 << 9, s, d)
+    for q in (Q.TRIANGLE, Q.CLIQUE4, Q.CYCLE4):
+        base = oracle.run(G, q, collect=True)
+        for order in Q.valid_orders(q)[:6]:
+            r = oracle.run(G, Q.with_order(q, order), collect=True, threads=3)
+            assert np.array_equal(r["rows"], base["rows"])
+
+
+def test_seed_slices_partition():
+    s, d = synth.rmat_draws(9, seed=5)
+    G = oracle.Graph(1 << 9, s, d)
+    E = G.num_edges
+    full = oracle.run(G, Q.TRIANGLE, collect=True)
+    cuts = [0, 17, 400, E // 2, E]
+    parts = [oracle.run(G, Q.TRIANGLE, collect=True, seed_lo=a, seed_hi=b)
+             for a, b in zip(cuts[:-1], cuts[1:])]
+    assert sum(p["matches"] for p in parts) == full["matches"]
+    assert sum(p["extensions"][2] for p in parts) == full["extensions"][2]
+    rows = np.concatenate([p["rows"] for p in parts])
+    assert np.array_equal(rows[np.lexsort(rows.T[::-1])], full["rows"])
+
+
+def test_invalid_queries():
+    assert not oracle.query_valid((3, [(0, 1), (1, 2)], [0, 2, 1]))  # a1,a3 share no atom
+    assert not oracle.query_valid((3, [(0, 0), (0, 1), (1, 2)], [0, 1, 2]))  # self-loop atom
+    assert not oracle.query_valid((4, [(0, 1), (2, 3)], [0, 1, 2, 3]))  # cartesian product
+    assert not oracle.query_valid((3, [(0, 1), (1, 2)], [0, 1, 1]))  # not a permutation
+    assert oracle.query_valid(Q.CYCLE4)
+
+
+# ---------------------------------------------------------------- delta queries
+def test_delta_forced_cancellation():
+    """Insert 1->2 and delete 2->3 with 1->3 present: dQ_1 emits (1,2,3) +1,
+    dQ_2 emits it -1; the consolidated change is empty."""
+    G = oracle.Graph(4, [2, 1], [3, 3])
+    r = oracle.delta(G, [1, 2], [2, 3], [1, -1], Q.TRIANGLE)
+    assert r["raw_emissions"] == 2
+    assert r["count_delta"] == 0
+    assert len(r["rows"]) == 0
+    assert sorted(zip(*G.edge_list())) == [(1, 2), (1, 3)]
+
+
+@pytest.mark.parametrize("name", ["triangle", "cyclic_triangle", "clique4", "diamond",
+                                  "cycle4", "reciprocal"])
+def test_delta_equals_recompute_difference(name):
+    q = Q.ALL[name]
+    n = 18
+    rng = np.random.default_rng(hash(name) % 1000)
+    s, d = rand_graph(n, 110, 21)
+    G = oracle.Graph(n, s, d)
+    for step in range(6):
+        before = brute.as_set(oracle.run(G, q, collect=True)["rows"])
+        b = int(rng.integers(1, 25))
+        bs = rng.integers(0, n, b).astype(np.uint32)
+        bd = rng.integers(0, n, b).astype(np.uint32)
+        sg = np.where(rng.random(b) < 0.4, -1, 1).astype(np.int8)
+        # deletions target existing edges half of the time
+        es, ed = G.edge_list()
+        for k in range(b):
+            if sg[k] < 0 and rng.random() < 0.5 and len(es):
+                j = rng.integers(0, len(es))
+                bs[k], bd[k] = es[j], ed[j]
+        # drop insert/delete conflicts
+        dels = {(int(x), int(y)) for x, y, g in zip(bs, bd, sg) if g < 0}
+        keep = np.array([not (g > 0 and (int(x), int(y)) in dels) for x, y, g in zip(bs, bd, sg)])
+        bs, bd, sg = bs[keep], bd[keep], sg[keep]
+        r = oracle.delta(G, bs, bd, sg, q)
+        after_rows = oracle.run(G, q, collect=True)["rows"]
+        after = brute.as_set(after_rows)
+        # the new graph equals the brute-force application of the batch
+        A = brute.adjacency(n, *G.edge_list())
+        assert brute.as_set(brute.matches(A, q)) == after
+        got_plus = {t for t, g in zip(map(tuple, r["rows"].tolist()), r["signs"]) if g > 0}
+        got_minus = {t for t, g in zip(map(tuple, r["rows"].tolist()), r["signs"]) if g < 0}
+        assert got_plus == after - before
+        assert got_minus == before - after
+        assert r["count_delta"] == len(after) - len(before)
+        assert set(np.unique(r["signs"]).tolist()) <= {-1, 1}
+
+
+def test_delta_conflict_rejected():
+    G = oracle.Graph(5, [0, 1], [1, 2])
+    with pytest.raises(oracle.OracleError):
+        oracle.delta(G, [3, 3], [4, 4], [1, -1], Q.TRIANGLE)
+    assert G.num_edges == 2
+
+
+def test_delta_noops_counted():
+    G = oracle.Graph(5, [0, 1], [1, 2])
+    oracle.delta(G, [0, 3, 4], [1, 4, 4], [1, -1, 1], Q.TRIANGLE)
+    assert G.noops() == (1, 1)
+    assert G.num_edges == 2
