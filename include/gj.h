@@ -1,0 +1,184 @@
+/*
+ * gj.h -- C ABI of the MI355X Generic Join library (libgj.so).
+ *
+ * Evaluates subgraph queries as multiway self-joins of one edge relation with
+ * Generic Join, and maintains their results under edge insertions and
+ * deletions with delta queries.  Paper: Ammar, McSherry, Salihoglu,
+ * Joglekar, "Distributed Evaluation of Subgraph Queries Using Worst-case
+ * Optimal Low-Memory Dataflows" (VLDB 2018).
+ *
+ * Conventions for every call:
+ *  - Returns gj_status; nothing throws across the ABI.  On failure a message
+ *    is available from gj_last_error() of the context.
+ *  - Inputs are copied (host or device pointers, as each call states);
+ *    handles are owned by the library; output buffers are owned by the caller.
+ *  - One context per host thread.  Work is issued on the context's HIP
+ *    stream; calls return after their results are in the caller's buffers.
+ *  - Vertex ids are uint32 < num_vertices; edges per graph < 2^32.
+ *  - Counts are exact unsigned 64-bit integers.
+ */
+#ifndef GJ_H
+#define GJ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GJ_OK = 0,
+  GJ_EINVAL = 1,       /* invalid argument, query or update batch */
+  GJ_ENOMEM = 2,       /* device allocation failed */
+  GJ_EDEVICE = 3,      /* HIP runtime error */
+  GJ_EOVERFLOW = 4,    /* output buffer too small; required size reported */
+  GJ_EUNSUPPORTED = 5, /* outside the supported limits */
+  GJ_EBUSY = 6         /* resource in use */
+} gj_status;
+
+#define GJ_MAX_ATTRS 8
+#define GJ_MAX_ATOMS 16
+
+typedef struct gj_ctx gj_ctx;
+typedef struct gj_graph gj_graph;
+typedef struct gj_query gj_query;
+
+/* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t to
+ * issue work on (NULL: the library creates its own).  Internal buffers are
+ * device allocations owned by the context and reused across calls. */
+gj_status gj_ctx_create(int device, void* hip_stream, gj_ctx** out);
+/* Releases the context.  Graphs built on it must be destroyed first. */
+void gj_ctx_destroy(gj_ctx* ctx);
+
+/* Message of the last failed call on `ctx`; owned by ctx, valid until the
+ * next call.  Never NULL. */
+const char* gj_last_error(const gj_ctx* ctx);
+
+/* Tuning options (integers).  Keys:
+ *   "frontier_cap"  max prefixes held per stage buffer and max candidates
+ *                   proposed per batch (the batch bound B of Sec. 3.1.2);
+ *                   default 2^25, minimum 64
+ *   "seed_chunk"    max seed edges per P_2 batch (default 2^25)
+ *   "strategy"      intersection kernel choice: 0 auto, 1 generic
+ *                   per-candidate search only, 2 owner-grouped LDS kernel
+ *                   where applicable
+ * Returns GJ_EINVAL for an unknown key or out-of-range value. */
+gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
+
+/* ---------------------------------------------------------------- graphs */
+
+#define GJ_INPUT_DEVICE 1u /* src/dst are device pointers (default: host) */
+#define GJ_KEEP_LOOPS 2u   /* not supported: self-loops are always dropped */
+
+/* Builds the forward (out-neighbour) and reverse (in-neighbour) indices of
+ * the edge relation (one physical copy each, Sec. 4.1): CSR rows sorted
+ * ascending, repeated edges collapsed, self-loops dropped.
+ * src, dst: m vertex ids each (host memory unless GJ_INPUT_DEVICE).
+ * Errors: GJ_EINVAL for an id >= num_vertices, num_vertices == 0 or an
+ * unknown flag; GJ_EUNSUPPORTED if m >= 2^32. */
+gj_status gj_graph_build(gj_ctx* ctx, const uint32_t* src, const uint32_t* dst,
+                         uint64_t m, uint32_t num_vertices, uint32_t flags,
+                         gj_graph** out);
+
+/* Sizes of the current version.  Any pointer may be NULL. */
+gj_status gj_graph_info(const gj_graph* g, uint64_t* edges, uint32_t* vertices,
+                        uint32_t* max_out, uint32_t* max_in, uint64_t* version);
+
+/* Device pointers of the current version's index (valid until the next
+ * gj_apply_updates or gj_graph_destroy): reverse = 0 forward, 1 reverse.
+ * row_ptr has vertices+1 entries, col and row have `edges` entries; row[e] is
+ * the row (source for forward, destination for reverse) of entry e. */
+gj_status gj_graph_csr(const gj_graph* g, int reverse, const uint32_t** row_ptr,
+                       const uint32_t** col, const uint32_t** row);
+
+void gj_graph_destroy(gj_graph* g);
+
+/* ---------------------------------------------------------------- queries */
+
+/* atom = edge(a_src, a_dst) (Sec. 1.1: one atom per query edge) */
+typedef struct {
+  uint8_t src_attr, dst_attr;
+} gj_atom;
+
+/* Registers Q(a_0..a_{m-1}) := edge(...), ... with a global attribute order
+ * (Sec. 2.2).  order is a permutation of 0..num_attrs-1.  P_2 is seeded from
+ * the edges of the lowest-index atom over order[0], order[1] (Sec. 4.2).
+ * Errors (GJ_EINVAL): num_attrs outside [2, 8]; num_atoms outside [1, 16];
+ * an atom over one attribute twice or outside the attributes; order not a
+ * permutation; no atom over order[0], order[1]; a later attribute with no
+ * atom to an earlier one. */
+gj_status gj_query_register(gj_ctx* ctx, uint32_t num_attrs, const gj_atom* atoms,
+                            uint32_t num_atoms, const uint8_t* order, gj_query** out);
+void gj_query_destroy(gj_query* q);
+
+/* Per-call counters.  prefixes[j] = |P_j| (j >= 2; prefixes[m] = matches),
+ * extensions[j] = sum over p in P_j of the smallest extension-set size
+ * (count-minimisation, Sec. 3.1), i.e. candidates proposed at stage j. */
+typedef struct {
+  uint64_t matches;
+  uint64_t prefixes[GJ_MAX_ATTRS + 1];
+  uint64_t extensions[GJ_MAX_ATTRS + 1];
+  uint64_t noop_inserts;   /* gj_apply_updates: insertions of present edges */
+  uint64_t noop_deletes;   /* gj_apply_updates: deletions of absent edges */
+  uint64_t raw_emissions;  /* gj_apply_updates: signed rows before consolidation */
+  uint64_t kernel_launches;/* launches of the propose+intersect kernels */
+  double kernel_ms;        /* their summed device time (HIP events on the context stream) */
+  double ms;               /* wall time of the call */
+} gj_stats;
+
+#define GJ_MODE_COUNT 0
+#define GJ_MODE_ENUMERATE 1
+
+/* Runs Generic Join (Sec. 2.2) in the edge-seeded form (Sec. 4.2) over seed
+ * edges [seed_lo, seed_hi) of the seed atom's index (forward when the seed
+ * atom is edge(order[0], order[1]), else reverse; clamped to the edge
+ * count; 0, UINT64_MAX = all).
+ * mode COUNT: stats->matches only (out may be NULL).
+ * mode ENUMERATE: writes the matches to `out` as rows of num_attrs uint32,
+ * columns in attribute-index order, rows sorted ascending (unsigned
+ * lexicographic); `out` is device memory if out_on_device, else host.  If
+ * more than out_cap_rows rows match, returns GJ_EOVERFLOW with
+ * stats->matches = the required row count (buffer contents unspecified).
+ * stats may be NULL. */
+gj_status gj_run(gj_ctx* ctx, const gj_graph* g, const gj_query* q, int mode,
+                 uint64_t seed_lo, uint64_t seed_hi, uint32_t* out,
+                 uint64_t out_cap_rows, int out_on_device, gj_stats* stats);
+
+/* Applies one signed update batch (sign +1 insert, -1 delete; host memory
+ * unless on_device) as a new version of the graph, and returns for each of
+ * the nq queries the change of its result (Delta-GJ, Sec. 3.3.1: the signed
+ * union of the delta queries dQ_i, consolidated).
+ * Batch normalisation: self-loops dropped; repeated rows collapse; inserting
+ * a present edge / deleting an absent one is a no-op (counted in stats).
+ * Errors (graph unchanged): GJ_EINVAL for an id >= num_vertices, a sign
+ * other than +-1, or one edge both inserted and deleted in the batch.
+ * count_delta[q]: signed change of the match count.
+ * delta_rows / delta_sign (either array or any entry may be NULL: counts
+ * only): per query, up to cap[q] rows of num_attrs uint32 in attribute order,
+ * sorted ascending, with sign +1 (new match) or -1 (lost match); host memory
+ * unless on_device.  n_delta[q] = number of consolidated rows; if it exceeds
+ * cap[q] the call still applies the batch and returns GJ_EOVERFLOW.
+ * stats may be NULL or an array of nq. */
+gj_status gj_apply_updates(gj_ctx* ctx, gj_graph* g, const uint32_t* src,
+                           const uint32_t* dst, const int8_t* sign, uint64_t b,
+                           int on_device, const gj_query* const* qs, uint32_t nq,
+                           int64_t* count_delta, uint32_t* const* delta_rows,
+                           int8_t* const* delta_sign, const uint64_t* cap,
+                           uint64_t* n_delta, gj_stats* stats);
+
+/* Copies the consolidated delta rows of query number q (its position in the
+ * qs list) of the most recent gj_apply_updates on ctx that requested rows
+ * (non-NULL delta_rows or delta_sign for q): up to cap rows and signs, in
+ * the layout gj_apply_updates uses, device memory if on_device else host.
+ * *n receives the row count.  Lets a caller that got GJ_EOVERFLOW fetch the
+ * rows without re-applying the batch.  The rows stay available until the
+ * next gj_apply_updates on ctx.  Errors: GJ_EINVAL if q has no kept rows;
+ * GJ_EOVERFLOW if *n > cap (nothing copied). */
+gj_status gj_last_delta(gj_ctx* ctx, uint32_t q, uint32_t* rows, int8_t* signs,
+                        uint64_t cap, int on_device, uint64_t* n);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GJ_H */

@@ -61,11 +61,13 @@ struct Graph {
     const auto& l = out[u];
     return std::binary_search(l.begin(), l.end(), v);
   }
-  void rebuild_lists(const std::set<std::pair<uint32_t, uint32_t>>& s) {
+  // `s`: the edge set, sorted ascending by (src, dst), no repeats
+  void rebuild_lists(const std::vector<std::pair<uint32_t, uint32_t>>& s) {
     out.assign(n, {});
     in.assign(n, {});
-    fwd_edges.assign(s.begin(), s.end());
+    fwd_edges = s;
     rev_edges.clear();
+    rev_edges.reserve(s.size());
     for (auto& e : s) {
       out[e.first].push_back(e.second);
       in[e.second].push_back(e.first);
@@ -323,14 +325,17 @@ extern "C" {
 
 // Graph: drops self-loops and repeated edges.  Vertex ids must be < n.
 void* or_graph_new(uint32_t n, const uint32_t* src, const uint32_t* dst, uint64_t m) {
-  std::set<std::pair<uint32_t, uint32_t>> s;
+  std::vector<std::pair<uint32_t, uint32_t>> s;
+  s.reserve(m);
   Graph* g = new Graph();
   g->n = n;
   for (uint64_t i = 0; i < m; ++i) {
     if (src[i] >= n || dst[i] >= n) { delete g; return nullptr; }
     if (src[i] == dst[i]) { ++g->dropped_loops; continue; }
-    s.insert({src[i], dst[i]});
+    s.push_back({src[i], dst[i]});
   }
+  std::sort(s.begin(), s.end());
+  s.erase(std::unique(s.begin(), s.end()), s.end());
   g->rebuild_lists(s);
   return g;
 }
@@ -490,11 +495,12 @@ void* or_delta(void* gp, const uint32_t* src, const uint32_t* dst, const int8_t*
     if (!g->has(e.first, e.second)) ++noop_d;
     else dE.push_back({e, -1});
   }
-  std::set<std::pair<uint32_t, uint32_t>> s(g->fwd_edges.begin(), g->fwd_edges.end());
+  std::set<std::pair<uint32_t, uint32_t>> ss(g->fwd_edges.begin(), g->fwd_edges.end());
   for (auto& x : dE) {
-    if (x.second > 0) s.insert(x.first);
-    else s.erase(x.first);
+    if (x.second > 0) ss.insert(x.first);
+    else ss.erase(x.first);
   }
+  std::vector<std::pair<uint32_t, uint32_t>> s(ss.begin(), ss.end());
   Graph g_new;
   g_new.n = g->n;
   g_new.rebuild_lists(s);

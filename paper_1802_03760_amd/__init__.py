@@ -1,0 +1,323 @@
+"""MI355X Generic Join: Python binding of libgj.so (include/gj.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of libgj.so.  PyTorch provides device memory and streams.  Importing
+this package fails loudly when the library has not been built.
+"""
+import atexit
+import ctypes
+import os
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgj.so")
+
+GJ_OK, GJ_EINVAL, GJ_ENOMEM, GJ_EDEVICE, GJ_EOVERFLOW, GJ_EUNSUPPORTED, GJ_EBUSY = range(7)
+MODE_COUNT, MODE_ENUMERATE = 0, 1
+GJ_INPUT_DEVICE = 1
+MAX_ATTRS = 8
+STATUS_NAMES = {0: "GJ_OK", 1: "GJ_EINVAL", 2: "GJ_ENOMEM", 3: "GJ_EDEVICE",
+                4: "GJ_EOVERFLOW", 5: "GJ_EUNSUPPORTED", 6: "GJ_EBUSY"}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libgj.so is not built (run __graft_entry__.build() or "
+                      "python paper_1802_03760_amd/build.py); there is no fallback")
+_lib = ctypes.CDLL(LIB_PATH)
+
+EXPORTS = ["gj_ctx_create", "gj_ctx_destroy", "gj_last_error", "gj_ctx_set_option",
+           "gj_graph_build", "gj_graph_info", "gj_graph_csr", "gj_graph_destroy",
+           "gj_query_register", "gj_query_destroy", "gj_run", "gj_apply_updates",
+           "gj_last_delta"]
+
+
+class Atom(ctypes.Structure):
+    _fields_ = [("src_attr", ctypes.c_uint8), ("dst_attr", ctypes.c_uint8)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("matches", ctypes.c_uint64),
+                ("prefixes", ctypes.c_uint64 * (MAX_ATTRS + 1)),
+                ("extensions", ctypes.c_uint64 * (MAX_ATTRS + 1)),
+                ("noop_inserts", ctypes.c_uint64),
+                ("noop_deletes", ctypes.c_uint64),
+                ("raw_emissions", ctypes.c_uint64),
+                ("kernel_launches", ctypes.c_uint64),
+                ("kernel_ms", ctypes.c_double),
+                ("ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"matches": int(self.matches),
+                "prefixes": [int(x) for x in self.prefixes],
+                "extensions": [int(x) for x in self.extensions],
+                "noop_inserts": int(self.noop_inserts),
+                "noop_deletes": int(self.noop_deletes),
+                "raw_emissions": int(self.raw_emissions),
+                "kernel_launches": int(self.kernel_launches),
+                "kernel_ms": float(self.kernel_ms),
+                "ms": float(self.ms)}
+
+
+_vp, _u64, _u32, _i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+_lib.gj_ctx_create.argtypes = [_i32, _vp, ctypes.POINTER(_vp)]
+_lib.gj_ctx_create.restype = _i32
+_lib.gj_ctx_destroy.argtypes = [_vp]
+_lib.gj_ctx_destroy.restype = None
+_lib.gj_last_error.argtypes = [_vp]
+_lib.gj_last_error.restype = ctypes.c_char_p
+_lib.gj_ctx_set_option.argtypes = [_vp, ctypes.c_char_p, ctypes.c_int64]
+_lib.gj_ctx_set_option.restype = _i32
+_lib.gj_graph_build.argtypes = [_vp, _vp, _vp, _u64, _u32, _u32, ctypes.POINTER(_vp)]
+_lib.gj_graph_build.restype = _i32
+_lib.gj_graph_info.argtypes = [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
+                               ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u64)]
+_lib.gj_graph_info.restype = _i32
+_lib.gj_graph_csr.argtypes = [_vp, _i32, ctypes.POINTER(_vp), ctypes.POINTER(_vp), ctypes.POINTER(_vp)]
+_lib.gj_graph_csr.restype = _i32
+_lib.gj_graph_destroy.argtypes = [_vp]
+_lib.gj_graph_destroy.restype = None
+_lib.gj_query_register.argtypes = [_vp, _u32, ctypes.POINTER(Atom), _u32, _vp, ctypes.POINTER(_vp)]
+_lib.gj_query_register.restype = _i32
+_lib.gj_query_destroy.argtypes = [_vp]
+_lib.gj_query_destroy.restype = None
+_lib.gj_run.argtypes = [_vp, _vp, _vp, _i32, _u64, _u64, _vp, _u64, _i32, ctypes.POINTER(Stats)]
+_lib.gj_run.restype = _i32
+_lib.gj_apply_updates.argtypes = [_vp, _vp, _vp, _vp, _vp, _u64, _i32, ctypes.POINTER(_vp), _u32,
+                                  _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp,
+                                  ctypes.POINTER(Stats)]
+_lib.gj_apply_updates.restype = _i32
+_lib.gj_last_delta.argtypes = [_vp, _u32, _vp, _vp, _u64, _i32, ctypes.POINTER(_u64)]
+_lib.gj_last_delta.restype = _i32
+
+
+# Live handles, released in dependency order (queries, graphs, contexts) at
+# interpreter exit while the HIP runtime is still fully up; afterwards the
+# finalisers do nothing.
+_live = weakref.WeakSet()
+_finalised = False
+
+
+def _release_all():
+    global _finalised
+    for kind in (Query, Graph, Context):
+        for obj in list(_live):
+            if isinstance(obj, kind):
+                obj.close()
+    _finalised = True
+
+
+atexit.register(_release_all)
+
+
+class GJError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def _np_ptr(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None and a.size else None
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x):
+    """Device or host address of a torch tensor / numpy array."""
+    if x is None:
+        return None
+    if _is_torch(x):
+        return ctypes.c_void_p(x.data_ptr()) if x.numel() else None
+    return _np_ptr(x)
+
+
+class Context:
+    """gj_ctx on one HIP device; issues work on `stream` (a torch.cuda.Stream,
+    a raw hipStream_t int, or None for the library's own stream)."""
+
+    def __init__(self, device=0, stream=None):
+        h = _vp()
+        raw = None
+        if stream is not None:
+            raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+        st = _lib.gj_ctx_create(device, _vp(raw) if raw else None, ctypes.byref(h))
+        if st != GJ_OK:
+            raise GJError(st, "gj_ctx_create(device=%d) failed" % device)
+        self._h = h
+        self.device = device
+        self._children = weakref.WeakSet()
+        _live.add(self)
+
+    def check(self, st, what):
+        if st != GJ_OK:
+            raise GJError(st, "%s: %s" % (what, _lib.gj_last_error(self._h).decode()))
+
+    def set_option(self, key, value):
+        self.check(_lib.gj_ctx_set_option(self._h, key.encode(), int(value)), "set_option")
+
+    def close(self):
+        """Destroys the context and every graph and query created on it."""
+        if getattr(self, "_h", None):
+            for kind in (Query, Graph):
+                for obj in list(self._children):
+                    if isinstance(obj, kind):
+                        obj.close()
+            _lib.gj_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        if not _finalised:
+            self.close()
+
+
+class Graph:
+    """Forward and reverse CSR indexes of an edge list (gj_graph_build)."""
+
+    def __init__(self, ctx, src, dst, num_vertices):
+        self.ctx = ctx
+        h = _vp()
+        if _is_torch(src):
+            flags = GJ_INPUT_DEVICE if src.is_cuda else 0
+            m = src.numel()
+        else:
+            src = np.ascontiguousarray(src, dtype=np.uint32)
+            dst = np.ascontiguousarray(dst, dtype=np.uint32)
+            flags, m = 0, len(src)
+        ctx.check(_lib.gj_graph_build(ctx._h, _ptr(src), _ptr(dst), m, num_vertices, flags,
+                                      ctypes.byref(h)), "gj_graph_build")
+        self._h = h
+        ctx._children.add(self)
+        _live.add(self)
+
+    def info(self):
+        e, n, mo, mi, v = _u64(), _u32(), _u32(), _u32(), _u64()
+        _lib.gj_graph_info(self._h, ctypes.byref(e), ctypes.byref(n), ctypes.byref(mo),
+                           ctypes.byref(mi), ctypes.byref(v))
+        return {"edges": e.value, "vertices": n.value, "max_out": mo.value,
+                "max_in": mi.value, "version": v.value}
+
+    def csr_ptrs(self, reverse=False):
+        rp, col, row = _vp(), _vp(), _vp()
+        self.ctx.check(_lib.gj_graph_csr(self._h, int(reverse), ctypes.byref(rp), ctypes.byref(col),
+                                         ctypes.byref(row)), "gj_graph_csr")
+        return rp.value, col.value, row.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.gj_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        if not _finalised:
+            self.close()
+
+
+class Query:
+    """Q(a_0..a_{m-1}) := edge(s, d), ... with a global order (gj_query_register)."""
+
+    def __init__(self, ctx, num_attrs, atoms, order=None):
+        self.ctx = ctx
+        self.num_attrs = num_attrs
+        self.atoms = [tuple(a) for a in atoms]
+        self.order = list(range(num_attrs)) if order is None else list(order)
+        arr = (Atom * len(self.atoms))(*[Atom(s, d) for s, d in self.atoms])
+        o = np.array(self.order, dtype=np.uint8)
+        h = _vp()
+        ctx.check(_lib.gj_query_register(ctx._h, num_attrs, arr, len(self.atoms), _np_ptr(o),
+                                         ctypes.byref(h)), "gj_query_register")
+        self._h = h
+        ctx._children.add(self)
+        _live.add(self)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.gj_query_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        if not _finalised:
+            self.close()
+
+
+def count(ctx, graph, query, seed_lo=0, seed_hi=(1 << 64) - 1):
+    st = Stats()
+    ctx.check(_lib.gj_run(ctx._h, graph._h, query._h, MODE_COUNT, seed_lo, seed_hi, None, 0, 0,
+                          ctypes.byref(st)), "gj_run(count)")
+    return st.as_dict()
+
+
+def enumerate_rows(ctx, graph, query, seed_lo=0, seed_hi=(1 << 64) - 1, out=None, cap=None):
+    """Sorted match rows (attribute order).  `out`: a torch int32 cuda tensor of
+    shape (cap, m) to write into, or a numpy uint32 host array; None sizes a host
+    array from a count pass.  Returns (stats, rows)."""
+    m = query.num_attrs
+    if out is None:
+        if cap is None:
+            cap = count(ctx, graph, query, seed_lo, seed_hi)["matches"]
+        out = np.empty((max(cap, 1), m), dtype=np.uint32)
+    on_dev = 1 if (_is_torch(out) and out.is_cuda) else 0
+    cap = out.shape[0] if cap is None else cap
+    st = Stats()
+    s = _lib.gj_run(ctx._h, graph._h, query._h, MODE_ENUMERATE, seed_lo, seed_hi, _ptr(out), cap,
+                    on_dev, ctypes.byref(st))
+    ctx.check(s, "gj_run(enumerate)")
+    return st.as_dict(), out[: st.matches]
+
+
+def apply_updates(ctx, graph, src, dst, sign, queries, rows=False, cap=1 << 16):
+    """Applies one signed batch; per query returns count_delta, and with
+    rows=True the consolidated (rows, signs) as host arrays (fetched again with
+    gj_last_delta when they outgrow the first buffer of `cap` rows)."""
+    on_dev = 1 if (_is_torch(src) and src.is_cuda) else 0
+    if not _is_torch(src):
+        src = np.ascontiguousarray(src, dtype=np.uint32)
+        dst = np.ascontiguousarray(dst, dtype=np.uint32)
+        sign = np.ascontiguousarray(sign, dtype=np.int8)
+    b = src.numel() if _is_torch(src) else len(src)
+    nq = len(queries)
+    qh = (_vp * max(nq, 1))(*[q._h.value for q in queries])
+    cd = np.zeros(max(nq, 1), dtype=np.int64)
+    nd = np.zeros(max(nq, 1), dtype=np.uint64)
+    stats = (Stats * max(nq, 1))()
+    row_bufs, sign_bufs = [], []
+    rp = sp = capa = None
+    if rows:
+        if on_dev:
+            raise ValueError("rows=True needs a host batch in this binding")
+        capa = np.array([cap] * nq, dtype=np.uint64)
+        for q in queries:
+            row_bufs.append(np.empty((max(cap, 1), q.num_attrs), dtype=np.uint32))
+            sign_bufs.append(np.empty(max(cap, 1), dtype=np.int8))
+        rp = (_vp * nq)(*[r.ctypes.data for r in row_bufs])
+        sp = (_vp * nq)(*[s.ctypes.data for s in sign_bufs])
+    s = _lib.gj_apply_updates(ctx._h, graph._h, _ptr(src), _ptr(dst), _ptr(sign), b, on_dev, qh, nq,
+                              _np_ptr(cd), rp, sp, _np_ptr(capa), _np_ptr(nd), stats)
+    if not (rows and s == GJ_EOVERFLOW):
+        ctx.check(s, "gj_apply_updates")
+    out = []
+    for i in range(nq):
+        r = {"count_delta": int(cd[i]), "n_delta": int(nd[i]), "stats": stats[i].as_dict()}
+        if rows:
+            k = int(nd[i])
+            if k > cap:
+                row_bufs[i] = np.empty((k, queries[i].num_attrs), dtype=np.uint32)
+                sign_bufs[i] = np.empty(k, dtype=np.int8)
+                got = _u64()
+                ctx.check(_lib.gj_last_delta(ctx._h, i, _np_ptr(row_bufs[i]), _np_ptr(sign_bufs[i]), k, 0,
+                                             ctypes.byref(got)), "gj_last_delta")
+            r["rows"] = row_bufs[i][:k]
+            r["signs"] = sign_bufs[i][:k]
+        out.append(r)
+    return out
+
+
+def last_delta(ctx, q_index, num_attrs, cap):
+    """Rows and signs kept from the last apply_updates for query position q_index."""
+    rows = np.empty((max(cap, 1), num_attrs), dtype=np.uint32)
+    signs = np.empty(max(cap, 1), dtype=np.int8)
+    got = _u64()
+    ctx.check(_lib.gj_last_delta(ctx._h, q_index, _np_ptr(rows), _np_ptr(signs), cap, 0,
+                                 ctypes.byref(got)), "gj_last_delta")
+    return rows[: got.value], signs[: got.value]

@@ -1,0 +1,355 @@
+// C ABI of libgj.so (declared in include/gj.h): argument checks, device
+// memory, error reporting.  The computation lives in the other sources.
+#include <chrono>
+#include <cstring>
+#include <new>
+
+#include "engine.h"
+#include "gj_internal.h"
+
+namespace gj {
+
+void* dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{GJ_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  return p;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+// Named grow-only workspace buffers owned by the context.
+void* ws_get(gj_ctx* c, const std::string& name, size_t bytes) {
+  DevBuf& b = c->ws[name];
+  if (bytes <= b.bytes && b.p) return b.p;
+  size_t want = bytes + bytes / 8 + 256;
+  if (b.p) {
+    GJ_HIP(hipStreamSynchronize(c->stream));
+    dev_free(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  b.p = dev_alloc(want);
+  b.bytes = want;
+  return b.p;
+}
+
+void read_bytes(gj_ctx* c, void* host, const void* dptr, size_t bytes) {
+  if (bytes <= 4096) {
+    GJ_HIP(hipMemcpyAsync(c->pinned, dptr, bytes, hipMemcpyDeviceToHost, c->stream));
+    GJ_HIP(hipStreamSynchronize(c->stream));
+    memcpy(host, c->pinned, bytes);
+  } else {
+    GJ_HIP(hipMemcpyAsync(host, dptr, bytes, hipMemcpyDeviceToHost, c->stream));
+    GJ_HIP(hipStreamSynchronize(c->stream));
+  }
+}
+
+void KernelTimer::start() {
+  if (c_->events.size() < 2 * (n_ + 1)) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      GJ_HIP(hipEventCreate(&e));
+      c_->events.push_back(e);
+    }
+  }
+  GJ_HIP(hipEventRecord(c_->events[2 * n_], c_->stream));
+}
+
+void KernelTimer::stop() {
+  GJ_HIP(hipEventRecord(c_->events[2 * n_ + 1], c_->stream));
+  ++n_;
+}
+
+double KernelTimer::total_ms() {
+  GJ_HIP(hipStreamSynchronize(c_->stream));
+  double t = 0;
+  for (size_t i = 0; i < n_; ++i) {
+    float ms = 0;
+    GJ_HIP(hipEventElapsedTime(&ms, c_->events[2 * i], c_->events[2 * i + 1]));
+    t += ms;
+  }
+  return t;
+}
+
+uint64_t read_u64(gj_ctx* c, const void* dptr) {
+  uint64_t v = 0;
+  read_bytes(c, &v, dptr, sizeof(v));
+  return v;
+}
+
+}  // namespace gj
+
+using gj::Error;
+
+template <class F>
+static gj_status guarded(gj_ctx* c, F&& f) {
+  try {
+    if (c) {
+      hipError_t e = hipSetDevice(c->device);
+      if (e != hipSuccess) throw Error{GJ_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(e)};
+    }
+    f();
+    if (c) c->err.clear();
+    return GJ_OK;
+  } catch (const Error& e) {
+    if (c) c->err = e.msg;
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (c) c->err = "host allocation failed";
+    return GJ_ENOMEM;
+  } catch (...) {
+    if (c) c->err = "unexpected failure";
+    return GJ_EDEVICE;
+  }
+}
+
+extern "C" {
+
+gj_status gj_ctx_create(int device, void* hip_stream, gj_ctx** out) {
+  if (!out) return GJ_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return GJ_EDEVICE;
+  gj_ctx* c = new (std::nothrow) gj_ctx();
+  if (!c) return GJ_ENOMEM;
+  c->device = device;
+  gj_status s = guarded(c, [&] {
+    if (hip_stream) {
+      c->stream = (hipStream_t)hip_stream;
+    } else {
+      GJ_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+      c->own_stream = true;
+    }
+    GJ_HIP(hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault));
+    hipDeviceProp_t prop;
+    GJ_HIP(hipGetDeviceProperties(&prop, device));
+    c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  });
+  if (s != GJ_OK) {
+    gj_ctx_destroy(c);
+    return s;
+  }
+  *out = c;
+  return GJ_OK;
+}
+
+void gj_ctx_destroy(gj_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& kv : c->ws) gj::dev_free(kv.second.p);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* gj_last_error(const gj_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
+  if (!c || !key) return GJ_EINVAL;
+  return guarded(c, [&] {
+    std::string k(key);
+    if (k == "frontier_cap") {
+      GJ_CHECK(value >= 64 && value <= (1ll << 34), GJ_EINVAL, "frontier_cap out of range");
+      c->frontier_cap = (uint64_t)value;
+    } else if (k == "seed_chunk") {
+      GJ_CHECK(value >= 1 && value <= (1ll << 32), GJ_EINVAL, "seed_chunk out of range");
+      c->seed_chunk = (uint64_t)value;
+    } else if (k == "strategy") {
+      GJ_CHECK(value >= 0 && value <= 2, GJ_EINVAL, "strategy out of range");
+      c->strategy = (int)value;
+    } else {
+      throw Error{GJ_EINVAL, "unknown option " + k};
+    }
+  });
+}
+
+gj_status gj_graph_build(gj_ctx* c, const uint32_t* src, const uint32_t* dst, uint64_t m, uint32_t nv,
+                         uint32_t flags, gj_graph** out) {
+  if (!c || !out) return GJ_EINVAL;
+  *out = nullptr;
+  gj_graph* g = nullptr;
+  gj_status s = guarded(c, [&] {
+    GJ_CHECK((flags & ~GJ_INPUT_DEVICE) == 0, GJ_EINVAL, "unknown or unsupported graph flags");
+    GJ_CHECK(nv > 0, GJ_EINVAL, "num_vertices must be positive");
+    GJ_CHECK(m < (1ull << 32), GJ_EUNSUPPORTED, "graphs of 2^32 edges or more are not supported");
+    GJ_CHECK(m == 0 || (src && dst), GJ_EINVAL, "null edge arrays");
+    g = new gj_graph();
+    g->ctx = c;
+    g->n = nv;
+    const uint32_t *ds = src, *dd = dst;
+    if (!(flags & GJ_INPUT_DEVICE) && m) {
+      uint32_t* s2 = (uint32_t*)gj::ws_get(c, "in_src", m * sizeof(uint32_t));
+      uint32_t* d2 = (uint32_t*)gj::ws_get(c, "in_dst", m * sizeof(uint32_t));
+      GJ_HIP(hipMemcpyAsync(s2, src, m * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+      GJ_HIP(hipMemcpyAsync(d2, dst, m * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+      ds = s2;
+      dd = d2;
+    }
+    gj::graph_build(c, g, ds, dd, m);
+    GJ_HIP(hipStreamSynchronize(c->stream));
+  });
+  if (s != GJ_OK) {
+    gj_graph_destroy(g);
+    return s;
+  }
+  *out = g;
+  return GJ_OK;
+}
+
+gj_status gj_graph_info(const gj_graph* g, uint64_t* edges, uint32_t* vertices, uint32_t* max_out,
+                        uint32_t* max_in, uint64_t* version) {
+  if (!g) return GJ_EINVAL;
+  const gj::Version& v = g->ver[g->cur];
+  if (edges) *edges = v.m;
+  if (vertices) *vertices = g->n;
+  if (max_out) *max_out = v.max_deg[0];
+  if (max_in) *max_in = v.max_deg[1];
+  if (version) *version = g->version;
+  return GJ_OK;
+}
+
+gj_status gj_graph_csr(const gj_graph* g, int reverse, const uint32_t** row_ptr, const uint32_t** col,
+                       const uint32_t** row) {
+  if (!g || (reverse != 0 && reverse != 1)) return GJ_EINVAL;
+  const gj::CsrDir& d = g->ver[g->cur].d[reverse];
+  if (row_ptr) *row_ptr = d.rp;
+  if (col) *col = d.col;
+  if (row) *row = d.row;
+  return GJ_OK;
+}
+
+void gj_graph_destroy(gj_graph* g) {
+  if (!g) return;
+  if (g->ctx) {
+    (void)hipSetDevice(g->ctx->device);
+    (void)hipStreamSynchronize(g->ctx->stream);
+  }
+  gj::version_free(g->ver[0]);
+  gj::version_free(g->ver[1]);
+  delete g;
+}
+
+gj_status gj_query_register(gj_ctx* c, uint32_t num_attrs, const gj_atom* atoms, uint32_t num_atoms,
+                            const uint8_t* order, gj_query** out) {
+  if (!c || !out) return GJ_EINVAL;
+  *out = nullptr;
+  gj_query* q = nullptr;
+  gj_status s = guarded(c, [&] {
+    GJ_CHECK(num_attrs >= 2 && num_attrs <= GJ_MAX_ATTRS, GJ_EINVAL, "num_attrs must be in [2, 8]");
+    GJ_CHECK(num_atoms >= 1 && num_atoms <= GJ_MAX_ATOMS, GJ_EINVAL, "num_atoms must be in [1, 16]");
+    GJ_CHECK(atoms && order, GJ_EINVAL, "null atoms or order");
+    int m = (int)num_attrs;
+    std::vector<int> seen(m, 0), pos(m);
+    for (int j = 0; j < m; ++j) {
+      GJ_CHECK(order[j] < m && !seen[order[j]], GJ_EINVAL, "order is not a permutation of the attributes");
+      seen[order[j]] = 1;
+      pos[order[j]] = j;
+    }
+    for (uint32_t i = 0; i < num_atoms; ++i) {
+      GJ_CHECK(atoms[i].src_attr < m && atoms[i].dst_attr < m, GJ_EINVAL, "atom attribute out of range");
+      GJ_CHECK(atoms[i].src_attr != atoms[i].dst_attr, GJ_EINVAL, "atom over one attribute twice");
+    }
+    for (int j = 1; j < m; ++j) {
+      bool any = false;
+      for (uint32_t i = 0; i < num_atoms; ++i)
+        if (std::max(pos[atoms[i].src_attr], pos[atoms[i].dst_attr]) == j) any = true;
+      GJ_CHECK(any, GJ_EINVAL,
+               j == 1 ? "no atom over the first two attributes of the order"
+                      : "an attribute has no atom to an earlier attribute of the order");
+    }
+    q = new gj_query();
+    q->m = m;
+    q->atoms.assign(atoms, atoms + num_atoms);
+    q->order.assign(order, order + m);
+    // plan limits are checked here so that run time never fails on them
+    gj::PlanHCheck(q);
+  });
+  if (s != GJ_OK) {
+    delete q;
+    return s;
+  }
+  *out = q;
+  return GJ_OK;
+}
+
+void gj_query_destroy(gj_query* q) { delete q; }
+
+gj_status gj_run(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint64_t seed_lo, uint64_t seed_hi,
+                 uint32_t* out, uint64_t out_cap_rows, int out_on_device, gj_stats* stats) {
+  if (!c || !g || !q) return GJ_EINVAL;
+  auto t0 = std::chrono::steady_clock::now();
+  gj_stats st{};
+  bool overflow = false;
+  gj_status s = guarded(c, [&] {
+    GJ_CHECK(mode == GJ_MODE_COUNT || mode == GJ_MODE_ENUMERATE, GJ_EINVAL, "mode must be COUNT or ENUMERATE");
+    GJ_CHECK(mode == GJ_MODE_COUNT || out || out_cap_rows == 0, GJ_EINVAL, "null output buffer");
+    gj::run_static(c, g, q, mode, seed_lo, seed_hi, out, out_cap_rows, out_on_device, &st, overflow);
+  });
+  st.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats) *stats = st;
+  if (s == GJ_OK && overflow) {
+    c->err = "output buffer too small";
+    return GJ_EOVERFLOW;
+  }
+  return s;
+}
+
+gj_status gj_apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst, const int8_t* sign,
+                           uint64_t b, int on_device, const gj_query* const* qs, uint32_t nq, int64_t* count_delta,
+                           uint32_t* const* delta_rows, int8_t* const* delta_sign, const uint64_t* cap,
+                           uint64_t* n_delta, gj_stats* stats) {
+  if (!c || !g) return GJ_EINVAL;
+  auto t0 = std::chrono::steady_clock::now();
+  bool overflow = false;
+  gj_status s = guarded(c, [&] {
+    GJ_CHECK(b == 0 || (src && dst && sign), GJ_EINVAL, "null batch arrays");
+    GJ_CHECK(nq == 0 || qs, GJ_EINVAL, "null query list");
+    for (uint32_t i = 0; i < nq; ++i) GJ_CHECK(qs[i], GJ_EINVAL, "null query");
+    gj::apply_updates(c, g, src, dst, sign, b, on_device, qs, nq, count_delta, delta_rows, delta_sign, cap,
+                      n_delta, stats, overflow);
+  });
+  double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (stats)
+    for (uint32_t i = 0; i < nq; ++i) stats[i].ms = ms;
+  if (s == GJ_OK && overflow) {
+    c->err = "delta output buffer too small";
+    return GJ_EOVERFLOW;
+  }
+  return s;
+}
+
+gj_status gj_last_delta(gj_ctx* c, uint32_t q, uint32_t* rows, int8_t* signs, uint64_t cap, int on_device,
+                        uint64_t* n) {
+  if (!c || !n) return GJ_EINVAL;
+  bool overflow = false;
+  gj_status s = guarded(c, [&] {
+    GJ_CHECK(q < c->last_delta.size() && c->last_delta[q].kept, GJ_EINVAL,
+             "no delta rows kept for this query position");
+    const gj_ctx::LastDelta& ld = c->last_delta[q];
+    *n = ld.n;
+    if (ld.n > cap) {
+      overflow = true;
+      return;
+    }
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    if (rows && ld.n) GJ_HIP(hipMemcpyAsync(rows, ld.rows, ld.n * ld.m * sizeof(uint32_t), kind, c->stream));
+    if (signs && ld.n) GJ_HIP(hipMemcpyAsync(signs, ld.signs, ld.n, kind, c->stream));
+    GJ_HIP(hipStreamSynchronize(c->stream));
+  });
+  if (s == GJ_OK && overflow) {
+    c->err = "buffer too small for the kept delta rows";
+    return GJ_EOVERFLOW;
+  }
+  return s;
+}
+
+}  // extern "C"

@@ -1,0 +1,390 @@
+// Delta queries (Delta-GJ, Sec. 3.3.1; Delta-BiGJoin, Sec. 3.3.2 and 4.3).
+//
+// An update batch is normalised into a signed edge change dE, the next
+// version of both indexes is built next to the current one (old and new stay
+// resident together, the two versions every dQ_i reads), and for every atom i
+// of every query the delta query dQ_i runs through the same stage kernels as
+// the static path: seeded with dE on R_i's attributes, atoms before i read the
+// new version and atoms after i the old one, each prefix carrying the sign of
+// its seed.  The signed outputs of all dQ_i are consolidated per tuple.
+#include <algorithm>
+#include <cstring>
+
+#include "engine.h"
+#include "gj_internal.h"
+#include "prim.h"
+
+namespace gj {
+
+// ---------------------------------------------------------------- batch normalisation
+__global__ void k_batch_keys(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst,
+                             const int8_t* __restrict__ sign, uint64_t b, uint32_t n, uint64_t* __restrict__ keys,
+                             uint32_t* __restrict__ vals, uint32_t* __restrict__ bad) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b; i += gs) {
+    uint32_t s = src[i], d = dst[i];
+    int8_t g = sign[i];
+    if (s >= n || d >= n || (g != 1 && g != -1)) atomicOr(bad, 1u);
+    keys[i] = ((uint64_t)s << 32) | d;
+    vals[i] = g > 0 ? 1u : 0u;
+  }
+}
+
+// One flag per distinct (src, dst) of the sorted batch: 1 if it changes the
+// graph.  counters: [0] no-op inserts, [1] no-op deletes, [2] conflicts.
+__global__ void k_batch_classify(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ ins, uint64_t b,
+                                 const uint32_t* __restrict__ rp, const uint32_t* __restrict__ col,
+                                 uint32_t* __restrict__ flags, int8_t* __restrict__ dsign,
+                                 unsigned long long* __restrict__ counters) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b; i += gs) {
+    uint64_t k = keys[i];
+    flags[i] = 0;
+    if (i > 0 && keys[i - 1] == k) continue;  // not the head of its run
+    uint32_t s = (uint32_t)(k >> 32), d = (uint32_t)k;
+    bool any_ins = false, any_del = false;
+    for (uint64_t j = i; j < b && keys[j] == k; ++j) {
+      if (ins[j])
+        any_ins = true;
+      else
+        any_del = true;
+    }
+    if (s == d) continue;  // self-loops are dropped
+    if (any_ins && any_del) {
+      atomicAdd(counters + 2, 1ull);
+      continue;
+    }
+    bool present = contains_u32(col, rp[s], rp[s + 1], d);
+    if (any_ins && present) {
+      atomicAdd(counters + 0, 1ull);
+      continue;
+    }
+    if (any_del && !present) {
+      atomicAdd(counters + 1, 1ull);
+      continue;
+    }
+    flags[i] = 1;
+    dsign[i] = any_ins ? (int8_t)1 : (int8_t)-1;
+  }
+}
+
+__global__ void k_batch_compact(const uint64_t* __restrict__ keys, const int8_t* __restrict__ dsign,
+                                const uint32_t* __restrict__ flags, const uint64_t* __restrict__ off, uint64_t b,
+                                uint32_t* __restrict__ es, uint32_t* __restrict__ ed, int8_t* __restrict__ eg,
+                                uint64_t* __restrict__ swapped, uint32_t* __restrict__ sidx) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b; i += gs) {
+    if (!flags[i]) continue;
+    uint64_t p = off[i], k = keys[i];
+    es[p] = (uint32_t)(k >> 32);
+    ed[p] = (uint32_t)k;
+    eg[p] = dsign[i];
+    swapped[p] = (k << 32) | (k >> 32);
+    sidx[p] = (uint32_t)p;
+  }
+}
+
+// ---------------------------------------------------------------- versioned index update
+// dE of one direction: rows r[i], values x[i], signs g[i], sorted by (r, x);
+// drp = per-row ranges of dE (n + 1); ins_scan = exclusive scan of insert flags.
+struct DeltaDir {
+  const uint32_t* r;
+  const uint32_t* x;
+  const int8_t* g;
+  const uint32_t* drp;
+  const uint64_t* ins_scan;
+};
+
+__global__ void k_ins_flags(const int8_t* __restrict__ g, uint64_t k, uint32_t* __restrict__ f) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gs) f[i] = g[i] > 0 ? 1u : 0u;
+}
+
+// new degree of every row
+__global__ void k_new_deg(const uint32_t* __restrict__ rp, DeltaDir D, uint32_t n, uint32_t* __restrict__ deg) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gs) {
+    uint32_t a = D.drp[v], b = D.drp[v + 1];
+    uint32_t ins = (uint32_t)(D.ins_scan[b] - D.ins_scan[a]);
+    uint32_t del = (b - a) - ins;
+    deg[v] = rp[v + 1] - rp[v] + ins - del;
+  }
+}
+
+// copy the surviving old entries to their new positions
+__global__ void k_move_old(const uint32_t* __restrict__ orp, const uint32_t* __restrict__ ocol,
+                           const uint32_t* __restrict__ orow, uint64_t om, DeltaDir D,
+                           const uint32_t* __restrict__ nrp, uint32_t* __restrict__ ncol,
+                           uint32_t* __restrict__ nrow) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < om; e += gs) {
+    uint32_t r = orow[e], x = ocol[e];
+    uint32_t a = D.drp[r], b = D.drp[r + 1];
+    uint64_t pos = (uint64_t)nrp[r] + (e - orp[r]);
+    if (a != b) {
+      uint32_t i = lower_bound_u32(D.x, a, b, x);
+      if (i < b && D.x[i] == x) continue;  // deleted (an insert of a present edge never reaches dE)
+      uint32_t ins_before = (uint32_t)(D.ins_scan[i] - D.ins_scan[a]);
+      uint32_t del_before = (i - a) - ins_before;
+      pos = pos + ins_before - del_before;
+    }
+    ncol[pos] = x;
+    nrow[pos] = r;
+  }
+}
+
+// place the inserted entries
+__global__ void k_place_ins(const uint32_t* __restrict__ orp, const uint32_t* __restrict__ ocol, DeltaDir D,
+                            uint64_t k, const uint32_t* __restrict__ nrp, uint32_t* __restrict__ ncol,
+                            uint32_t* __restrict__ nrow) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gs) {
+    if (D.g[i] < 0) continue;
+    uint32_t r = D.r[i], x = D.x[i];
+    uint32_t a = D.drp[r];
+    uint32_t old_less = lower_bound_u32(ocol, orp[r], orp[r + 1], x) - orp[r];
+    uint32_t ins_before = (uint32_t)(D.ins_scan[i] - D.ins_scan[a]);
+    uint32_t del_before = ((uint32_t)i - a) - ins_before;  // every delete below x is an old entry below x
+    uint64_t pos = (uint64_t)nrp[r] + old_less - del_before + ins_before;
+    ncol[pos] = x;
+    nrow[pos] = r;
+  }
+}
+
+__global__ void k_rowptr_of(const uint32_t* __restrict__ row, uint64_t m, uint32_t n, uint32_t* __restrict__ rp) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += gs) {
+    uint64_t lo = 0, len = m;
+    while (len > 0) {
+      uint64_t half = len >> 1;
+      if (row[lo + half] < v) {
+        lo += half + 1;
+        len -= half + 1;
+      } else {
+        len = half;
+      }
+    }
+    rp[v] = (uint32_t)lo;
+  }
+}
+
+__global__ void k_unswap(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ idx,
+                         const int8_t* __restrict__ g, uint64_t k, uint32_t* __restrict__ r, uint32_t* __restrict__ x,
+                         int8_t* __restrict__ og) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gs) {
+    r[i] = (uint32_t)(keys[i] >> 32);
+    x[i] = (uint32_t)keys[i];
+    og[i] = g[idx[i]];
+  }
+}
+
+static void update_dir(gj_ctx* c, uint32_t n, const CsrDir& od, uint64_t om, const uint32_t* r, const uint32_t* x,
+                       const int8_t* g, uint64_t k, CsrDir& nd, const std::string& tag) {
+  uint32_t* drp = (uint32_t*)ws_get(c, "up_drp" + tag, ((uint64_t)n + 1) * sizeof(uint32_t));
+  uint32_t* insf = (uint32_t*)ws_get(c, "up_insf" + tag, (k + 1) * sizeof(uint32_t));
+  uint64_t* ins_scan = (uint64_t*)ws_get(c, "up_inss" + tag, (k + 1) * sizeof(uint64_t));
+  uint32_t* deg = (uint32_t*)ws_get(c, "up_deg", ((uint64_t)n + 1) * sizeof(uint32_t));
+  unsigned gn = grid_for((uint64_t)n + 1, kBlock, 1u << 16);
+  unsigned gk = grid_for(k, kBlock, 1u << 16);
+  k_rowptr_of<<<gn, kBlock, 0, c->stream>>>(r, k, n, drp);
+  k_ins_flags<<<gk, kBlock, 0, c->stream>>>(g, k, insf);
+  scan_u32_to_u64(c, insf, ins_scan, k);
+  DeltaDir D{r, x, g, drp, ins_scan};
+  k_new_deg<<<gn, kBlock, 0, c->stream>>>(od.rp, D, n, deg);
+  scan_u32(c, deg, nd.rp, n);
+  if (om) k_move_old<<<grid_for(om, kBlock, 1u << 16), kBlock, 0, c->stream>>>(od.rp, od.col, od.row, om, D, nd.rp, nd.col, nd.row);
+  k_place_ins<<<gk, kBlock, 0, c->stream>>>(od.rp, od.col, D, k, nd.rp, nd.col, nd.row);
+  GJ_HIP(hipGetLastError());
+}
+
+static void add_stats(gj_stats& a, const gj_stats& b) {
+  for (int j = 0; j <= GJ_MAX_ATTRS; ++j) {
+    a.prefixes[j] += b.prefixes[j];
+    a.extensions[j] += b.extensions[j];
+  }
+  a.kernel_ms += b.kernel_ms;
+  a.kernel_launches += b.kernel_launches;
+}
+
+void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst, const int8_t* sign, uint64_t b,
+                   int on_device, const gj_query* const* qs, uint32_t nq, int64_t* count_delta,
+                   uint32_t* const* out_rows, int8_t* const* out_signs, const uint64_t* cap, uint64_t* n_delta,
+                   gj_stats* stats, bool& overflow) {
+  overflow = false;
+  uint32_t n = g->n;
+  int bits = bits_for(n);
+  Version& ov = g->ver[g->cur];
+  Version& nv = g->ver[1 - g->cur];
+  c->last_delta.assign(nq, gj_ctx::LastDelta{});
+  for (uint32_t k = 0; k < nq; ++k) {
+    if (count_delta) count_delta[k] = 0;
+    if (n_delta) n_delta[k] = 0;
+    if (stats) memset(&stats[k], 0, sizeof(gj_stats));
+  }
+  GJ_CHECK(b < (1ull << 32), GJ_EUNSUPPORTED, "update batch of 2^32 rows or more");
+  // ---- upload and normalise the batch
+  const uint32_t *ds = src, *dd = dst;
+  const int8_t* dg = sign;
+  if (!on_device && b) {
+    uint32_t* s2 = (uint32_t*)ws_get(c, "ub_src", b * sizeof(uint32_t));
+    uint32_t* d2 = (uint32_t*)ws_get(c, "ub_dst", b * sizeof(uint32_t));
+    int8_t* g2 = (int8_t*)ws_get(c, "ub_sign", b);
+    GJ_HIP(hipMemcpyAsync(s2, src, b * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+    GJ_HIP(hipMemcpyAsync(d2, dst, b * sizeof(uint32_t), hipMemcpyHostToDevice, c->stream));
+    GJ_HIP(hipMemcpyAsync(g2, sign, b, hipMemcpyHostToDevice, c->stream));
+    ds = s2;
+    dd = d2;
+    dg = g2;
+  }
+  uint64_t* keys = (uint64_t*)ws_get(c, "ub_keys", (b + 1) * sizeof(uint64_t));
+  uint64_t* keys2 = (uint64_t*)ws_get(c, "ub_keys2", (b + 1) * sizeof(uint64_t));
+  uint32_t* vals = (uint32_t*)ws_get(c, "ub_vals", (b + 1) * sizeof(uint32_t));
+  uint32_t* vals2 = (uint32_t*)ws_get(c, "ub_vals2", (b + 1) * sizeof(uint32_t));
+  unsigned long long* cnt = (unsigned long long*)ws_get(c, "ub_cnt", 4 * sizeof(unsigned long long));
+  uint32_t* bad = (uint32_t*)ws_get(c, "ub_bad", sizeof(uint32_t));
+  GJ_HIP(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), c->stream));
+  GJ_HIP(hipMemsetAsync(bad, 0, sizeof(uint32_t), c->stream));
+  unsigned gb = grid_for(b, kBlock, 1u << 16);
+  if (b) k_batch_keys<<<gb, kBlock, 0, c->stream>>>(ds, dd, dg, b, n, keys, vals, bad);
+  uint32_t hbad = 0;
+  read_bytes(c, &hbad, bad, sizeof(hbad));
+  GJ_CHECK(!hbad, GJ_EINVAL, "update batch: vertex id >= num_vertices or sign not +-1");
+  sort_kv_u64(c, keys, vals, keys2, vals2, b, bits, bits);
+  uint32_t* flags = (uint32_t*)ws_get(c, "ub_flags", (b + 1) * sizeof(uint32_t));
+  int8_t* dsign = (int8_t*)ws_get(c, "ub_dsign", b + 1);
+  uint64_t* off = (uint64_t*)ws_get(c, "ub_off", (b + 1) * sizeof(uint64_t));
+  if (b) k_batch_classify<<<gb, kBlock, 0, c->stream>>>(keys, vals, b, ov.d[0].rp, ov.d[0].col, flags, dsign, cnt);
+  scan_u32_to_u64(c, flags, off, b);
+  unsigned long long hc[3];
+  read_bytes(c, hc, cnt, sizeof(hc));
+  GJ_CHECK(hc[2] == 0, GJ_EINVAL, "update batch inserts and deletes the same edge");
+  uint64_t k = read_u64(c, off + b);
+  // dE sorted by (src, dst) and by (dst, src)
+  uint32_t* es = (uint32_t*)ws_get(c, "de_src", (k + 1) * sizeof(uint32_t));
+  uint32_t* ed = (uint32_t*)ws_get(c, "de_dst", (k + 1) * sizeof(uint32_t));
+  int8_t* eg = (int8_t*)ws_get(c, "de_sign", k + 1);
+  uint64_t* sw = (uint64_t*)ws_get(c, "de_sw", (k + 1) * sizeof(uint64_t));
+  uint64_t* sw2 = (uint64_t*)ws_get(c, "de_sw2", (k + 1) * sizeof(uint64_t));
+  uint32_t* si = (uint32_t*)ws_get(c, "de_si", (k + 1) * sizeof(uint32_t));
+  uint32_t* si2 = (uint32_t*)ws_get(c, "de_si2", (k + 1) * sizeof(uint32_t));
+  if (b) k_batch_compact<<<gb, kBlock, 0, c->stream>>>(keys, dsign, flags, off, b, es, ed, eg, sw, si);
+  GJ_HIP(hipGetLastError());
+  for (uint32_t q = 0; q < nq; ++q) {
+    if (stats) {
+      stats[q].noop_inserts = hc[0];
+      stats[q].noop_deletes = hc[1];
+    }
+  }
+  if (k == 0) return;  // nothing changes: same version
+  sort_kv_u64(c, sw, si, sw2, si2, k, bits, bits);
+  uint32_t* rs = (uint32_t*)ws_get(c, "de_rsrc", (k + 1) * sizeof(uint32_t));
+  uint32_t* rd = (uint32_t*)ws_get(c, "de_rdst", (k + 1) * sizeof(uint32_t));
+  int8_t* rg = (int8_t*)ws_get(c, "de_rsign", k + 1);
+  k_unswap<<<grid_for(k, kBlock, 1u << 16), kBlock, 0, c->stream>>>(sw, si, eg, k, rd, rs, rg);
+  // ---- next version of both indexes
+  uint64_t ins_total = 0;
+  {
+    // upper bound of the new edge count: old + all of dE
+    version_alloc(nv, n, ov.m + k);
+  }
+  update_dir(c, n, ov.d[0], ov.m, es, ed, eg, k, nv.d[0], "f");
+  update_dir(c, n, ov.d[1], ov.m, rd, rs, rg, k, nv.d[1], "r");
+  uint32_t newm = 0;
+  read_bytes(c, &newm, nv.d[0].rp + n, sizeof(newm));
+  nv.m = newm;
+  (void)ins_total;
+  version_finish(c, nv, n);
+  // ---- delta queries
+  for (uint32_t qi = 0; qi < nq; ++qi) {
+    const gj_query* q = qs[qi];
+    bool want_rows = (out_rows && out_rows[qi]) || (out_signs && out_signs[qi]);
+    gj_stats acc{};
+    int64_t cd = 0;
+    uint64_t raw = 0;
+    uint32_t* all_rows = nullptr;
+    int8_t* all_signs = nullptr;
+    uint64_t all_n = 0, all_cap = 0;
+    for (int i = 0; i < (int)q->atoms.size(); ++i) {
+      PlanH P = make_plan(q, delta_order(q, i), i);
+      Views V{&ov, &nv, i};
+      Runner R(c, P, V, true, want_rows, std::max<uint64_t>(1, std::min<uint64_t>(c->seed_chunk, k)));
+      if (want_rows) R.own_rows(~0ull, true);
+      R.seed(es, ed, eg, k);
+      uint64_t matches = 0;
+      int64_t ws = 0;
+      R.finish(matches, ws);
+      add_stats(acc, R.st);
+      raw += matches;
+      if (!want_rows) {
+        cd += ws;
+        continue;
+      }
+      if (matches) {
+        if (all_n + matches > all_cap) {
+          uint64_t ncap = std::max<uint64_t>(all_n + matches, all_cap * 2);
+          uint32_t* nr = (uint32_t*)dev_alloc(ncap * q->m * sizeof(uint32_t));
+          int8_t* ns = (int8_t*)dev_alloc(ncap);
+          if (all_n) {
+            GJ_HIP(hipMemcpyAsync(nr, all_rows, all_n * q->m * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
+            GJ_HIP(hipMemcpyAsync(ns, all_signs, all_n, hipMemcpyDeviceToDevice, c->stream));
+            GJ_HIP(hipStreamSynchronize(c->stream));
+          }
+          dev_free(all_rows);
+          dev_free(all_signs);
+          all_rows = nr;
+          all_signs = ns;
+          all_cap = ncap;
+        }
+        GJ_HIP(hipMemcpyAsync(all_rows + all_n * q->m, R.rows, matches * q->m * sizeof(uint32_t),
+                              hipMemcpyDeviceToDevice, c->stream));
+        GJ_HIP(hipMemcpyAsync(all_signs + all_n, R.rsign, matches, hipMemcpyDeviceToDevice, c->stream));
+        GJ_HIP(hipStreamSynchronize(c->stream));
+        all_n += matches;
+      }
+    }
+    uint64_t nd = 0;
+    if (want_rows) {
+      try {
+        gj_ctx::LastDelta& ld = c->last_delta[qi];
+        ld.kept = true;
+        ld.m = q->m;
+        if (all_n) {
+          sort_rows(c, all_rows, all_signs, all_n, q->m, n);
+          ld.rows = (uint32_t*)ws_get(c, "dq_res_rows" + std::to_string(qi), all_n * q->m * sizeof(uint32_t));
+          ld.signs = (int8_t*)ws_get(c, "dq_res_signs" + std::to_string(qi), all_n);
+          nd = consolidate_rows(c, all_rows, all_signs, all_n, q->m, ld.rows, ld.signs, all_n, &cd);
+          ld.n = nd;
+          uint64_t ucap = cap ? cap[qi] : 0;
+          uint64_t w = std::min(nd, ucap);
+          uint32_t* orow = out_rows ? out_rows[qi] : nullptr;
+          int8_t* osg = out_signs ? out_signs[qi] : nullptr;
+          hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+          if (orow && w) GJ_HIP(hipMemcpyAsync(orow, ld.rows, w * q->m * sizeof(uint32_t), kind, c->stream));
+          if (osg && w) GJ_HIP(hipMemcpyAsync(osg, ld.signs, w, kind, c->stream));
+          GJ_HIP(hipStreamSynchronize(c->stream));
+          if (nd > ucap) overflow = true;
+        }
+      } catch (...) {
+        dev_free(all_rows);
+        dev_free(all_signs);
+        throw;
+      }
+      dev_free(all_rows);
+      dev_free(all_signs);
+    }
+    if (count_delta) count_delta[qi] = cd;
+    if (n_delta) n_delta[qi] = nd;
+    if (stats) {
+      acc.noop_inserts = hc[0];
+      acc.noop_deletes = hc[1];
+      acc.raw_emissions = raw;
+      acc.matches = raw;
+      stats[qi] = acc;
+    }
+  }
+  g->cur = 1 - g->cur;
+  g->version += 1;
+}
+
+}  // namespace gj

@@ -1,0 +1,300 @@
+// Host side of the plain Generic Join path: query plans, the depth-first
+// batch scheduler over bounded frontiers, and the static entry point.
+//
+// Scheduling follows the BiGJoin batching rule (Sec. 3.2 with the batching
+// optimisation of Sec. 3.1.2): candidates of a stage are proposed in batches
+// of at most B = frontier_cap, and each batch's survivors are extended to the
+// end before the next batch of the shallower stage is proposed (the deepest
+// stage with work always goes first).  Every frontier buffer therefore holds
+// at most B prefixes, and memory stays O(m * B) beside the indexes (Lemma 3.1).
+#include <algorithm>
+#include <cstring>
+
+#include "engine.h"
+#include "gj_internal.h"
+
+namespace gj {
+
+PlanH make_plan(const gj_query* q, const std::vector<int>& order, int forced_seed) {
+  PlanH P;
+  P.m = q->m;
+  P.order = order;
+  std::vector<int> pos(q->m);
+  for (int j = 0; j < q->m; ++j) pos[order[j]] = j;
+  P.bind.assign(q->m, {});
+  for (int i = 0; i < (int)q->atoms.size(); ++i) {
+    int s = q->atoms[i].src_attr, d = q->atoms[i].dst_attr;
+    int j = std::max(pos[s], pos[d]);
+    if (j == 1) {
+      bool is_seed = forced_seed >= 0 ? i == forced_seed : P.seed_atom < 0;
+      if (is_seed) {
+        P.seed_atom = i;
+        P.seed_fwd = pos[s] == 0;
+      } else {
+        // keep (x0, x1) iff edge(x_s, x_d): x_d in out(x_s)
+        P.filters.push_back({i, pos[s], pos[d]});
+      }
+    } else if (pos[d] == j) {
+      P.bind[j].push_back({i, pos[s], 0});  // edge(y, x): x in out(y)
+    } else {
+      P.bind[j].push_back({i, pos[d], 1});  // edge(x, y): x in in(y)
+    }
+  }
+  for (int j = 2; j < q->m; ++j)
+    GJ_CHECK(P.bind[j].size() <= (size_t)kMaxBind, GJ_EUNSUPPORTED, "more than 8 atoms bind one attribute");
+  GJ_CHECK(P.filters.size() <= (size_t)kMaxBind, GJ_EUNSUPPORTED, "more than 8 atoms over the first two attributes");
+  return P;
+}
+
+StageDesc stage_desc(const PlanH& P, const Views& V, int j) {
+  StageDesc d;
+  memset(&d, 0, sizeof(d));
+  d.j = j;
+  d.k = (int)P.bind[j].size();
+  for (int a = 0; a < d.k; ++a) {
+    const BindH& b = P.bind[j][a];
+    const Version& v = V.of(b.atom);
+    d.col[a] = b.col;
+    d.rp[a] = v.d[b.dir].rp;
+    d.adj[a] = v.d[b.dir].col;
+  }
+  for (int a = d.k; a < kMaxBind; ++a) {
+    d.col[a] = 0;
+    d.rp[a] = d.rp[0];
+    d.adj[a] = d.adj[0];
+  }
+  return d;
+}
+
+SeedFilter seed_filter(const PlanH& P, const Views& V) {
+  SeedFilter f;
+  memset(&f, 0, sizeof(f));
+  f.n = (int)P.filters.size();
+  for (int a = 0; a < f.n; ++a) {
+    const Version& v = V.of(P.filters[a].atom);
+    f.key[a] = P.filters[a].key;
+    f.val[a] = P.filters[a].val;
+    f.rp[a] = v.d[0].rp;
+    f.adj[a] = v.d[0].col;
+  }
+  return f;
+}
+
+// Order of dQ_i: the atom's (src, dst), then repeatedly the earliest attribute
+// of the global order that shares an atom with a bound attribute.
+std::vector<int> delta_order(const gj_query* q, int i) {
+  std::vector<int> ord = {q->atoms[i].src_attr, q->atoms[i].dst_attr};
+  std::vector<int> bound(q->m, 0);
+  bound[ord[0]] = bound[ord[1]] = 1;
+  while ((int)ord.size() < q->m) {
+    int pick = -1;
+    for (int a : q->order) {
+      if (bound[a]) continue;
+      bool adj = false;
+      for (auto& at : q->atoms)
+        if ((at.src_attr == a && bound[at.dst_attr]) || (at.dst_attr == a && bound[at.src_attr])) adj = true;
+      if (adj) {
+        pick = a;
+        break;
+      }
+    }
+    GJ_CHECK(pick >= 0, GJ_EINVAL, "query graph is not connected");
+    ord.push_back(pick);
+    bound[pick] = 1;
+  }
+  return ord;
+}
+
+// Plans of the static order and of every delta query must fit the kernels.
+void PlanHCheck(const gj_query* q) {
+  make_plan(q, q->order, -1);
+  for (int i = 0; i < (int)q->atoms.size(); ++i) make_plan(q, delta_order(q, i), i);
+}
+
+// ---------------------------------------------------------------- Runner
+Runner::Runner(gj_ctx* c_, const PlanH& P_, const Views& V_, bool weighted_, bool collect_, uint64_t seed_cap)
+    : c(c_), P(P_), V(V_), weighted(weighted_), collect(collect_), timer(c_) {
+  map.m = P.m;
+  for (int k = 0; k < P.m; ++k) map.attr[k] = P.order[k];
+  uint64_t fcap = c->frontier_cap;
+  for (int j = 2; j < P.m; ++j) {
+    Level& l = L[j];
+    l.cap = j == 2 ? seed_cap : fcap;
+    std::string t = "L" + std::to_string(j) + "_";
+    l.F = (uint32_t*)ws_get(c, t + "F", l.cap * j * sizeof(uint32_t) + 16);
+    l.Fw = weighted ? (int8_t*)ws_get(c, t + "Fw", l.cap + 16) : nullptr;
+    l.minc = (uint32_t*)ws_get(c, t + "minc", l.cap * sizeof(uint32_t) + 16);
+    l.mini = (uint8_t*)ws_get(c, t + "mini", l.cap + 16);
+    l.off = (uint64_t*)ws_get(c, t + "off", (l.cap + 1) * sizeof(uint64_t));
+    uint64_t words = fcap / 64 + 2;
+    l.mask = (uint64_t*)ws_get(c, t + "mask", words * sizeof(uint64_t));
+    l.wcnt = (uint32_t*)ws_get(c, t + "wcnt", words * sizeof(uint32_t));
+    l.woff = (uint64_t*)ws_get(c, t + "woff", (words + 1) * sizeof(uint64_t));
+  }
+  if (P.m == 2) {
+    Level& l = L[2];
+    l.cap = seed_cap;
+    l.F = (uint32_t*)ws_get(c, "L2_F", l.cap * 2 * sizeof(uint32_t) + 16);
+    l.Fw = weighted ? (int8_t*)ws_get(c, "L2_Fw", l.cap + 16) : nullptr;
+  }
+  acc = (unsigned long long*)ws_get(c, "acc", 4 * sizeof(unsigned long long));
+  GJ_HIP(hipMemsetAsync(acc, 0, 4 * sizeof(unsigned long long), c->stream));
+  seed_flags = (uint32_t*)ws_get(c, "seed_flags", (seed_cap + 1) * sizeof(uint32_t));
+  seed_off = (uint64_t*)ws_get(c, "seed_off", (seed_cap + 1) * sizeof(uint64_t));
+}
+
+Runner::~Runner() {
+  if (rows_owned) dev_free(rows);
+  if (signs_owned) dev_free(rsign);
+}
+
+void Runner::use_rows(uint32_t* dev_rows, int8_t* dev_signs, uint64_t cap) {
+  rows = dev_rows;
+  rsign = dev_signs;
+  rcap = cap;
+  rows_alloc = cap;
+}
+
+void Runner::own_rows(uint64_t cap, bool with_signs) {
+  rows_owned = true;
+  signs_owned = with_signs;
+  rcap = cap;
+  rows_alloc = 0;
+  want_signs = with_signs;
+}
+
+// grows an internal row buffer (keeping its contents) to hold `need` rows
+void Runner::ensure_rows(uint64_t need) {
+  if (!rows_owned || need <= rows_alloc) return;
+  uint64_t want = std::max<uint64_t>(need, rows_alloc * 2);
+  want = std::min<uint64_t>(std::max<uint64_t>(want, 1024), rcap);
+  if (want <= rows_alloc) return;
+  uint32_t* nr = (uint32_t*)dev_alloc(want * P.m * sizeof(uint32_t));
+  int8_t* ns = want_signs ? (int8_t*)dev_alloc(want) : nullptr;
+  if (rows_alloc) {
+    GJ_HIP(hipMemcpyAsync(nr, rows, rows_alloc * P.m * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
+    if (ns) GJ_HIP(hipMemcpyAsync(ns, rsign, rows_alloc, hipMemcpyDeviceToDevice, c->stream));
+    GJ_HIP(hipStreamSynchronize(c->stream));
+  }
+  dev_free(rows);
+  dev_free(rsign);
+  rows = nr;
+  rsign = ns;
+  rows_alloc = want;
+}
+
+void Runner::seed(const uint32_t* x0, const uint32_t* x1, const int8_t* w, uint64_t cnt) {
+  uint64_t chunk = L[2].cap;
+  SeedFilter f = seed_filter(P, V);
+  for (uint64_t s = 0; s < cnt; s += chunk) {
+    uint64_t k = std::min(chunk, cnt - s);
+    launch_seed(c, x0 + s, x1 + s, w ? w + s : nullptr, k, f, seed_flags, seed_off, L[2].F, L[2].cap,
+                weighted ? L[2].Fw : nullptr);
+    uint64_t n2 = read_u64(c, seed_off + k);
+    stage(2, n2);
+  }
+}
+
+void Runner::stage(int j, uint64_t n) {
+  st.prefixes[j] += n;
+  Level& l = L[j];
+  if (j == P.m) {  // two-attribute query: P_2 is the result
+    if (collect) ensure_rows(std::min(rcap, nrows + n));
+    launch_rows_from_frontier(c, l.F, l.cap, n, l.Fw, map, collect ? rows : nullptr, collect ? rsign : nullptr,
+                              nrows, collect ? std::min(rcap, rows_alloc) : 0, acc);
+    nrows += n;
+    return;
+  }
+  if (n == 0) return;
+  StageDesc d = stage_desc(P, V, j);
+  launch_count_min(c, l.F, l.cap, n, d, l.minc, l.mini);
+  scan_u32_to_u64(c, l.minc, l.off, n);
+  uint64_t W = read_u64(c, l.off + n);
+  st.extensions[j] += W;
+  if (W == 0) return;
+  bool final = j + 1 == P.m;
+  if (final && !collect) {
+    timer.start();
+    launch_propose(c, weighted ? 2 : 1, l.F, l.cap, n, l.off, l.mini, d, 0, W, nullptr, nullptr, l.Fw, acc);
+    timer.stop();
+    return;
+  }
+  uint64_t piece = c->frontier_cap;
+  for (uint64_t w0 = 0; w0 < W; w0 += piece) {
+    uint64_t w1 = std::min(W, w0 + piece);
+    uint64_t words = (w1 - w0 + 63) >> 6;
+    timer.start();
+    launch_propose(c, 0, l.F, l.cap, n, l.off, l.mini, d, w0, w1, l.mask, l.wcnt, nullptr, nullptr);
+    timer.stop();
+    scan_u32_to_u64(c, l.wcnt, l.woff, words);
+    uint64_t T = read_u64(c, l.woff + words);
+    if (T == 0) continue;
+    if (final) {
+      st.prefixes[j + 1] += T;
+      ensure_rows(std::min(rcap, nrows + T));
+      launch_emit(c, true, l.F, l.cap, n, l.off, l.mini, d, w0, w1, l.mask, l.woff, l.Fw, rows, 0, rsign, map,
+                  nrows, std::min(rcap, rows_alloc));
+      nrows += T;
+    } else {
+      Level& nl = L[j + 1];
+      launch_emit(c, false, l.F, l.cap, n, l.off, l.mini, d, w0, w1, l.mask, l.woff, l.Fw, nl.F, nl.cap,
+                  weighted ? nl.Fw : nullptr, map, 0, 0);
+      stage(j + 1, T);
+    }
+  }
+}
+
+// counts: acc[0] unsigned matches, acc[1] signed weight sum
+void Runner::finish(uint64_t& matches, int64_t& wsum) {
+  unsigned long long h[2];
+  read_bytes(c, h, acc, sizeof(h));
+  if (collect) {
+    matches = nrows;
+    wsum = 0;
+  } else {
+    matches = P.m == 2 ? nrows : h[0];
+    wsum = (int64_t)h[1];
+  }
+  if (P.m >= 3) st.prefixes[P.m] = matches;
+  st.kernel_ms = timer.total_ms();
+  st.kernel_launches = timer.launches();
+}
+
+static bool identity(const std::vector<int>& o) {
+  for (int i = 0; i < (int)o.size(); ++i)
+    if (o[i] != i) return false;
+  return true;
+}
+
+void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint64_t lo, uint64_t hi,
+                uint32_t* out, uint64_t cap, int out_on_device, gj_stats* st, bool& overflow) {
+  PlanH P = make_plan(q, q->order, -1);
+  const Version& v = g->ver[g->cur];
+  Views V{&v, &v, -1};
+  int dir = P.seed_fwd ? 0 : 1;
+  hi = std::min<uint64_t>(hi, v.m);
+  lo = std::min<uint64_t>(lo, hi);
+  bool collect = mode == GJ_MODE_ENUMERATE;
+  uint64_t seed_cap = std::max<uint64_t>(1, std::min<uint64_t>(c->seed_chunk, hi - lo));
+  Runner R(c, P, V, false, collect, seed_cap);
+  if (collect) {
+    if (out_on_device)
+      R.use_rows(out, nullptr, cap);
+    else
+      R.own_rows(cap, false);
+  }
+  R.seed(v.d[dir].row + lo, v.d[dir].col + lo, nullptr, hi - lo);
+  uint64_t matches = 0;
+  int64_t ws = 0;
+  R.finish(matches, ws);
+  overflow = collect && matches > cap;
+  if (collect && !overflow && matches > 1 && !identity(P.order))
+    sort_rows(c, R.rows, nullptr, matches, P.m, g->n);
+  if (collect && !overflow && !out_on_device && matches)
+    GJ_HIP(hipMemcpyAsync(out, R.rows, matches * P.m * sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  GJ_HIP(hipStreamSynchronize(c->stream));
+  R.st.matches = matches;
+  *st = R.st;
+}
+
+}  // namespace gj

@@ -1,0 +1,207 @@
+// Internal declarations shared by the HIP sources of libgj.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/gj.h"
+
+namespace gj {
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
+constexpr int kMaxBind = 8;       // binding atoms per stage handled by the kernels
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  gj_status code;
+  std::string msg;
+};
+
+#define GJ_HIP(call)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      throw ::gj::Error{GJ_EDEVICE, std::string(#call) + ": " +             \
+                                        hipGetErrorString(e_)};             \
+  } while (0)
+
+#define GJ_CHECK(cond, code, msg)                      \
+  do {                                                 \
+    if (!(cond)) throw ::gj::Error{(code), (msg)};     \
+  } while (0)
+
+// ---------------------------------------------------------------- device structs
+// One stage P_j -> P_{j+1}: the atoms binding the new attribute.  For binding
+// atom a the extension set of prefix p is adj[a][rp[a][v] .. rp[a][v+1]) with
+// v = prefix column col[a] of p.  Binding atoms are in atom-index order so
+// that count-minimisation ties resolve to the lowest atom.
+struct StageDesc {
+  int j;                 // bound columns
+  int k;                 // binding atoms (1..kMaxBind)
+  int col[kMaxBind];
+  const uint32_t* rp[kMaxBind];
+  const uint32_t* adj[kMaxBind];
+};
+
+// Membership filters of the seed pairs (atoms over the first two attributes
+// other than the seed atom): keep (x0, x1) iff x[val] is in adj[rp[x[key]]..].
+struct SeedFilter {
+  int n;
+  int key[kMaxBind];
+  int val[kMaxBind];
+  const uint32_t* rp[kMaxBind];
+  const uint32_t* adj[kMaxBind];
+};
+
+// Column permutation for final rows: value of prefix column c goes to
+// attribute attr[c] of a row of m values.
+struct RowMap {
+  int m;
+  int attr[GJ_MAX_ATTRS];
+};
+
+// ---------------------------------------------------------------- host structs
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct CsrDir {
+  uint32_t* rp = nullptr;   // n + 1
+  uint32_t* col = nullptr;  // cap
+  uint32_t* row = nullptr;  // cap
+};
+
+struct Version {
+  CsrDir d[2];  // 0 forward, 1 reverse
+  uint64_t m = 0, cap = 0;
+  uint32_t max_deg[2] = {0, 0};
+};
+
+}  // namespace gj
+
+struct gj_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  uint64_t frontier_cap = 1ull << 25;
+  uint64_t seed_chunk = 1ull << 25;
+  int strategy = 0;
+  int num_cus = 256;
+  std::map<std::string, gj::DevBuf> ws;
+  void* pinned = nullptr;  // small pinned host staging (4 KiB)
+  std::vector<hipEvent_t> events;  // pool for kernel timing (pairs)
+  // consolidated delta rows of the last gj_apply_updates, per query position
+  struct LastDelta {
+    bool kept = false;
+    int m = 0;
+    uint64_t n = 0;
+    uint32_t* rows = nullptr;
+    int8_t* signs = nullptr;
+  };
+  std::vector<LastDelta> last_delta;
+};
+
+struct gj_graph {
+  gj_ctx* ctx = nullptr;
+  uint32_t n = 0;
+  gj::Version ver[2];
+  int cur = 0;
+  uint64_t version = 0;
+};
+
+struct gj_query {
+  int m = 0;
+  std::vector<gj_atom> atoms;
+  std::vector<int> order;
+};
+
+namespace gj {
+
+// ---------------------------------------------------------------- host helpers
+// Times the hot kernels of one call with HIP events on the context stream.
+class KernelTimer {
+ public:
+  explicit KernelTimer(gj_ctx* c) : c_(c) {}
+  void start();
+  void stop();
+  // synchronises the stream; returns summed milliseconds of the recorded pairs
+  double total_ms();
+  uint64_t launches() const { return n_; }
+
+ private:
+  gj_ctx* c_;
+  size_t n_ = 0;
+};
+
+void* ws_get(gj_ctx* c, const std::string& name, size_t bytes);
+void dev_free(void* p);
+void* dev_alloc(size_t bytes);
+uint64_t read_u64(gj_ctx* c, const void* dptr);
+void read_bytes(gj_ctx* c, void* host, const void* dptr, size_t bytes);
+
+inline unsigned grid_for(uint64_t items, uint64_t per_block, unsigned cap = 1u << 20) {
+  uint64_t g = (items + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// scan.hip: exclusive scans; out has n + 1 entries (out[n] = total)
+void scan_u32_to_u64(gj_ctx* c, const uint32_t* in, uint64_t* out, uint64_t n);
+void scan_u64(gj_ctx* c, const uint64_t* in, uint64_t* out, uint64_t n);
+void scan_u32(gj_ctx* c, const uint32_t* in, uint32_t* out, uint64_t n);
+
+// sort.hip: stable LSD radix sorts; return the buffer holding the result
+uint64_t* sort_u64(gj_ctx* c, uint64_t* keys, uint64_t* alt, uint64_t n, int lo_bits, int hi_bits);
+// sorts (key, val) pairs by key (stable); key/val and alt buffers swap
+void sort_kv_u64(gj_ctx* c, uint64_t*& key, uint32_t*& val, uint64_t*& key_alt, uint32_t*& val_alt,
+                 uint64_t n, int lo_bits, int hi_bits);
+void sort_kv_u32(gj_ctx* c, uint32_t*& key, uint32_t*& val, uint32_t*& key_alt,
+                 uint32_t*& val_alt, uint64_t n, int bits);
+
+// graph.hip
+void graph_build(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m);
+void version_alloc(Version& v, uint32_t n, uint64_t cap);
+void version_free(Version& v);
+
+// stage.hip
+void launch_seed(gj_ctx* c, const uint32_t* x0, const uint32_t* x1, const int8_t* w, uint64_t cnt,
+                 const SeedFilter& f, uint32_t* flags, uint64_t* off, uint32_t* F, uint64_t stride,
+                 int8_t* Fw);
+void launch_count_min(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const StageDesc& d,
+                      uint32_t* minc, uint8_t* mini);
+void launch_propose(gj_ctx* c, int mode, const uint32_t* F, uint64_t stride, uint64_t n, const uint64_t* off,
+                    const uint8_t* mini, const StageDesc& d, uint64_t w0, uint64_t w1, uint64_t* mask,
+                    uint32_t* wcnt, const int8_t* wt, unsigned long long* acc);
+void launch_emit(gj_ctx* c, bool final_rows, const uint32_t* F, uint64_t stride, uint64_t n, const uint64_t* off,
+                 const uint8_t* mini, const StageDesc& d, uint64_t w0, uint64_t w1, const uint64_t* mask,
+                 const uint64_t* woff, const int8_t* wt, uint32_t* G, uint64_t gstride, int8_t* Gw,
+                 const RowMap& map, uint64_t obase, uint64_t ocap);
+void launch_rows_from_frontier(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const int8_t* wt,
+                               const RowMap& map, uint32_t* rows, int8_t* osign, uint64_t obase, uint64_t ocap,
+                               unsigned long long* acc);
+
+// rows.hip: sort rows (and optional signs) ascending; consolidate signed rows
+void sort_rows(gj_ctx* c, uint32_t* rows, int8_t* signs, uint64_t nrows, int m, uint32_t nverts);
+uint64_t consolidate_rows(gj_ctx* c, const uint32_t* rows, const int8_t* signs, uint64_t nrows, int m,
+                          uint32_t* out_rows, int8_t* out_signs, uint64_t cap, int64_t* sum);
+int bits_for(uint32_t n);
+void version_finish(gj_ctx* c, Version& v, uint32_t n);
+
+// engine.hip
+void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint64_t lo,
+                uint64_t hi, uint32_t* out, uint64_t cap, int out_on_device, gj_stats* st,
+                bool& overflow);
+void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst,
+                   const int8_t* sign, uint64_t b, int on_device, const gj_query* const* qs,
+                   uint32_t nq, int64_t* count_delta, uint32_t* const* rows,
+                   int8_t* const* signs, const uint64_t* cap, uint64_t* n_delta,
+                   gj_stats* stats, bool& overflow);
+
+}  // namespace gj

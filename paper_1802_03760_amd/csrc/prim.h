@@ -1,0 +1,135 @@
+// Wave64 / workgroup primitives used by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace gj {
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  int l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+
+__device__ __forceinline__ uint64_t shfl_up_u64(uint64_t v, int o) {
+  uint32_t lo = __shfl_up((unsigned)v, o, 64);
+  uint32_t hi = __shfl_up((unsigned)(v >> 32), o, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_down_u64(uint64_t v, int o) {
+  uint32_t lo = __shfl_down((unsigned)v, o, 64);
+  uint32_t hi = __shfl_down((unsigned)(v >> 32), o, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_u64(uint64_t v, int src) {
+  uint32_t lo = __shfl((unsigned)v, src, 64);
+  uint32_t hi = __shfl((unsigned)(v >> 32), src, 64);
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t t = __shfl_up(v, o, 64);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+  int l = lane_id();
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint64_t t = shfl_up_u64(v, o);
+    if (l >= o) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum(uint64_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += shfl_down_u64(v, o);
+  return shfl_u64(v, 0);
+}
+__device__ __forceinline__ uint32_t wave_max(uint32_t v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    uint32_t t = __shfl_down(v, o, 64);
+    v = t > v ? t : v;
+  }
+  return __shfl(v, 0, 64);
+}
+
+// Exclusive scan over the workgroup (blockDim.x == NT, NT/64 waves).
+// `total` receives the workgroup sum.  Contains __syncthreads.
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T& total) {
+  __shared__ T wsum[NT / 64];
+  T inc = wave_incl_scan(v);
+  if (lane_id() == 63) wsum[wave_id()] = inc;
+  __syncthreads();
+  T before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    T s = wsum[w];
+    if (w < wave_id()) before += s;
+    all += s;
+  }
+  __syncthreads();
+  total = all;
+  return before + inc - v;
+}
+
+template <int NT>
+__device__ __forceinline__ uint64_t block_sum(uint64_t v) {
+  __shared__ uint64_t wsum[NT / 64];
+  v = wave_sum(v);
+  if (lane_id() == 0) wsum[wave_id()] = v;
+  __syncthreads();
+  uint64_t all = 0;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) all += wsum[w];
+  __syncthreads();
+  return all;
+}
+
+// lower_bound of x in sorted a[lo, hi): first index with a[i] >= x
+__device__ __forceinline__ uint32_t lower_bound_u32(const uint32_t* __restrict__ a, uint32_t lo,
+                                                    uint32_t hi, uint32_t x) {
+  uint32_t n = hi - lo;
+  while (n > 0) {
+    uint32_t half = n >> 1;
+    if (a[lo + half] < x) {
+      lo += half + 1;
+      n -= half + 1;
+    } else {
+      n = half;
+    }
+  }
+  return lo;
+}
+
+__device__ __forceinline__ bool contains_u32(const uint32_t* __restrict__ a, uint32_t lo,
+                                             uint32_t hi, uint32_t x) {
+  uint32_t i = lower_bound_u32(a, lo, hi, x);
+  return i < hi && a[i] == x;
+}
+
+// p in [lo, hi) with off[p] <= g < off[p+1]; requires off[lo] <= g < off[hi].
+__device__ __forceinline__ uint64_t find_segment(const uint64_t* __restrict__ off, uint64_t lo,
+                                                 uint64_t hi, uint64_t g) {
+  while (hi - lo > 1) {
+    uint64_t mid = (lo + hi) >> 1;
+    if (off[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace gj

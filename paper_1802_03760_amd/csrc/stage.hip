@@ -1,0 +1,306 @@
+// Generic Join prefix-extension stage P_j -> P_{j+1} (Sec. 2.2; the three
+// steps of the dataflow primitive, Sec. 3.1): count-minimisation over the
+// atoms binding the next attribute, proposal from the smallest extension set,
+// and intersection of every proposal with the other sets.
+//
+// Frontiers are column-major: column c of prefix p at F[c * stride + p].  The
+// candidates of a stage form one index space [0, W): prefix p owns
+// [off[p], off[p+1]) with off the exclusive scan of its smallest set size, so
+// work is split in equal candidate ranges whatever the degree skew (the
+// (prefix, range) split of Sec. 3.4, applied inside the GPU).  Each wave takes
+// 64 consecutive candidates, keeps a 64-bit ballot of the survivors, and a
+// later pass writes survivors in candidate order, so every frontier stays
+// sorted in the order's lexicographic order.
+#include "gj_internal.h"
+#include "prim.h"
+
+namespace gj {
+
+// ---------------------------------------------------------------- seeding P_2
+// Seed pairs (x0[i], x1[i]) (the seed atom's edges, or a signed update batch)
+// pass the membership filters of the other atoms over the first two attributes.
+__global__ void k_seed_flags(const uint32_t* __restrict__ x0, const uint32_t* __restrict__ x1, uint64_t cnt,
+                             SeedFilter f, uint32_t* __restrict__ flags) {
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride) {
+    uint32_t x[2] = {x0[i], x1[i]};
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < kMaxBind; ++a) {
+      if (a < f.n && ok) {
+        uint32_t key = f.key[a] ? x[1] : x[0];
+        uint32_t val = f.val[a] ? x[1] : x[0];
+        ok = contains_u32(f.adj[a], f.rp[a][key], f.rp[a][key + 1], val);
+      }
+    }
+    flags[i] = ok ? 1u : 0u;
+  }
+}
+
+__global__ void k_seed_scatter(const uint32_t* __restrict__ x0, const uint32_t* __restrict__ x1,
+                               const int8_t* __restrict__ w, uint64_t cnt, const uint32_t* __restrict__ flags,
+                               const uint64_t* __restrict__ off, uint32_t* __restrict__ F, uint64_t stride,
+                               int8_t* __restrict__ Fw) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += gs) {
+    if (!flags[i]) continue;
+    uint64_t p = off[i];
+    F[p] = x0[i];
+    F[stride + p] = x1[i];
+    if (Fw) Fw[p] = w ? w[i] : (int8_t)1;
+  }
+}
+
+// ---------------------------------------------------------------- count-minimisation
+// min_c = smallest extension-set size over the binding atoms, min_i = its
+// binding index (ties: lowest, i.e. lowest atom index).
+__global__ void k_count_min(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n, StageDesc d,
+                            uint32_t* __restrict__ minc, uint8_t* __restrict__ mini) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
+    uint32_t best = 0xFFFFFFFFu;
+    int bi = 0;
+#pragma unroll
+    for (int a = 0; a < kMaxBind; ++a) {
+      if (a < d.k) {
+        uint32_t v = F[(uint64_t)d.col[a] * stride + p];
+        uint32_t c = d.rp[a][v + 1] - d.rp[a][v];
+        if (c < best) {
+          best = c;
+          bi = a;
+        }
+      }
+    }
+    minc[p] = best;
+    mini[p] = (uint8_t)bi;
+  }
+}
+
+// ---------------------------------------------------------------- propose + intersect
+// Candidate g of the range: its prefix p, the proposing atom, the proposed value.
+struct Cand {
+  uint64_t p;
+  uint32_t e;
+  int am;
+};
+
+__device__ __forceinline__ Cand resolve(const uint32_t* __restrict__ F, uint64_t stride,
+                                        const uint64_t* __restrict__ off, const uint8_t* __restrict__ mini,
+                                        const StageDesc& d, uint64_t plo, uint64_t phi, uint64_t g) {
+  Cand c;
+  c.p = find_segment(off, plo, phi, g);
+  uint32_t k = (uint32_t)(g - off[c.p]);
+  c.am = mini[c.p];
+  const uint32_t* rp = d.rp[0];
+  const uint32_t* adj = d.adj[0];
+  int col = d.col[0];
+#pragma unroll
+  for (int a = 1; a < kMaxBind; ++a) {
+    if (a == c.am) {
+      rp = d.rp[a];
+      adj = d.adj[a];
+      col = d.col[a];
+    }
+  }
+  uint32_t v = F[(uint64_t)col * stride + c.p];
+  c.e = adj[rp[v] + k];
+  return c;
+}
+
+__device__ __forceinline__ bool intersect_all(const uint32_t* __restrict__ F, uint64_t stride, const StageDesc& d,
+                                              const Cand& c) {
+  bool keep = true;
+#pragma unroll
+  for (int a = 0; a < kMaxBind; ++a) {
+    if (a < d.k && a != c.am && keep) {
+      uint32_t u = F[(uint64_t)d.col[a] * stride + c.p];
+      keep = contains_u32(d.adj[a], d.rp[a][u], d.rp[a][u + 1], c.e);
+    }
+  }
+  return keep;
+}
+
+// Prefix range covering candidates [gf, gl] (wave-uniform).
+__device__ __forceinline__ void wave_prefix_range(const uint64_t* __restrict__ off, uint64_t n, uint64_t gf,
+                                                  uint64_t gl, uint64_t& plo, uint64_t& phi) {
+  plo = find_segment(off, 0, n, gf);
+  phi = find_segment(off, plo, n, gl) + 1;
+}
+
+// MODE 0: write survivor ballots mask[word] and counts wcnt[word].
+// MODE 1: acc[0] += survivors.
+// MODE 2: acc[0] += survivors, acc[1] += sum of survivor weights (signed).
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_propose(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n,
+                                                    const uint64_t* __restrict__ off,
+                                                    const uint8_t* __restrict__ mini, StageDesc d, uint64_t w0,
+                                                    uint64_t w1, uint64_t* __restrict__ mask,
+                                                    uint32_t* __restrict__ wcnt, const int8_t* __restrict__ wt,
+                                                    unsigned long long* __restrict__ acc) {
+  const int lane = lane_id();
+  const uint64_t nwords = (w1 - w0 + 63) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  uint64_t cnt = 0;
+  int64_t wsum = 0;
+  for (uint64_t wd = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wd < nwords; wd += nwaves) {
+    uint64_t gf = w0 + (wd << 6);
+    uint64_t gl = gf + 63 < w1 ? gf + 63 : w1 - 1;
+    uint64_t g = gf + lane;
+    bool keep = false;
+    int8_t w = 1;
+    uint64_t plo, phi;
+    wave_prefix_range(off, n, gf, gl, plo, phi);
+    if (g < w1) {
+      Cand c = resolve(F, stride, off, mini, d, plo, phi, g);
+      keep = intersect_all(F, stride, d, c);
+      if (MODE == 2) w = wt[c.p];
+    }
+    uint64_t b = __ballot(keep);
+    if (MODE == 0) {
+      if (lane == 0) {
+        mask[wd] = b;
+        wcnt[wd] = (uint32_t)__popcll(b);
+      }
+    } else {
+      cnt += keep ? 1 : 0;
+      if (MODE == 2) wsum += keep ? w : 0;
+    }
+  }
+  if (MODE != 0) {
+    uint64_t t = block_sum<kBlock>(cnt);
+    if (threadIdx.x == 0 && t) atomicAdd(acc, (unsigned long long)t);
+    if (MODE == 2) {
+      uint64_t s = block_sum<kBlock>((uint64_t)wsum);
+      if (threadIdx.x == 0 && s) atomicAdd(acc + 1, (unsigned long long)s);
+    }
+  }
+}
+
+// Writes the survivors of [w0, w1) in candidate order.
+// FINAL = false: prefixes p . e into frontier G (j + 1 columns), weights to Gw.
+// FINAL = true: rows of map.m values in attribute order at rows[(obase+pos)*m],
+// signs to osign, only for obase + pos < ocap.
+template <bool FINAL>
+__global__ void __launch_bounds__(kBlock) k_emit(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n,
+                                                 const uint64_t* __restrict__ off, const uint8_t* __restrict__ mini,
+                                                 StageDesc d, uint64_t w0, uint64_t w1,
+                                                 const uint64_t* __restrict__ mask, const uint64_t* __restrict__ woff,
+                                                 const int8_t* __restrict__ wt, uint32_t* __restrict__ G,
+                                                 uint64_t gstride, int8_t* __restrict__ Gw, RowMap map,
+                                                 uint64_t obase, uint64_t ocap) {
+  const int lane = lane_id();
+  const uint64_t nwords = (w1 - w0 + 63) >> 6;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t wd = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wd < nwords; wd += nwaves) {
+    uint64_t b = mask[wd];
+    if (b == 0) continue;
+    uint64_t gf = w0 + (wd << 6);
+    uint64_t gl = gf + 63 < w1 ? gf + 63 : w1 - 1;
+    uint64_t plo, phi;
+    wave_prefix_range(off, n, gf, gl, plo, phi);
+    if (!((b >> lane) & 1)) continue;
+    Cand c = resolve(F, stride, off, mini, d, plo, phi, gf + lane);
+    uint64_t pos = woff[wd] + __popcll(b & lanemask_lt());
+    if (!FINAL) {
+      for (int col = 0; col < d.j; ++col) G[(uint64_t)col * gstride + pos] = F[(uint64_t)col * stride + c.p];
+      G[(uint64_t)d.j * gstride + pos] = c.e;
+      if (Gw) Gw[pos] = wt ? wt[c.p] : (int8_t)1;
+    } else {
+      uint64_t r = obase + pos;
+      if (r >= ocap) continue;
+      uint32_t* row = G + r * (uint64_t)map.m;
+      for (int col = 0; col < d.j; ++col) row[map.attr[col]] = F[(uint64_t)col * stride + c.p];
+      row[map.attr[d.j]] = c.e;
+      if (Gw) Gw[r] = wt ? wt[c.p] : (int8_t)1;
+    }
+  }
+}
+
+// Rows of a two-attribute query straight from P_2.
+__global__ void k_rows_from_frontier(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n,
+                                     const int8_t* __restrict__ wt, RowMap map, uint32_t* __restrict__ rows,
+                                     int8_t* __restrict__ osign, uint64_t obase, uint64_t ocap,
+                                     unsigned long long* __restrict__ acc) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  int64_t ws = 0;
+  uint64_t cnt = 0;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
+    int8_t w = wt ? wt[p] : (int8_t)1;
+    ws += w;
+    ++cnt;
+    uint64_t r = obase + p;
+    if (rows && r < ocap) {
+      for (int col = 0; col < map.m; ++col) rows[r * map.m + map.attr[col]] = F[(uint64_t)col * stride + p];
+      if (osign) osign[r] = w;
+    }
+  }
+  uint64_t t = block_sum<kBlock>(cnt);
+  uint64_t s = block_sum<kBlock>((uint64_t)ws);
+  if (threadIdx.x == 0) {
+    atomicAdd(acc, (unsigned long long)t);
+    atomicAdd(acc + 1, (unsigned long long)s);
+  }
+}
+
+// ---------------------------------------------------------------- host launchers
+void launch_seed(gj_ctx* c, const uint32_t* x0, const uint32_t* x1, const int8_t* w, uint64_t cnt,
+                 const SeedFilter& f, uint32_t* flags, uint64_t* off, uint32_t* F, uint64_t stride,
+                 int8_t* Fw) {
+  unsigned gr = grid_for(cnt, kBlock, 1u << 16);
+  k_seed_flags<<<gr, kBlock, 0, c->stream>>>(x0, x1, cnt, f, flags);
+  scan_u32_to_u64(c, flags, off, cnt);
+  k_seed_scatter<<<gr, kBlock, 0, c->stream>>>(x0, x1, w, cnt, flags, off, F, stride, Fw);
+  GJ_HIP(hipGetLastError());
+}
+
+void launch_count_min(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const StageDesc& d,
+                      uint32_t* minc, uint8_t* mini) {
+  k_count_min<<<grid_for(n, kBlock, 1u << 16), kBlock, 0, c->stream>>>(F, stride, n, d, minc, mini);
+  GJ_HIP(hipGetLastError());
+}
+
+static unsigned propose_grid(gj_ctx* c, uint64_t words) {
+  uint64_t waves = words;
+  uint64_t cap = (uint64_t)c->num_cus * 32;  // persistent-ish: 32 waves per CU
+  if (waves > cap * 4) waves = cap * 4;
+  return grid_for(waves, kBlock / 64, 1u << 20);
+}
+
+void launch_propose(gj_ctx* c, int mode, const uint32_t* F, uint64_t stride, uint64_t n, const uint64_t* off,
+                    const uint8_t* mini, const StageDesc& d, uint64_t w0, uint64_t w1, uint64_t* mask,
+                    uint32_t* wcnt, const int8_t* wt, unsigned long long* acc) {
+  uint64_t words = (w1 - w0 + 63) >> 6;
+  unsigned gr = propose_grid(c, words);
+  if (mode == 0)
+    k_propose<0><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);
+  else if (mode == 1)
+    k_propose<1><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);
+  else
+    k_propose<2><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);
+  GJ_HIP(hipGetLastError());
+}
+
+void launch_emit(gj_ctx* c, bool final_rows, const uint32_t* F, uint64_t stride, uint64_t n, const uint64_t* off,
+                 const uint8_t* mini, const StageDesc& d, uint64_t w0, uint64_t w1, const uint64_t* mask,
+                 const uint64_t* woff, const int8_t* wt, uint32_t* G, uint64_t gstride, int8_t* Gw,
+                 const RowMap& map, uint64_t obase, uint64_t ocap) {
+  uint64_t words = (w1 - w0 + 63) >> 6;
+  unsigned gr = propose_grid(c, words);
+  if (final_rows)
+    k_emit<true><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, wt, G, gstride,
+                                               Gw, map, obase, ocap);
+  else
+    k_emit<false><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, wt, G, gstride,
+                                                Gw, map, obase, ocap);
+  GJ_HIP(hipGetLastError());
+}
+
+void launch_rows_from_frontier(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const int8_t* wt,
+                               const RowMap& map, uint32_t* rows, int8_t* osign, uint64_t obase, uint64_t ocap,
+                               unsigned long long* acc) {
+  k_rows_from_frontier<<<grid_for(n, kBlock, 1u << 14), kBlock, 0, c->stream>>>(F, stride, n, wt, map, rows,
+                                                                                 osign, obase, ocap, acc);
+  GJ_HIP(hipGetLastError());
+}
+
+}  // namespace gj

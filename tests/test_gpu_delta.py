@@ -1,0 +1,175 @@
+"""GPU parity of the delta-query path (gj_apply_updates through the C ABI)
+against the CPU oracle's Delta-GJ: signed consolidated rows, count deltas,
+raw emissions, per-stage counters, no-op counts and the new edge set."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import queries as Q
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gj():
+    import paper_1802_03760_amd as gj
+    return gj
+
+
+@pytest.fixture(scope="module")
+def ctx(gj):
+    return gj.Context(0)
+
+
+def edge_set(G):
+    hip = ctypes.CDLL("libamdhip64.so")
+    info = G.info()
+    E = info["edges"]
+    rp, col, row = G.csr_ptrs(0)
+    s = np.empty(E, np.uint32)
+    d = np.empty(E, np.uint32)
+    for arr, p in ((s, row), (d, col)):
+        if E:
+            assert hip.hipMemcpy(ctypes.c_void_p(arr.ctypes.data), ctypes.c_void_p(p),
+                                 ctypes.c_size_t(arr.nbytes), 2) == 0
+    return s, d
+
+
+def step(gj, ctx, G, O, qs_py, qs_gj, bs, bd, bg):
+    res = gj.apply_updates(ctx, G, bs, bd, bg, qs_gj, rows=True)
+    first = True
+    O_before = O.copy()
+    for q, r in zip(qs_py, res):
+        Oq = O_before.copy()
+        ref = oracle.delta(Oq, bs, bd, bg, q)
+        assert r["count_delta"] == ref["count_delta"], (q, r["count_delta"], ref["count_delta"])
+        assert r["n_delta"] == len(ref["rows"])
+        assert np.array_equal(r["rows"], ref["rows"]), q
+        assert np.array_equal(r["signs"], ref["signs"]), q
+        assert r["stats"]["raw_emissions"] == ref["raw_emissions"]
+        assert r["stats"]["prefixes"] == ref["prefixes"]
+        assert r["stats"]["extensions"] == ref["extensions"]
+        if first:
+            bi, bd_ = O_before.noops()
+            ni, nd = Oq.noops()
+            assert (r["stats"]["noop_inserts"], r["stats"]["noop_deletes"]) == (ni - bi, nd - bd_)
+            first = False
+    oracle.delta(O, bs, bd, bg)  # advance the reference graph
+    s, d = edge_set(G)
+    es, ed = O.edge_list()
+    assert np.array_equal(s, es) and np.array_equal(d, ed)
+    return res
+
+
+def test_forced_cancellation(gj, ctx):
+    G = gj.Graph(ctx, np.array([2, 1], np.uint32), np.array([3, 3], np.uint32), 4)
+    q = gj.Query(ctx, *Q.TRIANGLE)
+    r = gj.apply_updates(ctx, G, np.array([1, 2], np.uint32), np.array([2, 3], np.uint32),
+                         np.array([1, -1], np.int8), [q], rows=True)[0]
+    assert r["stats"]["raw_emissions"] == 2
+    assert r["count_delta"] == 0 and r["n_delta"] == 0
+    assert G.info()["edges"] == 2 and G.info()["version"] == 1
+
+
+@pytest.mark.parametrize("names", [("triangle", "cyclic_triangle", "reciprocal"),
+                                   ("clique4", "diamond", "cycle4", "paper_diamond")])
+def test_random_batches(gj, ctx, names):
+    n = 30
+    rng = np.random.default_rng(len(names))
+    src = rng.integers(0, n, 200).astype(np.uint32)
+    dst = rng.integers(0, n, 200).astype(np.uint32)
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle.Graph(n, src, dst)
+    qs_py = [Q.ALL[k] for k in names]
+    qs_gj = [gj.Query(ctx, *q) for q in qs_py]
+    for it in range(8):
+        b = int(rng.integers(1, 40))
+        bs = rng.integers(0, n, b).astype(np.uint32)
+        bd = rng.integers(0, n, b).astype(np.uint32)
+        bg = np.where(rng.random(b) < 0.4, -1, 1).astype(np.int8)
+        es, ed = O.edge_list()
+        for k in range(b):
+            if bg[k] < 0 and len(es) and rng.random() < 0.6:
+                j = rng.integers(0, len(es))
+                bs[k], bd[k] = es[j], ed[j]
+        dels = {(int(x), int(y)) for x, y, g in zip(bs, bd, bg) if g < 0}
+        keep = np.array([not (g > 0 and (int(x), int(y)) in dels) for x, y, g in zip(bs, bd, bg)])
+        step(gj, ctx, G, O, qs_py, qs_gj, bs[keep], bd[keep], bg[keep])
+
+
+def test_rmat_update_stream(gj, ctx):
+    """Base R-MAT scale 11 (seed 0), then a stream of log-uniform batches
+    (sizes in [1, 2,000], 10% deletions of base edges, seed 1)."""
+    scale = 11
+    src, dst = synth.rmat_draws(scale, seed=0)
+    n = 1 << scale
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle.Graph(n, src, dst)
+    qs_py = [Q.TRIANGLE, Q.CLIQUE4]
+    qs_gj = [gj.Query(ctx, *q) for q in qs_py]
+    for k, bs, bd, bg in synth.update_stream(scale, 0, 1, 6, 1, 2000):
+        step(gj, ctx, G, O, qs_py, qs_gj, bs, bd, bg)
+    # counts of the final graph agree too
+    for q, qg in zip(qs_py, qs_gj):
+        assert gj.count(ctx, G, qg)["matches"] == oracle.run(O, q)["matches"]
+
+
+def test_overflow_then_fetch(gj, ctx):
+    """A too-small row buffer: the batch is applied, the call reports
+    GJ_EOVERFLOW with the row count, and gj_last_delta returns the rows."""
+    src, dst = synth.rmat_draws(9, seed=8)
+    n = 1 << 9
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle.Graph(n, src, dst)
+    q = gj.Query(ctx, *Q.TRIANGLE)
+    (k, bs, bd, bg), = list(synth.update_stream(9, 8, 9, 1, 300, 300))
+    ref = oracle.delta(O, bs, bd, bg, Q.TRIANGLE)
+    assert len(ref["rows"]) > 3
+    r = gj.apply_updates(ctx, G, bs, bd, bg, [q], rows=True, cap=2)[0]
+    assert r["n_delta"] == len(ref["rows"])
+    assert np.array_equal(r["rows"], ref["rows"]) and np.array_equal(r["signs"], ref["signs"])
+    with pytest.raises(gj.GJError) as e:
+        gj.last_delta(ctx, 0, 3, 1)
+    assert e.value.status == gj.GJ_EOVERFLOW
+    rows, signs = gj.last_delta(ctx, 0, 3, len(ref["rows"]))
+    assert np.array_equal(rows, ref["rows"])
+    with pytest.raises(gj.GJError):
+        gj.last_delta(ctx, 1, 3, 10)
+
+
+def test_count_only_matches_rows(gj, ctx):
+    src, dst = synth.rmat_draws(10, seed=5)
+    n = 1 << 10
+    G1 = gj.Graph(ctx, src, dst, n)
+    G2 = gj.Graph(ctx, src, dst, n)
+    q = gj.Query(ctx, *Q.TRIANGLE)
+    for k, bs, bd, bg in synth.update_stream(10, 5, 7, 4, 1, 500):
+        a = gj.apply_updates(ctx, G1, bs, bd, bg, [q], rows=False)[0]
+        b = gj.apply_updates(ctx, G2, bs, bd, bg, [q], rows=True)[0]
+        assert a["count_delta"] == b["count_delta"] == int(b["signs"].astype(np.int64).sum())
+
+
+def test_conflict_and_bad_input(gj, ctx):
+    G = gj.Graph(ctx, np.array([0, 1], np.uint32), np.array([1, 2], np.uint32), 5)
+    q = gj.Query(ctx, *Q.TRIANGLE)
+    with pytest.raises(gj.GJError) as e:
+        gj.apply_updates(ctx, G, np.array([3, 3], np.uint32), np.array([4, 4], np.uint32),
+                         np.array([1, -1], np.int8), [q])
+    assert e.value.status == gj.GJ_EINVAL
+    with pytest.raises(gj.GJError) as e:
+        gj.apply_updates(ctx, G, np.array([7], np.uint32), np.array([1], np.uint32),
+                         np.array([1], np.int8), [q])
+    assert e.value.status == gj.GJ_EINVAL
+    with pytest.raises(gj.GJError) as e:
+        gj.apply_updates(ctx, G, np.array([2], np.uint32), np.array([1], np.uint32),
+                         np.array([3], np.int8), [q])
+    assert e.value.status == gj.GJ_EINVAL
+    assert G.info()["edges"] == 2 and G.info()["version"] == 0
+    # empty and all-no-op batches leave the version unchanged
+    r = gj.apply_updates(ctx, G, np.array([0, 4], np.uint32), np.array([1, 4], np.uint32),
+                         np.array([1, 1], np.int8), [q])[0]
+    assert r["count_delta"] == 0 and r["stats"]["noop_inserts"] == 1
+    assert G.info()["version"] == 0
