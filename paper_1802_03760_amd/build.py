@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgj.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build", "gj")
-SOURCES = ["api.hip", "scan.hip", "sort.hip", "graph.hip", "stage.hip", "engine.hip",
+SOURCES = ["api.hip", "scan.hip", "sort.hip", "graph.hip", "stage.hip", "engine.hip", "owner.hip",
            "rows.hip", "delta.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

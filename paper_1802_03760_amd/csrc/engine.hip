@@ -12,6 +12,7 @@
 
 #include "engine.h"
 #include "gj_internal.h"
+#include "owner.h"
 
 namespace gj {
 
@@ -275,6 +276,27 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
   hi = std::min<uint64_t>(hi, v.m);
   lo = std::min<uint64_t>(lo, hi);
   bool collect = mode == GJ_MODE_ENUMERATE;
+  // Owner-grouped kernel: counting a three-attribute query over all seed
+  // edges whose last attribute is bound by one atom on each seed attribute.
+  if (!collect && c->strategy != 1 && P.m == 3 && P.filters.empty() && lo == 0 && hi == v.m &&
+      P.bind[2].size() == 2 && P.bind[2][0].col != P.bind[2][1].col) {
+    const BindH& A = P.bind[2][0].col == 0 ? P.bind[2][0] : P.bind[2][1];
+    const BindH& B = P.bind[2][0].col == 0 ? P.bind[2][1] : P.bind[2][0];
+    OwnerArgs a{v.d[A.dir].rp, v.d[A.dir].col, v.d[B.dir].rp, v.d[B.dir].col,
+                v.d[dir].rp,   v.d[dir].col,   v.d[1 - dir].rp, v.d[1 - dir].col, g->n};
+    KernelTimer timer(c);
+    uint64_t matches = 0, ext = 0;
+    owner_count(c, a, v.d[dir].row, v.d[dir].col, v.d[1 - dir].row, v.d[1 - dir].col, v.m, timer, matches, ext);
+    gj_stats s{};
+    s.prefixes[2] = v.m;
+    s.extensions[2] = ext;
+    s.prefixes[3] = matches;
+    s.matches = matches;
+    s.kernel_ms = timer.total_ms();
+    s.kernel_launches = timer.launches();
+    *st = s;
+    return;
+  }
   uint64_t seed_cap = std::max<uint64_t>(1, std::min<uint64_t>(c->seed_chunk, hi - lo));
   Runner R(c, P, V, false, collect, seed_cap);
   if (collect) {

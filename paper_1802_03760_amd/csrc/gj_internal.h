@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/gj.h"
+#include "gj.h"
 
 namespace gj {
 

@@ -68,7 +68,9 @@ __global__ void k_rowptr(const uint32_t* __restrict__ row, uint64_t m, uint32_t 
   }
 }
 
-__global__ void k_maxdeg(const uint32_t* __restrict__ rp, uint32_t n, uint32_t* __restrict__ out) {
+__global__ void __launch_bounds__(kBlock) k_maxdeg(const uint32_t* __restrict__ rp, uint32_t n,
+                                                   uint32_t* __restrict__ out) {
+  __shared__ uint32_t wbest[kBlock / 64];
   uint32_t best = 0;
   uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
@@ -76,7 +78,12 @@ __global__ void k_maxdeg(const uint32_t* __restrict__ rp, uint32_t n, uint32_t* 
     best = d > best ? d : best;
   }
   best = wave_max(best);
-  if (lane_id() == 0) atomicMax(out, best);
+  if (lane_id() == 0) wbest[wave_id()] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) best = wbest[w] > best ? wbest[w] : best;
+    atomicMax(out, best);  // one atomic per workgroup
+  }
 }
 
 void version_alloc(Version& v, uint32_t n, uint64_t cap) {
@@ -116,7 +123,7 @@ void version_finish(gj_ctx* c, Version& v, uint32_t n) {
   GJ_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(uint32_t), c->stream));
   for (int d = 0; d < 2; ++d) {
     k_rowptr<<<grid_for((uint64_t)n + 1, kBlock, 1u << 16), kBlock, 0, c->stream>>>(v.d[d].row, v.m, n, v.d[d].rp);
-    k_maxdeg<<<grid_for(n, kBlock, 1u << 14), kBlock, 0, c->stream>>>(v.d[d].rp, n, mx + d);
+    k_maxdeg<<<grid_for(n, kBlock * 16, 1024), kBlock, 0, c->stream>>>(v.d[d].rp, n, mx + d);
   }
   GJ_HIP(hipGetLastError());
   uint32_t h[2];

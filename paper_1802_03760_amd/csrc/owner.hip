@@ -1,0 +1,390 @@
+// Owner-grouped intersection for the first extension stage of an
+// edge-seeded query with two binding atoms, one on each seed attribute:
+// count over seed edges (x0, x1) of |LA(x0) ∩ LB(x1)|.  Triangle counting is
+// this stage (LA = out(a1), LB = out(a2)); so is the cyclic triangle.
+//
+// Count-minimisation (Sec. 3.1) makes the smaller of the two sets propose and
+// the larger one check.  Here every seed edge is assigned to the owner of its
+// larger set -- x0 when |LB(x1)| <= |LA(x0)| (ties: atom order), else x1 -- and
+// all edges of one owner are processed together: a workgroup loads the
+// owner's set once into an LDS hash table and streams the proposing sets of
+// its partners through it with coalesced reads.  The paper's extension-index
+// property of O(1) membership tests (Sec. 2.2) is what the LDS table
+// provides; proposals per edge stay min(|LA|, |LB|), so the candidate count
+// equals the count-minimisation total.
+//
+// Owner units (v, r): r = 0 holds the edges (v, x1) (partners from the seed
+// index row of v, probe set LA(v)); r = 1 holds the edges (x0, v) (partners
+// from the transposed seed index row of v, probe set LB(v)).  A unit's work
+// is split into tasks of partner ranges; persistent workgroups take tasks
+// from a device counter in owner-id order (hubs first on R-MAT ids), which is
+// the (prefix, range) balancing of Sec. 3.4 applied within the GPU.  Probe
+// sets larger than half the table are processed in id-range segments.  Edges
+// whose larger set is below kDMin go to a per-edge merge in the same launch.
+#include "gj_internal.h"
+#include "owner.h"
+#include "prim.h"
+
+namespace gj {
+
+constexpr int kOwnNT = 1024;
+constexpr int kLogSlots = 14;
+constexpr uint32_t kSlots = 1u << kLogSlots;  // 64 KiB table
+constexpr uint32_t kSegMax = kSlots / 2;      // load factor <= 1/2
+constexpr uint32_t kDMin = 64;
+constexpr uint32_t kLong = 64;  // proposing sets streamed by a whole wave
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+
+struct UnitLists {
+  const uint32_t *prp, *padj;  // probe set
+  const uint32_t *srp, *sadj;  // partners
+  const uint32_t *qrp, *qadj;  // proposing sets of the partners
+};
+
+__device__ __forceinline__ UnitLists unit_lists(const OwnerArgs& a, uint32_t r) {
+  UnitLists L;
+  if (r == 0) {
+    L.prp = a.rpA; L.padj = a.adjA;
+    L.srp = a.rpS0; L.sadj = a.adjS0;
+    L.qrp = a.rpB; L.qadj = a.adjB;
+  } else {
+    L.prp = a.rpB; L.padj = a.adjB;
+    L.srp = a.rpS1; L.sadj = a.adjS1;
+    L.qrp = a.rpA; L.qadj = a.adjA;
+  }
+  return L;
+}
+
+// r = 0 owns partners whose set is not larger; r = 1 only strictly smaller
+__device__ __forceinline__ bool owned(uint32_t r, uint32_t s, uint32_t D) { return r == 0 ? s <= D : s < D; }
+
+// ---------------------------------------------------------------- planning
+// Per index entry (owner v = row, partner u = column) of role r: the number of
+// proposals the entry contributes to unit (v, r), zero when the unit does not
+// own the edge or its probe set is below kDMin.  A scan of these gives each
+// unit's work and the work offset of each of its partners.
+__global__ void k_owner_vals(OwnerArgs a, uint32_t r, const uint32_t* __restrict__ row,
+                             const uint32_t* __restrict__ col, uint64_t m, uint32_t* __restrict__ vals) {
+  UnitLists L = unit_lists(a, r);
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gs) {
+    uint32_t v = row[e], u = col[e];
+    uint32_t D = L.prp[v + 1] - L.prp[v];
+    uint32_t s = L.qrp[u + 1] - L.qrp[u];
+    vals[e] = (D >= kDMin && owned(r, s, D)) ? s : 0u;
+  }
+}
+
+// task count of every unit: work / task size, at most one task per partner
+__global__ void k_owner_units(OwnerArgs a, const uint64_t* __restrict__ wscan0, const uint64_t* __restrict__ wscan1,
+                              uint64_t tw_min, uint32_t* __restrict__ ntasks) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < 2ull * a.n; u += gs) {
+    uint32_t v = (uint32_t)(u >> 1), r = (uint32_t)(u & 1);
+    UnitLists L = unit_lists(a, r);
+    const uint64_t* ws = r ? wscan1 : wscan0;
+    uint32_t ps = L.srp[v], pe = L.srp[v + 1];
+    uint64_t w = ws[pe] - ws[ps];
+    uint32_t nt = 0;
+    if (w) {
+      uint32_t D = L.prp[v + 1] - L.prp[v];
+      uint64_t nseg = (D + kSegMax - 1) / kSegMax;
+      uint64_t tw = tw_min > 8ull * D * nseg ? tw_min : 8ull * D * nseg;
+      uint64_t k = (w + tw - 1) / tw;
+      uint64_t P = pe - ps;
+      nt = (uint32_t)(k < P ? k : P);
+    }
+    ntasks[u] = nt;
+  }
+}
+
+// task = (unit, partner range); boundaries split the unit's work evenly
+__global__ void k_owner_tasks(OwnerArgs a, const uint64_t* __restrict__ wscan0, const uint64_t* __restrict__ wscan1,
+                              const uint32_t* __restrict__ ntasks, const uint64_t* __restrict__ toff,
+                              uint32_t* __restrict__ tasks) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < 2ull * a.n; u += gs) {
+    uint32_t nt = ntasks[u];
+    if (!nt) continue;
+    uint32_t v = (uint32_t)(u >> 1), r = (uint32_t)(u & 1);
+    UnitLists L = unit_lists(a, r);
+    const uint64_t* ws = r ? wscan1 : wscan0;
+    uint32_t ps = L.srp[v], pe = L.srp[v + 1];
+    uint64_t w0 = ws[ps], W = ws[pe] - w0;
+    uint64_t base = toff[u];
+    uint32_t prev = 0;
+    for (uint32_t k = 0; k < nt; ++k) {
+      uint32_t next = pe - ps;
+      if (k + 1 < nt) {
+        // first partner whose work offset reaches the k+1-th share
+        uint64_t target = w0 + W * (k + 1) / nt;
+        uint32_t lo = ps, len = pe - ps;
+        while (len > 0) {
+          uint32_t half = len >> 1;
+          if (ws[lo + half] < target) {
+            lo += half + 1;
+            len -= half + 1;
+          } else {
+            len = half;
+          }
+        }
+        next = lo - ps;
+        if (next < prev) next = prev;
+      }
+      tasks[3 * (base + k) + 0] = (uint32_t)u;
+      tasks[3 * (base + k) + 1] = prev;
+      tasks[3 * (base + k) + 2] = next;
+      prev = next;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- LDS hash
+// Open addressing over buckets of four 32-bit slots, probed bucket by bucket
+// (one 16-byte LDS read each).  Insertion claims the first empty slot of the
+// first bucket with room, so the filled slots of a bucket are a prefix and a
+// bucket with an empty last slot ends an unsuccessful search.
+__device__ __forceinline__ uint32_t bucket_of(uint32_t x, int shift) { return (x * 0x9E3779B1u) >> shift; }
+
+__device__ __forceinline__ void insert(uint32_t* H, uint32_t x, int shift, uint32_t bmask) {
+  uint32_t b = bucket_of(x, shift);
+  for (;;) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (atomicCAS(&H[4 * b + k], kEmpty, x) == kEmpty) return;
+    b = (b + 1) & bmask;
+  }
+}
+
+// continues an unsuccessful search after bucket b
+__device__ __noinline__ bool probe_from(const uint32_t* H, uint32_t x, uint32_t b, uint32_t bmask) {
+  const uint4* B = reinterpret_cast<const uint4*>(H);
+  for (;;) {
+    b = (b + 1) & bmask;
+    uint4 q = B[b];
+    if (q.x == x || q.y == x || q.z == x || q.w == x) return true;
+    if (q.w == kEmpty) return false;
+  }
+}
+
+__device__ __forceinline__ bool probe(const uint32_t* H, uint32_t x, int shift, uint32_t bmask) {
+  const uint4* B = reinterpret_cast<const uint4*>(H);
+  uint32_t b = bucket_of(x, shift);
+  uint4 q = B[b];
+  if (q.x == x || q.y == x || q.z == x || q.w == x) return true;
+  if (q.w == kEmpty) return false;
+  return probe_from(H, x, b, bmask);
+}
+
+// p in [lo, hi) with off[p] <= g < off[p+1] over an LDS array
+__device__ __forceinline__ uint32_t find_lds(const uint32_t* off, uint32_t lo, uint32_t hi, uint32_t g) {
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (off[mid] <= g)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------- main kernel
+// Per task: the owner's probe set goes into the LDS table (segment by
+// segment), then its partners are taken kOwnNT at a time.  Partners whose
+// proposing set has at least kLong elements are streamed by one wave each
+// (four coalesced 64-element loads in flight per step); shorter ones are
+// concatenated and walked in 64-element windows.
+template <int U>
+__device__ __forceinline__ uint32_t stream_probe(const uint32_t* __restrict__ qadj, uint32_t st, uint32_t s,
+                                                 const uint32_t* H, int shift, uint32_t mask) {
+  const uint4* B = reinterpret_cast<const uint4*>(H);
+  const uint32_t lane = (uint32_t)lane_id();
+  uint32_t hits = 0;
+  for (uint32_t i = lane; i < s; i += 64 * U) {
+    uint32_t x[U], b[U];
+    bool ok[U];
+    uint4 q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ok[u] = i + 64 * u < s;
+      x[u] = ok[u] ? qadj[st + i + 64 * u] : 0u;
+    }
+    // first buckets of all U values read before any is resolved
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      b[u] = bucket_of(x[u], shift);
+      q[u] = B[b[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      bool hit = q[u].x == x[u] || q[u].y == x[u] || q[u].z == x[u] || q[u].w == x[u];
+      if (ok[u] && !hit && q[u].w != kEmpty) hit = probe_from(H, x[u], b[u], mask);
+      hits += (ok[u] && hit) ? 1u : 0u;
+    }
+  }
+  return hits;
+}
+
+__global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))) k_owner_count(OwnerArgs a, const uint32_t* __restrict__ tasks,
+                                                        uint32_t ntask, unsigned int* __restrict__ counter,
+                                                        const uint32_t* __restrict__ seed_row,
+                                                        const uint32_t* __restrict__ seed_col, uint64_t E,
+                                                        unsigned long long* __restrict__ acc) {
+  __shared__ __attribute__((aligned(16))) uint32_t H[kSlots];
+  __shared__ uint32_t pst[kOwnNT];       // start of each partner's proposing set
+  __shared__ uint32_t pval[kOwnNT + 1];  // long: size; short: offset in the short space
+  __shared__ uint32_t s_task, s_long;
+  const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
+  constexpr int nwaves = kOwnNT / 64;
+  uint64_t hits = 0, ext = 0;
+
+  for (;;) {
+    if (tid == 0) s_task = atomicAdd(counter, 1u);
+    __syncthreads();
+    uint32_t t = s_task;
+    __syncthreads();
+    if (t >= ntask) break;
+    uint32_t unit = tasks[3 * (uint64_t)t], plo = tasks[3 * (uint64_t)t + 1], phi = tasks[3 * (uint64_t)t + 2];
+    uint32_t v = unit >> 1, r = unit & 1;
+    UnitLists L = unit_lists(a, r);
+    uint32_t Lb = L.prp[v], D = L.prp[v + 1] - Lb;
+    uint32_t Sb = L.srp[v];
+    uint32_t nseg = (D + kSegMax - 1) / kSegMax;
+    for (uint32_t seg = 0; seg < nseg; ++seg) {
+      uint32_t e0 = seg * kSegMax, e1 = min(D, e0 + kSegMax), cnt = e1 - e0;
+      // slots: power of two >= 4 * cnt (load <= 1/4) up to the table size
+      int lg = 6;
+      while ((1u << lg) < 4 * cnt && lg < kLogSlots) ++lg;
+      uint32_t slots = 1u << lg, mask = (slots >> 2) - 1;  // mask over buckets
+      int shift = 32 - (lg - 2);
+      for (uint32_t i = tid; i < slots; i += kOwnNT) H[i] = kEmpty;
+      __syncthreads();
+      for (uint32_t i = tid; i < cnt; i += kOwnNT) insert(H, L.padj[Lb + e0 + i], shift, mask);
+      __syncthreads();
+      uint32_t lo_s = L.padj[Lb + e0], hi_s = L.padj[Lb + e1 - 1];
+      for (uint32_t c = plo; c < phi; c += kOwnNT) {
+        uint32_t i = c + tid;
+        uint32_t s = 0, st = 0;
+        if (i < phi) {
+          uint32_t u = L.sadj[Sb + i];
+          uint32_t qb = L.qrp[u];
+          s = L.qrp[u + 1] - qb;
+          if (!owned(r, s, D)) s = 0;
+          if (seg == 0) ext += s;
+          st = qb;
+          if (s && nseg > 1) {
+            // vertex ids are below 2^32 - 1, so hi_s + 1 does not wrap
+            uint32_t b0 = lower_bound_u32(L.qadj, qb, qb + s, lo_s);
+            uint32_t b1 = lower_bound_u32(L.qadj, b0, qb + s, hi_s + 1);
+            st = b0;
+            s = b1 - b0;
+          }
+        }
+        // one scan: long-partner count in the high half, short sizes in the low half
+        bool is_long = s >= kLong;
+        uint32_t total;
+        uint32_t pre = block_excl_scan<kOwnNT, uint32_t>(is_long ? (1u << 16) : s, total);
+        uint32_t nlong = total >> 16, short_total = total & 0xFFFFu;
+        uint32_t kl = pre >> 16;
+        if (is_long) {
+          pst[kl] = st;
+          pval[kl] = s;
+        } else {
+          uint32_t j = nlong + ((uint32_t)tid - kl);
+          pst[j] = st;
+          pval[j] = pre & 0xFFFFu;
+        }
+        if (tid == 0) {
+          pval[kOwnNT] = short_total;
+          s_long = 0;
+        }
+        __syncthreads();
+        // long partners: one wave each, taken dynamically
+        for (;;) {
+          uint32_t k = 0;
+          if (lane == 0) k = atomicAdd(&s_long, 1u);
+          k = __shfl(k, 0, 64);
+          if (k >= nlong) break;
+          hits += stream_probe<4>(L.qadj, pst[k], pval[k], H, shift, mask);
+        }
+        // short partners: 64-element windows over their concatenation
+        for (uint32_t g0 = (uint32_t)wave * 64; g0 < short_total; g0 += nwaves * 64) {
+          uint32_t gl = min(g0 + 63, short_total - 1);
+          uint32_t pf = find_lds(pval, nlong, kOwnNT, g0);
+          uint32_t pl = find_lds(pval, pf, kOwnNT, gl);
+          uint32_t g = g0 + lane;
+          if (g < short_total) {
+            uint32_t p = find_lds(pval, pf, pl + 1, g);
+            uint32_t x = L.qadj[pst[p] + (g - pval[p])];
+            hits += probe(H, x, shift, mask) ? 1 : 0;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+
+  // edges whose larger set is small: per-edge merge
+  uint64_t gs = (uint64_t)gridDim.x * kOwnNT;
+  for (uint64_t e = (uint64_t)blockIdx.x * kOwnNT + tid; e < E; e += gs) {
+    uint32_t x0 = seed_row[e], x1 = seed_col[e];
+    uint32_t la = a.rpA[x0], da = a.rpA[x0 + 1] - la;
+    uint32_t lb = a.rpB[x1], db = a.rpB[x1 + 1] - lb;
+    if ((da > db ? da : db) >= kDMin) continue;
+    ext += da < db ? da : db;
+    uint32_t i = 0, j = 0;
+    while (i < da && j < db) {
+      uint32_t p = a.adjA[la + i], q = a.adjB[lb + j];
+      hits += p == q ? 1 : 0;
+      i += p <= q ? 1 : 0;
+      j += q <= p ? 1 : 0;
+    }
+  }
+
+  uint64_t th = block_sum<kOwnNT>(hits);
+  uint64_t te = block_sum<kOwnNT>(ext);
+  if (tid == 0) {
+    atomicAdd(acc, (unsigned long long)th);
+    atomicAdd(acc + 1, (unsigned long long)te);
+  }
+}
+
+// ---------------------------------------------------------------- host
+void owner_count(gj_ctx* c, const OwnerArgs& a, const uint32_t* seed_row, const uint32_t* seed_col,
+                 const uint32_t* t_row, const uint32_t* t_col, uint64_t E, KernelTimer& timer, uint64_t& matches,
+                 uint64_t& extensions) {
+  uint64_t units = 2ull * a.n;
+  uint32_t* ntasks = (uint32_t*)ws_get(c, "own_nt", (units + 1) * sizeof(uint32_t));
+  uint64_t* toff = (uint64_t*)ws_get(c, "own_toff", (units + 1) * sizeof(uint64_t));
+  unsigned long long* acc = (unsigned long long*)ws_get(c, "own_acc", 2 * sizeof(unsigned long long));
+  unsigned int* counter = (unsigned int*)ws_get(c, "own_ctr", sizeof(unsigned int));
+  GJ_HIP(hipMemsetAsync(acc, 0, 2 * sizeof(unsigned long long), c->stream));
+  GJ_HIP(hipMemsetAsync(counter, 0, sizeof(unsigned int), c->stream));
+  const uint64_t tw_min = 1ull << 17;
+  uint32_t* vals = (uint32_t*)ws_get(c, "own_vals", (E + 1) * sizeof(uint32_t));
+  uint64_t* wscan0 = (uint64_t*)ws_get(c, "own_ws0", (E + 1) * sizeof(uint64_t));
+  uint64_t* wscan1 = (uint64_t*)ws_get(c, "own_ws1", (E + 1) * sizeof(uint64_t));
+  unsigned ge = grid_for(E, kBlock, 1u << 16);
+  if (E) k_owner_vals<<<ge, kBlock, 0, c->stream>>>(a, 0, seed_row, seed_col, E, vals);
+  scan_u32_to_u64(c, vals, wscan0, E);
+  if (E) k_owner_vals<<<ge, kBlock, 0, c->stream>>>(a, 1, t_row, t_col, E, vals);
+  scan_u32_to_u64(c, vals, wscan1, E);
+  k_owner_units<<<grid_for(units, kBlock, 1u << 16), kBlock, 0, c->stream>>>(a, wscan0, wscan1, tw_min, ntasks);
+  scan_u32_to_u64(c, ntasks, toff, units);
+  uint64_t nt = read_u64(c, toff + units);
+  GJ_CHECK(nt < (1ull << 32), GJ_EUNSUPPORTED, "too many owner tasks");
+  uint32_t* tasks = (uint32_t*)ws_get(c, "own_tasks", (3 * nt + 3) * sizeof(uint32_t));
+  k_owner_tasks<<<grid_for(units, kBlock, 1u << 16), kBlock, 0, c->stream>>>(a, wscan0, wscan1, ntasks, toff, tasks);
+  GJ_HIP(hipGetLastError());
+  unsigned grid = (unsigned)c->num_cus * 2;
+  timer.start();
+  k_owner_count<<<grid, kOwnNT, 0, c->stream>>>(a, tasks, (uint32_t)nt, counter, seed_row, seed_col, E, acc);
+  timer.stop();
+  GJ_HIP(hipGetLastError());
+  unsigned long long h[2];
+  read_bytes(c, h, acc, sizeof(h));
+  matches = h[0];
+  extensions = h[1];
+}
+
+}  // namespace gj
