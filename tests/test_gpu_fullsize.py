@@ -1,0 +1,170 @@
+"""Parity at full workload sizes, in the launch configuration bench.py times.
+
+R-MAT scale 22 (65.2M edges) and scale 20 (16.1M edges): the full counts are
+checked through properties that hold at any size (edge count and extension
+counter computed independently with numpy; the owner-grouped count equals the
+generic per-candidate count), and sampled seed slices are checked
+element by element against the oracle.  Delta batches at scale 22 are
+checked by count conservation and by validity of every reported row.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import queries as Q
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gj():
+    import paper_1802_03760_amd as gj
+    return gj
+
+
+def distinct_edges(src, dst):
+    k = (src.astype(np.uint64) << np.uint64(32)) | dst.astype(np.uint64)
+    k = np.unique(k[src != dst])
+    return (k >> np.uint64(32)).astype(np.int64), (k & np.uint64(0xFFFFFFFF)).astype(np.int64)
+
+
+def slices(E, count, width):
+    return [((E * i) // count, min(E, (E * i) // count + width)) for i in range(count)]
+
+
+@pytest.fixture(scope="module")
+def rmat22(gj):
+    src, dst = synth.rmat_draws(22, seed=0)
+    return src, dst
+
+
+@pytest.fixture(scope="module")
+def oracle22(rmat22):
+    src, dst = rmat22
+    return oracle.Graph(1 << 22, src, dst)
+
+
+def test_rmat22_triangle_count(gj, rmat22, oracle22):
+    src, dst = rmat22
+    n = 1 << 22
+    ctx = gj.Context(0)
+    G = gj.Graph(ctx, src, dst, n)
+    q = gj.Query(ctx, *Q.TRIANGLE)
+    full = gj.count(ctx, G, q)  # owner-grouped kernel, as in bench.py
+    assert full["kernel_launches"] == 1
+    es, ed = distinct_edges(src, dst)
+    assert full["prefixes"][2] == len(es) == G.info()["edges"]
+    outd = np.bincount(es, minlength=n)
+    assert full["extensions"][2] == int(np.minimum(outd[es], outd[ed]).sum())
+    # generic per-candidate kernel on the same graph
+    gen = gj.Context(0)
+    gen.set_option("strategy", 1)
+    G2 = gj.Graph(gen, src, dst, n)
+    g = gj.count(gen, G2, gj.Query(gen, *Q.TRIANGLE))
+    assert g["matches"] == full["matches"] and g["extensions"] == full["extensions"]
+    # sampled seed slices: generic kernel vs oracle, element by element
+    O = oracle22
+    E = O.num_edges
+    for lo, hi in slices(E, 8, 3000):
+        ref = oracle.run(O, Q.TRIANGLE, collect=True, seed_lo=lo, seed_hi=hi, threads=16)
+        st, rows = gj.enumerate_rows(gen, G2, gj.Query(gen, *Q.TRIANGLE), lo, hi)
+        assert st["matches"] == ref["matches"] and np.array_equal(rows, ref["rows"]), (lo, hi)
+        assert st["extensions"] == ref["extensions"]
+    G2.close()
+    gen.close()
+    G.close()
+    ctx.close()
+
+
+def test_rmat22_four_clique_and_diamond_slices(gj, rmat22, oracle22):
+    src, dst = rmat22
+    n = 1 << 22
+    ctx = gj.Context(0)
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle22
+    E = O.num_edges
+    for q, width in ((Q.CLIQUE4, 400), (Q.CYCLIC_TRIANGLE, 2000)):
+        qh = gj.Query(ctx, *q)
+        # the first slice starts at the hubs: 20 seeds there keep the oracle within seconds
+        for lo, hi in [(0, 20)] + slices(E, 6, width)[1:]:
+            ref = oracle.run(O, q, seed_lo=lo, seed_hi=hi, threads=16)
+            got = gj.count(ctx, G, qh, lo, hi)
+            assert got["matches"] == ref["matches"], (q, lo, hi)
+            assert got["prefixes"] == ref["prefixes"] and got["extensions"] == ref["extensions"]
+    # diamond: seeds from the low-degree end of the edge range
+    qh = gj.Query(ctx, *Q.DIAMOND)
+    for lo in (E - 5000, E - 40000):
+        ref = oracle.run(O, Q.DIAMOND, seed_lo=lo, seed_hi=lo + 200, threads=16)
+        got = gj.count(ctx, G, qh, lo, lo + 200)
+        assert got["matches"] == ref["matches"] and got["extensions"] == ref["extensions"]
+    G.close()
+    ctx.close()
+
+
+def test_rmat20_enumerate_slices(gj):
+    """R-MAT scale 20 triangle count and enumeration (sorted rows) on
+    sampled seed slices; the full count through both kernels."""
+    src, dst = synth.rmat_draws(20, seed=0)
+    n = 1 << 20
+    ctx = gj.Context(0)
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle.Graph(n, src, dst)
+    E = O.num_edges
+    q = gj.Query(ctx, *Q.TRIANGLE)
+    full = gj.count(ctx, G, q)
+    gen = gj.Context(0)
+    gen.set_option("strategy", 1)
+    G2 = gj.Graph(gen, src, dst, n)
+    assert gj.count(gen, G2, gj.Query(gen, *Q.TRIANGLE))["matches"] == full["matches"]
+    for lo, hi in slices(E, 10, 5000):
+        ref = oracle.run(O, Q.TRIANGLE, collect=True, seed_lo=lo, seed_hi=hi, threads=16)
+        st, rows = gj.enumerate_rows(ctx, G, q, lo, hi)
+        assert np.array_equal(rows, ref["rows"]), (lo, hi)
+    G2.close()
+    gen.close()
+    G.close()
+    ctx.close()
+
+
+def test_rmat22_delta_stream_properties(gj, rmat22):
+    """Delta batches on the scale-22 graph: the sum of count deltas equals
+    the change of the full count, and every reported row is a triangle of
+    the new graph (sign +1) or of the old graph (sign -1), not of both."""
+    src, dst = rmat22
+    n = 1 << 22
+    ctx = gj.Context(0)
+    G = gj.Graph(ctx, src, dst, n)
+    q = gj.Query(ctx, *Q.TRIANGLE)
+    c0 = gj.count(ctx, G, q)["matches"]
+    es, ed = distinct_edges(src, dst)
+    keys = np.sort((es << 32) | ed)
+    total = 0
+    for k, bs, bd, bg in synth.update_stream(22, 0, 1, 6, 1, 20000):
+        r = gj.apply_updates(ctx, G, bs, bd, bg, [q], rows=True)[0]
+        total += r["count_delta"]
+        assert r["count_delta"] == int(r["signs"].astype(np.int64).sum())
+        # the edge set after the batch, by numpy
+        bk = (bs.astype(np.int64) << 32) | bd.astype(np.int64)
+        loops = bs == bd
+        ins = np.setdiff1d(bk[(bg > 0) & ~loops], keys)
+        dels = np.intersect1d(bk[(bg < 0) & ~loops], keys)
+        new_keys = np.union1d(np.setdiff1d(keys, dels), ins)
+        assert G.info()["edges"] == len(new_keys)
+        rows = r["rows"].astype(np.int64)
+        if len(rows):
+            def present(kk, a, b):
+                x = (a << 32) | b
+                i = np.searchsorted(kk, x)
+                return (i < len(kk)) & (kk[np.minimum(i, len(kk) - 1)] == x)
+
+            def tri(kk):
+                return (present(kk, rows[:, 0], rows[:, 1]) & present(kk, rows[:, 1], rows[:, 2])
+                        & present(kk, rows[:, 0], rows[:, 2]))
+            t_new, t_old = tri(new_keys), tri(keys)
+            assert np.all(np.where(r["signs"] > 0, t_new & ~t_old, t_old & ~t_new))
+        keys = new_keys
+    c1 = gj.count(ctx, G, q)["matches"]
+    assert c1 - c0 == total
+    G.close()
+    ctx.close()
