@@ -62,6 +62,10 @@ const char* gj_last_error(const gj_ctx* ctx);
  *   "strategy"      intersection kernel choice: 0 auto, 1 generic
  *                   per-candidate search only, 2 owner-grouped LDS kernel
  *                   where applicable
+ *   "batch_lin"     gj_run_batch: linear instead of binary search in
+ *                   extension sets of at most this size (default 8)
+ *   "batch_waves_per_cu"  gj_run_batch: resident waves per CU of its
+ *                   persistent grids, a multiple of 4 in [4, 128] (default 32)
  * Returns GJ_EINVAL for an unknown key or out-of-range value. */
 gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
 
@@ -165,6 +169,38 @@ gj_status gj_apply_updates(gj_ctx* ctx, gj_graph* g, const uint32_t* src,
                            int64_t* count_delta, uint32_t* const* delta_rows,
                            int8_t* const* delta_sign, const uint64_t* cap,
                            uint64_t* n_delta, gj_stats* stats);
+
+/* ---------------------------------------------------------------- batches */
+
+/* Counts nreq requests (query qs[i] over seed edges [seed_lo[i], seed_hi[i])
+ * of its seed atom, as gj_run) on the current version in one fused pipeline:
+ * every level of every request shares one count-minimisation, scan and
+ * propose+intersect launch, with sizes kept in device memory, captured once
+ * as a hipGraph and replayed (the synchronous dataflow primitive of
+ * Sec. 3.1.1 over all requests).  counts[i] and stats[i] (stats may be NULL)
+ * equal what gj_run(COUNT) returns for request i.  A level larger than
+ * "frontier_cap" prefixes makes the call fall back to one depth-first gj_run
+ * per request (same results, bounded memory). */
+gj_status gj_run_batch(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_query* const* qs,
+                       const uint64_t* seed_lo, const uint64_t* seed_hi, uint64_t* counts,
+                       gj_stats* stats);
+
+typedef struct {
+  uint32_t batch_lin;          /* linear search below this extension-set size */
+  uint32_t batch_waves_per_cu; /* waves per CU of the persistent grids */
+  double best_ms;              /* device time of the chosen configuration (-1: cached) */
+  int configs_tried;
+  int from_cache;
+} gj_tuning;
+
+/* Times every candidate configuration of gj_run_batch on this batch, keeps the
+ * fastest in ctx (options "batch_lin", "batch_waves_per_cu") and, if
+ * cache_path is not NULL, records it in that JSON file keyed by graph size and
+ * query set (a cached key is reused without timing).  All configurations
+ * must agree on the counts (else GJ_EDEVICE).  out may be NULL. */
+gj_status gj_autotune(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_query* const* qs,
+                      const uint64_t* seed_lo, const uint64_t* seed_hi, const char* cache_path,
+                      gj_tuning* out);
 
 /* Copies the consolidated delta rows of query number q (its position in the
  * qs list) of the most recent gj_apply_updates on ctx that requested rows

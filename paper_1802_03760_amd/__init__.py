@@ -29,11 +29,17 @@ _lib = ctypes.CDLL(LIB_PATH)
 EXPORTS = ["gj_ctx_create", "gj_ctx_destroy", "gj_last_error", "gj_ctx_set_option",
            "gj_graph_build", "gj_graph_info", "gj_graph_csr", "gj_graph_destroy",
            "gj_query_register", "gj_query_destroy", "gj_run", "gj_apply_updates",
-           "gj_last_delta"]
+           "gj_last_delta", "gj_run_batch", "gj_autotune"]
 
 
 class Atom(ctypes.Structure):
     _fields_ = [("src_attr", ctypes.c_uint8), ("dst_attr", ctypes.c_uint8)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("batch_lin", ctypes.c_uint32), ("batch_waves_per_cu", ctypes.c_uint32),
+                ("best_ms", ctypes.c_double), ("configs_tried", ctypes.c_int),
+                ("from_cache", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
@@ -89,6 +95,11 @@ _lib.gj_apply_updates.argtypes = [_vp, _vp, _vp, _vp, _vp, _u64, _i32, ctypes.PO
 _lib.gj_apply_updates.restype = _i32
 _lib.gj_last_delta.argtypes = [_vp, _u32, _vp, _vp, _u64, _i32, ctypes.POINTER(_u64)]
 _lib.gj_last_delta.restype = _i32
+_lib.gj_run_batch.argtypes = [_vp, _vp, _u32, ctypes.POINTER(_vp), _vp, _vp, _vp, ctypes.POINTER(Stats)]
+_lib.gj_run_batch.restype = _i32
+_lib.gj_autotune.argtypes = [_vp, _vp, _u32, ctypes.POINTER(_vp), _vp, _vp, ctypes.c_char_p,
+                             ctypes.POINTER(Tuning)]
+_lib.gj_autotune.restype = _i32
 
 
 # Live handles, released in dependency order (queries, graphs, contexts) at
@@ -246,6 +257,35 @@ def count(ctx, graph, query, seed_lo=0, seed_hi=(1 << 64) - 1):
     ctx.check(_lib.gj_run(ctx._h, graph._h, query._h, MODE_COUNT, seed_lo, seed_hi, None, 0, 0,
                           ctypes.byref(st)), "gj_run(count)")
     return st.as_dict()
+
+
+def _requests(requests):
+    n = len(requests)
+    qh = (_vp * max(n, 1))(*[q._h.value for q, _, _ in requests])
+    lo = np.array([int(l) for _, l, _ in requests] or [0], dtype=np.uint64)
+    hi = np.array([int(h) for _, _, h in requests] or [0], dtype=np.uint64)
+    return n, qh, lo, hi
+
+
+def run_batch(ctx, graph, requests):
+    """Counts of [(query, seed_lo, seed_hi), ...] in one fused, graph-captured
+    pipeline (gj_run_batch).  Returns (counts, per-request stats)."""
+    n, qh, lo, hi = _requests(requests)
+    counts = np.zeros(max(n, 1), dtype=np.uint64)
+    stats = (Stats * max(n, 1))()
+    ctx.check(_lib.gj_run_batch(ctx._h, graph._h, n, qh, _np_ptr(lo), _np_ptr(hi), _np_ptr(counts), stats),
+              "gj_run_batch")
+    return [int(x) for x in counts[:n]], [stats[i].as_dict() for i in range(n)]
+
+
+def autotune(ctx, graph, requests, cache_path=None):
+    n, qh, lo, hi = _requests(requests)
+    out = Tuning()
+    ctx.check(_lib.gj_autotune(ctx._h, graph._h, n, qh, _np_ptr(lo), _np_ptr(hi),
+                               cache_path.encode() if cache_path else None, ctypes.byref(out)),
+              "gj_autotune")
+    return {"batch_lin": out.batch_lin, "batch_waves_per_cu": out.batch_waves_per_cu,
+            "best_ms": out.best_ms, "configs_tried": out.configs_tried, "from_cache": bool(out.from_cache)}
 
 
 def enumerate_rows(ctx, graph, query, seed_lo=0, seed_hi=(1 << 64) - 1, out=None, cap=None):

@@ -4,6 +4,7 @@
 #include <cstring>
 #include <new>
 
+#include "batch.h"
 #include "engine.h"
 #include "gj_internal.h"
 
@@ -144,6 +145,7 @@ void gj_ctx_destroy(gj_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  gj::batch_destroy(c);
   for (auto& kv : c->ws) gj::dev_free(kv.second.p);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->pinned) (void)hipHostFree(c->pinned);
@@ -166,6 +168,12 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "strategy") {
       GJ_CHECK(value >= 0 && value <= 2, GJ_EINVAL, "strategy out of range");
       c->strategy = (int)value;
+    } else if (k == "batch_lin") {
+      GJ_CHECK(value >= 0 && value <= 4096, GJ_EINVAL, "batch_lin out of range");
+      c->batch_lin = (uint32_t)value;
+    } else if (k == "batch_waves_per_cu") {
+      GJ_CHECK(value >= 4 && value <= 128 && value % 4 == 0, GJ_EINVAL, "batch_waves_per_cu out of range");
+      c->batch_waves_per_cu = (uint32_t)value;
     } else {
       throw Error{GJ_EINVAL, "unknown option " + k};
     }
@@ -325,6 +333,39 @@ gj_status gj_apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const ui
     return GJ_EOVERFLOW;
   }
   return s;
+}
+
+gj_status gj_run_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs,
+                       const uint64_t* seed_lo, const uint64_t* seed_hi, uint64_t* counts, gj_stats* stats) {
+  if (!c || !g || (nreq && (!qs || !seed_lo || !seed_hi || !counts))) return GJ_EINVAL;
+  auto t0 = std::chrono::steady_clock::now();
+  return guarded(c, [&] {
+    for (uint32_t i = 0; i < nreq; ++i) GJ_CHECK(qs[i], GJ_EINVAL, "null query");
+    if (nreq == 0) return;
+    if (!c->batch) c->batch = new gj::BatchExec();
+    bool overflow = false;
+    c->batch->run(c, g, nreq, qs, seed_lo, seed_hi, counts, stats, overflow);
+    if (overflow) {
+      // a level outgrew its capacity: depth-first path, bounded frontiers
+      for (uint32_t i = 0; i < nreq; ++i) {
+        gj_stats st{};
+        bool ov = false;
+        gj::run_static(c, g, qs[i], GJ_MODE_COUNT, seed_lo[i], seed_hi[i], nullptr, 0, 1, &st, ov);
+        counts[i] = st.matches;
+        if (stats) stats[i] = st;
+      }
+    }
+    double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (stats)
+      for (uint32_t i = 0; i < nreq; ++i) stats[i].ms = ms;
+  });
+}
+
+gj_status gj_autotune(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs,
+                      const uint64_t* seed_lo, const uint64_t* seed_hi, const char* cache_path,
+                      gj_tuning* out) {
+  if (!c || !g || !nreq || !qs || !seed_lo || !seed_hi) return GJ_EINVAL;
+  return guarded(c, [&] { gj::autotune(c, g, nreq, qs, seed_lo, seed_hi, cache_path, out); });
 }
 
 gj_status gj_last_delta(gj_ctx* c, uint32_t q, uint32_t* rows, int8_t* signs, uint64_t cap, int on_device,

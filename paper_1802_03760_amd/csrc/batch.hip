@@ -1,0 +1,480 @@
+// Batched execution: many count requests (query, seed slice) fused stage by
+// stage into one pipeline whose sizes live in device memory, captured once as
+// a hipGraph and replayed.
+//
+// Every prefix carries the id of its request; the per-request query plans
+// (seed index, filters, binding atoms of every stage, in the version the
+// request reads) sit in a device table.  Level j holds the prefixes of length
+// j of every request that has not finished; one count-minimisation pass, one
+// scan and one propose+intersect pass per level serve all of them, so
+// frontiers of very different sizes share launches (the synchronous dataflow
+// primitive of Sec. 3.1.1 applied to all requests at once).  Requests whose
+// query ends at attribute j+1 are counted there; the others are compacted into
+// level j+1 with one atomic per wave.  If a level would exceed its capacity
+// the run reports it and the host reruns the batch one request at a time on
+// the depth-first path, whose frontiers are bounded.
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+
+#include "batch.h"
+#include "engine.h"
+#include "gj_internal.h"
+#include "prim.h"
+
+namespace gj {
+
+struct BReq {
+  uint32_t m;
+  uint32_t pad;
+  uint64_t seed_lo;
+  const uint32_t* seed_row;
+  const uint32_t* seed_col;
+  SeedFilter filt;
+  StageDesc st[GJ_MAX_ATTRS];
+};
+
+// header of the device state: sizes and flags read by every kernel
+struct BHead {
+  uint32_t nreq;
+  uint32_t lin;        // tuned: linear search below this extension-set size
+  uint64_t seeds;      // total seed edges over all requests
+  unsigned long long nlev[GJ_MAX_ATTRS + 1];
+  uint32_t overflow;
+};
+
+constexpr int kStat = GJ_MAX_ATTRS + 1;
+
+__device__ __forceinline__ bool member(const uint32_t* __restrict__ a, uint32_t lo, uint32_t hi, uint32_t x,
+                                       uint32_t lin) {
+  if (hi - lo <= lin) {
+    for (uint32_t i = lo; i < hi; ++i) {
+      uint32_t y = a[i];
+      if (y >= x) return y == x;
+    }
+    return false;
+  }
+  return contains_u32(a, lo, hi, x);
+}
+
+// adds val to arr[key] for the active lanes: one atomic when the wave agrees on key
+__device__ __forceinline__ void agg_add(unsigned long long* arr, uint32_t key, uint64_t val, bool active) {
+  uint64_t act = __ballot(active);
+  if (!act) return;
+  int leader = __ffsll((unsigned long long)act) - 1;
+  uint32_t k0 = __shfl(key, leader, 64);
+  bool mixed = __ballot(active && key != k0) != 0;
+  if (!mixed) {
+    uint64_t s = wave_sum(active ? val : 0);
+    if (lane_id() == leader && s) atomicAdd(&arr[k0], (unsigned long long)s);
+  } else if (active && val) {
+    atomicAdd(&arr[key], (unsigned long long)val);
+  }
+}
+
+// wave-level slot reservation for the active lanes in an unordered buffer
+__device__ __forceinline__ uint64_t wave_reserve(unsigned long long* counter, bool active) {
+  uint64_t b = __ballot(active);
+  uint64_t base = 0;
+  if (lane_id() == 0 && b) base = atomicAdd(counter, (unsigned long long)__popcll(b));
+  base = shfl_u64(base, 0);
+  return base + __popcll(b & lanemask_lt());
+}
+
+__global__ void k_bt_clear(unsigned long long* __restrict__ p, uint64_t n) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) p[i] = 0;
+}
+
+__global__ void k_bt_head_reset(BHead* h) {
+  if (threadIdx.x == 0) {
+    for (int j = 0; j <= GJ_MAX_ATTRS; ++j) h->nlev[j] = 0;
+    h->overflow = 0;
+  }
+}
+
+// P_2 of every request: seed g of the concatenated seed space -> request r
+__global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, const uint64_t* __restrict__ roff,
+                                                    BHead* __restrict__ H, uint32_t* __restrict__ F,
+                                                    uint32_t* __restrict__ rid, uint64_t cap,
+                                                    unsigned long long* __restrict__ cnt,
+                                                    unsigned long long* __restrict__ pre) {
+  const uint32_t nreq = H->nreq;
+  const uint64_t total = H->seeds;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t base = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; base < total;
+       base += nwaves * 64) {
+    uint64_t g = base + lane_id();
+    bool valid = g < total;
+    uint32_t r = 0;
+    bool keep = false, fin = false;
+    uint32_t x0 = 0, x1 = 0;
+    if (valid) {
+      r = (uint32_t)find_segment(roff, 0, nreq, g);
+      const BReq& q = R[r];
+      uint64_t e = q.seed_lo + (g - roff[r]);
+      x0 = q.seed_row[e];
+      x1 = q.seed_col[e];
+      keep = true;
+      uint32_t x[2] = {x0, x1};
+      for (int a = 0; a < q.filt.n && keep; ++a) {
+        uint32_t key = x[q.filt.key[a]], val = x[q.filt.val[a]];
+        keep = contains_u32(q.filt.adj[a], q.filt.rp[a][key], q.filt.rp[a][key + 1], val);
+      }
+      fin = q.m == 2;
+    }
+    agg_add(pre, r * kStat + 2, 1, valid && keep);
+    agg_add(cnt, r, 1, valid && keep && fin);
+    bool store = valid && keep && !fin;
+    uint64_t pos = wave_reserve(&H->nlev[2], store);
+    if (store) {
+      if (pos < cap) {
+        F[pos] = x0;
+        F[cap + pos] = x1;
+        rid[pos] = r;
+      } else {
+        atomicOr(&H->overflow, 1u);
+      }
+    }
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_bt_count_min(const BReq* __restrict__ R, int j, BHead* __restrict__ H,
+                                                         const uint32_t* __restrict__ F,
+                                                         const uint32_t* __restrict__ rid, uint64_t cap,
+                                                         uint32_t* __restrict__ minc, uint8_t* __restrict__ mini,
+                                                         unsigned long long* __restrict__ ext) {
+  uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t base = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; base < n;
+       base += nwaves * 64) {
+    uint64_t p = base + lane_id();
+    bool valid = p < n;
+    uint32_t r = 0, best = 0;
+    if (valid) {
+      r = rid[p];
+      const StageDesc& d = R[r].st[j];
+      best = 0xFFFFFFFFu;
+      int bi = 0;
+      for (int a = 0; a < d.k; ++a) {
+        uint32_t v = F[(uint64_t)d.col[a] * cap + p];
+        uint32_t c = d.rp[a][v + 1] - d.rp[a][v];
+        if (c < best) {
+          best = c;
+          bi = a;
+        }
+      }
+      minc[p] = best;
+      mini[p] = (uint8_t)bi;
+    }
+    agg_add(ext, r * kStat + j, best, valid);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ R, int j, BHead* __restrict__ H,
+                                                       const uint32_t* __restrict__ F,
+                                                       const uint32_t* __restrict__ rid, uint64_t cap,
+                                                       const uint64_t* __restrict__ off,
+                                                       const uint8_t* __restrict__ mini, uint32_t* __restrict__ G,
+                                                       uint32_t* __restrict__ grid_, uint64_t gcap,
+                                                       unsigned long long* __restrict__ cnt,
+                                                       unsigned long long* __restrict__ pre) {
+  const uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
+  const uint64_t W = off[n];
+  const uint32_t lin = H->lin;
+  const int lane = lane_id();
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  const uint64_t nwords = (W + 63) >> 6;
+  for (uint64_t wd = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wd < nwords; wd += nwaves) {
+    uint64_t gf = wd << 6;
+    uint64_t gl = gf + 63 < W ? gf + 63 : W - 1;
+    uint64_t plo = find_segment(off, 0, n, gf);
+    uint64_t phi = find_segment(off, plo, n, gl) + 1;
+    uint64_t g = gf + lane;
+    bool valid = g < W, keep = false, fin = false;
+    uint32_t r = 0, e = 0;
+    uint64_t p = 0;
+    if (valid) {
+      p = find_segment(off, plo, phi, g);
+      r = rid[p];
+      const StageDesc& d = R[r].st[j];
+      uint32_t k = (uint32_t)(g - off[p]);
+      int am = mini[p];
+      uint32_t v = F[(uint64_t)d.col[am] * cap + p];
+      e = d.adj[am][d.rp[am][v] + k];
+      keep = true;
+      for (int a = 0; a < d.k && keep; ++a) {
+        if (a == am) continue;
+        uint32_t u = F[(uint64_t)d.col[a] * cap + p];
+        keep = member(d.adj[a], d.rp[a][u], d.rp[a][u + 1], e, lin);
+      }
+      fin = R[r].m == (uint32_t)(j + 1);
+    }
+    agg_add(pre, r * kStat + j + 1, 1, valid && keep);
+    agg_add(cnt, r, 1, valid && keep && fin);
+    bool store = valid && keep && !fin;
+    uint64_t pos = wave_reserve(&H->nlev[j + 1], store);
+    if (store) {
+      if (pos < gcap) {
+        for (int c = 0; c < j; ++c) G[(uint64_t)c * gcap + pos] = F[(uint64_t)c * cap + p];
+        G[(uint64_t)j * gcap + pos] = e;
+        grid_[pos] = r;
+      } else {
+        atomicOr(&H->overflow, 1u);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- device-size scan
+constexpr int kBtTile = kBlock * 8;
+
+__global__ void __launch_bounds__(kBlock) k_bt_scan_reduce(const uint32_t* __restrict__ in, const BHead* H, int j,
+                                                           uint64_t cap, uint64_t* __restrict__ part) {
+  uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
+  uint64_t base = (uint64_t)blockIdx.x * kBtTile;
+  uint64_t s = 0;
+  if (base < n) {
+    for (int i = 0; i < 8; ++i) {
+      uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
+      if (idx < n) s += in[idx];
+    }
+  }
+  s = block_sum<kBlock>(s);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ void __launch_bounds__(kBlock) k_bt_scan_down(const uint32_t* __restrict__ in, const BHead* H, int j,
+                                                         uint64_t cap, const uint64_t* __restrict__ part_off,
+                                                         uint64_t nparts, uint64_t* __restrict__ out) {
+  __shared__ uint64_t tile[kBtTile];
+  uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
+  uint64_t base = (uint64_t)blockIdx.x * kBtTile;
+  if (base > n) return;
+  for (int i = 0; i < 8; ++i) {
+    uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
+    tile[i * kBlock + threadIdx.x] = idx < n ? in[idx] : 0;
+  }
+  __syncthreads();
+  uint64_t loc[8], s = 0;
+  for (int i = 0; i < 8; ++i) {
+    loc[i] = tile[threadIdx.x * 8 + i];
+    s += loc[i];
+  }
+  uint64_t tot;
+  uint64_t run = block_excl_scan<kBlock, uint64_t>(s, tot) + part_off[blockIdx.x];
+  for (int i = 0; i < 8; ++i) {
+    tile[threadIdx.x * 8 + i] = run;
+    run += loc[i];
+  }
+  __syncthreads();
+  for (int i = 0; i < 8; ++i) {
+    uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
+    if (idx <= n) out[idx] = idx < n ? tile[i * kBlock + threadIdx.x] : part_off[nparts];
+  }
+}
+
+// exclusive scan of the block sums, one workgroup walking tiles (no host size)
+__global__ void __launch_bounds__(kBlock) k_bt_scan_parts(const uint64_t* __restrict__ part, uint64_t n,
+                                                          uint64_t* __restrict__ out) {
+  uint64_t carry = 0;
+  for (uint64_t base = 0; base < n; base += kBtTile) {
+    uint64_t loc[8], s = 0;
+    for (int i = 0; i < 8; ++i) {
+      uint64_t idx = base + (uint64_t)threadIdx.x * 8 + i;
+      loc[i] = idx < n ? part[idx] : 0;
+      s += loc[i];
+    }
+    uint64_t tot;
+    uint64_t run = carry + block_excl_scan<kBlock, uint64_t>(s, tot);
+    for (int i = 0; i < 8; ++i) {
+      uint64_t idx = base + (uint64_t)threadIdx.x * 8 + i;
+      if (idx < n) out[idx] = run;
+      run += loc[i];
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n] = carry;
+}
+
+// ---------------------------------------------------------------- executor
+struct BatchExec::Impl {
+  uint32_t max_req = 0;
+  int max_m = 0;
+  uint64_t cap = 0;
+  BReq* d_req = nullptr;
+  uint64_t* d_roff = nullptr;
+  BHead* d_head = nullptr;
+  unsigned long long* d_cnt = nullptr;  // [max_req]
+  unsigned long long* d_pre = nullptr;  // [max_req * kStat]
+  unsigned long long* d_ext = nullptr;  // [max_req * kStat]
+  uint32_t* F[GJ_MAX_ATTRS + 1] = {};
+  uint32_t* rid[GJ_MAX_ATTRS + 1] = {};
+  uint32_t* minc[GJ_MAX_ATTRS + 1] = {};
+  uint8_t* mini[GJ_MAX_ATTRS + 1] = {};
+  uint64_t* off[GJ_MAX_ATTRS + 1] = {};
+  uint64_t* part = nullptr;
+  uint64_t* part_off = nullptr;
+  uint64_t nparts = 0;
+  void* h_stage = nullptr;  // pinned staging for the request table and results
+  size_t h_stage_bytes = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  unsigned grid_cfg = 0;
+  std::vector<void*> allocs;
+
+  void* alloc(size_t b) {
+    void* p = dev_alloc(b);
+    allocs.push_back(p);
+    return p;
+  }
+  ~Impl() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (void* p : allocs) dev_free(p);
+    if (h_stage) (void)hipHostFree(h_stage);
+  }
+};
+
+BatchExec::BatchExec() : p(new Impl) {}
+BatchExec::~BatchExec() { delete p; }
+
+static void enqueue(gj_ctx* c, BatchExec::Impl& s, unsigned grid) {
+  hipStream_t st = c->stream;
+  uint64_t stat_words = (uint64_t)s.max_req * (1 + 2 * kStat);
+  k_bt_head_reset<<<1, 64, 0, st>>>(s.d_head);
+  k_bt_clear<<<grid_for(stat_words, kBlock, 1024), kBlock, 0, st>>>(s.d_cnt, stat_words);
+  k_bt_seed<<<grid, kBlock, 0, st>>>(s.d_req, s.d_roff, s.d_head, s.F[2], s.rid[2], s.cap, s.d_cnt, s.d_pre);
+  for (int j = 2; j < s.max_m; ++j) {
+    k_bt_count_min<<<grid, kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j], s.cap, s.minc[j], s.mini[j],
+                                           s.d_ext);
+    k_bt_scan_reduce<<<(unsigned)s.nparts, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part);
+    k_bt_scan_parts<<<1, kBlock, 0, st>>>(s.part, s.nparts, s.part_off);
+    k_bt_scan_down<<<(unsigned)s.nparts, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part_off, s.nparts,
+                                                         s.off[j]);
+    uint32_t* G = j + 1 < s.max_m ? s.F[j + 1] : nullptr;
+    uint32_t* Gr = j + 1 < s.max_m ? s.rid[j + 1] : nullptr;
+    k_bt_propose<<<grid, kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j], s.cap, s.off[j], s.mini[j], G, Gr,
+                                         G ? s.cap : 0, s.d_cnt, s.d_pre);
+  }
+}
+
+static void fill_req(BReq& b, const PlanH& P, const Views& V, uint64_t lo) {
+  memset(&b, 0, sizeof(b));
+  b.m = (uint32_t)P.m;
+  const Version& sv = V.of(P.seed_atom);
+  int dir = P.seed_fwd ? 0 : 1;
+  b.seed_lo = lo;
+  b.seed_row = sv.d[dir].row;
+  b.seed_col = sv.d[dir].col;
+  b.filt = seed_filter(P, V);
+  for (int j = 2; j < P.m; ++j) b.st[j] = stage_desc(P, V, j);
+}
+
+void BatchExec::run(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* lo,
+                    const uint64_t* hi, uint64_t* counts, gj_stats* stats, bool& overflow) {
+  Impl& s = *p;
+  overflow = false;
+  int max_m = 2;
+  for (uint32_t i = 0; i < nreq; ++i) max_m = std::max(max_m, qs[i]->m);
+  uint64_t cap = c->frontier_cap;
+  unsigned grid = (unsigned)c->num_cus * (c->batch_waves_per_cu / 4 > 0 ? c->batch_waves_per_cu / 4 : 1);
+  bool rebuild = nreq > s.max_req || max_m > s.max_m || cap != s.cap || grid != s.grid_cfg || !s.exec;
+  if (rebuild) {
+    uint32_t mr = std::max<uint32_t>(nreq, std::max<uint32_t>(s.max_req, 64));
+    int mm = std::max(max_m, std::max(s.max_m, 3));
+    delete p;
+    p = new Impl;
+    Impl& t = *p;
+    t.max_req = mr;
+    t.max_m = mm;
+    t.cap = cap;
+    t.grid_cfg = grid;
+    t.d_req = (BReq*)t.alloc(sizeof(BReq) * mr);
+    t.d_roff = (uint64_t*)t.alloc(sizeof(uint64_t) * (mr + 1));
+    t.d_head = (BHead*)t.alloc(sizeof(BHead));
+    t.d_cnt = (unsigned long long*)t.alloc(sizeof(unsigned long long) * mr * (1 + 2 * kStat));
+    t.d_pre = t.d_cnt + mr;
+    t.d_ext = t.d_pre + (uint64_t)mr * kStat;
+    for (int j = 2; j < mm; ++j) {
+      t.F[j] = (uint32_t*)t.alloc(cap * j * sizeof(uint32_t));
+      t.rid[j] = (uint32_t*)t.alloc(cap * sizeof(uint32_t));
+      t.minc[j] = (uint32_t*)t.alloc(cap * sizeof(uint32_t));
+      t.mini[j] = (uint8_t*)t.alloc(cap);
+      t.off[j] = (uint64_t*)t.alloc((cap + 1) * sizeof(uint64_t));
+    }
+    t.nparts = (cap + kBtTile - 1) / kBtTile + 1;
+    t.part = (uint64_t*)t.alloc(t.nparts * sizeof(uint64_t));
+    t.part_off = (uint64_t*)t.alloc((t.nparts + 1) * sizeof(uint64_t));
+    t.h_stage_bytes = sizeof(BHead) + sizeof(BReq) * mr + sizeof(uint64_t) * (mr + 1) +
+                      sizeof(unsigned long long) * mr * (1 + 2 * kStat);
+    GJ_HIP(hipHostMalloc(&t.h_stage, t.h_stage_bytes, hipHostMallocDefault));
+    // capture the level pipeline once; it reads every size from device memory
+    GJ_HIP(hipStreamSynchronize(c->stream));
+    GJ_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+    enqueue(c, t, grid);
+    hipError_t ce = hipStreamEndCapture(c->stream, &t.graph);
+    GJ_CHECK(ce == hipSuccess, GJ_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ce));
+    GJ_HIP(hipGraphInstantiate(&t.exec, t.graph, nullptr, nullptr, 0));
+  }
+  Impl& t = *p;
+  // request table
+  const Version& v = g->ver[g->cur];
+  Views V{&v, &v, -1};
+  char* hs = (char*)t.h_stage;
+  BHead* hh = (BHead*)hs;
+  BReq* hr = (BReq*)(hs + sizeof(BHead));
+  uint64_t* ho = (uint64_t*)(hr + t.max_req);
+  memset(hh, 0, sizeof(BHead));
+  uint64_t tot = 0;
+  for (uint32_t i = 0; i < nreq; ++i) {
+    PlanH P = make_plan(qs[i], qs[i]->order, -1);
+    uint64_t E = v.m;
+    uint64_t h = std::min<uint64_t>(hi[i], E), l = std::min<uint64_t>(lo[i], h);
+    fill_req(hr[i], P, V, l);
+    ho[i] = tot;
+    tot += h - l;
+  }
+  ho[nreq] = tot;
+  hh->nreq = nreq;
+  hh->lin = c->batch_lin;
+  hh->seeds = tot;
+  GJ_HIP(hipMemcpyAsync(t.d_req, hr, sizeof(BReq) * nreq, hipMemcpyHostToDevice, c->stream));
+  GJ_HIP(hipMemcpyAsync(t.d_roff, ho, sizeof(uint64_t) * (nreq + 1), hipMemcpyHostToDevice, c->stream));
+  GJ_HIP(hipMemcpyAsync(t.d_head, hh, sizeof(BHead), hipMemcpyHostToDevice, c->stream));
+  KernelTimer timer(c);
+  timer.start();
+  GJ_HIP(hipGraphLaunch(t.exec, c->stream));
+  timer.stop();
+  unsigned long long* res = (unsigned long long*)(ho + t.max_req + 1);
+  uint64_t words = (uint64_t)t.max_req * (1 + 2 * kStat);
+  GJ_HIP(hipMemcpyAsync(res, t.d_cnt, words * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+  GJ_HIP(hipMemcpyAsync(hh, t.d_head, sizeof(BHead), hipMemcpyDeviceToHost, c->stream));
+  double kms = timer.total_ms();  // synchronises
+  overflow = hh->overflow != 0;
+  if (overflow) return;
+  for (uint32_t i = 0; i < nreq; ++i) {
+    counts[i] = res[i];
+    if (stats) {
+      gj_stats st{};
+      st.matches = res[i];
+      for (int j = 0; j < kStat; ++j) {
+        st.prefixes[j] = res[t.max_req + (uint64_t)i * kStat + j];
+        st.extensions[j] = res[t.max_req + (uint64_t)t.max_req * kStat + (uint64_t)i * kStat + j];
+      }
+      st.kernel_ms = kms;
+      st.kernel_launches = 1;
+      stats[i] = st;
+    }
+  }
+}
+
+void batch_destroy(gj_ctx* c) {
+  delete c->batch;
+  c->batch = nullptr;
+}
+
+}  // namespace gj

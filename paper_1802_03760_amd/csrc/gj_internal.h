@@ -11,6 +11,7 @@
 #include "gj.h"
 
 namespace gj {
+class BatchExec;
 
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kMaxBind = 8;       // binding atoms per stage handled by the kernels
@@ -105,6 +106,10 @@ struct gj_ctx {
     int8_t* signs = nullptr;
   };
   std::vector<LastDelta> last_delta;
+  // batched executor and its tuned parameters
+  gj::BatchExec* batch = nullptr;
+  uint32_t batch_lin = 8;           // linear search below this extension-set size
+  uint32_t batch_waves_per_cu = 32; // resident waves per CU of the persistent grids
 };
 
 struct gj_graph {
@@ -193,6 +198,10 @@ uint64_t consolidate_rows(gj_ctx* c, const uint32_t* rows, const int8_t* signs, 
                           uint32_t* out_rows, int8_t* out_signs, uint64_t cap, int64_t* sum);
 int bits_for(uint32_t n);
 void version_finish(gj_ctx* c, Version& v, uint32_t n);
+
+// tune.cpp
+void autotune(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* lo,
+              const uint64_t* hi, const char* cache_path, gj_tuning* out);
 
 // engine.hip
 void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint64_t lo,
