@@ -67,6 +67,48 @@ def cpu_baseline(src, dst, n, budget_s, threads):
             "seconds": round(el, 2), "extensions": ext}
 
 
+def batched_vs_plain(gj, ctx, G, nreq, seed, log, max_width=1000):
+    """Seed-slice count requests of the 4-clique and diamond queries (plus
+    triangle and 4-cycle) over the same graph, with uneven sizes: one gj_run
+    per request (plain, depth-first, host-driven) against one fused
+    gj_run_batch (hipGraph replay) after autotuning.  Both must agree."""
+    import numpy as np
+    E = G.info()["edges"]
+    rng = np.random.default_rng(seed)
+    kinds = {"4-clique": (4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]),
+             "diamond": (4, [(0, 1), (0, 2), (1, 3), (2, 3)]),
+             "triangle": (3, [(0, 1), (1, 2), (0, 2)]),
+             "4-cycle": (4, [(0, 1), (1, 2), (2, 3), (3, 0)])}
+    qs = {k: gj.Query(ctx, *v) for k, v in kinds.items()}
+    names = ["4-clique", "diamond", "4-clique", "diamond", "triangle", "4-cycle"]
+    reqs = []
+    for i in range(nreq):
+        k = names[i % len(names)]
+        lo = int(rng.integers(E // 8, E))
+        width = int(np.exp(rng.uniform(0, np.log(max_width))))
+        reqs.append((qs[k], lo, min(E, lo + width)))
+    tune = gj.autotune(ctx, G, reqs)
+    gj.run_batch(ctx, G, reqs)
+    t0 = time.perf_counter()
+    counts, bst = gj.run_batch(ctx, G, reqs)
+    tb = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plain = [gj.count(ctx, G, q, lo, hi) for q, lo, hi in reqs]
+    tp = time.perf_counter() - t0
+    assert counts == [p["matches"] for p in plain]
+    fallbacks = ctx.get_option("batch_fallbacks")
+    assert all(b["extensions"] == p["extensions"] for b, p in zip(bst, plain))
+    ext = sum(sum(p["extensions"]) for p in plain)
+    log("batched: %d requests, %d extensions: plain %.1f ms, batched %.1f ms (fallbacks %d)"
+        % (nreq, ext, tp * 1e3, tb * 1e3, ctx.get_option("batch_fallbacks")))
+    return {"requests": nreq, "queries": "4-clique, diamond, triangle, 4-cycle seed slices (widths "
+                                          "log-uniform in [1, %d] seed edges)" % max_width,
+            "extensions": ext, "matches": int(sum(counts)),
+            "plain_ms": tp * 1e3, "batched_ms": tb * 1e3,
+            "plain_extensions_per_s": ext / tp, "batched_extensions_per_s": ext / tb,
+            "speedup": tp / tb, "tuning": tune, "fallbacks": fallbacks}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +119,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--strategy", type=int, default=0)
+    ap.add_argument("--batch-requests", type=int, default=64)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of known "
                          "traffic that scales the HBM counters of a profiling run")
@@ -144,6 +187,11 @@ def main():
     log("triangle count: %d matches, %d extensions, %.2f ms/step, kernel %.2f ms (%d launches)"
         % (matches, ext, ms_step, kern_ms, launches))
 
+    batched = None
+    if args.batch_requests:
+        batched = {"small_requests": batched_vs_plain(gj, ctx, G, 4 * args.batch_requests, 11, log, 100),
+                   "large_requests": batched_vs_plain(gj, ctx, G, args.batch_requests, 7, log, 1000)}
+
     # delta-batch latency: update stream on the same graph
     lat = []
     qd = [q]
@@ -196,6 +244,7 @@ def main():
                      "avg_launch_ms": kern_ms / max(launches, 1),
                      "algorithmic_bytes_per_step": step_bytes},
         "cpu_baseline": cpu,
+        "batched": batched,
     }
     print(json.dumps(out), flush=True)
 

@@ -66,8 +66,14 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   extension sets of at most this size (default 8)
  *   "batch_waves_per_cu"  gj_run_batch: resident waves per CU of its
  *                   persistent grids, a multiple of 4 in [4, 128] (default 32)
+ *   "batch_cap"     gj_run_batch: prefixes per level (default 2^27)
  * Returns GJ_EINVAL for an unknown key or out-of-range value. */
 gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
+
+/* Reads an option (keys above, plus "batch_cap" and the counter
+ * "batch_fallbacks": gj_run_batch calls that fell back to the depth-first
+ * path). */
+gj_status gj_ctx_get_option(gj_ctx* ctx, const char* key, int64_t* value);
 
 /* ---------------------------------------------------------------- graphs */
 
@@ -179,7 +185,7 @@ gj_status gj_apply_updates(gj_ctx* ctx, gj_graph* g, const uint32_t* src,
  * as a hipGraph and replayed (the synchronous dataflow primitive of
  * Sec. 3.1.1 over all requests).  counts[i] and stats[i] (stats may be NULL)
  * equal what gj_run(COUNT) returns for request i.  A level larger than
- * "frontier_cap" prefixes makes the call fall back to one depth-first gj_run
+ * "batch_cap" prefixes makes the call fall back to one depth-first gj_run
  * per request (same results, bounded memory). */
 gj_status gj_run_batch(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_query* const* qs,
                        const uint64_t* seed_lo, const uint64_t* seed_hi, uint64_t* counts,

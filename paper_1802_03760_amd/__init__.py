@@ -26,7 +26,7 @@ if not os.path.exists(LIB_PATH):
                       "python paper_1802_03760_amd/build.py); there is no fallback")
 _lib = ctypes.CDLL(LIB_PATH)
 
-EXPORTS = ["gj_ctx_create", "gj_ctx_destroy", "gj_last_error", "gj_ctx_set_option",
+EXPORTS = ["gj_ctx_create", "gj_ctx_destroy", "gj_last_error", "gj_ctx_set_option", "gj_ctx_get_option",
            "gj_graph_build", "gj_graph_info", "gj_graph_csr", "gj_graph_destroy",
            "gj_query_register", "gj_query_destroy", "gj_run", "gj_apply_updates",
            "gj_last_delta", "gj_run_batch", "gj_autotune"]
@@ -74,6 +74,8 @@ _lib.gj_last_error.argtypes = [_vp]
 _lib.gj_last_error.restype = ctypes.c_char_p
 _lib.gj_ctx_set_option.argtypes = [_vp, ctypes.c_char_p, ctypes.c_int64]
 _lib.gj_ctx_set_option.restype = _i32
+_lib.gj_ctx_get_option.argtypes = [_vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64)]
+_lib.gj_ctx_get_option.restype = _i32
 _lib.gj_graph_build.argtypes = [_vp, _vp, _vp, _u64, _u32, _u32, ctypes.POINTER(_vp)]
 _lib.gj_graph_build.restype = _i32
 _lib.gj_graph_info.argtypes = [_vp, ctypes.POINTER(_u64), ctypes.POINTER(_u32),
@@ -167,6 +169,11 @@ class Context:
 
     def set_option(self, key, value):
         self.check(_lib.gj_ctx_set_option(self._h, key.encode(), int(value)), "set_option")
+
+    def get_option(self, key):
+        v = ctypes.c_int64()
+        self.check(_lib.gj_ctx_get_option(self._h, key.encode(), ctypes.byref(v)), "get_option")
+        return v.value
 
     def close(self):
         """Destroys the context and every graph and query created on it."""

@@ -168,6 +168,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "strategy") {
       GJ_CHECK(value >= 0 && value <= 2, GJ_EINVAL, "strategy out of range");
       c->strategy = (int)value;
+    } else if (k == "batch_cap") {
+      GJ_CHECK(value >= 64 && value <= (1ll << 32), GJ_EINVAL, "batch_cap out of range");
+      c->batch_cap = (uint64_t)value;
     } else if (k == "batch_lin") {
       GJ_CHECK(value >= 0 && value <= 4096, GJ_EINVAL, "batch_lin out of range");
       c->batch_lin = (uint32_t)value;
@@ -177,6 +180,21 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else {
       throw Error{GJ_EINVAL, "unknown option " + k};
     }
+  });
+}
+
+gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
+  if (!c || !key || !value) return GJ_EINVAL;
+  return guarded(c, [&] {
+    std::string k(key);
+    if (k == "frontier_cap") *value = (int64_t)c->frontier_cap;
+    else if (k == "seed_chunk") *value = (int64_t)c->seed_chunk;
+    else if (k == "strategy") *value = c->strategy;
+    else if (k == "batch_cap") *value = (int64_t)c->batch_cap;
+    else if (k == "batch_lin") *value = c->batch_lin;
+    else if (k == "batch_waves_per_cu") *value = c->batch_waves_per_cu;
+    else if (k == "batch_fallbacks") *value = (int64_t)c->batch_fallbacks;
+    else throw Error{GJ_EINVAL, "unknown option " + k};
   });
 }
 
@@ -347,6 +365,7 @@ gj_status gj_run_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_que
     c->batch->run(c, g, nreq, qs, seed_lo, seed_hi, counts, stats, overflow);
     if (overflow) {
       // a level outgrew its capacity: depth-first path, bounded frontiers
+      ++c->batch_fallbacks;
       for (uint32_t i = 0; i < nreq; ++i) {
         gj_stats st{};
         bool ov = false;

@@ -43,8 +43,11 @@ struct BHead {
   uint32_t lin;        // tuned: linear search below this extension-set size
   uint64_t seeds;      // total seed edges over all requests
   unsigned long long nlev[GJ_MAX_ATTRS + 1];
+  unsigned long long claim[GJ_MAX_ATTRS + 1];  // next unclaimed word chunk per level
   uint32_t overflow;
 };
+
+constexpr uint32_t kChunkWords = 16;  // 1024 candidates claimed at a time
 
 constexpr int kStat = GJ_MAX_ATTRS + 1;
 
@@ -60,20 +63,34 @@ __device__ __forceinline__ bool member(const uint32_t* __restrict__ a, uint32_t 
   return contains_u32(a, lo, hi, x);
 }
 
-// adds val to arr[key] for the active lanes: one atomic when the wave agrees on key
-__device__ __forceinline__ void agg_add(unsigned long long* arr, uint32_t key, uint64_t val, bool active) {
-  uint64_t act = __ballot(active);
-  if (!act) return;
-  int leader = __ffsll((unsigned long long)act) - 1;
-  uint32_t k0 = __shfl(key, leader, 64);
-  bool mixed = __ballot(active && key != k0) != 0;
-  if (!mixed) {
-    uint64_t s = wave_sum(active ? val : 0);
-    if (lane_id() == leader && s) atomicAdd(&arr[k0], (unsigned long long)s);
-  } else if (active && val) {
-    atomicAdd(&arr[key], (unsigned long long)val);
+// Wave-resident accumulator of arr[key] += val: runs of iterations that agree
+// on one key add in registers and flush with a single atomic when the key
+// changes (or at the end); a wave mixing keys adds lane by lane.  key and the
+// running sum are wave-uniform.
+struct WaveAcc {
+  uint32_t key = 0xFFFFFFFFu;
+  uint64_t sum = 0;
+  __device__ __forceinline__ void flush(unsigned long long* arr) {
+    if (lane_id() == 0 && sum && key != 0xFFFFFFFFu) atomicAdd(&arr[key], (unsigned long long)sum);
+    sum = 0;
   }
-}
+  __device__ __forceinline__ void add(unsigned long long* arr, uint32_t k, uint64_t val, bool active, bool unit) {
+    uint64_t act = __ballot(active);
+    if (!act) return;
+    int leader = __ffsll((unsigned long long)act) - 1;
+    uint32_t k0 = __builtin_amdgcn_readfirstlane(__shfl(k, leader, 64));
+    if (__ballot(active && k != k0) == 0) {
+      uint64_t s = unit ? (uint64_t)__popcll(act) : wave_sum(active ? val : 0);
+      if (k0 != key) {
+        flush(arr);
+        key = k0;
+      }
+      sum += s;
+    } else if (active && val) {
+      atomicAdd(&arr[k], (unsigned long long)val);
+    }
+  }
+};
 
 // wave-level slot reservation for the active lanes in an unordered buffer
 __device__ __forceinline__ uint64_t wave_reserve(unsigned long long* counter, bool active) {
@@ -91,7 +108,7 @@ __global__ void k_bt_clear(unsigned long long* __restrict__ p, uint64_t n) {
 
 __global__ void k_bt_head_reset(BHead* h) {
   if (threadIdx.x == 0) {
-    for (int j = 0; j <= GJ_MAX_ATTRS; ++j) h->nlev[j] = 0;
+    for (int j = 0; j <= GJ_MAX_ATTRS; ++j) h->nlev[j] = h->claim[j] = 0;
     h->overflow = 0;
   }
 }
@@ -105,6 +122,7 @@ __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, 
   const uint32_t nreq = H->nreq;
   const uint64_t total = H->seeds;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  WaveAcc a_pre, a_cnt;
   for (uint64_t base = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; base < total;
        base += nwaves * 64) {
     uint64_t g = base + lane_id();
@@ -126,8 +144,8 @@ __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, 
       }
       fin = q.m == 2;
     }
-    agg_add(pre, r * kStat + 2, 1, valid && keep);
-    agg_add(cnt, r, 1, valid && keep && fin);
+    a_pre.add(pre, r * kStat + 2, 1, valid && keep, true);
+    a_cnt.add(cnt, r, 1, valid && keep && fin, true);
     bool store = valid && keep && !fin;
     uint64_t pos = wave_reserve(&H->nlev[2], store);
     if (store) {
@@ -140,6 +158,18 @@ __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, 
       }
     }
   }
+  a_pre.flush(pre);
+  a_cnt.flush(cnt);
+}
+
+// The lanes of a wave are served one request at a time: the first pending
+// request id is made wave-uniform, its plan is read with scalar loads into
+// registers (loops over binding atoms fully unrolled), and the lanes of that
+// request run; a wave spanning a request boundary takes a second pass.
+__device__ __forceinline__ uint32_t first_pending(uint32_t r, bool todo) {
+  uint64_t m = __ballot(todo);
+  int l = __ffsll((unsigned long long)m) - 1;
+  return __builtin_amdgcn_readfirstlane(__shfl(r, l, 64));
 }
 
 __global__ void __launch_bounds__(kBlock) k_bt_count_min(const BReq* __restrict__ R, int j, BHead* __restrict__ H,
@@ -149,29 +179,38 @@ __global__ void __launch_bounds__(kBlock) k_bt_count_min(const BReq* __restrict_
                                                          unsigned long long* __restrict__ ext) {
   uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  WaveAcc a_ext;
   for (uint64_t base = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; base < n;
        base += nwaves * 64) {
     uint64_t p = base + lane_id();
     bool valid = p < n;
-    uint32_t r = 0, best = 0;
-    if (valid) {
-      r = rid[p];
-      const StageDesc& d = R[r].st[j];
-      best = 0xFFFFFFFFu;
-      int bi = 0;
-      for (int a = 0; a < d.k; ++a) {
-        uint32_t v = F[(uint64_t)d.col[a] * cap + p];
-        uint32_t c = d.rp[a][v + 1] - d.rp[a][v];
-        if (c < best) {
-          best = c;
-          bi = a;
+    uint32_t r = valid ? rid[p] : 0u, best = 0;
+    bool todo = valid;
+    while (__ballot(todo)) {
+      uint32_t rc = first_pending(r, todo);
+      const StageDesc d = R[rc].st[j];
+      if (todo && r == rc) {
+        best = 0xFFFFFFFFu;
+        int bi = 0;
+#pragma unroll
+        for (int a = 0; a < kMaxBind; ++a) {
+          if (a < d.k) {
+            uint32_t v = F[(uint64_t)d.col[a] * cap + p];
+            uint32_t c = d.rp[a][v + 1] - d.rp[a][v];
+            if (c < best) {
+              best = c;
+              bi = a;
+            }
+          }
         }
+        minc[p] = best;
+        mini[p] = (uint8_t)bi;
+        todo = false;
       }
-      minc[p] = best;
-      mini[p] = (uint8_t)bi;
     }
-    agg_add(ext, r * kStat + j, best, valid);
+    a_ext.add(ext, r * kStat + j, best, valid, false);
   }
+  a_ext.flush(ext);
 }
 
 __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ R, int j, BHead* __restrict__ H,
@@ -188,11 +227,22 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
   const int lane = lane_id();
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   const uint64_t nwords = (W + 63) >> 6;
-  for (uint64_t wd = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wd < nwords; wd += nwaves) {
+  (void)nwaves;
+  WaveAcc a_pre, a_cnt;
+  // waves claim chunks of kChunkWords words from a device counter and walk
+  // each chunk galloping forward over the prefixes
+  for (;;) {
+    uint64_t cb = 0;
+    if (lane == 0) cb = atomicAdd(&H->claim[j], 1ull);
+    cb = shfl_u64(cb, 0) * kChunkWords;
+    if (cb >= nwords) break;
+    uint64_t ce = cb + kChunkWords < nwords ? cb + kChunkWords : nwords;
+    uint64_t plo = find_segment(off, 0, n, cb << 6);
+  for (uint64_t wd = cb; wd < ce; ++wd) {
     uint64_t gf = wd << 6;
     uint64_t gl = gf + 63 < W ? gf + 63 : W - 1;
-    uint64_t plo = find_segment(off, 0, n, gf);
-    uint64_t phi = find_segment(off, plo, n, gl) + 1;
+    plo = gallop_segment(off, plo, n, gf);
+    uint64_t phi = gallop_segment(off, plo, n, gl) + 1;
     uint64_t g = gf + lane;
     bool valid = g < W, keep = false, fin = false;
     uint32_t r = 0, e = 0;
@@ -200,21 +250,42 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
     if (valid) {
       p = find_segment(off, plo, phi, g);
       r = rid[p];
-      const StageDesc& d = R[r].st[j];
-      uint32_t k = (uint32_t)(g - off[p]);
-      int am = mini[p];
-      uint32_t v = F[(uint64_t)d.col[am] * cap + p];
-      e = d.adj[am][d.rp[am][v] + k];
-      keep = true;
-      for (int a = 0; a < d.k && keep; ++a) {
-        if (a == am) continue;
-        uint32_t u = F[(uint64_t)d.col[a] * cap + p];
-        keep = member(d.adj[a], d.rp[a][u], d.rp[a][u + 1], e, lin);
-      }
-      fin = R[r].m == (uint32_t)(j + 1);
     }
-    agg_add(pre, r * kStat + j + 1, 1, valid && keep);
-    agg_add(cnt, r, 1, valid && keep && fin);
+    bool todo = valid;
+    while (__ballot(todo)) {
+      uint32_t rc = first_pending(r, todo);
+      const StageDesc d = R[rc].st[j];
+      const uint32_t mc = R[rc].m;
+      if (todo && r == rc) {
+        uint32_t k = (uint32_t)(g - off[p]);
+        int am = mini[p];
+        const uint32_t* rp_m = d.rp[0];
+        const uint32_t* adj_m = d.adj[0];
+        int col_m = d.col[0];
+#pragma unroll
+        for (int a = 1; a < kMaxBind; ++a) {
+          if (a == am) {
+            rp_m = d.rp[a];
+            adj_m = d.adj[a];
+            col_m = d.col[a];
+          }
+        }
+        uint32_t v = F[(uint64_t)col_m * cap + p];
+        e = adj_m[rp_m[v] + k];
+        keep = true;
+#pragma unroll
+        for (int a = 0; a < kMaxBind; ++a) {
+          if (a < d.k && a != am && keep) {
+            uint32_t u = F[(uint64_t)d.col[a] * cap + p];
+            keep = member(d.adj[a], d.rp[a][u], d.rp[a][u + 1], e, lin);
+          }
+        }
+        fin = mc == (uint32_t)(j + 1);
+        todo = false;
+      }
+    }
+    a_pre.add(pre, r * kStat + j + 1, 1, valid && keep, true);
+    a_cnt.add(cnt, r, 1, valid && keep && fin, true);
     bool store = valid && keep && !fin;
     uint64_t pos = wave_reserve(&H->nlev[j + 1], store);
     if (store) {
@@ -227,6 +298,9 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
       }
     }
   }
+  }
+  a_pre.flush(pre);
+  a_cnt.flush(cnt);
 }
 
 // ---------------------------------------------------------------- device-size scan
@@ -349,8 +423,9 @@ static void enqueue(gj_ctx* c, BatchExec::Impl& s, unsigned grid) {
   k_bt_clear<<<grid_for(stat_words, kBlock, 1024), kBlock, 0, st>>>(s.d_cnt, stat_words);
   k_bt_seed<<<grid, kBlock, 0, st>>>(s.d_req, s.d_roff, s.d_head, s.F[2], s.rid[2], s.cap, s.d_cnt, s.d_pre);
   for (int j = 2; j < s.max_m; ++j) {
-    k_bt_count_min<<<grid, kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j], s.cap, s.minc[j], s.mini[j],
-                                           s.d_ext);
+    // latency-bound, no dynamic claiming: oversubscribe (idle blocks exit at once)
+    k_bt_count_min<<<grid_for(s.cap, kBlock * 4, 8192), kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j],
+                                                                         s.cap, s.minc[j], s.mini[j], s.d_ext);
     k_bt_scan_reduce<<<(unsigned)s.nparts, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part);
     k_bt_scan_parts<<<1, kBlock, 0, st>>>(s.part, s.nparts, s.part_off);
     k_bt_scan_down<<<(unsigned)s.nparts, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part_off, s.nparts,
@@ -380,7 +455,7 @@ void BatchExec::run(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query*
   overflow = false;
   int max_m = 2;
   for (uint32_t i = 0; i < nreq; ++i) max_m = std::max(max_m, qs[i]->m);
-  uint64_t cap = c->frontier_cap;
+  uint64_t cap = c->batch_cap;
   unsigned grid = (unsigned)c->num_cus * (c->batch_waves_per_cu / 4 > 0 ? c->batch_waves_per_cu / 4 : 1);
   bool rebuild = nreq > s.max_req || max_m > s.max_m || cap != s.cap || grid != s.grid_cfg || !s.exec;
   if (rebuild) {

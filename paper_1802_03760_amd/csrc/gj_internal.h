@@ -110,6 +110,8 @@ struct gj_ctx {
   gj::BatchExec* batch = nullptr;
   uint32_t batch_lin = 8;           // linear search below this extension-set size
   uint32_t batch_waves_per_cu = 32; // resident waves per CU of the persistent grids
+  uint64_t batch_cap = 1ull << 27;  // prefixes per level of the batched pipeline
+  uint64_t batch_fallbacks = 0;     // batches rerun depth-first after a level overflow
 };
 
 struct gj_graph {

@@ -132,4 +132,18 @@ __device__ __forceinline__ uint64_t find_segment(const uint64_t* __restrict__ of
   return lo;
 }
 
+// As find_segment, searching forward from a known lower bound lo (off[lo] <= g)
+// by doubling steps first: cheap when g lies a few segments past lo.
+__device__ __forceinline__ uint64_t gallop_segment(const uint64_t* __restrict__ off, uint64_t lo, uint64_t n,
+                                                   uint64_t g) {
+  uint64_t step = 1, hi = lo + 1;
+  while (hi < n && off[hi] <= g) {
+    lo = hi;
+    step <<= 1;
+    hi = lo + step;
+  }
+  if (hi > n) hi = n;
+  return find_segment(off, lo, hi, g);
+}
+
 }  // namespace gj

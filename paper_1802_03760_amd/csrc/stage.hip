@@ -120,13 +120,6 @@ __device__ __forceinline__ bool intersect_all(const uint32_t* __restrict__ F, ui
   return keep;
 }
 
-// Prefix range covering candidates [gf, gl] (wave-uniform).
-__device__ __forceinline__ void wave_prefix_range(const uint64_t* __restrict__ off, uint64_t n, uint64_t gf,
-                                                  uint64_t gl, uint64_t& plo, uint64_t& phi) {
-  plo = find_segment(off, 0, n, gf);
-  phi = find_segment(off, plo, n, gl) + 1;
-}
-
 // MODE 0: write survivor ballots mask[word] and counts wcnt[word].
 // MODE 1: acc[0] += survivors.
 // MODE 2: acc[0] += survivors, acc[1] += sum of survivor weights (signed).
@@ -142,14 +135,19 @@ __global__ void __launch_bounds__(kBlock) k_propose(const uint32_t* __restrict__
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   uint64_t cnt = 0;
   int64_t wsum = 0;
-  for (uint64_t wd = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wd < nwords; wd += nwaves) {
+  // each wave walks a contiguous run of words, galloping forward over prefixes
+  const uint64_t per = (nwords + nwaves - 1) / nwaves;
+  const uint64_t wbeg = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * per;
+  const uint64_t wend = wbeg + per < nwords ? wbeg + per : nwords;
+  uint64_t plo = 0, phi;
+  for (uint64_t wd = wbeg; wd < wend; ++wd) {
     uint64_t gf = w0 + (wd << 6);
     uint64_t gl = gf + 63 < w1 ? gf + 63 : w1 - 1;
     uint64_t g = gf + lane;
     bool keep = false;
     int8_t w = 1;
-    uint64_t plo, phi;
-    wave_prefix_range(off, n, gf, gl, plo, phi);
+    plo = gallop_segment(off, plo, n, gf);
+    phi = gallop_segment(off, plo, n, gl) + 1;
     if (g < w1) {
       Cand c = resolve(F, stride, off, mini, d, plo, phi, g);
       keep = intersect_all(F, stride, d, c);
@@ -191,13 +189,17 @@ __global__ void __launch_bounds__(kBlock) k_emit(const uint32_t* __restrict__ F,
   const int lane = lane_id();
   const uint64_t nwords = (w1 - w0 + 63) >> 6;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t wd = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; wd < nwords; wd += nwaves) {
+  const uint64_t per = (nwords + nwaves - 1) / nwaves;
+  const uint64_t wbeg = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * per;
+  const uint64_t wend = wbeg + per < nwords ? wbeg + per : nwords;
+  uint64_t plo = 0, phi;
+  for (uint64_t wd = wbeg; wd < wend; ++wd) {
     uint64_t b = mask[wd];
     if (b == 0) continue;
     uint64_t gf = w0 + (wd << 6);
     uint64_t gl = gf + 63 < w1 ? gf + 63 : w1 - 1;
-    uint64_t plo, phi;
-    wave_prefix_range(off, n, gf, gl, plo, phi);
+    plo = gallop_segment(off, plo, n, gf);
+    phi = gallop_segment(off, plo, n, gl) + 1;
     if (!((b >> lane) & 1)) continue;
     Cand c = resolve(F, stride, off, mini, d, plo, phi, gf + lane);
     uint64_t pos = woff[wd] + __popcll(b & lanemask_lt());

@@ -45,6 +45,7 @@ def test_batch_equals_plain_and_oracle(gj):
     rng = np.random.default_rng(1)
     reqs, specs = mixed_requests(gj, ctx, E, rng, 45)
     counts, stats = gj.run_batch(ctx, G, reqs)
+    assert ctx.get_option("batch_fallbacks") == 0
     for (qh, lo, hi), (q, _, _), c, st in zip(reqs, specs, counts, stats):
         plain = gj.count(ctx, G, qh, lo, hi)
         ref = oracle.run(O, q, seed_lo=lo, seed_hi=hi)
@@ -78,7 +79,7 @@ def test_overflow_falls_back(gj):
     src, dst = synth.rmat_draws(10, seed=3)
     n = 1 << 10
     ctx = gj.Context(0)
-    ctx.set_option("frontier_cap", 64)
+    ctx.set_option("batch_cap", 64)
     G = gj.Graph(ctx, src, dst, n)
     E = G.info()["edges"]
     q = gj.Query(ctx, *Q.CLIQUE4)
@@ -87,6 +88,7 @@ def test_overflow_falls_back(gj):
     O = oracle.Graph(n, src, dst)
     assert counts == [oracle.run(O, Q.CLIQUE4)["matches"],
                       oracle.run(O, Q.CLIQUE4, seed_lo=5, seed_hi=400)["matches"]]
+    assert ctx.get_option("batch_fallbacks") == 1
 
 
 def test_batch_after_updates(gj):
