@@ -67,6 +67,10 @@ const char* gj_last_error(const gj_ctx* ctx);
  *   "batch_waves_per_cu"  gj_run_batch: resident waves per CU of its
  *                   persistent grids, a multiple of 4 in [4, 128] (default 32)
  *   "batch_cap"     gj_run_batch: prefixes per level (default 2^27)
+ *   "delta_fused"   gj_apply_updates: 1 (default) runs the delta queries of
+ *                   every query that asks for counts only as one fused
+ *                   pipeline (as gj_run_batch, with signed seeds); 0 runs
+ *                   each dQ_i on the depth-first path
  * Returns GJ_EINVAL for an unknown key or out-of-range value. */
 gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
 
@@ -207,6 +211,61 @@ typedef struct {
 gj_status gj_autotune(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_query* const* qs,
                       const uint64_t* seed_lo, const uint64_t* seed_hi, const char* cache_path,
                       gj_tuning* out);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A request server: a worker thread that owns ctx and g (make no other call
+ * on them while the server exists) and serves count requests and update
+ * batches.  Updates are applied in arrival order, one version each (count
+ * deltas through the fused delta queries).  A count request sees every
+ * update submitted before it and none submitted after (the logical
+ * sequencing of Sec. 4.3).  Count requests waiting at the head of the queue
+ * are admitted together -- at most max_batch, and while their estimated
+ * frontier memory (seed edges x average degree per later attribute x bytes
+ * per prefix) stays within mem_budget_bytes (0: no limit) -- and run as one
+ * fused pipeline (gj_run_batch); requests arriving meanwhile join the next
+ * batch as soon as the device is free.  Results equal gj_run / gj_apply_updates
+ * issued alone in submission order. */
+typedef struct gj_server gj_server;
+
+#define GJ_REQ_COUNT 0
+#define GJ_REQ_UPDATE 1
+#define GJ_SERVER_MAX_QUERIES 16
+
+typedef struct {
+  int kind;          /* GJ_REQ_COUNT or GJ_REQ_UPDATE */
+  gj_status status;  /* status of the underlying gj_run_batch / gj_apply_updates */
+  uint64_t count;    /* count request: matches */
+  uint32_t nq;       /* update: number of queries */
+  int64_t count_delta[GJ_SERVER_MAX_QUERIES]; /* update: change of each query's count */
+  uint64_t version;  /* graph version after the request */
+  uint32_t batch_size; /* requests served in the same launch */
+  int64_t submit_ns, start_ns, done_ns; /* steady-clock timestamps */
+} gj_server_result;
+
+typedef struct {
+  uint64_t completed_counts, completed_updates, count_batches;
+  double mean_count_batch;
+  double count_p50_ms, count_p99_ms;   /* submit -> done */
+  double update_p50_ms, update_p99_ms;
+} gj_server_stats;
+
+gj_status gj_server_create(gj_ctx* ctx, gj_graph* g, uint32_t max_batch, uint64_t mem_budget_bytes,
+                           gj_server** out);
+/* Queues a count of query q over seed edges [seed_lo, seed_hi) (as gj_run);
+ * *ticket identifies the result.  The query must outlive the request. */
+gj_status gj_server_submit_count(gj_server* s, const gj_query* q, uint64_t seed_lo, uint64_t seed_hi,
+                                 uint64_t* ticket);
+/* Queues an update batch (host arrays, copied) and the queries (at most
+ * GJ_SERVER_MAX_QUERIES) whose count deltas to report. */
+gj_status gj_server_submit_update(gj_server* s, const uint32_t* src, const uint32_t* dst, const int8_t* sign,
+                                  uint64_t b, const gj_query* const* qs, uint32_t nq, uint64_t* ticket);
+/* Waits for a result (timeout_ms < 0: no limit; GJ_EBUSY on timeout).  A
+ * result is returned once. */
+gj_status gj_server_wait(gj_server* s, uint64_t ticket, int64_t timeout_ms, gj_server_result* out);
+gj_status gj_server_get_stats(gj_server* s, gj_server_stats* out);
+/* Serves everything queued, then stops the worker. */
+void gj_server_destroy(gj_server* s);
 
 /* Copies the consolidated delta rows of query number q (its position in the
  * qs list) of the most recent gj_apply_updates on ctx that requested rows

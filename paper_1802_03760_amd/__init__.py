@@ -29,7 +29,10 @@ _lib = ctypes.CDLL(LIB_PATH)
 EXPORTS = ["gj_ctx_create", "gj_ctx_destroy", "gj_last_error", "gj_ctx_set_option", "gj_ctx_get_option",
            "gj_graph_build", "gj_graph_info", "gj_graph_csr", "gj_graph_destroy",
            "gj_query_register", "gj_query_destroy", "gj_run", "gj_apply_updates",
-           "gj_last_delta", "gj_run_batch", "gj_autotune"]
+           "gj_last_delta", "gj_run_batch", "gj_autotune", "gj_server_create", "gj_server_submit_count",
+           "gj_server_submit_update", "gj_server_wait", "gj_server_get_stats", "gj_server_destroy"]
+REQ_COUNT, REQ_UPDATE = 0, 1
+SERVER_MAX_QUERIES = 16
 
 
 class Atom(ctypes.Structure):
@@ -40,6 +43,20 @@ class Tuning(ctypes.Structure):
     _fields_ = [("batch_lin", ctypes.c_uint32), ("batch_waves_per_cu", ctypes.c_uint32),
                 ("best_ms", ctypes.c_double), ("configs_tried", ctypes.c_int),
                 ("from_cache", ctypes.c_int)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("status", ctypes.c_int), ("count", ctypes.c_uint64),
+                ("nq", ctypes.c_uint32), ("count_delta", ctypes.c_int64 * 16),
+                ("version", ctypes.c_uint64), ("batch_size", ctypes.c_uint32),
+                ("submit_ns", ctypes.c_int64), ("start_ns", ctypes.c_int64), ("done_ns", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("completed_counts", ctypes.c_uint64), ("completed_updates", ctypes.c_uint64),
+                ("count_batches", ctypes.c_uint64), ("mean_count_batch", ctypes.c_double),
+                ("count_p50_ms", ctypes.c_double), ("count_p99_ms", ctypes.c_double),
+                ("update_p50_ms", ctypes.c_double), ("update_p99_ms", ctypes.c_double)]
 
 
 class Stats(ctypes.Structure):
@@ -97,6 +114,19 @@ _lib.gj_apply_updates.argtypes = [_vp, _vp, _vp, _vp, _vp, _u64, _i32, ctypes.PO
 _lib.gj_apply_updates.restype = _i32
 _lib.gj_last_delta.argtypes = [_vp, _u32, _vp, _vp, _u64, _i32, ctypes.POINTER(_u64)]
 _lib.gj_last_delta.restype = _i32
+_lib.gj_server_create.argtypes = [_vp, _vp, _u32, _u64, ctypes.POINTER(_vp)]
+_lib.gj_server_create.restype = _i32
+_lib.gj_server_submit_count.argtypes = [_vp, _vp, _u64, _u64, ctypes.POINTER(_u64)]
+_lib.gj_server_submit_count.restype = _i32
+_lib.gj_server_submit_update.argtypes = [_vp, _vp, _vp, _vp, _u64, ctypes.POINTER(_vp), _u32,
+                                         ctypes.POINTER(_u64)]
+_lib.gj_server_submit_update.restype = _i32
+_lib.gj_server_wait.argtypes = [_vp, _u64, ctypes.c_int64, ctypes.POINTER(ServerResult)]
+_lib.gj_server_wait.restype = _i32
+_lib.gj_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
+_lib.gj_server_get_stats.restype = _i32
+_lib.gj_server_destroy.argtypes = [_vp]
+_lib.gj_server_destroy.restype = None
 _lib.gj_run_batch.argtypes = [_vp, _vp, _u32, ctypes.POINTER(_vp), _vp, _vp, _vp, ctypes.POINTER(Stats)]
 _lib.gj_run_batch.restype = _i32
 _lib.gj_autotune.argtypes = [_vp, _vp, _u32, ctypes.POINTER(_vp), _vp, _vp, ctypes.c_char_p,
@@ -113,7 +143,7 @@ _finalised = False
 
 def _release_all():
     global _finalised
-    for kind in (Query, Graph, Context):
+    for kind in (Server, Query, Graph, Context):
         for obj in list(_live):
             if isinstance(obj, kind):
                 obj.close()
@@ -178,7 +208,7 @@ class Context:
     def close(self):
         """Destroys the context and every graph and query created on it."""
         if getattr(self, "_h", None):
-            for kind in (Query, Graph):
+            for kind in (Server, Query, Graph):
                 for obj in list(self._children):
                     if isinstance(obj, kind):
                         obj.close()
@@ -264,6 +294,68 @@ def count(ctx, graph, query, seed_lo=0, seed_hi=(1 << 64) - 1):
     ctx.check(_lib.gj_run(ctx._h, graph._h, query._h, MODE_COUNT, seed_lo, seed_hi, None, 0, 0,
                           ctypes.byref(st)), "gj_run(count)")
     return st.as_dict()
+
+
+class Server:
+    """Request server over a context and a graph (gj_server_*): the worker
+    thread owns both until close()."""
+
+    def __init__(self, ctx, graph, max_batch=64, mem_budget_bytes=0):
+        self.ctx, self.graph = ctx, graph
+        h = _vp()
+        st = _lib.gj_server_create(ctx._h, graph._h, max_batch, mem_budget_bytes, ctypes.byref(h))
+        if st != GJ_OK:
+            raise GJError(st, "gj_server_create")
+        self._h = h
+        self._keep = {}  # queries referenced by queued requests
+        ctx._children.add(self)
+        _live.add(self)
+
+    def submit_count(self, query, seed_lo=0, seed_hi=(1 << 64) - 1):
+        t = _u64()
+        st = _lib.gj_server_submit_count(self._h, query._h, seed_lo, seed_hi, ctypes.byref(t))
+        if st != GJ_OK:
+            raise GJError(st, "gj_server_submit_count")
+        self._keep[t.value] = query
+        return t.value
+
+    def submit_update(self, src, dst, sign, queries):
+        src = np.ascontiguousarray(src, dtype=np.uint32)
+        dst = np.ascontiguousarray(dst, dtype=np.uint32)
+        sign = np.ascontiguousarray(sign, dtype=np.int8)
+        qh = (_vp * max(len(queries), 1))(*[q._h.value for q in queries])
+        t = _u64()
+        st = _lib.gj_server_submit_update(self._h, _np_ptr(src), _np_ptr(dst), _np_ptr(sign), len(src), qh,
+                                          len(queries), ctypes.byref(t))
+        if st != GJ_OK:
+            raise GJError(st, "gj_server_submit_update")
+        self._keep[t.value] = list(queries)
+        return t.value
+
+    def wait(self, ticket, timeout_ms=-1):
+        r = ServerResult()
+        st = _lib.gj_server_wait(self._h, ticket, timeout_ms, ctypes.byref(r))
+        if st != GJ_OK:
+            raise GJError(st, "gj_server_wait")
+        self._keep.pop(ticket, None)
+        return {"kind": r.kind, "status": r.status, "count": int(r.count),
+                "count_delta": [int(r.count_delta[i]) for i in range(r.nq)], "version": int(r.version),
+                "batch_size": int(r.batch_size), "latency_ms": (r.done_ns - r.submit_ns) * 1e-6,
+                "queue_ms": (r.start_ns - r.submit_ns) * 1e-6, "service_ms": (r.done_ns - r.start_ns) * 1e-6}
+
+    def stats(self):
+        s = ServerStats()
+        _lib.gj_server_get_stats(self._h, ctypes.byref(s))
+        return {f: getattr(s, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.gj_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        if not _finalised:
+            self.close()
 
 
 def _requests(requests):

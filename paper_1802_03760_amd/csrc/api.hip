@@ -168,6 +168,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "strategy") {
       GJ_CHECK(value >= 0 && value <= 2, GJ_EINVAL, "strategy out of range");
       c->strategy = (int)value;
+    } else if (k == "delta_fused") {
+      GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "delta_fused must be 0 or 1");
+      c->delta_fused = (int)value;
     } else if (k == "batch_cap") {
       GJ_CHECK(value >= 64 && value <= (1ll << 32), GJ_EINVAL, "batch_cap out of range");
       c->batch_cap = (uint64_t)value;
@@ -194,6 +197,7 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "batch_lin") *value = c->batch_lin;
     else if (k == "batch_waves_per_cu") *value = c->batch_waves_per_cu;
     else if (k == "batch_fallbacks") *value = (int64_t)c->batch_fallbacks;
+    else if (k == "delta_fused") *value = c->delta_fused;
     else throw Error{GJ_EINVAL, "unknown option " + k};
   });
 }

@@ -33,6 +33,7 @@ struct BReq {
   uint64_t seed_lo;
   const uint32_t* seed_row;
   const uint32_t* seed_col;
+  const int8_t* seed_w;  // signed seeds of a delta query, or null (+1)
   SeedFilter filt;
   StageDesc st[GJ_MAX_ATTRS];
 };
@@ -116,13 +117,14 @@ __global__ void k_bt_head_reset(BHead* h) {
 // P_2 of every request: seed g of the concatenated seed space -> request r
 __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, const uint64_t* __restrict__ roff,
                                                     BHead* __restrict__ H, uint32_t* __restrict__ F,
-                                                    uint32_t* __restrict__ rid, uint64_t cap,
+                                                    uint32_t* __restrict__ rid, int8_t* __restrict__ Fw, uint64_t cap,
                                                     unsigned long long* __restrict__ cnt,
-                                                    unsigned long long* __restrict__ pre) {
+                                                    unsigned long long* __restrict__ pre,
+                                                    unsigned long long* __restrict__ wsum) {
   const uint32_t nreq = H->nreq;
   const uint64_t total = H->seeds;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  WaveAcc a_pre, a_cnt;
+  WaveAcc a_pre, a_cnt, a_ws;
   for (uint64_t base = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; base < total;
        base += nwaves * 64) {
     uint64_t g = base + lane_id();
@@ -130,12 +132,14 @@ __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, 
     uint32_t r = 0;
     bool keep = false, fin = false;
     uint32_t x0 = 0, x1 = 0;
+    int8_t w = 1;
     if (valid) {
       r = (uint32_t)find_segment(roff, 0, nreq, g);
       const BReq& q = R[r];
       uint64_t e = q.seed_lo + (g - roff[r]);
       x0 = q.seed_row[e];
       x1 = q.seed_col[e];
+      if (q.seed_w) w = q.seed_w[e];
       keep = true;
       uint32_t x[2] = {x0, x1};
       for (int a = 0; a < q.filt.n && keep; ++a) {
@@ -146,6 +150,7 @@ __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, 
     }
     a_pre.add(pre, r * kStat + 2, 1, valid && keep, true);
     a_cnt.add(cnt, r, 1, valid && keep && fin, true);
+    a_ws.add(wsum, r, (uint64_t)(int64_t)w, valid && keep && fin, false);
     bool store = valid && keep && !fin;
     uint64_t pos = wave_reserve(&H->nlev[2], store);
     if (store) {
@@ -153,6 +158,7 @@ __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, 
         F[pos] = x0;
         F[cap + pos] = x1;
         rid[pos] = r;
+        Fw[pos] = w;
       } else {
         atomicOr(&H->overflow, 1u);
       }
@@ -160,6 +166,7 @@ __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, 
   }
   a_pre.flush(pre);
   a_cnt.flush(cnt);
+  a_ws.flush(wsum);
 }
 
 // The lanes of a wave are served one request at a time: the first pending
@@ -217,10 +224,12 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
                                                        const uint32_t* __restrict__ F,
                                                        const uint32_t* __restrict__ rid, uint64_t cap,
                                                        const uint64_t* __restrict__ off,
-                                                       const uint8_t* __restrict__ mini, uint32_t* __restrict__ G,
-                                                       uint32_t* __restrict__ grid_, uint64_t gcap,
+                                                       const uint8_t* __restrict__ mini, const int8_t* __restrict__ Fw,
+                                                       uint32_t* __restrict__ G, uint32_t* __restrict__ grid_,
+                                                       int8_t* __restrict__ Gw, uint64_t gcap,
                                                        unsigned long long* __restrict__ cnt,
-                                                       unsigned long long* __restrict__ pre) {
+                                                       unsigned long long* __restrict__ pre,
+                                                       unsigned long long* __restrict__ wsum) {
   const uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
   const uint64_t W = off[n];
   const uint32_t lin = H->lin;
@@ -228,7 +237,7 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   const uint64_t nwords = (W + 63) >> 6;
   (void)nwaves;
-  WaveAcc a_pre, a_cnt;
+  WaveAcc a_pre, a_cnt, a_ws;
   // waves claim chunks of kChunkWords words from a device counter and walk
   // each chunk galloping forward over the prefixes
   for (;;) {
@@ -284,8 +293,10 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
         todo = false;
       }
     }
+    int8_t w = valid ? Fw[p] : (int8_t)0;
     a_pre.add(pre, r * kStat + j + 1, 1, valid && keep, true);
     a_cnt.add(cnt, r, 1, valid && keep && fin, true);
+    a_ws.add(wsum, r, (uint64_t)(int64_t)w, valid && keep && fin, false);
     bool store = valid && keep && !fin;
     uint64_t pos = wave_reserve(&H->nlev[j + 1], store);
     if (store) {
@@ -293,6 +304,7 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
         for (int c = 0; c < j; ++c) G[(uint64_t)c * gcap + pos] = F[(uint64_t)c * cap + p];
         G[(uint64_t)j * gcap + pos] = e;
         grid_[pos] = r;
+        Gw[pos] = w;
       } else {
         atomicOr(&H->overflow, 1u);
       }
@@ -301,6 +313,7 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
   }
   a_pre.flush(pre);
   a_cnt.flush(cnt);
+  a_ws.flush(wsum);
 }
 
 // ---------------------------------------------------------------- device-size scan
@@ -382,11 +395,10 @@ struct BatchExec::Impl {
   BReq* d_req = nullptr;
   uint64_t* d_roff = nullptr;
   BHead* d_head = nullptr;
-  unsigned long long* d_cnt = nullptr;  // [max_req]
-  unsigned long long* d_pre = nullptr;  // [max_req * kStat]
-  unsigned long long* d_ext = nullptr;  // [max_req * kStat]
+  unsigned long long* d_stat = nullptr;  // cnt[mr], wsum[mr], pre[mr * kStat], ext[mr * kStat]
   uint32_t* F[GJ_MAX_ATTRS + 1] = {};
   uint32_t* rid[GJ_MAX_ATTRS + 1] = {};
+  int8_t* W[GJ_MAX_ATTRS + 1] = {};
   uint32_t* minc[GJ_MAX_ATTRS + 1] = {};
   uint8_t* mini[GJ_MAX_ATTRS + 1] = {};
   uint64_t* off[GJ_MAX_ATTRS + 1] = {};
@@ -400,6 +412,11 @@ struct BatchExec::Impl {
   unsigned grid_cfg = 0;
   std::vector<void*> allocs;
 
+  uint64_t stat_words() const { return (uint64_t)max_req * (2 + 2 * kStat); }
+  unsigned long long* cnt() { return d_stat; }
+  unsigned long long* wsum() { return d_stat + max_req; }
+  unsigned long long* pre() { return d_stat + 2ull * max_req; }
+  unsigned long long* ext() { return d_stat + 2ull * max_req + (uint64_t)max_req * kStat; }
   void* alloc(size_t b) {
     void* p = dev_alloc(b);
     allocs.push_back(p);
@@ -418,49 +435,41 @@ BatchExec::~BatchExec() { delete p; }
 
 static void enqueue(gj_ctx* c, BatchExec::Impl& s, unsigned grid) {
   hipStream_t st = c->stream;
-  uint64_t stat_words = (uint64_t)s.max_req * (1 + 2 * kStat);
   k_bt_head_reset<<<1, 64, 0, st>>>(s.d_head);
-  k_bt_clear<<<grid_for(stat_words, kBlock, 1024), kBlock, 0, st>>>(s.d_cnt, stat_words);
-  k_bt_seed<<<grid, kBlock, 0, st>>>(s.d_req, s.d_roff, s.d_head, s.F[2], s.rid[2], s.cap, s.d_cnt, s.d_pre);
+  k_bt_clear<<<grid_for(s.stat_words(), kBlock, 1024), kBlock, 0, st>>>(s.d_stat, s.stat_words());
+  k_bt_seed<<<grid, kBlock, 0, st>>>(s.d_req, s.d_roff, s.d_head, s.F[2], s.rid[2], s.W[2], s.cap, s.cnt(),
+                                     s.pre(), s.wsum());
   for (int j = 2; j < s.max_m; ++j) {
     // latency-bound, no dynamic claiming: oversubscribe (idle blocks exit at once)
     k_bt_count_min<<<grid_for(s.cap, kBlock * 4, 8192), kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j],
-                                                                         s.cap, s.minc[j], s.mini[j], s.d_ext);
+                                                                         s.cap, s.minc[j], s.mini[j], s.ext());
     k_bt_scan_reduce<<<(unsigned)s.nparts, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part);
     k_bt_scan_parts<<<1, kBlock, 0, st>>>(s.part, s.nparts, s.part_off);
     k_bt_scan_down<<<(unsigned)s.nparts, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part_off, s.nparts,
                                                          s.off[j]);
-    uint32_t* G = j + 1 < s.max_m ? s.F[j + 1] : nullptr;
-    uint32_t* Gr = j + 1 < s.max_m ? s.rid[j + 1] : nullptr;
-    k_bt_propose<<<grid, kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j], s.cap, s.off[j], s.mini[j], G, Gr,
-                                         G ? s.cap : 0, s.d_cnt, s.d_pre);
+    bool last = j + 1 >= s.max_m;
+    k_bt_propose<<<grid, kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j], s.cap, s.off[j], s.mini[j], s.W[j],
+                                         last ? nullptr : s.F[j + 1], last ? nullptr : s.rid[j + 1],
+                                         last ? nullptr : s.W[j + 1], last ? 0 : s.cap, s.cnt(), s.pre(),
+                                         s.wsum());
   }
 }
 
-static void fill_req(BReq& b, const PlanH& P, const Views& V, uint64_t lo) {
-  memset(&b, 0, sizeof(b));
-  b.m = (uint32_t)P.m;
-  const Version& sv = V.of(P.seed_atom);
-  int dir = P.seed_fwd ? 0 : 1;
-  b.seed_lo = lo;
-  b.seed_row = sv.d[dir].row;
-  b.seed_col = sv.d[dir].col;
-  b.filt = seed_filter(P, V);
-  for (int j = 2; j < P.m; ++j) b.st[j] = stage_desc(P, V, j);
-}
-
-void BatchExec::run(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* lo,
-                    const uint64_t* hi, uint64_t* counts, gj_stats* stats, bool& overflow) {
-  Impl& s = *p;
+void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t* counts, int64_t* wsums,
+                          gj_stats* stats, bool& overflow) {
   overflow = false;
+  uint32_t nreq = (uint32_t)specs.size();
+  if (!nreq) return;
   int max_m = 2;
-  for (uint32_t i = 0; i < nreq; ++i) max_m = std::max(max_m, qs[i]->m);
+  for (auto& r : specs) max_m = std::max(max_m, r.P.m);
   uint64_t cap = c->batch_cap;
   unsigned grid = (unsigned)c->num_cus * (c->batch_waves_per_cu / 4 > 0 ? c->batch_waves_per_cu / 4 : 1);
+  Impl& s = *p;
   bool rebuild = nreq > s.max_req || max_m > s.max_m || cap != s.cap || grid != s.grid_cfg || !s.exec;
   if (rebuild) {
     uint32_t mr = std::max<uint32_t>(nreq, std::max<uint32_t>(s.max_req, 64));
     int mm = std::max(max_m, std::max(s.max_m, 3));
+    GJ_HIP(hipStreamSynchronize(c->stream));
     delete p;
     p = new Impl;
     Impl& t = *p;
@@ -471,12 +480,11 @@ void BatchExec::run(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query*
     t.d_req = (BReq*)t.alloc(sizeof(BReq) * mr);
     t.d_roff = (uint64_t*)t.alloc(sizeof(uint64_t) * (mr + 1));
     t.d_head = (BHead*)t.alloc(sizeof(BHead));
-    t.d_cnt = (unsigned long long*)t.alloc(sizeof(unsigned long long) * mr * (1 + 2 * kStat));
-    t.d_pre = t.d_cnt + mr;
-    t.d_ext = t.d_pre + (uint64_t)mr * kStat;
+    t.d_stat = (unsigned long long*)t.alloc(sizeof(unsigned long long) * t.stat_words());
     for (int j = 2; j < mm; ++j) {
       t.F[j] = (uint32_t*)t.alloc(cap * j * sizeof(uint32_t));
       t.rid[j] = (uint32_t*)t.alloc(cap * sizeof(uint32_t));
+      t.W[j] = (int8_t*)t.alloc(cap);
       t.minc[j] = (uint32_t*)t.alloc(cap * sizeof(uint32_t));
       t.mini[j] = (uint8_t*)t.alloc(cap);
       t.off[j] = (uint64_t*)t.alloc((cap + 1) * sizeof(uint64_t));
@@ -485,10 +493,9 @@ void BatchExec::run(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query*
     t.part = (uint64_t*)t.alloc(t.nparts * sizeof(uint64_t));
     t.part_off = (uint64_t*)t.alloc((t.nparts + 1) * sizeof(uint64_t));
     t.h_stage_bytes = sizeof(BHead) + sizeof(BReq) * mr + sizeof(uint64_t) * (mr + 1) +
-                      sizeof(unsigned long long) * mr * (1 + 2 * kStat);
+                      sizeof(unsigned long long) * t.stat_words();
     GJ_HIP(hipHostMalloc(&t.h_stage, t.h_stage_bytes, hipHostMallocDefault));
     // capture the level pipeline once; it reads every size from device memory
-    GJ_HIP(hipStreamSynchronize(c->stream));
     GJ_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
     enqueue(c, t, grid);
     hipError_t ce = hipStreamEndCapture(c->stream, &t.graph);
@@ -496,9 +503,6 @@ void BatchExec::run(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query*
     GJ_HIP(hipGraphInstantiate(&t.exec, t.graph, nullptr, nullptr, 0));
   }
   Impl& t = *p;
-  // request table
-  const Version& v = g->ver[g->cur];
-  Views V{&v, &v, -1};
   char* hs = (char*)t.h_stage;
   BHead* hh = (BHead*)hs;
   BReq* hr = (BReq*)(hs + sizeof(BHead));
@@ -506,12 +510,18 @@ void BatchExec::run(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query*
   memset(hh, 0, sizeof(BHead));
   uint64_t tot = 0;
   for (uint32_t i = 0; i < nreq; ++i) {
-    PlanH P = make_plan(qs[i], qs[i]->order, -1);
-    uint64_t E = v.m;
-    uint64_t h = std::min<uint64_t>(hi[i], E), l = std::min<uint64_t>(lo[i], h);
-    fill_req(hr[i], P, V, l);
+    const ReqSpec& r = specs[i];
+    BReq& b = hr[i];
+    memset(&b, 0, sizeof(b));
+    b.m = (uint32_t)r.P.m;
+    b.seed_lo = r.lo;
+    b.seed_row = r.row;
+    b.seed_col = r.col;
+    b.seed_w = r.w;
+    b.filt = seed_filter(r.P, r.V);
+    for (int j = 2; j < r.P.m; ++j) b.st[j] = stage_desc(r.P, r.V, j);
     ho[i] = tot;
-    tot += h - l;
+    tot += r.len;
   }
   ho[nreq] = tot;
   hh->nreq = nreq;
@@ -525,26 +535,48 @@ void BatchExec::run(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query*
   GJ_HIP(hipGraphLaunch(t.exec, c->stream));
   timer.stop();
   unsigned long long* res = (unsigned long long*)(ho + t.max_req + 1);
-  uint64_t words = (uint64_t)t.max_req * (1 + 2 * kStat);
-  GJ_HIP(hipMemcpyAsync(res, t.d_cnt, words * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+  GJ_HIP(hipMemcpyAsync(res, t.d_stat, t.stat_words() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                        c->stream));
   GJ_HIP(hipMemcpyAsync(hh, t.d_head, sizeof(BHead), hipMemcpyDeviceToHost, c->stream));
   double kms = timer.total_ms();  // synchronises
   overflow = hh->overflow != 0;
   if (overflow) return;
+  const uint64_t mr = t.max_req;
   for (uint32_t i = 0; i < nreq; ++i) {
-    counts[i] = res[i];
+    if (counts) counts[i] = res[i];
+    if (wsums) wsums[i] = (int64_t)res[mr + i];
     if (stats) {
       gj_stats st{};
       st.matches = res[i];
       for (int j = 0; j < kStat; ++j) {
-        st.prefixes[j] = res[t.max_req + (uint64_t)i * kStat + j];
-        st.extensions[j] = res[t.max_req + (uint64_t)t.max_req * kStat + (uint64_t)i * kStat + j];
+        st.prefixes[j] = res[2 * mr + (uint64_t)i * kStat + j];
+        st.extensions[j] = res[2 * mr + mr * kStat + (uint64_t)i * kStat + j];
       }
       st.kernel_ms = kms;
       st.kernel_launches = 1;
       stats[i] = st;
     }
   }
+}
+
+void BatchExec::run(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* lo,
+                    const uint64_t* hi, uint64_t* counts, gj_stats* stats, bool& overflow) {
+  const Version& v = g->ver[g->cur];
+  Views V{&v, &v, -1};
+  std::vector<ReqSpec> specs;
+  specs.reserve(nreq);
+  for (uint32_t i = 0; i < nreq; ++i) {
+    ReqSpec r{make_plan(qs[i], qs[i]->order, -1), V};
+    int dir = r.P.seed_fwd ? 0 : 1;
+    uint64_t h = std::min<uint64_t>(hi[i], v.m), l = std::min<uint64_t>(lo[i], h);
+    r.row = v.d[dir].row;
+    r.col = v.d[dir].col;
+    r.w = nullptr;
+    r.lo = l;
+    r.len = h - l;
+    specs.push_back(std::move(r));
+  }
+  run_specs(c, specs, counts, nullptr, stats, overflow);
 }
 
 void batch_destroy(gj_ctx* c) {

@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "batch.h"
 #include "engine.h"
 #include "gj_internal.h"
 #include "prim.h"
@@ -296,7 +297,66 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   (void)ins_total;
   version_finish(c, nv, n);
   // ---- delta queries
+  // Queries that only need count deltas: every dQ_i of all of them runs as
+  // one fused, graph-captured pipeline with signed seeds.
+  std::vector<char> done(nq, 0);
+  if (c->delta_fused) {
+    std::vector<gj::ReqSpec> specs;
+    std::vector<uint32_t> owner;
+    for (uint32_t qi = 0; qi < nq; ++qi) {
+      bool want_rows = (out_rows && out_rows[qi]) || (out_signs && out_signs[qi]);
+      if (want_rows) continue;
+      const gj_query* q = qs[qi];
+      for (int i = 0; i < (int)q->atoms.size(); ++i) {
+        ReqSpec r{make_plan(q, delta_order(q, i), i), Views{&ov, &nv, i}};
+        r.row = es;
+        r.col = ed;
+        r.w = eg;
+        r.lo = 0;
+        r.len = k;
+        specs.push_back(std::move(r));
+        owner.push_back(qi);
+      }
+    }
+    if (!specs.empty()) {
+      std::vector<uint64_t> cnts(specs.size());
+      std::vector<int64_t> ws(specs.size());
+      std::vector<gj_stats> sts(specs.size());
+      bool ov_b = false;
+      if (!c->batch) c->batch = new BatchExec();
+      c->batch->run_specs(c, specs, cnts.data(), ws.data(), sts.data(), ov_b);
+      if (!ov_b) {
+        std::vector<gj_stats> acc(nq);
+        std::vector<int64_t> cd(nq, 0);
+        std::vector<uint64_t> raw(nq, 0);
+        for (size_t x = 0; x < specs.size(); ++x) {
+          uint32_t qi = owner[x];
+          add_stats(acc[qi], sts[x]);
+          acc[qi].kernel_ms = sts[x].kernel_ms;  // one launch for all
+          acc[qi].kernel_launches = 1;
+          cd[qi] += ws[x];
+          raw[qi] += cnts[x];
+          done[qi] = 1;
+        }
+        for (uint32_t qi = 0; qi < nq; ++qi) {
+          if (!done[qi]) continue;
+          if (count_delta) count_delta[qi] = cd[qi];
+          if (n_delta) n_delta[qi] = 0;
+          if (stats) {
+            acc[qi].noop_inserts = hc[0];
+            acc[qi].noop_deletes = hc[1];
+            acc[qi].raw_emissions = raw[qi];
+            acc[qi].matches = raw[qi];
+            stats[qi] = acc[qi];
+          }
+        }
+      } else {
+        ++c->batch_fallbacks;
+      }
+    }
+  }
   for (uint32_t qi = 0; qi < nq; ++qi) {
+    if (done[qi]) continue;
     const gj_query* q = qs[qi];
     bool want_rows = (out_rows && out_rows[qi]) || (out_signs && out_signs[qi]);
     gj_stats acc{};

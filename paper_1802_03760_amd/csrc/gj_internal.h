@@ -112,6 +112,7 @@ struct gj_ctx {
   uint32_t batch_waves_per_cu = 32; // resident waves per CU of the persistent grids
   uint64_t batch_cap = 1ull << 27;  // prefixes per level of the batched pipeline
   uint64_t batch_fallbacks = 0;     // batches rerun depth-first after a level overflow
+  int delta_fused = 1;              // count-only delta queries through the fused pipeline
 };
 
 struct gj_graph {

@@ -173,3 +173,29 @@ def test_conflict_and_bad_input(gj, ctx):
                          np.array([1, 1], np.int8), [q])[0]
     assert r["count_delta"] == 0 and r["stats"]["noop_inserts"] == 1
     assert G.info()["version"] == 0
+
+
+def test_fused_delta_equals_depth_first(gj):
+    """Count-only deltas through the fused pipeline (one launch for every dQ_i
+    of every query) equal the depth-first path and the oracle."""
+    scale = 11
+    src, dst = synth.rmat_draws(scale, seed=12)
+    n = 1 << scale
+    cf = gj.Context(0)
+    cp = gj.Context(0)
+    cp.set_option("delta_fused", 0)
+    Gf, Gp = gj.Graph(cf, src, dst, n), gj.Graph(cp, src, dst, n)
+    names = ["triangle", "cyclic_triangle", "clique4", "diamond", "cycle4", "reciprocal"]
+    qf = [gj.Query(cf, *Q.ALL[k]) for k in names]
+    qp = [gj.Query(cp, *Q.ALL[k]) for k in names]
+    O = oracle.Graph(n, src, dst)
+    for k, bs, bd, bg in synth.update_stream(scale, 12, 13, 5, 1, 3000):
+        rf = gj.apply_updates(cf, Gf, bs, bd, bg, qf)
+        rp = gj.apply_updates(cp, Gp, bs, bd, bg, qp)
+        for name, a, b in zip(names, rf, rp):
+            ref = oracle.delta(O.copy(), bs, bd, bg, Q.ALL[name])
+            assert a["count_delta"] == b["count_delta"] == ref["count_delta"], name
+            for key in ("raw_emissions", "prefixes", "extensions", "noop_inserts", "noop_deletes"):
+                assert a["stats"][key] == b["stats"][key] == (ref[key] if key in ref else b["stats"][key]), key
+        oracle.delta(O, bs, bd, bg)
+    assert cf.get_option("batch_fallbacks") == 0

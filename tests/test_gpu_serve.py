@@ -1,0 +1,116 @@
+"""Served form: requests submitted to the server (continuously batched, in
+one mix with update batches, from several threads) return exactly what the
+same requests return issued alone, in submission order, on a separate
+replica of the graph."""
+import threading
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import queries as Q
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gj():
+    import paper_1802_03760_amd as gj
+    return gj
+
+
+def make_requests(rng, E, n_counts, names):
+    out = []
+    for i in range(n_counts):
+        lo = int(rng.integers(0, E))
+        out.append((names[i % len(names)], lo, lo + int(rng.integers(0, 400))))
+    return out
+
+
+def replay_and_check(gj, src, dst, n, submitted, results):
+    """submitted: [(ticket, ("count", name, lo, hi) | ("update", bs, bd, bg, names))] in ticket order."""
+    ref_ctx = gj.Context(0)
+    ref_ctx.set_option("delta_fused", 0)
+    G = gj.Graph(ref_ctx, src, dst, n)
+    qs = {k: gj.Query(ref_ctx, *Q.ALL[k]) for k in Q.ALL}
+    version = 0
+    O = oracle.Graph(n, src, dst)
+    for ticket, req in sorted(submitted, key=lambda x: x[0]):
+        r = results[ticket]
+        assert r["status"] == 0
+        if req[0] == "count":
+            _, name, lo, hi = req
+            alone = gj.count(ref_ctx, G, qs[name], lo, hi)["matches"]
+            assert r["count"] == alone, (ticket, name, lo, hi)
+            assert r["count"] == oracle.run(O, Q.ALL[name], seed_lo=lo, seed_hi=hi)["matches"]
+            assert r["version"] == version
+        else:
+            _, bs, bd, bg, names = req
+            alone = gj.apply_updates(ref_ctx, G, bs, bd, bg, [qs[k] for k in names])
+            version = G.info()["version"]
+            assert r["count_delta"] == [a["count_delta"] for a in alone]
+            assert r["version"] == version
+            oracle.delta(O, bs, bd, bg)
+
+
+def test_served_mix_equals_alone(gj):
+    scale = 11
+    src, dst = synth.rmat_draws(scale, seed=31)
+    n = 1 << scale
+    ctx = gj.Context(0)
+    G = gj.Graph(ctx, src, dst, n)
+    qs = {k: gj.Query(ctx, *Q.ALL[k]) for k in Q.ALL}
+    E = G.info()["edges"]
+    rng = np.random.default_rng(5)
+    srv = gj.Server(ctx, G, max_batch=32)
+    submitted = []
+    stream = list(synth.update_stream(scale, 31, 32, 6, 1, 500))
+    names = ["triangle", "clique4", "diamond", "cycle4", "cyclic_triangle", "reciprocal"]
+    for k in range(6):
+        for name, lo, hi in make_requests(rng, E, 25, names):
+            submitted.append((srv.submit_count(qs[name], lo, hi), ("count", name, lo, hi)))
+        _, bs, bd, bg = stream[k]
+        upd_names = ["triangle", "clique4", "diamond"]
+        submitted.append((srv.submit_update(bs, bd, bg, [qs[x] for x in upd_names]),
+                          ("update", bs, bd, bg, upd_names)))
+    results = {t: srv.wait(t) for t, _ in submitted}
+    st = srv.stats()
+    srv.close()
+    assert st["completed_counts"] == 150 and st["completed_updates"] == 6
+    assert max(r["batch_size"] for r in results.values()) > 1  # requests were batched
+    replay_and_check(gj, src, dst, n, submitted, results)
+
+
+def test_served_from_threads(gj):
+    scale = 10
+    src, dst = synth.rmat_draws(scale, seed=41)
+    n = 1 << scale
+    ctx = gj.Context(0)
+    G = gj.Graph(ctx, src, dst, n)
+    qs = {k: gj.Query(ctx, *Q.ALL[k]) for k in Q.ALL}
+    E = G.info()["edges"]
+    srv = gj.Server(ctx, G, max_batch=16, mem_budget_bytes=1 << 24)
+    submitted, lock = [], threading.Lock()
+    stream = list(synth.update_stream(scale, 41, 42, 4, 1, 300))
+
+    def client(cid):
+        rng = np.random.default_rng(100 + cid)
+        for name, lo, hi in make_requests(rng, E, 30, ["triangle", "clique4", "cycle4"]):
+            t = srv.submit_count(qs[name], lo, hi)
+            with lock:
+                submitted.append((t, ("count", name, lo, hi)))
+            if cid == 0 and rng.random() < 0.15 and stream:
+                _, bs, bd, bg = stream.pop()
+                with lock:
+                    t = srv.submit_update(bs, bd, bg, [qs["triangle"]])
+                    submitted.append((t, ("update", bs, bd, bg, ["triangle"])))
+
+    threads = [threading.Thread(target=client, args=(i,)) for i in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    results = {t: srv.wait(t, 60000) for t, _ in submitted}
+    srv.close()
+    replay_and_check(gj, src, dst, n, submitted, results)
