@@ -109,6 +109,138 @@ def batched_vs_plain(gj, ctx, G, nreq, seed, log, max_width=1000):
             "speedup": tp / tb, "tuning": tune, "fallbacks": fallbacks}
 
 
+def update_latency(gj, src, dst, n, scale, nbatch, log):
+    """Update stream (sizes log-uniform in [1, 100,000], 10% deletions, seed 1)
+    maintaining the triangle count: one gj_apply_updates at a time with each
+    dQ_i on the depth-first path (plain) against the server (fused delta
+    queries), both closed-loop so that latency is service time."""
+    import numpy as np
+    tri = (3, [(0, 1), (1, 2), (0, 2)])
+    out = {}
+    for mode in ("plain", "served"):
+        ctx = gj.Context(0)
+        ctx.set_option("delta_fused", 0 if mode == "plain" else 1)
+        G = gj.Graph(ctx, src, dst, n)
+        q = gj.Query(ctx, *tri)
+        lat, deltas = [], []
+        srv = gj.Server(ctx, G) if mode == "served" else None
+        for k, bs, bd, bg in synth_stream(scale, nbatch, 1, 100000):
+            if srv is None:
+                t0 = time.perf_counter()
+                r = gj.apply_updates(ctx, G, bs, bd, bg, [q])[0]
+                lat.append((time.perf_counter() - t0) * 1e3)
+                deltas.append(r["count_delta"])
+            else:
+                r = srv.wait(srv.submit_update(bs, bd, bg, [q]))
+                lat.append(r["latency_ms"])
+                deltas.append(r["count_delta"][0])
+        if srv is not None:
+            srv.close()
+        out[mode] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                     "mean_ms": float(np.mean(lat)), "deltas": deltas}
+        G.close()
+        ctx.close()
+    assert out["plain"]["deltas"] == out["served"]["deltas"]
+    for m in out.values():
+        m.pop("deltas")
+    log("update latency: plain p50 %.2f p99 %.2f ms; served p50 %.2f p99 %.2f ms"
+        % (out["plain"]["p50_ms"], out["plain"]["p99_ms"], out["served"]["p50_ms"], out["served"]["p99_ms"]))
+    return out
+
+
+def synth_stream(scale, nbatch, lo, hi):
+    import synth
+    return synth.update_stream(scale, 0, 1, nbatch, lo, hi)
+
+
+def mixed_serving(gj, src, dst, n, scale, nreq, seed, log):
+    """Mixed served workload: nreq requests arriving by Poisson, each a seed-slice
+    count (triangle, 4-cycle, diamond or 4-clique; widths log-uniform in
+    [1, 1000]) or an update batch (log-uniform in [10, 100,000] edges).  The
+    arrival rate is 70% of the plain path's capacity (measured first).  Plain:
+    one request at a time in arrival order; served: the server.  Latency =
+    arrival to result."""
+    import numpy as np
+    import synth
+    rng = np.random.default_rng(seed)
+    kinds = {"triangle": (3, [(0, 1), (1, 2), (0, 2)]), "4-cycle": (4, [(0, 1), (1, 2), (2, 3), (3, 0)]),
+             "diamond": (4, [(0, 1), (0, 2), (1, 3), (2, 3)]),
+             "4-clique": (4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)])}
+    names = list(kinds) + ["update"]
+    plan = []
+    k_upd = 0
+    for i in range(nreq):
+        kind = names[int(rng.integers(0, len(names)))]
+        if kind == "update":
+            size = synth.batch_size(3, k_upd, 10, 100000)
+            bs, bd, bg = synth.update_batch(scale, 0, 16 << scale, 3, k_upd, size)
+            k_upd += 1
+            plan.append(("update", bs, bd, bg))
+        else:
+            plan.append((kind, float(rng.random()), int(np.exp(rng.uniform(0, np.log(1000))))))
+
+    def run(mode, arrivals):
+        ctx = gj.Context(0)
+        ctx.set_option("delta_fused", 0 if mode == "plain" else 1)
+        G = gj.Graph(ctx, src, dst, n)
+        E = G.info()["edges"]
+        qs = {k: gj.Query(ctx, *v) for k, v in kinds.items()}
+        srv = gj.Server(ctx, G, max_batch=16) if mode == "served" else None
+        lat, res, tickets, ext = [], [], [], 0
+        t0 = time.perf_counter()
+        for i, req in enumerate(plan):
+            now = time.perf_counter() - t0
+            if arrivals is not None and arrivals[i] > now:
+                time.sleep(arrivals[i] - now)
+            arr = (time.perf_counter() - t0) if arrivals is None else arrivals[i]
+            if req[0] == "update":
+                if srv:
+                    tickets.append((arr, srv.submit_update(req[1], req[2], req[3], [qs["triangle"]])))
+                else:
+                    r = gj.apply_updates(ctx, G, req[1], req[2], req[3], [qs["triangle"]])[0]
+                    res.append(r["count_delta"])
+                    lat.append((time.perf_counter() - t0 - arr) * 1e3)
+            else:
+                lo = int(req[1] * E)
+                hi = min(E, lo + req[2])
+                if srv:
+                    tickets.append((arr, srv.submit_count(qs[req[0]], lo, hi)))
+                else:
+                    r = gj.count(ctx, G, qs[req[0]], lo, hi)
+                    ext += sum(r["extensions"])
+                    res.append(r["matches"])
+                    lat.append((time.perf_counter() - t0 - arr) * 1e3)
+        for arr, t in tickets:
+            r = srv.wait(t)
+            res.append(r["count_delta"][0] if r["kind"] == gj.REQ_UPDATE else r["count"])
+            lat.append(r["latency_ms"])  # submitted at its arrival time
+        span = time.perf_counter() - t0
+        st = srv.stats() if srv else None
+        if srv:
+            srv.close()
+        G.close()
+        ctx.close()
+        return res, np.array(lat), span, ext, st
+
+    # capacity of the plain path: back-to-back, then arrivals at 70% of it
+    res_p0, _, span0, ext, _ = run("plain", None)
+    rate = 0.7 * nreq / span0
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
+    res_p, lat_p, span_p, _, _ = run("plain", arrivals)
+    res_s, lat_s, span_s, _, st = run("served", arrivals)
+    assert res_p == res_s == res_p0
+    out = {"requests": nreq, "arrival_rate_per_s": rate, "graph_scale": scale,
+           "mix": "uniform over triangle / 4-cycle / diamond / 4-clique seed-slice counts and update batches",
+           "plain": {"p50_ms": float(np.percentile(lat_p, 50)), "p99_ms": float(np.percentile(lat_p, 99)),
+                     "throughput_req_per_s": nreq / span_p},
+           "served": {"p50_ms": float(np.percentile(lat_s, 50)), "p99_ms": float(np.percentile(lat_s, 99)),
+                      "throughput_req_per_s": nreq / span_s, "mean_batch": st["mean_count_batch"]}}
+    log("mixed serving (%d requests at %.0f/s): plain p50 %.2f p99 %.2f ms; served p50 %.2f p99 %.2f ms"
+        % (nreq, rate, out["plain"]["p50_ms"], out["plain"]["p99_ms"], out["served"]["p50_ms"],
+           out["served"]["p99_ms"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +252,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--strategy", type=int, default=0)
     ap.add_argument("--batch-requests", type=int, default=64)
+    ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--latency-batches", type=int, default=200)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of known "
                          "traffic that scales the HBM counters of a profiling run")
@@ -192,6 +326,13 @@ def main():
         batched = {"small_requests": batched_vs_plain(gj, ctx, G, 4 * args.batch_requests, 11, log, 100),
                    "large_requests": batched_vs_plain(gj, ctx, G, args.batch_requests, 7, log, 1000)}
 
+    latency = None
+    if args.latency_batches:
+        latency = update_latency(gj, src, dst, n, args.scale, args.latency_batches, log)
+    serving = None
+    if args.serve_requests:
+        serving = mixed_serving(gj, src, dst, n, args.scale, args.serve_requests, 5, log)
+
     # delta-batch latency: update stream on the same graph
     lat = []
     qd = [q]
@@ -245,6 +386,8 @@ def main():
                      "algorithmic_bytes_per_step": step_bytes},
         "cpu_baseline": cpu,
         "batched": batched,
+        "update_latency": latency,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
 

@@ -357,27 +357,40 @@ gj_status gj_apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const ui
   return s;
 }
 
+}  // extern "C"
+
+namespace gj {
+// Counts of nreq requests on version `ver` (null: current): one fused run,
+// or depth-first runs if a level outgrew the batch capacity.
+void count_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* seed_lo,
+                 const uint64_t* seed_hi, uint64_t* counts, gj_stats* stats, const Version* ver) {
+  for (uint32_t i = 0; i < nreq; ++i) GJ_CHECK(qs[i], GJ_EINVAL, "null query");
+  if (nreq == 0) return;
+  if (!c->batch) c->batch = new BatchExec();
+  bool overflow = false;
+  c->batch->run(c, g, nreq, qs, seed_lo, seed_hi, counts, stats, overflow, ver);
+  if (overflow) {
+    // a level outgrew its capacity: depth-first path, bounded frontiers
+    ++c->batch_fallbacks;
+    for (uint32_t i = 0; i < nreq; ++i) {
+      gj_stats st{};
+      bool ov = false;
+      run_static(c, g, qs[i], GJ_MODE_COUNT, seed_lo[i], seed_hi[i], nullptr, 0, 1, &st, ov, ver);
+      counts[i] = st.matches;
+      if (stats) stats[i] = st;
+    }
+  }
+}
+}  // namespace gj
+
+extern "C" {
+
 gj_status gj_run_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs,
                        const uint64_t* seed_lo, const uint64_t* seed_hi, uint64_t* counts, gj_stats* stats) {
   if (!c || !g || (nreq && (!qs || !seed_lo || !seed_hi || !counts))) return GJ_EINVAL;
   auto t0 = std::chrono::steady_clock::now();
   return guarded(c, [&] {
-    for (uint32_t i = 0; i < nreq; ++i) GJ_CHECK(qs[i], GJ_EINVAL, "null query");
-    if (nreq == 0) return;
-    if (!c->batch) c->batch = new gj::BatchExec();
-    bool overflow = false;
-    c->batch->run(c, g, nreq, qs, seed_lo, seed_hi, counts, stats, overflow);
-    if (overflow) {
-      // a level outgrew its capacity: depth-first path, bounded frontiers
-      ++c->batch_fallbacks;
-      for (uint32_t i = 0; i < nreq; ++i) {
-        gj_stats st{};
-        bool ov = false;
-        gj::run_static(c, g, qs[i], GJ_MODE_COUNT, seed_lo[i], seed_hi[i], nullptr, 0, 1, &st, ov);
-        counts[i] = st.matches;
-        if (stats) stats[i] = st;
-      }
-    }
+    gj::count_batch(c, g, nreq, qs, seed_lo, seed_hi, counts, stats, nullptr);
     double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats)
       for (uint32_t i = 0; i < nreq; ++i) stats[i].ms = ms;

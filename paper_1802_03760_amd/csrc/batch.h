@@ -28,7 +28,7 @@ class BatchExec {
   // counts of nreq (query, seed slice) requests on the current version of g;
   // overflow = a level exceeded the capacity (results not set)
   void run(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* lo,
-           const uint64_t* hi, uint64_t* counts, gj_stats* stats, bool& overflow);
+           const uint64_t* hi, uint64_t* counts, gj_stats* stats, bool& overflow, const Version* ver = nullptr);
   // general form: per request the match count, the signed sum of match
   // weights and the per-level counters (any output may be null)
   void run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t* counts, int64_t* wsums, gj_stats* stats,

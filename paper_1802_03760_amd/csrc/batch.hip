@@ -66,8 +66,8 @@ __device__ __forceinline__ bool member(const uint32_t* __restrict__ a, uint32_t 
 
 // Wave-resident accumulator of arr[key] += val: runs of iterations that agree
 // on one key add in registers and flush with a single atomic when the key
-// changes (or at the end); a wave mixing keys adds lane by lane.  key and the
-// running sum are wave-uniform.
+// changes (or at the end); a wave mixing keys reduces per distinct key.  key
+// and the running sum are wave-uniform.
 struct WaveAcc {
   uint32_t key = 0xFFFFFFFFu;
   uint64_t sum = 0;
@@ -87,8 +87,18 @@ struct WaveAcc {
         key = k0;
       }
       sum += s;
-    } else if (active && val) {
-      atomicAdd(&arr[k], (unsigned long long)val);
+    } else {
+      // mixed keys: one reduction and one atomic per distinct key
+      bool todo = active;
+      while (__ballot(todo)) {
+        uint64_t m = __ballot(todo);
+        int l = __ffsll((unsigned long long)m) - 1;
+        uint32_t kc = __builtin_amdgcn_readfirstlane(__shfl(k, l, 64));
+        bool mine = todo && k == kc;
+        uint64_t s = unit ? (uint64_t)__popcll(__ballot(mine)) : wave_sum(mine ? val : 0);
+        if (lane_id() == l && s) atomicAdd(&arr[kc], (unsigned long long)s);
+        todo = todo && !mine;
+      }
     }
   }
 };
@@ -319,54 +329,64 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
 // ---------------------------------------------------------------- device-size scan
 constexpr int kBtTile = kBlock * 8;
 
+// The scan kernels walk tiles with a fixed grid and stop at the live level
+// size, so a small level costs a few tiles whatever the capacity.
+constexpr unsigned kScanGrid = 1024;
+
 __global__ void __launch_bounds__(kBlock) k_bt_scan_reduce(const uint32_t* __restrict__ in, const BHead* H, int j,
                                                            uint64_t cap, uint64_t* __restrict__ part) {
   uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
-  uint64_t base = (uint64_t)blockIdx.x * kBtTile;
-  uint64_t s = 0;
-  if (base < n) {
+  uint64_t tiles = (n + kBtTile - 1) / kBtTile + 1;
+  for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    uint64_t base = t * kBtTile;
+    uint64_t s = 0;
     for (int i = 0; i < 8; ++i) {
       uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
       if (idx < n) s += in[idx];
     }
+    s = block_sum<kBlock>(s);
+    if (threadIdx.x == 0) part[t] = s;
   }
-  s = block_sum<kBlock>(s);
-  if (threadIdx.x == 0) part[blockIdx.x] = s;
 }
 
 __global__ void __launch_bounds__(kBlock) k_bt_scan_down(const uint32_t* __restrict__ in, const BHead* H, int j,
                                                          uint64_t cap, const uint64_t* __restrict__ part_off,
-                                                         uint64_t nparts, uint64_t* __restrict__ out) {
+                                                         uint64_t* __restrict__ out) {
   __shared__ uint64_t tile[kBtTile];
   uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
-  uint64_t base = (uint64_t)blockIdx.x * kBtTile;
-  if (base > n) return;
-  for (int i = 0; i < 8; ++i) {
-    uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
-    tile[i * kBlock + threadIdx.x] = idx < n ? in[idx] : 0;
-  }
-  __syncthreads();
-  uint64_t loc[8], s = 0;
-  for (int i = 0; i < 8; ++i) {
-    loc[i] = tile[threadIdx.x * 8 + i];
-    s += loc[i];
-  }
-  uint64_t tot;
-  uint64_t run = block_excl_scan<kBlock, uint64_t>(s, tot) + part_off[blockIdx.x];
-  for (int i = 0; i < 8; ++i) {
-    tile[threadIdx.x * 8 + i] = run;
-    run += loc[i];
-  }
-  __syncthreads();
-  for (int i = 0; i < 8; ++i) {
-    uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
-    if (idx <= n) out[idx] = idx < n ? tile[i * kBlock + threadIdx.x] : part_off[nparts];
+  uint64_t tiles = (n + kBtTile - 1) / kBtTile + 1;
+  for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    uint64_t base = t * kBtTile;
+    for (int i = 0; i < 8; ++i) {
+      uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
+      tile[i * kBlock + threadIdx.x] = idx < n ? in[idx] : 0;
+    }
+    __syncthreads();
+    uint64_t loc[8], s = 0;
+    for (int i = 0; i < 8; ++i) {
+      loc[i] = tile[threadIdx.x * 8 + i];
+      s += loc[i];
+    }
+    uint64_t tot;
+    uint64_t run = block_excl_scan<kBlock, uint64_t>(s, tot) + part_off[t];
+    for (int i = 0; i < 8; ++i) {
+      tile[threadIdx.x * 8 + i] = run;
+      run += loc[i];
+    }
+    __syncthreads();
+    for (int i = 0; i < 8; ++i) {
+      uint64_t idx = base + (uint64_t)i * kBlock + threadIdx.x;
+      if (idx <= n) out[idx] = idx < n ? tile[i * kBlock + threadIdx.x] : part_off[tiles];
+    }
+    __syncthreads();
   }
 }
 
-// exclusive scan of the block sums, one workgroup walking tiles (no host size)
-__global__ void __launch_bounds__(kBlock) k_bt_scan_parts(const uint64_t* __restrict__ part, uint64_t n,
-                                                          uint64_t* __restrict__ out) {
+// exclusive scan of the block sums of the live tiles, one workgroup
+__global__ void __launch_bounds__(kBlock) k_bt_scan_parts(const uint64_t* __restrict__ part, const BHead* H, int j,
+                                                          uint64_t cap, uint64_t* __restrict__ out) {
+  uint64_t nl = H->nlev[j] < cap ? H->nlev[j] : cap;
+  uint64_t n = (nl + kBtTile - 1) / kBtTile + 1;
   uint64_t carry = 0;
   for (uint64_t base = 0; base < n; base += kBtTile) {
     uint64_t loc[8], s = 0;
@@ -443,10 +463,9 @@ static void enqueue(gj_ctx* c, BatchExec::Impl& s, unsigned grid) {
     // latency-bound, no dynamic claiming: oversubscribe (idle blocks exit at once)
     k_bt_count_min<<<grid_for(s.cap, kBlock * 4, 8192), kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j],
                                                                          s.cap, s.minc[j], s.mini[j], s.ext());
-    k_bt_scan_reduce<<<(unsigned)s.nparts, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part);
-    k_bt_scan_parts<<<1, kBlock, 0, st>>>(s.part, s.nparts, s.part_off);
-    k_bt_scan_down<<<(unsigned)s.nparts, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part_off, s.nparts,
-                                                         s.off[j]);
+    k_bt_scan_reduce<<<kScanGrid, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part);
+    k_bt_scan_parts<<<1, kBlock, 0, st>>>(s.part, s.d_head, j, s.cap, s.part_off);
+    k_bt_scan_down<<<kScanGrid, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part_off, s.off[j]);
     bool last = j + 1 >= s.max_m;
     k_bt_propose<<<grid, kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j], s.cap, s.off[j], s.mini[j], s.W[j],
                                          last ? nullptr : s.F[j + 1], last ? nullptr : s.rid[j + 1],
@@ -560,8 +579,8 @@ void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t
 }
 
 void BatchExec::run(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* lo,
-                    const uint64_t* hi, uint64_t* counts, gj_stats* stats, bool& overflow) {
-  const Version& v = g->ver[g->cur];
+                    const uint64_t* hi, uint64_t* counts, gj_stats* stats, bool& overflow, const Version* ver) {
+  const Version& v = ver ? *ver : g->ver[g->cur];
   Views V{&v, &v, -1};
   std::vector<ReqSpec> specs;
   specs.reserve(nreq);

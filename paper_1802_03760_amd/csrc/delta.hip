@@ -286,8 +286,10 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   // ---- next version of both indexes
   uint64_t ins_total = 0;
   {
-    // upper bound of the new edge count: old + all of dE
-    version_alloc(nv, n, ov.m + k);
+    // upper bound of the new edge count: old + all of dE, with slack so that a
+    // growing graph does not reallocate the spare version on every batch
+    uint64_t need = ov.m + k;
+    if (need > nv.cap) version_alloc(nv, n, need + need / 16 + (1u << 20));
   }
   update_dir(c, n, ov.d[0], ov.m, es, ed, eg, k, nv.d[0], "f");
   update_dir(c, n, ov.d[1], ov.m, rd, rs, rg, k, nv.d[1], "r");
@@ -295,7 +297,7 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   read_bytes(c, &newm, nv.d[0].rp + n, sizeof(newm));
   nv.m = newm;
   (void)ins_total;
-  version_finish(c, nv, n);
+  version_finish(c, nv, n, true);  // row pointers come from the update
   // ---- delta queries
   // Queries that only need count deltas: every dQ_i of all of them runs as
   // one fused, graph-captured pipeline with signed seeds.

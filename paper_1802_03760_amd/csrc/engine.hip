@@ -268,9 +268,9 @@ static bool identity(const std::vector<int>& o) {
 }
 
 void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint64_t lo, uint64_t hi,
-                uint32_t* out, uint64_t cap, int out_on_device, gj_stats* st, bool& overflow) {
+                uint32_t* out, uint64_t cap, int out_on_device, gj_stats* st, bool& overflow, const Version* ver) {
   PlanH P = make_plan(q, q->order, -1);
-  const Version& v = g->ver[g->cur];
+  const Version& v = ver ? *ver : g->ver[g->cur];
   Views V{&v, &v, -1};
   int dir = P.seed_fwd ? 0 : 1;
   hi = std::min<uint64_t>(hi, v.m);

@@ -200,16 +200,21 @@ void sort_rows(gj_ctx* c, uint32_t* rows, int8_t* signs, uint64_t nrows, int m, 
 uint64_t consolidate_rows(gj_ctx* c, const uint32_t* rows, const int8_t* signs, uint64_t nrows, int m,
                           uint32_t* out_rows, int8_t* out_signs, uint64_t cap, int64_t* sum);
 int bits_for(uint32_t n);
-void version_finish(gj_ctx* c, Version& v, uint32_t n);
+void version_finish(gj_ctx* c, Version& v, uint32_t n, bool rowptrs_ready);
+
+// api.hip: counts of nreq requests on version ver (null: current), fused
+void count_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* seed_lo,
+                 const uint64_t* seed_hi, uint64_t* counts, gj_stats* stats, const Version* ver);
 
 // tune.cpp
 void autotune(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* lo,
               const uint64_t* hi, const char* cache_path, gj_tuning* out);
 
 // engine.hip
+// ver: the graph version to read (null: the current one)
 void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint64_t lo,
                 uint64_t hi, uint32_t* out, uint64_t cap, int out_on_device, gj_stats* st,
-                bool& overflow);
+                bool& overflow, const Version* ver = nullptr);
 void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst,
                    const int8_t* sign, uint64_t b, int on_device, const gj_query* const* qs,
                    uint32_t nq, int64_t* count_delta, uint32_t* const* rows,

@@ -118,11 +118,12 @@ int bits_for(uint32_t n) {
   return b;
 }
 
-void version_finish(gj_ctx* c, Version& v, uint32_t n) {
+void version_finish(gj_ctx* c, Version& v, uint32_t n, bool rowptrs_ready) {
   uint32_t* mx = (uint32_t*)ws_get(c, "maxdeg", 2 * sizeof(uint32_t));
   GJ_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(uint32_t), c->stream));
   for (int d = 0; d < 2; ++d) {
-    k_rowptr<<<grid_for((uint64_t)n + 1, kBlock, 1u << 16), kBlock, 0, c->stream>>>(v.d[d].row, v.m, n, v.d[d].rp);
+    if (!rowptrs_ready)
+      k_rowptr<<<grid_for((uint64_t)n + 1, kBlock, 1u << 16), kBlock, 0, c->stream>>>(v.d[d].row, v.m, n, v.d[d].rp);
     k_maxdeg<<<grid_for(n, kBlock * 16, 1024), kBlock, 0, c->stream>>>(v.d[d].rp, n, mx + d);
   }
   GJ_HIP(hipGetLastError());
@@ -160,7 +161,7 @@ void graph_build(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32_t* 
   uint64_t* rsorted = sort_u64(c, other, other_alt, mu, bits, bits);
   if (mu) k_split_keys<<<grid_for(mu, kBlock, 1u << 16), kBlock, 0, c->stream>>>(rsorted, mu, v.d[1].row, v.d[1].col);
   GJ_HIP(hipGetLastError());
-  version_finish(c, v, n);
+  version_finish(c, v, n, false);
 }
 
 }  // namespace gj

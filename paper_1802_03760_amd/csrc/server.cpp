@@ -134,8 +134,16 @@ static void serve_loop(gj_server* s) {
         lo.push_back(r.lo);
         hi.push_back(r.hi);
       }
-      gj_status st = gj_run_batch(s->ctx, s->g, (uint32_t)batch.size(), qs.data(), lo.data(), hi.data(),
-                                  cnt.data(), nullptr);
+      gj_status st;
+      if (batch.size() == 1) {
+        // alone in the queue: the depth-first path, no fused-level overhead
+        gj_stats one{};
+        st = gj_run(s->ctx, s->g, qs[0], GJ_MODE_COUNT, lo[0], hi[0], nullptr, 0, 0, &one);
+        cnt[0] = one.matches;
+      } else {
+        st = gj_run_batch(s->ctx, s->g, (uint32_t)batch.size(), qs.data(), lo.data(), hi.data(), cnt.data(),
+                          nullptr);
+      }
       for (size_t i = 0; i < batch.size(); ++i) {
         memset(&out[i], 0, sizeof(gj_server_result));
         out[i].kind = GJ_REQ_COUNT;
