@@ -186,7 +186,7 @@ def mixed_serving(gj, src, dst, n, scale, nreq, seed, log):
         E = G.info()["edges"]
         qs = {k: gj.Query(ctx, *v) for k, v in kinds.items()}
         srv = gj.Server(ctx, G, max_batch=16) if mode == "served" else None
-        lat, res, tickets, ext = [], [], [], 0
+        lat, res, tickets, ext, kinds_done = [], [], [], 0, []
         t0 = time.perf_counter()
         for i, req in enumerate(plan):
             now = time.perf_counter() - t0
@@ -200,6 +200,7 @@ def mixed_serving(gj, src, dst, n, scale, nreq, seed, log):
                     r = gj.apply_updates(ctx, G, req[1], req[2], req[3], [qs["triangle"]])[0]
                     res.append(r["count_delta"])
                     lat.append((time.perf_counter() - t0 - arr) * 1e3)
+                    kinds_done.append("update")
             else:
                 lo = int(req[1] * E)
                 hi = min(E, lo + req[2])
@@ -210,34 +211,46 @@ def mixed_serving(gj, src, dst, n, scale, nreq, seed, log):
                     ext += sum(r["extensions"])
                     res.append(r["matches"])
                     lat.append((time.perf_counter() - t0 - arr) * 1e3)
+                    kinds_done.append("count")
         for arr, t in tickets:
             r = srv.wait(t)
             res.append(r["count_delta"][0] if r["kind"] == gj.REQ_UPDATE else r["count"])
             lat.append(r["latency_ms"])  # submitted at its arrival time
+            kinds_done.append("update" if r["kind"] == gj.REQ_UPDATE else "count")
         span = time.perf_counter() - t0
         st = srv.stats() if srv else None
         if srv:
             srv.close()
         G.close()
         ctx.close()
-        return res, np.array(lat), span, ext, st
+        return res, np.array(lat), span, ext, st, np.array(kinds_done)
 
     # capacity of the plain path: back-to-back, then arrivals at 70% of it
-    res_p0, _, span0, ext, _ = run("plain", None)
+    res_p0, _, span0, ext, _, _ = run("plain", None)
     rate = 0.7 * nreq / span0
     arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
-    res_p, lat_p, span_p, _, _ = run("plain", arrivals)
-    res_s, lat_s, span_s, _, st = run("served", arrivals)
+    res_p, lat_p, span_p, _, _, kind_p = run("plain", arrivals)
+    res_s, lat_s, span_s, _, st, kind_s = run("served", arrivals)
+
+    def pct(lat, kinds, kind):
+        x = lat[kinds == kind]
+        return {"p50_ms": float(np.percentile(x, 50)), "p99_ms": float(np.percentile(x, 99)), "n": int(len(x))}
     assert res_p == res_s == res_p0
     out = {"requests": nreq, "arrival_rate_per_s": rate, "graph_scale": scale,
            "mix": "uniform over triangle / 4-cycle / diamond / 4-clique seed-slice counts and update batches",
            "plain": {"p50_ms": float(np.percentile(lat_p, 50)), "p99_ms": float(np.percentile(lat_p, 99)),
-                     "throughput_req_per_s": nreq / span_p},
+                     "throughput_req_per_s": nreq / span_p,
+                     "counts": pct(lat_p, kind_p, "count"), "updates": pct(lat_p, kind_p, "update")},
            "served": {"p50_ms": float(np.percentile(lat_s, 50)), "p99_ms": float(np.percentile(lat_s, 99)),
-                      "throughput_req_per_s": nreq / span_s, "mean_batch": st["mean_count_batch"]}}
+                      "throughput_req_per_s": nreq / span_s, "mean_batch": st["mean_count_batch"],
+                      "counts": pct(lat_s, kind_s, "count"), "updates": pct(lat_s, kind_s, "update")}}
     log("mixed serving (%d requests at %.0f/s): plain p50 %.2f p99 %.2f ms; served p50 %.2f p99 %.2f ms"
         % (nreq, rate, out["plain"]["p50_ms"], out["plain"]["p99_ms"], out["served"]["p50_ms"],
            out["served"]["p99_ms"]))
+    for k in ("counts", "updates"):
+        log("  %s: plain p50 %.2f p99 %.2f ms; served p50 %.2f p99 %.2f ms"
+            % (k, out["plain"][k]["p50_ms"], out["plain"][k]["p99_ms"], out["served"][k]["p50_ms"],
+               out["served"][k]["p99_ms"]))
     return out
 
 

@@ -214,18 +214,26 @@ gj_status gj_autotune(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_qu
 
 /* ---------------------------------------------------------------- serving */
 
-/* A request server: a worker thread that owns ctx and g (make no other call
- * on them while the server exists) and serves count requests and update
- * batches.  Updates are applied in arrival order, one version each (count
- * deltas through the fused delta queries).  A count request sees every
- * update submitted before it and none submitted after (the logical
- * sequencing of Sec. 4.3).  Count requests waiting at the head of the queue
- * are admitted together -- at most max_batch, and while their estimated
- * frontier memory (seed edges x average degree per later attribute x bytes
- * per prefix) stays within mem_budget_bytes (0: no limit) -- and run as one
- * fused pipeline (gj_run_batch); requests arriving meanwhile join the next
- * batch as soon as the device is free.  Results equal gj_run / gj_apply_updates
- * issued alone in submission order. */
+/* A request server: two worker threads that own ctx and g (make no other call
+ * on them while the server exists) and serve count requests and update
+ * batches, overlapped on the device.  Updates are applied in arrival order on
+ * ctx and its stream, one version each (count deltas through the fused delta
+ * queries).  Counts run on a second context with its own stream that the
+ * server creates on ctx's device (with ctx's options).  A count request sees
+ * every update submitted before it and none submitted after (the logical
+ * sequencing of Sec. 4.3): it reads whichever of the graph's two resident
+ * versions holds that state, so counts of the state before an update run
+ * while the update builds the next version; an update waits only while a
+ * queued or running count still needs the version it would overwrite.  Count
+ * requests whose state is resident are admitted together in arrival order --
+ * at most max_batch, all on one version, and while their estimated frontier
+ * memory (seed edges x average degree per later attribute x bytes per prefix)
+ * stays within mem_budget_bytes (0: no limit) -- and run as one fused
+ * pipeline (a request alone runs the depth-first path); requests arriving
+ * meanwhile join the next batch as soon as the count stream is free.  Results
+ * equal gj_run / gj_apply_updates issued alone in submission order.
+ * gj_server_create returns GJ_EDEVICE / GJ_ENOMEM if the second context or
+ * the threads cannot be created. */
 typedef struct gj_server gj_server;
 
 #define GJ_REQ_COUNT 0
@@ -238,7 +246,7 @@ typedef struct {
   uint64_t count;    /* count request: matches */
   uint32_t nq;       /* update: number of queries */
   int64_t count_delta[GJ_SERVER_MAX_QUERIES]; /* update: change of each query's count */
-  uint64_t version;  /* graph version after the request */
+  uint64_t version;  /* graph version the request read (count) or left (update) */
   uint32_t batch_size; /* requests served in the same launch */
   int64_t submit_ns, start_ns, done_ns; /* steady-clock timestamps */
 } gj_server_result;
@@ -264,7 +272,8 @@ gj_status gj_server_submit_update(gj_server* s, const uint32_t* src, const uint3
  * result is returned once. */
 gj_status gj_server_wait(gj_server* s, uint64_t ticket, int64_t timeout_ms, gj_server_result* out);
 gj_status gj_server_get_stats(gj_server* s, gj_server_stats* out);
-/* Serves everything queued, then stops the worker. */
+/* Serves everything queued, then stops the workers and frees the second
+ * context. */
 void gj_server_destroy(gj_server* s);
 
 /* Copies the consolidated delta rows of query number q (its position in the

@@ -381,6 +381,33 @@ void count_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* co
     }
   }
 }
+gj_status count_on_version(gj_ctx* c, const gj_graph* g, const Version* ver, uint32_t nreq,
+                           const gj_query* const* qs, const uint64_t* seed_lo, const uint64_t* seed_hi,
+                           uint64_t* counts) {
+  return guarded(c, [&] {
+    if (nreq == 1) {
+      // alone: the depth-first path, no fused-level overhead
+      gj_stats st{};
+      bool ov = false;
+      GJ_CHECK(qs[0], GJ_EINVAL, "null query");
+      run_static(c, g, qs[0], GJ_MODE_COUNT, seed_lo[0], seed_hi[0], nullptr, 0, 1, &st, ov, ver);
+      counts[0] = st.matches;
+    } else {
+      count_batch(c, g, nreq, qs, seed_lo, seed_hi, counts, nullptr, ver);
+    }
+  });
+}
+
+void copy_options(gj_ctx* dst, const gj_ctx* src) {
+  dst->frontier_cap = src->frontier_cap;
+  dst->seed_chunk = src->seed_chunk;
+  dst->strategy = src->strategy;
+  dst->batch_lin = src->batch_lin;
+  dst->batch_waves_per_cu = src->batch_waves_per_cu;
+  dst->batch_cap = src->batch_cap;
+  dst->delta_fused = src->delta_fused;
+}
+
 }  // namespace gj
 
 extern "C" {

@@ -206,6 +206,14 @@ void version_finish(gj_ctx* c, Version& v, uint32_t n, bool rowptrs_ready);
 void count_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* seed_lo,
                  const uint64_t* seed_hi, uint64_t* counts, gj_stats* stats, const Version* ver);
 
+// api.hip: counts of nreq requests on an explicit version, as a status
+// (one request alone: the depth-first path; more: the fused pipeline)
+gj_status count_on_version(gj_ctx* c, const gj_graph* g, const Version* ver, uint32_t nreq,
+                           const gj_query* const* qs, const uint64_t* seed_lo, const uint64_t* seed_hi,
+                           uint64_t* counts);
+// api.hip: copy the tunable options of one context to another
+void copy_options(gj_ctx* dst, const gj_ctx* src);
+
 // tune.cpp
 void autotune(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* lo,
               const uint64_t* hi, const char* cache_path, gj_tuning* out);

@@ -1,14 +1,22 @@
-// Request server: one worker thread owns a context and a graph, keeps the
-// indexes resident, and serves count requests and update batches.
+// Request server: owns a graph while it lives, keeps its indexes resident,
+// and serves count requests and update batches from two threads that overlap
+// on the device.
 //
-// Updates are applied in arrival order, each as one new version (its count
-// deltas from the fused delta queries).  Count requests see the version that
-// is current when they reach the head of the queue, i.e. every update that
-// arrived before them and none that arrived after (logical sequencing as in
-// Sec. 4.3).  Count requests waiting at the head are admitted together, up
-// to max_batch of them and a frontier-memory budget, and run as one fused
-// pipeline; requests that arrive meanwhile join the next batch as soon as the
-// device is free (continuous batching).
+// Updates are applied in arrival order on the caller's context (and stream),
+// each producing the next version with its count deltas from the fused delta
+// queries.  A count request sees exactly the updates that arrived before it
+// and none after (logical sequencing as in Sec. 4.3): it is tagged at submit
+// time with the number of updates ahead of it, its "state", and runs on an
+// internal second context and stream against the resident version that holds
+// that state.  The graph keeps two versions (an update reads the current one
+// and writes the spare), so counts of the state just before an update run
+// concurrently with it; an update only waits while a count still needs the
+// state held by the spare it is about to overwrite.
+//
+// Count requests whose state is resident are admitted in arrival order, up to
+// max_batch of them and a frontier-memory budget, all on one version, and run
+// as one fused pipeline; requests that arrive meanwhile join the next batch as
+// soon as the count stream is free (continuous batching).
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -36,6 +44,7 @@ struct Req {
   int kind = 0;  // GJ_REQ_COUNT or GJ_REQ_UPDATE
   const gj_query* q = nullptr;
   uint64_t lo = 0, hi = 0;
+  uint64_t state = 0;  // count: updates submitted before it
   std::vector<uint32_t> src, dst;
   std::vector<int8_t> sign;
   std::vector<const gj_query*> qs;
@@ -52,22 +61,32 @@ double percentile(std::vector<double> v, double p) {
   return v[lo] * (1.0 - f) + v[hi] * f;
 }
 
+constexpr uint64_t kNone = ~0ull;
+
 }  // namespace
 
 struct gj_server {
-  gj_ctx* ctx = nullptr;
+  gj_ctx* ctx = nullptr;   // updates: the caller's context
+  gj_ctx* cctx = nullptr;  // counts: internal context with its own stream
   gj_graph* g = nullptr;
   uint32_t max_batch = 64;
   uint64_t mem_budget = 0;
   std::mutex mu;
-  std::condition_variable cv_work, cv_done;
-  std::deque<Req> queue;
+  std::condition_variable cv_count, cv_update, cv_done;
+  std::deque<Req> counts, updates;
   std::unordered_map<uint64_t, gj_server_result> results;
   uint64_t next_ticket = 1;
   bool stop = false;
-  std::thread worker;
+  std::thread count_worker, update_worker;
+  // version bookkeeping (under mu): state u = the graph after the first u
+  // update requests; buffer b of the graph holds states [lo[b], hi[b]]
+  uint64_t submitted_updates = 0, applied = 0;
+  int cur = 0;
+  uint64_t lo[2] = {0, 1}, hi[2] = {0, 0};
+  uint64_t version_no[2] = {0, 0};
+  uint64_t inflight_state = kNone;  // smallest state of the running count batch
   std::vector<double> lat_count, lat_update;
-  uint64_t batches = 0, batched = 0, fallbacks = 0;
+  uint64_t batches = 0, batched = 0;
 };
 
 namespace gj {
@@ -76,11 +95,10 @@ namespace gj {
 // degree once per later attribute (bytes per prefix of each level), the
 // admission test of the server.  An underestimate is harmless: a level that
 // outgrows the batch capacity reruns on the bounded depth-first path.
-static uint64_t estimate_bytes(const gj_graph* g, const Req& r) {
-  const Version& v = g->ver[g->cur];
-  double avg = g->n ? (double)v.m / (double)g->n : 1.0;
+static uint64_t estimate_bytes(uint32_t n, uint64_t m, const Req& r) {
+  double avg = n ? (double)m / (double)n : 1.0;
   if (avg < 1.0) avg = 1.0;
-  uint64_t hi = std::min<uint64_t>(r.hi, v.m), lo = std::min<uint64_t>(r.lo, hi);
+  uint64_t hi = std::min<uint64_t>(r.hi, m), lo = std::min<uint64_t>(r.lo, hi);
   double prefixes = (double)(hi - lo), total = 0;
   for (int j = 2; j < r.q->m; ++j) {
     total += prefixes * (4.0 * j + 14.0);
@@ -89,87 +107,148 @@ static uint64_t estimate_bytes(const gj_graph* g, const Req& r) {
   return (uint64_t)std::min(total, 1e18);
 }
 
-static void serve_loop(gj_server* s) {
-  (void)hipSetDevice(s->ctx->device);
+static int buffer_of(const gj_server* s, uint64_t state) {
+  for (int b = 0; b < 2; ++b)
+    if (s->lo[b] <= state && state <= s->hi[b]) return b;
+  return -1;
+}
+
+static void finish(gj_server* s, std::vector<Req>& reqs, std::vector<gj_server_result>& out, int64_t start) {
+  int64_t done = now_ns();
+  for (size_t i = 0; i < reqs.size(); ++i) {
+    gj_server_result& res = out[i];
+    res.submit_ns = reqs[i].submit_ns;
+    res.start_ns = start;
+    res.done_ns = done;
+    double ms = (double)(done - reqs[i].submit_ns) * 1e-6;
+    (res.kind == GJ_REQ_UPDATE ? s->lat_update : s->lat_count).push_back(ms);
+    s->results[reqs[i].ticket] = res;
+  }
+}
+
+static void count_loop(gj_server* s) {
+  (void)hipSetDevice(s->cctx->device);
   for (;;) {
     std::vector<Req> batch;
+    Version ver;
+    uint64_t vno = 0;
     {
       std::unique_lock<std::mutex> lk(s->mu);
-      s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
-      if (s->queue.empty()) break;  // stop requested and drained
-      if (s->queue.front().kind == GJ_REQ_UPDATE) {
-        batch.push_back(std::move(s->queue.front()));
-        s->queue.pop_front();
-      } else {
-        uint64_t est = 0;
-        while (!s->queue.empty() && s->queue.front().kind == GJ_REQ_COUNT && batch.size() < s->max_batch) {
-          uint64_t e = estimate_bytes(s->g, s->queue.front());
-          if (!batch.empty() && s->mem_budget && est + e > s->mem_budget) break;
-          est += e;
-          batch.push_back(std::move(s->queue.front()));
-          s->queue.pop_front();
-        }
+      s->cv_count.wait(lk, [&] {
+        return (s->stop && s->counts.empty()) || (!s->counts.empty() && s->counts.front().state <= s->applied);
+      });
+      if (s->counts.empty()) break;  // stop requested and drained
+      int b = buffer_of(s, s->counts.front().state);
+      if (b < 0) {
+        // unreachable by construction: updates wait for the counts of the
+        // state they overwrite; fail the request rather than read freed memory
+        Req r = std::move(s->counts.front());
+        s->counts.pop_front();
+        gj_server_result res;
+        memset(&res, 0, sizeof(res));
+        res.kind = GJ_REQ_COUNT;
+        res.status = GJ_EDEVICE;
+        std::vector<Req> one;
+        one.push_back(std::move(r));
+        std::vector<gj_server_result> out(1, res);
+        finish(s, one, out, now_ns());
+        lk.unlock();
+        s->cv_done.notify_all();
+        continue;
       }
+      ver = s->g->ver[b];
+      vno = s->version_no[b];
+      uint64_t est = 0;
+      while (!s->counts.empty() && batch.size() < s->max_batch) {
+        const Req& r = s->counts.front();
+        if (r.state > s->applied || r.state < s->lo[b] || r.state > s->hi[b]) break;
+        uint64_t e = estimate_bytes(s->g->n, ver.m, r);
+        if (!batch.empty() && s->mem_budget && est + e > s->mem_budget) break;
+        est += e;
+        batch.push_back(std::move(s->counts.front()));
+        s->counts.pop_front();
+      }
+      s->inflight_state = batch.front().state;
     }
     int64_t start = now_ns();
-    std::vector<gj_server_result> out(batch.size());
-    if (batch[0].kind == GJ_REQ_UPDATE) {
-      Req& r = batch[0];
-      gj_server_result& res = out[0];
-      memset(&res, 0, sizeof(res));
-      res.kind = GJ_REQ_UPDATE;
-      res.nq = (uint32_t)r.qs.size();
-      int64_t cd[GJ_SERVER_MAX_QUERIES] = {0};
-      gj_status st = gj_apply_updates(s->ctx, s->g, r.src.data(), r.dst.data(), r.sign.data(), r.src.size(), 0,
-                                      r.qs.data(), (uint32_t)r.qs.size(), cd, nullptr, nullptr, nullptr,
-                                      nullptr, nullptr);
-      res.status = st;
-      for (uint32_t i = 0; i < res.nq; ++i) res.count_delta[i] = cd[i];
-      res.batch_size = 1;
-    } else {
-      std::vector<const gj_query*> qs;
-      std::vector<uint64_t> lo, hi, cnt(batch.size());
-      for (auto& r : batch) {
-        qs.push_back(r.q);
-        lo.push_back(r.lo);
-        hi.push_back(r.hi);
-      }
-      gj_status st;
-      if (batch.size() == 1) {
-        // alone in the queue: the depth-first path, no fused-level overhead
-        gj_stats one{};
-        st = gj_run(s->ctx, s->g, qs[0], GJ_MODE_COUNT, lo[0], hi[0], nullptr, 0, 0, &one);
-        cnt[0] = one.matches;
-      } else {
-        st = gj_run_batch(s->ctx, s->g, (uint32_t)batch.size(), qs.data(), lo.data(), hi.data(), cnt.data(),
-                          nullptr);
-      }
-      for (size_t i = 0; i < batch.size(); ++i) {
-        memset(&out[i], 0, sizeof(gj_server_result));
-        out[i].kind = GJ_REQ_COUNT;
-        out[i].status = st;
-        out[i].count = cnt[i];
-        out[i].batch_size = (uint32_t)batch.size();
-      }
+    std::vector<const gj_query*> qs;
+    std::vector<uint64_t> lo, hi, cnt(batch.size());
+    for (auto& r : batch) {
+      qs.push_back(r.q);
+      lo.push_back(r.lo);
+      hi.push_back(r.hi);
     }
-    int64_t done = now_ns();
+    gj_status st = count_on_version(s->cctx, s->g, &ver, (uint32_t)batch.size(), qs.data(), lo.data(), hi.data(),
+                                    cnt.data());
+    std::vector<gj_server_result> out(batch.size());
+    for (size_t i = 0; i < batch.size(); ++i) {
+      memset(&out[i], 0, sizeof(gj_server_result));
+      out[i].kind = GJ_REQ_COUNT;
+      out[i].status = st;
+      out[i].count = cnt[i];
+      out[i].batch_size = (uint32_t)batch.size();
+      out[i].version = vno;
+    }
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      for (size_t i = 0; i < batch.size(); ++i) {
-        gj_server_result& res = out[i];
-        res.version = s->g->version;
-        res.submit_ns = batch[i].submit_ns;
-        res.start_ns = start;
-        res.done_ns = done;
-        double ms = (double)(done - batch[i].submit_ns) * 1e-6;
-        (res.kind == GJ_REQ_UPDATE ? s->lat_update : s->lat_count).push_back(ms);
-        s->results[batch[i].ticket] = res;
-      }
-      if (batch[0].kind == GJ_REQ_COUNT) {
-        ++s->batches;
-        s->batched += batch.size();
-      }
+      finish(s, batch, out, start);
+      ++s->batches;
+      s->batched += batch.size();
+      s->inflight_state = kNone;
     }
+    s->cv_update.notify_all();
+    s->cv_done.notify_all();
+  }
+}
+
+static void update_loop(gj_server* s) {
+  (void)hipSetDevice(s->ctx->device);
+  for (;;) {
+    std::vector<Req> one;
+    {
+      std::unique_lock<std::mutex> lk(s->mu);
+      // the spare buffer may be overwritten once no queued or running count
+      // needs a state older than the current buffer's
+      auto spare_free = [&] {
+        uint64_t need = s->inflight_state;
+        if (!s->counts.empty()) need = std::min(need, s->counts.front().state);
+        return need == kNone || need >= s->lo[s->cur];
+      };
+      s->cv_update.wait(lk, [&] { return (s->stop && s->updates.empty()) || (!s->updates.empty() && spare_free()); });
+      if (s->updates.empty()) break;
+      one.push_back(std::move(s->updates.front()));
+      s->updates.pop_front();
+    }
+    Req& r = one[0];
+    int64_t start = now_ns();
+    std::vector<gj_server_result> out(1);
+    gj_server_result& res = out[0];
+    memset(&res, 0, sizeof(res));
+    res.kind = GJ_REQ_UPDATE;
+    res.nq = (uint32_t)r.qs.size();
+    int64_t cd[GJ_SERVER_MAX_QUERIES] = {0};
+    gj_status st = gj_apply_updates(s->ctx, s->g, r.src.data(), r.dst.data(), r.sign.data(), r.src.size(), 0,
+                                    r.qs.data(), (uint32_t)r.qs.size(), cd, nullptr, nullptr, nullptr, nullptr,
+                                    nullptr);
+    res.status = st;
+    for (uint32_t i = 0; i < res.nq; ++i) res.count_delta[i] = cd[i];
+    res.batch_size = 1;
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      uint64_t u = ++s->applied;
+      if (s->g->cur != s->cur) {
+        // the update wrote the spare buffer, which now holds state u alone
+        s->cur = s->g->cur;
+        s->lo[s->cur] = s->hi[s->cur] = u;
+        s->version_no[s->cur] = s->g->version;
+      } else {
+        // nothing changed (all no-ops, or the batch was rejected)
+        s->hi[s->cur] = u;
+      }
+      res.version = s->version_no[s->cur];
+      finish(s, one, out, start);
+    }
+    s->cv_count.notify_all();
     s->cv_done.notify_all();
   }
 }
@@ -187,21 +266,54 @@ gj_status gj_server_create(gj_ctx* ctx, gj_graph* g, uint32_t max_batch, uint64_
   s->g = g;
   s->max_batch = max_batch;
   s->mem_budget = mem_budget_bytes;
-  s->worker = std::thread(gj::serve_loop, s);
+  gj_status st = gj_ctx_create(ctx->device, nullptr, &s->cctx);
+  if (st != GJ_OK) {
+    delete s;
+    return st;
+  }
+  gj::copy_options(s->cctx, ctx);
+  s->cur = g->cur;
+  s->lo[s->cur] = 0;
+  s->hi[s->cur] = 0;
+  s->lo[1 - s->cur] = 1;  // empty range
+  s->hi[1 - s->cur] = 0;
+  s->version_no[s->cur] = g->version;
+  try {
+    s->count_worker = std::thread(gj::count_loop, s);
+    s->update_worker = std::thread(gj::update_loop, s);
+  } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(s->mu);
+      s->stop = true;
+    }
+    s->cv_count.notify_all();
+    s->cv_update.notify_all();
+    if (s->count_worker.joinable()) s->count_worker.join();
+    gj_ctx_destroy(s->cctx);
+    delete s;
+    return GJ_ENOMEM;
+  }
   *out = s;
   return GJ_OK;
 }
 
 static gj_status enqueue_req(gj_server* s, Req&& r, uint64_t* ticket) {
+  bool update = r.kind == GJ_REQ_UPDATE;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->stop) return GJ_EBUSY;
     r.ticket = s->next_ticket++;
     r.submit_ns = now_ns();
     *ticket = r.ticket;
-    s->queue.push_back(std::move(r));
+    if (update) {
+      ++s->submitted_updates;
+      s->updates.push_back(std::move(r));
+    } else {
+      r.state = s->submitted_updates;
+      s->counts.push_back(std::move(r));
+    }
   }
-  s->cv_work.notify_one();
+  (update ? s->cv_update : s->cv_count).notify_one();
   return GJ_OK;
 }
 
@@ -265,8 +377,11 @@ void gj_server_destroy(gj_server* s) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->stop = true;
   }
-  s->cv_work.notify_all();
-  if (s->worker.joinable()) s->worker.join();
+  s->cv_count.notify_all();
+  s->cv_update.notify_all();
+  if (s->count_worker.joinable()) s->count_worker.join();
+  if (s->update_worker.joinable()) s->update_worker.join();
+  gj_ctx_destroy(s->cctx);
   delete s;
 }
 

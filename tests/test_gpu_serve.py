@@ -114,3 +114,49 @@ def test_served_from_threads(gj):
     results = {t: srv.wait(t, 60000) for t, _ in submitted}
     srv.close()
     replay_and_check(gj, src, dst, n, submitted, results)
+
+
+def test_served_versions_with_noop_and_rejected_updates(gj):
+    """Counts interleaved with many small updates submitted at once (the
+    update thread runs ahead of the counts it must not overwrite), an update
+    made only of no-ops (the version does not change) and a rejected one
+    (vertex out of range: an error status, the graph unchanged)."""
+    scale = 10
+    src, dst = synth.rmat_draws(scale, seed=51)
+    n = 1 << scale
+    ctx = gj.Context(0)
+    G = gj.Graph(ctx, src, dst, n)
+    qs = {k: gj.Query(ctx, *Q.ALL[k]) for k in Q.ALL}
+    E = G.info()["edges"]
+    srv = gj.Server(ctx, G, max_batch=8)
+    stream = list(synth.update_stream(scale, 51, 52, 10, 1, 200))
+    rng = np.random.default_rng(9)
+    submitted, rejected = [], None
+    for k in range(12):
+        for name, lo, hi in make_requests(rng, E, 3, ["triangle", "clique4"]):
+            submitted.append((srv.submit_count(qs[name], lo, hi), ("count", name, lo, hi)))
+        # a full-range count too (the owner-grouped kernel when it runs alone)
+        submitted.append((srv.submit_count(qs["triangle"]), ("count", "triangle", 0, 1 << 40)))
+        if k == 4:
+            # re-insert edges already present: all no-ops
+            bs, bd = np.asarray(src[:50], np.uint32), np.asarray(dst[:50], np.uint32)
+            keep = bs != bd
+            bs, bd = bs[keep], bd[keep]
+            bg = np.ones(len(bs), np.int8)
+            submitted.append((srv.submit_update(bs, bd, bg, [qs["triangle"]]), ("update", bs, bd, bg, ["triangle"])))
+        elif k == 7:
+            bs = np.array([1, n + 5], np.uint32)
+            bd = np.array([2, 3], np.uint32)
+            bg = np.ones(2, np.int8)
+            rejected = srv.submit_update(bs, bd, bg, [qs["triangle"]])
+        else:
+            _, bs, bd, bg = stream.pop(0)
+            submitted.append((srv.submit_update(bs, bd, bg, [qs["triangle"], qs["clique4"]]),
+                              ("update", bs, bd, bg, ["triangle", "clique4"])))
+    results = {t: srv.wait(t, 60000) for t, _ in submitted}
+    rej = srv.wait(rejected, 60000)
+    srv.close()
+    assert rej["status"] != 0 and rej["kind"] == gj.REQ_UPDATE
+    noop = [results[t] for t, r in submitted if r[0] == "update" and len(r[4]) == 1][0]
+    assert noop["count_delta"] == [0]
+    replay_and_check(gj, src, dst, n, submitted, results)
