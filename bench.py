@@ -231,13 +231,17 @@ def mixed_serving(gj, src, dst, n, scale, nreq, seed, log):
     arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
     res_p, lat_p, span_p, _, _, kind_p = run("plain", arrivals)
     res_s, lat_s, span_s, _, st, kind_s = run("served", arrivals)
+    # capacity: every request submitted at once (served) against back-to-back (plain)
+    res_c, _, span_c, _, _, _ = run("served", None)
 
     def pct(lat, kinds, kind):
         x = lat[kinds == kind]
         return {"p50_ms": float(np.percentile(x, 50)), "p99_ms": float(np.percentile(x, 99)), "n": int(len(x))}
-    assert res_p == res_s == res_p0
+    assert res_p == res_s == res_p0 == res_c
     out = {"requests": nreq, "arrival_rate_per_s": rate, "graph_scale": scale,
            "mix": "uniform over triangle / 4-cycle / diamond / 4-clique seed-slice counts and update batches",
+           "capacity": {"plain_req_per_s": nreq / span0, "served_req_per_s": nreq / span_c,
+                        "plain_count_ext_per_s": ext / span0, "served_count_ext_per_s": ext / span_c},
            "plain": {"p50_ms": float(np.percentile(lat_p, 50)), "p99_ms": float(np.percentile(lat_p, 99)),
                      "throughput_req_per_s": nreq / span_p,
                      "counts": pct(lat_p, kind_p, "count"), "updates": pct(lat_p, kind_p, "update")},
@@ -247,6 +251,8 @@ def mixed_serving(gj, src, dst, n, scale, nreq, seed, log):
     log("mixed serving (%d requests at %.0f/s): plain p50 %.2f p99 %.2f ms; served p50 %.2f p99 %.2f ms"
         % (nreq, rate, out["plain"]["p50_ms"], out["plain"]["p99_ms"], out["served"]["p50_ms"],
            out["served"]["p99_ms"]))
+    log("  capacity (all requests at once): plain %.0f req/s, served %.0f req/s"
+        % (out["capacity"]["plain_req_per_s"], out["capacity"]["served_req_per_s"]))
     for k in ("counts", "updates"):
         log("  %s: plain p50 %.2f p99 %.2f ms; served p50 %.2f p99 %.2f ms"
             % (k, out["plain"][k]["p50_ms"], out["plain"][k]["p99_ms"], out["served"][k]["p50_ms"],

@@ -214,26 +214,43 @@ gj_status gj_autotune(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_qu
 
 /* ---------------------------------------------------------------- serving */
 
-/* A request server: two worker threads that own ctx and g (make no other call
- * on them while the server exists) and serve count requests and update
- * batches, overlapped on the device.  Updates are applied in arrival order on
- * ctx and its stream, one version each (count deltas through the fused delta
- * queries).  Counts run on a second context with its own stream that the
- * server creates on ctx's device (with ctx's options).  A count request sees
+/* A request server: worker threads that own ctx and g (make no other call on
+ * them while the server exists) and serve count requests and update batches,
+ * overlapped on the device.
+ *
+ * Updates are applied in arrival order on ctx and its stream, one version
+ * each (count deltas through the fused delta queries).  A count request sees
  * every update submitted before it and none submitted after (the logical
- * sequencing of Sec. 4.3): it reads whichever of the graph's two resident
- * versions holds that state, so counts of the state before an update run
- * while the update builds the next version; an update waits only while a
- * queued or running count still needs the version it would overwrite.  Count
- * requests whose state is resident are admitted together in arrival order --
- * at most max_batch, all on one version, and while their estimated frontier
- * memory (seed edges x average degree per later attribute x bytes per prefix)
- * stays within mem_budget_bytes (0: no limit) -- and run as one fused
- * pipeline (a request alone runs the depth-first path); requests arriving
- * meanwhile join the next batch as soon as the count stream is free.  Results
+ * sequencing of Sec. 4.3): it reads the resident version that holds that
+ * state.  The server rotates the graph through up to "versions" resident
+ * versions (default 4, each the size of the graph's indexes, allocated on
+ * first use and kept until gj_graph_destroy), so counts of older versions run
+ * while updates build newer ones; an update waits only while every other
+ * version is still needed by a queued or running count.
+ *
+ * Counts run on contexts with their own streams that the server creates on
+ * ctx's device (with ctx's options) -- one for light requests, and
+ * "heavy_lanes" more (default 3, created at the first request) -- as
+ * continuous batching: a request joins as soon as its version is resident;
+ * its work is estimated from its seed edges (the exact level-3 extension
+ * count per seed, times a bound for deeper levels, rescaled by what its
+ * finished chunks did).  Light requests (at most iteration_work / 8
+ * estimated extensions; iteration_work defaults to 2^24) run whole, shortest
+ * first, up to max_batch and iteration_work per iteration and while their
+ * estimated frontier memory (seed edges x average degree per later attribute
+ * x bytes per prefix) stays within mem_budget_bytes (0: no limit), in one
+ * fused pipeline per iteration (a request alone runs the depth-first path).
+ * Heavy requests are cut into chunks of about "heavy_work" estimated
+ * extensions (0, the default: 4 x iteration_work) that the heavy lanes run
+ * concurrently on the depth-first path, each lane taking the oldest heavy
+ * request no other lane is running.  Requests whose version an update waits
+ * for go first; with "update_priority" (default 1) no new count iteration or
+ * chunk starts while an update batch is on the device.  With iteration_work
+ * 0 requests run whole, in arrival order, in the fused pipeline.  Results
  * equal gj_run / gj_apply_updates issued alone in submission order.
- * gj_server_create returns GJ_EDEVICE / GJ_ENOMEM if the second context or
- * the threads cannot be created. */
+ * gj_server_create returns GJ_EDEVICE / GJ_ENOMEM if the light context or
+ * the threads cannot be created; the first submit returns GJ_EDEVICE if no
+ * heavy lane can be created. */
 typedef struct gj_server gj_server;
 
 #define GJ_REQ_COUNT 0
@@ -247,19 +264,25 @@ typedef struct {
   uint32_t nq;       /* update: number of queries */
   int64_t count_delta[GJ_SERVER_MAX_QUERIES]; /* update: change of each query's count */
   uint64_t version;  /* graph version the request read (count) or left (update) */
-  uint32_t batch_size; /* requests served in the same launch */
+  uint32_t batch_size; /* chunks in the step (fused iteration or heavy chunk) that finished it */
   int64_t submit_ns, start_ns, done_ns; /* steady-clock timestamps */
 } gj_server_result;
 
 typedef struct {
-  uint64_t completed_counts, completed_updates, count_batches;
-  double mean_count_batch;
+  uint64_t completed_counts, completed_updates;
+  uint64_t count_batches;   /* scheduler steps: fused iterations and heavy chunks */
+  double mean_count_batch;  /* chunks per step */
   double count_p50_ms, count_p99_ms;   /* submit -> done */
   double update_p50_ms, update_p99_ms;
 } gj_server_stats;
 
 gj_status gj_server_create(gj_ctx* ctx, gj_graph* g, uint32_t max_batch, uint64_t mem_budget_bytes,
                            gj_server** out);
+/* Server options: "iteration_work" (>= 0), "heavy_work" (>= 0),
+ * "update_priority" (0 or 1), "max_batch" (1..65536) at any time;
+ * "versions" (2..8) and "heavy_lanes" (1..4) before the first request, else
+ * GJ_EBUSY.  GJ_EINVAL for an unknown key or a value out of range. */
+gj_status gj_server_set_option(gj_server* s, const char* key, int64_t value);
 /* Queues a count of query q over seed edges [seed_lo, seed_hi) (as gj_run);
  * *ticket identifies the result.  The query must outlive the request. */
 gj_status gj_server_submit_count(gj_server* s, const gj_query* q, uint64_t seed_lo, uint64_t seed_hi,

@@ -30,7 +30,8 @@ EXPORTS = ["gj_ctx_create", "gj_ctx_destroy", "gj_last_error", "gj_ctx_set_optio
            "gj_graph_build", "gj_graph_info", "gj_graph_csr", "gj_graph_destroy",
            "gj_query_register", "gj_query_destroy", "gj_run", "gj_apply_updates",
            "gj_last_delta", "gj_run_batch", "gj_autotune", "gj_server_create", "gj_server_submit_count",
-           "gj_server_submit_update", "gj_server_wait", "gj_server_get_stats", "gj_server_destroy"]
+           "gj_server_submit_update", "gj_server_wait", "gj_server_get_stats", "gj_server_destroy",
+           "gj_server_set_option"]
 REQ_COUNT, REQ_UPDATE = 0, 1
 SERVER_MAX_QUERIES = 16
 
@@ -123,6 +124,8 @@ _lib.gj_server_submit_update.argtypes = [_vp, _vp, _vp, _vp, _u64, ctypes.POINTE
 _lib.gj_server_submit_update.restype = _i32
 _lib.gj_server_wait.argtypes = [_vp, _u64, ctypes.c_int64, ctypes.POINTER(ServerResult)]
 _lib.gj_server_wait.restype = _i32
+_lib.gj_server_set_option.argtypes = [_vp, ctypes.c_char_p, ctypes.c_int64]
+_lib.gj_server_set_option.restype = _i32
 _lib.gj_server_get_stats.argtypes = [_vp, ctypes.POINTER(ServerStats)]
 _lib.gj_server_get_stats.restype = _i32
 _lib.gj_server_destroy.argtypes = [_vp]
@@ -297,10 +300,11 @@ def count(ctx, graph, query, seed_lo=0, seed_hi=(1 << 64) - 1):
 
 
 class Server:
-    """Request server over a context and a graph (gj_server_*): the worker
-    thread owns both until close()."""
+    """Request server over a context and a graph (gj_server_*): its worker
+    threads own both until close().  iteration_work, versions: server options
+    (None keeps the library default)."""
 
-    def __init__(self, ctx, graph, max_batch=64, mem_budget_bytes=0):
+    def __init__(self, ctx, graph, max_batch=64, mem_budget_bytes=0, iteration_work=None, versions=None):
         self.ctx, self.graph = ctx, graph
         h = _vp()
         st = _lib.gj_server_create(ctx._h, graph._h, max_batch, mem_budget_bytes, ctypes.byref(h))
@@ -310,6 +314,15 @@ class Server:
         self._keep = {}  # queries referenced by queued requests
         ctx._children.add(self)
         _live.add(self)
+        if iteration_work is not None:
+            self.set_option("iteration_work", iteration_work)
+        if versions is not None:
+            self.set_option("versions", versions)
+
+    def set_option(self, key, value):
+        st = _lib.gj_server_set_option(self._h, key.encode(), int(value))
+        if st != GJ_OK:
+            raise GJError(st, "gj_server_set_option(%s)" % key)
 
     def submit_count(self, query, seed_lo=0, seed_hi=(1 << 64) - 1):
         t = _u64()

@@ -263,8 +263,7 @@ void gj_graph_destroy(gj_graph* g) {
     (void)hipSetDevice(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
   }
-  gj::version_free(g->ver[0]);
-  gj::version_free(g->ver[1]);
+  for (auto& v : g->ver) gj::version_free(v);
   delete g;
 }
 
@@ -381,20 +380,62 @@ void count_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* co
     }
   }
 }
-gj_status count_on_version(gj_ctx* c, const gj_graph* g, const Version* ver, uint32_t nreq,
-                           const gj_query* const* qs, const uint64_t* seed_lo, const uint64_t* seed_hi,
-                           uint64_t* counts) {
+gj_status count_on_versions(gj_ctx* c, const gj_graph* g, const Version* const* vers, uint32_t nreq,
+                            const gj_query* const* qs, const uint64_t* seed_lo, const uint64_t* seed_hi,
+                            uint64_t* counts, gj_stats* stats) {
   return guarded(c, [&] {
+    for (uint32_t i = 0; i < nreq; ++i) GJ_CHECK(qs[i] && vers[i], GJ_EINVAL, "null query or version");
     if (nreq == 1) {
       // alone: the depth-first path, no fused-level overhead
       gj_stats st{};
       bool ov = false;
-      GJ_CHECK(qs[0], GJ_EINVAL, "null query");
-      run_static(c, g, qs[0], GJ_MODE_COUNT, seed_lo[0], seed_hi[0], nullptr, 0, 1, &st, ov, ver);
+      run_static(c, g, qs[0], GJ_MODE_COUNT, seed_lo[0], seed_hi[0], nullptr, 0, 1, &st, ov, vers[0]);
       counts[0] = st.matches;
-    } else {
-      count_batch(c, g, nreq, qs, seed_lo, seed_hi, counts, nullptr, ver);
+      if (stats) stats[0] = st;
+      return;
     }
+    if (!c->batch) c->batch = new BatchExec();
+    std::vector<ReqSpec> specs;
+    specs.reserve(nreq);
+    for (uint32_t i = 0; i < nreq; ++i) {
+      const Version& v = *vers[i];
+      ReqSpec r{make_plan(qs[i], qs[i]->order, -1), Views{&v, &v, -1}};
+      int dir = r.P.seed_fwd ? 0 : 1;
+      uint64_t h = std::min<uint64_t>(seed_hi[i], v.m), l = std::min<uint64_t>(seed_lo[i], h);
+      r.row = v.d[dir].row;
+      r.col = v.d[dir].col;
+      r.lo = l;
+      r.len = h - l;
+      specs.push_back(std::move(r));
+    }
+    bool overflow = false;
+    c->batch->run_specs(c, specs, counts, nullptr, stats, overflow);
+    if (overflow) {
+      ++c->batch_fallbacks;
+      for (uint32_t i = 0; i < nreq; ++i) {
+        gj_stats st{};
+        bool ov = false;
+        run_static(c, g, qs[i], GJ_MODE_COUNT, seed_lo[i], seed_hi[i], nullptr, 0, 1, &st, ov, vers[i]);
+        counts[i] = st.matches;
+        if (stats) stats[i] = st;
+      }
+    }
+  });
+}
+
+gj_status update_into(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst, const int8_t* sign,
+                      uint64_t b, const gj_query* const* qs, uint32_t nq, int64_t* count_delta, int target) {
+  return guarded(c, [&] {
+    bool overflow = false;
+    apply_updates(c, g, src, dst, sign, b, 0, qs, nq, count_delta, nullptr, nullptr, nullptr, nullptr, nullptr,
+                  overflow, target);
+  });
+}
+
+gj_status reserve_version(gj_ctx* c, gj_graph* g, int b, uint64_t cap) {
+  return guarded(c, [&] {
+    GJ_CHECK(b >= 0 && b < kMaxVersions && b != g->cur, GJ_EINVAL, "bad version slot");
+    version_alloc(g->ver[b], g->n, cap);
   });
 }
 

@@ -211,12 +211,14 @@ static void add_stats(gj_stats& a, const gj_stats& b) {
 void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst, const int8_t* sign, uint64_t b,
                    int on_device, const gj_query* const* qs, uint32_t nq, int64_t* count_delta,
                    uint32_t* const* out_rows, int8_t* const* out_signs, const uint64_t* cap, uint64_t* n_delta,
-                   gj_stats* stats, bool& overflow) {
+                   gj_stats* stats, bool& overflow, int target) {
   overflow = false;
   uint32_t n = g->n;
   int bits = bits_for(n);
+  if (target < 0) target = g->cur < 2 ? 1 - g->cur : 0;
+  GJ_CHECK(target < kMaxVersions && target != g->cur, GJ_EINVAL, "update target is the current version");
   Version& ov = g->ver[g->cur];
-  Version& nv = g->ver[1 - g->cur];
+  Version& nv = g->ver[target];
   c->last_delta.assign(nq, gj_ctx::LastDelta{});
   for (uint32_t k = 0; k < nq; ++k) {
     if (count_delta) count_delta[k] = 0;
@@ -445,7 +447,7 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
       stats[qi] = acc;
     }
   }
-  g->cur = 1 - g->cur;
+  g->cur = target;
   g->version += 1;
 }
 

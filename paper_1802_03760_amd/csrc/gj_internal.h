@@ -115,10 +115,16 @@ struct gj_ctx {
   int delta_fused = 1;              // count-only delta queries through the fused pipeline
 };
 
+// Resident versions of a graph: ver[cur] is current; an update reads it and
+// writes another slot (allocated on first use), which then becomes current.
+// Two slots serve the plain update path; a server may rotate through more so
+// that counts of older versions keep running while updates proceed.
+constexpr int kMaxVersions = 8;
+
 struct gj_graph {
   gj_ctx* ctx = nullptr;
   uint32_t n = 0;
-  gj::Version ver[2];
+  gj::Version ver[kMaxVersions];
   int cur = 0;
   uint64_t version = 0;
 };
@@ -206,11 +212,17 @@ void version_finish(gj_ctx* c, Version& v, uint32_t n, bool rowptrs_ready);
 void count_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* seed_lo,
                  const uint64_t* seed_hi, uint64_t* counts, gj_stats* stats, const Version* ver);
 
-// api.hip: counts of nreq requests on an explicit version, as a status
-// (one request alone: the depth-first path; more: the fused pipeline)
-gj_status count_on_version(gj_ctx* c, const gj_graph* g, const Version* ver, uint32_t nreq,
-                           const gj_query* const* qs, const uint64_t* seed_lo, const uint64_t* seed_hi,
-                           uint64_t* counts);
+// api.hip: counts of nreq requests, request i on version vers[i], as a status
+// (one request alone: the depth-first path; more: one fused pipeline)
+gj_status count_on_versions(gj_ctx* c, const gj_graph* g, const Version* const* vers, uint32_t nreq,
+                            const gj_query* const* qs, const uint64_t* seed_lo, const uint64_t* seed_hi,
+                            uint64_t* counts, gj_stats* stats);
+// api.hip: an update batch from host arrays written into version slot
+// `target`, count deltas only, as a status
+gj_status update_into(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst, const int8_t* sign,
+                      uint64_t b, const gj_query* const* qs, uint32_t nq, int64_t* count_delta, int target);
+// api.hip: allocate version slot b with room for cap edges, as a status
+gj_status reserve_version(gj_ctx* c, gj_graph* g, int b, uint64_t cap);
 // api.hip: copy the tunable options of one context to another
 void copy_options(gj_ctx* dst, const gj_ctx* src);
 
@@ -223,10 +235,11 @@ void autotune(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const
 void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint64_t lo,
                 uint64_t hi, uint32_t* out, uint64_t cap, int out_on_device, gj_stats* st,
                 bool& overflow, const Version* ver = nullptr);
+// target: the version slot to write (-1: slot 1 - cur for cur < 2, else 0)
 void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst,
                    const int8_t* sign, uint64_t b, int on_device, const gj_query* const* qs,
                    uint32_t nq, int64_t* count_delta, uint32_t* const* rows,
                    int8_t* const* signs, const uint64_t* cap, uint64_t* n_delta,
-                   gj_stats* stats, bool& overflow);
+                   gj_stats* stats, bool& overflow, int target = -1);
 
 }  // namespace gj

@@ -54,7 +54,12 @@ def replay_and_check(gj, src, dst, n, submitted, results):
             oracle.delta(O, bs, bd, bg)
 
 
-def test_served_mix_equals_alone(gj):
+@pytest.mark.parametrize("iteration_work,versions,heavy_work", [(None, None, None), (0, 2, None), (4096, 3, 2048),
+                                                                (1 << 16, 8, None), (256, 4, 1 << 14)])
+def test_served_mix_equals_alone(gj, iteration_work, versions, heavy_work):
+    """iteration_work 0: whole requests in arrival order; small budgets: most
+    requests heavy, cut into many chunks on the heavy lanes; versions:
+    resident version slots."""
     scale = 11
     src, dst = synth.rmat_draws(scale, seed=31)
     n = 1 << scale
@@ -63,7 +68,9 @@ def test_served_mix_equals_alone(gj):
     qs = {k: gj.Query(ctx, *Q.ALL[k]) for k in Q.ALL}
     E = G.info()["edges"]
     rng = np.random.default_rng(5)
-    srv = gj.Server(ctx, G, max_batch=32)
+    srv = gj.Server(ctx, G, max_batch=32, iteration_work=iteration_work, versions=versions)
+    if heavy_work is not None:
+        srv.set_option("heavy_work", heavy_work)
     submitted = []
     stream = list(synth.update_stream(scale, 31, 32, 6, 1, 500))
     names = ["triangle", "clique4", "diamond", "cycle4", "cyclic_triangle", "reciprocal"]
@@ -78,7 +85,10 @@ def test_served_mix_equals_alone(gj):
     st = srv.stats()
     srv.close()
     assert st["completed_counts"] == 150 and st["completed_updates"] == 6
-    assert max(r["batch_size"] for r in results.values()) > 1  # requests were batched
+    if iteration_work != 256:  # 256: nearly every request is heavy
+        assert max(r["batch_size"] for r in results.values()) > 1  # requests were batched
+    if iteration_work == 4096:
+        assert st["count_batches"] > 150  # requests were cut into chunks
     replay_and_check(gj, src, dst, n, submitted, results)
 
 
@@ -128,7 +138,7 @@ def test_served_versions_with_noop_and_rejected_updates(gj):
     G = gj.Graph(ctx, src, dst, n)
     qs = {k: gj.Query(ctx, *Q.ALL[k]) for k in Q.ALL}
     E = G.info()["edges"]
-    srv = gj.Server(ctx, G, max_batch=8)
+    srv = gj.Server(ctx, G, max_batch=8, iteration_work=1 << 14, versions=3)
     stream = list(synth.update_stream(scale, 51, 52, 10, 1, 200))
     rng = np.random.default_rng(9)
     submitted, rejected = [], None
@@ -160,3 +170,31 @@ def test_served_versions_with_noop_and_rejected_updates(gj):
     noop = [results[t] for t, r in submitted if r[0] == "update" and len(r[4]) == 1][0]
     assert noop["count_delta"] == [0]
     replay_and_check(gj, src, dst, n, submitted, results)
+
+
+def test_server_options(gj):
+    ctx = gj.Context(0)
+    src, dst = synth.rmat_draws(8, seed=3)
+    G = gj.Graph(ctx, src, dst, 1 << 8)
+    q = gj.Query(ctx, *Q.TRIANGLE)
+    srv = gj.Server(ctx, G)
+    for key, val in (("versions", 1), ("versions", 9), ("iteration_work", -1), ("max_batch", 0), ("nope", 1),
+                     ("heavy_lanes", 0), ("heavy_lanes", 5), ("heavy_work", -1), ("update_priority", 2)):
+        with pytest.raises(gj.GJError) as e:
+            srv.set_option(key, val)
+        assert e.value.status == gj.GJ_EINVAL
+    srv.set_option("versions", 5)
+    srv.set_option("heavy_lanes", 1)
+    srv.set_option("update_priority", 0)
+    srv.set_option("heavy_work", 1 << 20)
+    r = srv.wait(srv.submit_count(q))
+    assert r["count"] == oracle.run(oracle.Graph(1 << 8, src, dst), Q.TRIANGLE)["matches"]
+    for key in ("versions", "heavy_lanes"):
+        with pytest.raises(gj.GJError) as e:
+            srv.set_option(key, 3)  # after the first request
+        assert e.value.status == gj.GJ_EBUSY
+    srv.set_option("iteration_work", 0)
+    assert srv.wait(srv.submit_count(q))["count"] == r["count"]
+    srv.close()
+    G.close()
+    ctx.close()
