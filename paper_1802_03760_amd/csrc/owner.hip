@@ -171,7 +171,7 @@ __device__ __forceinline__ bool probe(const uint32_t* H, uint32_t x, int shift, 
   const uint4* B = reinterpret_cast<const uint4*>(H);
   uint32_t b = bucket_of(x, shift);
   uint4 q = B[b];
-  if (q.x == x || q.y == x || q.z == x || q.w == x) return true;
+  if (min(min(q.x ^ x, q.y ^ x), min(q.z ^ x, q.w ^ x)) == 0u) return true;
   if (q.w == kEmpty) return false;
   return probe_from(H, x, b, bmask);
 }
@@ -192,34 +192,66 @@ __device__ __forceinline__ uint32_t find_lds(const uint32_t* off, uint32_t lo, u
 // Per task: the owner's probe set goes into the LDS table (segment by
 // segment), then its partners are taken kOwnNT at a time.  Partners whose
 // proposing set has at least kLong elements are streamed by one wave each
-// (four coalesced 64-element loads in flight per step); shorter ones are
-// concatenated and walked in 64-element windows.
+// (stream_probe); shorter ones are concatenated and walked in 64-element
+// windows.
+
+// Buffer resource word 3 for gfx9-family raw buffers (32-bit dwords, no
+// swizzle); loads at or past num_records bytes return zero.
+constexpr int kBufWord3 = 0x00020000;
+
+// One wave streams one proposing set through the table: U coalesced loads in
+// flight per step (raw-buffer loads off the wave-uniform base of the set, so
+// addressing is one offset per step), then U first-bucket reads, and a
+// membership test as a minimum of slot-xor-value (zero iff present), which
+// keeps the test to a few full-rate instructions.  Values whose first bucket
+// is full and lacks them walk on to later buckets behind one wave-uniform
+// branch.
 template <int U>
-__device__ __forceinline__ uint32_t stream_probe(const uint32_t* __restrict__ qadj, uint32_t st, uint32_t s,
-                                                 const uint32_t* H, int shift, uint32_t mask) {
+__device__ __forceinline__ uint32_t stream_probe(const uint32_t* __restrict__ set, uint32_t s, const uint32_t* H,
+                                                 int shift, uint32_t mask) {
   const uint4* B = reinterpret_cast<const uint4*>(H);
   const uint32_t lane = (uint32_t)lane_id();
+  // the wave's proposing set (wave-uniform base and size) as a raw buffer
+  __amdgpu_buffer_rsrc_t R = __builtin_amdgcn_make_buffer_rsrc((void*)set, (short)0, (int)(s * 4u), kBufWord3);
   uint32_t hits = 0;
   for (uint32_t i = lane; i < s; i += 64 * U) {
     uint32_t x[U], b[U];
     bool ok[U];
     uint4 q[U];
+    // lanes past the end load zero (out of the buffer's range); ok masks them
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       ok[u] = i + 64 * u < s;
-      x[u] = ok[u] ? qadj[st + i + 64 * u] : 0u;
+      x[u] = __builtin_amdgcn_raw_buffer_load_b32(R, i * 4u + 256u * u, 0, 0);
     }
-    // first buckets of all U values read before any is resolved
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       b[u] = bucket_of(x[u], shift);
       q[u] = B[b[u]];
     }
+    uint32_t pend = 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      bool hit = q[u].x == x[u] || q[u].y == x[u] || q[u].z == x[u] || q[u].w == x[u];
-      if (ok[u] && !hit && q[u].w != kEmpty) hit = probe_from(H, x[u], b[u], mask);
-      hits += (ok[u] && hit) ? 1u : 0u;
+      bool hit = min(min(q[u].x ^ x[u], q[u].y ^ x[u]), min(q[u].z ^ x[u], q[u].w ^ x[u])) == 0u;
+      hits += (ok[u] & hit) ? 1u : 0u;
+      pend |= (ok[u] & !hit & (q[u].w != kEmpty)) ? (1u << u) : 0u;
+    }
+    // a full first bucket without the value: walk on (one wave-uniform branch)
+    if (__ballot(pend != 0)) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        bool more = (pend >> u) & 1u;
+        uint32_t bb = b[u];
+        while (__ballot(more)) {
+          if (more) {
+            bb = (bb + 1) & mask;
+            uint4 r = B[bb];
+            bool hit = min(min(r.x ^ x[u], r.y ^ x[u]), min(r.z ^ x[u], r.w ^ x[u])) == 0u;
+            hits += hit ? 1u : 0u;
+            more = !hit & (r.w != kEmpty);
+          }
+        }
+      }
     }
   }
   return hits;
@@ -252,9 +284,9 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
     uint32_t nseg = (D + kSegMax - 1) / kSegMax;
     for (uint32_t seg = 0; seg < nseg; ++seg) {
       uint32_t e0 = seg * kSegMax, e1 = min(D, e0 + kSegMax), cnt = e1 - e0;
-      // slots: power of two >= 4 * cnt (load <= 1/4) up to the table size
+      // slots: power of two >= 8 * cnt (load <= 1/8) up to the table size
       int lg = 6;
-      while ((1u << lg) < 4 * cnt && lg < kLogSlots) ++lg;
+      while ((1u << lg) < 8 * cnt && lg < kLogSlots) ++lg;
       uint32_t slots = 1u << lg, mask = (slots >> 2) - 1;  // mask over buckets
       int shift = 32 - (lg - 2);
       for (uint32_t i = tid; i < slots; i += kOwnNT) H[i] = kEmpty;
@@ -305,7 +337,10 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
           if (lane == 0) k = atomicAdd(&s_long, 1u);
           k = __shfl(k, 0, 64);
           if (k >= nlong) break;
-          hits += stream_probe<4>(L.qadj, pst[k], pval[k], H, shift, mask);
+          // one wave per partner: its set's start and size are wave-uniform
+          uint32_t st_k = __builtin_amdgcn_readfirstlane(pst[k]);
+          uint32_t s_k = __builtin_amdgcn_readfirstlane(pval[k]);
+          hits += stream_probe<4>(L.qadj + st_k, s_k, H, shift, mask);
         }
         // short partners: 64-element windows over their concatenation
         for (uint32_t g0 = (uint32_t)wave * 64; g0 < short_total; g0 += nwaves * 64) {
