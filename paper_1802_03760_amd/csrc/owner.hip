@@ -199,9 +199,10 @@ __device__ __forceinline__ uint32_t find_lds(const uint32_t* off, uint32_t lo, u
 // swizzle); loads at or past num_records bytes return zero.
 constexpr int kBufWord3 = 0x00020000;
 
-// One wave streams one proposing set through the table: U coalesced loads in
-// flight per step (raw-buffer loads off the wave-uniform base of the set, so
-// addressing is one offset per step), then U first-bucket reads, and a
+// One wave streams one proposing set through the table: U coalesced loads per
+// step (raw-buffer loads off the wave-uniform base of the set, so addressing
+// is one offset per step), issued one step ahead so that they are in flight
+// while the previous step probes; then U first-bucket reads, and a
 // membership test as a minimum of slot-xor-value (zero iff present), which
 // keeps the test to a few full-rate instructions.  Values whose first bucket
 // is full and lacks them walk on to later buckets behind one wave-uniform
@@ -214,16 +215,21 @@ __device__ __forceinline__ uint32_t stream_probe(const uint32_t* __restrict__ se
   // the wave's proposing set (wave-uniform base and size) as a raw buffer
   __amdgpu_buffer_rsrc_t R = __builtin_amdgcn_make_buffer_rsrc((void*)set, (short)0, (int)(s * 4u), kBufWord3);
   uint32_t hits = 0;
+  uint32_t xn[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) xn[u] = __builtin_amdgcn_raw_buffer_load_b32(R, lane * 4u + 256u * u, 0, 0);
   for (uint32_t i = lane; i < s; i += 64 * U) {
     uint32_t x[U], b[U];
     bool ok[U];
     uint4 q[U];
-    // lanes past the end load zero (out of the buffer's range); ok masks them
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       ok[u] = i + 64 * u < s;
-      x[u] = __builtin_amdgcn_raw_buffer_load_b32(R, i * 4u + 256u * u, 0, 0);
+      x[u] = xn[u];
     }
+    // next step's loads in flight while this one probes (zero past the end)
+#pragma unroll
+    for (int u = 0; u < U; ++u) xn[u] = __builtin_amdgcn_raw_buffer_load_b32(R, (i + 64u * U) * 4u + 256u * u, 0, 0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       b[u] = bucket_of(x[u], shift);
@@ -340,7 +346,13 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
           // one wave per partner: its set's start and size are wave-uniform
           uint32_t st_k = __builtin_amdgcn_readfirstlane(pst[k]);
           uint32_t s_k = __builtin_amdgcn_readfirstlane(pval[k]);
-          hits += stream_probe<4>(L.qadj + st_k, s_k, H, shift, mask);
+          // loads per step by set size: fewer wasted lanes on short sets
+          if (s_k <= 128)
+            hits += stream_probe<2>(L.qadj + st_k, s_k, H, shift, mask);
+          else if (s_k <= 192)
+            hits += stream_probe<3>(L.qadj + st_k, s_k, H, shift, mask);
+          else
+            hits += stream_probe<4>(L.qadj + st_k, s_k, H, shift, mask);
         }
         // short partners: 64-element windows over their concatenation
         for (uint32_t g0 = (uint32_t)wave * 64; g0 < short_total; g0 += nwaves * 64) {
