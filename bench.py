@@ -24,7 +24,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one k_owner_count launch on this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB device copy in the same
 # run; valid only for the kernel source it was measured on (sha256 prefix).
-MEASURED_TRAFFIC = {"owner.hip": "6f8ffaccb5da0110", "bytes": 133.15e9 + 0.020e9}
+MEASURED_TRAFFIC = {"owner.hip": "7ba31d338846310c", "bytes": 126.47e9 + 1.010e9}
 TRIANGLE = (3, [(0, 1), (1, 2), (0, 2)], [0, 1, 2])
 
 

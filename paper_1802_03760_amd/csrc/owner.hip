@@ -176,16 +176,16 @@ __device__ __forceinline__ bool probe(const uint32_t* H, uint32_t x, int shift, 
   return probe_from(H, x, b, bmask);
 }
 
-// p in [lo, hi) with off[p] <= g < off[p+1] over an LDS array
-__device__ __forceinline__ uint32_t find_lds(const uint32_t* off, uint32_t lo, uint32_t hi, uint32_t g) {
-  while (hi - lo > 1) {
-    uint32_t mid = (lo + hi) >> 1;
-    if (off[mid] <= g)
-      lo = mid;
-    else
-      hi = mid;
+// first i in [lo, hi) with a[i] >= x (hi if none), searching forward from lo
+// by doubling steps first: cheap when the answer lies near lo
+__device__ __forceinline__ uint32_t gallop_lb(const uint32_t* __restrict__ a, uint32_t lo, uint32_t hi, uint32_t x) {
+  uint64_t step = 1, b = lo;
+  while (b < hi && a[b] < x) {
+    lo = (uint32_t)b + 1;
+    b = lo + step;
+    step <<= 1;
   }
-  return lo;
+  return lower_bound_u32(a, lo, b < hi ? (uint32_t)b : hi, x);
 }
 
 // ---------------------------------------------------------------- main kernel
@@ -271,6 +271,7 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
   __shared__ __attribute__((aligned(16))) uint32_t H[kSlots];
   __shared__ uint32_t pst[kOwnNT];       // start of each partner's proposing set
   __shared__ uint32_t pval[kOwnNT + 1];  // long: size; short: offset in the short space
+  __shared__ uint16_t wstart[kOwnNT];    // short window -> set holding its first element
   __shared__ uint32_t s_task, s_long;
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   constexpr int nwaves = kOwnNT / 64;
@@ -288,35 +289,41 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
     uint32_t Lb = L.prp[v], D = L.prp[v + 1] - Lb;
     uint32_t Sb = L.srp[v];
     uint32_t nseg = (D + kSegMax - 1) / kSegMax;
-    for (uint32_t seg = 0; seg < nseg; ++seg) {
-      uint32_t e0 = seg * kSegMax, e1 = min(D, e0 + kSegMax), cnt = e1 - e0;
-      // slots: power of two >= 8 * cnt (load <= 1/8) up to the table size
-      int lg = 6;
-      while ((1u << lg) < 8 * cnt && lg < kLogSlots) ++lg;
-      uint32_t slots = 1u << lg, mask = (slots >> 2) - 1;  // mask over buckets
-      int shift = 32 - (lg - 2);
-      for (uint32_t i = tid; i < slots; i += kOwnNT) H[i] = kEmpty;
-      __syncthreads();
-      for (uint32_t i = tid; i < cnt; i += kOwnNT) insert(H, L.padj[Lb + e0 + i], shift, mask);
-      __syncthreads();
-      uint32_t lo_s = L.padj[Lb + e0], hi_s = L.padj[Lb + e1 - 1];
-      for (uint32_t c = plo; c < phi; c += kOwnNT) {
-        uint32_t i = c + tid;
-        uint32_t s = 0, st = 0;
-        if (i < phi) {
-          uint32_t u = L.sadj[Sb + i];
-          uint32_t qb = L.qrp[u];
-          s = L.qrp[u + 1] - qb;
-          if (!owned(r, s, D)) s = 0;
-          if (seg == 0) ext += s;
-          st = qb;
-          if (s && nseg > 1) {
-            // vertex ids are below 2^32 - 1, so hi_s + 1 does not wrap
-            uint32_t b0 = lower_bound_u32(L.qadj, qb, qb + s, lo_s);
-            uint32_t b1 = lower_bound_u32(L.qadj, b0, qb + s, hi_s + 1);
-            st = b0;
-            s = b1 - b0;
-          }
+    // partners kOwnNT at a time; per chunk, the owner's set segment by
+    // segment (the table is built once when the set is one segment)
+    for (uint32_t c = plo; c < phi; c += kOwnNT) {
+      uint32_t i = c + tid;
+      uint32_t qb = 0, s_full = 0;
+      if (i < phi) {
+        uint32_t u = L.sadj[Sb + i];
+        qb = L.qrp[u];
+        s_full = L.qrp[u + 1] - qb;
+        if (!owned(r, s_full, D)) s_full = 0;
+        ext += s_full;
+      }
+      uint32_t cur = qb;  // first element of the proposing set not yet given to a segment
+      for (uint32_t seg = 0; seg < nseg; ++seg) {
+        uint32_t e0 = seg * kSegMax, e1 = min(D, e0 + kSegMax), cnt = e1 - e0;
+        // slots: power of two >= 8 * cnt (load <= 1/8) up to the table size
+        int lg = 6;
+        while ((1u << lg) < 8 * cnt && lg < kLogSlots) ++lg;
+        uint32_t slots = 1u << lg, mask = (slots >> 2) - 1;  // mask over buckets
+        int shift = 32 - (lg - 2);
+        if (nseg > 1 || c == plo) {
+          for (uint32_t k = tid; k < slots; k += kOwnNT) H[k] = kEmpty;
+          __syncthreads();
+          for (uint32_t k = tid; k < cnt; k += kOwnNT) insert(H, L.padj[Lb + e0 + k], shift, mask);
+          __syncthreads();
+        }
+        // this segment takes the proposing elements up to its largest value
+        // (those below its smallest are in no segment and simply miss)
+        uint32_t st = cur, s = 0;
+        if (s_full) {
+          uint32_t end = qb + s_full;
+          // vertex ids are below 2^32 - 1, so hi_s + 1 does not wrap
+          uint32_t b1 = seg + 1 == nseg ? end : gallop_lb(L.qadj, cur, end, L.padj[Lb + e1 - 1] + 1);
+          s = b1 - cur;
+          cur = b1;
         }
         // one scan: long-partner count in the high half, short sizes in the low half
         bool is_long = s >= kLong;
@@ -329,8 +336,11 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
           pval[kl] = s;
         } else {
           uint32_t j = nlong + ((uint32_t)tid - kl);
+          uint32_t off = pre & 0xFFFFu;
           pst[j] = st;
-          pval[j] = pre & 0xFFFFu;
+          pval[j] = off;
+          // the windows of 64 short elements that start inside this set
+          for (uint32_t w = (off + 63) >> 6; (w << 6) < off + s; ++w) wstart[w] = (uint16_t)j;
         }
         if (tid == 0) {
           pval[kOwnNT] = short_total;
@@ -354,14 +364,13 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
           else
             hits += stream_probe<4>(L.qadj + st_k, s_k, H, shift, mask);
         }
-        // short partners: 64-element windows over their concatenation
+        // short partners: 64-element windows over their concatenation; a
+        // lane starts from the set holding its window's first element
         for (uint32_t g0 = (uint32_t)wave * 64; g0 < short_total; g0 += nwaves * 64) {
-          uint32_t gl = min(g0 + 63, short_total - 1);
-          uint32_t pf = find_lds(pval, nlong, kOwnNT, g0);
-          uint32_t pl = find_lds(pval, pf, kOwnNT, gl);
           uint32_t g = g0 + lane;
           if (g < short_total) {
-            uint32_t p = find_lds(pval, pf, pl + 1, g);
+            uint32_t p = wstart[g0 >> 6];
+            while (pval[p + 1] <= g) ++p;
             uint32_t x = L.qadj[pst[p] + (g - pval[p])];
             hits += probe(H, x, shift, mask) ? 1 : 0;
           }
@@ -407,7 +416,7 @@ void owner_count(gj_ctx* c, const OwnerArgs& a, const uint32_t* seed_row, const 
   unsigned int* counter = (unsigned int*)ws_get(c, "own_ctr", sizeof(unsigned int));
   GJ_HIP(hipMemsetAsync(acc, 0, 2 * sizeof(unsigned long long), c->stream));
   GJ_HIP(hipMemsetAsync(counter, 0, sizeof(unsigned int), c->stream));
-  const uint64_t tw_min = 1ull << 17;
+  const uint64_t tw_min = 1ull << 20;
   uint32_t* vals = (uint32_t*)ws_get(c, "own_vals", (E + 1) * sizeof(uint32_t));
   uint64_t* wscan0 = (uint64_t*)ws_get(c, "own_ws0", (E + 1) * sizeof(uint64_t));
   uint64_t* wscan1 = (uint64_t*)ws_get(c, "own_ws1", (E + 1) * sizeof(uint64_t));
