@@ -71,6 +71,12 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   every query that asks for counts only as one fused
  *                   pipeline (as gj_run_batch, with signed seeds); 0 runs
  *                   each dQ_i on the depth-first path
+ *   "delta_owner_min"  gj_apply_updates: batches with at least this many
+ *                   distinct changes (default 2^17, >= 0) run the count-only
+ *                   delta queries of three-attribute queries whose every
+ *                   dQ_i binds the last attribute by one atom on each seed
+ *                   attribute (the triangle shapes) on the owner-grouped
+ *                   kernel, unless "strategy" is 1
  * Returns GJ_EINVAL for an unknown key or out-of-range value. */
 gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
 

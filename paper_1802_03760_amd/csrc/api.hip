@@ -168,6 +168,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "strategy") {
       GJ_CHECK(value >= 0 && value <= 2, GJ_EINVAL, "strategy out of range");
       c->strategy = (int)value;
+    } else if (k == "delta_owner_min") {
+      GJ_CHECK(value >= 0, GJ_EINVAL, "delta_owner_min must be >= 0");
+      c->delta_owner_min = (uint64_t)value;
     } else if (k == "delta_fused") {
       GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "delta_fused must be 0 or 1");
       c->delta_fused = (int)value;
@@ -198,6 +201,7 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "batch_waves_per_cu") *value = c->batch_waves_per_cu;
     else if (k == "batch_fallbacks") *value = (int64_t)c->batch_fallbacks;
     else if (k == "delta_fused") *value = c->delta_fused;
+    else if (k == "delta_owner_min") *value = (int64_t)c->delta_owner_min;
     else throw Error{GJ_EINVAL, "unknown option " + k};
   });
 }
@@ -447,6 +451,7 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->batch_waves_per_cu = src->batch_waves_per_cu;
   dst->batch_cap = src->batch_cap;
   dst->delta_fused = src->delta_fused;
+  dst->delta_owner_min = src->delta_owner_min;
 }
 
 }  // namespace gj

@@ -13,6 +13,7 @@
 #include "batch.h"
 #include "engine.h"
 #include "gj_internal.h"
+#include "owner.h"
 #include "prim.h"
 
 namespace gj {
@@ -301,15 +302,71 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   (void)ins_total;
   version_finish(c, nv, n, true);  // row pointers come from the update
   // ---- delta queries
+  std::vector<char> done(nq, 0);
+  // Count-only queries whose every dQ_i extends the seed edge by one attribute
+  // bound by one atom on each seed attribute (the triangle shapes): each dQ_i
+  // runs the owner-grouped kernel over the signed seeds, grouped by source
+  // (the forward delta rows) and by destination (the reverse ones), for
+  // batches with enough changes to pay for its planning over every vertex.
+  if (c->strategy != 1 && k >= c->delta_owner_min) {
+    const uint32_t* drp_f = (const uint32_t*)ws_get(c, "up_drpf", ((uint64_t)n + 1) * sizeof(uint32_t));
+    const uint32_t* drp_r = (const uint32_t*)ws_get(c, "up_drpr", ((uint64_t)n + 1) * sizeof(uint32_t));
+    for (uint32_t qi = 0; qi < nq; ++qi) {
+      bool want_rows = (out_rows && out_rows[qi]) || (out_signs && out_signs[qi]);
+      const gj_query* q = qs[qi];
+      if (want_rows || q->m != 3) continue;
+      std::vector<PlanH> plans;
+      bool ok = true;
+      for (int i = 0; i < (int)q->atoms.size() && ok; ++i) {
+        plans.push_back(make_plan(q, delta_order(q, i), i));
+        const PlanH& P = plans.back();
+        ok = P.filters.empty() && P.bind[2].size() == 2 && P.bind[2][0].col != P.bind[2][1].col;
+      }
+      if (!ok) continue;
+      gj_stats acc{};
+      int64_t cd = 0;
+      uint64_t raw = 0;
+      for (int i = 0; i < (int)plans.size(); ++i) {
+        const PlanH& P = plans[i];
+        Views V{&ov, &nv, i};
+        const BindH& A = P.bind[2][0].col == 0 ? P.bind[2][0] : P.bind[2][1];
+        const BindH& B = P.bind[2][0].col == 0 ? P.bind[2][1] : P.bind[2][0];
+        const Version& VA = V.of(A.atom);
+        const Version& VB = V.of(B.atom);
+        OwnerArgs oa{VA.d[A.dir].rp, VA.d[A.dir].col, VB.d[B.dir].rp, VB.d[B.dir].col, drp_f, ed, drp_r, rs,
+                     n, eg, rg};
+        KernelTimer timer(c);
+        uint64_t mt = 0, ex = 0;
+        int64_t ws = 0;
+        owner_count(c, oa, es, ed, rd, rs, k, timer, mt, ex, &ws);
+        acc.prefixes[2] += k;
+        acc.extensions[2] += ex;
+        acc.prefixes[3] += mt;
+        acc.kernel_ms += timer.total_ms();
+        acc.kernel_launches += timer.launches();
+        cd += ws;
+        raw += mt;
+      }
+      done[qi] = 1;
+      if (count_delta) count_delta[qi] = cd;
+      if (n_delta) n_delta[qi] = 0;
+      if (stats) {
+        acc.noop_inserts = hc[0];
+        acc.noop_deletes = hc[1];
+        acc.raw_emissions = raw;
+        acc.matches = raw;
+        stats[qi] = acc;
+      }
+    }
+  }
   // Queries that only need count deltas: every dQ_i of all of them runs as
   // one fused, graph-captured pipeline with signed seeds.
-  std::vector<char> done(nq, 0);
   if (c->delta_fused) {
     std::vector<gj::ReqSpec> specs;
     std::vector<uint32_t> owner;
     for (uint32_t qi = 0; qi < nq; ++qi) {
       bool want_rows = (out_rows && out_rows[qi]) || (out_signs && out_signs[qi]);
-      if (want_rows) continue;
+      if (want_rows || done[qi]) continue;
       const gj_query* q = qs[qi];
       for (int i = 0; i < (int)q->atoms.size(); ++i) {
         ReqSpec r{make_plan(q, delta_order(q, i), i), Views{&ov, &nv, i}};
@@ -333,6 +390,7 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
         std::vector<gj_stats> acc(nq);
         std::vector<int64_t> cd(nq, 0);
         std::vector<uint64_t> raw(nq, 0);
+        std::vector<char> fused(nq, 0);
         for (size_t x = 0; x < specs.size(); ++x) {
           uint32_t qi = owner[x];
           add_stats(acc[qi], sts[x]);
@@ -340,10 +398,11 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
           acc[qi].kernel_launches = 1;
           cd[qi] += ws[x];
           raw[qi] += cnts[x];
+          fused[qi] = 1;
           done[qi] = 1;
         }
         for (uint32_t qi = 0; qi < nq; ++qi) {
-          if (!done[qi]) continue;
+          if (!fused[qi]) continue;
           if (count_delta) count_delta[qi] = cd[qi];
           if (n_delta) n_delta[qi] = 0;
           if (stats) {

@@ -113,6 +113,7 @@ struct gj_ctx {
   uint64_t batch_cap = 1ull << 27;  // prefixes per level of the batched pipeline
   uint64_t batch_fallbacks = 0;     // batches rerun depth-first after a level overflow
   int delta_fused = 1;              // count-only delta queries through the fused pipeline
+  uint64_t delta_owner_min = 1ull << 17;  // changes from which triangle-shaped deltas use the owner kernel
 };
 
 // Resident versions of a graph: ver[cur] is current; an update reads it and

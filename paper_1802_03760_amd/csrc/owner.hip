@@ -263,6 +263,8 @@ __device__ __forceinline__ uint32_t stream_probe(const uint32_t* __restrict__ se
   return hits;
 }
 
+// SIGNED: seed edges carry signs (a.sg0, a.sg1), acc[2] gets the signed sum
+template <bool SIGNED>
 __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))) k_owner_count(OwnerArgs a, const uint32_t* __restrict__ tasks,
                                                         uint32_t ntask, unsigned int* __restrict__ counter,
                                                         const uint32_t* __restrict__ seed_row,
@@ -272,10 +274,12 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
   __shared__ uint32_t pst[kOwnNT];       // start of each partner's proposing set
   __shared__ uint32_t pval[kOwnNT + 1];  // long: size; short: offset in the short space
   __shared__ uint16_t wstart[kOwnNT];    // short window -> set holding its first element
+  __shared__ int8_t psg[kOwnNT];         // sign of each partner's seed edge
   __shared__ uint32_t s_task, s_long;
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   constexpr int nwaves = kOwnNT / 64;
   uint64_t hits = 0, ext = 0;
+  int64_t shits = 0;  // hits times the sign of their seed edge
 
   for (;;) {
     if (tid == 0) s_task = atomicAdd(counter, 1u);
@@ -294,7 +298,9 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
     for (uint32_t c = plo; c < phi; c += kOwnNT) {
       uint32_t i = c + tid;
       uint32_t qb = 0, s_full = 0;
+      int8_t sg = 1;
       if (i < phi) {
+        if (SIGNED) sg = (r ? a.sg1 : a.sg0)[Sb + i];
         uint32_t u = L.sadj[Sb + i];
         qb = L.qrp[u];
         s_full = L.qrp[u + 1] - qb;
@@ -334,11 +340,13 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
         if (is_long) {
           pst[kl] = st;
           pval[kl] = s;
+          if (SIGNED) psg[kl] = sg;
         } else {
           uint32_t j = nlong + ((uint32_t)tid - kl);
           uint32_t off = pre & 0xFFFFu;
           pst[j] = st;
           pval[j] = off;
+          if (SIGNED) psg[j] = sg;
           // the windows of 64 short elements that start inside this set
           for (uint32_t w = (off + 63) >> 6; (w << 6) < off + s; ++w) wstart[w] = (uint16_t)j;
         }
@@ -357,12 +365,15 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
           uint32_t st_k = __builtin_amdgcn_readfirstlane(pst[k]);
           uint32_t s_k = __builtin_amdgcn_readfirstlane(pval[k]);
           // loads per step by set size: fewer wasted lanes on short sets
+          uint32_t h;
           if (s_k <= 128)
-            hits += stream_probe<2>(L.qadj + st_k, s_k, H, shift, mask);
+            h = stream_probe<2>(L.qadj + st_k, s_k, H, shift, mask);
           else if (s_k <= 192)
-            hits += stream_probe<3>(L.qadj + st_k, s_k, H, shift, mask);
+            h = stream_probe<3>(L.qadj + st_k, s_k, H, shift, mask);
           else
-            hits += stream_probe<4>(L.qadj + st_k, s_k, H, shift, mask);
+            h = stream_probe<4>(L.qadj + st_k, s_k, H, shift, mask);
+          hits += h;
+          if (SIGNED) shits += (int64_t)psg[k] * h;
         }
         // short partners: 64-element windows over their concatenation; a
         // lane starts from the set holding its window's first element
@@ -372,7 +383,9 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
             uint32_t p = wstart[g0 >> 6];
             while (pval[p + 1] <= g) ++p;
             uint32_t x = L.qadj[pst[p] + (g - pval[p])];
-            hits += probe(H, x, shift, mask) ? 1 : 0;
+            bool hit = probe(H, x, shift, mask);
+            hits += hit ? 1 : 0;
+            if (SIGNED) shits += hit ? psg[p] : 0;
           }
         }
         __syncthreads();
@@ -388,13 +401,15 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
     uint32_t lb = a.rpB[x1], db = a.rpB[x1 + 1] - lb;
     if ((da > db ? da : db) >= kDMin) continue;
     ext += da < db ? da : db;
-    uint32_t i = 0, j = 0;
+    uint32_t i = 0, j = 0, eh = 0;
     while (i < da && j < db) {
       uint32_t p = a.adjA[la + i], q = a.adjB[lb + j];
-      hits += p == q ? 1 : 0;
+      eh += p == q ? 1 : 0;
       i += p <= q ? 1 : 0;
       j += q <= p ? 1 : 0;
     }
+    hits += eh;
+    if (SIGNED) shits += (int64_t)a.sg0[e] * eh;
   }
 
   uint64_t th = block_sum<kOwnNT>(hits);
@@ -403,18 +418,22 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
     atomicAdd(acc, (unsigned long long)th);
     atomicAdd(acc + 1, (unsigned long long)te);
   }
+  if (SIGNED) {
+    uint64_t ts = block_sum<kOwnNT>((uint64_t)shits);  // two's complement: the signed sum
+    if (tid == 0) atomicAdd(acc + 2, (unsigned long long)ts);
+  }
 }
 
 // ---------------------------------------------------------------- host
 void owner_count(gj_ctx* c, const OwnerArgs& a, const uint32_t* seed_row, const uint32_t* seed_col,
                  const uint32_t* t_row, const uint32_t* t_col, uint64_t E, KernelTimer& timer, uint64_t& matches,
-                 uint64_t& extensions) {
+                 uint64_t& extensions, int64_t* wsum) {
   uint64_t units = 2ull * a.n;
   uint32_t* ntasks = (uint32_t*)ws_get(c, "own_nt", (units + 1) * sizeof(uint32_t));
   uint64_t* toff = (uint64_t*)ws_get(c, "own_toff", (units + 1) * sizeof(uint64_t));
-  unsigned long long* acc = (unsigned long long*)ws_get(c, "own_acc", 2 * sizeof(unsigned long long));
+  unsigned long long* acc = (unsigned long long*)ws_get(c, "own_acc", 3 * sizeof(unsigned long long));
   unsigned int* counter = (unsigned int*)ws_get(c, "own_ctr", sizeof(unsigned int));
-  GJ_HIP(hipMemsetAsync(acc, 0, 2 * sizeof(unsigned long long), c->stream));
+  GJ_HIP(hipMemsetAsync(acc, 0, 3 * sizeof(unsigned long long), c->stream));
   GJ_HIP(hipMemsetAsync(counter, 0, sizeof(unsigned int), c->stream));
   const uint64_t tw_min = 1ull << 20;
   uint32_t* vals = (uint32_t*)ws_get(c, "own_vals", (E + 1) * sizeof(uint32_t));
@@ -434,13 +453,18 @@ void owner_count(gj_ctx* c, const OwnerArgs& a, const uint32_t* seed_row, const 
   GJ_HIP(hipGetLastError());
   unsigned grid = (unsigned)c->num_cus * 2;
   timer.start();
-  k_owner_count<<<grid, kOwnNT, 0, c->stream>>>(a, tasks, (uint32_t)nt, counter, seed_row, seed_col, E, acc);
+  GJ_CHECK((a.sg0 == nullptr) == (a.sg1 == nullptr), GJ_EINVAL, "owner kernel: signs for one order only");
+  if (a.sg0)
+    k_owner_count<true><<<grid, kOwnNT, 0, c->stream>>>(a, tasks, (uint32_t)nt, counter, seed_row, seed_col, E, acc);
+  else
+    k_owner_count<false><<<grid, kOwnNT, 0, c->stream>>>(a, tasks, (uint32_t)nt, counter, seed_row, seed_col, E, acc);
   timer.stop();
   GJ_HIP(hipGetLastError());
-  unsigned long long h[2];
+  unsigned long long h[3];
   read_bytes(c, h, acc, sizeof(h));
   matches = h[0];
   extensions = h[1];
+  if (wsum) *wsum = a.sg0 ? (int64_t)h[2] : (int64_t)h[0];
 }
 
 }  // namespace gj

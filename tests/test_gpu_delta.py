@@ -199,3 +199,36 @@ def test_fused_delta_equals_depth_first(gj):
                 assert a["stats"][key] == b["stats"][key] == (ref[key] if key in ref else b["stats"][key]), key
         oracle.delta(O, bs, bd, bg)
     assert cf.get_option("batch_fallbacks") == 0
+
+
+def test_owner_delta_equals_depth_first(gj):
+    """Count-only deltas of the triangle shapes through the owner-grouped
+    kernel (forced for every batch size) equal the depth-first path and the
+    oracle, counters included; other queries in the same call take the fused
+    pipeline."""
+    scale = 11
+    src, dst = synth.rmat_draws(scale, seed=14)
+    n = 1 << scale
+    co = gj.Context(0)
+    co.set_option("delta_owner_min", 1)
+    assert co.get_option("delta_owner_min") == 1
+    cp = gj.Context(0)
+    cp.set_option("delta_fused", 0)
+    Go, Gp = gj.Graph(co, src, dst, n), gj.Graph(cp, src, dst, n)
+    names = ["triangle", "cyclic_triangle", "diamond", "clique4"]
+    qo = [gj.Query(co, *Q.ALL[k]) for k in names]
+    qp = [gj.Query(cp, *Q.ALL[k]) for k in names]
+    O = oracle.Graph(n, src, dst)
+    for k, bs, bd, bg in synth.update_stream(scale, 14, 15, 6, 1, 4000):
+        ro = gj.apply_updates(co, Go, bs, bd, bg, qo)
+        rp = gj.apply_updates(cp, Gp, bs, bd, bg, qp)
+        for name, a, b in zip(names, ro, rp):
+            ref = oracle.delta(O.copy(), bs, bd, bg, Q.ALL[name])
+            assert a["count_delta"] == b["count_delta"] == ref["count_delta"], name
+            for key in ("raw_emissions", "prefixes", "extensions", "noop_inserts", "noop_deletes"):
+                assert a["stats"][key] == b["stats"][key], (name, key)
+            if name in ("triangle", "cyclic_triangle") and a["stats"]["raw_emissions"]:
+                assert a["stats"]["kernel_launches"] == 3  # one owner launch per dQ_i
+        oracle.delta(O, bs, bd, bg)
+    with pytest.raises(gj.GJError):
+        co.set_option("delta_owner_min", -1)
