@@ -24,7 +24,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one k_owner_count launch on this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB device copy in the same
 # run; valid only for the kernel source it was measured on (sha256 prefix).
-MEASURED_TRAFFIC = {"owner.hip": "7ba31d338846310c", "bytes": 126.47e9 + 1.010e9}
+MEASURED_TRAFFIC = {"owner.hip": "acc8f2abfea5e5bd", "bytes": 127.05e9 + 1.089e9}
 TRIANGLE = (3, [(0, 1), (1, 2), (0, 2)], [0, 1, 2])
 
 
@@ -153,13 +153,14 @@ def synth_stream(scale, nbatch, lo, hi):
     return synth.update_stream(scale, 0, 1, nbatch, lo, hi)
 
 
-def mixed_serving(gj, src, dst, n, scale, nreq, seed, log):
+def mixed_serving(gj, src, dst, n, scale, nreq, seed, log, max_width=1000, max_update=100000, skip=0.0):
     """Mixed served workload: nreq requests arriving by Poisson, each a seed-slice
     count (triangle, 4-cycle, diamond or 4-clique; widths log-uniform in
-    [1, 1000]) or an update batch (log-uniform in [10, 100,000] edges).  The
-    arrival rate is 70% of the plain path's capacity (measured first).  Plain:
-    one request at a time in arrival order; served: the server.  Latency =
-    arrival to result."""
+    [1, max_width], starting uniformly in the edge range past its first
+    `skip` fraction) or an update batch (log-uniform in [10, max_update]
+    edges).  The arrival rate is 70% of the plain path's capacity (measured
+    first).  Plain: one request at a time in arrival order; served: the
+    server.  Latency = arrival to result."""
     import numpy as np
     import synth
     rng = np.random.default_rng(seed)
@@ -172,18 +173,22 @@ def mixed_serving(gj, src, dst, n, scale, nreq, seed, log):
     for i in range(nreq):
         kind = names[int(rng.integers(0, len(names)))]
         if kind == "update":
-            size = synth.batch_size(3, k_upd, 10, 100000)
+            size = synth.batch_size(3, k_upd, 10, max_update)
             bs, bd, bg = synth.update_batch(scale, 0, 16 << scale, 3, k_upd, size)
             k_upd += 1
             plan.append(("update", bs, bd, bg))
         else:
-            plan.append((kind, float(rng.random()), int(np.exp(rng.uniform(0, np.log(1000))))))
+            plan.append((kind, skip + (1.0 - skip) * float(rng.random()),
+                         int(np.exp(rng.uniform(0, np.log(max_width))))))
+
+    edges_seen = []
 
     def run(mode, arrivals):
         ctx = gj.Context(0)
         ctx.set_option("delta_fused", 0 if mode == "plain" else 1)
         G = gj.Graph(ctx, src, dst, n)
         E = G.info()["edges"]
+        edges_seen.append(E)
         qs = {k: gj.Query(ctx, *v) for k, v in kinds.items()}
         srv = gj.Server(ctx, G, max_batch=16) if mode == "served" else None
         lat, res, tickets, ext, kinds_done = [], [], [], 0, []
@@ -238,7 +243,8 @@ def mixed_serving(gj, src, dst, n, scale, nreq, seed, log):
         x = lat[kinds == kind]
         return {"p50_ms": float(np.percentile(x, 50)), "p99_ms": float(np.percentile(x, 99)), "n": int(len(x))}
     assert res_p == res_s == res_p0 == res_c
-    out = {"requests": nreq, "arrival_rate_per_s": rate, "graph_scale": scale,
+    out = {"requests": nreq, "arrival_rate_per_s": rate, "graph_scale": scale, "graph_edges": int(edges_seen[0]),
+           "max_slice_width": max_width, "max_update_edges": max_update, "skipped_head_fraction": skip,
            "mix": "uniform over triangle / 4-cycle / diamond / 4-clique seed-slice counts and update batches",
            "capacity": {"plain_req_per_s": nreq / span0, "served_req_per_s": nreq / span_c,
                         "plain_count_ext_per_s": ext / span0, "served_count_ext_per_s": ext / span_c},
@@ -272,6 +278,12 @@ def main():
     ap.add_argument("--strategy", type=int, default=0)
     ap.add_argument("--batch-requests", type=int, default=64)
     ap.add_argument("--serve-requests", type=int, default=256)
+    ap.add_argument("--serve-scale", type=int, default=0,
+                    help="R-MAT scale of the serving leg's graph (0: --scale)")
+    ap.add_argument("--serve-max-width", type=int, default=1000)
+    ap.add_argument("--serve-max-update", type=int, default=100000)
+    ap.add_argument("--serve-skip", type=float, default=0.0,
+                    help="fraction of the edge range (the hub rows) where no count slice starts")
     ap.add_argument("--latency-batches", type=int, default=200)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of known "
@@ -350,7 +362,15 @@ def main():
         latency = update_latency(gj, src, dst, n, args.scale, args.latency_batches, log)
     serving = None
     if args.serve_requests:
-        serving = mixed_serving(gj, src, dst, n, args.scale, args.serve_requests, 5, log)
+        ss = args.serve_scale or args.scale
+        if ss == args.scale:
+            s_src, s_dst = src, dst
+        else:
+            s_src, s_dst = synth.rmat_draws(ss, seed=0)
+            log("serving graph: R-MAT scale %d, %d draws" % (ss, len(s_src)))
+        serving = mixed_serving(gj, s_src, s_dst, 1 << ss, ss, args.serve_requests, 5, log,
+                                args.serve_max_width, args.serve_max_update, args.serve_skip)
+        del s_src, s_dst
 
     # delta-batch latency: update stream on the same graph
     lat = []

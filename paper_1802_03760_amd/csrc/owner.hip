@@ -393,23 +393,65 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
     }
   }
 
-  // edges whose larger set is small: per-edge merge
-  uint64_t gs = (uint64_t)gridDim.x * kOwnNT;
-  for (uint64_t e = (uint64_t)blockIdx.x * kOwnNT + tid; e < E; e += gs) {
-    uint32_t x0 = seed_row[e], x1 = seed_col[e];
-    uint32_t la = a.rpA[x0], da = a.rpA[x0 + 1] - la;
-    uint32_t lb = a.rpB[x1], db = a.rpB[x1 + 1] - lb;
-    if ((da > db ? da : db) >= kDMin) continue;
-    ext += da < db ? da : db;
-    uint32_t i = 0, j = 0, eh = 0;
-    while (i < da && j < db) {
-      uint32_t p = a.adjA[la + i], q = a.adjB[lb + j];
-      eh += p == q ? 1 : 0;
-      i += p <= q ? 1 : 0;
-      j += q <= p ? 1 : 0;
+  // Edges whose larger set is small (below kDMin = 64 values): each wave
+  // scans 64 seed edges at a time, and the small ones among them are
+  // intersected by the whole wave, up to four at once: each set in one
+  // coalesced load, then every value of LA(x0) looked up among the values of
+  // LB(x1) held in registers, through shuffles.
+  for (uint64_t e0 = ((uint64_t)blockIdx.x * nwaves + wave) * 64; e0 < E;
+       e0 += (uint64_t)gridDim.x * nwaves * 64) {
+    uint64_t e = e0 + lane;
+    uint32_t la = 0, da = 0, lb = 0, db = 0;
+    bool small = false;
+    if (e < E) {
+      uint32_t x0 = seed_row[e], x1 = seed_col[e];
+      la = a.rpA[x0];
+      da = a.rpA[x0 + 1] - la;
+      lb = a.rpB[x1];
+      db = a.rpB[x1 + 1] - lb;
+      small = (da > db ? da : db) < kDMin;
     }
-    hits += eh;
-    if (SIGNED) shits += (int64_t)a.sg0[e] * eh;
+    if (small) ext += da < db ? da : db;
+    uint64_t m = __ballot(small);
+    while (m) {
+      constexpr int kG = 4;
+      int src[kG];
+#pragma unroll
+      for (int t = 0; t < kG; ++t) {
+        src[t] = m ? __ffsll((unsigned long long)m) - 1 : -1;
+        m &= m ? m - 1 : 0;
+      }
+      uint32_t va[kG], vb[kG], na[kG];
+#pragma unroll
+      for (int t = 0; t < kG; ++t) {
+        va[t] = vb[t] = 0xFFFFFFFFu;
+        na[t] = 0;
+        if (src[t] >= 0) {
+          uint32_t lat = __shfl(la, src[t], 64), dat = __shfl(da, src[t], 64);
+          uint32_t lbt = __shfl(lb, src[t], 64), dbt = __shfl(db, src[t], 64);
+          na[t] = dat;
+          if ((uint32_t)lane < dat) va[t] = a.adjA[lat + lane];
+          if ((uint32_t)lane < dbt) vb[t] = a.adjB[lbt + lane];
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < kG; ++t) {
+        if (src[t] < 0) continue;
+        // pos = number of (padded) values of LB below va, at most 63
+        uint32_t pos = 0;
+#pragma unroll
+        for (uint32_t step = 32; step >= 1; step >>= 1) {
+          uint32_t y = (uint32_t)__shfl((int)vb[t], (int)(pos + step - 1), 64);
+          if (y < va[t]) pos += step;
+        }
+        uint32_t at = (uint32_t)__shfl((int)vb[t], (int)pos, 64);
+        uint32_t eh = (uint32_t)__popcll(__ballot((uint32_t)lane < na[t] && at == va[t]));
+        if (lane == 0) {
+          hits += eh;
+          if (SIGNED) shits += (int64_t)a.sg0[e0 + src[t]] * eh;
+        }
+      }
+    }
   }
 
   uint64_t th = block_sum<kOwnNT>(hits);
