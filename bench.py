@@ -191,6 +191,11 @@ def mixed_serving(gj, src, dst, n, scale, nreq, seed, log, max_width=1000, max_u
         edges_seen.append(E)
         qs = {k: gj.Query(ctx, *v) for k, v in kinds.items()}
         srv = gj.Server(ctx, G, max_batch=16) if mode == "served" else None
+        if srv is not None:
+            # start-up outside the timed region (as the index build): its
+            # streams and spare versions, through an empty update batch
+            e = np.zeros(0, np.uint32)
+            srv.wait(srv.submit_update(e, e, np.zeros(0, np.int8), []))
         lat, res, tickets, ext, kinds_done = [], [], [], 0, []
         t0 = time.perf_counter()
         for i, req in enumerate(plan):
@@ -232,12 +237,16 @@ def mixed_serving(gj, src, dst, n, scale, nreq, seed, log, max_width=1000, max_u
 
     # capacity of the plain path: back-to-back, then arrivals at 70% of it
     res_p0, _, span0, ext, _, _ = run("plain", None)
+    log("  serving: plain back-to-back %.0f ms" % (span0 * 1e3))
     rate = 0.7 * nreq / span0
     arrivals = np.cumsum(rng.exponential(1.0 / rate, nreq))
     res_p, lat_p, span_p, _, _, kind_p = run("plain", arrivals)
+    log("  serving: plain at %.0f/s done" % rate)
     res_s, lat_s, span_s, _, st, kind_s = run("served", arrivals)
+    log("  serving: served at %.0f/s done" % rate)
     # capacity: every request submitted at once (served) against back-to-back (plain)
     res_c, _, span_c, _, _, _ = run("served", None)
+    log("  serving: served all at once %.0f ms" % (span_c * 1e3))
 
     def pct(lat, kinds, kind):
         x = lat[kinds == kind]

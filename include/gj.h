@@ -250,8 +250,8 @@ gj_status gj_autotune(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_qu
  * extensions (0, the default: 4 x iteration_work) that the heavy lanes run
  * concurrently on the depth-first path, each lane taking the oldest heavy
  * request no other lane is running.  Requests whose version an update waits
- * for go first; with "update_priority" (default 1) no new count iteration or
- * chunk starts while an update batch is on the device.  With iteration_work
+ * for go first; with "update_priority" (default 1) no new heavy chunk starts
+ * while an update batch is on the device (light iterations go on).  With iteration_work
  * 0 requests run whole, in arrival order, in the fused pipeline.  Results
  * equal gj_run / gj_apply_updates issued alone in submission order.
  * gj_server_create returns GJ_EDEVICE / GJ_ENOMEM if the light context or

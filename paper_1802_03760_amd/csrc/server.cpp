@@ -23,8 +23,9 @@
 // other lane is running; so light requests never wait behind heavy ones and
 // a heavy request can pass a heavier one.  Requests whose version slot an
 // update waits for go first.  While an update batch is on the device no new
-// iteration or chunk starts (update priority).  With a budget of zero,
-// requests run whole, in arrival order, up to max_batch per iteration.
+// heavy chunk starts (update priority); light iterations go on.  With a
+// budget of zero, requests run whole, in arrival order, up to max_batch per
+// iteration.
 #include <algorithm>
 #include <chrono>
 #include <condition_variable>
@@ -131,7 +132,7 @@ struct gj_server {
   std::map<uint64_t, uint32_t> pending;  // states of queued and admitted counts
   int want = -1;                          // slot an update waits for
   bool updating = false;                  // an update batch is on the device
-  bool update_priority = true;            // no new count iteration meanwhile
+  bool update_priority = true;            // no new heavy chunk meanwhile
   std::vector<double> lat_count, lat_update;
   uint64_t batches = 0, batched = 0;
 };
@@ -369,8 +370,10 @@ static void count_loop(gj_server* s) {
     uint64_t mem_budget;
     {
       std::unique_lock<std::mutex> lk(s->mu);
+      // (light iterations keep running while an update is on the device:
+      // they are short, and holding them would put every count behind
+      // every update)
       s->cv_count.wait(lk, [&] {
-        if (s->updating && s->update_priority) return false;  // updates first
         return !active.empty() || (s->stop && s->counts.empty()) ||
                (!s->counts.empty() && s->counts.front().state <= s->applied);
       });
