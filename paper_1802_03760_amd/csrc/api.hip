@@ -439,7 +439,16 @@ gj_status update_into(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_
 gj_status reserve_version(gj_ctx* c, gj_graph* g, int b, uint64_t cap) {
   return guarded(c, [&] {
     GJ_CHECK(b >= 0 && b < kMaxVersions && b != g->cur, GJ_EINVAL, "bad version slot");
-    version_alloc(g->ver[b], g->n, cap);
+    Version& v = g->ver[b];
+    version_alloc(v, g->n, cap);
+    // write the slot once now (a fill kernel), so that whatever the first
+    // access to fresh device memory costs is paid here, not by an update
+    for (int d = 0; d < 2; ++d) {
+      GJ_HIP(hipMemsetAsync(v.d[d].rp, 0, ((uint64_t)g->n + 1) * sizeof(uint32_t), c->stream));
+      GJ_HIP(hipMemsetAsync(v.d[d].col, 0, v.cap * sizeof(uint32_t), c->stream));
+      GJ_HIP(hipMemsetAsync(v.d[d].row, 0, v.cap * sizeof(uint32_t), c->stream));
+    }
+    GJ_HIP(hipStreamSynchronize(c->stream));
   });
 }
 

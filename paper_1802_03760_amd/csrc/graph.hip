@@ -154,7 +154,9 @@ void graph_build(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32_t* 
   scan_u32_to_u64(c, flags, off, m);
   uint64_t mu = read_u64(c, off + m);
   Version& v = g->ver[g->cur];
-  version_alloc(v, n, mu);
+  // the same growth room as the versions updates write, so that no slot is
+  // reallocated when updates come back round to it
+  version_alloc(v, n, mu + mu / 16 + (1ull << 20));
   v.m = mu;
   if (m) k_compact_edges<<<gr, kBlock, 0, c->stream>>>(sorted, m, flags, off, v.d[0].row, v.d[0].col, other);
   uint64_t* other_alt = sorted;  // free for reuse now
