@@ -47,7 +47,8 @@ typedef struct gj_query gj_query;
  * issue work on (NULL: the library creates its own).  Internal buffers are
  * device allocations owned by the context and reused across calls. */
 gj_status gj_ctx_create(int device, void* hip_stream, gj_ctx** out);
-/* Releases the context.  Graphs built on it must be destroyed first. */
+/* Releases the context.  Servers and graphs built on it must be destroyed
+ * first: gj_graph_destroy waits on the context's stream. */
 void gj_ctx_destroy(gj_ctx* ctx);
 
 /* Message of the last failed call on `ctx`; owned by ctx, valid until the
@@ -111,6 +112,8 @@ gj_status gj_graph_info(const gj_graph* g, uint64_t* edges, uint32_t* vertices,
 gj_status gj_graph_csr(const gj_graph* g, int reverse, const uint32_t** row_ptr,
                        const uint32_t** col, const uint32_t** row);
 
+/* Waits for the context's stream, then frees every version.  Before the
+ * context is destroyed, and after any server on the graph. */
 void gj_graph_destroy(gj_graph* g);
 
 /* ---------------------------------------------------------------- queries */
@@ -301,8 +304,9 @@ gj_status gj_server_submit_update(gj_server* s, const uint32_t* src, const uint3
  * result is returned once. */
 gj_status gj_server_wait(gj_server* s, uint64_t ticket, int64_t timeout_ms, gj_server_result* out);
 gj_status gj_server_get_stats(gj_server* s, gj_server_stats* out);
-/* Serves everything queued, then stops the workers and frees the second
- * context. */
+/* Serves everything queued, then stops the workers and frees the server's
+ * own contexts.  Before its context, its graph or a query of its requests is
+ * destroyed. */
 void gj_server_destroy(gj_server* s);
 
 /* Copies the consolidated delta rows of query number q (its position in the

@@ -7,7 +7,6 @@ this package fails loudly when the library has not been built.
 import atexit
 import ctypes
 import os
-import weakref
 
 import numpy as np
 
@@ -137,23 +136,75 @@ _lib.gj_autotune.argtypes = [_vp, _vp, _u32, ctypes.POINTER(_vp), _vp, _vp, ctyp
 _lib.gj_autotune.restype = _i32
 
 
-# Live handles, released in dependency order (queries, graphs, contexts) at
-# interpreter exit while the HIP runtime is still fully up; afterwards the
-# finalisers do nothing.
-_live = weakref.WeakSet()
+class _Handle:
+    """A library handle plus the handles that must be released before it.
+
+    The records live apart from the Python objects that own them and hold
+    their dependants strongly, so a handle is never destroyed before what
+    was built on it, whatever order finalisers run in.  (When the garbage
+    collector frees a reference cycle it clears weak references first and
+    then calls __del__ in no particular order.)"""
+
+    __slots__ = ("h", "destroy", "deps", "parents")
+
+    def __init__(self, h, destroy, parents=()):
+        self.h, self.destroy, self.deps, self.parents = h, destroy, {}, []
+        for p in parents:
+            self.depend(p)
+
+    def depend(self, parent):
+        """Release self before parent."""
+        if parent.h is not None and id(self) not in parent.deps:
+            parent.deps[id(self)] = self
+            self.parents.append(parent)
+
+    def close(self):
+        if self.h is None:
+            return
+        for d in list(self.deps.values()):
+            d.close()
+        h, self.h = self.h, None
+        self.destroy(h)
+        for p in self.parents:
+            p.deps.pop(id(self), None)
+        self.parents = []
+
+
+# Context handles still open; at interpreter exit each is released, with
+# everything built on it, while the HIP runtime is still fully up.
+# Afterwards the finalisers do nothing.
+_roots = {}
 _finalised = False
 
 
 def _release_all():
     global _finalised
-    for kind in (Server, Query, Graph, Context):
-        for obj in list(_live):
-            if isinstance(obj, kind):
-                obj.close()
+    for hd in list(_roots.values()):
+        hd.close()
+    _roots.clear()
     _finalised = True
 
 
 atexit.register(_release_all)
+
+
+class _Owner:
+    """Base of the handle-owning wrappers: close() releases the handle and
+    everything that depends on it; __del__ does the same until exit."""
+
+    _hd = None
+
+    @property
+    def _h(self):
+        return self._hd.h if self._hd is not None else None
+
+    def close(self):
+        if self._hd is not None:
+            self._hd.close()
+
+    def __del__(self):
+        if not _finalised:
+            self.close()
 
 
 class GJError(RuntimeError):
@@ -179,7 +230,7 @@ def _ptr(x):
     return _np_ptr(x)
 
 
-class Context:
+class Context(_Owner):
     """gj_ctx on one HIP device; issues work on `stream` (a torch.cuda.Stream,
     a raw hipStream_t int, or None for the library's own stream)."""
 
@@ -191,10 +242,9 @@ class Context:
         st = _lib.gj_ctx_create(device, _vp(raw) if raw else None, ctypes.byref(h))
         if st != GJ_OK:
             raise GJError(st, "gj_ctx_create(device=%d) failed" % device)
-        self._h = h
+        self._hd = _Handle(h, _lib.gj_ctx_destroy)
         self.device = device
-        self._children = weakref.WeakSet()
-        _live.add(self)
+        _roots[id(self._hd)] = self._hd
 
     def check(self, st, what):
         if st != GJ_OK:
@@ -209,21 +259,14 @@ class Context:
         return v.value
 
     def close(self):
-        """Destroys the context and every graph and query created on it."""
-        if getattr(self, "_h", None):
-            for kind in (Server, Query, Graph):
-                for obj in list(self._children):
-                    if isinstance(obj, kind):
-                        obj.close()
-            _lib.gj_ctx_destroy(self._h)
-            self._h = None
-
-    def __del__(self):
-        if not _finalised:
-            self.close()
+        """Destroys the context and every server, graph and query created on it."""
+        hd = self._hd
+        if hd is not None:
+            hd.close()
+            _roots.pop(id(hd), None)
 
 
-class Graph:
+class Graph(_Owner):
     """Forward and reverse CSR indexes of an edge list (gj_graph_build)."""
 
     def __init__(self, ctx, src, dst, num_vertices):
@@ -238,9 +281,7 @@ class Graph:
             flags, m = 0, len(src)
         ctx.check(_lib.gj_graph_build(ctx._h, _ptr(src), _ptr(dst), m, num_vertices, flags,
                                       ctypes.byref(h)), "gj_graph_build")
-        self._h = h
-        ctx._children.add(self)
-        _live.add(self)
+        self._hd = _Handle(h, _lib.gj_graph_destroy, (ctx._hd,))
 
     def info(self):
         e, n, mo, mi, v = _u64(), _u32(), _u32(), _u32(), _u64()
@@ -255,17 +296,9 @@ class Graph:
                                          ctypes.byref(row)), "gj_graph_csr")
         return rp.value, col.value, row.value
 
-    def close(self):
-        if getattr(self, "_h", None):
-            _lib.gj_graph_destroy(self._h)
-            self._h = None
-
-    def __del__(self):
-        if not _finalised:
-            self.close()
 
 
-class Query:
+class Query(_Owner):
     """Q(a_0..a_{m-1}) := edge(s, d), ... with a global order (gj_query_register)."""
 
     def __init__(self, ctx, num_attrs, atoms, order=None):
@@ -278,18 +311,7 @@ class Query:
         h = _vp()
         ctx.check(_lib.gj_query_register(ctx._h, num_attrs, arr, len(self.atoms), _np_ptr(o),
                                          ctypes.byref(h)), "gj_query_register")
-        self._h = h
-        ctx._children.add(self)
-        _live.add(self)
-
-    def close(self):
-        if getattr(self, "_h", None):
-            _lib.gj_query_destroy(self._h)
-            self._h = None
-
-    def __del__(self):
-        if not _finalised:
-            self.close()
+        self._hd = _Handle(h, _lib.gj_query_destroy, (ctx._hd,))
 
 
 def count(ctx, graph, query, seed_lo=0, seed_hi=(1 << 64) - 1):
@@ -299,7 +321,7 @@ def count(ctx, graph, query, seed_lo=0, seed_hi=(1 << 64) - 1):
     return st.as_dict()
 
 
-class Server:
+class Server(_Owner):
     """Request server over a context and a graph (gj_server_*): its worker
     threads own both until close().  iteration_work, versions: server options
     (None keeps the library default)."""
@@ -310,10 +332,9 @@ class Server:
         st = _lib.gj_server_create(ctx._h, graph._h, max_batch, mem_budget_bytes, ctypes.byref(h))
         if st != GJ_OK:
             raise GJError(st, "gj_server_create")
-        self._h = h
+        # Released before the context, the graph and every query it was sent.
+        self._hd = _Handle(h, _lib.gj_server_destroy, (ctx._hd, graph._hd))
         self._keep = {}  # queries referenced by queued requests
-        ctx._children.add(self)
-        _live.add(self)
         if iteration_work is not None:
             self.set_option("iteration_work", iteration_work)
         if versions is not None:
@@ -329,6 +350,7 @@ class Server:
         st = _lib.gj_server_submit_count(self._h, query._h, seed_lo, seed_hi, ctypes.byref(t))
         if st != GJ_OK:
             raise GJError(st, "gj_server_submit_count")
+        self._hd.depend(query._hd)
         self._keep[t.value] = query
         return t.value
 
@@ -342,6 +364,8 @@ class Server:
                                           len(queries), ctypes.byref(t))
         if st != GJ_OK:
             raise GJError(st, "gj_server_submit_update")
+        for q in queries:
+            self._hd.depend(q._hd)
         self._keep[t.value] = list(queries)
         return t.value
 
@@ -361,14 +385,6 @@ class Server:
         _lib.gj_server_get_stats(self._h, ctypes.byref(s))
         return {f: getattr(s, f) for f, _ in ServerStats._fields_}
 
-    def close(self):
-        if getattr(self, "_h", None):
-            _lib.gj_server_destroy(self._h)
-            self._h = None
-
-    def __del__(self):
-        if not _finalised:
-            self.close()
 
 
 def _requests(requests):
