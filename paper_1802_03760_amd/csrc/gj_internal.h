@@ -174,7 +174,10 @@ void scan_u32(gj_ctx* c, const uint32_t* in, uint32_t* out, uint64_t n);
 
 // sort.hip: stable LSD radix sorts; return the buffer holding the result
 uint64_t* sort_u64(gj_ctx* c, uint64_t* keys, uint64_t* alt, uint64_t n, int lo_bits, int hi_bits);
-// sorts (key, val) pairs by key (stable); key/val and alt buffers swap
+// sorts (key, val) pairs by key; key/val and alt buffers swap.  Equal keys
+// keep their input order above 2048 pairs and are ordered by val below (one
+// workgroup sorts those), so callers must not rely on the order among equal
+// keys.
 void sort_kv_u64(gj_ctx* c, uint64_t*& key, uint32_t*& val, uint64_t*& key_alt, uint32_t*& val_alt,
                  uint64_t n, int lo_bits, int hi_bits);
 void sort_kv_u32(gj_ctx* c, uint32_t*& key, uint32_t*& val, uint32_t*& key_alt,

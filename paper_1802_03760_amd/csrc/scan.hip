@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(kBlock) k_scan_down(const Tin* __restrict__ in
     s += loc[i];
   }
   Tout total;
-  Tout run = block_excl_scan<kBlock, Tout>(s, total) + part_off[blockIdx.x];
+  Tout run = block_excl_scan<kBlock, Tout>(s, total) + (part_off ? part_off[blockIdx.x] : (Tout)0);
 #pragma unroll
   for (int i = 0; i < kScanItems; ++i) {
     tile[threadIdx.x * kScanItems + i] = run;
@@ -64,10 +64,9 @@ static void scan_impl(gj_ctx* c, const Tin* in, Tout* out, uint64_t n, int level
   }
   uint64_t nb = (n + kScanTile - 1) / kScanTile;
   GJ_CHECK(nb < (1ull << 31), GJ_EUNSUPPORTED, "scan too large");
-  Tout* off = (Tout*)ws_get(c, "scan_off" + std::to_string(level), (nb + 1) * sizeof(Tout));
-  if (nb == 1) {
-    GJ_HIP(hipMemsetAsync(off, 0, sizeof(Tout), c->stream));
-  } else {
+  Tout* off = nullptr;  // one tile: no tile offsets
+  if (nb > 1) {
+    off = (Tout*)ws_get(c, "scan_off" + std::to_string(level), (nb + 1) * sizeof(Tout));
     Tout* part = (Tout*)ws_get(c, "scan_part" + std::to_string(level), nb * sizeof(Tout));
     k_scan_reduce<Tin, Tout><<<(unsigned)nb, kBlock, 0, c->stream>>>(in, n, part);
     scan_impl<Tout, Tout>(c, part, off, nb, level + 1);

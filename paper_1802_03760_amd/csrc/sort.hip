@@ -82,6 +82,48 @@ __global__ void __launch_bounds__(kBlock) k_scatter(const K* __restrict__ keys, 
   }
 }
 
+// Up to kSmallSort (key, value) pairs sorted by one workgroup in LDS:
+// bitonic sort over (key, value), padded to a power of two with the largest
+// pair; equal keys end up in ascending value order.
+constexpr int kSmallSort = 2048;
+
+__global__ void __launch_bounds__(1024) k_small_sort_kv(const uint64_t* __restrict__ keys,
+                                                        const uint32_t* __restrict__ vals, uint32_t n,
+                                                        uint32_t p2, uint64_t* __restrict__ okeys,
+                                                        uint32_t* __restrict__ ovals) {
+  __shared__ uint64_t K[kSmallSort];
+  __shared__ uint32_t V[kSmallSort];
+  for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) {
+    K[i] = i < n ? keys[i] : ~0ull;
+    V[i] = i < n ? vals[i] : ~0u;
+  }
+  __syncthreads();
+  for (uint32_t size = 2; size <= p2; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = threadIdx.x; i < p2; i += blockDim.x) {
+        uint32_t j = i ^ stride;
+        if (j > i) {
+          bool up = (i & size) == 0;
+          uint64_t ki = K[i], kj = K[j];
+          uint32_t vi = V[i], vj = V[j];
+          bool gt = ki > kj || (ki == kj && vi > vj);
+          if (gt == up) {
+            K[i] = kj;
+            K[j] = ki;
+            V[i] = vj;
+            V[j] = vi;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    okeys[i] = K[i];
+    ovals[i] = V[i];
+  }
+}
+
 template <typename K, bool VAL>
 static void radix_pass(gj_ctx* c, const K* keys, const uint32_t* vals, K* okeys, uint32_t* ovals,
                        uint64_t n, int shift) {
@@ -111,6 +153,16 @@ uint64_t* sort_u64(gj_ctx* c, uint64_t* keys, uint64_t* alt, uint64_t n, int lo_
 void sort_kv_u64(gj_ctx* c, uint64_t*& key, uint32_t*& val, uint64_t*& key_alt, uint32_t*& val_alt,
                  uint64_t n, int lo_bits, int hi_bits) {
   if (n <= 1) return;
+  if (n <= (uint64_t)kSmallSort) {
+    // one launch instead of a histogram, scan and scatter per digit
+    uint32_t p2 = 2;
+    while (p2 < n) p2 <<= 1;
+    k_small_sort_kv<<<1, 1024, 0, c->stream>>>(key, val, (uint32_t)n, p2, key_alt, val_alt);
+    GJ_HIP(hipGetLastError());
+    std::swap(key, key_alt);
+    std::swap(val, val_alt);
+    return;
+  }
   for (int shift = 0; shift < 64; shift += 8) {
     bool need = shift < lo_bits || (shift >= 32 && shift - 32 < hi_bits);
     if (!need) continue;
