@@ -102,36 +102,102 @@ __global__ void k_ins_flags(const int8_t* __restrict__ g, uint64_t k, uint32_t* 
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gs) f[i] = g[i] > 0 ? 1u : 0u;
 }
 
-// new degree of every row
-__global__ void k_new_deg(const uint32_t* __restrict__ rp, DeltaDir D, uint32_t n, uint32_t* __restrict__ deg) {
-  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gs) {
-    uint32_t a = D.drp[v], b = D.drp[v + 1];
-    uint32_t ins = (uint32_t)(D.ins_scan[b] - D.ins_scan[a]);
-    uint32_t del = (b - a) - ins;
-    deg[v] = rp[v + 1] - rp[v] + ins - del;
+// Per row v of one direction: drp[v], where the rows of dE (sorted) reach v;
+// the row's new degree deg[v]; and the largest new degree, folded into
+// *maxdeg by at most one atomicMax per workgroup (launched with few
+// workgroups for that reason).  A wave covers 63 rows at a time: its lane 63
+// only finds where row v + 1 starts, for lane 62.
+__global__ void __launch_bounds__(kBlock) k_delta_rows(const uint32_t* __restrict__ r, uint64_t k,
+                                                       const uint64_t* __restrict__ ins_scan,
+                                                       const uint32_t* __restrict__ rp, uint32_t n,
+                                                       uint32_t* __restrict__ drp, uint32_t* __restrict__ deg,
+                                                       uint32_t* __restrict__ maxdeg) {
+  __shared__ uint32_t wbest[kBlock / 64];
+  const int lane = lane_id();
+  const uint64_t wave = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  uint32_t best = 0;
+  for (uint64_t base = wave * 63; base <= n; base += waves * 63) {
+    uint64_t v = base + lane;
+    uint64_t lo = k;
+    if (v <= n) {
+      uint64_t len = k;
+      lo = 0;
+      while (len > 0) {
+        uint64_t half = len >> 1;
+        if (r[lo + half] < v) {
+          lo += half + 1;
+          len -= half + 1;
+        } else {
+          len = half;
+        }
+      }
+      drp[v] = (uint32_t)lo;
+    }
+    uint32_t hi = __shfl_down((uint32_t)lo, 1, 64);
+    if (lane < 63 && v < n) {
+      uint32_t ins = (uint32_t)(ins_scan[hi] - ins_scan[lo]);
+      uint32_t del = (hi - (uint32_t)lo) - ins;
+      uint32_t d = rp[v + 1] - rp[v] + ins - del;
+      deg[v] = d;
+      best = d > best ? d : best;
+    }
+  }
+  best = wave_max(best);
+  if (lane == 0) wbest[wave_id()] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) best = wbest[w] > best ? wbest[w] : best;
+    // the atomics of many workgroups on one word serialise: most are skipped
+    if (best > __hip_atomic_load(maxdeg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(maxdeg, best);
   }
 }
 
-// copy the surviving old entries to their new positions
-__global__ void k_move_old(const uint32_t* __restrict__ orp, const uint32_t* __restrict__ ocol,
-                           const uint32_t* __restrict__ orow, uint64_t om, DeltaDir D,
-                           const uint32_t* __restrict__ nrp, uint32_t* __restrict__ ncol,
-                           uint32_t* __restrict__ nrow) {
-  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < om; e += gs) {
-    uint32_t r = orow[e], x = ocol[e];
-    uint32_t a = D.drp[r], b = D.drp[r + 1];
-    uint64_t pos = (uint64_t)nrp[r] + (e - orp[r]);
-    if (a != b) {
-      uint32_t i = lower_bound_u32(D.x, a, b, x);
-      if (i < b && D.x[i] == x) continue;  // deleted (an insert of a present edge never reaches dE)
-      uint32_t ins_before = (uint32_t)(D.ins_scan[i] - D.ins_scan[a]);
-      uint32_t del_before = (i - a) - ins_before;
-      pos = pos + ins_before - del_before;
+// copy the surviving old entries to their new positions.  A workgroup moves a
+// tile of kMoveU * kBlock consecutive entries, each thread kMoveU of them
+// kBlock apart, with every load of a tile issued before the row lookups that
+// depend on them, so that a wave has kMoveU independent loads in flight.
+constexpr int kMoveU = 4;
+__global__ void __launch_bounds__(kBlock) k_move_old(const uint32_t* __restrict__ orp,
+                                                     const uint32_t* __restrict__ ocol,
+                                                     const uint32_t* __restrict__ orow, uint64_t om, DeltaDir D,
+                                                     const uint32_t* __restrict__ nrp, uint32_t* __restrict__ ncol,
+                                                     uint32_t* __restrict__ nrow) {
+  const uint64_t tile = (uint64_t)kBlock * kMoveU;
+  for (uint64_t base = (uint64_t)blockIdx.x * tile; base < om; base += (uint64_t)gridDim.x * tile) {
+    uint32_t r[kMoveU], x[kMoveU], a[kMoveU], b[kMoveU], np[kMoveU], op[kMoveU];
+#pragma unroll
+    for (int u = 0; u < kMoveU; ++u) {
+      uint64_t e = base + (uint64_t)u * kBlock + threadIdx.x;
+      r[u] = 0;  // row 0 exists: the lookups below stay in bounds past the end
+      x[u] = 0;
+      if (e < om) {
+        r[u] = orow[e];
+        x[u] = ocol[e];
+      }
     }
-    ncol[pos] = x;
-    nrow[pos] = r;
+#pragma unroll
+    for (int u = 0; u < kMoveU; ++u) {
+      a[u] = D.drp[r[u]];
+      b[u] = D.drp[r[u] + 1];
+      np[u] = nrp[r[u]];
+      op[u] = orp[r[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kMoveU; ++u) {
+      uint64_t e = base + (uint64_t)u * kBlock + threadIdx.x;
+      if (e >= om) continue;
+      uint64_t pos = (uint64_t)np[u] + (e - op[u]);
+      if (a[u] != b[u]) {
+        uint32_t i = lower_bound_u32(D.x, a[u], b[u], x[u]);
+        if (i < b[u] && D.x[i] == x[u]) continue;  // deleted (an insert of a present edge never reaches dE)
+        uint32_t ins_before = (uint32_t)(D.ins_scan[i] - D.ins_scan[a[u]]);
+        uint32_t del_before = (i - a[u]) - ins_before;
+        pos = pos + ins_before - del_before;
+      }
+      ncol[pos] = x[u];
+      nrow[pos] = r[u];
+    }
   }
 }
 
@@ -153,23 +219,6 @@ __global__ void k_place_ins(const uint32_t* __restrict__ orp, const uint32_t* __
   }
 }
 
-__global__ void k_rowptr_of(const uint32_t* __restrict__ row, uint64_t m, uint32_t n, uint32_t* __restrict__ rp) {
-  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v <= n; v += gs) {
-    uint64_t lo = 0, len = m;
-    while (len > 0) {
-      uint64_t half = len >> 1;
-      if (row[lo + half] < v) {
-        lo += half + 1;
-        len -= half + 1;
-      } else {
-        len = half;
-      }
-    }
-    rp[v] = (uint32_t)lo;
-  }
-}
-
 __global__ void k_unswap(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ idx,
                          const int8_t* __restrict__ g, uint64_t k, uint32_t* __restrict__ r, uint32_t* __restrict__ x,
                          int8_t* __restrict__ og) {
@@ -182,20 +231,20 @@ __global__ void k_unswap(const uint64_t* __restrict__ keys, const uint32_t* __re
 }
 
 static void update_dir(gj_ctx* c, uint32_t n, const CsrDir& od, uint64_t om, const uint32_t* r, const uint32_t* x,
-                       const int8_t* g, uint64_t k, CsrDir& nd, const std::string& tag) {
+                       const int8_t* g, uint64_t k, CsrDir& nd, const std::string& tag, uint32_t* maxdeg) {
   uint32_t* drp = (uint32_t*)ws_get(c, "up_drp" + tag, ((uint64_t)n + 1) * sizeof(uint32_t));
   uint32_t* insf = (uint32_t*)ws_get(c, "up_insf" + tag, (k + 1) * sizeof(uint32_t));
   uint64_t* ins_scan = (uint64_t*)ws_get(c, "up_inss" + tag, (k + 1) * sizeof(uint64_t));
   uint32_t* deg = (uint32_t*)ws_get(c, "up_deg", ((uint64_t)n + 1) * sizeof(uint32_t));
-  unsigned gn = grid_for((uint64_t)n + 1, kBlock, 1u << 16);
+  unsigned gn = grid_for(((uint64_t)n + 63) / 63 * 64, kBlock, 2048);  // a wave per 63 rows
   unsigned gk = grid_for(k, kBlock, 1u << 16);
-  k_rowptr_of<<<gn, kBlock, 0, c->stream>>>(r, k, n, drp);
   k_ins_flags<<<gk, kBlock, 0, c->stream>>>(g, k, insf);
   scan_u32_to_u64(c, insf, ins_scan, k);
+  k_delta_rows<<<gn, kBlock, 0, c->stream>>>(r, k, ins_scan, od.rp, n, drp, deg, maxdeg);
   DeltaDir D{r, x, g, drp, ins_scan};
-  k_new_deg<<<gn, kBlock, 0, c->stream>>>(od.rp, D, n, deg);
   scan_u32(c, deg, nd.rp, n);
-  if (om) k_move_old<<<grid_for(om, kBlock, 1u << 16), kBlock, 0, c->stream>>>(od.rp, od.col, od.row, om, D, nd.rp, nd.col, nd.row);
+  if (om)
+    k_move_old<<<grid_for((om + kMoveU - 1) / kMoveU, kBlock, 1u << 16), kBlock, 0, c->stream>>>(od.rp, od.col, od.row, om, D, nd.rp, nd.col, nd.row);
   k_place_ins<<<gk, kBlock, 0, c->stream>>>(od.rp, od.col, D, k, nd.rp, nd.col, nd.row);
   GJ_HIP(hipGetLastError());
 }
@@ -294,13 +343,15 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
     uint64_t need = ov.m + k;
     if (need > nv.cap) version_alloc(nv, n, need + need / 16 + (1u << 20));
   }
-  update_dir(c, n, ov.d[0], ov.m, es, ed, eg, k, nv.d[0], "f");
-  update_dir(c, n, ov.d[1], ov.m, rd, rs, rg, k, nv.d[1], "r");
+  uint32_t* mx = (uint32_t*)ws_get(c, "maxdeg", 2 * sizeof(uint32_t));
+  GJ_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(uint32_t), c->stream));
+  update_dir(c, n, ov.d[0], ov.m, es, ed, eg, k, nv.d[0], "f", mx);
+  update_dir(c, n, ov.d[1], ov.m, rd, rs, rg, k, nv.d[1], "r", mx + 1);
   uint32_t newm = 0;
   read_bytes(c, &newm, nv.d[0].rp + n, sizeof(newm));
   nv.m = newm;
   (void)ins_total;
-  version_finish(c, nv, n, true);  // row pointers come from the update
+  version_finish(c, nv, n, true);  // row pointers and largest degrees come from the update
   // ---- delta queries
   std::vector<char> done(nq, 0);
   // Count-only queries whose every dQ_i extends the seed edge by one attribute

@@ -210,7 +210,10 @@ void sort_rows(gj_ctx* c, uint32_t* rows, int8_t* signs, uint64_t nrows, int m, 
 uint64_t consolidate_rows(gj_ctx* c, const uint32_t* rows, const int8_t* signs, uint64_t nrows, int m,
                           uint32_t* out_rows, int8_t* out_signs, uint64_t cap, int64_t* sum);
 int bits_for(uint32_t n);
-void version_finish(gj_ctx* c, Version& v, uint32_t n, bool rowptrs_ready);
+// Row pointers and largest degrees of both directions: computed here from the
+// rows, or (from_update) already written by the update, the degrees into the
+// "maxdeg" workspace.  Reads the degrees back to the host.
+void version_finish(gj_ctx* c, Version& v, uint32_t n, bool from_update);
 
 // api.hip: counts of nreq requests on version ver (null: current), fused
 void count_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* seed_lo,

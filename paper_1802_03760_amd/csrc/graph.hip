@@ -118,15 +118,17 @@ int bits_for(uint32_t n) {
   return b;
 }
 
-void version_finish(gj_ctx* c, Version& v, uint32_t n, bool rowptrs_ready) {
+void version_finish(gj_ctx* c, Version& v, uint32_t n, bool from_update) {
   uint32_t* mx = (uint32_t*)ws_get(c, "maxdeg", 2 * sizeof(uint32_t));
-  GJ_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(uint32_t), c->stream));
-  for (int d = 0; d < 2; ++d) {
-    if (!rowptrs_ready)
-      k_rowptr<<<grid_for((uint64_t)n + 1, kBlock, 1u << 16), kBlock, 0, c->stream>>>(v.d[d].row, v.m, n, v.d[d].rp);
-    k_maxdeg<<<grid_for(n, kBlock * 16, 1024), kBlock, 0, c->stream>>>(v.d[d].rp, n, mx + d);
+  if (!from_update) {
+    GJ_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(uint32_t), c->stream));
+    for (int d = 0; d < 2; ++d) {
+      k_rowptr<<<grid_for((uint64_t)n + 1, kBlock, 1u << 16), kBlock, 0, c->stream>>>(v.d[d].row, v.m, n,
+                                                                                        v.d[d].rp);
+      k_maxdeg<<<grid_for(n, kBlock * 16, 1024), kBlock, 0, c->stream>>>(v.d[d].rp, n, mx + d);
+    }
+    GJ_HIP(hipGetLastError());
   }
-  GJ_HIP(hipGetLastError());
   uint32_t h[2];
   read_bytes(c, h, mx, sizeof(h));
   v.max_deg[0] = h[0];

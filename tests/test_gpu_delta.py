@@ -24,18 +24,30 @@ def ctx(gj):
     return gj.Context(0)
 
 
-def edge_set(G):
+def _dev(p, n, dtype=np.uint32):
     hip = ctypes.CDLL("libamdhip64.so")
+    a = np.empty(n, dtype)
+    if n:
+        assert hip.hipMemcpy(ctypes.c_void_p(a.ctypes.data), ctypes.c_void_p(p), ctypes.c_size_t(a.nbytes), 2) == 0
+    return a
+
+
+def check_index(G, es, ed):
+    """Both directions of the current version (rows, values and row
+    pointers) and the largest degrees against the edge list (es, ed), sorted
+    by (src, dst)."""
     info = G.info()
-    E = info["edges"]
-    rp, col, row = G.csr_ptrs(0)
-    s = np.empty(E, np.uint32)
-    d = np.empty(E, np.uint32)
-    for arr, p in ((s, row), (d, col)):
-        if E:
-            assert hip.hipMemcpy(ctypes.c_void_p(arr.ctypes.data), ctypes.c_void_p(p),
-                                 ctypes.c_size_t(arr.nbytes), 2) == 0
-    return s, d
+    n, E = info["vertices"], info["edges"]
+    assert E == len(es)
+    order = np.lexsort((es, ed))  # by (dst, src)
+    for rev, (rows, cols) in enumerate(((es, ed), (ed[order], es[order]))):
+        rp, col, row = G.csr_ptrs(rev)
+        assert np.array_equal(_dev(row, E), rows) and np.array_equal(_dev(col, E), cols), rev
+        want_rp = np.searchsorted(rows, np.arange(n + 1, dtype=np.uint64)).astype(np.uint32)
+        assert np.array_equal(_dev(rp, n + 1), want_rp), rev
+    deg_out = np.bincount(es, minlength=n) if E else np.zeros(n, np.int64)
+    deg_in = np.bincount(ed, minlength=n) if E else np.zeros(n, np.int64)
+    assert (info["max_out"], info["max_in"]) == (int(deg_out.max(initial=0)), int(deg_in.max(initial=0)))
 
 
 def step(gj, ctx, G, O, qs_py, qs_gj, bs, bd, bg):
@@ -58,9 +70,8 @@ def step(gj, ctx, G, O, qs_py, qs_gj, bs, bd, bg):
             assert (r["stats"]["noop_inserts"], r["stats"]["noop_deletes"]) == (ni - bi, nd - bd_)
             first = False
     oracle.delta(O, bs, bd, bg)  # advance the reference graph
-    s, d = edge_set(G)
     es, ed = O.edge_list()
-    assert np.array_equal(s, es) and np.array_equal(d, ed)
+    check_index(G, np.asarray(es, np.uint32), np.asarray(ed, np.uint32))
     return res
 
 

@@ -5,8 +5,11 @@ checked through properties that hold at any size (edge count and extension
 counter computed independently with numpy; the owner-grouped count equals the
 generic per-candidate count), and sampled seed slices are checked
 element by element against the oracle.  Delta batches at scale 22 are
-checked by count conservation and by validity of every reported row.
+checked by count conservation, by validity of every reported row, and by the
+largest degrees and row pointers of the new versions.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -150,7 +153,11 @@ def test_rmat22_delta_stream_properties(gj, rmat22):
         ins = np.setdiff1d(bk[(bg > 0) & ~loops], keys)
         dels = np.intersect1d(bk[(bg < 0) & ~loops], keys)
         new_keys = np.union1d(np.setdiff1d(keys, dels), ins)
-        assert G.info()["edges"] == len(new_keys)
+        info = G.info()
+        assert info["edges"] == len(new_keys)
+        deg_out = np.bincount((new_keys >> 32).astype(np.int64), minlength=n)
+        deg_in = np.bincount((new_keys & 0xFFFFFFFF).astype(np.int64), minlength=n)
+        assert (info["max_out"], info["max_in"]) == (int(deg_out.max()), int(deg_in.max()))
         rows = r["rows"].astype(np.int64)
         if len(rows):
             def present(kk, a, b):
@@ -166,5 +173,12 @@ def test_rmat22_delta_stream_properties(gj, rmat22):
         keys = new_keys
     c1 = gj.count(ctx, G, q)["matches"]
     assert c1 - c0 == total
+    # row pointers of both directions of the last version
+    hip = ctypes.CDLL("libamdhip64.so")
+    for rev, deg in ((0, deg_out), (1, deg_in)):
+        rp = np.empty(n + 1, np.uint32)
+        assert hip.hipMemcpy(ctypes.c_void_p(rp.ctypes.data), ctypes.c_void_p(G.csr_ptrs(rev)[0]),
+                             ctypes.c_size_t(rp.nbytes), 2) == 0
+        assert rp[0] == 0 and np.array_equal(np.diff(rp.astype(np.int64)), deg), rev
     G.close()
     ctx.close()
