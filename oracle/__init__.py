@@ -8,7 +8,11 @@ shares no code with it.
 Paper: Ammar, McSherry, Salihoglu, Joglekar, "Distributed Evaluation of
 Subgraph Queries Using Worst-case Optimal Low-Memory Dataflows".  Generic Join
 (Sec. 2.2, Fig. 1), its prefix-extension stage (Sec. 3.1, Sec. 4.1), the
-edge-seeded dataflow (Sec. 4.2) and Delta-GJ (Sec. 3.3.1).
+edge-seeded dataflow (Sec. 4.2), Delta-GJ (Sec. 3.3.1) and the symmetry
+breaking of Sec. 5.4 (inequality filters; vertices renamed by degree).
+
+A query is (num_attrs, atoms, order) or (num_attrs, atoms, order, less), with
+less a list of (x, y) meaning the value of a_x is below that of a_y.
 """
 import ctypes
 import os
@@ -55,13 +59,13 @@ def _load():
         L.or_graph_edge_list.argtypes = [vp, vp, vp]
         L.or_graph_noops.argtypes = [vp, vp, vp]
         L.or_query_valid.restype = i32
-        L.or_query_valid.argtypes = [i32, vp, vp, i32, vp]
+        L.or_query_valid.argtypes = [i32, vp, vp, i32, vp, vp, vp, i32]
         L.or_run.restype = vp
-        L.or_run.argtypes = [vp, i32, vp, vp, i32, vp, i32, u64, u64, i32, ip]
+        L.or_run.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, i32, i32, u64, u64, i32, ip]
         L.or_run_textbook.restype = vp
         L.or_run_textbook.argtypes = [vp, i32, vp, vp, i32, vp, vp, ip]
         L.or_delta.restype = vp
-        L.or_delta.argtypes = [vp, vp, vp, vp, u64, i32, vp, vp, i32, vp, ip]
+        L.or_delta.argtypes = [vp, vp, vp, vp, u64, i32, vp, vp, i32, vp, vp, vp, i32, ip]
         L.or_result_matches.restype = u64
         L.or_result_matches.argtypes = [vp]
         L.or_result_counters.argtypes = [vp, vp, vp]
@@ -83,16 +87,19 @@ def _p(a):
 
 
 def _query_arrays(query):
-    num_attrs, atoms, order = query
+    num_attrs, atoms, order = query[:3]
+    less = list(query[3]) if len(query) > 3 else []
     s = np.array([a for a, _ in atoms], dtype=np.uint8)
     d = np.array([b for _, b in atoms], dtype=np.uint8)
     o = np.array(order, dtype=np.uint8)
-    return num_attrs, s, d, len(atoms), o
+    lx = np.array([x for x, _ in less], dtype=np.uint8)
+    ly = np.array([y for _, y in less], dtype=np.uint8)
+    return num_attrs, s, d, len(atoms), o, lx, ly, len(less)
 
 
 def query_valid(query):
-    m, s, d, k, o = _query_arrays(query)
-    return bool(_load().or_query_valid(m, _p(s), _p(d), k, _p(o)))
+    m, s, d, k, o, lx, ly, nl = _query_arrays(query)
+    return bool(_load().or_query_valid(m, _p(s), _p(d), k, _p(o), _p(lx), _p(ly), nl))
 
 
 class Graph:
@@ -167,10 +174,10 @@ def _take(res, m, want_rows, want_signs=False):
 
 def run(graph, query, collect=False, seed_lo=0, seed_hi=None, threads=1):
     """Edge-seeded Generic Join; rows in attribute-index order, sorted."""
-    m, s, d, k, o = _query_arrays(query)
+    m, s, d, k, o, lx, ly, nl = _query_arrays(query)
     st = ctypes.c_int(0)
     hi = (1 << 64) - 1 if seed_hi is None else seed_hi
-    res = _load().or_run(graph._h, m, _p(s), _p(d), k, _p(o), int(collect),
+    res = _load().or_run(graph._h, m, _p(s), _p(d), k, _p(o), _p(lx), _p(ly), nl, int(collect),
                          seed_lo, hi, threads, ctypes.byref(st))
     if st.value != 0:
         if res:
@@ -180,8 +187,11 @@ def run(graph, query, collect=False, seed_lo=0, seed_hi=None, threads=1):
 
 
 def textbook(graph, query):
-    """Textbook GJ from P_0; returns [P_1, ..., P_m] as position-order arrays."""
-    m, s, d, k, o = _query_arrays(query)
+    """Textbook GJ from P_0; returns [P_1, ..., P_m] as position-order arrays
+    (queries without inequalities)."""
+    m, s, d, k, o, _, _, nl = _query_arrays(query)
+    if nl:
+        raise OracleError("textbook(): inequalities are not supported")
     sizes = np.zeros(MAX_ATTRS + 2, dtype=np.uint64)
     st = ctypes.c_int(0)
     res = _load().or_run_textbook(graph._h, m, _p(s), _p(d), k, _p(o), _p(sizes),
@@ -210,15 +220,51 @@ def delta(graph, src, dst, sign, query=None):
     st = ctypes.c_int(0)
     if query is None:
         res = _load().or_delta(graph._h, _p(src), _p(dst), _p(sign), len(src),
-                               0, None, None, 0, None, ctypes.byref(st))
+                               0, None, None, 0, None, None, None, 0, ctypes.byref(st))
         m = 0
     else:
-        m, s, d, k, o = _query_arrays(query)
+        m, s, d, k, o, lx, ly, nl = _query_arrays(query)
         res = _load().or_delta(graph._h, _p(src), _p(dst), _p(sign), len(src),
-                               m, _p(s), _p(d), k, _p(o), ctypes.byref(st))
+                               m, _p(s), _p(d), k, _p(o), _p(lx), _p(ly), nl, ctypes.byref(st))
     if st.value != 0:
         raise OracleError("or_delta status %d" % st.value)
     if query is None:
         _load().or_result_free(res)
         return None
     return _take(res, m, True, True)
+
+
+def symmetric_edges(n, src, dst):
+    """Every distinct unordered pair {u, v}, u != v, of the input edges in
+    both directions, sorted by (src, dst)."""
+    s = np.asarray(src, dtype=np.int64)
+    d = np.asarray(dst, dtype=np.int64)
+    keep = s != d
+    lo = np.minimum(s[keep], d[keep])
+    hi = np.maximum(s[keep], d[keep])
+    pairs = np.unique(lo * n + hi)
+    a, b = pairs // n, pairs % n
+    u = np.concatenate([a, b])
+    v = np.concatenate([b, a])
+    order = np.lexsort((v, u))
+    return u[order].astype(np.uint32), v[order].astype(np.uint32)
+
+
+def relabel_by_degree(n, src, dst, undirected=False):
+    """The input transform of the symmetry-breaking optimisation (Sec. 5.4):
+    the input is read as undirected (distinct unordered pairs {u, v}, u != v);
+    vertex u's degree is the number of pairs that contain it; new ids are the
+    ranks of the vertices by ascending degree, ties by ascending old id.  Each
+    pair becomes the edge from its lower new id to its higher one, or both
+    directions when `undirected`.  Returns (src, dst, old_of_new): the edges in
+    new ids sorted by (src, dst), and the old id of every new id."""
+    u, v = symmetric_edges(n, src, dst)
+    deg = np.bincount(u.astype(np.int64), minlength=n)
+    old_of_new = np.lexsort((np.arange(n), deg))  # primary key: degree
+    new_of_old = np.empty(n, dtype=np.int64)
+    new_of_old[old_of_new] = np.arange(n)
+    nu, nv = new_of_old[u], new_of_old[v]
+    keep = np.ones(len(nu), dtype=bool) if undirected else nu < nv
+    nu, nv = nu[keep], nv[keep]
+    order = np.lexsort((nv, nu))
+    return nu[order].astype(np.uint32), nv[order].astype(np.uint32), old_of_new.astype(np.uint32)

@@ -24,6 +24,11 @@
 //  * Delta-GJ (Sec. 3.3.1): dQ_i = R'_1..R'_{i-1}, dR_i, R_{i+1}..R_n, each
 //    ordered starting with R_i's attributes; the signed union of the dQ_i is
 //    the change of the output.
+//  * Symmetry breaking (Sec. 5.4): a query may carry inequalities a_x < a_y
+//    between attributes, applied as filters to the prefixes: a prefix that
+//    binds both attributes is dropped unless the inequality holds.  The
+//    filters do not change which set is proposed from, so the extension
+//    counters are those of the query without them.
 //
 // Readings where the paper is silent (each is listed with its reason in the
 // design notes): count-minimisation ties go to the lowest atom index; the
@@ -45,6 +50,7 @@ namespace {
 
 constexpr int kMaxAttrs = 8;
 constexpr int kMaxAtoms = 16;
+constexpr int kMaxLess = 28;  // every pair of 8 attributes once
 
 enum { OR_OK = 0, OR_EINVAL = 1, OR_EOVERFLOW = 4 };
 
@@ -87,6 +93,7 @@ struct Query {
   int m = 0;
   std::vector<Atom> atoms;
   std::vector<int> order;  // order[j] = attribute bound at position j
+  std::vector<Atom> less;  // (x, y): the value of a_x is below that of a_y
 };
 
 // An extension set reference: the neighbour list of the value in prefix
@@ -110,6 +117,9 @@ bool valid_query(const Query& q) {
     if (at.s < 0 || at.s >= q.m || at.d < 0 || at.d >= q.m) return false;
     if (at.s == at.d) return false;
   }
+  if ((int)q.less.size() > kMaxLess) return false;
+  for (auto& l : q.less)
+    if (l.s < 0 || l.s >= q.m || l.d < 0 || l.d >= q.m || l.s == l.d) return false;
   std::vector<int> pos(q.m);
   for (int j = 0; j < q.m; ++j) pos[q.order[j]] = j;
   // the first two attributes must share an atom (P_2 is seeded from edges)
@@ -130,12 +140,29 @@ bool valid_query(const Query& q) {
 // Per-query plan derived from the order: the seed atom (lowest index over the
 // first two attributes), filter atoms over the same two, and for every later
 // position j the atoms binding order[j] with their bound column.
+// An inequality checked when position `later` is bound: the value there must
+// be above (above = true) or below the value in prefix column `col`.
+struct Ineq {
+  int col;
+  bool above;
+};
+
 struct Plan {
   int seed_atom = -1;
   bool seed_fwd = true;  // P_2 = (u, v) with u -> v (true) or v -> u (false)
   std::vector<int> filters;
   std::vector<std::vector<Binding>> bind;  // bind[j], j = 2..m-1
+  std::vector<std::vector<Ineq>> ineq;     // ineq[j], j = 1..m-1
 };
+
+// Does value e at position j satisfy the inequalities against the prefix?
+bool ineq_ok(const Plan& p, int j, const std::vector<uint32_t>& prefix, uint32_t e) {
+  for (const Ineq& iq : p.ineq[j]) {
+    uint32_t o = prefix[iq.col];
+    if (iq.above ? !(e > o) : !(e < o)) return false;
+  }
+  return true;
+}
 
 Plan make_plan(const Query& q) {
   Plan p;
@@ -162,6 +189,15 @@ Plan make_plan(const Query& q) {
       p.bind[j].push_back({i, pos[at.s], true});
     else  // edge(x, y): x ranges over in(y)
       p.bind[j].push_back({i, pos[at.d], false});
+  }
+  // a_x < a_y is checked when the later of the two is bound
+  p.ineq.assign(q.m, {});
+  for (const Atom& l : q.less) {
+    int jx = pos[l.s], jy = pos[l.d];
+    if (jy > jx)
+      p.ineq[jy].push_back({jx, true});   // new a_y must exceed a_x
+    else
+      p.ineq[jx].push_back({jy, false});  // new a_x must stay below a_y
   }
   return p;
 }
@@ -235,7 +271,7 @@ void extend(const Query& q, const Plan& plan, const Views& views, int j,
       const std::vector<uint32_t>& l = ext_list(views, B[i], prefix[B[i].col]);
       keep = std::binary_search(l.begin(), l.end(), e);
     }
-    if (!keep) continue;
+    if (!keep || !ineq_ok(plan, j, prefix, e)) continue;
     prefix.push_back(e);
     extend(q, plan, views, j + 1, prefix, c, collect, rows);
     prefix.pop_back();
@@ -263,7 +299,8 @@ void run_seeds(const Query& q, const Plan& plan, const Views& views,
     uint32_t x0 = E[k].first, x1 = E[k].second;
     bool ok = true;
     for (int f : plan.filters) ok = ok && pair_ok(q, views, f, x0, x1);
-    if (!ok) continue;
+    prefix.assign({x0});
+    if (!ok || !ineq_ok(plan, 1, prefix, x1)) continue;
     prefix.assign({x0, x1});
     extend(q, plan, views, 2, prefix, c, collect, rows);
   }
@@ -286,14 +323,19 @@ struct Result {
   uint64_t raw_emissions = 0;   // delta: signed outputs before consolidation
 };
 
+// The query's inequalities: lx[k] < ly[k] for k < num_less.
 bool parse_query(int num_attrs, const uint8_t* as, const uint8_t* ad, int num_atoms,
-                 const uint8_t* order, Query& q) {
-  if (num_attrs < 0 || num_attrs > kMaxAttrs || num_atoms < 0 || num_atoms > kMaxAtoms)
+                 const uint8_t* order, const uint8_t* lx, const uint8_t* ly, int num_less,
+                 Query& q) {
+  if (num_attrs < 0 || num_attrs > kMaxAttrs || num_atoms < 0 || num_atoms > kMaxAtoms ||
+      num_less < 0 || num_less > kMaxLess)
     return false;
   q.m = num_attrs;
   q.atoms.clear();
   for (int i = 0; i < num_atoms; ++i) q.atoms.push_back({as[i], ad[i]});
   q.order.assign(order, order + num_attrs);
+  q.less.clear();
+  for (int i = 0; i < num_less; ++i) q.less.push_back({lx[i], ly[i]});
   return valid_query(q);
 }
 
@@ -353,9 +395,9 @@ void or_graph_edge_list(const void* gp, uint32_t* src, uint32_t* dst) {
 }
 
 int or_query_valid(int num_attrs, const uint8_t* as, const uint8_t* ad, int num_atoms,
-                   const uint8_t* order) {
+                   const uint8_t* order, const uint8_t* lx, const uint8_t* ly, int num_less) {
   Query q;
-  return parse_query(num_attrs, as, ad, num_atoms, order, q) ? 1 : 0;
+  return parse_query(num_attrs, as, ad, num_atoms, order, lx, ly, num_less, q) ? 1 : 0;
 }
 
 // Edge-seeded Generic Join over seed edges [seed_lo, seed_hi) of the seed
@@ -363,11 +405,12 @@ int or_query_valid(int num_attrs, const uint8_t* as, const uint8_t* ad, int num_
 // Seeds are split over `threads` std::threads in contiguous chunks; the
 // result does not depend on the thread count.
 void* or_run(const void* gp, int num_attrs, const uint8_t* as, const uint8_t* ad,
-             int num_atoms, const uint8_t* order, int collect, uint64_t seed_lo,
-             uint64_t seed_hi, int threads, int* status) {
+             int num_atoms, const uint8_t* order, const uint8_t* lx, const uint8_t* ly,
+             int num_less, int collect, uint64_t seed_lo, uint64_t seed_hi, int threads,
+             int* status) {
   const Graph* g = (const Graph*)gp;
   Query q;
-  if (!parse_query(num_attrs, as, ad, num_atoms, order, q)) {
+  if (!parse_query(num_attrs, as, ad, num_atoms, order, lx, ly, num_less, q)) {
     *status = OR_EINVAL;
     return nullptr;
   }
@@ -465,11 +508,12 @@ void* or_run_textbook(const void* gp, int num_attrs, const uint8_t* as, const ui
 // graph unchanged).  Pass num_atoms = 0 to only apply the batch.
 void* or_delta(void* gp, const uint32_t* src, const uint32_t* dst, const int8_t* sign,
                uint64_t b, int num_attrs, const uint8_t* as, const uint8_t* ad,
-               int num_atoms, const uint8_t* order, int* status) {
+               int num_atoms, const uint8_t* order, const uint8_t* lx, const uint8_t* ly,
+               int num_less, int* status) {
   Graph* g = (Graph*)gp;
   Query q;
   bool have_query = num_atoms > 0;
-  if (have_query && !parse_query(num_attrs, as, ad, num_atoms, order, q)) {
+  if (have_query && !parse_query(num_attrs, as, ad, num_atoms, order, lx, ly, num_less, q)) {
     *status = OR_EINVAL;
     return nullptr;
   }
@@ -530,8 +574,9 @@ void* or_delta(void* gp, const uint32_t* src, const uint32_t* dst, const int8_t*
         uint32_t x0 = x.first.first, x1 = x.first.second;
         bool ok = true;
         for (int f : plan.filters) ok = ok && pair_ok(qi, views, f, x0, x1);
-        if (!ok) continue;
-        std::vector<uint32_t> prefix = {x0, x1}, rows;
+        std::vector<uint32_t> prefix = {x0}, rows;
+        if (!ok || !ineq_ok(plan, 1, prefix, x1)) continue;
+        prefix.push_back(x1);
         Counters c;
         extend(qi, plan, views, 2, prefix, c, true, rows);
         r->c.merge(c);

@@ -14,12 +14,17 @@ def adjacency(n, src, dst):
 
 
 def matches(A, query):
-    m, atoms, _ = query
+    """query = (m, atoms, order) or (m, atoms, order, less); (x, y) in less
+    requires the value of a_x to be below that of a_y."""
+    m, atoms = query[0], query[1]
+    less = query[3] if len(query) > 3 else []
     n = A.shape[0]
     T = np.indices((n,) * m).reshape(m, -1)  # lexicographic order
     ok = np.ones(T.shape[1], dtype=bool)
     for s, d in atoms:
         ok &= A[T[s], T[d]]
+    for x, y in less:
+        ok &= T[x] < T[y]
     return T[:, ok].T.astype(np.uint32)
 
 

@@ -54,3 +54,19 @@ def valid_orders(q):
         if ok:
             out.append(list(perm))
     return out
+
+
+# Symmetry breaking (Sec. 5.4): inequalities (x, y), value of a_x below a_y,
+# that pick one match of every orbit of the query's automorphisms on an
+# undirected (symmetric) input, with the size of that group.
+SYM_LESS = {
+    "triangle": ([(0, 1), (1, 2)], 6),
+    "clique4": ([(0, 1), (1, 2), (2, 3)], 24),
+    "clique5": ([(0, 1), (1, 2), (2, 3), (3, 4)], 120),
+    # house: swapping a2, a3 or a1, a4 preserves it (each pair is adjacent)
+    "house": ([(1, 2), (0, 3)], 4),
+}
+
+
+def with_less(q, less):
+    return (q[0], q[1], list(q[2]), list(less))

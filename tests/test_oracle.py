@@ -282,3 +282,156 @@ def test_delta_noops_counted():
     oracle.delta(G, [0, 3, 4], [1, 4, 4], [1, -1, 1], Q.TRIANGLE)
     assert G.noops() == (1, 1)
     assert G.num_edges == 2
+
+
+# ---------------------------------------------------------------- symmetry breaking (Sec. 5.4)
+def rand_less(rng, m):
+    pairs = [(x, y) for x in range(m) for y in range(m) if x != y]
+    k = int(rng.integers(1, 4))
+    return [pairs[i] for i in rng.choice(len(pairs), k, replace=False)]
+
+
+@pytest.mark.parametrize("name", ["triangle", "cyclic_triangle", "clique4", "diamond",
+                                  "cycle4", "reciprocal"])
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_inequalities_brute_force(name, seed):
+    """Inequality filters (Sec. 5.4) on random digraphs, random inequality sets
+    and every valid order: the rows are the brute-force matches that satisfy
+    the inequalities, and the extension counters do not depend on them."""
+    rng = np.random.default_rng(100 + seed)
+    q = Q.ALL[name]
+    n = 8
+    s, d = rand_graph(n, 30, 40 + seed)
+    G = oracle.Graph(n, s, d)
+    A = brute.adjacency(n, s, d)
+    for order in Q.valid_orders(q)[:6]:
+        less = rand_less(rng, q[0])
+        ql = Q.with_less(Q.with_order(q, order), less)
+        r = oracle.run(G, ql, collect=True)
+        want = brute.matches(A, ql)
+        assert brute.as_set(r["rows"]) == brute.as_set(want) and len(r["rows"]) == len(want)
+        assert r["prefixes"][q[0]] == r["matches"] == len(want)
+        plain = oracle.run(G, Q.with_order(q, order))
+        assert r["extensions"][:2] == plain["extensions"][:2]
+        assert r["prefixes"][2] <= plain["prefixes"][2]
+
+
+def undirected_graph(n, m, seed):
+    s, d = rand_graph(n, m, seed, loops=False)
+    return oracle.symmetric_edges(n, s, d)
+
+
+@pytest.mark.parametrize("name", sorted(Q.SYM_LESS))
+def test_automorphism_identity(name):
+    """On an undirected input the plain count is |Aut| times the count with
+    the symmetry-breaking inequalities, in every valid order (each inequality
+    is between adjacent attributes, so the group acts freely on matches)."""
+    q = Q.ALL[name]
+    less, aut = Q.SYM_LESS[name]
+    n = 40 if q[0] < 5 else 18
+    u, v = undirected_graph(n, 260 if q[0] < 5 else 160, 7)
+    G = oracle.Graph(n, u, v)
+    plain = oracle.run(G, q)["matches"]
+    assert plain > 0
+    for order in Q.valid_orders(q)[::7][:4]:
+        sym = oracle.run(G, Q.with_less(Q.with_order(q, order), less))["matches"]
+        assert sym * aut == plain, order
+
+
+def test_inequality_closed_form_complete_graph():
+    """Complete undirected graph K_n: cliques with a1 < ... < ak number C(n, k);
+    the plain clique count is n! / (n - k)!."""
+    n = 9
+    s, d = np.nonzero(~np.eye(n, dtype=bool))
+    G = oracle.Graph(n, s, d)
+    for name, k in (("triangle", 3), ("clique4", 4), ("clique5", 5)):
+        q = Q.ALL[name]
+        less = [(i, i + 1) for i in range(k - 1)]
+        assert oracle.run(G, Q.with_less(q, less))["matches"] == math.comb(n, k)
+        assert oracle.run(G, q)["matches"] == math.perm(n, k)
+        # contradictory inequalities leave nothing
+        assert oracle.run(G, Q.with_less(q, [(0, 1), (1, 0)]))["matches"] == 0
+
+
+@pytest.mark.parametrize("name", ["triangle", "clique4", "house"])
+def test_delta_with_inequalities_equals_recompute_difference(name):
+    """Delta-GJ of a query with inequalities: the signed rows are exactly the
+    change of the static result."""
+    q = Q.with_less(Q.ALL[name], Q.SYM_LESS[name][0])
+    n = 12
+    rng = np.random.default_rng(5)
+    u, v = undirected_graph(n, 50, 9)
+    G = oracle.Graph(n, u, v)
+    for step in range(5):
+        before = brute.as_set(oracle.run(G, q, collect=True)["rows"])
+        b = int(rng.integers(1, 20))
+        bs = rng.integers(0, n, b).astype(np.uint32)
+        bd = rng.integers(0, n, b).astype(np.uint32)
+        sg = np.where(rng.random(b) < 0.4, -1, 1).astype(np.int8)
+        dels = {(int(x), int(y)) for x, y, g in zip(bs, bd, sg) if g < 0}
+        keep = np.array([not (g > 0 and (int(x), int(y)) in dels) for x, y, g in zip(bs, bd, sg)])
+        r = oracle.delta(G, bs[keep], bd[keep], sg[keep], q)
+        after = brute.as_set(brute.matches(brute.adjacency(n, *G.edge_list()), q))
+        assert brute.as_set(oracle.run(G, q, collect=True)["rows"]) == after
+        plus = {t for t, g in zip(map(tuple, r["rows"].tolist()), r["signs"]) if g > 0}
+        minus = {t for t, g in zip(map(tuple, r["rows"].tolist()), r["signs"]) if g < 0}
+        assert plus == after - before and minus == before - after
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_degree_relabel_invariants(seed):
+    """The renaming of Sec. 5.4: a permutation under which degrees ascend (ties
+    by old id); the renamed edges are the input's distinct undirected pairs,
+    once from the lower new id to the higher, or both ways."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(5, 60))
+    s, d = rand_graph(n, int(rng.integers(0, 4 * n)), 300 + seed)  # loops, repeats, reciprocal pairs
+    pairs = {(min(a, b), max(a, b)) for a, b in zip(s.tolist(), d.tolist()) if a != b}
+    deg = np.zeros(n, dtype=np.int64)
+    for a, b in pairs:
+        deg[a] += 1
+        deg[b] += 1
+    for undirected in (False, True):
+        u, v, old = oracle.relabel_by_degree(n, s, d, undirected=undirected)
+        assert sorted(old.tolist()) == list(range(n))
+        key = [(int(deg[o]), int(o)) for o in old]
+        assert key == sorted(key)
+        back = {(min(int(old[a]), int(old[b])), max(int(old[a]), int(old[b]))) for a, b in zip(u, v)}
+        assert back == pairs
+        e = list(zip(u.tolist(), v.tolist()))
+        assert e == sorted(set(e))
+        if undirected:
+            assert len(e) == 2 * len(pairs) and set(e) == {(b, a) for a, b in e}
+        else:
+            assert len(e) == len(pairs) and all(a < b for a, b in e)
+
+
+def test_degree_relabel_star_and_clique_counts():
+    """A star's centre has the largest degree, so it gets the last id and every
+    edge points into it.  On a random undirected graph the plain clique query
+    over the oriented graph counts each undirected clique once: the number of
+    vertex subsets that are cliques, and the symmetric count over |Aut|."""
+    import itertools
+    k = 7
+    s = np.full(k, 3, dtype=np.uint32)
+    d = np.array([0, 1, 2, 4, 5, 6, 7], dtype=np.uint32)
+    u, v, old = oracle.relabel_by_degree(k + 1, s, d)
+    assert old[-1] == 3 and np.all(v == k) and len(u) == k
+    n = 20
+    a, b = undirected_graph(n, 110, 13)
+    A = brute.adjacency(n, a, b)
+    u, v, old = oracle.relabel_by_degree(n, a, b)
+    G_or = oracle.Graph(n, u, v)
+    G_sym = oracle.Graph(n, a, b)
+    for name, kk in (("triangle", 3), ("clique4", 4), ("clique5", 5)):
+        subsets = sum(all(A[x, y] for x, y in itertools.combinations(c, 2))
+                      for c in itertools.combinations(range(n), kk))
+        assert oracle.run(G_or, Q.ALL[name])["matches"] == subsets
+        assert oracle.run(G_sym, Q.ALL[name])["matches"] == subsets * math.factorial(kk)
+
+
+def test_invalid_inequalities():
+    q = Q.TRIANGLE
+    assert oracle.query_valid(Q.with_less(q, [(0, 2)]))
+    assert not oracle.query_valid(Q.with_less(q, [(0, 0)]))
+    assert not oracle.query_valid(Q.with_less(q, [(0, 3)]))
