@@ -90,13 +90,24 @@ gj_status gj_ctx_get_option(gj_ctx* ctx, const char* key, int64_t* value);
 
 #define GJ_INPUT_DEVICE 1u /* src/dst are device pointers (default: host) */
 #define GJ_KEEP_LOOPS 2u   /* not supported: self-loops are always dropped */
+/* The input edges are read as undirected: every distinct pair {u, v}, u != v,
+ * is stored in both directions. */
+#define GJ_BUILD_UNDIRECTED 4u
+/* Symmetry breaking's input transform (Sec. 5.4): the input is read as
+ * undirected, vertices get new ids in ascending order of (number of distinct
+ * neighbours, old id), and each pair is stored once, from its lower new id
+ * to its higher (both directions with GJ_BUILD_UNDIRECTED).  A clique query
+ * over this graph finds each undirected clique once.  gj_graph_vertex_ids
+ * gives the old id of every new one. */
+#define GJ_BUILD_DEGREE_ORDER 8u
 
 /* Builds the forward (out-neighbour) and reverse (in-neighbour) indices of
  * the edge relation (one physical copy each, Sec. 4.1): CSR rows sorted
  * ascending, repeated edges collapsed, self-loops dropped.
  * src, dst: m vertex ids each (host memory unless GJ_INPUT_DEVICE).
  * Errors: GJ_EINVAL for an id >= num_vertices, num_vertices == 0 or an
- * unknown flag; GJ_EUNSUPPORTED if m >= 2^32. */
+ * unknown flag; GJ_EUNSUPPORTED if m >= 2^32, or m >= 2^31 with
+ * GJ_BUILD_UNDIRECTED or GJ_BUILD_DEGREE_ORDER. */
 gj_status gj_graph_build(gj_ctx* ctx, const uint32_t* src, const uint32_t* dst,
                          uint64_t m, uint32_t num_vertices, uint32_t flags,
                          gj_graph** out);
@@ -116,6 +127,12 @@ gj_status gj_graph_csr(const gj_graph* g, int reverse, const uint32_t** row_ptr,
  * context is destroyed, and after any server on the graph. */
 void gj_graph_destroy(gj_graph* g);
 
+/* Old vertex id of every vertex id of g (num_vertices entries written to
+ * old_of_new, a host or device array as out_on_device says): the renaming of
+ * GJ_BUILD_DEGREE_ORDER, else the identity.  Match rows and update batches
+ * use the graph's own ids. */
+gj_status gj_graph_vertex_ids(const gj_graph* g, uint32_t* old_of_new, int out_on_device);
+
 /* ---------------------------------------------------------------- queries */
 
 /* atom = edge(a_src, a_dst) (Sec. 1.1: one atom per query edge) */
@@ -132,6 +149,25 @@ typedef struct {
  * atom to an earlier one. */
 gj_status gj_query_register(gj_ctx* ctx, uint32_t num_attrs, const gj_atom* atoms,
                             uint32_t num_atoms, const uint8_t* order, gj_query** out);
+
+/* Inequality a_lo < a_hi between attribute values (symmetry breaking,
+ * Sec. 5.4). */
+typedef struct {
+  uint8_t lo_attr, hi_attr;
+} gj_less;
+#define GJ_MAX_LESS 28
+
+/* gj_query_register plus inequalities every match must satisfy (less may be
+ * NULL when num_less is 0).  Each is a filter on the prefixes, applied when
+ * the later of its two attributes is bound (to the seed pair if both are the
+ * first two); extension counters are those of the query without them.  With
+ * one inequality per automorphism-equivalent pair of adjacent attributes, an
+ * undirected (symmetric) graph yields each subgraph once instead of |Aut|
+ * times.  Errors (GJ_EINVAL) as gj_query_register, and: num_less above
+ * GJ_MAX_LESS, an attribute out of range, lo_attr == hi_attr. */
+gj_status gj_query_register_ex(gj_ctx* ctx, uint32_t num_attrs, const gj_atom* atoms,
+                               uint32_t num_atoms, const uint8_t* order, const gj_less* less,
+                               uint32_t num_less, gj_query** out);
 void gj_query_destroy(gj_query* q);
 
 /* Per-call counters.  prefixes[j] = |P_j| (j >= 2; prefixes[m] = matches),

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(_HERE, "libgj.so")
 GJ_OK, GJ_EINVAL, GJ_ENOMEM, GJ_EDEVICE, GJ_EOVERFLOW, GJ_EUNSUPPORTED, GJ_EBUSY = range(7)
 MODE_COUNT, MODE_ENUMERATE = 0, 1
 GJ_INPUT_DEVICE = 1
+GJ_BUILD_UNDIRECTED, GJ_BUILD_DEGREE_ORDER = 4, 8
+MAX_LESS = 28
 MAX_ATTRS = 8
 STATUS_NAMES = {0: "GJ_OK", 1: "GJ_EINVAL", 2: "GJ_ENOMEM", 3: "GJ_EDEVICE",
                 4: "GJ_EOVERFLOW", 5: "GJ_EUNSUPPORTED", 6: "GJ_EBUSY"}
@@ -30,13 +32,17 @@ EXPORTS = ["gj_ctx_create", "gj_ctx_destroy", "gj_last_error", "gj_ctx_set_optio
            "gj_query_register", "gj_query_destroy", "gj_run", "gj_apply_updates",
            "gj_last_delta", "gj_run_batch", "gj_autotune", "gj_server_create", "gj_server_submit_count",
            "gj_server_submit_update", "gj_server_wait", "gj_server_get_stats", "gj_server_destroy",
-           "gj_server_set_option"]
+           "gj_server_set_option", "gj_query_register_ex", "gj_graph_vertex_ids"]
 REQ_COUNT, REQ_UPDATE = 0, 1
 SERVER_MAX_QUERIES = 16
 
 
 class Atom(ctypes.Structure):
     _fields_ = [("src_attr", ctypes.c_uint8), ("dst_attr", ctypes.c_uint8)]
+
+
+class Less(ctypes.Structure):
+    _fields_ = [("lo_attr", ctypes.c_uint8), ("hi_attr", ctypes.c_uint8)]
 
 
 class Tuning(ctypes.Structure):
@@ -104,6 +110,11 @@ _lib.gj_graph_destroy.argtypes = [_vp]
 _lib.gj_graph_destroy.restype = None
 _lib.gj_query_register.argtypes = [_vp, _u32, ctypes.POINTER(Atom), _u32, _vp, ctypes.POINTER(_vp)]
 _lib.gj_query_register.restype = _i32
+_lib.gj_query_register_ex.argtypes = [_vp, _u32, ctypes.POINTER(Atom), _u32, _vp, ctypes.POINTER(Less), _u32,
+                                      ctypes.POINTER(_vp)]
+_lib.gj_query_register_ex.restype = _i32
+_lib.gj_graph_vertex_ids.argtypes = [_vp, _vp, _i32]
+_lib.gj_graph_vertex_ids.restype = _i32
 _lib.gj_query_destroy.argtypes = [_vp]
 _lib.gj_query_destroy.restype = None
 _lib.gj_run.argtypes = [_vp, _vp, _vp, _i32, _u64, _u64, _vp, _u64, _i32, ctypes.POINTER(Stats)]
@@ -267,10 +278,14 @@ class Context(_Owner):
 
 
 class Graph(_Owner):
-    """Forward and reverse CSR indexes of an edge list (gj_graph_build)."""
+    """Forward and reverse CSR indexes of an edge list (gj_graph_build).
+    undirected: store every distinct pair both ways; degree_order: rename
+    vertices by degree and keep each pair once, lower new id to higher (both
+    ways if undirected too) -- see vertex_ids()."""
 
-    def __init__(self, ctx, src, dst, num_vertices):
+    def __init__(self, ctx, src, dst, num_vertices, undirected=False, degree_order=False):
         self.ctx = ctx
+        self.num_vertices = num_vertices
         h = _vp()
         if _is_torch(src):
             flags = GJ_INPUT_DEVICE if src.is_cuda else 0
@@ -279,6 +294,7 @@ class Graph(_Owner):
             src = np.ascontiguousarray(src, dtype=np.uint32)
             dst = np.ascontiguousarray(dst, dtype=np.uint32)
             flags, m = 0, len(src)
+        flags |= (GJ_BUILD_UNDIRECTED if undirected else 0) | (GJ_BUILD_DEGREE_ORDER if degree_order else 0)
         ctx.check(_lib.gj_graph_build(ctx._h, _ptr(src), _ptr(dst), m, num_vertices, flags,
                                       ctypes.byref(h)), "gj_graph_build")
         self._hd = _Handle(h, _lib.gj_graph_destroy, (ctx._hd,))
@@ -290,6 +306,12 @@ class Graph(_Owner):
         return {"edges": e.value, "vertices": n.value, "max_out": mo.value,
                 "max_in": mi.value, "version": v.value}
 
+    def vertex_ids(self):
+        """Old id of every vertex id (gj_graph_vertex_ids), a numpy array."""
+        out = np.empty(self.num_vertices, dtype=np.uint32)
+        self.ctx.check(_lib.gj_graph_vertex_ids(self._h, _np_ptr(out), 0), "gj_graph_vertex_ids")
+        return out
+
     def csr_ptrs(self, reverse=False):
         rp, col, row = _vp(), _vp(), _vp()
         self.ctx.check(_lib.gj_graph_csr(self._h, int(reverse), ctypes.byref(rp), ctypes.byref(col),
@@ -299,18 +321,22 @@ class Graph(_Owner):
 
 
 class Query(_Owner):
-    """Q(a_0..a_{m-1}) := edge(s, d), ... with a global order (gj_query_register)."""
+    """Q(a_0..a_{m-1}) := edge(s, d), ... with a global order and optional
+    inequalities less = [(x, y), ...]: value of a_x below that of a_y
+    (gj_query_register_ex)."""
 
-    def __init__(self, ctx, num_attrs, atoms, order=None):
+    def __init__(self, ctx, num_attrs, atoms, order=None, less=()):
         self.ctx = ctx
         self.num_attrs = num_attrs
         self.atoms = [tuple(a) for a in atoms]
         self.order = list(range(num_attrs)) if order is None else list(order)
+        self.less = [tuple(x) for x in less]
         arr = (Atom * len(self.atoms))(*[Atom(s, d) for s, d in self.atoms])
+        lt = (Less * max(len(self.less), 1))(*[Less(x, y) for x, y in self.less])
         o = np.array(self.order, dtype=np.uint8)
         h = _vp()
-        ctx.check(_lib.gj_query_register(ctx._h, num_attrs, arr, len(self.atoms), _np_ptr(o),
-                                         ctypes.byref(h)), "gj_query_register")
+        ctx.check(_lib.gj_query_register_ex(ctx._h, num_attrs, arr, len(self.atoms), _np_ptr(o), lt,
+                                            len(self.less), ctypes.byref(h)), "gj_query_register_ex")
         self._hd = _Handle(h, _lib.gj_query_destroy, (ctx._hd,))
 
 

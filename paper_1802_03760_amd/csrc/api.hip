@@ -212,9 +212,13 @@ gj_status gj_graph_build(gj_ctx* c, const uint32_t* src, const uint32_t* dst, ui
   *out = nullptr;
   gj_graph* g = nullptr;
   gj_status s = guarded(c, [&] {
-    GJ_CHECK((flags & ~GJ_INPUT_DEVICE) == 0, GJ_EINVAL, "unknown or unsupported graph flags");
+    GJ_CHECK((flags & ~(GJ_INPUT_DEVICE | GJ_BUILD_UNDIRECTED | GJ_BUILD_DEGREE_ORDER)) == 0, GJ_EINVAL,
+             "unknown or unsupported graph flags");
     GJ_CHECK(nv > 0, GJ_EINVAL, "num_vertices must be positive");
     GJ_CHECK(m < (1ull << 32), GJ_EUNSUPPORTED, "graphs of 2^32 edges or more are not supported");
+    bool sym = (flags & (GJ_BUILD_UNDIRECTED | GJ_BUILD_DEGREE_ORDER)) != 0;
+    GJ_CHECK(!sym || m < (1ull << 31), GJ_EUNSUPPORTED,
+             "undirected builds of 2^31 input edges or more are not supported");
     GJ_CHECK(m == 0 || (src && dst), GJ_EINVAL, "null edge arrays");
     g = new gj_graph();
     g->ctx = c;
@@ -228,7 +232,11 @@ gj_status gj_graph_build(gj_ctx* c, const uint32_t* src, const uint32_t* dst, ui
       ds = s2;
       dd = d2;
     }
-    gj::graph_build(c, g, ds, dd, m);
+    if (sym)
+      gj::graph_build_sym(c, g, ds, dd, m, (flags & GJ_BUILD_DEGREE_ORDER) != 0,
+                          (flags & GJ_BUILD_UNDIRECTED) != 0);
+    else
+      gj::graph_build(c, g, ds, dd, m);
     GJ_HIP(hipStreamSynchronize(c->stream));
   });
   if (s != GJ_OK) {
@@ -268,11 +276,37 @@ void gj_graph_destroy(gj_graph* g) {
     (void)hipStreamSynchronize(g->ctx->stream);
   }
   for (auto& v : g->ver) gj::version_free(v);
+  gj::dev_free(g->old_of_new);
   delete g;
+}
+
+gj_status gj_graph_vertex_ids(const gj_graph* g, uint32_t* old_of_new, int out_on_device) {
+  if (!g || !old_of_new) return GJ_EINVAL;
+  gj_ctx* c = g->ctx;
+  return guarded(c, [&] {
+    uint64_t bytes = (uint64_t)g->n * sizeof(uint32_t);
+    if (g->old_of_new) {
+      GJ_HIP(hipMemcpyAsync(old_of_new, g->old_of_new, bytes,
+                            out_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+      GJ_HIP(hipStreamSynchronize(c->stream));
+    } else if (!out_on_device) {
+      for (uint32_t i = 0; i < g->n; ++i) old_of_new[i] = i;
+    } else {
+      std::vector<uint32_t> id(g->n);
+      for (uint32_t i = 0; i < g->n; ++i) id[i] = i;
+      GJ_HIP(hipMemcpyAsync(old_of_new, id.data(), bytes, hipMemcpyHostToDevice, c->stream));
+      GJ_HIP(hipStreamSynchronize(c->stream));
+    }
+  });
 }
 
 gj_status gj_query_register(gj_ctx* c, uint32_t num_attrs, const gj_atom* atoms, uint32_t num_atoms,
                             const uint8_t* order, gj_query** out) {
+  return gj_query_register_ex(c, num_attrs, atoms, num_atoms, order, nullptr, 0, out);
+}
+
+gj_status gj_query_register_ex(gj_ctx* c, uint32_t num_attrs, const gj_atom* atoms, uint32_t num_atoms,
+                               const uint8_t* order, const gj_less* less, uint32_t num_less, gj_query** out) {
   if (!c || !out) return GJ_EINVAL;
   *out = nullptr;
   gj_query* q = nullptr;
@@ -291,6 +325,12 @@ gj_status gj_query_register(gj_ctx* c, uint32_t num_attrs, const gj_atom* atoms,
       GJ_CHECK(atoms[i].src_attr < m && atoms[i].dst_attr < m, GJ_EINVAL, "atom attribute out of range");
       GJ_CHECK(atoms[i].src_attr != atoms[i].dst_attr, GJ_EINVAL, "atom over one attribute twice");
     }
+    GJ_CHECK(num_less <= GJ_MAX_LESS, GJ_EINVAL, "more than 28 inequalities");
+    GJ_CHECK(less || num_less == 0, GJ_EINVAL, "null inequalities");
+    for (uint32_t i = 0; i < num_less; ++i) {
+      GJ_CHECK(less[i].lo_attr < m && less[i].hi_attr < m, GJ_EINVAL, "inequality attribute out of range");
+      GJ_CHECK(less[i].lo_attr != less[i].hi_attr, GJ_EINVAL, "inequality over one attribute twice");
+    }
     for (int j = 1; j < m; ++j) {
       bool any = false;
       for (uint32_t i = 0; i < num_atoms; ++i)
@@ -303,6 +343,7 @@ gj_status gj_query_register(gj_ctx* c, uint32_t num_attrs, const gj_atom* atoms,
     q->m = m;
     q->atoms.assign(atoms, atoms + num_atoms);
     q->order.assign(order, order + m);
+    if (num_less) q->less.assign(less, less + num_less);
     // plan limits are checked here so that run time never fails on them
     gj::PlanHCheck(q);
   });

@@ -156,6 +156,7 @@ __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, 
         uint32_t key = x[q.filt.key[a]], val = x[q.filt.val[a]];
         keep = contains_u32(q.filt.adj[a], q.filt.rp[a][key], q.filt.rp[a][key + 1], val);
       }
+      keep = keep && seed_ineq_ok(q.filt.above, q.filt.below, x0, x1);
       fin = q.m == 2;
     }
     a_pre.add(pre, r * kStat + 2, 1, valid && keep, true);
@@ -291,7 +292,7 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
         }
         uint32_t v = F[(uint64_t)col_m * cap + p];
         e = adj_m[rp_m[v] + k];
-        keep = true;
+        keep = ineq_ok(F, cap, p, d.above, d.below, e);
 #pragma unroll
         for (int a = 0; a < kMaxBind; ++a) {
           if (a < d.k && a != am && keep) {

@@ -371,7 +371,7 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
       for (int i = 0; i < (int)q->atoms.size() && ok; ++i) {
         plans.push_back(make_plan(q, delta_order(q, i), i));
         const PlanH& P = plans.back();
-        ok = P.filters.empty() && P.bind[2].size() == 2 && P.bind[2][0].col != P.bind[2][1].col;
+        ok = P.filters.empty() && !P.has_ineq() && P.bind[2].size() == 2 && P.bind[2][0].col != P.bind[2][1].col;
       }
       if (!ok) continue;
       gj_stats acc{};

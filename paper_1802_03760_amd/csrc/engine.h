@@ -24,6 +24,14 @@ struct PlanH {
   bool seed_fwd = true;
   std::vector<FilterH> filters;
   std::vector<std::vector<BindH>> bind;
+  // inequalities checked when position j is bound: the value there must
+  // exceed the prefix columns in above[j] and stay below those in below[j]
+  std::vector<uint32_t> above, below;
+  bool has_ineq() const {
+    for (int j = 0; j < m; ++j)
+      if (above[j] | below[j]) return true;
+    return false;
+  }
 };
 
 PlanH make_plan(const gj_query* q, const std::vector<int>& order, int forced_seed);

@@ -41,6 +41,16 @@ PlanH make_plan(const gj_query* q, const std::vector<int>& order, int forced_see
       P.bind[j].push_back({i, pos[d], 1});  // edge(x, y): x in in(y)
     }
   }
+  // a_x < a_y is checked when the later of the two is bound (Sec. 5.4)
+  P.above.assign(q->m, 0u);
+  P.below.assign(q->m, 0u);
+  for (const gj_less& l : q->less) {
+    int jx = pos[l.lo_attr], jy = pos[l.hi_attr];
+    if (jy > jx)
+      P.above[jy] |= 1u << jx;
+    else
+      P.below[jx] |= 1u << jy;
+  }
   for (int j = 2; j < q->m; ++j)
     GJ_CHECK(P.bind[j].size() <= (size_t)kMaxBind, GJ_EUNSUPPORTED, "more than 8 atoms bind one attribute");
   GJ_CHECK(P.filters.size() <= (size_t)kMaxBind, GJ_EUNSUPPORTED, "more than 8 atoms over the first two attributes");
@@ -52,6 +62,8 @@ StageDesc stage_desc(const PlanH& P, const Views& V, int j) {
   memset(&d, 0, sizeof(d));
   d.j = j;
   d.k = (int)P.bind[j].size();
+  d.above = P.above[j];
+  d.below = P.below[j];
   for (int a = 0; a < d.k; ++a) {
     const BindH& b = P.bind[j][a];
     const Version& v = V.of(b.atom);
@@ -71,6 +83,8 @@ SeedFilter seed_filter(const PlanH& P, const Views& V) {
   SeedFilter f;
   memset(&f, 0, sizeof(f));
   f.n = (int)P.filters.size();
+  f.above = P.above[1];
+  f.below = P.below[1];
   for (int a = 0; a < f.n; ++a) {
     const Version& v = V.of(P.filters[a].atom);
     f.key[a] = P.filters[a].key;
@@ -278,7 +292,7 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
   bool collect = mode == GJ_MODE_ENUMERATE;
   // Owner-grouped kernel: counting a three-attribute query over all seed
   // edges whose last attribute is bound by one atom on each seed attribute.
-  if (!collect && c->strategy != 1 && P.m == 3 && P.filters.empty() && lo == 0 && hi == v.m &&
+  if (!collect && c->strategy != 1 && P.m == 3 && P.filters.empty() && !P.has_ineq() && lo == 0 && hi == v.m &&
       P.bind[2].size() == 2 && P.bind[2][0].col != P.bind[2][1].col) {
     const BindH& A = P.bind[2][0].col == 0 ? P.bind[2][0] : P.bind[2][1];
     const BindH& B = P.bind[2][0].col == 0 ? P.bind[2][1] : P.bind[2][0];

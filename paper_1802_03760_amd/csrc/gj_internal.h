@@ -43,6 +43,7 @@ struct Error {
 struct StageDesc {
   int j;                 // bound columns
   int k;                 // binding atoms (1..kMaxBind)
+  uint32_t above, below;  // inequalities: the new value exceeds / stays below these columns
   int col[kMaxBind];
   const uint32_t* rp[kMaxBind];
   const uint32_t* adj[kMaxBind];
@@ -52,6 +53,7 @@ struct StageDesc {
 // other than the seed atom): keep (x0, x1) iff x[val] is in adj[rp[x[key]]..].
 struct SeedFilter {
   int n;
+  uint32_t above, below;  // bit 0: x1 must exceed / stay below x0 (inequalities)
   int key[kMaxBind];
   int val[kMaxBind];
   const uint32_t* rp[kMaxBind];
@@ -125,6 +127,7 @@ constexpr int kMaxVersions = 8;
 struct gj_graph {
   gj_ctx* ctx = nullptr;
   uint32_t n = 0;
+  uint32_t* old_of_new = nullptr;  // device, n entries: renamed by degree, else null
   gj::Version ver[kMaxVersions];
   int cur = 0;
   uint64_t version = 0;
@@ -134,6 +137,7 @@ struct gj_query {
   int m = 0;
   std::vector<gj_atom> atoms;
   std::vector<int> order;
+  std::vector<gj_less> less;  // value(lo_attr) < value(hi_attr)
 };
 
 namespace gj {
@@ -185,6 +189,12 @@ void sort_kv_u32(gj_ctx* c, uint32_t*& key, uint32_t*& val, uint32_t*& key_alt,
 
 // graph.hip
 void graph_build(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m);
+// The input read as undirected: its symmetric edge set (both directions of
+// every distinct pair), or with degree_order the vertices renamed by ascending
+// (degree, id) and each pair kept once from the lower new id to the higher
+// (both directions when `undirected`).  Sets g->old_of_new when renaming.
+void graph_build_sym(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
+                     bool degree_order, bool undirected);
 void version_alloc(Version& v, uint32_t n, uint64_t cap);
 void version_free(Version& v);
 

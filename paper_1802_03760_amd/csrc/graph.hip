@@ -168,4 +168,111 @@ void graph_build(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32_t* 
   version_finish(c, v, n, false);
 }
 
+// ---------------------------------------------------------------- renaming by degree (Sec. 5.4)
+// Both directions of every input edge as (src, dst) keys.
+__global__ void k_make_sym_keys(const uint32_t* __restrict__ src, const uint32_t* __restrict__ dst, uint64_t m,
+                                uint32_t n, uint64_t* __restrict__ keys, uint32_t* __restrict__ bad) {
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    uint32_t s = src[i], d = dst[i];
+    if (s >= n || d >= n) atomicOr(bad, 1u);
+    keys[i] = ((uint64_t)s << 32) | d;
+    keys[m + i] = ((uint64_t)d << 32) | s;
+  }
+}
+
+// (degree, id) of every vertex; the degree is its row length in the
+// symmetric edge set, i.e. the number of distinct neighbours
+__global__ void k_degree_keys(const uint32_t* __restrict__ rp, uint32_t n, uint64_t* __restrict__ vkeys) {
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride)
+    vkeys[v] = ((uint64_t)(rp[v + 1] - rp[v]) << 32) | v;
+}
+
+// new id = rank in (degree, id) order
+__global__ void k_rank_ids(const uint64_t* __restrict__ vkeys, uint32_t n, uint32_t* __restrict__ old_of_new,
+                           uint32_t* __restrict__ new_of_old) {
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint32_t o = (uint32_t)vkeys[i];
+    old_of_new[i] = o;
+    new_of_old[o] = (uint32_t)i;
+  }
+}
+
+// Renames both ends; with `up_only` an edge that does not go from a lower new
+// id to a higher one is written as a self-loop, which the build drops.
+__global__ void k_rename_edges(const uint32_t* __restrict__ row, const uint32_t* __restrict__ col, uint64_t m,
+                               const uint32_t* __restrict__ new_of_old, int up_only, uint32_t* __restrict__ osrc,
+                               uint32_t* __restrict__ odst) {
+  uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride) {
+    uint32_t u = new_of_old[row[i]], v = new_of_old[col[i]];
+    osrc[i] = u;
+    odst[i] = (up_only && !(u < v)) ? u : v;
+  }
+}
+
+void graph_build_sym(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
+                     bool degree_order, bool undirected) {
+  uint32_t n = g->n;
+  int bits = bits_for(n);
+  uint64_t m2 = 2 * m;
+  struct Temps {  // freed on every exit, errors included
+    std::vector<void*> p;
+    ~Temps() {
+      for (void* x : p) dev_free(x);
+    }
+  } tmp;
+  auto alloc = [&](size_t bytes) {
+    void* p = dev_alloc(bytes ? bytes : 1);
+    tmp.p.push_back(p);
+    return p;
+  };
+  uint64_t* keys = (uint64_t*)alloc((m2 + 1) * sizeof(uint64_t));
+  uint64_t* alt = (uint64_t*)alloc((m2 + 1) * sizeof(uint64_t));
+  uint32_t* flags = (uint32_t*)alloc((m2 + 1) * sizeof(uint32_t));
+  uint64_t* off = (uint64_t*)alloc((m2 + 1) * sizeof(uint64_t));
+  uint32_t* bad = (uint32_t*)alloc(sizeof(uint32_t));
+  GJ_HIP(hipMemsetAsync(bad, 0, sizeof(uint32_t), c->stream));
+  unsigned gr = grid_for(m, kBlock, 1u << 16), gr2 = grid_for(m2, kBlock, 1u << 16);
+  if (m) k_make_sym_keys<<<gr, kBlock, 0, c->stream>>>(d_src, d_dst, m, n, keys, bad);
+  GJ_HIP(hipGetLastError());
+  uint32_t hbad = 0;
+  read_bytes(c, &hbad, bad, sizeof(hbad));
+  GJ_CHECK(!hbad, GJ_EINVAL, "vertex id >= num_vertices");
+  // the symmetric edge set: both directions of every distinct pair, no loops
+  uint64_t* sorted = sort_u64(c, keys, alt, m2, bits, bits);
+  uint64_t* other = sorted == keys ? alt : keys;
+  if (m2) k_unique_flags<<<gr2, kBlock, 0, c->stream>>>(sorted, m2, flags);
+  scan_u32_to_u64(c, flags, off, m2);
+  uint64_t ms = read_u64(c, off + m2);
+  uint32_t* srow = (uint32_t*)alloc((ms + 1) * sizeof(uint32_t));
+  uint32_t* scol = (uint32_t*)alloc((ms + 1) * sizeof(uint32_t));
+  if (m2) k_compact_edges<<<gr2, kBlock, 0, c->stream>>>(sorted, m2, flags, off, srow, scol, other);
+  const uint32_t *es = srow, *ed = scol;
+  if (degree_order) {
+    uint32_t* rp = (uint32_t*)alloc(((uint64_t)n + 1) * sizeof(uint32_t));
+    uint64_t* vk = (uint64_t*)alloc((uint64_t)n * sizeof(uint64_t));
+    uint64_t* vk2 = (uint64_t*)alloc((uint64_t)n * sizeof(uint64_t));
+    uint32_t* new_of_old = (uint32_t*)alloc((uint64_t)n * sizeof(uint32_t));
+    unsigned gn = grid_for((uint64_t)n + 1, kBlock, 1u << 16);
+    k_rowptr<<<gn, kBlock, 0, c->stream>>>(srow, ms, n, rp);
+    k_degree_keys<<<gn, kBlock, 0, c->stream>>>(rp, n, vk);
+    uint64_t* vs = sort_u64(c, vk, vk2, n, bits, bits);
+    g->old_of_new = (uint32_t*)dev_alloc((uint64_t)n * sizeof(uint32_t));
+    k_rank_ids<<<gn, kBlock, 0, c->stream>>>(vs, n, g->old_of_new, new_of_old);
+    uint32_t* osrc = (uint32_t*)alloc((ms + 1) * sizeof(uint32_t));
+    uint32_t* odst = (uint32_t*)alloc((ms + 1) * sizeof(uint32_t));
+    if (ms)
+      k_rename_edges<<<grid_for(ms, kBlock, 1u << 16), kBlock, 0, c->stream>>>(srow, scol, ms, new_of_old,
+                                                                               undirected ? 0 : 1, osrc, odst);
+    es = osrc;
+    ed = odst;
+  }
+  GJ_HIP(hipGetLastError());
+  graph_build(c, g, es, ed, ms);
+  GJ_HIP(hipStreamSynchronize(c->stream));
+}
+
 }  // namespace gj

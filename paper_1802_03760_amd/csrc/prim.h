@@ -8,6 +8,29 @@
 namespace gj {
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Inequality filters of symmetry breaking (Sec. 5.4): value e joining the
+// prefix in slot p of a column-major frontier must exceed prefix column c
+// for every bit c of `above` and stay below it for every bit of `below`.
+__device__ __forceinline__ bool ineq_ok(const uint32_t* __restrict__ F, uint64_t stride, uint64_t p,
+                                        uint32_t above, uint32_t below, uint32_t e) {
+  if (!(above | below)) return true;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    if (((above | below) >> c) & 1) {
+      uint32_t o = F[(uint64_t)c * stride + p];
+      if ((above >> c) & 1) ok = ok && e > o;
+      if ((below >> c) & 1) ok = ok && e < o;
+    }
+  }
+  return ok;
+}
+
+// Both seed attributes at hand: bit 0 of the masks relates x1 to x0.
+__device__ __forceinline__ bool seed_ineq_ok(uint32_t above, uint32_t below, uint32_t x0, uint32_t x1) {
+  return (!(above & 1) || x1 > x0) && (!(below & 1) || x1 < x0);
+}
 __device__ __forceinline__ int wave_id() { return threadIdx.x >> 6; }
 
 __device__ __forceinline__ uint64_t lanemask_lt() {

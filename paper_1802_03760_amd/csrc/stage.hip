@@ -33,7 +33,7 @@ __global__ void k_seed_flags(const uint32_t* __restrict__ x0, const uint32_t* __
         ok = contains_u32(f.adj[a], f.rp[a][key], f.rp[a][key + 1], val);
       }
     }
-    flags[i] = ok ? 1u : 0u;
+    flags[i] = (ok && seed_ineq_ok(f.above, f.below, x[0], x[1])) ? 1u : 0u;
   }
 }
 
@@ -109,7 +109,7 @@ __device__ __forceinline__ Cand resolve(const uint32_t* __restrict__ F, uint64_t
 
 __device__ __forceinline__ bool intersect_all(const uint32_t* __restrict__ F, uint64_t stride, const StageDesc& d,
                                               const Cand& c) {
-  bool keep = true;
+  bool keep = ineq_ok(F, stride, c.p, d.above, d.below, c.e);
 #pragma unroll
   for (int a = 0; a < kMaxBind; ++a) {
     if (a < d.k && a != c.am && keep) {
