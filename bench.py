@@ -109,6 +109,54 @@ def batched_vs_plain(gj, ctx, G, nreq, seed, log, max_width=1000):
             "speedup": tp / tb, "tuning": tune, "fallbacks": fallbacks}
 
 
+def symmetry_breaking(gj, ctx, scale, log, full=False):
+    """Undirected triangle and 4-clique counts on R-MAT (seed 0) read as an
+    undirected graph, three ways (Sec. 5.4): the plain query over the
+    symmetric graph (each clique |Aut| times), the query with the inequalities
+    a1 < a2 < ... over it, and the plain query over the degree-ordered graph.
+    The plain symmetric 4-clique count runs only with `full` (minutes at
+    scale 22)."""
+    import synth
+    src, dst = synth.rmat_draws(scale, seed=0)
+    n = 1 << scale
+    out = {"scale": scale}
+    t0 = time.perf_counter()
+    Gu = gj.Graph(ctx, src, dst, n, undirected=True)
+    out["undirected_build_ms"] = (time.perf_counter() - t0) * 1e3
+    t0 = time.perf_counter()
+    Go = gj.Graph(ctx, src, dst, n, degree_order=True)
+    out["degree_order_build_ms"] = (time.perf_counter() - t0) * 1e3
+    out["undirected_edges"] = Gu.info()["edges"]
+    out["oriented_edges"], out["oriented_max_out"] = Go.info()["edges"], Go.info()["max_out"]
+    del src, dst
+    tri = (3, [(0, 1), (1, 2), (0, 2)], [0, 1, 2])
+    k4 = (4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)], [0, 1, 2, 3])
+
+    def timed(G, q, less=()):
+        Q = gj.Query(ctx, *q, less=less)
+        gj.count(ctx, G, Q, 0, 1000)
+        t = time.perf_counter()
+        r = gj.count(ctx, G, Q)
+        dt = time.perf_counter() - t
+        ext = sum(r["extensions"])
+        return {"matches": r["matches"], "extensions": ext, "s": dt, "extensions_per_s": ext / dt}
+
+    for name, q, aut in (("triangle", tri, 6), ("4-clique", k4, 24)):
+        less = [(i, i + 1) for i in range(q[0] - 1)]
+        res = {"oriented": timed(Go, q), "undirected_less": timed(Gu, q, less)}
+        if name == "triangle" or full:
+            res["undirected_plain"] = timed(Gu, q)
+            assert res["undirected_plain"]["matches"] == aut * res["oriented"]["matches"]
+        assert res["undirected_less"]["matches"] == res["oriented"]["matches"]
+        out[name] = res
+        log("symmetry breaking, %s at scale %d: %d undirected; oriented %.3f s, inequalities %.3f s%s"
+            % (name, scale, res["oriented"]["matches"], res["oriented"]["s"], res["undirected_less"]["s"],
+               ", plain symmetric %.3f s" % res["undirected_plain"]["s"] if "undirected_plain" in res else ""))
+    Gu.close()
+    Go.close()
+    return out
+
+
 def update_latency(gj, src, dst, n, scale, nbatch, log):
     """Update stream (sizes log-uniform in [1, 100,000], 10% deletions, seed 1)
     maintaining the triangle count: one gj_apply_updates at a time with each
@@ -294,6 +342,10 @@ def main():
     ap.add_argument("--serve-skip", type=float, default=0.0,
                     help="fraction of the edge range (the hub rows) where no count slice starts")
     ap.add_argument("--latency-batches", type=int, default=200)
+    ap.add_argument("--sym-scale", type=int, default=20,
+                    help="R-MAT scale of the symmetry-breaking leg (0: skip)")
+    ap.add_argument("--sym-full", action="store_true",
+                    help="also count 4-cliques with the plain query over the symmetric graph")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of known "
                          "traffic that scales the HBM counters of a profiling run")
@@ -381,6 +433,8 @@ def main():
                                 args.serve_max_width, args.serve_max_update, args.serve_skip)
         del s_src, s_dst
 
+    sym = symmetry_breaking(gj, ctx, args.sym_scale, log, args.sym_full) if args.sym_scale else None
+
     # delta-batch latency: update stream on the same graph
     lat = []
     qd = [q]
@@ -436,6 +490,7 @@ def main():
         "batched": batched,
         "update_latency": latency,
         "serving": serving,
+        "symmetry_breaking": sym,
     }
     print(json.dumps(out), flush=True)
 
