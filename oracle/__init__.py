@@ -61,7 +61,7 @@ def _load():
         L.or_query_valid.restype = i32
         L.or_query_valid.argtypes = [i32, vp, vp, i32, vp, vp, vp, i32]
         L.or_run.restype = vp
-        L.or_run.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, i32, i32, u64, u64, i32, ip]
+        L.or_run.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, i32, i32, i32, u64, u64, i32, ip]
         L.or_run_textbook.restype = vp
         L.or_run_textbook.argtypes = [vp, i32, vp, vp, i32, vp, vp, ip]
         L.or_delta.restype = vp
@@ -172,13 +172,15 @@ def _take(res, m, want_rows, want_signs=False):
     return out
 
 
-def run(graph, query, collect=False, seed_lo=0, seed_hi=None, threads=1):
-    """Edge-seeded Generic Join; rows in attribute-index order, sorted."""
+def run(graph, query, collect=False, seed_lo=0, seed_hi=None, threads=1, factorise=False):
+    """Edge-seeded Generic Join; rows in attribute-index order, sorted.
+    factorise: count a trailing run of independent attributes as a product
+    of their extension counts (counts only)."""
     m, s, d, k, o, lx, ly, nl = _query_arrays(query)
     st = ctypes.c_int(0)
     hi = (1 << 64) - 1 if seed_hi is None else seed_hi
     res = _load().or_run(graph._h, m, _p(s), _p(d), k, _p(o), _p(lx), _p(ly), nl, int(collect),
-                         seed_lo, hi, threads, ctypes.byref(st))
+                         int(factorise), seed_lo, hi, threads, ctypes.byref(st))
     if st.value != 0:
         if res:
             _load().or_result_free(res)

@@ -29,6 +29,13 @@
 //    binds both attributes is dropped unless the inequality holds.  The
 //    filters do not change which set is proposed from, so the extension
 //    counters are those of the query without them.
+//  * Factorised counting (Sec. 5.4): when the last attributes of the order
+//    share no atom and no inequality, each one's extensions depend only on the
+//    prefix before them, so a count multiplies their extension-set sizes
+//    instead of enumerating the combinations.  Counters then cover the work
+//    done: extensions[t] sums the smallest set of attribute t over the
+//    prefixes where the trailing run starts; the prefixes inside the run are
+//    not materialised (0); prefixes[m] is the count.
 //
 // Readings where the paper is silent (each is listed with its reason in the
 // design notes): count-minimisation ties go to the lowest atom index; the
@@ -153,6 +160,7 @@ struct Plan {
   std::vector<int> filters;
   std::vector<std::vector<Binding>> bind;  // bind[j], j = 2..m-1
   std::vector<std::vector<Ineq>> ineq;     // ineq[j], j = 1..m-1
+  int fact_from = 0;  // first position of a trailing independent run of >= 2, else 0
 };
 
 // Does value e at position j satisfy the inequalities against the prefix?
@@ -190,6 +198,23 @@ Plan make_plan(const Query& q) {
     else  // edge(x, y): x ranges over in(y)
       p.bind[j].push_back({i, pos[at.d], false});
   }
+  // the longest run of trailing positions whose attributes share no atom and
+  // no inequality (positions 0 and 1 are the seed)
+  auto linked = [&](int x, int y) {
+    for (auto& at : q.atoms)
+      if ((at.s == x && at.d == y) || (at.s == y && at.d == x)) return true;
+    for (auto& l : q.less)
+      if ((l.s == x && l.d == y) || (l.s == y && l.d == x)) return true;
+    return false;
+  };
+  int j0 = q.m - 1;
+  while (j0 - 1 >= 2) {
+    bool free_ = true;
+    for (int t = j0; t < q.m; ++t) free_ = free_ && !linked(q.order[j0 - 1], q.order[t]);
+    if (!free_) break;
+    --j0;
+  }
+  p.fact_from = q.m - j0 >= 2 ? j0 : 0;
   // a_x < a_y is checked when the later of the two is bound
   p.ineq.assign(q.m, {});
   for (const Atom& l : q.less) {
@@ -241,10 +266,48 @@ struct Counters {
 // Count-minimisation picks the smallest extension set (ties: lowest atom
 // index), proposes its values in ascending order and keeps a value only if
 // every other binding set contains it (Sec. 3.1 steps; Sec. 4.1 operators).
+// Count-minimisation and intersection of position j's sets for one prefix:
+// returns the number of values kept and adds the proposals to the counters.
+uint64_t count_extensions(const Plan& plan, const Views& views, int j,
+                          const std::vector<uint32_t>& prefix, Counters& c) {
+  const std::vector<Binding>& B = plan.bind[j];
+  size_t best = 0;
+  for (size_t i = 1; i < B.size(); ++i) {
+    size_t ci = ext_list(views, B[i], prefix[B[i].col]).size();
+    size_t cb = ext_list(views, B[best], prefix[B[best].col]).size();
+    if (ci < cb) best = i;
+  }
+  const std::vector<uint32_t>& prop = ext_list(views, B[best], prefix[B[best].col]);
+  c.add(c.extensions[j], prop.size());
+  uint64_t kept = 0;
+  for (uint32_t e : prop) {
+    bool keep = true;
+    for (size_t i = 0; i < B.size() && keep; ++i) {
+      if (i == best) continue;
+      const std::vector<uint32_t>& l = ext_list(views, B[i], prefix[B[i].col]);
+      keep = std::binary_search(l.begin(), l.end(), e);
+    }
+    if (keep && ineq_ok(plan, j, prefix, e)) ++kept;
+  }
+  return kept;
+}
+
 void extend(const Query& q, const Plan& plan, const Views& views, int j,
             std::vector<uint32_t>& prefix, Counters& c, bool collect,
-            std::vector<uint32_t>& rows) {
+            std::vector<uint32_t>& rows, bool factorise = false) {
   c.add(c.prefixes[j], 1);
+  if (factorise && !collect && j == plan.fact_from && j > 0) {
+    // the trailing attributes are independent given the prefix: the number
+    // of matches extending it is the product of their extension counts
+    uint64_t prod = 1;
+    for (int t = j; t < q.m; ++t) {
+      uint64_t k = count_extensions(plan, views, t, prefix, c);
+      if (__builtin_mul_overflow(prod, k, &prod)) c.overflow = true;
+    }
+    c.add(c.matches, prod);
+    c.add(c.prefixes[q.m], prod);
+    return;
+  }
   if (j == q.m) {
     c.add(c.matches, 1);
     if (collect) {
@@ -273,7 +336,7 @@ void extend(const Query& q, const Plan& plan, const Views& views, int j,
     }
     if (!keep || !ineq_ok(plan, j, prefix, e)) continue;
     prefix.push_back(e);
-    extend(q, plan, views, j + 1, prefix, c, collect, rows);
+    extend(q, plan, views, j + 1, prefix, c, collect, rows, factorise);
     prefix.pop_back();
   }
 }
@@ -290,7 +353,7 @@ bool pair_ok(const Query& q, const Views& v, int atom, uint32_t x0, uint32_t x1)
 // atom's edge list, in the seed atom's version.
 void run_seeds(const Query& q, const Plan& plan, const Views& views,
                uint64_t lo, uint64_t hi, Counters& c, bool collect,
-               std::vector<uint32_t>& rows) {
+               std::vector<uint32_t>& rows, bool factorise) {
   const Graph& g = views.of(plan.seed_atom);
   const auto& E = plan.seed_fwd ? g.fwd_edges : g.rev_edges;
   std::vector<uint32_t> prefix;
@@ -302,7 +365,7 @@ void run_seeds(const Query& q, const Plan& plan, const Views& views,
     prefix.assign({x0});
     if (!ok || !ineq_ok(plan, 1, prefix, x1)) continue;
     prefix.assign({x0, x1});
-    extend(q, plan, views, 2, prefix, c, collect, rows);
+    extend(q, plan, views, 2, prefix, c, collect, rows, factorise);
   }
 }
 
@@ -406,8 +469,8 @@ int or_query_valid(int num_attrs, const uint8_t* as, const uint8_t* ad, int num_
 // result does not depend on the thread count.
 void* or_run(const void* gp, int num_attrs, const uint8_t* as, const uint8_t* ad,
              int num_atoms, const uint8_t* order, const uint8_t* lx, const uint8_t* ly,
-             int num_less, int collect, uint64_t seed_lo, uint64_t seed_hi, int threads,
-             int* status) {
+             int num_less, int collect, int factorise, uint64_t seed_lo, uint64_t seed_hi,
+             int threads, int* status) {
   const Graph* g = (const Graph*)gp;
   Query q;
   if (!parse_query(num_attrs, as, ad, num_atoms, order, lx, ly, num_less, q)) {
@@ -427,7 +490,9 @@ void* or_run(const void* gp, int num_attrs, const uint8_t* as, const uint8_t* ad
   std::vector<std::thread> pool;
   for (int t = 0; t < threads; ++t) {
     uint64_t a = lo + span * t / threads, b = lo + span * (t + 1) / threads;
-    pool.emplace_back([&, t, a, b] { run_seeds(q, plan, views, a, b, cs[t], collect != 0, rs[t]); });
+    pool.emplace_back([&, t, a, b] {
+      run_seeds(q, plan, views, a, b, cs[t], collect != 0, rs[t], factorise != 0);
+    });
   }
   for (auto& th : pool) th.join();
   Result* r = new Result();

@@ -70,3 +70,23 @@ SYM_LESS = {
 
 def with_less(q, less):
     return (q[0], q[1], list(q[2]), list(less))
+
+
+# Queries whose last attributes share no atom, so counts factorise (Sec. 5.4):
+# the house (trailing a4, a5), a 3-star (three out-neighbours of a1) and a fan
+# (a path a1 -> a2 with two out-neighbours of a2).
+STAR3 = (4, [(0, 1), (0, 2), (0, 3)], [0, 1, 2, 3])
+FAN = (4, [(0, 1), (1, 2), (1, 3)], [0, 1, 2, 3])
+FACTORISABLE = {"house": HOUSE, "star3": STAR3, "fan": FAN}
+
+
+def trailing_run(q):
+    """First position of the trailing run of attributes that share no atom and
+    no inequality (at least two of them, after the seed pair), else 0."""
+    m, atoms, order = q[0], q[1], q[2]
+    less = q[3] if len(q) > 3 else []
+    pairs = {frozenset(a) for a in atoms} | {frozenset(x) for x in less}
+    j0 = m - 1
+    while j0 - 1 >= 2 and all(frozenset((order[j0 - 1], order[t])) not in pairs for t in range(j0, m)):
+        j0 -= 1
+    return j0 if m - j0 >= 2 else 0
