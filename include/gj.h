@@ -78,6 +78,14 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   dQ_i binds the last attribute by one atom on each seed
  *                   attribute (the triangle shapes) on the owner-grouped
  *                   kernel, unless "strategy" is 1
+ *   "factorise"     gj_run counts: 1 counts a trailing run of at least two
+ *                   attributes that share no atom and no inequality as the
+ *                   product of their extension counts per prefix before the
+ *                   run (factorisation, Sec. 5.4): the same count, without
+ *                   enumerating the run's prefixes.  Counters then cover that
+ *                   work: prefixes inside the run are 0, extensions[t] sums
+ *                   the smallest set of position t over the prefixes where
+ *                   the run starts.  0 (default) enumerates
  * Returns GJ_EINVAL for an unknown key or out-of-range value. */
 gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
 

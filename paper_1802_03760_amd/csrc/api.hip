@@ -174,6 +174,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "delta_fused") {
       GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "delta_fused must be 0 or 1");
       c->delta_fused = (int)value;
+    } else if (k == "factorise") {
+      GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "factorise must be 0 or 1");
+      c->factorise = (int)value;
     } else if (k == "batch_cap") {
       GJ_CHECK(value >= 64 && value <= (1ll << 32), GJ_EINVAL, "batch_cap out of range");
       c->batch_cap = (uint64_t)value;
@@ -202,6 +205,7 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "batch_fallbacks") *value = (int64_t)c->batch_fallbacks;
     else if (k == "delta_fused") *value = c->delta_fused;
     else if (k == "delta_owner_min") *value = (int64_t)c->delta_owner_min;
+    else if (k == "factorise") *value = c->factorise;
     else throw Error{GJ_EINVAL, "unknown option " + k};
   });
 }
@@ -502,6 +506,7 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->batch_cap = src->batch_cap;
   dst->delta_fused = src->delta_fused;
   dst->delta_owner_min = src->delta_owner_min;
+  dst->factorise = src->factorise;
 }
 
 }  // namespace gj

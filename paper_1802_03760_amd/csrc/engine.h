@@ -27,6 +27,10 @@ struct PlanH {
   // inequalities checked when position j is bound: the value there must
   // exceed the prefix columns in above[j] and stay below those in below[j]
   std::vector<uint32_t> above, below;
+  // first position of a trailing run of >= 2 attributes that share no atom
+  // and no inequality (their extensions depend only on the prefix before the
+  // run, so counts may multiply), else 0
+  int fact_from = 0;
   bool has_ineq() const {
     for (int j = 0; j < m; ++j)
       if (above[j] | below[j]) return true;
@@ -85,6 +89,7 @@ class Runner {
 
  private:
   void stage(int j, uint64_t n);
+  void factorised(int j0, uint64_t n);
   void ensure_rows(uint64_t need);
   Level L[GJ_MAX_ATTRS + 1];
   RowMap map;

@@ -41,6 +41,22 @@ PlanH make_plan(const gj_query* q, const std::vector<int>& order, int forced_see
       P.bind[j].push_back({i, pos[d], 1});  // edge(x, y): x in in(y)
     }
   }
+  // trailing run of attributes that share no atom and no inequality
+  auto linked = [&](int x, int y) {
+    for (const gj_atom& at : q->atoms)
+      if ((at.src_attr == x && at.dst_attr == y) || (at.src_attr == y && at.dst_attr == x)) return true;
+    for (const gj_less& l : q->less)
+      if ((l.lo_attr == x && l.hi_attr == y) || (l.lo_attr == y && l.hi_attr == x)) return true;
+    return false;
+  };
+  int j0 = q->m - 1;
+  while (j0 - 1 >= 2) {
+    bool free_ = true;
+    for (int t = j0; t < q->m; ++t) free_ = free_ && !linked(order[j0 - 1], order[t]);
+    if (!free_) break;
+    --j0;
+  }
+  P.fact_from = q->m - j0 >= 2 ? j0 : 0;
   // a_x < a_y is checked when the later of the two is bound (Sec. 5.4)
   P.above.assign(q->m, 0u);
   P.below.assign(q->m, 0u);
@@ -221,6 +237,10 @@ void Runner::stage(int j, uint64_t n) {
     return;
   }
   if (n == 0) return;
+  if (!collect && !weighted && c->factorise && P.fact_from && j == P.fact_from) {
+    factorised(j, n);
+    return;
+  }
   StageDesc d = stage_desc(P, V, j);
   launch_count_min(c, l.F, l.cap, n, d, l.minc, l.mini);
   scan_u32_to_u64(c, l.minc, l.off, n);
@@ -257,6 +277,34 @@ void Runner::stage(int j, uint64_t n) {
       stage(j + 1, T);
     }
   }
+}
+
+// Factorised count (Sec. 5.4): the attributes at positions j0..m-1 share no
+// atom, so each one's extension set is a function of the prefix in P_j0 and a
+// prefix contributes the product of their extension counts.  Per trailing
+// attribute: count-minimisation, scan, and a propose pass that counts the
+// survivors of every prefix; then one pass sums the products.  The prefixes
+// inside the run are never materialised.
+void Runner::factorised(int j0, uint64_t n) {
+  Level& l = L[j0];
+  int T = P.m - j0;
+  uint32_t* cnt = (uint32_t*)ws_get(c, "fact_cnt", (uint64_t)T * l.cap * sizeof(uint32_t) + 16);
+  bool zero = false;
+  for (int t = j0; t < P.m; ++t) {
+    StageDesc d = stage_desc(P, V, t);  // its columns and inequalities all lie before j0
+    launch_count_min(c, l.F, l.cap, n, d, l.minc, l.mini);
+    scan_u32_to_u64(c, l.minc, l.off, n);
+    uint64_t W = read_u64(c, l.off + n);
+    st.extensions[t] += W;
+    if (W == 0) zero = true;
+    if (zero) continue;  // the products are all zero; the proposals are still counted
+    uint32_t* ct = cnt + (uint64_t)(t - j0) * l.cap;
+    GJ_HIP(hipMemsetAsync(ct, 0, n * sizeof(uint32_t), c->stream));
+    timer.start();
+    launch_propose(c, 3, l.F, l.cap, n, l.off, l.mini, d, 0, W, nullptr, ct, nullptr, nullptr);
+    timer.stop();
+  }
+  if (!zero) launch_factor_sum(c, cnt, l.cap, n, T, acc);
 }
 
 // counts: acc[0] unsigned matches, acc[1] signed weight sum

@@ -116,6 +116,7 @@ struct gj_ctx {
   uint64_t batch_fallbacks = 0;     // batches rerun depth-first after a level overflow
   int delta_fused = 1;              // count-only delta queries through the fused pipeline
   uint64_t delta_owner_min = 1ull << 17;  // changes from which triangle-shaped deltas use the owner kernel
+  int factorise = 0;  // gj_run counts: trailing independent attributes as products
 };
 
 // Resident versions of a graph: ver[cur] is current; an update reads it and
@@ -204,6 +205,10 @@ void launch_seed(gj_ctx* c, const uint32_t* x0, const uint32_t* x1, const int8_t
                  int8_t* Fw);
 void launch_count_min(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const StageDesc& d,
                       uint32_t* minc, uint8_t* mini);
+// Sum over the n prefixes of the product of T per-prefix counts
+// cnt[t * stride + p], added to acc[0].
+void launch_factor_sum(gj_ctx* c, const uint32_t* cnt, uint64_t stride, uint64_t n, int T,
+                       unsigned long long* acc);
 void launch_propose(gj_ctx* c, int mode, const uint32_t* F, uint64_t stride, uint64_t n, const uint64_t* off,
                     const uint8_t* mini, const StageDesc& d, uint64_t w0, uint64_t w1, uint64_t* mask,
                     uint32_t* wcnt, const int8_t* wt, unsigned long long* acc);

@@ -123,6 +123,8 @@ __device__ __forceinline__ bool intersect_all(const uint32_t* __restrict__ F, ui
 // MODE 0: write survivor ballots mask[word] and counts wcnt[word].
 // MODE 1: acc[0] += survivors.
 // MODE 2: acc[0] += survivors, acc[1] += sum of survivor weights (signed).
+// MODE 3: wcnt[p] += survivors of prefix p (a prefix's candidates are
+//         consecutive, so a wave adds once per prefix it touches).
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_propose(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n,
                                                     const uint64_t* __restrict__ off,
@@ -146,12 +148,14 @@ __global__ void __launch_bounds__(kBlock) k_propose(const uint32_t* __restrict__
     uint64_t g = gf + lane;
     bool keep = false;
     int8_t w = 1;
+    uint64_t pp = ~0ull;
     plo = gallop_segment(off, plo, n, gf);
     phi = gallop_segment(off, plo, n, gl) + 1;
     if (g < w1) {
       Cand c = resolve(F, stride, off, mini, d, plo, phi, g);
       keep = intersect_all(F, stride, d, c);
       if (MODE == 2) w = wt[c.p];
+      pp = c.p;
     }
     uint64_t b = __ballot(keep);
     if (MODE == 0) {
@@ -159,12 +163,25 @@ __global__ void __launch_bounds__(kBlock) k_propose(const uint32_t* __restrict__
         mask[wd] = b;
         wcnt[wd] = (uint32_t)__popcll(b);
       }
+    } else if (MODE == 3) {
+      // lanes of one prefix form a run; the first lane of each run adds the
+      // survivors of the run
+      uint64_t prev = shfl_up_u64(pp, 1);
+      bool start = pp != ~0ull && (lane == 0 || prev != pp);
+      uint64_t sb = __ballot(start);
+      if (start) {
+        uint64_t later = lane == 63 ? 0ull : (sb >> (lane + 1)) << (lane + 1);
+        int end = later ? __ffsll((unsigned long long)later) - 1 : 64;
+        uint64_t run = (end == 64 ? ~0ull : ((1ull << end) - 1)) & ~lanemask_lt();
+        uint32_t k = (uint32_t)__popcll(b & run);
+        if (k) atomicAdd(wcnt + pp, k);
+      }
     } else {
       cnt += keep ? 1 : 0;
       if (MODE == 2) wsum += keep ? w : 0;
     }
   }
-  if (MODE != 0) {
+  if (MODE == 1 || MODE == 2) {
     uint64_t t = block_sum<kBlock>(cnt);
     if (threadIdx.x == 0 && t) atomicAdd(acc, (unsigned long long)t);
     if (MODE == 2) {
@@ -277,8 +294,29 @@ void launch_propose(gj_ctx* c, int mode, const uint32_t* F, uint64_t stride, uin
     k_propose<0><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);
   else if (mode == 1)
     k_propose<1><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);
-  else
+  else if (mode == 2)
     k_propose<2><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);
+  else
+    k_propose<3><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);
+  GJ_HIP(hipGetLastError());
+}
+
+__global__ void __launch_bounds__(kBlock) k_factor_sum(const uint32_t* __restrict__ cnt, uint64_t stride,
+                                                       uint64_t n, int T, unsigned long long* __restrict__ acc) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t s = 0;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
+    uint64_t prod = cnt[p];
+    for (int t = 1; t < T; ++t) prod *= cnt[(uint64_t)t * stride + p];
+    s += prod;
+  }
+  uint64_t tot = block_sum<kBlock>(s);
+  if (threadIdx.x == 0 && tot) atomicAdd(acc, (unsigned long long)tot);
+}
+
+void launch_factor_sum(gj_ctx* c, const uint32_t* cnt, uint64_t stride, uint64_t n, int T,
+                       unsigned long long* acc) {
+  k_factor_sum<<<grid_for(n, kBlock, 4096), kBlock, 0, c->stream>>>(cnt, stride, n, T, acc);
   GJ_HIP(hipGetLastError());
 }
 
