@@ -182,3 +182,27 @@ def test_rmat22_delta_stream_properties(gj, rmat22):
         assert rp[0] == 0 and np.array_equal(np.diff(rp.astype(np.int64)), deg), rev
     G.close()
     ctx.close()
+
+
+def test_rmat22_factorised_closed_forms(gj, rmat22):
+    """Factorised counts at scale 22 against closed forms computed with numpy:
+    the 3-star counts sum out(v)^3 and the fan sum in(v) out(v)^2; the first
+    trailing attribute's extension counter is the same sum over the seed
+    edges of the proposing set size (out(a1) for the star, out(a2) for the
+    fan)."""
+    src, dst = rmat22
+    n = 1 << 22
+    es, ed = distinct_edges(src, dst)
+    out = np.bincount(es.astype(np.int64), minlength=n).astype(object)
+    inn = np.bincount(ed.astype(np.int64), minlength=n).astype(object)
+    c = gj.Context(0)
+    c.set_option("factorise", 1)
+    G = gj.Graph(c, src, dst, n)
+    star = gj.count(c, G, gj.Query(c, *Q.STAR3))
+    fan = gj.count(c, G, gj.Query(c, *Q.FAN))
+    assert star["matches"] == int(sum(out ** 3))
+    assert star["extensions"][2] == star["extensions"][3] == int(sum(out ** 2))
+    assert fan["matches"] == int(sum(inn * out ** 2))
+    assert fan["extensions"][2] == fan["extensions"][3] == int(sum(inn * out))
+    G.close()
+    c.close()
