@@ -11,8 +11,10 @@ Subgraph Queries Using Worst-case Optimal Low-Memory Dataflows".  Generic Join
 edge-seeded dataflow (Sec. 4.2), Delta-GJ (Sec. 3.3.1) and the symmetry
 breaking of Sec. 5.4 (inequality filters; vertices renamed by degree).
 
-A query is (num_attrs, atoms, order) or (num_attrs, atoms, order, less), with
-less a list of (x, y) meaning the value of a_x is below that of a_y.
+A query is (num_attrs, atoms, order[, less[, tris]]): less a list of (x, y)
+meaning the value of a_x is below that of a_y; tris a list of (x, y, z), the
+ternary atoms tri(a_x, a_y, a_z) (x -> y, x -> z and y -> z are edges) of
+Sec. 5.4, each binding a_z after a_x and a_y.
 """
 import ctypes
 import os
@@ -59,9 +61,10 @@ def _load():
         L.or_graph_edge_list.argtypes = [vp, vp, vp]
         L.or_graph_noops.argtypes = [vp, vp, vp]
         L.or_query_valid.restype = i32
-        L.or_query_valid.argtypes = [i32, vp, vp, i32, vp, vp, vp, i32]
+        L.or_query_valid.argtypes = [i32, vp, vp, i32, vp, vp, vp, i32, vp, vp, vp, i32]
         L.or_run.restype = vp
-        L.or_run.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, i32, i32, i32, u64, u64, i32, ip]
+        L.or_run.argtypes = [vp, i32, vp, vp, i32, vp, vp, vp, i32, vp, vp, vp, i32, i32, i32, u64, u64,
+                             i32, ip]
         L.or_run_textbook.restype = vp
         L.or_run_textbook.argtypes = [vp, i32, vp, vp, i32, vp, vp, ip]
         L.or_delta.restype = vp
@@ -97,9 +100,16 @@ def _query_arrays(query):
     return num_attrs, s, d, len(atoms), o, lx, ly, len(less)
 
 
+def _tri_arrays(query):
+    tris = list(query[4]) if len(query) > 4 else []
+    return tuple(np.array([t[i] for t in tris], dtype=np.uint8) for i in range(3)) + (len(tris),)
+
+
 def query_valid(query):
     m, s, d, k, o, lx, ly, nl = _query_arrays(query)
-    return bool(_load().or_query_valid(m, _p(s), _p(d), k, _p(o), _p(lx), _p(ly), nl))
+    tx, ty, tz, nt = _tri_arrays(query)
+    return bool(_load().or_query_valid(m, _p(s), _p(d), k, _p(o), _p(lx), _p(ly), nl,
+                                       _p(tx), _p(ty), _p(tz), nt))
 
 
 class Graph:
@@ -177,10 +187,11 @@ def run(graph, query, collect=False, seed_lo=0, seed_hi=None, threads=1, factori
     factorise: count a trailing run of independent attributes as a product
     of their extension counts (counts only)."""
     m, s, d, k, o, lx, ly, nl = _query_arrays(query)
+    tx, ty, tz, nt = _tri_arrays(query)
     st = ctypes.c_int(0)
     hi = (1 << 64) - 1 if seed_hi is None else seed_hi
-    res = _load().or_run(graph._h, m, _p(s), _p(d), k, _p(o), _p(lx), _p(ly), nl, int(collect),
-                         int(factorise), seed_lo, hi, threads, ctypes.byref(st))
+    res = _load().or_run(graph._h, m, _p(s), _p(d), k, _p(o), _p(lx), _p(ly), nl, _p(tx), _p(ty), _p(tz),
+                         nt, int(collect), int(factorise), seed_lo, hi, threads, ctypes.byref(st))
     if st.value != 0:
         if res:
             _load().or_result_free(res)
@@ -192,8 +203,8 @@ def textbook(graph, query):
     """Textbook GJ from P_0; returns [P_1, ..., P_m] as position-order arrays
     (queries without inequalities)."""
     m, s, d, k, o, _, _, nl = _query_arrays(query)
-    if nl:
-        raise OracleError("textbook(): inequalities are not supported")
+    if nl or len(query) > 4:
+        raise OracleError("textbook(): inequalities and ternary atoms are not supported")
     sizes = np.zeros(MAX_ATTRS + 2, dtype=np.uint64)
     st = ctypes.c_int(0)
     res = _load().or_run_textbook(graph._h, m, _p(s), _p(d), k, _p(o), _p(sizes),
@@ -225,6 +236,8 @@ def delta(graph, src, dst, sign, query=None):
                                0, None, None, 0, None, None, None, 0, ctypes.byref(st))
         m = 0
     else:
+        if len(query) > 4 and query[4]:
+            raise OracleError("delta(): ternary atoms are not supported")
         m, s, d, k, o, lx, ly, nl = _query_arrays(query)
         res = _load().or_delta(graph._h, _p(src), _p(dst), _p(sign), len(src),
                                m, _p(s), _p(d), k, _p(o), _p(lx), _p(ly), nl, ctypes.byref(st))

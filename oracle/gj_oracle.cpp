@@ -29,6 +29,11 @@
 //    binds both attributes is dropped unless the inequality holds.  The
 //    filters do not change which set is proposed from, so the extension
 //    counters are those of the query without them.
+//  * Ternary relations (Sec. 5.4): an atom tri(a_x, a_y, a_z) holds when
+//    x -> y, x -> z and y -> z are all edges.  It binds a_z once a_x and a_y
+//    are bound; its extension set is out(x) intersected with out(y) when
+//    x -> y, else empty.  The oracle computes that set from the definition
+//    every time (no index).
 //  * Factorised counting (Sec. 5.4): when the last attributes of the order
 //    share no atom and no inequality, each one's extensions depend only on the
 //    prefix before them, so a count multiplies their extension-set sizes
@@ -45,6 +50,7 @@
 // that inserts and deletes one edge; output rows are in attribute-index order,
 // sorted ascending as unsigned tuples.
 #include <algorithm>
+#include <iterator>
 #include <cstdint>
 #include <cstring>
 #include <map>
@@ -101,14 +107,22 @@ struct Query {
   std::vector<Atom> atoms;
   std::vector<int> order;  // order[j] = attribute bound at position j
   std::vector<Atom> less;  // (x, y): the value of a_x is below that of a_y
+  struct Tri {
+    int x, y, z;
+  };
+  std::vector<Tri> tris;   // tri(a_x, a_y, a_z)
 };
 
 // An extension set reference: the neighbour list of the value in prefix
-// column `col`, outgoing (`out_dir`) or incoming, in the old or new version.
+// column `col`, outgoing (`out_dir`) or incoming, in the old or new version;
+// or, for a ternary atom (tri >= 0), the third vertices of the pair in
+// columns col, col2.
 struct Binding {
   int atom;
   int col;
   bool out_dir;
+  int tri = -1;
+  int col2 = -1;
 };
 
 bool valid_query(const Query& q) {
@@ -125,6 +139,11 @@ bool valid_query(const Query& q) {
     if (at.s == at.d) return false;
   }
   if ((int)q.less.size() > kMaxLess) return false;
+  if ((int)(q.atoms.size() + q.tris.size()) > kMaxAtoms) return false;
+  for (auto& t : q.tris) {
+    if (t.x < 0 || t.x >= q.m || t.y < 0 || t.y >= q.m || t.z < 0 || t.z >= q.m) return false;
+    if (t.x == t.y || t.x == t.z || t.y == t.z) return false;
+  }
   for (auto& l : q.less)
     if (l.s < 0 || l.s >= q.m || l.d < 0 || l.d >= q.m || l.s == l.d) return false;
   std::vector<int> pos(q.m);
@@ -134,11 +153,16 @@ bool valid_query(const Query& q) {
   for (auto& at : q.atoms)
     if (std::max(pos[at.s], pos[at.d]) == 1) seed = true;
   if (!seed) return false;
+  // a ternary atom binds its third attribute, after the other two
+  for (auto& t : q.tris)
+    if (pos[t.z] < std::max(pos[t.x], pos[t.y]) || pos[t.z] < 2) return false;
   // every later attribute needs an atom to an earlier one
   for (int j = 2; j < q.m; ++j) {
     bool any = false;
     for (auto& at : q.atoms)
       if (std::max(pos[at.s], pos[at.d]) == j) any = true;
+    for (auto& t : q.tris)
+      if (pos[t.z] == j) any = true;
     if (!any) return false;
   }
   return true;
@@ -198,6 +222,11 @@ Plan make_plan(const Query& q) {
     else  // edge(x, y): x ranges over in(y)
       p.bind[j].push_back({i, pos[at.d], false});
   }
+  // ternary atoms bind their third attribute, after the binary ones
+  for (int i = 0; i < (int)q.tris.size(); ++i) {
+    const Query::Tri& t = q.tris[i];
+    p.bind[pos[t.z]].push_back({-1, pos[t.x], true, i, pos[t.y]});
+  }
   // the longest run of trailing positions whose attributes share no atom and
   // no inequality (positions 0 and 1 are the seed)
   auto linked = [&](int x, int y) {
@@ -205,6 +234,10 @@ Plan make_plan(const Query& q) {
       if ((at.s == x && at.d == y) || (at.s == y && at.d == x)) return true;
     for (auto& l : q.less)
       if ((l.s == x && l.d == y) || (l.s == y && l.d == x)) return true;
+    for (auto& t : q.tris) {
+      bool hx = t.x == x || t.y == x || t.z == x, hy = t.x == y || t.y == y || t.z == y;
+      if (hx && hy) return true;
+    }
     return false;
   };
   int j0 = q.m - 1;
@@ -238,10 +271,22 @@ struct Views {
   }
 };
 
-const std::vector<uint32_t>& ext_list(const Views& v, const Binding& b,
-                                      uint32_t key) {
+// The extension set of binding b for a prefix: a neighbour list of the
+// graph, or for a ternary atom (static runs only: it reads the one graph) the
+// set written into `scratch`.
+const std::vector<uint32_t>& ext_list(const Views& v, const Binding& b, const std::vector<uint32_t>& prefix,
+                                      std::vector<uint32_t>& scratch) {
+  if (b.tri >= 0) {
+    const Graph& g = *v.g_old;
+    uint32_t x = prefix[b.col], y = prefix[b.col2];
+    scratch.clear();
+    if (g.has(x, y))
+      std::set_intersection(g.out[x].begin(), g.out[x].end(), g.out[y].begin(), g.out[y].end(),
+                            std::back_inserter(scratch));
+    return scratch;
+  }
   const Graph& g = v.of(b.atom);
-  return b.out_dir ? g.out[key] : g.in[key];
+  return b.out_dir ? g.out[prefix[b.col]] : g.in[prefix[b.col]];
 }
 
 struct Counters {
@@ -271,21 +316,20 @@ struct Counters {
 uint64_t count_extensions(const Plan& plan, const Views& views, int j,
                           const std::vector<uint32_t>& prefix, Counters& c) {
   const std::vector<Binding>& B = plan.bind[j];
+  std::vector<uint32_t> scratch[kMaxAtoms];
+  const std::vector<uint32_t>* sets[kMaxAtoms] = {};
+  for (size_t i = 0; i < B.size(); ++i) sets[i] = &ext_list(views, B[i], prefix, scratch[i]);
   size_t best = 0;
-  for (size_t i = 1; i < B.size(); ++i) {
-    size_t ci = ext_list(views, B[i], prefix[B[i].col]).size();
-    size_t cb = ext_list(views, B[best], prefix[B[best].col]).size();
-    if (ci < cb) best = i;
-  }
-  const std::vector<uint32_t>& prop = ext_list(views, B[best], prefix[B[best].col]);
+  for (size_t i = 1; i < B.size(); ++i)
+    if (sets[i]->size() < sets[best]->size()) best = i;
+  const std::vector<uint32_t>& prop = *sets[best];
   c.add(c.extensions[j], prop.size());
   uint64_t kept = 0;
   for (uint32_t e : prop) {
     bool keep = true;
     for (size_t i = 0; i < B.size() && keep; ++i) {
       if (i == best) continue;
-      const std::vector<uint32_t>& l = ext_list(views, B[i], prefix[B[i].col]);
-      keep = std::binary_search(l.begin(), l.end(), e);
+      keep = std::binary_search(sets[i]->begin(), sets[i]->end(), e);
     }
     if (keep && ineq_ok(plan, j, prefix, e)) ++kept;
   }
@@ -319,20 +363,19 @@ void extend(const Query& q, const Plan& plan, const Views& views, int j,
     return;
   }
   const std::vector<Binding>& B = plan.bind[j];
+  std::vector<uint32_t> scratch[kMaxAtoms];
+  const std::vector<uint32_t>* sets[kMaxAtoms] = {};
+  for (size_t i = 0; i < B.size(); ++i) sets[i] = &ext_list(views, B[i], prefix, scratch[i]);
   size_t best = 0;
-  for (size_t i = 1; i < B.size(); ++i) {
-    size_t ci = ext_list(views, B[i], prefix[B[i].col]).size();
-    size_t cb = ext_list(views, B[best], prefix[B[best].col]).size();
-    if (ci < cb) best = i;  // strict: ties keep the lower atom
-  }
-  const std::vector<uint32_t>& prop = ext_list(views, B[best], prefix[B[best].col]);
+  for (size_t i = 1; i < B.size(); ++i)
+    if (sets[i]->size() < sets[best]->size()) best = i;  // strict: ties keep the lower binding
+  const std::vector<uint32_t>& prop = *sets[best];
   c.add(c.extensions[j], prop.size());
   for (uint32_t e : prop) {
     bool keep = true;
     for (size_t i = 0; i < B.size() && keep; ++i) {
       if (i == best) continue;
-      const std::vector<uint32_t>& l = ext_list(views, B[i], prefix[B[i].col]);
-      keep = std::binary_search(l.begin(), l.end(), e);
+      keep = std::binary_search(sets[i]->begin(), sets[i]->end(), e);
     }
     if (!keep || !ineq_ok(plan, j, prefix, e)) continue;
     prefix.push_back(e);
@@ -386,10 +429,12 @@ struct Result {
   uint64_t raw_emissions = 0;   // delta: signed outputs before consolidation
 };
 
-// The query's inequalities: lx[k] < ly[k] for k < num_less.
+// The query's inequalities: lx[k] < ly[k] for k < num_less; its ternary atoms
+// tri(tx[k], ty[k], tz[k]) for k < num_tri.
 bool parse_query(int num_attrs, const uint8_t* as, const uint8_t* ad, int num_atoms,
                  const uint8_t* order, const uint8_t* lx, const uint8_t* ly, int num_less,
-                 Query& q) {
+                 Query& q, const uint8_t* tx = nullptr, const uint8_t* ty = nullptr,
+                 const uint8_t* tz = nullptr, int num_tri = 0) {
   if (num_attrs < 0 || num_attrs > kMaxAttrs || num_atoms < 0 || num_atoms > kMaxAtoms ||
       num_less < 0 || num_less > kMaxLess)
     return false;
@@ -399,6 +444,9 @@ bool parse_query(int num_attrs, const uint8_t* as, const uint8_t* ad, int num_at
   q.order.assign(order, order + num_attrs);
   q.less.clear();
   for (int i = 0; i < num_less; ++i) q.less.push_back({lx[i], ly[i]});
+  q.tris.clear();
+  if (num_tri < 0 || num_tri > kMaxAtoms) return false;
+  for (int i = 0; i < num_tri; ++i) q.tris.push_back({tx[i], ty[i], tz[i]});
   return valid_query(q);
 }
 
@@ -458,9 +506,11 @@ void or_graph_edge_list(const void* gp, uint32_t* src, uint32_t* dst) {
 }
 
 int or_query_valid(int num_attrs, const uint8_t* as, const uint8_t* ad, int num_atoms,
-                   const uint8_t* order, const uint8_t* lx, const uint8_t* ly, int num_less) {
+                   const uint8_t* order, const uint8_t* lx, const uint8_t* ly, int num_less,
+                   const uint8_t* tx, const uint8_t* ty, const uint8_t* tz, int num_tri) {
   Query q;
-  return parse_query(num_attrs, as, ad, num_atoms, order, lx, ly, num_less, q) ? 1 : 0;
+  return parse_query(num_attrs, as, ad, num_atoms, order, lx, ly, num_less, q, tx, ty, tz, num_tri) ? 1
+                                                                                                  : 0;
 }
 
 // Edge-seeded Generic Join over seed edges [seed_lo, seed_hi) of the seed
@@ -469,11 +519,12 @@ int or_query_valid(int num_attrs, const uint8_t* as, const uint8_t* ad, int num_
 // result does not depend on the thread count.
 void* or_run(const void* gp, int num_attrs, const uint8_t* as, const uint8_t* ad,
              int num_atoms, const uint8_t* order, const uint8_t* lx, const uint8_t* ly,
-             int num_less, int collect, int factorise, uint64_t seed_lo, uint64_t seed_hi,
-             int threads, int* status) {
+             int num_less, const uint8_t* tx, const uint8_t* ty, const uint8_t* tz, int num_tri,
+             int collect, int factorise, uint64_t seed_lo, uint64_t seed_hi, int threads,
+             int* status) {
   const Graph* g = (const Graph*)gp;
   Query q;
-  if (!parse_query(num_attrs, as, ad, num_atoms, order, lx, ly, num_less, q)) {
+  if (!parse_query(num_attrs, as, ad, num_atoms, order, lx, ly, num_less, q, tx, ty, tz, num_tri)) {
     *status = OR_EINVAL;
     return nullptr;
   }

@@ -14,10 +14,12 @@ def adjacency(n, src, dst):
 
 
 def matches(A, query):
-    """query = (m, atoms, order) or (m, atoms, order, less); (x, y) in less
-    requires the value of a_x to be below that of a_y."""
+    """query = (m, atoms, order[, less[, tris]]); (x, y) in less requires the
+    value of a_x to be below that of a_y; (x, y, z) in tris requires the
+    edges x -> y, x -> z and y -> z."""
     m, atoms = query[0], query[1]
     less = query[3] if len(query) > 3 else []
+    tris = query[4] if len(query) > 4 else []
     n = A.shape[0]
     T = np.indices((n,) * m).reshape(m, -1)  # lexicographic order
     ok = np.ones(T.shape[1], dtype=bool)
@@ -25,6 +27,8 @@ def matches(A, query):
         ok &= A[T[s], T[d]]
     for x, y in less:
         ok &= T[x] < T[y]
+    for x, y, z in tris:  # tri(x, y, z): x -> y, x -> z, y -> z
+        ok &= A[T[x], T[y]] & A[T[x], T[z]] & A[T[y], T[z]]
     return T[:, ok].T.astype(np.uint32)
 
 

@@ -90,3 +90,14 @@ def trailing_run(q):
     while j0 - 1 >= 2 and all(frozenset((order[j0 - 1], order[t])) not in pairs for t in range(j0, m)):
         j0 -= 1
     return j0 if m - j0 >= 2 else 0
+
+
+# Ternary atoms (Sec. 5.4): tri(x, y, z) is the triangle relation (x -> y,
+# x -> z, y -> z), binding a_z after a_x and a_y.  The paper's 4-clique over
+# three tri atoms (with the edge atom the seed pair comes from), a 5-clique
+# over six, and a mixed query.
+TRI_CLIQUE4 = (4, [(0, 1)], [0, 1, 2, 3], [], [(0, 1, 2), (0, 1, 3), (0, 2, 3)])
+TRI_CLIQUE5 = (5, [(0, 1)], [0, 1, 2, 3, 4], [],
+               [(0, 1, 2), (0, 1, 3), (0, 2, 3), (0, 1, 4), (0, 2, 4), (0, 3, 4)])
+TRI_MIXED = (4, [(0, 1), (2, 3)], [0, 1, 2, 3], [], [(0, 1, 2)])
+TRI = {"tri_clique4": TRI_CLIQUE4, "tri_clique5": TRI_CLIQUE5, "tri_mixed": TRI_MIXED}

@@ -487,3 +487,54 @@ def test_factorised_closed_forms():
     inn = np.bincount(ed.astype(np.int64), minlength=n)
     assert oracle.run(G, Q.STAR3, factorise=True)["matches"] == int((out ** 3).sum())
     assert oracle.run(G, Q.FAN, factorise=True)["matches"] == int((inn * out ** 2).sum())
+
+
+# ---------------------------------------------------------------- ternary atoms (Sec. 5.4)
+@pytest.mark.parametrize("name", sorted(Q.TRI))
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_tri_atoms_brute_force(name, seed):
+    """Queries over the triangle relation: rows equal the brute-force matches
+    (tri(x, y, z) read as the three edges), with and without an inequality."""
+    q = Q.TRI[name]
+    n = 8 if q[0] < 5 else 7
+    s, d = rand_graph(n, 36, 600 + seed)
+    G = oracle.Graph(n, s, d)
+    A = brute.adjacency(n, s, d)
+    for less in ([], [(0, 2)]):
+        ql = (q[0], q[1], q[2], less, q[4])
+        r = oracle.run(G, ql, collect=True)
+        want = brute.matches(A, ql)
+        assert brute.as_set(r["rows"]) == brute.as_set(want) and len(r["rows"]) == len(want)
+
+
+def test_tri_clique_identities():
+    """The 4- and 5-clique over tri atoms count what the plain cliques count;
+    the 4-clique's third position has as many prefixes, and its stage-2
+    proposals sum |out(x) & out(y)| over the edges, both the plain triangle
+    count."""
+    n = 40
+    s, d = rand_graph(n, 400, 31)
+    G = oracle.Graph(n, s, d)
+    tri = oracle.run(G, Q.TRIANGLE)["matches"]
+    t4 = oracle.run(G, Q.TRI_CLIQUE4)
+    assert t4["matches"] == oracle.run(G, Q.CLIQUE4)["matches"] > 0
+    assert t4["prefixes"][3] == t4["extensions"][2] == tri
+    assert oracle.run(G, Q.TRI_CLIQUE5)["matches"] == oracle.run(G, Q.CLIQUE5)["matches"]
+
+
+def test_tri_complete_digraph():
+    """Complete digraph K_n: every pair has n - 2 common out-neighbours."""
+    n = 9
+    s, d = np.nonzero(~np.eye(n, dtype=bool))
+    G = oracle.Graph(n, s, d)
+    r = oracle.run(G, Q.TRI_CLIQUE4)
+    assert r["matches"] == n * (n - 1) * (n - 2) * (n - 3)
+    assert r["extensions"][2] == n * (n - 1) * (n - 2)
+    assert r["extensions"][3] == n * (n - 1) * (n - 2) * (n - 2)
+
+
+def test_tri_invalid():
+    assert oracle.query_valid(Q.TRI_CLIQUE4)
+    assert not oracle.query_valid((3, [(0, 1)], [0, 1, 2], [], [(0, 2, 1)]))  # binds a middle attribute
+    assert not oracle.query_valid((3, [(0, 1)], [0, 1, 2], [], [(0, 0, 2)]))
+    assert not oracle.query_valid((3, [(0, 1)], [0, 1, 2], [], [(0, 1, 3)]))
