@@ -135,6 +135,14 @@ gj_status gj_graph_csr(const gj_graph* g, int reverse, const uint32_t** row_ptr,
  * context is destroyed, and after any server on the graph. */
 void gj_graph_destroy(gj_graph* g);
 
+/* Materialises the triangle relation of g's current version for ternary
+ * atoms (Sec. 5.4): for every edge (x, y) the sorted list out(x) & out(y),
+ * as a CSR over forward edge positions with 64-bit row pointers (8 B per
+ * edge + 4 B per triangle of device memory).  *num_triangles (may be NULL)
+ * receives the relation's size.  Kept until gj_graph_destroy or the next
+ * gj_apply_updates that changes the graph, which drops it. */
+gj_status gj_graph_index_triangles(gj_ctx* ctx, gj_graph* g, uint64_t* num_triangles);
+
 /* Old vertex id of every vertex id of g (num_vertices entries written to
  * old_of_new, a host or device array as out_on_device says): the renaming of
  * GJ_BUILD_DEGREE_ORDER, else the identity.  Match rows and update batches
@@ -165,6 +173,15 @@ typedef struct {
 } gj_less;
 #define GJ_MAX_LESS 28
 
+/* Ternary atom tri(a_x, a_y, a_z) over the triangle relation of the graph
+ * (x -> y, x -> z and y -> z are edges; Sec. 5.4).  It binds a_z, which the
+ * order must place after a_x and a_y; its extension set for a prefix is the
+ * list of third vertices of the pair (x, y), read from the graph's triangle
+ * index (gj_graph_index_triangles). */
+typedef struct {
+  uint8_t x_attr, y_attr, z_attr;
+} gj_tri_atom;
+
 /* gj_query_register plus inequalities every match must satisfy (less may be
  * NULL when num_less is 0).  Each is a filter on the prefixes, applied when
  * the later of its two attributes is bound (to the seed pair if both are the
@@ -176,6 +193,19 @@ typedef struct {
 gj_status gj_query_register_ex(gj_ctx* ctx, uint32_t num_attrs, const gj_atom* atoms,
                                uint32_t num_atoms, const uint8_t* order, const gj_less* less,
                                uint32_t num_less, gj_query** out);
+
+/* gj_query_register_ex plus ternary atoms (tris may be NULL when num_tris is
+ * 0).  num_atoms + num_tris is at most GJ_MAX_ATOMS; P_2 is still seeded
+ * from a binary atom over order[0], order[1].  A query with ternary atoms
+ * runs only through gj_run, on a graph whose triangle index is current
+ * (else GJ_EINVAL); gj_run_batch, the server and gj_apply_updates reject it
+ * (GJ_EUNSUPPORTED).  Errors (GJ_EINVAL) as gj_query_register_ex, and: a
+ * ternary atom over an attribute twice or out of range, or whose third
+ * attribute is not after the other two in the order. */
+gj_status gj_query_register_rel(gj_ctx* ctx, uint32_t num_attrs, const gj_atom* atoms,
+                                uint32_t num_atoms, const gj_tri_atom* tris, uint32_t num_tris,
+                                const uint8_t* order, const gj_less* less, uint32_t num_less,
+                                gj_query** out);
 void gj_query_destroy(gj_query* q);
 
 /* Per-call counters.  prefixes[j] = |P_j| (j >= 2; prefixes[m] = matches),

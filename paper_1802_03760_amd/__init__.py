@@ -32,7 +32,8 @@ EXPORTS = ["gj_ctx_create", "gj_ctx_destroy", "gj_last_error", "gj_ctx_set_optio
            "gj_query_register", "gj_query_destroy", "gj_run", "gj_apply_updates",
            "gj_last_delta", "gj_run_batch", "gj_autotune", "gj_server_create", "gj_server_submit_count",
            "gj_server_submit_update", "gj_server_wait", "gj_server_get_stats", "gj_server_destroy",
-           "gj_server_set_option", "gj_query_register_ex", "gj_graph_vertex_ids"]
+           "gj_server_set_option", "gj_query_register_ex", "gj_graph_vertex_ids", "gj_query_register_rel",
+           "gj_graph_index_triangles"]
 REQ_COUNT, REQ_UPDATE = 0, 1
 SERVER_MAX_QUERIES = 16
 
@@ -43,6 +44,10 @@ class Atom(ctypes.Structure):
 
 class Less(ctypes.Structure):
     _fields_ = [("lo_attr", ctypes.c_uint8), ("hi_attr", ctypes.c_uint8)]
+
+
+class TriAtom(ctypes.Structure):
+    _fields_ = [("x_attr", ctypes.c_uint8), ("y_attr", ctypes.c_uint8), ("z_attr", ctypes.c_uint8)]
 
 
 class Tuning(ctypes.Structure):
@@ -113,6 +118,11 @@ _lib.gj_query_register.restype = _i32
 _lib.gj_query_register_ex.argtypes = [_vp, _u32, ctypes.POINTER(Atom), _u32, _vp, ctypes.POINTER(Less), _u32,
                                       ctypes.POINTER(_vp)]
 _lib.gj_query_register_ex.restype = _i32
+_lib.gj_query_register_rel.argtypes = [_vp, _u32, ctypes.POINTER(Atom), _u32, ctypes.POINTER(TriAtom), _u32, _vp,
+                                       ctypes.POINTER(Less), _u32, ctypes.POINTER(_vp)]
+_lib.gj_query_register_rel.restype = _i32
+_lib.gj_graph_index_triangles.argtypes = [_vp, _vp, ctypes.POINTER(_u64)]
+_lib.gj_graph_index_triangles.restype = _i32
 _lib.gj_graph_vertex_ids.argtypes = [_vp, _vp, _i32]
 _lib.gj_graph_vertex_ids.restype = _i32
 _lib.gj_query_destroy.argtypes = [_vp]
@@ -306,6 +316,14 @@ class Graph(_Owner):
         return {"edges": e.value, "vertices": n.value, "max_out": mo.value,
                 "max_in": mi.value, "version": v.value}
 
+    def index_triangles(self):
+        """Builds the triangle relation for ternary atoms (gj_graph_index_triangles);
+        returns its size."""
+        t = _u64()
+        self.ctx.check(_lib.gj_graph_index_triangles(self.ctx._h, self._h, ctypes.byref(t)),
+                       "gj_graph_index_triangles")
+        return t.value
+
     def vertex_ids(self):
         """Old id of every vertex id (gj_graph_vertex_ids), a numpy array."""
         out = np.empty(self.num_vertices, dtype=np.uint32)
@@ -321,11 +339,12 @@ class Graph(_Owner):
 
 
 class Query(_Owner):
-    """Q(a_0..a_{m-1}) := edge(s, d), ... with a global order and optional
-    inequalities less = [(x, y), ...]: value of a_x below that of a_y
-    (gj_query_register_ex)."""
+    """Q(a_0..a_{m-1}) := edge(s, d), ... with a global order, optional
+    inequalities less = [(x, y), ...] (value of a_x below that of a_y) and
+    ternary atoms tris = [(x, y, z), ...] over the triangle relation
+    (gj_query_register_rel)."""
 
-    def __init__(self, ctx, num_attrs, atoms, order=None, less=()):
+    def __init__(self, ctx, num_attrs, atoms, order=None, less=(), tris=()):
         self.ctx = ctx
         self.num_attrs = num_attrs
         self.atoms = [tuple(a) for a in atoms]
@@ -333,10 +352,13 @@ class Query(_Owner):
         self.less = [tuple(x) for x in less]
         arr = (Atom * len(self.atoms))(*[Atom(s, d) for s, d in self.atoms])
         lt = (Less * max(len(self.less), 1))(*[Less(x, y) for x, y in self.less])
+        self.tris = [tuple(t) for t in tris]
+        tr = (TriAtom * max(len(self.tris), 1))(*[TriAtom(*t) for t in self.tris])
         o = np.array(self.order, dtype=np.uint8)
         h = _vp()
-        ctx.check(_lib.gj_query_register_ex(ctx._h, num_attrs, arr, len(self.atoms), _np_ptr(o), lt,
-                                            len(self.less), ctypes.byref(h)), "gj_query_register_ex")
+        ctx.check(_lib.gj_query_register_rel(ctx._h, num_attrs, arr, len(self.atoms), tr, len(self.tris),
+                                             _np_ptr(o), lt, len(self.less), ctypes.byref(h)),
+                  "gj_query_register_rel")
         self._hd = _Handle(h, _lib.gj_query_destroy, (ctx._hd,))
 
 

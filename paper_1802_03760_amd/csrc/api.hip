@@ -280,8 +280,17 @@ void gj_graph_destroy(gj_graph* g) {
     (void)hipStreamSynchronize(g->ctx->stream);
   }
   for (auto& v : g->ver) gj::version_free(v);
+  gj::tri_index_free(g);
   gj::dev_free(g->old_of_new);
   delete g;
+}
+
+gj_status gj_graph_index_triangles(gj_ctx* c, gj_graph* g, uint64_t* num_triangles) {
+  if (!c || !g) return GJ_EINVAL;
+  return guarded(c, [&] {
+    gj::tri_index_build(c, g);
+    if (num_triangles) *num_triangles = g->tri.size;
+  });
 }
 
 gj_status gj_graph_vertex_ids(const gj_graph* g, uint32_t* old_of_new, int out_on_device) {
@@ -311,12 +320,20 @@ gj_status gj_query_register(gj_ctx* c, uint32_t num_attrs, const gj_atom* atoms,
 
 gj_status gj_query_register_ex(gj_ctx* c, uint32_t num_attrs, const gj_atom* atoms, uint32_t num_atoms,
                                const uint8_t* order, const gj_less* less, uint32_t num_less, gj_query** out) {
+  return gj_query_register_rel(c, num_attrs, atoms, num_atoms, nullptr, 0, order, less, num_less, out);
+}
+
+gj_status gj_query_register_rel(gj_ctx* c, uint32_t num_attrs, const gj_atom* atoms, uint32_t num_atoms,
+                                const gj_tri_atom* tris, uint32_t num_tris, const uint8_t* order, const gj_less* less,
+                                uint32_t num_less, gj_query** out) {
   if (!c || !out) return GJ_EINVAL;
   *out = nullptr;
   gj_query* q = nullptr;
   gj_status s = guarded(c, [&] {
     GJ_CHECK(num_attrs >= 2 && num_attrs <= GJ_MAX_ATTRS, GJ_EINVAL, "num_attrs must be in [2, 8]");
-    GJ_CHECK(num_atoms >= 1 && num_atoms <= GJ_MAX_ATOMS, GJ_EINVAL, "num_atoms must be in [1, 16]");
+    GJ_CHECK(num_atoms >= 1 && num_atoms + num_tris <= GJ_MAX_ATOMS, GJ_EINVAL,
+             "num_atoms must be >= 1 and num_atoms + num_tris at most 16");
+    GJ_CHECK(tris || num_tris == 0, GJ_EINVAL, "null ternary atoms");
     GJ_CHECK(atoms && order, GJ_EINVAL, "null atoms or order");
     int m = (int)num_attrs;
     std::vector<int> seen(m, 0), pos(m);
@@ -329,6 +346,14 @@ gj_status gj_query_register_ex(gj_ctx* c, uint32_t num_attrs, const gj_atom* ato
       GJ_CHECK(atoms[i].src_attr < m && atoms[i].dst_attr < m, GJ_EINVAL, "atom attribute out of range");
       GJ_CHECK(atoms[i].src_attr != atoms[i].dst_attr, GJ_EINVAL, "atom over one attribute twice");
     }
+    for (uint32_t i = 0; i < num_tris; ++i) {
+      const gj_tri_atom& t = tris[i];
+      GJ_CHECK(t.x_attr < m && t.y_attr < m && t.z_attr < m, GJ_EINVAL, "ternary atom attribute out of range");
+      GJ_CHECK(t.x_attr != t.y_attr && t.x_attr != t.z_attr && t.y_attr != t.z_attr, GJ_EINVAL,
+               "ternary atom over one attribute twice");
+      GJ_CHECK(pos[t.z_attr] > pos[t.x_attr] && pos[t.z_attr] > pos[t.y_attr], GJ_EINVAL,
+               "a ternary atom's third attribute must come after the other two in the order");
+    }
     GJ_CHECK(num_less <= GJ_MAX_LESS, GJ_EINVAL, "more than 28 inequalities");
     GJ_CHECK(less || num_less == 0, GJ_EINVAL, "null inequalities");
     for (uint32_t i = 0; i < num_less; ++i) {
@@ -339,6 +364,8 @@ gj_status gj_query_register_ex(gj_ctx* c, uint32_t num_attrs, const gj_atom* ato
       bool any = false;
       for (uint32_t i = 0; i < num_atoms; ++i)
         if (std::max(pos[atoms[i].src_attr], pos[atoms[i].dst_attr]) == j) any = true;
+      for (uint32_t i = 0; i < num_tris && j >= 2; ++i)
+        if (pos[tris[i].z_attr] == j) any = true;
       GJ_CHECK(any, GJ_EINVAL,
                j == 1 ? "no atom over the first two attributes of the order"
                       : "an attribute has no atom to an earlier attribute of the order");
@@ -348,6 +375,7 @@ gj_status gj_query_register_ex(gj_ctx* c, uint32_t num_attrs, const gj_atom* ato
     q->atoms.assign(atoms, atoms + num_atoms);
     q->order.assign(order, order + m);
     if (num_less) q->less.assign(less, less + num_less);
+    if (num_tris) q->tris.assign(tris, tris + num_tris);
     // plan limits are checked here so that run time never fails on them
     gj::PlanHCheck(q);
   });
@@ -392,8 +420,12 @@ gj_status gj_apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const ui
     GJ_CHECK(b == 0 || (src && dst && sign), GJ_EINVAL, "null batch arrays");
     GJ_CHECK(nq == 0 || qs, GJ_EINVAL, "null query list");
     for (uint32_t i = 0; i < nq; ++i) GJ_CHECK(qs[i], GJ_EINVAL, "null query");
+    for (uint32_t i = 0; i < nq; ++i)
+      GJ_CHECK(qs[i]->tris.empty(), GJ_EUNSUPPORTED, "delta queries with ternary atoms are not supported");
+    uint64_t before = g->version;
     gj::apply_updates(c, g, src, dst, sign, b, on_device, qs, nq, count_delta, delta_rows, delta_sign, cap,
                       n_delta, stats, overflow);
+    if (g->version != before) gj::tri_index_free(g);  // the relation changed
   });
   double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (stats)
@@ -413,6 +445,8 @@ namespace gj {
 void count_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* seed_lo,
                  const uint64_t* seed_hi, uint64_t* counts, gj_stats* stats, const Version* ver) {
   for (uint32_t i = 0; i < nreq; ++i) GJ_CHECK(qs[i], GJ_EINVAL, "null query");
+  for (uint32_t i = 0; i < nreq; ++i)
+    GJ_CHECK(qs[i]->tris.empty(), GJ_EUNSUPPORTED, "ternary atoms run only through gj_run");
   if (nreq == 0) return;
   if (!c->batch) c->batch = new BatchExec();
   bool overflow = false;

@@ -10,6 +10,7 @@ namespace gj {
 
 struct BindH {
   int atom, col, dir;  // extension set: dir 0 out(prefix[col]), 1 in(prefix[col])
+  int col2 = -1;       // ternary atom: the third vertices of (prefix[col], prefix[col2])
 };
 struct FilterH {
   int atom, key, val;  // seed pair kept iff x[val] in out(x[key])
@@ -31,6 +32,7 @@ struct PlanH {
   // and no inequality (their extensions depend only on the prefix before the
   // run, so counts may multiply), else 0
   int fact_from = 0;
+  int ntri = 0;  // ternary atoms
   bool has_ineq() const {
     for (int j = 0; j < m; ++j)
       if (above[j] | below[j]) return true;
@@ -48,6 +50,7 @@ struct Views {
   const Version* old_v;
   const Version* new_v;
   int delta_atom;  // -1: every atom reads old_v
+  const TriIndex* tri = nullptr;  // for ternary atoms (static runs)
   const Version& of(int atom) const {
     return (delta_atom >= 0 && atom < delta_atom) ? *new_v : *old_v;
   }

@@ -41,12 +41,23 @@ PlanH make_plan(const gj_query* q, const std::vector<int>& order, int forced_see
       P.bind[j].push_back({i, pos[d], 1});  // edge(x, y): x in in(y)
     }
   }
+  // ternary atoms bind their third attribute, after the binary atoms
+  for (const gj_tri_atom& t : q->tris) {
+    BindH b{-1, pos[t.x_attr], 0, pos[t.y_attr]};
+    P.bind[pos[t.z_attr]].push_back(b);
+  }
+  P.ntri = (int)q->tris.size();
   // trailing run of attributes that share no atom and no inequality
   auto linked = [&](int x, int y) {
     for (const gj_atom& at : q->atoms)
       if ((at.src_attr == x && at.dst_attr == y) || (at.src_attr == y && at.dst_attr == x)) return true;
     for (const gj_less& l : q->less)
       if ((l.lo_attr == x && l.hi_attr == y) || (l.lo_attr == y && l.hi_attr == x)) return true;
+    for (const gj_tri_atom& t : q->tris) {
+      bool hx = t.x_attr == x || t.y_attr == x || t.z_attr == x;
+      bool hy = t.x_attr == y || t.y_attr == y || t.z_attr == y;
+      if (hx && hy) return true;
+    }
     return false;
   };
   int j0 = q->m - 1;
@@ -80,12 +91,25 @@ StageDesc stage_desc(const PlanH& P, const Views& V, int j) {
   d.k = (int)P.bind[j].size();
   d.above = P.above[j];
   d.below = P.below[j];
+  for (int a = 0; a < kMaxBind; ++a) d.col2[a] = -1;
   for (int a = 0; a < d.k; ++a) {
     const BindH& b = P.bind[j][a];
-    const Version& v = V.of(b.atom);
     d.col[a] = b.col;
+    if (b.col2 >= 0) {  // ternary: the triangle index of the version read
+      d.col2[a] = b.col2;
+      ++d.ntri;
+      continue;
+    }
+    const Version& v = V.of(b.atom);
     d.rp[a] = v.d[b.dir].rp;
     d.adj[a] = v.d[b.dir].col;
+  }
+  if (d.ntri) {
+    GJ_CHECK(V.tri && V.tri->rp, GJ_EINVAL, "ternary atom without a triangle index");
+    d.trp = V.tri->rp;
+    d.tcol = V.tri->col;
+    d.erp = V.old_v->d[0].rp;
+    d.ecol = V.old_v->d[0].col;
   }
   for (int a = d.k; a < kMaxBind; ++a) {
     d.col[a] = 0;
@@ -139,6 +163,7 @@ std::vector<int> delta_order(const gj_query* q, int i) {
 // Plans of the static order and of every delta query must fit the kernels.
 void PlanHCheck(const gj_query* q) {
   make_plan(q, q->order, -1);
+  if (!q->tris.empty()) return;  // no delta queries over the triangle relation
   for (int i = 0; i < (int)q->atoms.size(); ++i) make_plan(q, delta_order(q, i), i);
 }
 
@@ -334,13 +359,20 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
   PlanH P = make_plan(q, q->order, -1);
   const Version& v = ver ? *ver : g->ver[g->cur];
   Views V{&v, &v, -1};
+  if (P.ntri) {
+    GJ_CHECK(!ver, GJ_EUNSUPPORTED, "queries with ternary atoms run only through gj_run");
+    GJ_CHECK(g->tri.rp && g->tri.version == g->version && g->tri.slot == g->cur, GJ_EINVAL,
+             "no triangle index for the graph's current version (gj_graph_index_triangles)");
+    V.tri = &g->tri;
+  }
   int dir = P.seed_fwd ? 0 : 1;
   hi = std::min<uint64_t>(hi, v.m);
   lo = std::min<uint64_t>(lo, hi);
   bool collect = mode == GJ_MODE_ENUMERATE;
   // Owner-grouped kernel: counting a three-attribute query over all seed
   // edges whose last attribute is bound by one atom on each seed attribute.
-  if (!collect && c->strategy != 1 && P.m == 3 && P.filters.empty() && !P.has_ineq() && lo == 0 && hi == v.m &&
+  if (!collect && c->strategy != 1 && P.m == 3 && P.filters.empty() && !P.has_ineq() && !P.ntri && lo == 0 &&
+      hi == v.m &&
       P.bind[2].size() == 2 && P.bind[2][0].col != P.bind[2][1].col) {
     const BindH& A = P.bind[2][0].col == 0 ? P.bind[2][0] : P.bind[2][1];
     const BindH& B = P.bind[2][0].col == 0 ? P.bind[2][1] : P.bind[2][0];

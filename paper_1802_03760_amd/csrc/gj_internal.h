@@ -47,6 +47,15 @@ struct StageDesc {
   int col[kMaxBind];
   const uint32_t* rp[kMaxBind];
   const uint32_t* adj[kMaxBind];
+  // ternary bindings (col2[a] >= 0): the set of the pair (col, col2) is
+  // tcol[trp[e] .. trp[e+1]) with e the position of that pair in the forward
+  // CSR (erp, ecol); empty when the pair is no edge
+  int ntri;
+  int col2[kMaxBind];
+  const uint64_t* trp;
+  const uint32_t* tcol;
+  const uint32_t* erp;
+  const uint32_t* ecol;
 };
 
 // Membership filters of the seed pairs (atoms over the first two attributes
@@ -83,6 +92,15 @@ struct Version {
   CsrDir d[2];  // 0 forward, 1 reverse
   uint64_t m = 0, cap = 0;
   uint32_t max_deg[2] = {0, 0};
+};
+
+// The triangle relation of one version, keyed by forward edge position.
+struct TriIndex {
+  uint64_t* rp = nullptr;   // m + 1
+  uint32_t* col = nullptr;  // size
+  uint64_t size = 0;
+  uint64_t version = ~0ull;  // graph version it was built for
+  int slot = -1;
 };
 
 }  // namespace gj
@@ -129,6 +147,7 @@ struct gj_graph {
   gj_ctx* ctx = nullptr;
   uint32_t n = 0;
   uint32_t* old_of_new = nullptr;  // device, n entries: renamed by degree, else null
+  gj::TriIndex tri;
   gj::Version ver[kMaxVersions];
   int cur = 0;
   uint64_t version = 0;
@@ -139,6 +158,7 @@ struct gj_query {
   std::vector<gj_atom> atoms;
   std::vector<int> order;
   std::vector<gj_less> less;  // value(lo_attr) < value(hi_attr)
+  std::vector<gj_tri_atom> tris;
 };
 
 namespace gj {
@@ -205,6 +225,14 @@ void launch_seed(gj_ctx* c, const uint32_t* x0, const uint32_t* x1, const int8_t
                  int8_t* Fw);
 void launch_count_min(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const StageDesc& d,
                       uint32_t* minc, uint8_t* mini);
+// The new values of the survivors of [w0, w1) only, at out[obase + pos].
+void launch_emit_values(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const uint64_t* off,
+                        const uint8_t* mini, const StageDesc& d, uint64_t w0, uint64_t w1, const uint64_t* mask,
+                        const uint64_t* woff, uint32_t* out, uint64_t obase, uint64_t ocap);
+// tri.hip: the triangle relation of the graph's current version (replaces
+// g->tri); frees it
+void tri_index_build(gj_ctx* c, gj_graph* g);
+void tri_index_free(gj_graph* g);
 // Sum over the n prefixes of the product of T per-prefix counts
 // cnt[t * stride + p], added to acc[0].
 void launch_factor_sum(gj_ctx* c, const uint32_t* cnt, uint64_t stride, uint64_t n, int T,

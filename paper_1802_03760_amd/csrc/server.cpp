@@ -664,6 +664,7 @@ static gj_status enqueue_req(gj_server* s, Req&& r, uint64_t* ticket) {
 gj_status gj_server_submit_count(gj_server* s, const gj_query* q, uint64_t seed_lo, uint64_t seed_hi,
                                  uint64_t* ticket) {
   if (!s || !q || !ticket) return GJ_EINVAL;
+  if (!q->tris.empty()) return GJ_EUNSUPPORTED;  // ternary atoms run only through gj_run
   Req r;
   r.kind = GJ_REQ_COUNT;
   r.q = q;
@@ -676,6 +677,8 @@ gj_status gj_server_submit_update(gj_server* s, const uint32_t* src, const uint3
                                   uint64_t b, const gj_query* const* qs, uint32_t nq, uint64_t* ticket) {
   if (!s || !ticket || (b && (!src || !dst || !sign)) || nq > GJ_SERVER_MAX_QUERIES || (nq && !qs))
     return GJ_EINVAL;
+  for (uint32_t i = 0; i < nq; ++i)
+    if (!qs[i] || !qs[i]->tris.empty()) return qs[i] ? GJ_EUNSUPPORTED : GJ_EINVAL;
   Req r;
   r.kind = GJ_REQ_UPDATE;
   r.src.assign(src, src + b);

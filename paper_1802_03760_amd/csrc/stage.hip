@@ -51,6 +51,21 @@ __global__ void k_seed_scatter(const uint32_t* __restrict__ x0, const uint32_t* 
   }
 }
 
+// Ternary binding a (Sec. 5.4) for prefix p: the third vertices of the pair
+// in columns col, col2 are tcol[lo, lo + size); size 0 if the pair is no edge.
+__device__ __forceinline__ uint32_t tri_set(const StageDesc& d, int a, const uint32_t* __restrict__ F,
+                                            uint64_t stride, uint64_t p, uint64_t& lo) {
+  uint32_t x = F[(uint64_t)d.col[a] * stride + p], y = F[(uint64_t)d.col2[a] * stride + p];
+  uint32_t b = d.erp[x], e = d.erp[x + 1];
+  uint32_t i = lower_bound_u32(d.ecol, b, e, y);
+  if (i >= e || d.ecol[i] != y) {
+    lo = 0;
+    return 0;
+  }
+  lo = d.trp[i];
+  return (uint32_t)(d.trp[i + 1] - lo);
+}
+
 // ---------------------------------------------------------------- count-minimisation
 // min_c = smallest extension-set size over the binding atoms, min_i = its
 // binding index (ties: lowest, i.e. lowest atom index).
@@ -63,8 +78,14 @@ __global__ void k_count_min(const uint32_t* __restrict__ F, uint64_t stride, uin
 #pragma unroll
     for (int a = 0; a < kMaxBind; ++a) {
       if (a < d.k) {
-        uint32_t v = F[(uint64_t)d.col[a] * stride + p];
-        uint32_t c = d.rp[a][v + 1] - d.rp[a][v];
+        uint32_t c;
+        if (d.col2[a] >= 0) {
+          uint64_t lo;
+          c = tri_set(d, a, F, stride, p, lo);
+        } else {
+          uint32_t v = F[(uint64_t)d.col[a] * stride + p];
+          c = d.rp[a][v + 1] - d.rp[a][v];
+        }
         if (c < best) {
           best = c;
           bi = a;
@@ -91,6 +112,20 @@ __device__ __forceinline__ Cand resolve(const uint32_t* __restrict__ F, uint64_t
   c.p = find_segment(off, plo, phi, g);
   uint32_t k = (uint32_t)(g - off[c.p]);
   c.am = mini[c.p];
+  if (d.ntri) {
+    bool tri = false;
+#pragma unroll
+    for (int a = 0; a < kMaxBind; ++a)
+      if (a == c.am && d.col2[a] >= 0) tri = true;
+    if (tri) {
+      uint64_t lo = 0;
+#pragma unroll
+      for (int a = 0; a < kMaxBind; ++a)
+        if (a == c.am) tri_set(d, a, F, stride, c.p, lo);
+      c.e = d.tcol[lo + k];
+      return c;
+    }
+  }
   const uint32_t* rp = d.rp[0];
   const uint32_t* adj = d.adj[0];
   int col = d.col[0];
@@ -113,6 +148,12 @@ __device__ __forceinline__ bool intersect_all(const uint32_t* __restrict__ F, ui
 #pragma unroll
   for (int a = 0; a < kMaxBind; ++a) {
     if (a < d.k && a != c.am && keep) {
+      if (d.col2[a] >= 0) {
+        uint64_t lo;
+        uint32_t len = tri_set(d, a, F, stride, c.p, lo);
+        keep = contains_u32(d.tcol + lo, 0, len, c.e);
+        continue;
+      }
       uint32_t u = F[(uint64_t)d.col[a] * stride + c.p];
       keep = contains_u32(d.adj[a], d.rp[a][u], d.rp[a][u + 1], c.e);
     }
@@ -192,10 +233,11 @@ __global__ void __launch_bounds__(kBlock) k_propose(const uint32_t* __restrict__
 }
 
 // Writes the survivors of [w0, w1) in candidate order.
-// FINAL = false: prefixes p . e into frontier G (j + 1 columns), weights to Gw.
-// FINAL = true: rows of map.m values in attribute order at rows[(obase+pos)*m],
+// KIND 0: prefixes p . e into frontier G (j + 1 columns), weights to Gw.
+// KIND 1: rows of map.m values in attribute order at rows[(obase+pos)*m],
 // signs to osign, only for obase + pos < ocap.
-template <bool FINAL>
+// KIND 2: the new values only, at G[obase + pos] for obase + pos < ocap.
+template <int KIND>
 __global__ void __launch_bounds__(kBlock) k_emit(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n,
                                                  const uint64_t* __restrict__ off, const uint8_t* __restrict__ mini,
                                                  StageDesc d, uint64_t w0, uint64_t w1,
@@ -220,7 +262,9 @@ __global__ void __launch_bounds__(kBlock) k_emit(const uint32_t* __restrict__ F,
     if (!((b >> lane) & 1)) continue;
     Cand c = resolve(F, stride, off, mini, d, plo, phi, gf + lane);
     uint64_t pos = woff[wd] + __popcll(b & lanemask_lt());
-    if (!FINAL) {
+    if (KIND == 2) {
+      if (obase + pos < ocap) G[obase + pos] = c.e;
+    } else if (KIND == 0) {
       for (int col = 0; col < d.j; ++col) G[(uint64_t)col * gstride + pos] = F[(uint64_t)col * stride + c.p];
       G[(uint64_t)d.j * gstride + pos] = c.e;
       if (Gw) Gw[pos] = wt ? wt[c.p] : (int8_t)1;
@@ -327,11 +371,22 @@ void launch_emit(gj_ctx* c, bool final_rows, const uint32_t* F, uint64_t stride,
   uint64_t words = (w1 - w0 + 63) >> 6;
   unsigned gr = propose_grid(c, words);
   if (final_rows)
-    k_emit<true><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, wt, G, gstride,
-                                               Gw, map, obase, ocap);
+    k_emit<1><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, wt, G, gstride, Gw,
+                                            map, obase, ocap);
   else
-    k_emit<false><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, wt, G, gstride,
-                                                Gw, map, obase, ocap);
+    k_emit<0><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, wt, G, gstride, Gw,
+                                            map, obase, ocap);
+  GJ_HIP(hipGetLastError());
+}
+
+void launch_emit_values(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const uint64_t* off,
+                        const uint8_t* mini, const StageDesc& d, uint64_t w0, uint64_t w1, const uint64_t* mask,
+                        const uint64_t* woff, uint32_t* out, uint64_t obase, uint64_t ocap) {
+  uint64_t words = (w1 - w0 + 63) >> 6;
+  unsigned gr = propose_grid(c, words);
+  RowMap map{};
+  k_emit<2><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, nullptr, out, 0,
+                                          nullptr, map, obase, ocap);
   GJ_HIP(hipGetLastError());
 }
 

@@ -206,3 +206,23 @@ def test_rmat22_factorised_closed_forms(gj, rmat22):
     assert fan["extensions"][2] == fan["extensions"][3] == int(sum(inn * out))
     G.close()
     c.close()
+
+
+def test_rmat22_triangle_index(gj, rmat22):
+    """The triangle relation at scale 22 has as many entries as the owner
+    kernel counts triangles, and the 4-clique over it counts what the plain
+    4-clique counts on sampled seed slices."""
+    src, dst = rmat22
+    n = 1 << 22
+    c = gj.Context(0)
+    G = gj.Graph(c, src, dst, n)
+    tri = gj.count(c, G, gj.Query(c, *Q.TRIANGLE))["matches"]
+    assert G.index_triangles() == tri
+    t4 = gj.Query(c, Q.TRI_CLIQUE4[0], Q.TRI_CLIQUE4[1], Q.TRI_CLIQUE4[2], tris=Q.TRI_CLIQUE4[4])
+    k4 = gj.Query(c, *Q.CLIQUE4)
+    E = G.info()["edges"]
+    for lo, hi in slices(E, 6, 20000):
+        a, b = gj.count(c, G, t4, lo, hi), gj.count(c, G, k4, lo, hi)
+        assert a["matches"] == b["matches"] and a["prefixes"][3] == b["prefixes"][3], (lo, hi)
+    G.close()
+    c.close()
