@@ -190,6 +190,41 @@ def factorisation(gj, scale, log):
     return out
 
 
+def triangle_index(gj, scale, log):
+    """4-clique counts on R-MAT (seed 0), directed and degree-ordered, with
+    the six edge atoms and with three ternary atoms over the triangle
+    relation (Sec. 5.4), the index build timed apart; the counts must
+    agree."""
+    import synth
+    src, dst = synth.rmat_draws(scale, seed=0)
+    n = 1 << scale
+    k4 = (4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)], [0, 1, 2, 3])
+    tri_atoms = [(0, 1, 2), (0, 1, 3), (0, 2, 3)]
+    out = {"scale": scale}
+    c = gj.Context(0)
+    for kind in ("directed", "degree_ordered"):
+        G = gj.Graph(c, src, dst, n, degree_order=kind != "directed")
+        t = time.perf_counter()
+        ntri = G.index_triangles()
+        build = time.perf_counter() - t
+        res = {"triangles": ntri, "index_build_s": build}
+        for name, h in (("edge_atoms", gj.Query(c, *k4)),
+                        ("tri_atoms", gj.Query(c, 4, [(0, 1)], [0, 1, 2, 3], tris=tri_atoms))):
+            gj.count(c, G, h, 0, 100)
+            t = time.perf_counter()
+            r = gj.count(c, G, h)
+            res[name] = {"matches": r["matches"], "extensions": sum(r["extensions"]),
+                         "s": time.perf_counter() - t}
+        assert res["edge_atoms"]["matches"] == res["tri_atoms"]["matches"]
+        log("triangle index, 4-clique on %s R-MAT-%d: %d matches; edge atoms %.3f s, tri atoms %.3f s "
+            "(+ %.3f s index of %d triangles)" % (kind, scale, res["tri_atoms"]["matches"], res["edge_atoms"]["s"],
+                                                 res["tri_atoms"]["s"], build, ntri))
+        out[kind] = res
+        G.close()
+    c.close()
+    return out
+
+
 def update_latency(gj, src, dst, n, scale, nbatch, log):
     """Update stream (sizes log-uniform in [1, 100,000], 10% deletions, seed 1)
     maintaining the triangle count: one gj_apply_updates at a time with each
@@ -379,6 +414,8 @@ def main():
                     help="R-MAT scale of the symmetry-breaking leg (0: skip)")
     ap.add_argument("--factor-scale", type=int, default=16,
                     help="R-MAT scale of the factorised-count leg (0: skip)")
+    ap.add_argument("--tri-scale", type=int, default=18,
+                    help="R-MAT scale of the triangle-index leg (0: skip)")
     ap.add_argument("--sym-full", action="store_true",
                     help="also count 4-cliques with the plain query over the symmetric graph")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -470,6 +507,7 @@ def main():
 
     sym = symmetry_breaking(gj, ctx, args.sym_scale, log, args.sym_full) if args.sym_scale else None
     fact = factorisation(gj, args.factor_scale, log) if args.factor_scale else None
+    tri = triangle_index(gj, args.tri_scale, log) if args.tri_scale else None
 
     # delta-batch latency: update stream on the same graph
     lat = []
@@ -528,6 +566,7 @@ def main():
         "serving": serving,
         "symmetry_breaking": sym,
         "factorisation": fact,
+        "triangle_index": tri,
     }
     print(json.dumps(out), flush=True)
 
