@@ -78,6 +78,9 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   dQ_i binds the last attribute by one atom on each seed
  *                   attribute (the triangle shapes) on the owner-grouped
  *                   kernel, unless "strategy" is 1
+ *   "propose_u"     candidates per lane whose membership searches the
+ *                   generic propose kernel runs in lockstep: 1, 2 or 4
+ *                   (default 4; at most 2 in stages with ternary atoms)
  *   "factorise"     gj_run counts: 1 counts a trailing run of at least two
  *                   attributes that share no atom and no inequality as the
  *                   product of their extension counts per prefix before the

@@ -174,6 +174,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "delta_fused") {
       GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "delta_fused must be 0 or 1");
       c->delta_fused = (int)value;
+    } else if (k == "propose_u") {
+      GJ_CHECK(value == 1 || value == 2 || value == 4, GJ_EINVAL, "propose_u must be 1, 2 or 4");
+      c->propose_u = (int)value;
     } else if (k == "factorise") {
       GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "factorise must be 0 or 1");
       c->factorise = (int)value;
@@ -206,6 +209,7 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "delta_fused") *value = c->delta_fused;
     else if (k == "delta_owner_min") *value = (int64_t)c->delta_owner_min;
     else if (k == "factorise") *value = c->factorise;
+    else if (k == "propose_u") *value = c->propose_u;
     else throw Error{GJ_EINVAL, "unknown option " + k};
   });
 }
@@ -541,6 +545,7 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->delta_fused = src->delta_fused;
   dst->delta_owner_min = src->delta_owner_min;
   dst->factorise = src->factorise;
+  dst->propose_u = src->propose_u;
 }
 
 }  // namespace gj

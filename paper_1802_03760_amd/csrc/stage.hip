@@ -161,12 +161,69 @@ __device__ __forceinline__ bool intersect_all(const uint32_t* __restrict__ F, ui
   return keep;
 }
 
+// Membership tests of U candidates of a lane in lockstep: every step of their
+// binary searches issues the U loads before any comparison, so a wave keeps
+// U dependent-load chains in flight instead of one (the searches are bound by
+// load latency, not bandwidth).  Binary bindings only.
+template <int U>
+__device__ __forceinline__ void intersect_lockstep(const uint32_t* __restrict__ F, uint64_t stride,
+                                                   const StageDesc& d, const Cand (&c)[U], bool (&keep)[U]) {
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (keep[u]) keep[u] = ineq_ok(F, stride, c[u].p, d.above, d.below, c[u].e);
+#pragma unroll
+  for (int a = 0; a < kMaxBind; ++a) {
+    if (a < d.k) {
+      const uint32_t* arr = d.adj[a];
+      uint32_t lo[U], hi[U], n[U];
+      bool act[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        act[u] = keep[u] && a != c[u].am;
+        lo[u] = hi[u] = n[u] = 0;
+        if (act[u]) {
+          uint32_t x = F[(uint64_t)d.col[a] * stride + c[u].p];
+          lo[u] = d.rp[a][x];
+          hi[u] = d.rp[a][x + 1];
+          n[u] = hi[u] - lo[u];
+        }
+      }
+      for (;;) {
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < U; ++u) any = any || n[u] > 0;
+        if (!any) break;
+        uint32_t v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = n[u] > 0 ? arr[lo[u] + (n[u] >> 1)] : 0u;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (n[u] > 0) {
+            uint32_t half = n[u] >> 1;
+            if (v[u] < c[u].e) {
+              lo[u] += half + 1;
+              n[u] -= half + 1;
+            } else {
+              n[u] = half;
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (act[u]) keep[u] = lo[u] < hi[u] && arr[lo[u]] == c[u].e;
+    }
+  }
+}
+
 // MODE 0: write survivor ballots mask[word] and counts wcnt[word].
 // MODE 1: acc[0] += survivors.
 // MODE 2: acc[0] += survivors, acc[1] += sum of survivor weights (signed).
 // MODE 3: wcnt[p] += survivors of prefix p (a prefix's candidates are
 //         consecutive, so a wave adds once per prefix it touches).
-template <int MODE>
+// A wave takes U words (64 candidates each) per step, one candidate of each
+// per lane, and tests their memberships in lockstep.
+template <int MODE, int U>
 __global__ void __launch_bounds__(kBlock) k_propose(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n,
                                                     const uint64_t* __restrict__ off,
                                                     const uint8_t* __restrict__ mini, StageDesc d, uint64_t w0,
@@ -183,43 +240,60 @@ __global__ void __launch_bounds__(kBlock) k_propose(const uint32_t* __restrict__
   const uint64_t wbeg = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) * per;
   const uint64_t wend = wbeg + per < nwords ? wbeg + per : nwords;
   uint64_t plo = 0, phi;
-  for (uint64_t wd = wbeg; wd < wend; ++wd) {
+  for (uint64_t wd = wbeg; wd < wend; wd += U) {
+    const uint64_t wl = wd + U < wend ? wd + U : wend;  // words [wd, wl) this step
     uint64_t gf = w0 + (wd << 6);
-    uint64_t gl = gf + 63 < w1 ? gf + 63 : w1 - 1;
-    uint64_t g = gf + lane;
-    bool keep = false;
-    int8_t w = 1;
-    uint64_t pp = ~0ull;
+    uint64_t gl = w0 + (wl << 6) - 1 < w1 ? w0 + (wl << 6) - 1 : w1 - 1;
     plo = gallop_segment(off, plo, n, gf);
     phi = gallop_segment(off, plo, n, gl) + 1;
-    if (g < w1) {
-      Cand c = resolve(F, stride, off, mini, d, plo, phi, g);
-      keep = intersect_all(F, stride, d, c);
-      if (MODE == 2) w = wt[c.p];
-      pp = c.p;
+    Cand c[U];
+    bool keep[U];
+    uint64_t pp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint64_t g = gf + ((uint64_t)u << 6) + lane;
+      keep[u] = wd + u < wl && g < w1;
+      pp[u] = ~0ull;
+      c[u].p = 0;
+      c[u].e = 0;
+      c[u].am = 0;
+      if (keep[u]) {
+        c[u] = resolve(F, stride, off, mini, d, plo, phi, g);
+        pp[u] = c[u].p;
+      }
     }
-    uint64_t b = __ballot(keep);
-    if (MODE == 0) {
-      if (lane == 0) {
-        mask[wd] = b;
-        wcnt[wd] = (uint32_t)__popcll(b);
-      }
-    } else if (MODE == 3) {
-      // lanes of one prefix form a run; the first lane of each run adds the
-      // survivors of the run
-      uint64_t prev = shfl_up_u64(pp, 1);
-      bool start = pp != ~0ull && (lane == 0 || prev != pp);
-      uint64_t sb = __ballot(start);
-      if (start) {
-        uint64_t later = lane == 63 ? 0ull : (sb >> (lane + 1)) << (lane + 1);
-        int end = later ? __ffsll((unsigned long long)later) - 1 : 64;
-        uint64_t run = (end == 64 ? ~0ull : ((1ull << end) - 1)) & ~lanemask_lt();
-        uint32_t k = (uint32_t)__popcll(b & run);
-        if (k) atomicAdd(wcnt + pp, k);
-      }
+    if (U == 1 || d.ntri) {
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (keep[u]) keep[u] = intersect_all(F, stride, d, c[u]);
     } else {
-      cnt += keep ? 1 : 0;
-      if (MODE == 2) wsum += keep ? w : 0;
+      intersect_lockstep<U>(F, stride, d, c, keep);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      uint64_t b = __ballot(keep[u]);
+      if (MODE == 0) {
+        if (lane == 0 && wd + u < wl) {
+          mask[wd + u] = b;
+          wcnt[wd + u] = (uint32_t)__popcll(b);
+        }
+      } else if (MODE == 3) {
+        // lanes of one prefix form a run; the first lane of each run adds the
+        // survivors of the run
+        uint64_t prev = shfl_up_u64(pp[u], 1);
+        bool start = pp[u] != ~0ull && (lane == 0 || prev != pp[u]);
+        uint64_t sb = __ballot(start);
+        if (start) {
+          uint64_t later = lane == 63 ? 0ull : (sb >> (lane + 1)) << (lane + 1);
+          int end = later ? __ffsll((unsigned long long)later) - 1 : 64;
+          uint64_t run = (end == 64 ? ~0ull : ((1ull << end) - 1)) & ~lanemask_lt();
+          uint32_t k = (uint32_t)__popcll(b & run);
+          if (k) atomicAdd(wcnt + pp[u], k);
+        }
+      } else {
+        cnt += keep[u] ? 1 : 0;
+        if (MODE == 2 && keep[u]) wsum += wt[c[u].p];
+      }
     }
   }
   if (MODE == 1 || MODE == 2) {
@@ -334,14 +408,21 @@ void launch_propose(gj_ctx* c, int mode, const uint32_t* F, uint64_t stride, uin
                     uint32_t* wcnt, const int8_t* wt, unsigned long long* acc) {
   uint64_t words = (w1 - w0 + 63) >> 6;
   unsigned gr = propose_grid(c, words);
-  if (mode == 0)
-    k_propose<0><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);
-  else if (mode == 1)
-    k_propose<1><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);
-  else if (mode == 2)
-    k_propose<2><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);
-  else
-    k_propose<3><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);
+  // ternary bindings search one candidate at a time: wider steps only cost occupancy
+  int u = d.ntri && c->propose_u > 2 ? 2 : c->propose_u;
+  switch (mode * 8 + u) {
+#define GJ_PROPOSE(M, U)                                                                                  \
+  case M * 8 + U:                                                                                        \
+    k_propose<M, U><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc); \
+    break;
+    GJ_PROPOSE(0, 1) GJ_PROPOSE(0, 2) GJ_PROPOSE(0, 4)
+    GJ_PROPOSE(1, 1) GJ_PROPOSE(1, 2) GJ_PROPOSE(1, 4)
+    GJ_PROPOSE(2, 1) GJ_PROPOSE(2, 2) GJ_PROPOSE(2, 4)
+    GJ_PROPOSE(3, 1) GJ_PROPOSE(3, 2) GJ_PROPOSE(3, 4)
+#undef GJ_PROPOSE
+    default:
+      throw Error{GJ_EINVAL, "bad propose mode or width"};
+  }
   GJ_HIP(hipGetLastError());
 }
 

@@ -162,3 +162,28 @@ def test_errors(gj, ctx):
     with pytest.raises(gj.GJError) as e:
         gj.enumerate_rows(ctx, G, q, cap=n - 1)
     assert e.value.status == gj.GJ_EOVERFLOW
+
+
+@pytest.mark.parametrize("cap", [64, 1 << 25])
+def test_propose_widths_agree(gj, cap):
+    """The generic propose kernel tests 1, 2 or 4 candidates per lane in
+    lockstep; counts, counters and rows are the oracle's for every width,
+    with frontier caps that make odd word counts and ragged wave runs."""
+    src, dst = synth.rmat_draws(9, seed=41)
+    n = 1 << 9
+    O = oracle.Graph(n, src, dst)
+    c = gj.Context(0)
+    c.set_option("frontier_cap", cap)
+    G = gj.Graph(c, src, dst, n)
+    for q in (Q.CLIQUE4, Q.DIAMOND, Q.CYCLE4, Q.with_less(Q.HOUSE, [(1, 2)])):
+        ref = oracle.run(O, q, collect=q[0] < 5, threads=8)
+        h = gj.Query(c, *q)
+        for u in (1, 2, 4):
+            c.set_option("propose_u", u)
+            r = gj.count(c, G, h)
+            assert (r["matches"], r["prefixes"], r["extensions"]) == \
+                (ref["matches"], ref["prefixes"], ref["extensions"]), (q, u)
+            if q[0] < 5:
+                assert np.array_equal(gj.enumerate_rows(c, G, h)[1], ref["rows"]), (q, u)
+    with pytest.raises(gj.GJError):
+        c.set_option("propose_u", 3)
