@@ -68,6 +68,10 @@ const char* gj_last_error(const gj_ctx* ctx);
  *   "batch_waves_per_cu"  gj_run_batch: resident waves per CU of its
  *                   persistent grids, a multiple of 4 in [4, 128] (default 32)
  *   "batch_cap"     gj_run_batch: prefixes per level (default 2^27)
+ *   "batch_heavy"   gj_run_batch: requests whose estimated work (the
+ *                   server's seed-work estimate) reaches this run on the
+ *                   depth-first path, the rest fused (default 2^24; 0: all
+ *                   fused)
  *   "delta_fused"   gj_apply_updates: 1 (default) runs the delta queries of
  *                   every query that asks for counts only as one fused
  *                   pipeline (as gj_run_batch, with signed seeds); 0 runs

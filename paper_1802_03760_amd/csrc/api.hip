@@ -7,6 +7,7 @@
 #include "batch.h"
 #include "engine.h"
 #include "gj_internal.h"
+#include "sched.h"
 
 namespace gj {
 
@@ -174,6 +175,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "delta_fused") {
       GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "delta_fused must be 0 or 1");
       c->delta_fused = (int)value;
+    } else if (k == "batch_heavy") {
+      GJ_CHECK(value >= 0, GJ_EINVAL, "batch_heavy must be >= 0");
+      c->batch_heavy = (uint64_t)value;
     } else if (k == "propose_u") {
       GJ_CHECK(value == 1 || value == 2 || value == 4, GJ_EINVAL, "propose_u must be 1, 2 or 4");
       c->propose_u = (int)value;
@@ -210,6 +214,7 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "delta_owner_min") *value = (int64_t)c->delta_owner_min;
     else if (k == "factorise") *value = c->factorise;
     else if (k == "propose_u") *value = c->propose_u;
+    else if (k == "batch_heavy") *value = (int64_t)c->batch_heavy;
     else throw Error{GJ_EINVAL, "unknown option " + k};
   });
 }
@@ -444,14 +449,84 @@ gj_status gj_apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const ui
 }  // extern "C"
 
 namespace gj {
-// Counts of nreq requests on version `ver` (null: current): one fused run,
-// or depth-first runs if a level outgrew the batch capacity.
+static void count_fused(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs,
+                        const uint64_t* seed_lo, const uint64_t* seed_hi, uint64_t* counts, gj_stats* stats,
+                        const Version* ver);
+
+// Counts of nreq requests on version `ver` (null: current): requests of large
+// estimated work on the depth-first path, the others in one fused run.
 void count_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* seed_lo,
                  const uint64_t* seed_hi, uint64_t* counts, gj_stats* stats, const Version* ver) {
   for (uint32_t i = 0; i < nreq; ++i) GJ_CHECK(qs[i], GJ_EINVAL, "null query");
   for (uint32_t i = 0; i < nreq; ++i)
     GJ_CHECK(qs[i]->tris.empty(), GJ_EUNSUPPORTED, "ternary atoms run only through gj_run");
   if (nreq == 0) return;
+  if (c->batch_heavy && nreq > 1) {
+    // A request estimated at batch_heavy work or more fills the device alone,
+    // and the depth-first kernels serve it faster per candidate than the fused
+    // ones: it runs there, the rest stay fused.  Counts and counters are the
+    // same either way.
+    const Version& v = ver ? *ver : g->ver[g->cur];
+    std::vector<PlanH> plans;
+    plans.reserve(nreq);
+    std::vector<WorkReq> wr;
+    std::vector<uint32_t> est_of;
+    for (uint32_t i = 0; i < nreq; ++i) {
+      plans.push_back(make_plan(qs[i], qs[i]->order, -1));
+      uint64_t h = std::min<uint64_t>(seed_hi[i], v.m), l = std::min<uint64_t>(seed_lo[i], h);
+      if (h == l) continue;
+      wr.push_back(WorkReq{&plans.back(), &v, l, h - l, (uint32_t)std::min<uint64_t>(h - l, 0xffffffffu)});
+      est_of.push_back(i);
+    }
+    std::vector<uint64_t> out, off;
+    if (!wr.empty()) seed_work(c, wr, out, off);
+    std::vector<char> heavy(nreq, 0);
+    uint32_t nh = 0;
+    for (size_t k = 0; k < est_of.size(); ++k) {
+      uint64_t e = 0;
+      for (uint64_t b = off[k]; b < off[k + 1]; ++b) e += out[b];
+      if (e >= c->batch_heavy) {
+        heavy[est_of[k]] = 1;
+        ++nh;
+      }
+    }
+    if (nh) {
+      std::vector<const gj_query*> lq;
+      std::vector<uint64_t> llo, lhi, lc;
+      std::vector<uint32_t> li;
+      for (uint32_t i = 0; i < nreq; ++i)
+        if (!heavy[i]) {
+          li.push_back(i);
+          lq.push_back(qs[i]);
+          llo.push_back(seed_lo[i]);
+          lhi.push_back(seed_hi[i]);
+        }
+      lc.assign(li.size() + 1, 0);
+      std::vector<gj_stats> ls(li.size() + 1);
+      if (!li.empty())
+        count_fused(c, g, (uint32_t)li.size(), lq.data(), llo.data(), lhi.data(), lc.data(), ls.data(), ver);
+      for (size_t k = 0; k < li.size(); ++k) {
+        counts[li[k]] = lc[k];
+        if (stats) stats[li[k]] = ls[k];
+      }
+      for (uint32_t i = 0; i < nreq; ++i)
+        if (heavy[i]) {
+          gj_stats st{};
+          bool ov = false;
+          run_static(c, g, qs[i], GJ_MODE_COUNT, seed_lo[i], seed_hi[i], nullptr, 0, 1, &st, ov, ver);
+          counts[i] = st.matches;
+          if (stats) stats[i] = st;
+        }
+      return;
+    }
+  }
+  count_fused(c, g, nreq, qs, seed_lo, seed_hi, counts, stats, ver);
+}
+
+// One fused run, or depth-first runs if a level outgrew the batch capacity.
+static void count_fused(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs,
+                        const uint64_t* seed_lo, const uint64_t* seed_hi, uint64_t* counts, gj_stats* stats,
+                        const Version* ver) {
   if (!c->batch) c->batch = new BatchExec();
   bool overflow = false;
   c->batch->run(c, g, nreq, qs, seed_lo, seed_hi, counts, stats, overflow, ver);
@@ -546,6 +621,7 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->delta_owner_min = src->delta_owner_min;
   dst->factorise = src->factorise;
   dst->propose_u = src->propose_u;
+  dst->batch_heavy = src->batch_heavy;
 }
 
 }  // namespace gj

@@ -135,6 +135,7 @@ struct gj_ctx {
   int delta_fused = 1;              // count-only delta queries through the fused pipeline
   uint64_t delta_owner_min = 1ull << 17;  // changes from which triangle-shaped deltas use the owner kernel
   int factorise = 0;  // gj_run counts: trailing independent attributes as products
+  uint64_t batch_heavy = 1ull << 24;  // gj_run_batch: estimated work from which a request runs depth-first
   int propose_u = 4;  // candidates per lane tested in lockstep by the generic propose kernel (1, 2, 4)
 };
 

@@ -127,3 +127,25 @@ def test_autotune_and_cache(gj, tmp_path):
     t2 = gj.autotune(ctx2, G2, reqs2, path)
     assert t2["from_cache"] and (t2["batch_lin"], t2["batch_waves_per_cu"]) == (t["batch_lin"],
                                                                              t["batch_waves_per_cu"])
+
+
+@pytest.mark.parametrize("heavy", [0, 1, 2000])
+def test_heavy_requests_split_off(gj, heavy):
+    """Requests whose estimated work reaches batch_heavy run on the depth-first
+    path and the rest fused (0: all fused; 1: every non-empty request
+    depth-first; 2000: a mix): counts and counters equal the oracle's."""
+    src, dst = synth.rmat_draws(11, seed=23)
+    n = 1 << 11
+    ctx = gj.Context(0)
+    ctx.set_option("batch_heavy", heavy)
+    assert ctx.get_option("batch_heavy") == heavy
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle.Graph(n, src, dst)
+    reqs, specs = mixed_requests(gj, ctx, O.num_edges, np.random.default_rng(5), 36)
+    counts, stats = gj.run_batch(ctx, G, reqs)
+    for (q, lo, hi), c, st in zip(specs, counts, stats):
+        ref = oracle.run(O, q, seed_lo=lo, seed_hi=hi)
+        assert (c, st["prefixes"], st["extensions"]) == (ref["matches"], ref["prefixes"], ref["extensions"]), \
+            (q, lo, hi)
+    with pytest.raises(gj.GJError):
+        ctx.set_option("batch_heavy", -1)
