@@ -33,7 +33,9 @@ void tri_index_build(gj_ctx* c, gj_graph* g) {
   tri_index_free(g);
   const Version& v = g->ver[g->cur];
   uint64_t m = v.m;
-  TriIndex t;
+  // owned by the graph from the start (freed by gj_graph_destroy or the next
+  // build if this one fails); valid once version and slot are set at the end
+  TriIndex& t = g->tri;
   t.rp = (uint64_t*)dev_alloc((m + 1) * sizeof(uint64_t));
   // third attribute bound by out(x) and out(y)
   StageDesc d;
@@ -100,7 +102,6 @@ void tri_index_build(gj_ctx* c, gj_graph* g) {
   GJ_HIP(hipStreamSynchronize(c->stream));
   t.version = g->version;
   t.slot = g->cur;
-  g->tri = t;
 }
 
 }  // namespace gj
