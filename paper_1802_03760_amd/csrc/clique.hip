@@ -1,0 +1,186 @@
+// 4-clique counts grouped by seed edge (the transitive 4-clique query, every
+// atom from an earlier attribute of the order to a later one).  Generic Join
+// binds a2 from out(a0) & out(a1) and a3 from out(a0) & out(a1) & out(a2)
+// (Sec. 2.2); both share L = out(a0) & out(a1), so one wave per seed edge
+// intersects L once into LDS and counts, for each a2 in L, |L & out(a2)| --
+// the prefix's matches -- probing whichever side is smaller: out(a2)'s values
+// against L in LDS, or L's values against out(a2) in memory.  The work items
+// of all a2 of an edge are one flattened index space over the wave.
+//
+// The counters are those of the depth-first evaluation: extensions[2] sums
+// min(d0, d1) over the edges, prefixes[3] sums |L|, extensions[3] sums
+// min(d0, d1, d2) over the prefixes (a0, a1, a2).  An edge whose L does not
+// fit the wave's LDS share is left to the depth-first path (its id appended
+// to a list), contributing nothing here.
+#include "gj_internal.h"
+#include "prim.h"
+
+namespace gj {
+
+constexpr int kCqWaves = 4;          // waves per workgroup
+constexpr uint32_t kCqCap = 1024;    // entries of L per wave
+constexpr uint32_t kCqChunk = 16;    // edges claimed at a time
+
+// LDS written by some lanes of a wave and read by others
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ bool lds_contains(const uint32_t* a, uint32_t n0, uint32_t x) {
+  uint32_t lo = 0, n = n0;
+  while (n > 0) {
+    uint32_t half = n >> 1;
+    if (a[lo + half] < x) {
+      lo += half + 1;
+      n -= half + 1;
+    } else {
+      n = half;
+    }
+  }
+  return lo < n0 && a[lo] == x;
+}
+
+// last i in [0, n] with w[i] <= q (w ascending, w[0] = 0 <= q)
+__device__ __forceinline__ uint32_t lds_owner(const uint32_t* w, uint32_t n, uint32_t q) {
+  uint32_t lo = 0, hi = n + 1;  // w[lo] <= q < w[hi] (w[n + 1] taken as infinite)
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (w[mid] <= q)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kCqWaves * 64) k_clique4(const uint32_t* __restrict__ rp,
+                                                           const uint32_t* __restrict__ col,
+                                                           const uint32_t* __restrict__ row, uint64_t m,
+                                                           unsigned long long* __restrict__ claim,
+                                                           uint32_t* __restrict__ ovf,
+                                                           unsigned long long* __restrict__ acc) {
+  __shared__ uint32_t Ls[kCqWaves][kCqCap];
+  __shared__ uint32_t Ws[kCqWaves][kCqCap + 1];
+  const int lane = lane_id();
+  uint32_t* L = Ls[wave_id()];
+  uint32_t* Wp = Ws[wave_id()];
+  uint64_t matches = 0, pre3 = 0, ext2 = 0, ext3 = 0;
+  for (;;) {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(claim, (unsigned long long)kCqChunk);
+    base = shfl_u64(base, 0);
+    if (base >= m) break;
+    uint64_t end = base + kCqChunk < m ? base + kCqChunk : m;
+    for (uint64_t e = base; e < end; ++e) {
+      const uint32_t x0 = row[e], x1 = col[e];
+      const uint32_t b0 = rp[x0], d0 = rp[x0 + 1] - b0, b1 = rp[x1], d1 = rp[x1 + 1] - b1;
+      const uint32_t d01 = d0 < d1 ? d0 : d1;
+      // L = out(x0) & out(x1): the shorter list proposes, in order
+      const uint32_t sb = d0 <= d1 ? b0 : b1, gb = d0 <= d1 ? b1 : b0, gd = d0 <= d1 ? d1 : d0;
+      wave_lds_sync();  // the previous edge's reads of L are done
+      uint32_t nL = 0;
+      for (uint32_t t = 0; t < d01; t += 64) {
+        uint32_t i = t + lane;
+        uint32_t x = 0;
+        bool hit = false;
+        if (i < d01) {
+          x = col[sb + i];
+          hit = contains_u32(col, gb, gb + gd, x);
+        }
+        uint64_t bal = __ballot(hit);
+        uint32_t pos = nL + (uint32_t)__popcll(bal & lanemask_lt());
+        if (hit && pos < kCqCap) L[pos] = x;
+        nL += (uint32_t)__popcll(bal);
+      }
+      if (nL > kCqCap) {  // does not fit: the depth-first path takes this seed
+        if (lane == 0) ovf[atomicAdd(claim + 1, 1ull)] = (uint32_t)e;
+        continue;
+      }
+      if (lane == 0) {
+        ext2 += d01;
+        pre3 += nL;
+      }
+      if (nL == 0) continue;
+      wave_lds_sync();
+      // work of each a2: min(d2, |L|) probes; exclusive offsets in Wp
+      uint32_t run = 0;
+      for (uint32_t t = 0; t < nL; t += 64) {
+        uint32_t i = t + lane;
+        uint32_t w = 0;
+        if (i < nL) {
+          uint32_t a2 = L[i];
+          uint32_t d2 = rp[a2 + 1] - rp[a2];
+          w = d2 < nL ? d2 : nL;
+          ext3 += d2 < d01 ? d2 : d01;
+        }
+        uint32_t incl = wave_incl_scan(w);
+        if (i < nL) Wp[i] = run + incl - w;
+        run += __shfl(incl, 63, 64);
+      }
+      if (lane == 0) Wp[nL] = run;
+      wave_lds_sync();
+      for (uint32_t q0 = 0; q0 < run; q0 += 64) {
+        uint32_t q = q0 + lane;
+        bool found = false;
+        if (q < run) {
+          uint32_t i = lds_owner(Wp, nL, q);  // i < nL: Wp[nL] = run > q
+          uint32_t t = q - Wp[i];
+          uint32_t a2 = L[i];
+          uint32_t b2 = rp[a2], d2 = rp[a2 + 1] - b2;
+          if (d2 < nL)
+            found = lds_contains(L, nL, col[b2 + t]);  // t < d2
+          else
+            found = contains_u32(col, b2, b2 + d2, L[t]);  // t < nL
+        }
+        matches += found ? 1 : 0;
+      }
+    }
+  }
+  matches = wave_sum(matches);
+  ext3 = wave_sum(ext3);
+  ext2 = wave_sum(ext2);
+  pre3 = wave_sum(pre3);
+  if (lane == 0) {
+    if (matches) atomicAdd(acc + 0, (unsigned long long)matches);
+    if (pre3) atomicAdd(acc + 1, (unsigned long long)pre3);
+    if (ext2) atomicAdd(acc + 2, (unsigned long long)ext2);
+    if (ext3) atomicAdd(acc + 3, (unsigned long long)ext3);
+  }
+}
+
+__global__ void k_gather_seeds(const uint32_t* __restrict__ ids, uint64_t k, const uint32_t* __restrict__ row,
+                               const uint32_t* __restrict__ col, uint32_t* __restrict__ x0, uint32_t* __restrict__ x1) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gs) {
+    x0[i] = row[ids[i]];
+    x1[i] = col[ids[i]];
+  }
+}
+
+void clique4_count(gj_ctx* c, const Version& v, KernelTimer& timer, uint64_t out[4], uint32_t*& x0, uint32_t*& x1,
+                   uint64_t& n_left) {
+  const CsrDir& d = v.d[0];
+  unsigned long long* ctr = (unsigned long long*)ws_get(c, "cq_ctr", 6 * sizeof(unsigned long long));
+  uint32_t* ovf = (uint32_t*)ws_get(c, "cq_ovf", (v.m + 1) * sizeof(uint32_t));
+  GJ_HIP(hipMemsetAsync(ctr, 0, 6 * sizeof(unsigned long long), c->stream));
+  unsigned grid = (unsigned)c->num_cus * 4;  // 4 workgroups of 4 waves per CU (32 KiB LDS each)
+  timer.start();
+  if (v.m) k_clique4<<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2);
+  timer.stop();
+  GJ_HIP(hipGetLastError());
+  unsigned long long h[6];
+  read_bytes(c, h, ctr, sizeof(h));
+  n_left = h[1];
+  for (int i = 0; i < 4; ++i) out[i] = h[2 + i];
+  x0 = x1 = nullptr;
+  if (n_left) {
+    x0 = (uint32_t*)ws_get(c, "cq_x0", n_left * sizeof(uint32_t));
+    x1 = (uint32_t*)ws_get(c, "cq_x1", n_left * sizeof(uint32_t));
+    k_gather_seeds<<<grid_for(n_left, kBlock, 1u << 14), kBlock, 0, c->stream>>>(ovf, n_left, d.row, d.col, x0, x1);
+    GJ_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace gj

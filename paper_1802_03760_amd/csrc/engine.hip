@@ -391,6 +391,44 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
     *st = s;
     return;
   }
+  // Transitive 4-clique: grouped by seed edge (every atom from an earlier
+  // position to a later one, forward seeds, nothing else bound).
+  auto forward_from = [&](int j, int ncols) {
+    if ((int)P.bind[j].size() != ncols) return false;
+    int seen = 0;
+    for (const BindH& b : P.bind[j]) {
+      if (b.dir != 0 || b.col2 >= 0 || b.col >= ncols) return false;
+      seen |= 1 << b.col;
+    }
+    return seen == (1 << ncols) - 1;
+  };
+  if (!collect && c->strategy != 1 && P.m == 4 && P.filters.empty() && !P.has_ineq() && !P.ntri && P.seed_fwd &&
+      lo == 0 && hi == v.m && forward_from(2, 2) && forward_from(3, 3)) {
+    KernelTimer timer(c);
+    uint64_t o[4];
+    uint32_t *x0 = nullptr, *x1 = nullptr;
+    uint64_t left = 0;
+    clique4_count(c, v, timer, o, x0, x1, left);
+    gj_stats s{};
+    uint64_t mrest = 0;
+    if (left) {  // seeds whose common neighbourhood outgrew LDS
+      Runner R(c, P, V, false, false, std::max<uint64_t>(1, std::min<uint64_t>(c->seed_chunk, left)));
+      R.seed(x0, x1, nullptr, left);
+      int64_t ws = 0;
+      R.finish(mrest, ws);
+      s = R.st;
+    }
+    s.prefixes[2] = v.m;
+    s.extensions[2] += o[2];
+    s.prefixes[3] += o[1];
+    s.extensions[3] += o[3];
+    s.matches = mrest + o[0];
+    s.prefixes[4] = s.matches;
+    s.kernel_ms += timer.total_ms();
+    s.kernel_launches += timer.launches();
+    *st = s;
+    return;
+  }
   uint64_t seed_cap = std::max<uint64_t>(1, std::min<uint64_t>(c->seed_chunk, hi - lo));
   Runner R(c, P, V, false, collect, seed_cap);
   if (collect) {
