@@ -1,17 +1,21 @@
-// 4-clique counts grouped by seed edge (the transitive 4-clique query, every
-// atom from an earlier attribute of the order to a later one).  Generic Join
-// binds a2 from out(a0) & out(a1) and a3 from out(a0) & out(a1) & out(a2)
-// (Sec. 2.2); both share L = out(a0) & out(a1), so one wave per seed edge
-// intersects L once into LDS and counts, for each a2 in L, |L & out(a2)| --
-// the prefix's matches -- probing whichever side is smaller: out(a2)'s values
-// against L in LDS, or L's values against out(a2) in memory.  The work items
-// of all a2 of an edge are one flattened index space over the wave.
+// Whole counts of two four-attribute queries grouped by seed edge (a0, a1):
+// the transitive 4-clique (every atom from an earlier attribute of the order
+// to a later one), where Generic Join binds a2 from L = out(a0) & out(a1)
+// and a3 from L & out(a2) (Sec. 2.2); and the diamond edge(a0,a1),
+// edge(a0,a2), edge(a1,a3), edge(a2,a3), where a2 ranges over out(a0) and
+// a3 over out(a1) & out(a2).  In both, a3 ranges over S & out(a2) with S
+// (L, or out(a1)) fixed by the edge, so one wave per seed edge puts S in its
+// LDS share once and counts |S & out(a2)| for every a2, probing whichever
+// side is smaller: out(a2)'s values against S in LDS, or S's values against
+// out(a2) in memory.  The probes of all a2 of an edge (in chunks of the
+// offsets' LDS share) form one flattened index space over the wave.
 //
 // The counters are those of the depth-first evaluation: extensions[2] sums
-// min(d0, d1) over the edges, prefixes[3] sums |L|, extensions[3] sums
-// min(d0, d1, d2) over the prefixes (a0, a1, a2).  An edge whose L does not
-// fit the wave's LDS share is left to the depth-first path (its id appended
-// to a list), contributing nothing here.
+// the stage-2 count-minimisation (min(d0, d1), or d0) over the edges,
+// prefixes[3] the a2 per edge, extensions[3] the stage-3 minimum (min(d0, d1,
+// d2), or min(d1, d2)) over the prefixes.  An edge whose S does not fit the
+// wave's LDS share is left to the depth-first path (its id appended to a
+// list) and contributes nothing here.
 #include "gj_internal.h"
 #include "prim.h"
 
@@ -55,16 +59,21 @@ __device__ __forceinline__ uint32_t lds_owner(const uint32_t* w, uint32_t n, uin
   return lo;
 }
 
-__global__ void __launch_bounds__(kCqWaves * 64) k_clique4(const uint32_t* __restrict__ rp,
-                                                           const uint32_t* __restrict__ col,
-                                                           const uint32_t* __restrict__ row, uint64_t m,
-                                                           unsigned long long* __restrict__ claim,
-                                                           uint32_t* __restrict__ ovf,
-                                                           unsigned long long* __restrict__ acc) {
+// SHAPE 0, the transitive 4-clique: S = L = out(a0) & out(a1) and a2 ranges
+// over L.  SHAPE 1, the diamond edge(a0,a1), edge(a0,a2), edge(a1,a3),
+// edge(a2,a3): S = out(a1) and a2 ranges over out(a0).  Either way a3 ranges
+// over S & out(a2), and S sits in the wave's LDS share.
+template <int SHAPE>
+__global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restrict__ rp,
+                                                         const uint32_t* __restrict__ col,
+                                                         const uint32_t* __restrict__ row, uint64_t m,
+                                                         unsigned long long* __restrict__ claim,
+                                                         uint32_t* __restrict__ ovf,
+                                                         unsigned long long* __restrict__ acc) {
   __shared__ uint32_t Ls[kCqWaves][kCqCap];
   __shared__ uint32_t Ws[kCqWaves][kCqCap + 1];
   const int lane = lane_id();
-  uint32_t* L = Ls[wave_id()];
+  uint32_t* S = Ls[wave_id()];
   uint32_t* Wp = Ws[wave_id()];
   uint64_t matches = 0, pre3 = 0, ext2 = 0, ext3 = 0;
   for (;;) {
@@ -77,64 +86,78 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_clique4(const uint32_t* __res
       const uint32_t x0 = row[e], x1 = col[e];
       const uint32_t b0 = rp[x0], d0 = rp[x0 + 1] - b0, b1 = rp[x1], d1 = rp[x1 + 1] - b1;
       const uint32_t d01 = d0 < d1 ? d0 : d1;
-      // L = out(x0) & out(x1): the shorter list proposes, in order
-      const uint32_t sb = d0 <= d1 ? b0 : b1, gb = d0 <= d1 ? b1 : b0, gd = d0 <= d1 ? d1 : d0;
-      wave_lds_sync();  // the previous edge's reads of L are done
-      uint32_t nL = 0;
-      for (uint32_t t = 0; t < d01; t += 64) {
-        uint32_t i = t + lane;
-        uint32_t x = 0;
-        bool hit = false;
-        if (i < d01) {
-          x = col[sb + i];
-          hit = contains_u32(col, gb, gb + gd, x);
+      wave_lds_sync();  // the previous edge's reads of S are done
+      uint32_t nS = 0;
+      if (SHAPE == 0) {
+        // L = out(x0) & out(x1): the shorter list proposes, in order
+        const uint32_t sb = d0 <= d1 ? b0 : b1, gb = d0 <= d1 ? b1 : b0, gd = d0 <= d1 ? d1 : d0;
+        for (uint32_t t = 0; t < d01; t += 64) {
+          uint32_t i = t + lane;
+          uint32_t x = 0;
+          bool hit = false;
+          if (i < d01) {
+            x = col[sb + i];
+            hit = contains_u32(col, gb, gb + gd, x);
+          }
+          uint64_t bal = __ballot(hit);
+          uint32_t pos = nS + (uint32_t)__popcll(bal & lanemask_lt());
+          if (hit && pos < kCqCap) S[pos] = x;
+          nS += (uint32_t)__popcll(bal);
         }
-        uint64_t bal = __ballot(hit);
-        uint32_t pos = nL + (uint32_t)__popcll(bal & lanemask_lt());
-        if (hit && pos < kCqCap) L[pos] = x;
-        nL += (uint32_t)__popcll(bal);
+      } else {
+        nS = d1;  // S = out(x1)
+        if (nS <= kCqCap)
+          for (uint32_t i = lane; i < d1; i += 64) S[i] = col[b1 + i];
       }
-      if (nL > kCqCap) {  // does not fit: the depth-first path takes this seed
+      if (nS > kCqCap) {  // does not fit: the depth-first path takes this seed
         if (lane == 0) ovf[atomicAdd(claim + 1, 1ull)] = (uint32_t)e;
         continue;
       }
+      // the a2 list: L in LDS, or out(x0) in memory
+      const uint32_t na2 = SHAPE == 0 ? nS : d0;
       if (lane == 0) {
-        ext2 += d01;
-        pre3 += nL;
+        ext2 += SHAPE == 0 ? d01 : d0;
+        pre3 += na2;
       }
-      if (nL == 0) continue;
+      if (na2 == 0) continue;
       wave_lds_sync();
-      // work of each a2: min(d2, |L|) probes; exclusive offsets in Wp
-      uint32_t run = 0;
-      for (uint32_t t = 0; t < nL; t += 64) {
-        uint32_t i = t + lane;
-        uint32_t w = 0;
-        if (i < nL) {
-          uint32_t a2 = L[i];
-          uint32_t d2 = rp[a2 + 1] - rp[a2];
-          w = d2 < nL ? d2 : nL;
-          ext3 += d2 < d01 ? d2 : d01;
+      for (uint32_t c0 = 0; c0 < na2; c0 += kCqCap) {  // a2 in chunks of the offsets' LDS share
+        const uint32_t cn = na2 - c0 < kCqCap ? na2 - c0 : kCqCap;
+        // work of each a2: min(d2, |S|) probes; exclusive offsets in Wp
+        uint32_t run = 0;
+        for (uint32_t t = 0; t < cn; t += 64) {
+          uint32_t i = t + lane;
+          uint32_t w = 0;
+          if (i < cn) {
+            uint32_t a2 = SHAPE == 0 ? S[c0 + i] : col[b0 + c0 + i];
+            uint32_t d2 = rp[a2 + 1] - rp[a2];
+            w = d2 < nS ? d2 : nS;
+            uint32_t lim = SHAPE == 0 ? d01 : d1;  // count-minimisation of the last stage
+            ext3 += d2 < lim ? d2 : lim;
+          }
+          uint32_t incl = wave_incl_scan(w);
+          if (i < cn) Wp[i] = run + incl - w;
+          run += __shfl(incl, 63, 64);
         }
-        uint32_t incl = wave_incl_scan(w);
-        if (i < nL) Wp[i] = run + incl - w;
-        run += __shfl(incl, 63, 64);
-      }
-      if (lane == 0) Wp[nL] = run;
-      wave_lds_sync();
-      for (uint32_t q0 = 0; q0 < run; q0 += 64) {
-        uint32_t q = q0 + lane;
-        bool found = false;
-        if (q < run) {
-          uint32_t i = lds_owner(Wp, nL, q);  // i < nL: Wp[nL] = run > q
-          uint32_t t = q - Wp[i];
-          uint32_t a2 = L[i];
-          uint32_t b2 = rp[a2], d2 = rp[a2 + 1] - b2;
-          if (d2 < nL)
-            found = lds_contains(L, nL, col[b2 + t]);  // t < d2
-          else
-            found = contains_u32(col, b2, b2 + d2, L[t]);  // t < nL
+        wave_lds_sync();  // Wp's readers below may run ahead of this chunk's writers
+        if (lane == 0) Wp[cn] = run;
+        wave_lds_sync();
+        for (uint32_t q0 = 0; q0 < run; q0 += 64) {
+          uint32_t q = q0 + lane;
+          bool found = false;
+          if (q < run) {
+            uint32_t i = lds_owner(Wp, cn, q);  // i < cn: Wp[cn] = run > q
+            uint32_t t = q - Wp[i];
+            uint32_t a2 = SHAPE == 0 ? S[c0 + i] : col[b0 + c0 + i];
+            uint32_t b2 = rp[a2], d2 = rp[a2 + 1] - b2;
+            if (d2 < nS)
+              found = lds_contains(S, nS, col[b2 + t]);  // t < d2
+            else
+              found = contains_u32(col, b2, b2 + d2, S[t]);  // t < nS
+          }
+          matches += found ? 1 : 0;
         }
-        matches += found ? 1 : 0;
+        wave_lds_sync();  // this chunk's reads of Wp are done
       }
     }
   }
@@ -159,15 +182,16 @@ __global__ void k_gather_seeds(const uint32_t* __restrict__ ids, uint64_t k, con
   }
 }
 
-void clique4_count(gj_ctx* c, const Version& v, KernelTimer& timer, uint64_t out[4], uint32_t*& x0, uint32_t*& x1,
-                   uint64_t& n_left) {
+void edge4_count(gj_ctx* c, const Version& v, int shape, KernelTimer& timer, uint64_t out[4], uint32_t*& x0,
+                 uint32_t*& x1, uint64_t& n_left) {
   const CsrDir& d = v.d[0];
   unsigned long long* ctr = (unsigned long long*)ws_get(c, "cq_ctr", 6 * sizeof(unsigned long long));
   uint32_t* ovf = (uint32_t*)ws_get(c, "cq_ovf", (v.m + 1) * sizeof(uint32_t));
   GJ_HIP(hipMemsetAsync(ctr, 0, 6 * sizeof(unsigned long long), c->stream));
   unsigned grid = (unsigned)c->num_cus * 4;  // 4 workgroups of 4 waves per CU (32 KiB LDS each)
   timer.start();
-  if (v.m) k_clique4<<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2);
+  if (v.m && shape == 0) k_edge4<0><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2);
+  if (v.m && shape == 1) k_edge4<1><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2);
   timer.stop();
   GJ_HIP(hipGetLastError());
   unsigned long long h[6];

@@ -391,24 +391,28 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
     *st = s;
     return;
   }
-  // Transitive 4-clique: grouped by seed edge (every atom from an earlier
-  // position to a later one, forward seeds, nothing else bound).
-  auto forward_from = [&](int j, int ncols) {
-    if ((int)P.bind[j].size() != ncols) return false;
+  // Transitive 4-clique and diamond: grouped by seed edge (forward seeds,
+  // stage bindings all out-lists of exactly the given columns).
+  auto out_of = [&](int j, int cols) {
     int seen = 0;
     for (const BindH& b : P.bind[j]) {
-      if (b.dir != 0 || b.col2 >= 0 || b.col >= ncols) return false;
+      if (b.dir != 0 || b.col2 >= 0 || ((cols >> b.col) & 1) == 0 || ((seen >> b.col) & 1)) return false;
       seen |= 1 << b.col;
     }
-    return seen == (1 << ncols) - 1;
+    return seen == cols;
   };
+  int shape = -1;
   if (!collect && c->strategy != 1 && P.m == 4 && P.filters.empty() && !P.has_ineq() && !P.ntri && P.seed_fwd &&
-      lo == 0 && hi == v.m && forward_from(2, 2) && forward_from(3, 3)) {
+      lo == 0 && hi == v.m) {
+    if (out_of(2, 0b011) && out_of(3, 0b111)) shape = 0;       // a2: a0, a1; a3: a0, a1, a2
+    else if (out_of(2, 0b001) && out_of(3, 0b110)) shape = 1;  // a2: a0; a3: a1, a2
+  }
+  if (shape >= 0) {
     KernelTimer timer(c);
     uint64_t o[4];
     uint32_t *x0 = nullptr, *x1 = nullptr;
     uint64_t left = 0;
-    clique4_count(c, v, timer, o, x0, x1, left);
+    edge4_count(c, v, shape, timer, o, x0, x1, left);
     gj_stats s{};
     uint64_t mrest = 0;
     if (left) {  // seeds whose common neighbourhood outgrew LDS

@@ -190,11 +190,11 @@ def test_propose_widths_agree(gj, cap):
 
 
 def test_clique4_edge_grouped_kernel(gj, ctx):
-    """Full 4-clique counts run grouped by seed edge; seeds whose common
-    out-neighbourhood exceeds the kernel's LDS share (two hubs with 1,030
-    common neighbours, chained so 4-cliques exist) finish on the depth-first
-    path.  Counts and every counter equal the oracle's and the generic
-    path's (strategy 1)."""
+    """Full 4-clique and diamond counts run grouped by seed edge; seeds whose
+    fixed set exceeds the kernel's LDS share (two hubs with 1,030 common
+    neighbours, chained so 4-cliques exist) finish on the depth-first path.
+    Counts and every counter equal the oracle's and the generic path's
+    (strategy 1)."""
     k = 1030
     common = np.arange(2, 2 + k, dtype=np.uint32)
     s = [np.array([0], np.uint32), np.zeros(k, np.uint32), np.ones(k, np.uint32), common[:-1]]
@@ -207,12 +207,13 @@ def test_clique4_edge_grouped_kernel(gj, ctx):
     src, dst = np.concatenate(s), np.concatenate(d)
     n = 6000 + (1 << 11)
     G, O = gj.Graph(ctx, src, dst, n), oracle.Graph(n, src, dst)
-    ref = oracle.run(O, Q.CLIQUE4, threads=8)
-    assert ref["matches"] >= k - 1
     c1 = gj.Context(0)
     c1.set_option("strategy", 1)
     G1 = gj.Graph(c1, src, dst, n)
-    for cc, GG in ((ctx, G), (c1, G1)):
-        r = gj.count(cc, GG, gj.Query(cc, *Q.CLIQUE4))
-        assert (r["matches"], r["prefixes"], r["extensions"]) == \
-            (ref["matches"], ref["prefixes"], ref["extensions"])
+    for q in (Q.CLIQUE4, Q.DIAMOND):
+        ref = oracle.run(O, q, threads=8)
+        assert ref["matches"] >= k - 1
+        for cc, GG in ((ctx, G), (c1, G1)):
+            r = gj.count(cc, GG, gj.Query(cc, *q))
+            assert (r["matches"], r["prefixes"], r["extensions"]) == \
+                (ref["matches"], ref["prefixes"], ref["extensions"]), q
