@@ -538,3 +538,28 @@ def test_tri_invalid():
     assert not oracle.query_valid((3, [(0, 1)], [0, 1, 2], [], [(0, 2, 1)]))  # binds a middle attribute
     assert not oracle.query_valid((3, [(0, 1)], [0, 1, 2], [], [(0, 0, 2)]))
     assert not oracle.query_valid((3, [(0, 1)], [0, 1, 2], [], [(0, 1, 3)]))
+
+
+@pytest.mark.parametrize("n", [4, 7, 10])
+def test_counter_closed_forms(n):
+    """Per-stage counters beyond the first stage, from closed forms.
+    Complete digraph K_n: every set has n - 1 values, so each stage proposes
+    n - 1 per prefix; prefixes are the tuples of the shape's distinctness.
+    Transitive tournament (i -> j iff i < j): out(v) = n - 1 - v, so the
+    smallest set of a prefix is the out-list of its largest vertex."""
+    G = oracle.Graph(n, *complete(n))
+    k = n - 1
+    r = oracle.run(G, Q.TRIANGLE)
+    assert r["prefixes"][2:4] == [n * k, n * k * (n - 2)] and r["extensions"][2] == n * k * k
+    r = oracle.run(G, Q.CLIQUE4)
+    assert r["prefixes"][3] == n * k * (n - 2) and r["extensions"][3] == n * k * (n - 2) * k
+    for q in (Q.DIAMOND, Q.CYCLE4):  # a2 may repeat a1 (diamond) or a0 (4-cycle)
+        r = oracle.run(G, q)
+        assert r["prefixes"][3] == n * k * k and r["extensions"][2] == n * k * k
+        assert r["extensions"][3] == n * k ** 3
+    T = oracle.Graph(n, *tournament(n))
+    r = oracle.run(T, Q.TRIANGLE)
+    assert r["extensions"][2] == sum(j * (n - 1 - j) for j in range(n))
+    r = oracle.run(T, Q.CLIQUE4)
+    assert r["prefixes"][3] == math.comb(n, 3)
+    assert r["extensions"][3] == sum(math.comb(z, 2) * (n - 1 - z) for z in range(n))
