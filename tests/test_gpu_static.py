@@ -191,21 +191,24 @@ def test_propose_widths_agree(gj, cap):
 
 def test_clique4_edge_grouped_kernel(gj, ctx):
     """Full 4-clique and diamond counts run grouped by seed edge; seeds whose
-    fixed set exceeds the kernel's LDS share (two hubs with 1,030 common
-    neighbours, chained so 4-cliques exist) finish on the depth-first path.
-    Counts and every counter equal the oracle's and the generic path's
-    (strategy 1)."""
-    k = 1030
-    common = np.arange(2, 2 + k, dtype=np.uint32)
-    s = [np.array([0], np.uint32), np.zeros(k, np.uint32), np.ones(k, np.uint32), common[:-1]]
-    d = [np.array([1], np.uint32), common, common, common[1:]]
-    # a second, smaller hub pair below the LDS share, and an R-MAT background
-    rs, rd = synth.rmat_draws(11, seed=44)
-    s += [np.full(300, 5000, np.uint32), np.full(300, 5001, np.uint32), np.array([5000], np.uint32), rs + 6000]
-    d += [np.arange(5002, 5302, dtype=np.uint32), np.arange(5002, 5302, dtype=np.uint32),
-          np.array([5001], np.uint32), rd + 6000]
+    fixed set exceeds the kernel's LDS share (1,024 entries) finish on the
+    depth-first path.  Hub pairs with 300, 1,030 and 16,400 common
+    neighbours (chained so 4-cliques exist) fall on both sides.  Counts and
+    every counter equal the oracle's and the generic path's (strategy 1)."""
+    s, d = [], []
+    base = 0
+    for k in (300, 1030, 16400):
+        h0, h1 = base, base + 1
+        common = np.arange(base + 2, base + 2 + k, dtype=np.uint32)
+        s += [np.array([h0], np.uint32), np.full(k, h0, np.uint32), np.full(k, h1, np.uint32), common[:-1]]
+        d += [np.array([h1], np.uint32), common, common, common[1:]]
+        base += k + 2
+    rs, rd = synth.rmat_draws(11, seed=44)  # an R-MAT background
+    s.append(rs + base)
+    d.append(rd + base)
+    k = 300
     src, dst = np.concatenate(s), np.concatenate(d)
-    n = 6000 + (1 << 11)
+    n = base + (1 << 11)
     G, O = gj.Graph(ctx, src, dst, n), oracle.Graph(n, src, dst)
     c1 = gj.Context(0)
     c1.set_option("strategy", 1)
