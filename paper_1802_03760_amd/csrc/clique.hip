@@ -59,6 +59,26 @@ __device__ __forceinline__ uint32_t lds_owner(const uint32_t* w, uint32_t n, uin
   return lo;
 }
 
+// Inequalities of the query (symmetry breaking, Sec. 5.4): the value bound at
+// position j must exceed (above[j]) or stay below (below[j]) the values of
+// the prefix columns whose bits are set.
+struct EdgeIneq {
+  uint32_t above[4], below[4];
+};
+
+__device__ __forceinline__ bool ineq3(const EdgeIneq& q, int j, uint32_t v, uint32_t c0, uint32_t c1, uint32_t c2) {
+  const uint32_t a = q.above[j], b = q.below[j];
+  if (!(a | b)) return true;
+  bool ok = true;
+  if (a & 1) ok = ok && v > c0;
+  if (a & 2) ok = ok && v > c1;
+  if (a & 4) ok = ok && v > c2;
+  if (b & 1) ok = ok && v < c0;
+  if (b & 2) ok = ok && v < c1;
+  if (b & 4) ok = ok && v < c2;
+  return ok;
+}
+
 // SHAPE 0, the transitive 4-clique: S = L = out(a0) & out(a1) and a2 ranges
 // over L.  SHAPE 1, the diamond edge(a0,a1), edge(a0,a2), edge(a1,a3),
 // edge(a2,a3): S = out(a1) and a2 ranges over out(a0).  Either way a3 ranges
@@ -69,13 +89,13 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
                                                          const uint32_t* __restrict__ row, uint64_t m,
                                                          unsigned long long* __restrict__ claim,
                                                          uint32_t* __restrict__ ovf,
-                                                         unsigned long long* __restrict__ acc) {
+                                                         unsigned long long* __restrict__ acc, EdgeIneq iq) {
   __shared__ uint32_t Ls[kCqWaves][kCqCap];
   __shared__ uint32_t Ws[kCqWaves][kCqCap + 1];
   const int lane = lane_id();
   uint32_t* S = Ls[wave_id()];
   uint32_t* Wp = Ws[wave_id()];
-  uint64_t matches = 0, pre3 = 0, ext2 = 0, ext3 = 0;
+  uint64_t matches = 0, pre2 = 0, pre3 = 0, ext2 = 0, ext3 = 0;
   for (;;) {
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(claim, (unsigned long long)kCqChunk);
@@ -84,6 +104,7 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
     uint64_t end = base + kCqChunk < m ? base + kCqChunk : m;
     for (uint64_t e = base; e < end; ++e) {
       const uint32_t x0 = row[e], x1 = col[e];
+      if (!ineq3(iq, 1, x1, x0, 0, 0)) continue;  // the seed is not in P_2
       const uint32_t b0 = rp[x0], d0 = rp[x0 + 1] - b0, b1 = rp[x1], d1 = rp[x1 + 1] - b1;
       const uint32_t d01 = d0 < d1 ? d0 : d1;
       wave_lds_sync();  // the previous edge's reads of S are done
@@ -113,11 +134,12 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
         if (lane == 0) ovf[atomicAdd(claim + 1, 1ull)] = (uint32_t)e;
         continue;
       }
-      // the a2 list: L in LDS, or out(x0) in memory
+      // the a2 list: L in LDS, or out(x0) in memory; a2 failing an
+      // inequality gets no work (S stays whole: a3 may take such values)
       const uint32_t na2 = SHAPE == 0 ? nS : d0;
       if (lane == 0) {
         ext2 += SHAPE == 0 ? d01 : d0;
-        pre3 += na2;
+        pre2 += 1;
       }
       if (na2 == 0) continue;
       wave_lds_sync();
@@ -130,10 +152,13 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
           uint32_t w = 0;
           if (i < cn) {
             uint32_t a2 = SHAPE == 0 ? S[c0 + i] : col[b0 + c0 + i];
-            uint32_t d2 = rp[a2 + 1] - rp[a2];
-            w = d2 < nS ? d2 : nS;
-            uint32_t lim = SHAPE == 0 ? d01 : d1;  // count-minimisation of the last stage
-            ext3 += d2 < lim ? d2 : lim;
+            if (ineq3(iq, 2, a2, x0, x1, 0)) {
+              uint32_t d2 = rp[a2 + 1] - rp[a2];
+              w = d2 < nS ? d2 : nS;
+              uint32_t lim = SHAPE == 0 ? d01 : d1;  // count-minimisation of the last stage
+              ext3 += d2 < lim ? d2 : lim;
+              pre3 += 1;
+            }
           }
           uint32_t incl = wave_incl_scan(w);
           if (i < cn) Wp[i] = run + incl - w;
@@ -150,10 +175,9 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
             uint32_t t = q - Wp[i];
             uint32_t a2 = SHAPE == 0 ? S[c0 + i] : col[b0 + c0 + i];
             uint32_t b2 = rp[a2], d2 = rp[a2 + 1] - b2;
-            if (d2 < nS)
-              found = lds_contains(S, nS, col[b2 + t]);  // t < d2
-            else
-              found = contains_u32(col, b2, b2 + d2, S[t]);  // t < nS
+            uint32_t a3 = d2 < nS ? col[b2 + t] : S[t];  // t < d2, or t < nS
+            found = d2 < nS ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
+            found = found && ineq3(iq, 3, a3, x0, x1, a2);
           }
           matches += found ? 1 : 0;
         }
@@ -165,11 +189,13 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
   ext3 = wave_sum(ext3);
   ext2 = wave_sum(ext2);
   pre3 = wave_sum(pre3);
+  pre2 = wave_sum(pre2);
   if (lane == 0) {
     if (matches) atomicAdd(acc + 0, (unsigned long long)matches);
     if (pre3) atomicAdd(acc + 1, (unsigned long long)pre3);
     if (ext2) atomicAdd(acc + 2, (unsigned long long)ext2);
     if (ext3) atomicAdd(acc + 3, (unsigned long long)ext3);
+    if (pre2) atomicAdd(acc + 4, (unsigned long long)pre2);
   }
 }
 
@@ -182,22 +208,29 @@ __global__ void k_gather_seeds(const uint32_t* __restrict__ ids, uint64_t k, con
   }
 }
 
-void edge4_count(gj_ctx* c, const Version& v, int shape, KernelTimer& timer, uint64_t out[4], uint32_t*& x0,
-                 uint32_t*& x1, uint64_t& n_left) {
+void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4], const uint32_t below[4],
+                 KernelTimer& timer, uint64_t out[5], uint32_t*& x0, uint32_t*& x1, uint64_t& n_left) {
   const CsrDir& d = v.d[0];
-  unsigned long long* ctr = (unsigned long long*)ws_get(c, "cq_ctr", 6 * sizeof(unsigned long long));
+  unsigned long long* ctr = (unsigned long long*)ws_get(c, "cq_ctr", 7 * sizeof(unsigned long long));
   uint32_t* ovf = (uint32_t*)ws_get(c, "cq_ovf", (v.m + 1) * sizeof(uint32_t));
-  GJ_HIP(hipMemsetAsync(ctr, 0, 6 * sizeof(unsigned long long), c->stream));
+  GJ_HIP(hipMemsetAsync(ctr, 0, 7 * sizeof(unsigned long long), c->stream));
+  EdgeIneq iq;
+  for (int j = 0; j < 4; ++j) {
+    iq.above[j] = above[j];
+    iq.below[j] = below[j];
+  }
   unsigned grid = (unsigned)c->num_cus * 4;  // 4 workgroups of 4 waves per CU (32 KiB LDS each)
   timer.start();
-  if (v.m && shape == 0) k_edge4<0><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2);
-  if (v.m && shape == 1) k_edge4<1><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2);
+  if (v.m && shape == 0)
+    k_edge4<0><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
+  if (v.m && shape == 1)
+    k_edge4<1><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
   timer.stop();
   GJ_HIP(hipGetLastError());
-  unsigned long long h[6];
+  unsigned long long h[7];
   read_bytes(c, h, ctr, sizeof(h));
   n_left = h[1];
-  for (int i = 0; i < 4; ++i) out[i] = h[2 + i];
+  for (int i = 0; i < 5; ++i) out[i] = h[2 + i];
   x0 = x1 = nullptr;
   if (n_left) {
     x0 = (uint32_t*)ws_get(c, "cq_x0", n_left * sizeof(uint32_t));

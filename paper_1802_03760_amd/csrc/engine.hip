@@ -402,17 +402,17 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
     return seen == cols;
   };
   int shape = -1;
-  if (!collect && c->strategy != 1 && P.m == 4 && P.filters.empty() && !P.has_ineq() && !P.ntri && P.seed_fwd &&
-      lo == 0 && hi == v.m) {
+  if (!collect && c->strategy != 1 && P.m == 4 && P.filters.empty() && !P.ntri && P.seed_fwd && lo == 0 &&
+      hi == v.m) {
     if (out_of(2, 0b011) && out_of(3, 0b111)) shape = 0;       // a2: a0, a1; a3: a0, a1, a2
     else if (out_of(2, 0b001) && out_of(3, 0b110)) shape = 1;  // a2: a0; a3: a1, a2
   }
   if (shape >= 0) {
     KernelTimer timer(c);
-    uint64_t o[4];
+    uint64_t o[5];
     uint32_t *x0 = nullptr, *x1 = nullptr;
     uint64_t left = 0;
-    edge4_count(c, v, shape, timer, o, x0, x1, left);
+    edge4_count(c, v, shape, P.above.data(), P.below.data(), timer, o, x0, x1, left);
     gj_stats s{};
     uint64_t mrest = 0;
     if (left) {  // seeds whose common neighbourhood outgrew LDS
@@ -422,7 +422,7 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
       R.finish(mrest, ws);
       s = R.st;
     }
-    s.prefixes[2] = v.m;
+    s.prefixes[2] += o[4];  // seeds that pass the inequalities (the depth-first rest counted its own)
     s.extensions[2] += o[2];
     s.prefixes[3] += o[1];
     s.extensions[3] += o[3];

@@ -232,12 +232,13 @@ void launch_emit_values(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t 
                         const uint8_t* mini, const StageDesc& d, uint64_t w0, uint64_t w1, const uint64_t* mask,
                         const uint64_t* woff, uint32_t* out, uint64_t obase, uint64_t ocap);
 // clique.hip: the transitive 4-clique (shape 0) or the diamond (shape 1) over
-// every forward edge of v, grouped by seed edge.  out = {matches, prefixes[3],
-// extensions[2], extensions[3]} of the edges it finished; the n_left others
+// every forward edge of v, grouped by seed edge, with the plan's inequality
+// masks of positions 1..3.  out = {matches, prefixes[3], extensions[2],
+// extensions[3], prefixes[2]} of the seeds it finished; the n_left others
 // (their fixed set too large for LDS) are left as seed pairs (x0[i], x1[i]) in
 // context workspace for the depth-first path.
-void edge4_count(gj_ctx* c, const Version& v, int shape, KernelTimer& timer, uint64_t out[4], uint32_t*& x0,
-                 uint32_t*& x1, uint64_t& n_left);
+void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4], const uint32_t below[4],
+                 KernelTimer& timer, uint64_t out[5], uint32_t*& x0, uint32_t*& x1, uint64_t& n_left);
 // tri.hip: the triangle relation of the graph's current version (replaces
 // g->tri); frees it
 void tri_index_build(gj_ctx* c, gj_graph* g);
