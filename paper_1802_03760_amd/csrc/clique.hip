@@ -199,6 +199,112 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
   }
 }
 
+// The seeds whose fixed set outgrew a wave's share, again with a whole
+// workgroup per seed: 16,384 entries of S (64 KiB of LDS), compaction and
+// offsets by workgroup scans, the probes spread over 256 lanes.  Seeds
+// beyond that are appended to ovf for the depth-first path.
+constexpr uint32_t kCqCapWg = 16384;
+constexpr uint32_t kCqOffWg = 1024;
+
+template <int SHAPE>
+__global__ void __launch_bounds__(kBlock) k_edge4_wg(const uint32_t* __restrict__ rp,
+                                                     const uint32_t* __restrict__ col,
+                                                     const uint32_t* __restrict__ row, const uint32_t* __restrict__ ids,
+                                                     uint64_t m, unsigned long long* __restrict__ claim,
+                                                     uint32_t* __restrict__ ovf, unsigned long long* __restrict__ acc,
+                                                     EdgeIneq iq) {
+  __shared__ uint32_t S[kCqCapWg];
+  __shared__ uint32_t Wp[kCqOffWg + 1];
+  __shared__ unsigned long long next;
+  const uint32_t tid = threadIdx.x;
+  uint64_t matches = 0, pre2 = 0, pre3 = 0, ext2 = 0, ext3 = 0;
+  for (;;) {
+    __syncthreads();  // the previous seed's reads of S and Wp are done
+    if (tid == 0) next = atomicAdd(claim, 1ull);
+    __syncthreads();
+    const unsigned long long k = next;
+    if (k >= m) break;
+    const uint64_t e = ids[k];
+    const uint32_t x0 = row[e], x1 = col[e];
+    if (!ineq3(iq, 1, x1, x0, 0, 0)) continue;
+    const uint32_t b0 = rp[x0], d0 = rp[x0 + 1] - b0, b1 = rp[x1], d1 = rp[x1 + 1] - b1;
+    const uint32_t d01 = d0 < d1 ? d0 : d1;
+    uint32_t nS = 0;
+    if (SHAPE == 0) {
+      const uint32_t sb = d0 <= d1 ? b0 : b1, gb = d0 <= d1 ? b1 : b0, gd = d0 <= d1 ? d1 : d0;
+      for (uint32_t t = 0; t < d01; t += kBlock) {
+        uint32_t i = t + tid;
+        uint32_t x = 0, hit = 0;
+        if (i < d01) {
+          x = col[sb + i];
+          hit = contains_u32(col, gb, gb + gd, x) ? 1u : 0u;
+        }
+        uint32_t tot = 0;
+        uint32_t pos = nS + block_excl_scan<kBlock>(hit, tot);
+        if (hit && pos < kCqCapWg) S[pos] = x;
+        nS += tot;
+      }
+    } else {
+      nS = d1;
+      if (nS <= kCqCapWg)
+        for (uint32_t i = tid; i < d1; i += kBlock) S[i] = col[b1 + i];
+    }
+    if (nS > kCqCapWg) {
+      if (tid == 0) ovf[atomicAdd(claim + 1, 1ull)] = (uint32_t)e;
+      continue;
+    }
+    const uint32_t na2 = SHAPE == 0 ? nS : d0;
+    if (tid == 0) {
+      ext2 += SHAPE == 0 ? d01 : d0;
+      pre2 += 1;
+    }
+    __syncthreads();
+    for (uint32_t c0 = 0; c0 < na2; c0 += kCqOffWg) {
+      const uint32_t cn = na2 - c0 < kCqOffWg ? na2 - c0 : kCqOffWg;
+      uint32_t run = 0;
+      for (uint32_t t = 0; t < cn; t += kBlock) {
+        uint32_t i = t + tid;
+        uint32_t w = 0;
+        if (i < cn) {
+          uint32_t a2 = SHAPE == 0 ? S[c0 + i] : col[b0 + c0 + i];
+          if (ineq3(iq, 2, a2, x0, x1, 0)) {
+            uint32_t d2 = rp[a2 + 1] - rp[a2];
+            w = d2 < nS ? d2 : nS;
+            uint32_t lim = SHAPE == 0 ? d01 : d1;
+            ext3 += d2 < lim ? d2 : lim;
+            pre3 += 1;
+          }
+        }
+        uint32_t tot = 0;
+        uint32_t ex = block_excl_scan<kBlock>(w, tot);
+        if (i < cn) Wp[i] = run + ex;
+        run += tot;
+      }
+      if (tid == 0) Wp[cn] = run;
+      __syncthreads();
+      for (uint32_t q0 = 0; q0 < run; q0 += kBlock) {
+        uint32_t q = q0 + tid;
+        if (q < run) {
+          uint32_t i = lds_owner(Wp, cn, q);  // i < cn: Wp[cn] = run > q
+          uint32_t t = q - Wp[i];
+          uint32_t a2 = SHAPE == 0 ? S[c0 + i] : col[b0 + c0 + i];
+          uint32_t b2 = rp[a2], d2 = rp[a2 + 1] - b2;
+          uint32_t a3 = d2 < nS ? col[b2 + t] : S[t];
+          bool found = d2 < nS ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
+          matches += (found && ineq3(iq, 3, a3, x0, x1, a2)) ? 1 : 0;
+        }
+      }
+      __syncthreads();  // this chunk's reads of Wp are done
+    }
+  }
+  uint64_t v[5] = {matches, pre3, ext2, ext3, pre2};
+#pragma unroll
+  for (int i = 0; i < 5; ++i) {
+    uint64_t t = block_sum<kBlock>(v[i]);
+    if (tid == 0 && t) atomicAdd(acc + i, (unsigned long long)t);
+  }
+}
+
 __global__ void k_gather_seeds(const uint32_t* __restrict__ ids, uint64_t k, const uint32_t* __restrict__ row,
                                const uint32_t* __restrict__ col, uint32_t* __restrict__ x0, uint32_t* __restrict__ x1) {
   uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
@@ -211,9 +317,11 @@ __global__ void k_gather_seeds(const uint32_t* __restrict__ ids, uint64_t k, con
 void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4], const uint32_t below[4],
                  KernelTimer& timer, uint64_t out[5], uint32_t*& x0, uint32_t*& x1, uint64_t& n_left) {
   const CsrDir& d = v.d[0];
-  unsigned long long* ctr = (unsigned long long*)ws_get(c, "cq_ctr", 7 * sizeof(unsigned long long));
+  // ctr: [0] seed claim, [1] overflow count, [2, 7) counters, [7] second-pass
+  // claim, [8] its overflow count
+  unsigned long long* ctr = (unsigned long long*)ws_get(c, "cq_ctr", 9 * sizeof(unsigned long long));
   uint32_t* ovf = (uint32_t*)ws_get(c, "cq_ovf", (v.m + 1) * sizeof(uint32_t));
-  GJ_HIP(hipMemsetAsync(ctr, 0, 7 * sizeof(unsigned long long), c->stream));
+  GJ_HIP(hipMemsetAsync(ctr, 0, 9 * sizeof(unsigned long long), c->stream));
   EdgeIneq iq;
   for (int j = 0; j < 4; ++j) {
     iq.above[j] = above[j];
@@ -227,15 +335,29 @@ void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4]
     k_edge4<1><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
   timer.stop();
   GJ_HIP(hipGetLastError());
-  unsigned long long h[7];
+  unsigned long long n1 = 0;
+  read_bytes(c, &n1, ctr + 1, sizeof(n1));
+  const uint32_t* left = ovf;
+  // the 4-clique's larger sets: a workgroup per seed (measured slower than
+  // the depth-first path for the diamond, whose overflowing seeds go there)
+  if (n1 && shape == 0) {
+    uint32_t* ovf2 = (uint32_t*)ws_get(c, "cq_ovf2", (n1 + 1) * sizeof(uint32_t));
+    unsigned grid2 = (unsigned)c->num_cus * 2;  // 2 workgroups per CU (68 KiB of LDS each)
+    timer.start();
+    k_edge4_wg<0><<<grid2, kBlock, 0, c->stream>>>(d.rp, d.col, d.row, ovf, n1, ctr + 7, ovf2, ctr + 2, iq);
+    timer.stop();
+    GJ_HIP(hipGetLastError());
+    left = ovf2;
+  }
+  unsigned long long h[9];
   read_bytes(c, h, ctr, sizeof(h));
-  n_left = h[1];
+  n_left = n1 && shape == 0 ? h[8] : h[1];
   for (int i = 0; i < 5; ++i) out[i] = h[2 + i];
   x0 = x1 = nullptr;
   if (n_left) {
     x0 = (uint32_t*)ws_get(c, "cq_x0", n_left * sizeof(uint32_t));
     x1 = (uint32_t*)ws_get(c, "cq_x1", n_left * sizeof(uint32_t));
-    k_gather_seeds<<<grid_for(n_left, kBlock, 1u << 14), kBlock, 0, c->stream>>>(ovf, n_left, d.row, d.col, x0, x1);
+    k_gather_seeds<<<grid_for(n_left, kBlock, 1u << 14), kBlock, 0, c->stream>>>(left, n_left, d.row, d.col, x0, x1);
     GJ_HIP(hipGetLastError());
   }
 }
