@@ -16,6 +16,8 @@
 // d2), or min(d1, d2)) over the prefixes.  An edge whose S does not fit the
 // wave's LDS share is left to the depth-first path (its id appended to a
 // list) and contributes nothing here.
+#include <algorithm>
+
 #include "gj_internal.h"
 #include "prim.h"
 
@@ -360,6 +362,130 @@ void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4]
     k_gather_seeds<<<grid_for(n_left, kBlock, 1u << 14), kBlock, 0, c->stream>>>(left, n_left, d.row, d.col, x0, x1);
     GJ_HIP(hipGetLastError());
   }
+}
+
+// ---------------------------------------------------------------- diamond by 2-path counts
+// The diamond's matches from a0 are the pairs (a1, a2) of out(a0) with a
+// common out-neighbour a3, counted per a3: with k(a3) the number of 2-paths
+// a0 -> a1 -> a3, a0 contributes the sum of k(a3)^2 (a1 = a2 included, as
+// the join allows).  One workgroup per a0 counts its 2-path endpoints with
+// atomics in a private dense array of n counters, then walks the same
+// 2-paths again taking each count with an exchange to zero (the first visit
+// of an endpoint gets k, later ones 0), which leaves the array clear.  The
+// counters are the depth-first evaluation's: extensions[2] = prefixes[3] =
+// sum of d0^2 (a2 is proposed from out(a0) alone), extensions[3] = the sum
+// over (a1, a2) in out(a0)^2 of min(d(a1), d(a2)), from tiles of the
+// neighbours' degrees in LDS.
+constexpr uint32_t kDgTile = 4096;  // degrees per LDS tile
+constexpr uint32_t kDgOff = 1024;   // a1 per offsets chunk
+
+__global__ void __launch_bounds__(kBlock) k_diamond2p(const uint32_t* __restrict__ rp,
+                                                      const uint32_t* __restrict__ col, uint32_t n,
+                                                      unsigned int* __restrict__ cnt_all, uint64_t cnt_stride,
+                                                      unsigned long long* __restrict__ claim,
+                                                      unsigned long long* __restrict__ acc) {
+  __shared__ uint32_t DA[kDgTile], DB[kDgTile];
+  __shared__ uint32_t Wp[kDgOff + 1];
+  __shared__ unsigned long long next;
+  unsigned int* cnt = cnt_all + (uint64_t)blockIdx.x * cnt_stride;
+  const uint32_t tid = threadIdx.x;
+  uint64_t matches = 0, sq = 0, ext3 = 0;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) next = atomicAdd(claim, 1ull);
+    __syncthreads();
+    const unsigned long long a0 = next;
+    if (a0 >= n) break;
+    const uint32_t b0 = rp[a0], d0 = rp[a0 + 1] - b0;
+    if (d0 == 0) continue;
+    if (tid == 0) sq += (uint64_t)d0 * d0;
+    // extensions[3]: sum over ordered pairs of min(degree), in tiles
+    for (uint32_t ta = 0; ta < d0; ta += kDgTile) {
+      const uint32_t na = d0 - ta < kDgTile ? d0 - ta : kDgTile;
+      __syncthreads();
+      for (uint32_t i = tid; i < na; i += kBlock) {
+        uint32_t v = col[b0 + ta + i];
+        DA[i] = rp[v + 1] - rp[v];
+      }
+      for (uint32_t tb = 0; tb < d0; tb += kDgTile) {
+        const uint32_t nb = d0 - tb < kDgTile ? d0 - tb : kDgTile;
+        __syncthreads();
+        for (uint32_t i = tid; i < nb; i += kBlock) {
+          uint32_t v = col[b0 + tb + i];
+          DB[i] = rp[v + 1] - rp[v];
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < na; i += kBlock) {
+          const uint32_t x = DA[i];
+          uint64_t s = 0;
+          for (uint32_t j = 0; j < nb; ++j) {
+            uint32_t y = DB[j];
+            s += y < x ? y : x;
+          }
+          ext3 += s;
+        }
+      }
+    }
+    // the 2-paths, twice: counting, then taking the counts back to zero
+    for (int pass = 0; pass < 2; ++pass) {
+      for (uint32_t c0 = 0; c0 < d0; c0 += kDgOff) {
+        const uint32_t cn = d0 - c0 < kDgOff ? d0 - c0 : kDgOff;
+        uint32_t run = 0;
+        for (uint32_t t = 0; t < cn; t += kBlock) {
+          uint32_t i = t + tid, w = 0;
+          if (i < cn) {
+            uint32_t a1 = col[b0 + c0 + i];
+            w = rp[a1 + 1] - rp[a1];
+          }
+          uint32_t tot = 0;
+          uint32_t ex = block_excl_scan<kBlock>(w, tot);
+          if (i < cn) Wp[i] = run + ex;
+          run += tot;
+        }
+        if (tid == 0) Wp[cn] = run;
+        __syncthreads();
+        for (uint32_t q = tid; q < run; q += kBlock) {
+          uint32_t i = lds_owner(Wp, cn, q);  // i < cn: Wp[cn] = run > q
+          uint32_t a1 = col[b0 + c0 + i];
+          uint32_t a3 = col[rp[a1] + (q - Wp[i])];
+          if (pass == 0) {
+            atomicAdd(cnt + a3, 1u);
+          } else {
+            uint64_t k = atomicExch(cnt + a3, 0u);
+            matches += k * k;
+          }
+        }
+        __syncthreads();
+      }
+      // every count of this a0 is in before any is taken back
+      __threadfence();
+      __syncthreads();
+    }
+  }
+  uint64_t v[3] = {matches, sq, ext3};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    uint64_t t = block_sum<kBlock>(v[i]);
+    if (tid == 0 && t) atomicAdd(acc + i, (unsigned long long)t);
+  }
+}
+
+void diamond2p_count(gj_ctx* c, const Version& v, uint32_t n, KernelTimer& timer, uint64_t out[3]) {
+  const CsrDir& d = v.d[0];
+  // one dense counter array per workgroup, at most 16 GiB in all
+  uint64_t per = ((uint64_t)n + 63) / 64 * 64;
+  uint64_t wgs = std::min<uint64_t>((uint64_t)c->num_cus * 2, std::max<uint64_t>(1, (16ull << 30) / (per * 4)));
+  unsigned int* cnt = (unsigned int*)ws_get(c, "dg_cnt", wgs * per * sizeof(unsigned int));
+  unsigned long long* ctr = (unsigned long long*)ws_get(c, "dg_ctr", 4 * sizeof(unsigned long long));
+  GJ_HIP(hipMemsetAsync(cnt, 0, wgs * per * sizeof(unsigned int), c->stream));
+  GJ_HIP(hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), c->stream));
+  timer.start();
+  k_diamond2p<<<(unsigned)wgs, kBlock, 0, c->stream>>>(d.rp, d.col, n, cnt, per, ctr, ctr + 1);
+  timer.stop();
+  GJ_HIP(hipGetLastError());
+  unsigned long long h[4];
+  read_bytes(c, h, ctr, sizeof(h));
+  for (int i = 0; i < 3; ++i) out[i] = h[1 + i];
 }
 
 }  // namespace gj

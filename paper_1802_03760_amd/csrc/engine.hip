@@ -407,6 +407,20 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
     if (out_of(2, 0b011) && out_of(3, 0b111)) shape = 0;       // a2: a0, a1; a3: a0, a1, a2
     else if (out_of(2, 0b001) && out_of(3, 0b110)) shape = 1;  // a2: a0; a3: a1, a2
   }
+  if (shape == 1 && !P.has_ineq()) {  // diamond: 2-path counts per a0
+    KernelTimer timer(c);
+    uint64_t o[3];
+    diamond2p_count(c, v, g->n, timer, o);
+    gj_stats s{};
+    s.prefixes[2] = v.m;
+    s.extensions[2] = s.prefixes[3] = o[1];
+    s.extensions[3] = o[2];
+    s.matches = s.prefixes[4] = o[0];
+    s.kernel_ms = timer.total_ms();
+    s.kernel_launches = timer.launches();
+    *st = s;
+    return;
+  }
   if (shape >= 0) {
     KernelTimer timer(c);
     uint64_t o[5];

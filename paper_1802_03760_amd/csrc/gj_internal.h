@@ -239,6 +239,9 @@ void launch_emit_values(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t 
 // context workspace for the depth-first path.
 void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4], const uint32_t below[4],
                  KernelTimer& timer, uint64_t out[5], uint32_t*& x0, uint32_t*& x1, uint64_t& n_left);
+// clique.hip: the diamond over every forward edge of v by 2-path counts (no
+// inequalities): out = {matches, prefixes[3] = extensions[2], extensions[3]}.
+void diamond2p_count(gj_ctx* c, const Version& v, uint32_t n, KernelTimer& timer, uint64_t out[3]);
 // tri.hip: the triangle relation of the graph's current version (replaces
 // g->tri); frees it
 void tri_index_build(gj_ctx* c, gj_graph* g);
