@@ -488,4 +488,112 @@ void diamond2p_count(gj_ctx* c, const Version& v, uint32_t n, KernelTimer& timer
   for (int i = 0; i < 3; ++i) out[i] = h[1 + i];
 }
 
+// ---------------------------------------------------------------- 4-cycle by 2-path counts
+// The 4-cycle edge(a0,a1), edge(a1,a2), edge(a2,a3), edge(a3,a0): the
+// matches from a0 pair each forward 2-path a0 -> a1 -> a2 with each backward
+// one a2 -> a3 -> a0 of the same a2, so a0 contributes the sum over a2 of
+// k(a2) k'(a2) (forward times backward 2-path counts).  One workgroup per a0
+// adds the forward 2-paths' endpoints into its private counters, walks the
+// backward 2-paths (through the reverse index) summing the counters they
+// reach, and walks the forward ones again to clear them.  Counters as the
+// depth-first evaluation: extensions[2] = prefixes[3] = the forward 2-paths
+// (a2 is proposed from out(a1) alone), extensions[3] = the sum over them of
+// min(|out(a2)|, |in(a0)|).
+
+// Calls f(a1, a2) for every 2-path a0 -> a1 -> a2 with a1 in col1[b0, b0 + d0)
+// and a2 in the row of a1 in (rp2, col2), over the workgroup.
+template <class F>
+__device__ __forceinline__ void walk_2paths(const uint32_t* __restrict__ col1, uint32_t b0, uint32_t d0,
+                                            const uint32_t* __restrict__ rp2, const uint32_t* __restrict__ col2,
+                                            uint32_t* Wp, F f) {
+  const uint32_t tid = threadIdx.x;
+  for (uint32_t c0 = 0; c0 < d0; c0 += kDgOff) {
+    const uint32_t cn = d0 - c0 < kDgOff ? d0 - c0 : kDgOff;
+    uint32_t run = 0;
+    for (uint32_t t = 0; t < cn; t += kBlock) {
+      uint32_t i = t + tid, w = 0;
+      if (i < cn) {
+        uint32_t a1 = col1[b0 + c0 + i];
+        w = rp2[a1 + 1] - rp2[a1];
+      }
+      uint32_t tot = 0;
+      uint32_t ex = block_excl_scan<kBlock>(w, tot);
+      if (i < cn) Wp[i] = run + ex;
+      run += tot;
+    }
+    if (tid == 0) Wp[cn] = run;
+    __syncthreads();
+    for (uint32_t q = tid; q < run; q += kBlock) {
+      uint32_t i = lds_owner(Wp, cn, q);  // i < cn: Wp[cn] = run > q
+      uint32_t a1 = col1[b0 + c0 + i];
+      f(a1, col2[rp2[a1] + (q - Wp[i])]);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_cycle4_2p(const uint32_t* __restrict__ rpf,
+                                                      const uint32_t* __restrict__ colf,
+                                                      const uint32_t* __restrict__ rpr,
+                                                      const uint32_t* __restrict__ colr, uint32_t n,
+                                                      unsigned int* __restrict__ cnt_all, uint64_t cnt_stride,
+                                                      unsigned long long* __restrict__ claim,
+                                                      unsigned long long* __restrict__ acc) {
+  __shared__ uint32_t Wp[kDgOff + 1];
+  __shared__ unsigned long long next;
+  unsigned int* cnt = cnt_all + (uint64_t)blockIdx.x * cnt_stride;
+  const uint32_t tid = threadIdx.x;
+  uint64_t matches = 0, paths = 0, ext3 = 0;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) next = atomicAdd(claim, 1ull);
+    __syncthreads();
+    const unsigned long long a0 = next;
+    if (a0 >= n) break;
+    const uint32_t bo = rpf[a0], dout = rpf[a0 + 1] - bo, bi = rpr[a0], din = rpr[a0 + 1] - bi;
+    if (dout == 0) continue;
+    walk_2paths(colf, bo, dout, rpf, colf, Wp, [&](uint32_t, uint32_t a2) {
+      atomicAdd(cnt + a2, 1u);
+      uint32_t d2 = rpf[a2 + 1] - rpf[a2];
+      ext3 += d2 < din ? d2 : din;
+      paths += 1;
+    });
+    __threadfence();
+    __syncthreads();
+    if (din)
+      walk_2paths(colr, bi, din, rpr, colr, Wp, [&](uint32_t, uint32_t a2) {
+        matches += __hip_atomic_load(cnt + a2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // at L2
+      });
+    __syncthreads();
+    walk_2paths(colf, bo, dout, rpf, colf, Wp, [&](uint32_t, uint32_t a2) {
+      __hip_atomic_store(cnt + a2, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    });
+    __threadfence();
+    __syncthreads();
+  }
+  uint64_t v[3] = {matches, paths, ext3};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    uint64_t t = block_sum<kBlock>(v[i]);
+    if (tid == 0 && t) atomicAdd(acc + i, (unsigned long long)t);
+  }
+}
+
+void cycle4_2p_count(gj_ctx* c, const Version& v, uint32_t n, KernelTimer& timer, uint64_t out[3]) {
+  uint64_t per = ((uint64_t)n + 63) / 64 * 64;
+  uint64_t wgs = std::min<uint64_t>((uint64_t)c->num_cus * 2, std::max<uint64_t>(1, (16ull << 30) / (per * 4)));
+  unsigned int* cnt = (unsigned int*)ws_get(c, "dg_cnt", wgs * per * sizeof(unsigned int));
+  unsigned long long* ctr = (unsigned long long*)ws_get(c, "dg_ctr", 4 * sizeof(unsigned long long));
+  GJ_HIP(hipMemsetAsync(cnt, 0, wgs * per * sizeof(unsigned int), c->stream));
+  GJ_HIP(hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), c->stream));
+  timer.start();
+  k_cycle4_2p<<<(unsigned)wgs, kBlock, 0, c->stream>>>(v.d[0].rp, v.d[0].col, v.d[1].rp, v.d[1].col, n, cnt, per,
+                                                        ctr, ctr + 1);
+  timer.stop();
+  GJ_HIP(hipGetLastError());
+  unsigned long long h[4];
+  read_bytes(c, h, ctr, sizeof(h));
+  for (int i = 0; i < 3; ++i) out[i] = h[1 + i];
+}
+
 }  // namespace gj

@@ -407,10 +407,20 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
     if (out_of(2, 0b011) && out_of(3, 0b111)) shape = 0;       // a2: a0, a1; a3: a0, a1, a2
     else if (out_of(2, 0b001) && out_of(3, 0b110)) shape = 1;  // a2: a0; a3: a1, a2
   }
-  if (shape == 1 && !P.has_ineq()) {  // diamond: 2-path counts per a0
+  // 4-cycle: a2 from out(a1), a3 from out(a2) and in(a0)
+  auto is_bind = [&](const BindH& b, int col, int dir) { return b.col == col && b.dir == dir && b.col2 < 0; };
+  bool cycle4 = !collect && c->strategy != 1 && P.m == 4 && P.filters.empty() && !P.has_ineq() && !P.ntri &&
+                P.seed_fwd && lo == 0 && hi == v.m && P.bind[2].size() == 1 && is_bind(P.bind[2][0], 1, 0) &&
+                P.bind[3].size() == 2 &&
+                ((is_bind(P.bind[3][0], 2, 0) && is_bind(P.bind[3][1], 0, 1)) ||
+                 (is_bind(P.bind[3][1], 2, 0) && is_bind(P.bind[3][0], 0, 1)));
+  if ((shape == 1 && !P.has_ineq()) || cycle4) {  // diamond / 4-cycle: 2-path counts per a0
     KernelTimer timer(c);
     uint64_t o[3];
-    diamond2p_count(c, v, g->n, timer, o);
+    if (cycle4)
+      cycle4_2p_count(c, v, g->n, timer, o);
+    else
+      diamond2p_count(c, v, g->n, timer, o);
     gj_stats s{};
     s.prefixes[2] = v.m;
     s.extensions[2] = s.prefixes[3] = o[1];

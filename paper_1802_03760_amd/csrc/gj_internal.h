@@ -242,6 +242,10 @@ void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4]
 // clique.hip: the diamond over every forward edge of v by 2-path counts (no
 // inequalities): out = {matches, prefixes[3] = extensions[2], extensions[3]}.
 void diamond2p_count(gj_ctx* c, const Version& v, uint32_t n, KernelTimer& timer, uint64_t out[3]);
+// clique.hip: the 4-cycle a0 -> a1 -> a2 -> a3 -> a0 by forward and backward
+// 2-path counts (no inequalities): out = {matches, prefixes[3] =
+// extensions[2], extensions[3]}.
+void cycle4_2p_count(gj_ctx* c, const Version& v, uint32_t n, KernelTimer& timer, uint64_t out[3]);
 // tri.hip: the triangle relation of the graph's current version (replaces
 // g->tri); frees it
 void tri_index_build(gj_ctx* c, gj_graph* g);

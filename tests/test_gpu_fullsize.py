@@ -228,10 +228,11 @@ def test_rmat22_triangle_index(gj, rmat22):
     c.close()
 
 
-def test_rmat18_diamond_paths_agree(gj):
-    """The diamond count by 2-path counts (default) and by the generic
-    per-candidate path (strategy 1) agree on counts and every counter at
-    R-MAT scale 18."""
+@pytest.mark.parametrize("name", ["diamond", "cycle4"])
+def test_rmat18_2path_counts_agree(gj, name):
+    """The diamond and 4-cycle counts by 2-path counts (default) and by the
+    generic per-candidate path (strategy 1) agree on counts and every
+    counter at R-MAT scale 18."""
     src, dst = synth.rmat_draws(18, seed=0)
     n = 1 << 18
     res = []
@@ -239,7 +240,7 @@ def test_rmat18_diamond_paths_agree(gj):
         c = gj.Context(0)
         c.set_option("strategy", strategy)
         G = gj.Graph(c, src, dst, n)
-        r = gj.count(c, G, gj.Query(c, *Q.DIAMOND))
+        r = gj.count(c, G, gj.Query(c, *Q.ALL[name]))
         res.append((r["matches"], r["prefixes"], r["extensions"]))
         G.close()
         c.close()
