@@ -12,6 +12,7 @@ signed update batches maintained by delta queries on the same graph.
 Prints one JSON line.  --gpus above 1 is refused: this build targets one GPU.
 """
 import argparse
+import gc
 import json
 import os
 import sys
@@ -391,6 +392,47 @@ def mixed_serving(gj, src, dst, n, scale, nreq, seed, log, max_width=1000, max_u
     return out
 
 
+def lsm_updates(gj, src, dst, n, scale, batches, log):
+    """The delta stream (triangle maintenance, log-uniform batches of 1 to
+    100,000 rows, 10% deletions, seed 1) on two fresh graphs: every batch
+    written as a new version of both indexes, and log-structured (touched rows
+    appended, merged back when the slack is used up).  Count deltas must
+    agree; the last figure is the merge a static reader pays afterwards."""
+    import torch
+    import synth
+    out = {"scale": scale, "batches": batches, "query": "triangle"}
+    deltas = {}
+    for mode in ("rewrite", "lsm"):
+        ctx = gj.Context(0)
+        ctx.set_option("lsm_updates", 1 if mode == "lsm" else 0)
+        G = gj.Graph(ctx, src, dst, n)
+        q = gj.Query(ctx, *TRIANGLE)
+        lat, d = [], []
+        for k, bs, bd, bg in synth.update_stream(scale, 0, 1, batches, 1, 100000):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            r = gj.apply_updates(ctx, G, bs, bd, bg, [q])[0]
+            lat.append((time.perf_counter() - t1) * 1e3)
+            d.append(r["count_delta"])
+        compactions = ctx.get_option("lsm_compactions")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        G.info()  # the first static reader merges appended rows
+        merge_ms = (time.perf_counter() - t1) * 1e3
+        lat = np.array(lat)
+        out[mode] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                     "mean_ms": float(lat.mean()), "compactions_in_stream": int(compactions),
+                     "final_merge_ms": merge_ms}
+        deltas[mode] = d
+        log("update stream (%s, scale %d): p50 %.3f ms, p99 %.3f ms, mean %.3f ms, %d compactions, "
+            "final merge %.2f ms" % (mode, scale, out[mode]["p50_ms"], out[mode]["p99_ms"], out[mode]["mean_ms"],
+                                     compactions, merge_ms))
+        del G, q, ctx
+        gc.collect()
+    assert deltas["rewrite"] == deltas["lsm"], "log-structured count deltas differ"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -416,6 +458,8 @@ def main():
                     help="R-MAT scale of the factorised-count leg (0: skip)")
     ap.add_argument("--tri-scale", type=int, default=18,
                     help="R-MAT scale of the triangle-index leg (0: skip)")
+    ap.add_argument("--lsm-scale", type=int, default=-1,
+                    help="R-MAT scale of the log-structured update leg (-1: --scale, 0: skip)")
     ap.add_argument("--sym-full", action="store_true",
                     help="also count 4-cliques with the plain query over the symmetric graph")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -523,6 +567,16 @@ def main():
     log("delta stream: %d batches, p50 %.2f ms, p99 %.2f ms" % (args.delta_batches, np.percentile(lat, 50),
                                                              np.percentile(lat, 99)))
 
+    lsm = None
+    ls = args.scale if args.lsm_scale < 0 else args.lsm_scale
+    if ls and args.delta_batches:
+        if ls == args.scale:
+            l_src, l_dst = src, dst
+        else:
+            l_src, l_dst = synth.rmat_draws(ls, seed=0)
+        lsm = lsm_updates(gj, l_src, l_dst, 1 << ls, ls, args.delta_batches, log)
+        del l_src, l_dst
+
     cpu = None
     if not args.no_cpu_baseline:
         threads = len(os.sched_getaffinity(0))
@@ -567,6 +621,7 @@ def main():
         "symmetry_breaking": sym,
         "factorisation": fact,
         "triangle_index": tri,
+        "lsm_updates": lsm,
     }
     print(json.dumps(out), flush=True)
 

@@ -93,10 +93,29 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   work: prefixes inside the run are 0, extensions[t] sums
  *                   the smallest set of position t over the prefixes where
  *                   the run starts.  0 (default) enumerates
+ *   "lsm_updates"   gj_apply_updates: 1 keeps the index log-structured
+ *                   (the multi-version index of Sec. 4.3): a batch rewrites
+ *                   only the rows it touches, appended past the current
+ *                   version's edges in the slack of its column arrays and
+ *                   found through a per-vertex map, instead of writing a new
+ *                   version of both indexes.  The rows are merged back into
+ *                   one CSR (a compaction, into another version slot) when
+ *                   the slack is used up, and before any call that reads the
+ *                   graph other than gj_apply_updates: gj_run, gj_run_batch,
+ *                   gj_autotune, gj_graph_csr, gj_graph_info with max_out or
+ *                   max_in, gj_graph_index_triangles, gj_server_create.  A
+ *                   batch whose rows do not fit even a freshly compacted
+ *                   slot is written as a new version of both indexes.
+ *                   Results are the same either way.  0 (default) writes
+ *                   every batch as a new version of both indexes
+ *   "lsm_max_patch" with lsm_updates: at most this many appended entries
+ *                   per direction before a compaction (0, default: the
+ *                   slot's slack, m / 8 + 2^22 entries after a compaction)
  * Returns GJ_EINVAL for an unknown key or out-of-range value. */
 gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
 
-/* Reads an option (keys above, plus "batch_cap" and the counter
+/* Reads an option (keys above, plus "batch_cap", the counter
+ * "lsm_compactions": compactions run on this context, and the counter
  * "batch_fallbacks": gj_run_batch calls that fell back to the depth-first
  * path). */
 gj_status gj_ctx_get_option(gj_ctx* ctx, const char* key, int64_t* value);
@@ -127,12 +146,16 @@ gj_status gj_graph_build(gj_ctx* ctx, const uint32_t* src, const uint32_t* dst,
                          uint64_t m, uint32_t num_vertices, uint32_t flags,
                          gj_graph** out);
 
-/* Sizes of the current version.  Any pointer may be NULL. */
+/* Sizes of the current version.  Any pointer may be NULL.  Asking for
+ * max_out or max_in merges rows appended by log-structured updates first
+ * (option "lsm_updates"; errors as gj_apply_updates, on g's context). */
 gj_status gj_graph_info(const gj_graph* g, uint64_t* edges, uint32_t* vertices,
                         uint32_t* max_out, uint32_t* max_in, uint64_t* version);
 
 /* Device pointers of the current version's index (valid until the next
- * gj_apply_updates or gj_graph_destroy): reverse = 0 forward, 1 reverse.
+ * gj_apply_updates or gj_graph_destroy, or a call that merges rows appended
+ * by log-structured updates): reverse = 0 forward, 1 reverse.  Merges such
+ * rows first (on g's context).
  * row_ptr has vertices+1 entries, col and row have `edges` entries; row[e] is
  * the row (source for forward, destination for reverse) of entry e. */
 gj_status gj_graph_csr(const gj_graph* g, int reverse, const uint32_t** row_ptr,

@@ -309,12 +309,18 @@ class Graph(_Owner):
                                       ctypes.byref(h)), "gj_graph_build")
         self._hd = _Handle(h, _lib.gj_graph_destroy, (ctx._hd,))
 
-    def info(self):
+    def info(self, degrees=True):
+        """Edges, vertices and version; with degrees, the largest out- and
+        in-degree too (which merges rows appended by log-structured updates)."""
         e, n, mo, mi, v = _u64(), _u32(), _u32(), _u32(), _u64()
-        _lib.gj_graph_info(self._h, ctypes.byref(e), ctypes.byref(n), ctypes.byref(mo),
-                           ctypes.byref(mi), ctypes.byref(v))
-        return {"edges": e.value, "vertices": n.value, "max_out": mo.value,
-                "max_in": mi.value, "version": v.value}
+        self.ctx.check(_lib.gj_graph_info(self._h, ctypes.byref(e), ctypes.byref(n),
+                                          ctypes.byref(mo) if degrees else None,
+                                          ctypes.byref(mi) if degrees else None, ctypes.byref(v)),
+                       "gj_graph_info")
+        out = {"edges": e.value, "vertices": n.value, "version": v.value}
+        if degrees:
+            out.update(max_out=mo.value, max_in=mi.value)
+        return out
 
     def index_triangles(self):
         """Builds the triangle relation for ternary atoms (gj_graph_index_triangles);

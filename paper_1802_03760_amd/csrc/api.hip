@@ -184,6 +184,12 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "factorise") {
       GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "factorise must be 0 or 1");
       c->factorise = (int)value;
+    } else if (k == "lsm_updates") {
+      GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "lsm_updates must be 0 or 1");
+      c->lsm_updates = (int)value;
+    } else if (k == "lsm_max_patch") {
+      GJ_CHECK(value >= 0, GJ_EINVAL, "lsm_max_patch must be >= 0");
+      c->lsm_max_patch = (uint64_t)value;
     } else if (k == "batch_cap") {
       GJ_CHECK(value >= 64 && value <= (1ll << 32), GJ_EINVAL, "batch_cap out of range");
       c->batch_cap = (uint64_t)value;
@@ -215,6 +221,9 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "factorise") *value = c->factorise;
     else if (k == "propose_u") *value = c->propose_u;
     else if (k == "batch_heavy") *value = (int64_t)c->batch_heavy;
+    else if (k == "lsm_updates") *value = c->lsm_updates;
+    else if (k == "lsm_max_patch") *value = (int64_t)c->lsm_max_patch;
+    else if (k == "lsm_compactions") *value = (int64_t)c->lsm_compactions;
     else throw Error{GJ_EINVAL, "unknown option " + k};
   });
 }
@@ -263,8 +272,12 @@ gj_status gj_graph_build(gj_ctx* c, const uint32_t* src, const uint32_t* dst, ui
 gj_status gj_graph_info(const gj_graph* g, uint64_t* edges, uint32_t* vertices, uint32_t* max_out,
                         uint32_t* max_in, uint64_t* version) {
   if (!g) return GJ_EINVAL;
+  if (max_out || max_in) {
+    gj_status s = gj::settle(g->ctx, g);
+    if (s != GJ_OK) return s;
+  }
   const gj::Version& v = g->ver[g->cur];
-  if (edges) *edges = v.m;
+  if (edges) *edges = g->lsm.on ? g->lsm.m : v.m;
   if (vertices) *vertices = g->n;
   if (max_out) *max_out = v.max_deg[0];
   if (max_in) *max_in = v.max_deg[1];
@@ -275,6 +288,8 @@ gj_status gj_graph_info(const gj_graph* g, uint64_t* edges, uint32_t* vertices, 
 gj_status gj_graph_csr(const gj_graph* g, int reverse, const uint32_t** row_ptr, const uint32_t** col,
                        const uint32_t** row) {
   if (!g || (reverse != 0 && reverse != 1)) return GJ_EINVAL;
+  gj_status s = gj::settle(g->ctx, g);
+  if (s != GJ_OK) return s;
   const gj::CsrDir& d = g->ver[g->cur].d[reverse];
   if (row_ptr) *row_ptr = d.rp;
   if (col) *col = d.col;
@@ -289,6 +304,7 @@ void gj_graph_destroy(gj_graph* g) {
     (void)hipStreamSynchronize(g->ctx->stream);
   }
   for (auto& v : g->ver) gj::version_free(v);
+  gj::lsm_free(g);
   gj::tri_index_free(g);
   gj::dev_free(g->old_of_new);
   delete g;
@@ -297,6 +313,7 @@ void gj_graph_destroy(gj_graph* g) {
 gj_status gj_graph_index_triangles(gj_ctx* c, gj_graph* g, uint64_t* num_triangles) {
   if (!c || !g) return GJ_EINVAL;
   return guarded(c, [&] {
+    gj::graph_compact(c, g);
     gj::tri_index_build(c, g);
     if (num_triangles) *num_triangles = g->tri.size;
   });
@@ -407,6 +424,7 @@ gj_status gj_run(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint
   gj_status s = guarded(c, [&] {
     GJ_CHECK(mode == GJ_MODE_COUNT || mode == GJ_MODE_ENUMERATE, GJ_EINVAL, "mode must be COUNT or ENUMERATE");
     GJ_CHECK(mode == GJ_MODE_COUNT || out || out_cap_rows == 0, GJ_EINVAL, "null output buffer");
+    gj::graph_compact(c, const_cast<gj_graph*>(g));  // static runs read plain CSR
     gj::run_static(c, g, q, mode, seed_lo, seed_hi, out, out_cap_rows, out_on_device, &st, overflow);
   });
   st.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -622,6 +640,13 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->factorise = src->factorise;
   dst->propose_u = src->propose_u;
   dst->batch_heavy = src->batch_heavy;
+  dst->lsm_updates = src->lsm_updates;
+  dst->lsm_max_patch = src->lsm_max_patch;
+}
+
+gj_status settle(gj_ctx* c, const gj_graph* g) {
+  if (!g->lsm.on) return GJ_OK;
+  return guarded(c, [&] { graph_compact(c, const_cast<gj_graph*>(g)); });
 }
 
 }  // namespace gj
@@ -633,6 +658,7 @@ gj_status gj_run_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_que
   if (!c || !g || (nreq && (!qs || !seed_lo || !seed_hi || !counts))) return GJ_EINVAL;
   auto t0 = std::chrono::steady_clock::now();
   return guarded(c, [&] {
+    gj::graph_compact(c, const_cast<gj_graph*>(g));
     gj::count_batch(c, g, nreq, qs, seed_lo, seed_hi, counts, stats, nullptr);
     double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats)
@@ -644,7 +670,10 @@ gj_status gj_autotune(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_quer
                       const uint64_t* seed_lo, const uint64_t* seed_hi, const char* cache_path,
                       gj_tuning* out) {
   if (!c || !g || !nreq || !qs || !seed_lo || !seed_hi) return GJ_EINVAL;
-  return guarded(c, [&] { gj::autotune(c, g, nreq, qs, seed_lo, seed_hi, cache_path, out); });
+  return guarded(c, [&] {
+    gj::graph_compact(c, const_cast<gj_graph*>(g));
+    gj::autotune(c, g, nreq, qs, seed_lo, seed_hi, cache_path, out);
+  });
 }
 
 gj_status gj_last_delta(gj_ctx* c, uint32_t q, uint32_t* rows, int8_t* signs, uint64_t cap, int on_device,

@@ -154,7 +154,9 @@ __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, 
       uint32_t x[2] = {x0, x1};
       for (int a = 0; a < q.filt.n && keep; ++a) {
         uint32_t key = x[q.filt.key[a]], val = x[q.filt.val[a]];
-        keep = contains_u32(q.filt.adj[a], q.filt.rp[a][key], q.filt.rp[a][key + 1], val);
+        uint32_t lo, hi;
+        row_range(q.filt.rp[a], q.filt.pm[a], key, lo, hi);
+        keep = contains_u32(q.filt.adj[a], lo, hi, val);
       }
       keep = keep && seed_ineq_ok(q.filt.above, q.filt.below, x0, x1);
       fin = q.m == 2;
@@ -213,8 +215,9 @@ __global__ void __launch_bounds__(kBlock) k_bt_count_min(const BReq* __restrict_
 #pragma unroll
         for (int a = 0; a < kMaxBind; ++a) {
           if (a < d.k) {
-            uint32_t v = F[(uint64_t)d.col[a] * cap + p];
-            uint32_t c = d.rp[a][v + 1] - d.rp[a][v];
+            uint32_t v = F[(uint64_t)d.col[a] * cap + p], lo, hi;
+            row_range(d.rp[a], d.pm[a], v, lo, hi);
+            uint32_t c = hi - lo;
             if (c < best) {
               best = c;
               bi = a;
@@ -281,23 +284,27 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
         int am = mini[p];
         const uint32_t* rp_m = d.rp[0];
         const uint32_t* adj_m = d.adj[0];
+        const uint64_t* pm_m = d.pm[0];
         int col_m = d.col[0];
 #pragma unroll
         for (int a = 1; a < kMaxBind; ++a) {
           if (a == am) {
             rp_m = d.rp[a];
             adj_m = d.adj[a];
+            pm_m = d.pm[a];
             col_m = d.col[a];
           }
         }
-        uint32_t v = F[(uint64_t)col_m * cap + p];
-        e = adj_m[rp_m[v] + k];
+        uint32_t v = F[(uint64_t)col_m * cap + p], vlo, vhi;
+        row_range(rp_m, pm_m, v, vlo, vhi);
+        e = adj_m[vlo + k];
         keep = ineq_ok(F, cap, p, d.above, d.below, e);
 #pragma unroll
         for (int a = 0; a < kMaxBind; ++a) {
           if (a < d.k && a != am && keep) {
-            uint32_t u = F[(uint64_t)d.col[a] * cap + p];
-            keep = member(d.adj[a], d.rp[a][u], d.rp[a][u + 1], e, lin);
+            uint32_t u = F[(uint64_t)d.col[a] * cap + p], lo, hi;
+            row_range(d.rp[a], d.pm[a], u, lo, hi);
+            keep = member(d.adj[a], lo, hi, e, lin);
           }
         }
         fin = mc == (uint32_t)(j + 1);

@@ -13,6 +13,7 @@
 #include "batch.h"
 #include "engine.h"
 #include "gj_internal.h"
+#include "lsm.h"
 #include "owner.h"
 #include "prim.h"
 
@@ -36,7 +37,7 @@ __global__ void k_batch_keys(const uint32_t* __restrict__ src, const uint32_t* _
 // graph.  counters: [0] no-op inserts, [1] no-op deletes, [2] conflicts.
 __global__ void k_batch_classify(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ ins, uint64_t b,
                                  const uint32_t* __restrict__ rp, const uint32_t* __restrict__ col,
-                                 uint32_t* __restrict__ flags, int8_t* __restrict__ dsign,
+                                 const uint64_t* __restrict__ pm, uint32_t* __restrict__ flags, int8_t* __restrict__ dsign,
                                  unsigned long long* __restrict__ counters) {
   uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b; i += gs) {
@@ -56,7 +57,9 @@ __global__ void k_batch_classify(const uint64_t* __restrict__ keys, const uint32
       atomicAdd(counters + 2, 1ull);
       continue;
     }
-    bool present = contains_u32(col, rp[s], rp[s + 1], d);
+    uint32_t lo, hi;
+    row_range(rp, pm, s, lo, hi);
+    bool present = contains_u32(col, lo, hi, d);
     if (any_ins && present) {
       atomicAdd(counters + 0, 1ull);
       continue;
@@ -265,10 +268,12 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   overflow = false;
   uint32_t n = g->n;
   int bits = bits_for(n);
-  if (target < 0) target = g->cur < 2 ? 1 - g->cur : 0;
-  GJ_CHECK(target < kMaxVersions && target != g->cur, GJ_EINVAL, "update target is the current version");
-  Version& ov = g->ver[g->cur];
-  Version& nv = g->ver[target];
+  // log-structured updates for the plain entry point only: a caller that
+  // names the slot (the server) keeps every version a plain CSR
+  const bool lsm = c->lsm_updates && target < 0;
+  if (!lsm) graph_compact(c, g);  // the rewrite below reads the current version as one CSR
+  GJ_CHECK(target < 0 || (target < kMaxVersions && target != g->cur), GJ_EINVAL,
+           "update target is the current version");
   c->last_delta.assign(nq, gj_ctx::LastDelta{});
   for (uint32_t k = 0; k < nq; ++k) {
     if (count_delta) count_delta[k] = 0;
@@ -307,7 +312,11 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   uint32_t* flags = (uint32_t*)ws_get(c, "ub_flags", (b + 1) * sizeof(uint32_t));
   int8_t* dsign = (int8_t*)ws_get(c, "ub_dsign", b + 1);
   uint64_t* off = (uint64_t*)ws_get(c, "ub_off", (b + 1) * sizeof(uint64_t));
-  if (b) k_batch_classify<<<gb, kBlock, 0, c->stream>>>(keys, vals, b, ov.d[0].rp, ov.d[0].col, flags, dsign, cnt);
+  {
+    const Version& cv = g->ver[g->cur];
+    const uint64_t* pm = g->lsm.on ? g->lsm.map[g->lsm.cur_map][0] : nullptr;
+    if (b) k_batch_classify<<<gb, kBlock, 0, c->stream>>>(keys, vals, b, cv.d[0].rp, cv.d[0].col, pm, flags, dsign, cnt);
+  }
   scan_u32_to_u64(c, flags, off, b);
   unsigned long long hc[3];
   read_bytes(c, hc, cnt, sizeof(hc));
@@ -335,23 +344,39 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   uint32_t* rd = (uint32_t*)ws_get(c, "de_rdst", (k + 1) * sizeof(uint32_t));
   int8_t* rg = (int8_t*)ws_get(c, "de_rsign", k + 1);
   k_unswap<<<grid_for(k, kBlock, 1u << 16), kBlock, 0, c->stream>>>(sw, si, eg, k, rd, rs, rg);
-  // ---- next version of both indexes
-  uint64_t ins_total = 0;
-  {
+  // ---- next version: the touched rows appended (log-structured), else both
+  // indexes rewritten into another slot
+  Version lsm_old, lsm_new;
+  LsmCommit commit;
+  const bool patched =
+      lsm && lsm_update(c, g, {es, rd}, {ed, rs}, {eg, rg}, k, lsm_old, lsm_new, commit);
+  struct AbortGuard {  // an uncommitted log-structured update leaves the maps as they were
+    gj_ctx* c;
+    gj_graph* g;
+    bool armed;
+    ~AbortGuard() {
+      if (armed) lsm_abort(c, g);
+    }
+  } guard{c, g, patched};
+  if (!patched) {
+    if (target < 0) target = g->cur < 2 ? 1 - g->cur : 0;
+    Version& ov = g->ver[g->cur];
+    Version& nv = g->ver[target];
     // upper bound of the new edge count: old + all of dE, with slack so that a
     // growing graph does not reallocate the spare version on every batch
     uint64_t need = ov.m + k;
     if (need > nv.cap) version_alloc(nv, n, need + need / 16 + (1u << 20));
+    uint32_t* mx = (uint32_t*)ws_get(c, "maxdeg", 2 * sizeof(uint32_t));
+    GJ_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(uint32_t), c->stream));
+    update_dir(c, n, ov.d[0], ov.m, es, ed, eg, k, nv.d[0], "f", mx);
+    update_dir(c, n, ov.d[1], ov.m, rd, rs, rg, k, nv.d[1], "r", mx + 1);
+    uint32_t newm = 0;
+    read_bytes(c, &newm, nv.d[0].rp + n, sizeof(newm));
+    nv.m = newm;
+    version_finish(c, nv, n, true);  // row pointers and largest degrees come from the update
   }
-  uint32_t* mx = (uint32_t*)ws_get(c, "maxdeg", 2 * sizeof(uint32_t));
-  GJ_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(uint32_t), c->stream));
-  update_dir(c, n, ov.d[0], ov.m, es, ed, eg, k, nv.d[0], "f", mx);
-  update_dir(c, n, ov.d[1], ov.m, rd, rs, rg, k, nv.d[1], "r", mx + 1);
-  uint32_t newm = 0;
-  read_bytes(c, &newm, nv.d[0].rp + n, sizeof(newm));
-  nv.m = newm;
-  (void)ins_total;
-  version_finish(c, nv, n, true);  // row pointers and largest degrees come from the update
+  const Version& ov = patched ? lsm_old : g->ver[g->cur];
+  const Version& nv = patched ? lsm_new : g->ver[target];
   // ---- delta queries
   std::vector<char> done(nq, 0);
   // Count-only queries whose every dQ_i extends the seed edge by one attribute
@@ -359,7 +384,7 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   // runs the owner-grouped kernel over the signed seeds, grouped by source
   // (the forward delta rows) and by destination (the reverse ones), for
   // batches with enough changes to pay for its planning over every vertex.
-  if (c->strategy != 1 && k >= c->delta_owner_min) {
+  if (c->strategy != 1 && k >= c->delta_owner_min && !patched) {
     const uint32_t* drp_f = (const uint32_t*)ws_get(c, "up_drpf", ((uint64_t)n + 1) * sizeof(uint32_t));
     const uint32_t* drp_r = (const uint32_t*)ws_get(c, "up_drpr", ((uint64_t)n + 1) * sizeof(uint32_t));
     for (uint32_t qi = 0; qi < nq; ++qi) {
@@ -557,7 +582,12 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
       stats[qi] = acc;
     }
   }
-  g->cur = target;
+  if (patched) {
+    guard.armed = false;
+    lsm_commit(g, commit);
+  } else {
+    g->cur = target;
+  }
   g->version += 1;
 }
 

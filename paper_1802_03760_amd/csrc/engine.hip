@@ -103,6 +103,7 @@ StageDesc stage_desc(const PlanH& P, const Views& V, int j) {
     const Version& v = V.of(b.atom);
     d.rp[a] = v.d[b.dir].rp;
     d.adj[a] = v.d[b.dir].col;
+    d.pm[a] = v.pmap[b.dir];
   }
   if (d.ntri) {
     GJ_CHECK(V.tri && V.tri->rp, GJ_EINVAL, "ternary atom without a triangle index");
@@ -115,6 +116,7 @@ StageDesc stage_desc(const PlanH& P, const Views& V, int j) {
     d.col[a] = 0;
     d.rp[a] = d.rp[0];
     d.adj[a] = d.adj[0];
+    d.pm[a] = d.pm[0];
   }
   return d;
 }
@@ -131,6 +133,7 @@ SeedFilter seed_filter(const PlanH& P, const Views& V) {
     f.val[a] = P.filters[a].val;
     f.rp[a] = v.d[0].rp;
     f.adj[a] = v.d[0].col;
+    f.pm[a] = v.pmap[0];
   }
   return f;
 }

@@ -56,6 +56,9 @@ struct StageDesc {
   const uint32_t* tcol;
   const uint32_t* erp;
   const uint32_t* ecol;
+  // rows rewritten by log-structured updates (row_range in prim.h); null:
+  // every row of the atom's version is rp[v] .. rp[v + 1]
+  const uint64_t* pm[kMaxBind];
 };
 
 // Membership filters of the seed pairs (atoms over the first two attributes
@@ -67,6 +70,7 @@ struct SeedFilter {
   int val[kMaxBind];
   const uint32_t* rp[kMaxBind];
   const uint32_t* adj[kMaxBind];
+  const uint64_t* pm[kMaxBind];
 };
 
 // Column permutation for final rows: value of prefix column c goes to
@@ -92,6 +96,27 @@ struct Version {
   CsrDir d[2];  // 0 forward, 1 reverse
   uint64_t m = 0, cap = 0;
   uint32_t max_deg[2] = {0, 0};
+  // Views written by a log-structured update only (never a graph's slot):
+  // per direction and vertex, the row as arena offset | length << 32 when the
+  // update path has rewritten it into the tail of col, ~0 when it is still
+  // rp[v] .. rp[v + 1]; null when no row is rewritten.
+  const uint64_t* pmap[2] = {nullptr, nullptr};
+};
+
+// Log-structured updates (the multi-version index of Sec. 4.3): between two
+// compactions the current version is the compacted slot ver[cur] plus the
+// rows an update has rewritten, appended to the slack of that slot's column
+// arrays past m and found through one of two per-vertex maps (one for the
+// current version, the other written for the next, so that the old and the
+// new version of a batch are both readable while its delta queries run).
+struct LsmState {
+  bool on = false;      // some row is rewritten: the current version is ver[cur] + map[cur_map]
+  int cur_map = 0;
+  uint64_t* map[2][2] = {};  // [buffer][direction], n entries each, ~0 = row in the compacted slot
+  uint32_t* keys[2] = {};    // [direction]: vertices with a map entry since the last compaction
+  uint64_t nkeys[2] = {0, 0};
+  uint64_t used[2] = {0, 0};  // arena entries appended per direction
+  uint64_t m = 0;             // edges of the current version
 };
 
 // The triangle relation of one version, keyed by forward edge position.
@@ -137,6 +162,9 @@ struct gj_ctx {
   int factorise = 0;  // gj_run counts: trailing independent attributes as products
   uint64_t batch_heavy = 1ull << 24;  // gj_run_batch: estimated work from which a request runs depth-first
   int propose_u = 4;  // candidates per lane tested in lockstep by the generic propose kernel (1, 2, 4)
+  int lsm_updates = 0;  // gj_apply_updates: append rewritten rows instead of rewriting both indexes
+  uint64_t lsm_max_patch = 0;  // arena entries per direction before a compaction (0: the slot's slack)
+  uint64_t lsm_compactions = 0;  // compactions run on this context
 };
 
 // Resident versions of a graph: ver[cur] is current; an update reads it and
@@ -153,6 +181,7 @@ struct gj_graph {
   gj::Version ver[kMaxVersions];
   int cur = 0;
   uint64_t version = 0;
+  gj::LsmState lsm;
 };
 
 struct gj_query {
@@ -220,6 +249,13 @@ void graph_build_sym(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32
                      bool degree_order, bool undirected);
 void version_alloc(Version& v, uint32_t n, uint64_t cap);
 void version_free(Version& v);
+// Log-structured updates: merge the rewritten rows into a compacted slot
+// (no-op when none are); release the maps.
+void graph_compact(gj_ctx* c, gj_graph* g);
+void lsm_free(gj_graph* g);
+// graph_compact for readers that need the current version as one plain CSR
+// (the relation is unchanged); errors as a status
+gj_status settle(gj_ctx* c, const gj_graph* g);
 
 // stage.hip
 void launch_seed(gj_ctx* c, const uint32_t* x0, const uint32_t* x1, const int8_t* w, uint64_t cnt,

@@ -1,0 +1,398 @@
+// Log-structured updates: the multi-version index of Sec. 4.3 on one GPU.
+//
+// The paper's index holds a compacted index of old data, per-vertex
+// log-structured lists of committed changes that can be merged one vertex at
+// a time, and the uncommitted changes in order.  Here the compacted index is a
+// version slot (both CSR directions).  An update batch dE (already sorted and
+// classified against the current version) rewrites only the rows it touches:
+// each is merged with its run of dE and appended to the slack of the same
+// column array past the slot's m, and a per-vertex map records where the row
+// now lives.  The maps are double-buffered: the one of the current version
+// stays untouched while the one of the next version is written, so the old
+// and the new version of the batch are both readable while its delta queries
+// run (atoms before i read the new one, atoms after i the old one).  An
+// update thus writes the touched rows and the map entries of the rows
+// rewritten before it, not both indexes.  When the slack is used up, or when
+// a reader needs a plain CSR, every row is merged into another slot (a
+// compaction), which becomes current.
+#include <algorithm>
+#include <cstring>
+
+#include "gj_internal.h"
+#include "lsm.h"
+#include "prim.h"
+
+namespace gj {
+
+// ---------------------------------------------------------------- kernels
+__global__ void k_lsm_heads(const uint32_t* __restrict__ r, const int8_t* __restrict__ g, uint64_t k,
+                            uint32_t* __restrict__ head, uint32_t* __restrict__ insf) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gs) {
+    head[i] = (i == 0 || r[i] != r[i - 1]) ? 1u : 0u;
+    insf[i] = g[i] > 0 ? 1u : 0u;
+  }
+}
+
+// Run t of dE (one touched vertex): its vertex and first entry; dlo[nt] = k.
+__global__ void k_lsm_runs(const uint32_t* __restrict__ r, uint64_t k, const uint32_t* __restrict__ head,
+                           const uint64_t* __restrict__ hscan, uint32_t* __restrict__ tv, uint32_t* __restrict__ dlo) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gs) {
+    if (i == 0) dlo[hscan[k]] = (uint32_t)k;
+    if (!head[i]) continue;
+    uint64_t t = hscan[i];
+    tv[t] = r[i];
+    dlo[t] = (uint32_t)i;
+  }
+}
+
+// Per run t: the vertex's row in the current version (olo, olen), its length
+// after the batch (every delete of dE removes a present entry, every insert
+// adds an absent one), and whether the vertex has no rewritten row yet.
+__global__ void k_lsm_sizes(const uint32_t* __restrict__ tv, const uint32_t* __restrict__ dlo, uint64_t nt,
+                            const uint64_t* __restrict__ ins_scan, const uint32_t* __restrict__ rp,
+                            const uint64_t* __restrict__ pm, uint32_t* __restrict__ olo,
+                            uint32_t* __restrict__ olen, uint32_t* __restrict__ nlen, uint32_t* __restrict__ fresh) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gs) {
+    uint32_t v = tv[t], a = dlo[t], b = dlo[t + 1];
+    uint32_t ins = (uint32_t)(ins_scan[b] - ins_scan[a]);
+    uint32_t del = (b - a) - ins;
+    uint32_t lo, hi;
+    row_range(rp, pm, v, lo, hi);
+    olo[t] = lo;
+    olen[t] = hi - lo;
+    nlen[t] = hi - lo + ins - del;
+    fresh[t] = (!pm || pm[v] == ~0ull) ? 1u : 0u;
+  }
+}
+
+// Entry i of the concatenated old rows of the touched vertices, to its place
+// in the rewritten row (deleted entries dropped).  Reads and writes share col:
+// old rows lie below the append point, rewritten ones above it.
+__global__ void k_lsm_move(const uint64_t* __restrict__ ooff, uint64_t nt, uint64_t tot,
+                           const uint32_t* __restrict__ olo, const uint32_t* __restrict__ dlo,
+                           const uint32_t* __restrict__ dx, const uint64_t* __restrict__ ins_scan,
+                           const uint64_t* __restrict__ noff, uint64_t abase, uint32_t* col) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += gs) {
+    uint64_t t = find_segment(ooff, 0, nt, i);
+    uint32_t j = (uint32_t)(i - ooff[t]);
+    uint32_t x = col[olo[t] + j];
+    uint32_t a = dlo[t], b = dlo[t + 1];
+    uint32_t p = lower_bound_u32(dx, a, b, x);
+    if (p < b && dx[p] == x) continue;  // deleted
+    uint32_t ins_before = (uint32_t)(ins_scan[p] - ins_scan[a]);
+    uint32_t del_before = (p - a) - ins_before;
+    col[abase + noff[t] + j + ins_before - del_before] = x;
+  }
+}
+
+// Inserted entries of dE to their places in the rewritten rows: every entry
+// of the run before i is below x, and every delete among them an old entry.
+__global__ void k_lsm_ins(const uint32_t* __restrict__ dx, const int8_t* __restrict__ dg, uint64_t k,
+                          const uint64_t* __restrict__ hscan, const uint32_t* __restrict__ dlo,
+                          const uint32_t* __restrict__ olo, const uint32_t* __restrict__ olen,
+                          const uint64_t* __restrict__ ins_scan, const uint64_t* __restrict__ noff, uint64_t abase,
+                          uint32_t* col) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gs) {
+    if (dg[i] < 0) continue;
+    uint64_t t = hscan[i + 1] - 1;
+    uint32_t a = dlo[t], x = dx[i];
+    uint32_t less = lower_bound_u32(col, olo[t], olo[t] + olen[t], x) - olo[t];
+    uint32_t ins_before = (uint32_t)(ins_scan[i] - ins_scan[a]);
+    uint32_t del_before = ((uint32_t)i - a) - ins_before;
+    col[abase + noff[t] + less - del_before + ins_before] = x;
+  }
+}
+
+__global__ void k_lsm_copy_map(const uint32_t* __restrict__ keys, uint64_t nkeys, const uint64_t* __restrict__ from,
+                               uint64_t* __restrict__ to) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nkeys; i += gs) {
+    uint32_t v = keys[i];
+    to[v] = from[v];
+  }
+}
+
+__global__ void k_lsm_set_map(const uint32_t* __restrict__ tv, uint64_t nt, const uint64_t* __restrict__ noff,
+                              const uint32_t* __restrict__ nlen, uint64_t abase, const uint32_t* __restrict__ fresh,
+                              const uint64_t* __restrict__ fscan, uint64_t nkeys, uint64_t* __restrict__ to,
+                              uint32_t* __restrict__ keys) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; t < nt; t += gs) {
+    uint32_t v = tv[t];
+    to[v] = (abase + noff[t]) | ((uint64_t)nlen[t] << 32);
+    if (fresh[t]) keys[nkeys + fscan[t]] = v;
+  }
+}
+
+// ---- compaction
+__global__ void k_view_deg(const uint32_t* __restrict__ rp, const uint64_t* __restrict__ pm, uint32_t n,
+                           uint32_t* __restrict__ deg) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gs) {
+    uint32_t lo, hi;
+    row_range(rp, pm, (uint32_t)v, lo, hi);
+    deg[v] = hi - lo;
+  }
+}
+
+// entries of the compacted slot whose row was not rewritten
+__global__ void k_copy_base(const uint32_t* __restrict__ rp, const uint32_t* __restrict__ col,
+                            const uint32_t* __restrict__ row, uint64_t m, const uint64_t* __restrict__ pm,
+                            const uint32_t* __restrict__ nrp, uint32_t* __restrict__ ncol,
+                            uint32_t* __restrict__ nrow) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += gs) {
+    uint32_t r = row[e];
+    if (pm[r] != ~0ull) continue;
+    uint64_t pos = (uint64_t)nrp[r] + (e - rp[r]);
+    ncol[pos] = col[e];
+    nrow[pos] = r;
+  }
+}
+
+// rewritten rows, a wave per row
+__global__ void k_copy_rows(const uint32_t* __restrict__ keys, uint64_t nkeys, const uint64_t* __restrict__ pm,
+                            const uint32_t* __restrict__ col, const uint32_t* __restrict__ nrp,
+                            uint32_t* __restrict__ ncol, uint32_t* __restrict__ nrow) {
+  const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nkeys; w += waves) {
+    uint32_t v = keys[w];
+    uint64_t e = pm[v];
+    uint32_t lo = (uint32_t)e, len = (uint32_t)(e >> 32);
+    uint64_t dst = nrp[v];
+    for (uint32_t j = lane_id(); j < len; j += 64) {
+      ncol[dst + j] = col[lo + j];
+      nrow[dst + j] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- host
+static void lsm_alloc(gj_ctx* c, gj_graph* g) {
+  LsmState& L = g->lsm;
+  if (L.map[0][0]) return;
+  uint64_t bytes = (uint64_t)g->n * sizeof(uint64_t);
+  for (int b = 0; b < 2; ++b)
+    for (int d = 0; d < 2; ++d) {
+      L.map[b][d] = (uint64_t*)dev_alloc(bytes);
+      GJ_HIP(hipMemsetAsync(L.map[b][d], 0xFF, bytes, c->stream));
+    }
+  for (int d = 0; d < 2; ++d) L.keys[d] = (uint32_t*)dev_alloc((uint64_t)g->n * sizeof(uint32_t));
+}
+
+void lsm_free(gj_graph* g) {
+  LsmState& L = g->lsm;
+  for (int b = 0; b < 2; ++b)
+    for (int d = 0; d < 2; ++d) dev_free(L.map[b][d]);
+  for (int d = 0; d < 2; ++d) dev_free(L.keys[d]);
+  L = LsmState{};
+}
+
+static void lsm_reset_maps(gj_ctx* c, gj_graph* g) {
+  LsmState& L = g->lsm;
+  uint64_t bytes = (uint64_t)g->n * sizeof(uint64_t);
+  for (int b = 0; b < 2; ++b)
+    for (int d = 0; d < 2; ++d)
+      if (L.map[b][d]) GJ_HIP(hipMemsetAsync(L.map[b][d], 0xFF, bytes, c->stream));
+  L.on = false;
+  L.cur_map = 0;
+  L.nkeys[0] = L.nkeys[1] = 0;
+  L.used[0] = L.used[1] = 0;
+}
+
+void graph_compact(gj_ctx* c, gj_graph* g) {
+  LsmState& L = g->lsm;
+  if (!L.on) return;
+  uint32_t n = g->n;
+  int s = g->cur < 2 ? 1 - g->cur : 0;
+  Version& ov = g->ver[g->cur];
+  Version& nv = g->ver[s];
+  uint64_t m = L.m;
+  // room for the rewritten rows of the updates that follow
+  uint64_t need = m + m / 8 + (1ull << 22);
+  if (need > nv.cap) version_alloc(nv, n, need);
+  uint32_t* deg = (uint32_t*)ws_get(c, "lsm_deg", ((uint64_t)n + 1) * sizeof(uint32_t));
+  for (int d = 0; d < 2; ++d) {
+    const uint64_t* pm = L.map[L.cur_map][d];
+    k_view_deg<<<grid_for(n, kBlock, 1u << 16), kBlock, 0, c->stream>>>(ov.d[d].rp, pm, n, deg);
+    scan_u32(c, deg, nv.d[d].rp, n);
+    if (ov.m)
+      k_copy_base<<<grid_for(ov.m, kBlock, 1u << 16), kBlock, 0, c->stream>>>(ov.d[d].rp, ov.d[d].col, ov.d[d].row,
+                                                                             ov.m, pm, nv.d[d].rp, nv.d[d].col,
+                                                                             nv.d[d].row);
+    if (L.nkeys[d])
+      k_copy_rows<<<grid_for(L.nkeys[d] * 64, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+          L.keys[d], L.nkeys[d], pm, ov.d[d].col, nv.d[d].rp, nv.d[d].col, nv.d[d].row);
+    GJ_HIP(hipGetLastError());
+  }
+  nv.m = m;
+  version_finish(c, nv, n, false);
+  g->cur = s;
+  lsm_reset_maps(c, g);
+  ++c->lsm_compactions;
+  GJ_HIP(hipStreamSynchronize(c->stream));
+}
+
+namespace {
+
+// Scratch and sizes of one direction of one update.
+struct DirPlan {
+  const uint32_t* r;
+  const uint32_t* x;
+  const int8_t* g;
+  uint64_t k = 0;
+  uint32_t *head, *insf, *tv, *dlo, *olo, *olen, *nlen, *fresh;
+  uint64_t *hscan, *ins_scan, *noff, *ooff, *fscan;
+  uint64_t nt = 0, tot_new = 0, tot_old = 0, nfresh = 0, ins = 0;
+};
+
+void measure(gj_ctx* c, gj_graph* g, int d, DirPlan& P) {
+  const std::string tag = d ? "r" : "f";
+  uint64_t k = P.k;
+  auto u32 = [&](const char* name, uint64_t cnt) {
+    return (uint32_t*)ws_get(c, std::string("lsm_") + name + tag, (cnt + 1) * sizeof(uint32_t));
+  };
+  auto u64 = [&](const char* name, uint64_t cnt) {
+    return (uint64_t*)ws_get(c, std::string("lsm_") + name + tag, (cnt + 1) * sizeof(uint64_t));
+  };
+  P.head = u32("head", k);
+  P.insf = u32("insf", k);
+  P.hscan = u64("hscan", k);
+  P.ins_scan = u64("inss", k);
+  unsigned gk = grid_for(k, kBlock, 1u << 16);
+  k_lsm_heads<<<gk, kBlock, 0, c->stream>>>(P.r, P.g, k, P.head, P.insf);
+  scan_u32_to_u64(c, P.head, P.hscan, k);
+  scan_u32_to_u64(c, P.insf, P.ins_scan, k);
+  uint64_t h[2];
+  read_bytes(c, &h[0], P.hscan + k, sizeof(uint64_t));
+  read_bytes(c, &h[1], P.ins_scan + k, sizeof(uint64_t));
+  P.nt = h[0];
+  P.ins = h[1];
+  uint64_t nt = P.nt;
+  P.tv = u32("tv", nt);
+  P.dlo = u32("dlo", nt + 1);
+  P.olo = u32("olo", nt);
+  P.olen = u32("olen", nt);
+  P.nlen = u32("nlen", nt);
+  P.fresh = u32("fresh", nt);
+  P.noff = u64("noff", nt);
+  P.ooff = u64("ooff", nt);
+  P.fscan = u64("fscan", nt);
+  k_lsm_runs<<<gk, kBlock, 0, c->stream>>>(P.r, k, P.head, P.hscan, P.tv, P.dlo);
+  const LsmState& L = g->lsm;
+  const uint64_t* pm = L.on ? L.map[L.cur_map][d] : nullptr;
+  k_lsm_sizes<<<grid_for(nt, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+      P.tv, P.dlo, nt, P.ins_scan, g->ver[g->cur].d[d].rp, pm, P.olo, P.olen, P.nlen, P.fresh);
+  GJ_HIP(hipGetLastError());
+  scan_u32_to_u64(c, P.nlen, P.noff, nt);
+  scan_u32_to_u64(c, P.olen, P.ooff, nt);
+  scan_u32_to_u64(c, P.fresh, P.fscan, nt);
+  uint64_t t[3];
+  read_bytes(c, &t[0], P.noff + nt, sizeof(uint64_t));
+  read_bytes(c, &t[1], P.ooff + nt, sizeof(uint64_t));
+  read_bytes(c, &t[2], P.fscan + nt, sizeof(uint64_t));
+  P.tot_new = t[0];
+  P.tot_old = t[1];
+  P.nfresh = t[2];
+}
+
+// whether the rewritten rows of this update fit the current slot's slack
+bool fits(const gj_ctx* c, const gj_graph* g, const DirPlan (&P)[2]) {
+  const Version& v = g->ver[g->cur];
+  uint64_t room = v.cap - v.m;
+  if (c->lsm_max_patch) room = std::min(room, c->lsm_max_patch);
+  for (int d = 0; d < 2; ++d) {
+    uint64_t end = g->lsm.used[d] + P[d].tot_new;
+    if (end > room || v.m + end > 0xFFFFFFFFull) return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+bool lsm_update(gj_ctx* c, gj_graph* g, const uint32_t* const (&r)[2], const uint32_t* const (&x)[2],
+                const int8_t* const (&sg)[2], uint64_t k, Version& oldv, Version& newv, LsmCommit& commit) {
+  lsm_alloc(c, g);
+  DirPlan P[2];
+  for (int d = 0; d < 2; ++d) {
+    P[d].r = r[d];
+    P[d].x = x[d];
+    P[d].g = sg[d];
+    P[d].k = k;
+  }
+  for (int attempt = 0;; ++attempt) {
+    for (int d = 0; d < 2; ++d) measure(c, g, d, P[d]);
+    if (fits(c, g, P)) break;
+    // the compacted slot that follows has room for m / 8 + 2^22 rows entries
+    // per direction; a batch whose rows exceed even that is rewritten whole
+    if (!g->lsm.on || attempt > 0) return false;
+    graph_compact(c, g);
+  }
+  LsmState& L = g->lsm;
+  Version& base = g->ver[g->cur];
+  const int nb = 1 - L.cur_map;
+  for (int d = 0; d < 2; ++d) {
+    DirPlan& p = P[d];
+    uint64_t abase = base.m + L.used[d];
+    if (p.tot_old)
+      k_lsm_move<<<grid_for(p.tot_old, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+          p.ooff, p.nt, p.tot_old, p.olo, p.dlo, p.x, p.ins_scan, p.noff, abase, base.d[d].col);
+    k_lsm_ins<<<grid_for(k, kBlock, 1u << 16), kBlock, 0, c->stream>>>(p.x, p.g, k, p.hscan, p.dlo, p.olo, p.olen,
+                                                                      p.ins_scan, p.noff, abase, base.d[d].col);
+    if (L.nkeys[d])
+      k_lsm_copy_map<<<grid_for(L.nkeys[d], kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+          L.keys[d], L.nkeys[d], L.map[L.cur_map][d], L.map[nb][d]);
+    k_lsm_set_map<<<grid_for(p.nt, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+        p.tv, p.nt, p.noff, p.nlen, abase, p.fresh, p.fscan, L.nkeys[d], L.map[nb][d], L.keys[d]);
+    GJ_HIP(hipGetLastError());
+    commit.used[d] = L.used[d] + p.tot_new;
+    commit.nkeys[d] = L.nkeys[d] + p.nfresh;
+  }
+  // every insert and delete of dE appears once per direction
+  uint64_t ins = P[0].ins, del = k - P[0].ins;
+  const uint64_t m0 = L.on ? L.m : base.m;
+  commit.m = m0 + ins - del;
+  oldv = base;
+  newv = base;
+  for (int d = 0; d < 2; ++d) {
+    oldv.pmap[d] = L.on ? L.map[L.cur_map][d] : nullptr;
+    newv.pmap[d] = L.map[nb][d];
+  }
+  oldv.m = m0;
+  newv.m = commit.m;
+  return true;
+}
+
+void lsm_commit(gj_graph* g, const LsmCommit& commit) {
+  LsmState& L = g->lsm;
+  for (int d = 0; d < 2; ++d) {
+    L.used[d] = commit.used[d];
+    L.nkeys[d] = commit.nkeys[d];
+  }
+  L.m = commit.m;
+  L.cur_map = 1 - L.cur_map;
+  L.on = true;
+}
+
+void lsm_abort(gj_ctx* c, gj_graph* g) {
+  // the next version's map may hold entries of vertices outside the key list:
+  // make it equal to the current one again
+  LsmState& L = g->lsm;
+  if (!L.map[0][0]) return;
+  const int nb = 1 - L.cur_map;
+  uint64_t bytes = (uint64_t)g->n * sizeof(uint64_t);
+  for (int d = 0; d < 2; ++d) {
+    (void)hipMemsetAsync(L.map[nb][d], 0xFF, bytes, c->stream);
+    if (L.on && L.nkeys[d])
+      k_lsm_copy_map<<<grid_for(L.nkeys[d], kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+          L.keys[d], L.nkeys[d], L.map[L.cur_map][d], L.map[nb][d]);
+  }
+  (void)hipStreamSynchronize(c->stream);
+}
+
+}  // namespace gj

@@ -142,6 +142,24 @@ __device__ __forceinline__ bool contains_u32(const uint32_t* __restrict__ a, uin
   return i < hi && a[i] == x;
 }
 
+// Row v of one direction of a version: col[lo, hi).  A log-structured update
+// rewrites a row into the tail of the same column array and records it in
+// the version's per-vertex map pm (offset | length << 32; ~0 for a row still
+// at rp[v] .. rp[v + 1]); pm is null when no row is rewritten.
+__device__ __forceinline__ void row_range(const uint32_t* __restrict__ rp, const uint64_t* __restrict__ pm,
+                                          uint32_t v, uint32_t& lo, uint32_t& hi) {
+  if (pm) {
+    uint64_t e = pm[v];
+    if (e != ~0ull) {
+      lo = (uint32_t)e;
+      hi = lo + (uint32_t)(e >> 32);
+      return;
+    }
+  }
+  lo = rp[v];
+  hi = rp[v + 1];
+}
+
 // p in [lo, hi) with off[p] <= g < off[p+1]; requires off[lo] <= g < off[hi].
 __device__ __forceinline__ uint64_t find_segment(const uint64_t* __restrict__ off, uint64_t lo,
                                                  uint64_t hi, uint64_t g) {

@@ -590,6 +590,12 @@ extern "C" {
 gj_status gj_server_create(gj_ctx* ctx, gj_graph* g, uint32_t max_batch, uint64_t mem_budget_bytes,
                            gj_server** out) {
   if (!ctx || !g || !out || max_batch == 0) return GJ_EINVAL;
+  if (g->lsm.on) {
+    // the server rotates plain version slots: merge rows appended by
+    // log-structured updates first
+    gj_status cs = gj::settle(ctx, g);
+    if (cs != GJ_OK) return cs;
+  }
   gj_server* s = new (std::nothrow) gj_server();
   if (!s) return GJ_ENOMEM;
   s->ctx = ctx;

@@ -30,7 +30,9 @@ __global__ void k_seed_flags(const uint32_t* __restrict__ x0, const uint32_t* __
       if (a < f.n && ok) {
         uint32_t key = f.key[a] ? x[1] : x[0];
         uint32_t val = f.val[a] ? x[1] : x[0];
-        ok = contains_u32(f.adj[a], f.rp[a][key], f.rp[a][key + 1], val);
+        uint32_t lo, hi;
+        row_range(f.rp[a], f.pm[a], key, lo, hi);
+        ok = contains_u32(f.adj[a], lo, hi, val);
       }
     }
     flags[i] = (ok && seed_ineq_ok(f.above, f.below, x[0], x[1])) ? 1u : 0u;
@@ -83,8 +85,9 @@ __global__ void k_count_min(const uint32_t* __restrict__ F, uint64_t stride, uin
           uint64_t lo;
           c = tri_set(d, a, F, stride, p, lo);
         } else {
-          uint32_t v = F[(uint64_t)d.col[a] * stride + p];
-          c = d.rp[a][v + 1] - d.rp[a][v];
+          uint32_t v = F[(uint64_t)d.col[a] * stride + p], lo, hi;
+          row_range(d.rp[a], d.pm[a], v, lo, hi);
+          c = hi - lo;
         }
         if (c < best) {
           best = c;
@@ -128,17 +131,20 @@ __device__ __forceinline__ Cand resolve(const uint32_t* __restrict__ F, uint64_t
   }
   const uint32_t* rp = d.rp[0];
   const uint32_t* adj = d.adj[0];
+  const uint64_t* pm = d.pm[0];
   int col = d.col[0];
 #pragma unroll
   for (int a = 1; a < kMaxBind; ++a) {
     if (a == c.am) {
       rp = d.rp[a];
       adj = d.adj[a];
+      pm = d.pm[a];
       col = d.col[a];
     }
   }
-  uint32_t v = F[(uint64_t)col * stride + c.p];
-  c.e = adj[rp[v] + k];
+  uint32_t v = F[(uint64_t)col * stride + c.p], lo, hi;
+  row_range(rp, pm, v, lo, hi);
+  c.e = adj[lo + k];
   return c;
 }
 
@@ -154,8 +160,9 @@ __device__ __forceinline__ bool intersect_all(const uint32_t* __restrict__ F, ui
         keep = contains_u32(d.tcol + lo, 0, len, c.e);
         continue;
       }
-      uint32_t u = F[(uint64_t)d.col[a] * stride + c.p];
-      keep = contains_u32(d.adj[a], d.rp[a][u], d.rp[a][u + 1], c.e);
+      uint32_t u = F[(uint64_t)d.col[a] * stride + c.p], lo, hi;
+      row_range(d.rp[a], d.pm[a], u, lo, hi);
+      keep = contains_u32(d.adj[a], lo, hi, c.e);
     }
   }
   return keep;
@@ -183,8 +190,7 @@ __device__ __forceinline__ void intersect_lockstep(const uint32_t* __restrict__ 
         lo[u] = hi[u] = n[u] = 0;
         if (act[u]) {
           uint32_t x = F[(uint64_t)d.col[a] * stride + c[u].p];
-          lo[u] = d.rp[a][x];
-          hi[u] = d.rp[a][x + 1];
+          row_range(d.rp[a], d.pm[a], x, lo[u], hi[u]);
           n[u] = hi[u] - lo[u];
         }
       }

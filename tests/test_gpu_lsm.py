@@ -1,0 +1,197 @@
+"""GPU parity of log-structured updates (option lsm_updates: touched rows
+appended to the slack of the current version and found through per-vertex
+maps, merged back by compactions; the multi-version index of Sec. 4.3)
+against the CPU oracle's Delta-GJ: every batch's consolidated rows, count
+deltas and per-stage counters, then the compacted index and static counts.
+The edge set each version reads is the same as with whole-index rewrites, so
+the oracle's results are the reference either way."""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import queries as Q
+from tests.test_gpu_delta import check_index
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gj():
+    import paper_1802_03760_amd as gj
+    return gj
+
+
+def lsm_ctx(gj, max_patch=0, fused=1):
+    c = gj.Context(0)
+    c.set_option("lsm_updates", 1)
+    c.set_option("lsm_max_patch", max_patch)
+    c.set_option("delta_fused", fused)
+    return c
+
+
+def check_step(gj, ctx, G, O, qs_py, qs_gj, bs, bd, bg, rows=True):
+    res = gj.apply_updates(ctx, G, bs, bd, bg, qs_gj, rows=rows)
+    before = O.copy()
+    for q, r in zip(qs_py, res):
+        ref = oracle.delta(before.copy(), bs, bd, bg, q)
+        assert r["count_delta"] == ref["count_delta"], q
+        if rows:
+            assert np.array_equal(r["rows"], ref["rows"]), q
+            assert np.array_equal(r["signs"], ref["signs"]), q
+        assert r["stats"]["raw_emissions"] == ref["raw_emissions"], q
+        assert r["stats"]["prefixes"] == ref["prefixes"], q
+        assert r["stats"]["extensions"] == ref["extensions"], q
+    oracle.delta(O, bs, bd, bg)
+    # the edge count is known without merging the appended rows
+    assert G.info(degrees=False)["edges"] == len(O.edge_list()[0])
+    return res
+
+
+def random_batch(rng, O, n, b, pdel=0.4):
+    bs = rng.integers(0, n, b).astype(np.uint32)
+    bd = rng.integers(0, n, b).astype(np.uint32)
+    bg = np.where(rng.random(b) < pdel, -1, 1).astype(np.int8)
+    es, ed = O.edge_list()
+    for k in range(b):
+        if bg[k] < 0 and len(es) and rng.random() < 0.7:
+            j = rng.integers(0, len(es))
+            bs[k], bd[k] = es[j], ed[j]
+    dels = {(int(x), int(y)) for x, y, g in zip(bs, bd, bg) if g < 0}
+    keep = np.array([not (g > 0 and (int(x), int(y)) in dels) for x, y, g in zip(bs, bd, bg)])
+    return bs[keep], bd[keep], bg[keep]
+
+
+def final_checks(gj, ctx, G, O, qs_py, qs_gj):
+    es, ed = O.edge_list()
+    check_index(G, np.asarray(es, np.uint32), np.asarray(ed, np.uint32))
+    for q, qg in zip(qs_py, qs_gj):
+        assert gj.count(ctx, G, qg)["matches"] == oracle.run(O, q)["matches"], q
+
+
+@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("names", [("triangle", "cyclic_triangle", "reciprocal"),
+                                   ("clique4", "diamond", "cycle4", "house")])
+def test_lsm_random_batches(gj, names, fused):
+    """Small dense graph, many batches hitting the same rows again (rows
+    rewritten several times, deletes of appended entries, re-inserts), no
+    compaction until the final reads."""
+    n = 30
+    rng = np.random.default_rng(7 + len(names))
+    src = rng.integers(0, n, 200).astype(np.uint32)
+    dst = rng.integers(0, n, 200).astype(np.uint32)
+    ctx = lsm_ctx(gj, fused=fused)
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle.Graph(n, src, dst)
+    qs_py = [Q.ALL[k] for k in names]
+    qs_gj = [gj.Query(ctx, *q) for q in qs_py]
+    for it in range(10):
+        bs, bd, bg = random_batch(rng, O, n, int(rng.integers(1, 40)))
+        # count-only calls take the fused pipeline unless fused is 0
+        check_step(gj, ctx, G, O, qs_py, qs_gj, bs, bd, bg, rows=it % 2 == 0)
+    assert ctx.get_option("lsm_compactions") == 0
+    final_checks(gj, ctx, G, O, qs_py, qs_gj)
+    assert ctx.get_option("lsm_compactions") == 1
+
+
+def test_lsm_forced_compactions(gj):
+    """A small append limit: compactions between batches, and batches whose
+    rows exceed the limit even after one (written as a whole new version)."""
+    n = 40
+    rng = np.random.default_rng(21)
+    src = rng.integers(0, n, 300).astype(np.uint32)
+    dst = rng.integers(0, n, 300).astype(np.uint32)
+    ctx = lsm_ctx(gj, max_patch=120)
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle.Graph(n, src, dst)
+    qs_py = [Q.TRIANGLE, Q.CLIQUE4, Q.CYCLE4]
+    qs_gj = [gj.Query(ctx, *q) for q in qs_py]
+    for it in range(14):
+        b = int(rng.integers(1, 12)) if it % 5 else 120  # every fifth batch too large to append
+        bs, bd, bg = random_batch(rng, O, n, b)
+        check_step(gj, ctx, G, O, qs_py, qs_gj, bs, bd, bg)
+    assert ctx.get_option("lsm_compactions") > 0
+    final_checks(gj, ctx, G, O, qs_py, qs_gj)
+
+
+def test_lsm_rmat_stream(gj):
+    """R-MAT scale 11 (seed 0), then log-uniform batches of 1 to 2,000 rows
+    with 10% deletions (seed 1): hub rows rewritten by most batches."""
+    scale = 11
+    src, dst = synth.rmat_draws(scale, seed=0)
+    n = 1 << scale
+    ctx = lsm_ctx(gj)
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle.Graph(n, src, dst)
+    qs_py = [Q.TRIANGLE, Q.CLIQUE4]
+    qs_gj = [gj.Query(ctx, *q) for q in qs_py]
+    for k, bs, bd, bg in synth.update_stream(scale, 0, 1, 8, 1, 2000):
+        check_step(gj, ctx, G, O, qs_py, qs_gj, bs, bd, bg)
+    assert ctx.get_option("lsm_compactions") == 0
+    final_checks(gj, ctx, G, O, qs_py, qs_gj)
+
+
+def test_lsm_equals_rewrite_scale14(gj):
+    """At R-MAT scale 14 (beyond the oracle's reach per batch): count deltas
+    and counters equal the whole-index rewrite path batch by batch, with a
+    compaction in the middle of the stream; then the two indexes are equal."""
+    scale = 14
+    src, dst = synth.rmat_draws(scale, seed=3)
+    n = 1 << scale
+    cl = lsm_ctx(gj, max_patch=30000)
+    cp = gj.Context(0)
+    Gl, Gp = gj.Graph(cl, src, dst, n), gj.Graph(cp, src, dst, n)
+    names = ["triangle", "cyclic_triangle", "clique4", "diamond", "cycle4"]
+    ql = [gj.Query(cl, *Q.ALL[k]) for k in names]
+    qp = [gj.Query(cp, *Q.ALL[k]) for k in names]
+    for k, bs, bd, bg in synth.update_stream(scale, 3, 4, 12, 1, 20000):
+        a = gj.apply_updates(cl, Gl, bs, bd, bg, ql)
+        b = gj.apply_updates(cp, Gp, bs, bd, bg, qp)
+        for x, y, nm in zip(a, b, names):
+            assert x["count_delta"] == y["count_delta"], nm
+            assert x["stats"]["prefixes"] == y["stats"]["prefixes"], nm
+            assert x["stats"]["extensions"] == y["stats"]["extensions"], nm
+        assert Gl.info(degrees=False)["edges"] == Gp.info(degrees=False)["edges"]
+    assert cl.get_option("lsm_compactions") >= 1
+    il, ip = Gl.info(), Gp.info()
+    assert (il["edges"], il["max_out"], il["max_in"]) == (ip["edges"], ip["max_out"], ip["max_in"])
+    E = il["edges"]
+    from tests.test_gpu_delta import _dev
+    for rev in (0, 1):
+        pl, pp = Gl.csr_ptrs(rev), Gp.csr_ptrs(rev)
+        assert np.array_equal(_dev(pl[0], n + 1), _dev(pp[0], n + 1))
+        assert np.array_equal(_dev(pl[1], E), _dev(pp[1], E))
+        assert np.array_equal(_dev(pl[2], E), _dev(pp[2], E))
+    for x, y in zip(ql, qp):
+        assert gj.count(cl, Gl, x)["matches"] == gj.count(cp, Gp, y)["matches"]
+
+
+def test_lsm_option_off_mid_stream(gj):
+    """Switching lsm_updates off with appended rows pending merges them and
+    continues with whole-index rewrites; a server created on a graph with
+    appended rows starts from the merged index."""
+    n = 25
+    rng = np.random.default_rng(5)
+    src = rng.integers(0, n, 150).astype(np.uint32)
+    dst = rng.integers(0, n, 150).astype(np.uint32)
+    ctx = lsm_ctx(gj)
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle.Graph(n, src, dst)
+    qs_py = [Q.TRIANGLE, Q.DIAMOND]
+    qs_gj = [gj.Query(ctx, *q) for q in qs_py]
+    for it in range(3):
+        check_step(gj, ctx, G, O, qs_py, qs_gj, *random_batch(rng, O, n, 15))
+    ctx.set_option("lsm_updates", 0)
+    for it in range(2):
+        check_step(gj, ctx, G, O, qs_py, qs_gj, *random_batch(rng, O, n, 15))
+    assert ctx.get_option("lsm_compactions") == 1
+    ctx.set_option("lsm_updates", 1)
+    for it in range(2):
+        check_step(gj, ctx, G, O, qs_py, qs_gj, *random_batch(rng, O, n, 15))
+    srv = gj.Server(ctx, G, max_batch=4)
+    try:
+        r = srv.wait(srv.submit_count(qs_gj[0]))
+        assert r["count"] == oracle.run(O, Q.TRIANGLE)["matches"]
+    finally:
+        srv.close()
+    assert ctx.get_option("lsm_compactions") == 2
