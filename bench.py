@@ -396,8 +396,11 @@ def lsm_updates(gj, src, dst, n, scale, batches, log):
     """The delta stream (triangle maintenance, log-uniform batches of 1 to
     100,000 rows, 10% deletions, seed 1) on two fresh graphs: every batch
     written as a new version of both indexes, and log-structured (touched rows
-    appended, merged back when the slack is used up).  Count deltas must
-    agree; the last figure is the merge a static reader pays afterwards."""
+    appended; a batch too large to append, or that does not fit the rest of
+    the slack, written as a new version with the appended rows folded in).
+    Count deltas must agree; the last figure is the merge a static reader
+    pays afterwards."""
+    import numpy as np
     import torch
     import synth
     out = {"scale": scale, "batches": batches, "query": "triangle"}
@@ -415,6 +418,7 @@ def lsm_updates(gj, src, dst, n, scale, batches, log):
             lat.append((time.perf_counter() - t1) * 1e3)
             d.append(r["count_delta"])
         compactions = ctx.get_option("lsm_compactions")
+        folds = ctx.get_option("lsm_folds")
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         G.info()  # the first static reader merges appended rows
@@ -422,11 +426,11 @@ def lsm_updates(gj, src, dst, n, scale, batches, log):
         lat = np.array(lat)
         out[mode] = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                      "mean_ms": float(lat.mean()), "compactions_in_stream": int(compactions),
-                     "final_merge_ms": merge_ms}
+                     "folds": int(folds), "final_merge_ms": merge_ms}
         deltas[mode] = d
-        log("update stream (%s, scale %d): p50 %.3f ms, p99 %.3f ms, mean %.3f ms, %d compactions, "
+        log("update stream (%s, scale %d): p50 %.3f ms, p99 %.3f ms, mean %.3f ms, %d compactions, %d folds, "
             "final merge %.2f ms" % (mode, scale, out[mode]["p50_ms"], out[mode]["p99_ms"], out[mode]["mean_ms"],
-                                     compactions, merge_ms))
+                                     compactions, folds, merge_ms))
         del G, q, ctx
         gc.collect()
     assert deltas["rewrite"] == deltas["lsm"], "log-structured count deltas differ"

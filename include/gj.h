@@ -98,24 +98,30 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   only the rows it touches, appended past the current
  *                   version's edges in the slack of its column arrays and
  *                   found through a per-vertex map, instead of writing a new
- *                   version of both indexes.  The rows are merged back into
- *                   one CSR (a compaction, into another version slot) when
- *                   the slack is used up, and before any call that reads the
- *                   graph other than gj_apply_updates: gj_run, gj_run_batch,
- *                   gj_autotune, gj_graph_csr, gj_graph_info with max_out or
- *                   max_in, gj_graph_index_triangles, gj_server_create.  A
- *                   batch whose rows do not fit even a freshly compacted
- *                   slot is written as a new version of both indexes.
- *                   Results are the same either way.  0 (default) writes
- *                   every batch as a new version of both indexes
+ *                   version of both indexes.  A batch whose rewritten rows
+ *                   do not fit the rest of the slack, or exceed an eighth of
+ *                   the edges (2^16 entries at least) in a direction, is
+ *                   written as a new version of both indexes that takes the
+ *                   appended rows in too (counter "lsm_folds").  Any call
+ *                   that reads the graph other than gj_apply_updates merges
+ *                   appended rows into one CSR first (a compaction, into
+ *                   another version slot; counter "lsm_compactions"):
+ *                   gj_run, gj_run_batch, gj_autotune, gj_graph_csr,
+ *                   gj_graph_info with max_out or max_in,
+ *                   gj_graph_index_triangles, gj_server_create.  Results
+ *                   are the same either way.  0 (default) writes every
+ *                   batch as a new version of both indexes
  *   "lsm_max_patch" with lsm_updates: at most this many appended entries
- *                   per direction before a compaction (0, default: the
- *                   slot's slack, m / 8 + 2^22 entries after a compaction)
+ *                   per direction (0, default: the slot's slack; a
+ *                   compaction leaves m / 2 + 2^22 entries of it, and
+ *                   reallocates the slot when less than half of that is
+ *                   left)
  * Returns GJ_EINVAL for an unknown key or out-of-range value. */
 gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
 
-/* Reads an option (keys above, plus "batch_cap", the counter
- * "lsm_compactions": compactions run on this context, and the counter
+/* Reads an option (keys above, plus "batch_cap", the counters
+ * "lsm_compactions" and "lsm_folds" of this context (see "lsm_updates"),
+ * and the counter
  * "batch_fallbacks": gj_run_batch calls that fell back to the depth-first
  * path). */
 gj_status gj_ctx_get_option(gj_ctx* ctx, const char* key, int64_t* value);

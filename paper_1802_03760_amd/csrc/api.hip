@@ -53,6 +53,16 @@ void read_bytes(gj_ctx* c, void* host, const void* dptr, size_t bytes) {
   }
 }
 
+void read_u64s(gj_ctx* c, std::initializer_list<const uint64_t*> ptrs, uint64_t* host) {
+  GJ_CHECK(ptrs.size() * sizeof(uint64_t) <= 4096, GJ_EINVAL, "too many values to read");
+  uint64_t* st = (uint64_t*)c->pinned;
+  size_t i = 0;
+  for (const uint64_t* p : ptrs)
+    GJ_HIP(hipMemcpyAsync(st + i++, p, sizeof(uint64_t), hipMemcpyDeviceToHost, c->stream));
+  GJ_HIP(hipStreamSynchronize(c->stream));
+  memcpy(host, st, ptrs.size() * sizeof(uint64_t));
+}
+
 void KernelTimer::start() {
   if (c_->events.size() < 2 * (n_ + 1)) {
     for (int i = 0; i < 2; ++i) {
@@ -224,6 +234,7 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "lsm_updates") *value = c->lsm_updates;
     else if (k == "lsm_max_patch") *value = (int64_t)c->lsm_max_patch;
     else if (k == "lsm_compactions") *value = (int64_t)c->lsm_compactions;
+    else if (k == "lsm_folds") *value = (int64_t)c->lsm_folds;
     else throw Error{GJ_EINVAL, "unknown option " + k};
   });
 }

@@ -112,7 +112,8 @@ __global__ void k_ins_flags(const int8_t* __restrict__ g, uint64_t k, uint32_t* 
 // only finds where row v + 1 starts, for lane 62.
 __global__ void __launch_bounds__(kBlock) k_delta_rows(const uint32_t* __restrict__ r, uint64_t k,
                                                        const uint64_t* __restrict__ ins_scan,
-                                                       const uint32_t* __restrict__ rp, uint32_t n,
+                                                       const uint32_t* __restrict__ rp,
+                                                       const uint64_t* __restrict__ pm, uint32_t n,
                                                        uint32_t* __restrict__ drp, uint32_t* __restrict__ deg,
                                                        uint32_t* __restrict__ maxdeg) {
   __shared__ uint32_t wbest[kBlock / 64];
@@ -141,7 +142,9 @@ __global__ void __launch_bounds__(kBlock) k_delta_rows(const uint32_t* __restric
     if (lane < 63 && v < n) {
       uint32_t ins = (uint32_t)(ins_scan[hi] - ins_scan[lo]);
       uint32_t del = (hi - (uint32_t)lo) - ins;
-      uint32_t d = rp[v + 1] - rp[v] + ins - del;
+      uint32_t olo, ohi;
+      row_range(rp, pm, (uint32_t)v, olo, ohi);
+      uint32_t d = ohi - olo + ins - del;
       deg[v] = d;
       best = d > best ? d : best;
     }
@@ -160,15 +163,19 @@ __global__ void __launch_bounds__(kBlock) k_delta_rows(const uint32_t* __restric
 // tile of kMoveU * kBlock consecutive entries, each thread kMoveU of them
 // kBlock apart, with every load of a tile issued before the row lookups that
 // depend on them, so that a wave has kMoveU independent loads in flight.
+// Rows that a log-structured update rewrote (pm, when not null) are moved by
+// k_move_rewritten instead.
 constexpr int kMoveU = 4;
 __global__ void __launch_bounds__(kBlock) k_move_old(const uint32_t* __restrict__ orp,
                                                      const uint32_t* __restrict__ ocol,
-                                                     const uint32_t* __restrict__ orow, uint64_t om, DeltaDir D,
+                                                     const uint32_t* __restrict__ orow, uint64_t om,
+                                                     const uint64_t* __restrict__ pm, DeltaDir D,
                                                      const uint32_t* __restrict__ nrp, uint32_t* __restrict__ ncol,
                                                      uint32_t* __restrict__ nrow) {
   const uint64_t tile = (uint64_t)kBlock * kMoveU;
   for (uint64_t base = (uint64_t)blockIdx.x * tile; base < om; base += (uint64_t)gridDim.x * tile) {
     uint32_t r[kMoveU], x[kMoveU], a[kMoveU], b[kMoveU], np[kMoveU], op[kMoveU];
+    bool moved[kMoveU];
 #pragma unroll
     for (int u = 0; u < kMoveU; ++u) {
       uint64_t e = base + (uint64_t)u * kBlock + threadIdx.x;
@@ -185,11 +192,12 @@ __global__ void __launch_bounds__(kBlock) k_move_old(const uint32_t* __restrict_
       b[u] = D.drp[r[u] + 1];
       np[u] = nrp[r[u]];
       op[u] = orp[r[u]];
+      moved[u] = pm && pm[r[u]] != ~0ull;
     }
 #pragma unroll
     for (int u = 0; u < kMoveU; ++u) {
       uint64_t e = base + (uint64_t)u * kBlock + threadIdx.x;
-      if (e >= om) continue;
+      if (e >= om || moved[u]) continue;
       uint64_t pos = (uint64_t)np[u] + (e - op[u]);
       if (a[u] != b[u]) {
         uint32_t i = lower_bound_u32(D.x, a[u], b[u], x[u]);
@@ -204,16 +212,53 @@ __global__ void __launch_bounds__(kBlock) k_move_old(const uint32_t* __restrict_
   }
 }
 
+// the surviving entries of the rows a log-structured update rewrote (keys:
+// their vertices, koff: the offsets of their rows in key-list order, tot
+// entries; pm: where each row lies in ocol), spread over the grid entry by
+// entry so that long rows do not serialise on one wave
+__global__ void __launch_bounds__(kBlock) k_move_rewritten(const uint32_t* __restrict__ keys,
+                                                           const uint64_t* __restrict__ koff, uint64_t nkeys,
+                                                           uint64_t tot, const uint64_t* __restrict__ pm,
+                                                           const uint32_t* __restrict__ ocol, DeltaDir D,
+                                                           const uint32_t* __restrict__ nrp,
+                                                           uint32_t* __restrict__ ncol, uint32_t* __restrict__ nrow) {
+  const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t base = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; base < tot;
+       base += waves << 6) {
+    uint64_t t0 = wave_first_segment(koff, nkeys, base);
+    uint64_t e = base + lane_id();
+    if (e >= tot) continue;
+    uint64_t t = gallop_segment(koff, t0, nkeys, e);
+    uint32_t v = keys[t];
+    uint32_t j = (uint32_t)(e - koff[t]);
+    uint32_t x = ocol[(uint32_t)pm[v] + j];
+    uint32_t a = D.drp[v], b = D.drp[v + 1];
+    uint64_t pos = (uint64_t)nrp[v] + j;
+    if (a != b) {
+      uint32_t i = lower_bound_u32(D.x, a, b, x);
+      if (i < b && D.x[i] == x) continue;  // deleted
+      uint32_t ins_before = (uint32_t)(D.ins_scan[i] - D.ins_scan[a]);
+      uint32_t del_before = (i - a) - ins_before;
+      pos = pos + ins_before - del_before;
+    }
+    ncol[pos] = x;
+    nrow[pos] = v;
+  }
+}
+
 // place the inserted entries
-__global__ void k_place_ins(const uint32_t* __restrict__ orp, const uint32_t* __restrict__ ocol, DeltaDir D,
-                            uint64_t k, const uint32_t* __restrict__ nrp, uint32_t* __restrict__ ncol,
+__global__ void k_place_ins(const uint32_t* __restrict__ orp, const uint32_t* __restrict__ ocol,
+                            const uint64_t* __restrict__ pm, DeltaDir D, uint64_t k,
+                            const uint32_t* __restrict__ nrp, uint32_t* __restrict__ ncol,
                             uint32_t* __restrict__ nrow) {
   uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < k; i += gs) {
     if (D.g[i] < 0) continue;
     uint32_t r = D.r[i], x = D.x[i];
     uint32_t a = D.drp[r];
-    uint32_t old_less = lower_bound_u32(ocol, orp[r], orp[r + 1], x) - orp[r];
+    uint32_t olo, ohi;
+    row_range(orp, pm, r, olo, ohi);
+    uint32_t old_less = lower_bound_u32(ocol, olo, ohi, x) - olo;
     uint32_t ins_before = (uint32_t)(D.ins_scan[i] - D.ins_scan[a]);
     uint32_t del_before = ((uint32_t)i - a) - ins_before;  // every delete below x is an old entry below x
     uint64_t pos = (uint64_t)nrp[r] + old_less - del_before + ins_before;
@@ -233,8 +278,21 @@ __global__ void k_unswap(const uint64_t* __restrict__ keys, const uint32_t* __re
   }
 }
 
-static void update_dir(gj_ctx* c, uint32_t n, const CsrDir& od, uint64_t om, const uint32_t* r, const uint32_t* x,
-                       const int8_t* g, uint64_t k, CsrDir& nd, const std::string& tag, uint32_t* maxdeg) {
+// Rows appended by log-structured updates to one direction of the current
+// version: their map, vertices and offsets (see lsm_row_offsets).
+struct Rewritten {
+  const uint64_t* pm = nullptr;
+  const uint32_t* keys = nullptr;
+  const uint64_t* koff = nullptr;
+  uint64_t nkeys = 0, tot = 0;
+};
+
+// One direction of the next version, from the current one: the slot od with
+// om entries, and the rows appended since (rw).
+static void update_dir(gj_ctx* c, uint32_t n, const CsrDir& od, uint64_t om, const Rewritten& rw,
+                       const uint32_t* r, const uint32_t* x, const int8_t* g, uint64_t k, CsrDir& nd,
+                       const std::string& tag, uint32_t* maxdeg) {
+  const uint64_t* pm = rw.pm;
   uint32_t* drp = (uint32_t*)ws_get(c, "up_drp" + tag, ((uint64_t)n + 1) * sizeof(uint32_t));
   uint32_t* insf = (uint32_t*)ws_get(c, "up_insf" + tag, (k + 1) * sizeof(uint32_t));
   uint64_t* ins_scan = (uint64_t*)ws_get(c, "up_inss" + tag, (k + 1) * sizeof(uint64_t));
@@ -243,12 +301,16 @@ static void update_dir(gj_ctx* c, uint32_t n, const CsrDir& od, uint64_t om, con
   unsigned gk = grid_for(k, kBlock, 1u << 16);
   k_ins_flags<<<gk, kBlock, 0, c->stream>>>(g, k, insf);
   scan_u32_to_u64(c, insf, ins_scan, k);
-  k_delta_rows<<<gn, kBlock, 0, c->stream>>>(r, k, ins_scan, od.rp, n, drp, deg, maxdeg);
+  k_delta_rows<<<gn, kBlock, 0, c->stream>>>(r, k, ins_scan, od.rp, pm, n, drp, deg, maxdeg);
   DeltaDir D{r, x, g, drp, ins_scan};
   scan_u32(c, deg, nd.rp, n);
   if (om)
-    k_move_old<<<grid_for((om + kMoveU - 1) / kMoveU, kBlock, 1u << 16), kBlock, 0, c->stream>>>(od.rp, od.col, od.row, om, D, nd.rp, nd.col, nd.row);
-  k_place_ins<<<gk, kBlock, 0, c->stream>>>(od.rp, od.col, D, k, nd.rp, nd.col, nd.row);
+    k_move_old<<<grid_for((om + kMoveU - 1) / kMoveU, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+        od.rp, od.col, od.row, om, pm, D, nd.rp, nd.col, nd.row);
+  if (pm && rw.tot)
+    k_move_rewritten<<<grid_for(rw.tot, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+        rw.keys, rw.koff, rw.nkeys, rw.tot, pm, od.col, D, nd.rp, nd.col, nd.row);
+  k_place_ins<<<gk, kBlock, 0, c->stream>>>(od.rp, od.col, pm, D, k, nd.rp, nd.col, nd.row);
   GJ_HIP(hipGetLastError());
 }
 
@@ -271,7 +333,7 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   // log-structured updates for the plain entry point only: a caller that
   // names the slot (the server) keeps every version a plain CSR
   const bool lsm = c->lsm_updates && target < 0;
-  if (!lsm) graph_compact(c, g);  // the rewrite below reads the current version as one CSR
+  LsmState& L = g->lsm;
   GJ_CHECK(target < 0 || (target < kMaxVersions && target != g->cur), GJ_EINVAL,
            "update target is the current version");
   c->last_delta.assign(nq, gj_ctx::LastDelta{});
@@ -312,11 +374,16 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   uint32_t* flags = (uint32_t*)ws_get(c, "ub_flags", (b + 1) * sizeof(uint32_t));
   int8_t* dsign = (int8_t*)ws_get(c, "ub_dsign", b + 1);
   uint64_t* off = (uint64_t*)ws_get(c, "ub_off", (b + 1) * sizeof(uint64_t));
-  {
-    const Version& cv = g->ver[g->cur];
-    const uint64_t* pm = g->lsm.on ? g->lsm.map[g->lsm.cur_map][0] : nullptr;
-    if (b) k_batch_classify<<<gb, kBlock, 0, c->stream>>>(keys, vals, b, cv.d[0].rp, cv.d[0].col, pm, flags, dsign, cnt);
+  // the current version as the update reads it: the slot ver[cur], plus the
+  // rows appended by log-structured updates since its last rewrite
+  Version cur_view = g->ver[g->cur];
+  if (L.on) {
+    for (int d = 0; d < 2; ++d) cur_view.pmap[d] = L.map[L.cur_map][d];
+    cur_view.m = L.m;
   }
+  if (b)
+    k_batch_classify<<<gb, kBlock, 0, c->stream>>>(keys, vals, b, cur_view.d[0].rp, cur_view.d[0].col,
+                                                   cur_view.pmap[0], flags, dsign, cnt);
   scan_u32_to_u64(c, flags, off, b);
   unsigned long long hc[3];
   read_bytes(c, hc, cnt, sizeof(hc));
@@ -345,7 +412,8 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   int8_t* rg = (int8_t*)ws_get(c, "de_rsign", k + 1);
   k_unswap<<<grid_for(k, kBlock, 1u << 16), kBlock, 0, c->stream>>>(sw, si, eg, k, rd, rs, rg);
   // ---- next version: the touched rows appended (log-structured), else both
-  // indexes rewritten into another slot
+  // indexes written into another slot from the current version (appended
+  // rows included, which ends their epoch)
   Version lsm_old, lsm_new;
   LsmCommit commit;
   const bool patched =
@@ -360,22 +428,30 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   } guard{c, g, patched};
   if (!patched) {
     if (target < 0) target = g->cur < 2 ? 1 - g->cur : 0;
-    Version& ov = g->ver[g->cur];
+    const Version& bv = g->ver[g->cur];
     Version& nv = g->ver[target];
     // upper bound of the new edge count: old + all of dE, with slack so that a
     // growing graph does not reallocate the spare version on every batch
-    uint64_t need = ov.m + k;
+    uint64_t need = cur_view.m + k;
     if (need > nv.cap) version_alloc(nv, n, need + need / 16 + (1u << 20));
     uint32_t* mx = (uint32_t*)ws_get(c, "maxdeg", 2 * sizeof(uint32_t));
     GJ_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(uint32_t), c->stream));
-    update_dir(c, n, ov.d[0], ov.m, es, ed, eg, k, nv.d[0], "f", mx);
-    update_dir(c, n, ov.d[1], ov.m, rd, rs, rg, k, nv.d[1], "r", mx + 1);
+    for (int d = 0; d < 2; ++d) {
+      Rewritten rw;
+      if (L.on) {
+        rw.pm = cur_view.pmap[d];
+        rw.keys = L.keys[d];
+        rw.nkeys = L.nkeys[d];
+        rw.koff = lsm_row_offsets(c, g, d, rw.tot);
+      }
+      update_dir(c, n, bv.d[d], bv.m, rw, d ? rd : es, d ? rs : ed, d ? rg : eg, k, nv.d[d], d ? "r" : "f", mx + d);
+    }
     uint32_t newm = 0;
     read_bytes(c, &newm, nv.d[0].rp + n, sizeof(newm));
     nv.m = newm;
     version_finish(c, nv, n, true);  // row pointers and largest degrees come from the update
   }
-  const Version& ov = patched ? lsm_old : g->ver[g->cur];
+  const Version& ov = patched ? lsm_old : cur_view;
   const Version& nv = patched ? lsm_new : g->ver[target];
   // ---- delta queries
   std::vector<char> done(nq, 0);
@@ -384,7 +460,7 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   // runs the owner-grouped kernel over the signed seeds, grouped by source
   // (the forward delta rows) and by destination (the reverse ones), for
   // batches with enough changes to pay for its planning over every vertex.
-  if (c->strategy != 1 && k >= c->delta_owner_min && !patched) {
+  if (c->strategy != 1 && k >= c->delta_owner_min && !patched && !ov.pmap[0]) {
     const uint32_t* drp_f = (const uint32_t*)ws_get(c, "up_drpf", ((uint64_t)n + 1) * sizeof(uint32_t));
     const uint32_t* drp_r = (const uint32_t*)ws_get(c, "up_drpr", ((uint64_t)n + 1) * sizeof(uint32_t));
     for (uint32_t qi = 0; qi < nq; ++qi) {
@@ -587,6 +663,10 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
     lsm_commit(g, commit);
   } else {
     g->cur = target;
+    if (L.on) {  // the appended rows are in the new version now
+      lsm_clear(c, g);
+      ++c->lsm_folds;
+    }
   }
   g->version += 1;
 }

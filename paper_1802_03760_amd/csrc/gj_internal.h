@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <initializer_list>
 #include <map>
 #include <string>
 #include <vector>
@@ -165,6 +166,7 @@ struct gj_ctx {
   int lsm_updates = 0;  // gj_apply_updates: append rewritten rows instead of rewriting both indexes
   uint64_t lsm_max_patch = 0;  // arena entries per direction before a compaction (0: the slot's slack)
   uint64_t lsm_compactions = 0;  // compactions run on this context
+  uint64_t lsm_folds = 0;  // batches written as a new version while appended rows were pending
 };
 
 // Resident versions of a graph: ver[cur] is current; an update reads it and
@@ -215,6 +217,8 @@ void dev_free(void* p);
 void* dev_alloc(size_t bytes);
 uint64_t read_u64(gj_ctx* c, const void* dptr);
 void read_bytes(gj_ctx* c, void* host, const void* dptr, size_t bytes);
+// several device words, one synchronisation
+void read_u64s(gj_ctx* c, std::initializer_list<const uint64_t*> ptrs, uint64_t* host);
 
 inline unsigned grid_for(uint64_t items, uint64_t per_block, unsigned cap = 1u << 20) {
   uint64_t g = (items + per_block - 1) / per_block;

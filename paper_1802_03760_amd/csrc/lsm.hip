@@ -129,6 +129,16 @@ __global__ void k_lsm_set_map(const uint32_t* __restrict__ tv, uint64_t nt, cons
   }
 }
 
+__global__ void k_lsm_unset(const uint32_t* __restrict__ keys, uint64_t nkeys, uint64_t* __restrict__ m0,
+                            uint64_t* __restrict__ m1) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nkeys; i += gs) {
+    uint32_t v = keys[i];
+    m0[v] = ~0ull;
+    m1[v] = ~0ull;
+  }
+}
+
 // ---- compaction
 __global__ void k_view_deg(const uint32_t* __restrict__ rp, const uint64_t* __restrict__ pm, uint32_t n,
                            uint32_t* __restrict__ deg) {
@@ -155,20 +165,32 @@ __global__ void k_copy_base(const uint32_t* __restrict__ rp, const uint32_t* __r
   }
 }
 
-// rewritten rows, a wave per row
-__global__ void k_copy_rows(const uint32_t* __restrict__ keys, uint64_t nkeys, const uint64_t* __restrict__ pm,
-                            const uint32_t* __restrict__ col, const uint32_t* __restrict__ nrp,
-                            uint32_t* __restrict__ ncol, uint32_t* __restrict__ nrow) {
+__global__ void k_key_lens(const uint32_t* __restrict__ keys, uint64_t nkeys, const uint64_t* __restrict__ pm,
+                           uint32_t* __restrict__ lens) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nkeys; i += gs)
+    lens[i] = (uint32_t)(pm[keys[i]] >> 32);
+}
+
+// the entries of the rewritten rows, in key-list order (koff: their offsets)
+__global__ void __launch_bounds__(kBlock) k_copy_rows(const uint32_t* __restrict__ keys,
+                                                      const uint64_t* __restrict__ koff, uint64_t nkeys,
+                                                      uint64_t tot, const uint64_t* __restrict__ pm,
+                                                      const uint32_t* __restrict__ col,
+                                                      const uint32_t* __restrict__ nrp, uint32_t* __restrict__ ncol,
+                                                      uint32_t* __restrict__ nrow) {
   const uint64_t waves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
-  for (uint64_t w = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; w < nkeys; w += waves) {
-    uint32_t v = keys[w];
-    uint64_t e = pm[v];
-    uint32_t lo = (uint32_t)e, len = (uint32_t)(e >> 32);
-    uint64_t dst = nrp[v];
-    for (uint32_t j = lane_id(); j < len; j += 64) {
-      ncol[dst + j] = col[lo + j];
-      nrow[dst + j] = v;
-    }
+  for (uint64_t base = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; base < tot;
+       base += waves << 6) {
+    uint64_t t0 = wave_first_segment(koff, nkeys, base);
+    uint64_t i = base + lane_id();
+    if (i >= tot) continue;
+    uint64_t t = gallop_segment(koff, t0, nkeys, i);
+    uint32_t v = keys[t];
+    uint32_t j = (uint32_t)(i - koff[t]);
+    uint64_t dst = (uint64_t)nrp[v] + j;
+    ncol[dst] = col[(uint32_t)pm[v] + j];
+    nrow[dst] = v;
   }
 }
 
@@ -193,16 +215,33 @@ void lsm_free(gj_graph* g) {
   L = LsmState{};
 }
 
-static void lsm_reset_maps(gj_ctx* c, gj_graph* g) {
+void lsm_clear(gj_ctx* c, gj_graph* g) {
+  // every entry other than ~0 in either map belongs to a vertex of the key list
   LsmState& L = g->lsm;
-  uint64_t bytes = (uint64_t)g->n * sizeof(uint64_t);
-  for (int b = 0; b < 2; ++b)
-    for (int d = 0; d < 2; ++d)
-      if (L.map[b][d]) GJ_HIP(hipMemsetAsync(L.map[b][d], 0xFF, bytes, c->stream));
+  for (int d = 0; d < 2; ++d)
+    if (L.map[0][d] && L.nkeys[d])
+      k_lsm_unset<<<grid_for(L.nkeys[d], kBlock, 1u << 16), kBlock, 0, c->stream>>>(L.keys[d], L.nkeys[d],
+                                                                                    L.map[0][d], L.map[1][d]);
+  GJ_HIP(hipGetLastError());
   L.on = false;
   L.cur_map = 0;
   L.nkeys[0] = L.nkeys[1] = 0;
   L.used[0] = L.used[1] = 0;
+}
+
+const uint64_t* lsm_row_offsets(gj_ctx* c, const gj_graph* g, int d, uint64_t& total) {
+  const LsmState& L = g->lsm;
+  total = 0;
+  if (!L.on || !L.nkeys[d]) return nullptr;
+  const std::string tag = d ? "r" : "f";
+  uint64_t nk = L.nkeys[d];
+  uint32_t* lens = (uint32_t*)ws_get(c, "lsm_klen" + tag, (nk + 1) * sizeof(uint32_t));
+  uint64_t* off = (uint64_t*)ws_get(c, "lsm_koff" + tag, (nk + 1) * sizeof(uint64_t));
+  k_key_lens<<<grid_for(nk, kBlock, 1u << 16), kBlock, 0, c->stream>>>(L.keys[d], nk, L.map[L.cur_map][d], lens);
+  GJ_HIP(hipGetLastError());
+  scan_u32_to_u64(c, lens, off, nk);
+  total = read_u64(c, off + nk);
+  return off;
 }
 
 void graph_compact(gj_ctx* c, gj_graph* g) {
@@ -213,9 +252,11 @@ void graph_compact(gj_ctx* c, gj_graph* g) {
   Version& ov = g->ver[g->cur];
   Version& nv = g->ver[s];
   uint64_t m = L.m;
-  // room for the rewritten rows of the updates that follow
-  uint64_t need = m + m / 8 + (1ull << 22);
-  if (need > nv.cap) version_alloc(nv, n, need);
+  // room for the rows appended by the updates that follow: m / 2 + 2^22
+  // entries per direction, reallocated only when less than half of that is
+  // left (a graph that grows would otherwise reallocate at every compaction)
+  uint64_t room = m / 2 + (1ull << 22);
+  if (m + room / 2 > nv.cap) version_alloc(nv, n, m + room);
   uint32_t* deg = (uint32_t*)ws_get(c, "lsm_deg", ((uint64_t)n + 1) * sizeof(uint32_t));
   for (int d = 0; d < 2; ++d) {
     const uint64_t* pm = L.map[L.cur_map][d];
@@ -225,15 +266,17 @@ void graph_compact(gj_ctx* c, gj_graph* g) {
       k_copy_base<<<grid_for(ov.m, kBlock, 1u << 16), kBlock, 0, c->stream>>>(ov.d[d].rp, ov.d[d].col, ov.d[d].row,
                                                                              ov.m, pm, nv.d[d].rp, nv.d[d].col,
                                                                              nv.d[d].row);
-    if (L.nkeys[d])
-      k_copy_rows<<<grid_for(L.nkeys[d] * 64, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
-          L.keys[d], L.nkeys[d], pm, ov.d[d].col, nv.d[d].rp, nv.d[d].col, nv.d[d].row);
+    uint64_t tot = 0;
+    const uint64_t* koff = lsm_row_offsets(c, g, d, tot);
+    if (tot)
+      k_copy_rows<<<grid_for(tot, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+          L.keys[d], koff, L.nkeys[d], tot, pm, ov.d[d].col, nv.d[d].rp, nv.d[d].col, nv.d[d].row);
     GJ_HIP(hipGetLastError());
   }
   nv.m = m;
   version_finish(c, nv, n, false);
   g->cur = s;
-  lsm_reset_maps(c, g);
+  lsm_clear(c, g);
   ++c->lsm_compactions;
   GJ_HIP(hipStreamSynchronize(c->stream));
 }
@@ -251,39 +294,41 @@ struct DirPlan {
   uint64_t nt = 0, tot_new = 0, tot_old = 0, nfresh = 0, ins = 0;
 };
 
-void measure(gj_ctx* c, gj_graph* g, int d, DirPlan& P) {
-  const std::string tag = d ? "r" : "f";
+std::string tag_of(int d) { return d ? "r" : "f"; }
+
+uint32_t* ws32(gj_ctx* c, const char* name, int d, uint64_t cnt) {
+  return (uint32_t*)ws_get(c, std::string("lsm_") + name + tag_of(d), (cnt + 1) * sizeof(uint32_t));
+}
+uint64_t* ws64(gj_ctx* c, const char* name, int d, uint64_t cnt) {
+  return (uint64_t*)ws_get(c, std::string("lsm_") + name + tag_of(d), (cnt + 1) * sizeof(uint64_t));
+}
+
+// runs of dE per touched vertex, and insert counts (phase 1 of the sizing)
+void runs(gj_ctx* c, int d, DirPlan& P) {
   uint64_t k = P.k;
-  auto u32 = [&](const char* name, uint64_t cnt) {
-    return (uint32_t*)ws_get(c, std::string("lsm_") + name + tag, (cnt + 1) * sizeof(uint32_t));
-  };
-  auto u64 = [&](const char* name, uint64_t cnt) {
-    return (uint64_t*)ws_get(c, std::string("lsm_") + name + tag, (cnt + 1) * sizeof(uint64_t));
-  };
-  P.head = u32("head", k);
-  P.insf = u32("insf", k);
-  P.hscan = u64("hscan", k);
-  P.ins_scan = u64("inss", k);
-  unsigned gk = grid_for(k, kBlock, 1u << 16);
-  k_lsm_heads<<<gk, kBlock, 0, c->stream>>>(P.r, P.g, k, P.head, P.insf);
+  P.head = ws32(c, "head", d, k);
+  P.insf = ws32(c, "insf", d, k);
+  P.hscan = ws64(c, "hscan", d, k);
+  P.ins_scan = ws64(c, "inss", d, k);
+  k_lsm_heads<<<grid_for(k, kBlock, 1u << 16), kBlock, 0, c->stream>>>(P.r, P.g, k, P.head, P.insf);
   scan_u32_to_u64(c, P.head, P.hscan, k);
   scan_u32_to_u64(c, P.insf, P.ins_scan, k);
-  uint64_t h[2];
-  read_bytes(c, &h[0], P.hscan + k, sizeof(uint64_t));
-  read_bytes(c, &h[1], P.ins_scan + k, sizeof(uint64_t));
-  P.nt = h[0];
-  P.ins = h[1];
-  uint64_t nt = P.nt;
-  P.tv = u32("tv", nt);
-  P.dlo = u32("dlo", nt + 1);
-  P.olo = u32("olo", nt);
-  P.olen = u32("olen", nt);
-  P.nlen = u32("nlen", nt);
-  P.fresh = u32("fresh", nt);
-  P.noff = u64("noff", nt);
-  P.ooff = u64("ooff", nt);
-  P.fscan = u64("fscan", nt);
-  k_lsm_runs<<<gk, kBlock, 0, c->stream>>>(P.r, k, P.head, P.hscan, P.tv, P.dlo);
+}
+
+// per touched vertex, its current row and its length after the batch
+// (phase 2, once the number of touched vertices nt is known)
+void sizes(gj_ctx* c, gj_graph* g, int d, DirPlan& P) {
+  uint64_t k = P.k, nt = P.nt;
+  P.tv = ws32(c, "tv", d, nt);
+  P.dlo = ws32(c, "dlo", d, nt + 1);
+  P.olo = ws32(c, "olo", d, nt);
+  P.olen = ws32(c, "olen", d, nt);
+  P.nlen = ws32(c, "nlen", d, nt);
+  P.fresh = ws32(c, "fresh", d, nt);
+  P.noff = ws64(c, "noff", d, nt);
+  P.ooff = ws64(c, "ooff", d, nt);
+  P.fscan = ws64(c, "fscan", d, nt);
+  k_lsm_runs<<<grid_for(k, kBlock, 1u << 16), kBlock, 0, c->stream>>>(P.r, k, P.head, P.hscan, P.tv, P.dlo);
   const LsmState& L = g->lsm;
   const uint64_t* pm = L.on ? L.map[L.cur_map][d] : nullptr;
   k_lsm_sizes<<<grid_for(nt, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
@@ -292,23 +337,42 @@ void measure(gj_ctx* c, gj_graph* g, int d, DirPlan& P) {
   scan_u32_to_u64(c, P.nlen, P.noff, nt);
   scan_u32_to_u64(c, P.olen, P.ooff, nt);
   scan_u32_to_u64(c, P.fresh, P.fscan, nt);
-  uint64_t t[3];
-  read_bytes(c, &t[0], P.noff + nt, sizeof(uint64_t));
-  read_bytes(c, &t[1], P.ooff + nt, sizeof(uint64_t));
-  read_bytes(c, &t[2], P.fscan + nt, sizeof(uint64_t));
-  P.tot_new = t[0];
-  P.tot_old = t[1];
-  P.nfresh = t[2];
 }
 
-// whether the rewritten rows of this update fit the current slot's slack
-bool fits(const gj_ctx* c, const gj_graph* g, const DirPlan (&P)[2]) {
+void measure(gj_ctx* c, gj_graph* g, DirPlan (&P)[2]) {
+  for (int d = 0; d < 2; ++d) runs(c, d, P[d]);
+  uint64_t h[4];
+  read_u64s(c, {P[0].hscan + P[0].k, P[0].ins_scan + P[0].k, P[1].hscan + P[1].k, P[1].ins_scan + P[1].k}, h);
+  for (int d = 0; d < 2; ++d) {
+    P[d].nt = h[2 * d];
+    P[d].ins = h[2 * d + 1];
+    sizes(c, g, d, P[d]);
+  }
+  uint64_t t[6];
+  read_u64s(c, {P[0].noff + P[0].nt, P[0].ooff + P[0].nt, P[0].fscan + P[0].nt, P[1].noff + P[1].nt,
+                P[1].ooff + P[1].nt, P[1].fscan + P[1].nt},
+            t);
+  for (int d = 0; d < 2; ++d) {
+    P[d].tot_new = t[3 * d];
+    P[d].tot_old = t[3 * d + 1];
+    P[d].nfresh = t[3 * d + 2];
+  }
+}
+
+// Whether this update appends its rows: they fit the current slot's slack,
+// and they are at most an eighth of the edges (2^16 entries at least) per
+// direction.  A larger batch touches most of the heavy rows, so writing both
+// indexes anew costs little more than appending them, and leaves the slack
+// to the small batches that follow.
+bool appends(const gj_ctx* c, const gj_graph* g, const DirPlan (&P)[2]) {
   const Version& v = g->ver[g->cur];
+  const uint64_t m = g->lsm.on ? g->lsm.m : v.m;
   uint64_t room = v.cap - v.m;
   if (c->lsm_max_patch) room = std::min(room, c->lsm_max_patch);
   for (int d = 0; d < 2; ++d) {
     uint64_t end = g->lsm.used[d] + P[d].tot_new;
     if (end > room || v.m + end > 0xFFFFFFFFull) return false;
+    if (P[d].tot_new > std::max<uint64_t>(m / 8, 1u << 16)) return false;
   }
   return true;
 }
@@ -325,14 +389,8 @@ bool lsm_update(gj_ctx* c, gj_graph* g, const uint32_t* const (&r)[2], const uin
     P[d].g = sg[d];
     P[d].k = k;
   }
-  for (int attempt = 0;; ++attempt) {
-    for (int d = 0; d < 2; ++d) measure(c, g, d, P[d]);
-    if (fits(c, g, P)) break;
-    // the compacted slot that follows has room for m / 8 + 2^22 rows entries
-    // per direction; a batch whose rows exceed even that is rewritten whole
-    if (!g->lsm.on || attempt > 0) return false;
-    graph_compact(c, g);
-  }
+  measure(c, g, P);
+  if (!appends(c, g, P)) return false;
   LsmState& L = g->lsm;
   Version& base = g->ver[g->cur];
   const int nb = 1 - L.cur_map;

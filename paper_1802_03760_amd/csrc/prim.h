@@ -146,18 +146,20 @@ __device__ __forceinline__ bool contains_u32(const uint32_t* __restrict__ a, uin
 // rewrites a row into the tail of the same column array and records it in
 // the version's per-vertex map pm (offset | length << 32; ~0 for a row still
 // at rp[v] .. rp[v + 1]); pm is null when no row is rewritten.
+// The three loads are independent (issued together), so a map costs a
+// lookup no extra latency.
 __device__ __forceinline__ void row_range(const uint32_t* __restrict__ rp, const uint64_t* __restrict__ pm,
                                           uint32_t v, uint32_t& lo, uint32_t& hi) {
+  uint32_t a = rp[v], b = rp[v + 1];
   if (pm) {
     uint64_t e = pm[v];
     if (e != ~0ull) {
-      lo = (uint32_t)e;
-      hi = lo + (uint32_t)(e >> 32);
-      return;
+      a = (uint32_t)e;
+      b = a + (uint32_t)(e >> 32);
     }
   }
-  lo = rp[v];
-  hi = rp[v + 1];
+  lo = a;
+  hi = b;
 }
 
 // p in [lo, hi) with off[p] <= g < off[p+1]; requires off[lo] <= g < off[hi].
@@ -185,6 +187,18 @@ __device__ __forceinline__ uint64_t gallop_segment(const uint64_t* __restrict__ 
   }
   if (hi > n) hi = n;
   return find_segment(off, lo, hi, g);
+}
+
+// For a wave that walks elements [base, base + 64) of a concatenation of n
+// segments with offsets off (off[n] = total, base < total): the segment of
+// element base, found by lane 0 and broadcast; each lane then gallops from
+// it to its own element's segment, so long segments cost one search per
+// wave, not one per element.
+__device__ __forceinline__ uint64_t wave_first_segment(const uint64_t* __restrict__ off, uint64_t n,
+                                                       uint64_t base) {
+  uint64_t t0 = 0;
+  if (lane_id() == 0) t0 = find_segment(off, 0, n, base);
+  return shfl_u64(t0, 0);
 }
 
 }  // namespace gj

@@ -1,6 +1,7 @@
 """GPU parity of log-structured updates (option lsm_updates: touched rows
 appended to the slack of the current version and found through per-vertex
-maps, merged back by compactions; the multi-version index of Sec. 4.3)
+maps; large batches write both indexes anew with the appended rows folded in;
+static readers merge them first; the multi-version index of Sec. 4.3)
 against the CPU oracle's Delta-GJ: every batch's consolidated rows, count
 deltas and per-stage counters, then the compacted index and static counts.
 The edge set each version reads is the same as with whole-index rewrites, so
@@ -95,8 +96,9 @@ def test_lsm_random_batches(gj, names, fused):
 
 
 def test_lsm_forced_compactions(gj):
-    """A small append limit: compactions between batches, and batches whose
-    rows exceed the limit even after one (written as a whole new version)."""
+    """A small append limit: batches that do not fit the rest of it are
+    written as a new version of both indexes read through the maps (the
+    appended rows folded in), and every fifth batch exceeds the limit alone."""
     n = 40
     rng = np.random.default_rng(21)
     src = rng.integers(0, n, 300).astype(np.uint32)
@@ -110,7 +112,7 @@ def test_lsm_forced_compactions(gj):
         b = int(rng.integers(1, 12)) if it % 5 else 120  # every fifth batch too large to append
         bs, bd, bg = random_batch(rng, O, n, b)
         check_step(gj, ctx, G, O, qs_py, qs_gj, bs, bd, bg)
-    assert ctx.get_option("lsm_compactions") > 0
+    assert ctx.get_option("lsm_folds") > 0 and ctx.get_option("lsm_compactions") == 0
     final_checks(gj, ctx, G, O, qs_py, qs_gj)
 
 
@@ -133,8 +135,9 @@ def test_lsm_rmat_stream(gj):
 
 def test_lsm_equals_rewrite_scale14(gj):
     """At R-MAT scale 14 (beyond the oracle's reach per batch): count deltas
-    and counters equal the whole-index rewrite path batch by batch, with a
-    compaction in the middle of the stream; then the two indexes are equal."""
+    and counters equal the whole-index rewrite path batch by batch, with
+    appended rows folded into new versions along the stream; then the two
+    indexes are equal."""
     scale = 14
     src, dst = synth.rmat_draws(scale, seed=3)
     n = 1 << scale
@@ -152,7 +155,7 @@ def test_lsm_equals_rewrite_scale14(gj):
             assert x["stats"]["prefixes"] == y["stats"]["prefixes"], nm
             assert x["stats"]["extensions"] == y["stats"]["extensions"], nm
         assert Gl.info(degrees=False)["edges"] == Gp.info(degrees=False)["edges"]
-    assert cl.get_option("lsm_compactions") >= 1
+    assert cl.get_option("lsm_folds") >= 1
     il, ip = Gl.info(), Gp.info()
     assert (il["edges"], il["max_out"], il["max_in"]) == (ip["edges"], ip["max_out"], ip["max_in"])
     E = il["edges"]
@@ -167,9 +170,9 @@ def test_lsm_equals_rewrite_scale14(gj):
 
 
 def test_lsm_option_off_mid_stream(gj):
-    """Switching lsm_updates off with appended rows pending merges them and
-    continues with whole-index rewrites; a server created on a graph with
-    appended rows starts from the merged index."""
+    """Switching lsm_updates off with appended rows pending folds them into
+    the next whole-index rewrite; a server created on a graph with appended
+    rows starts from the merged index."""
     n = 25
     rng = np.random.default_rng(5)
     src = rng.integers(0, n, 150).astype(np.uint32)
@@ -184,7 +187,7 @@ def test_lsm_option_off_mid_stream(gj):
     ctx.set_option("lsm_updates", 0)
     for it in range(2):
         check_step(gj, ctx, G, O, qs_py, qs_gj, *random_batch(rng, O, n, 15))
-    assert ctx.get_option("lsm_compactions") == 1
+    assert ctx.get_option("lsm_folds") == 1 and ctx.get_option("lsm_compactions") == 0
     ctx.set_option("lsm_updates", 1)
     for it in range(2):
         check_step(gj, ctx, G, O, qs_py, qs_gj, *random_batch(rng, O, n, 15))
@@ -194,4 +197,4 @@ def test_lsm_option_off_mid_stream(gj):
         assert r["count"] == oracle.run(O, Q.TRIANGLE)["matches"]
     finally:
         srv.close()
-    assert ctx.get_option("lsm_compactions") == 2
+    assert ctx.get_option("lsm_compactions") == 1
