@@ -111,12 +111,12 @@ def batched_vs_plain(gj, ctx, G, nreq, seed, log, max_width=1000):
 
 
 def symmetry_breaking(gj, ctx, scale, log, full=False):
-    """Undirected triangle and 4-clique counts on R-MAT (seed 0) read as an
-    undirected graph, three ways (Sec. 5.4): the plain query over the
-    symmetric graph (each clique |Aut| times), the query with the inequalities
-    a1 < a2 < ... over it, and the plain query over the degree-ordered graph.
-    The plain symmetric 4-clique count runs only with `full` (minutes at
-    scale 22)."""
+    """Undirected triangle, 4-clique and 5-clique counts on R-MAT (seed 0)
+    read as an undirected graph, three ways (Sec. 5.4): the plain query over
+    the symmetric graph (each clique |Aut| times), the query with the
+    inequalities a1 < a2 < ... over it, and the plain query over the
+    degree-ordered graph.  The plain symmetric 4- and 5-clique counts and the
+    5-clique with inequalities run only with `full` (minutes at scale 22)."""
     import synth
     src, dst = synth.rmat_draws(scale, seed=0)
     n = 1 << scale
@@ -142,16 +142,20 @@ def symmetry_breaking(gj, ctx, scale, log, full=False):
         ext = sum(r["extensions"])
         return {"matches": r["matches"], "extensions": ext, "s": dt, "extensions_per_s": ext / dt}
 
-    for name, q, aut in (("triangle", tri, 6), ("4-clique", k4, 24)):
+    k5 = (5, [(i, j) for i in range(5) for j in range(i + 1, 5)], [0, 1, 2, 3, 4])
+    for name, q, aut in (("triangle", tri, 6), ("4-clique", k4, 24), ("5-clique", k5, 120)):
         less = [(i, i + 1) for i in range(q[0] - 1)]
-        res = {"oriented": timed(Go, q), "undirected_less": timed(Gu, q, less)}
+        res = {"oriented": timed(Go, q)}
+        if name != "5-clique" or full:
+            res["undirected_less"] = timed(Gu, q, less)
+            assert res["undirected_less"]["matches"] == res["oriented"]["matches"]
         if name == "triangle" or full:
             res["undirected_plain"] = timed(Gu, q)
             assert res["undirected_plain"]["matches"] == aut * res["oriented"]["matches"]
-        assert res["undirected_less"]["matches"] == res["oriented"]["matches"]
         out[name] = res
-        log("symmetry breaking, %s at scale %d: %d undirected; oriented %.3f s, inequalities %.3f s%s"
-            % (name, scale, res["oriented"]["matches"], res["oriented"]["s"], res["undirected_less"]["s"],
+        log("symmetry breaking, %s at scale %d: %d undirected; oriented %.3f s%s%s"
+            % (name, scale, res["oriented"]["matches"], res["oriented"]["s"],
+               ", inequalities %.3f s" % res["undirected_less"]["s"] if "undirected_less" in res else "",
                ", plain symmetric %.3f s" % res["undirected_plain"]["s"] if "undirected_plain" in res else ""))
     Gu.close()
     Go.close()

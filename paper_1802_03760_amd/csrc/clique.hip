@@ -364,6 +364,239 @@ void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4]
   }
 }
 
+// ---------------------------------------------------------------- transitive 5-clique
+// The transitive 5-clique binds a2 from L = out(a0) & out(a1), a3 from
+// L & out(a2) and a4 from L & out(a2) & out(a3) (Sec. 2.2).  Per seed edge a
+// wave keeps L (sorted) in LDS together with L's adjacency as bit masks over
+// L's positions, row i holding L & out(L[i]), built with the 4-clique
+// kernel's probes (whichever side is smaller).  The matches of the edge are
+// then the sum over a2 = L[i] and a3 = L[j] in row i of |row i & row j|,
+// popcounts of a few words.  Inequalities between vertex ids become ranges
+// of positions in the sorted L.  Counters are the depth-first evaluation's,
+// as for the 4-clique; edges with |L| > kC5Cap go to the depth-first path.
+constexpr int kC5Waves = 4;
+constexpr uint32_t kC5Cap = 256;           // entries of L per wave
+constexpr uint32_t kC5Words = kC5Cap / 64;  // mask words per row at most
+
+struct EdgeIneq5 {
+  uint32_t above[5], below[5];
+};
+
+// positions of L (sorted, distinct, n entries) that a value bound at
+// position p may take: [lo, hi), from the inequalities against the seed
+// values (lt / le: how many entries of L are below / at most x0 and x1) and
+// against the values at positions 2 and 3 (L[i2], L[i3])
+__device__ __forceinline__ void ineq_range(const EdgeIneq5& q, int p, const uint32_t (&lt)[2],
+                                           const uint32_t (&le)[2], uint32_t i2, uint32_t i3, uint32_t n,
+                                           uint32_t& lo, uint32_t& hi) {
+  lo = 0;
+  hi = n;
+  const uint32_t a = q.above[p], b = q.below[p];
+  if (!(a | b)) return;
+  for (int c = 0; c < 2; ++c) {
+    if ((a >> c) & 1) lo = le[c] > lo ? le[c] : lo;
+    if ((b >> c) & 1) hi = lt[c] < hi ? lt[c] : hi;
+  }
+  if (a & 4) lo = i2 + 1 > lo ? i2 + 1 : lo;
+  if (b & 4) hi = i2 < hi ? i2 : hi;
+  if (a & 8) lo = i3 + 1 > lo ? i3 + 1 : lo;
+  if (b & 8) hi = i3 < hi ? i3 : hi;
+}
+
+// the bits of mask word w (positions 64w .. 64w + 63) inside [lo, hi)
+__device__ __forceinline__ uint64_t range_bits(uint32_t w, uint32_t lo, uint32_t hi) {
+  const uint32_t base = w * 64;
+  if (lo >= hi || hi <= base || lo >= base + 64) return 0;
+  const uint32_t a = lo > base ? lo - base : 0, b = hi < base + 64 ? hi - base : 64;
+  uint64_t m = b == 64 ? ~0ull : ((1ull << b) - 1);
+  return m & ~((1ull << a) - 1);
+}
+
+__device__ __forceinline__ uint32_t lds_lower(const uint32_t* a, uint32_t n, uint32_t x) {
+  uint32_t lo = 0;
+  while (n > 0) {
+    uint32_t half = n >> 1;
+    if (a[lo + half] < x) {
+      lo += half + 1;
+      n -= half + 1;
+    } else {
+      n = half;
+    }
+  }
+  return lo;
+}
+
+__global__ void __launch_bounds__(kC5Waves * 64) k_clique5(const uint32_t* __restrict__ rp,
+                                                           const uint32_t* __restrict__ col,
+                                                           const uint32_t* __restrict__ row, uint64_t m,
+                                                           unsigned long long* __restrict__ claim,
+                                                           uint32_t* __restrict__ ovf,
+                                                           unsigned long long* __restrict__ acc, EdgeIneq5 iq) {
+  __shared__ uint32_t Ls[kC5Waves][kC5Cap];
+  __shared__ uint32_t Ds[kC5Waves][kC5Cap];
+  __shared__ uint32_t Ws[kC5Waves][kC5Cap + 1];
+  __shared__ unsigned long long Ms[kC5Waves][kC5Cap * kC5Words];
+  const int lane = lane_id();
+  uint32_t* S = Ls[wave_id()];
+  uint32_t* D = Ds[wave_id()];
+  uint32_t* Wp = Ws[wave_id()];
+  unsigned long long* M = Ms[wave_id()];
+  uint64_t matches = 0, pre2 = 0, ext2 = 0, pre3 = 0, ext3 = 0, pre4 = 0, ext4 = 0;
+  for (;;) {
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(claim, (unsigned long long)kCqChunk);
+    base = shfl_u64(base, 0);
+    if (base >= m) break;
+    uint64_t end = base + kCqChunk < m ? base + kCqChunk : m;
+    for (uint64_t e = base; e < end; ++e) {
+      const uint32_t x0 = row[e], x1 = col[e];
+      if (((iq.above[1] & 1) && !(x1 > x0)) || ((iq.below[1] & 1) && !(x1 < x0))) continue;
+      const uint32_t b0 = rp[x0], d0 = rp[x0 + 1] - b0, b1 = rp[x1], d1 = rp[x1 + 1] - b1;
+      const uint32_t d01 = d0 < d1 ? d0 : d1;
+      wave_lds_sync();  // the previous edge's reads are done
+      // L = out(x0) & out(x1), in order, from the shorter list
+      uint32_t nS = 0;
+      {
+        const uint32_t sb = d0 <= d1 ? b0 : b1, gb = d0 <= d1 ? b1 : b0, gd = d0 <= d1 ? d1 : d0;
+        for (uint32_t t = 0; t < d01; t += 64) {
+          uint32_t i = t + lane;
+          uint32_t x = 0;
+          bool hit = false;
+          if (i < d01) {
+            x = col[sb + i];
+            hit = contains_u32(col, gb, gb + gd, x);
+          }
+          uint64_t bal = __ballot(hit);
+          uint32_t pos = nS + (uint32_t)__popcll(bal & lanemask_lt());
+          if (hit && pos < kC5Cap) S[pos] = x;
+          nS += (uint32_t)__popcll(bal);
+        }
+      }
+      if (nS > kC5Cap) {  // does not fit: the depth-first path takes this seed
+        if (lane == 0) ovf[atomicAdd(claim + 1, 1ull)] = (uint32_t)e;
+        continue;
+      }
+      if (lane == 0) {
+        ext2 += d01;
+        pre2 += 1;
+      }
+      if (nS == 0) continue;
+      wave_lds_sync();
+      const uint32_t W = (nS + 63) >> 6;
+      uint32_t lt[2], le[2];
+      lt[0] = lds_lower(S, nS, x0);
+      le[0] = lds_lower(S, nS, x0 + 1);  // ids are below 2^32 - 1
+      lt[1] = lds_lower(S, nS, x1);
+      le[1] = lds_lower(S, nS, x1 + 1);
+      uint32_t lo2, hi2;
+      ineq_range(iq, 2, lt, le, 0, 0, nS, lo2, hi2);
+      for (uint32_t i = lane; i < nS * W; i += 64) M[i] = 0;
+      // degrees of L, and the probes of row i: min(d(L[i]), |L|).  Every row
+      // is built: L[i] may serve as a3 even where it fails a2's inequalities
+      uint32_t run = 0;
+      for (uint32_t t = 0; t < nS; t += 64) {
+        uint32_t i = t + lane;
+        uint32_t w = 0;
+        if (i < nS) {
+          uint32_t a2 = S[i];
+          uint32_t d2 = rp[a2 + 1] - rp[a2];
+          D[i] = d2;
+          w = d2 < nS ? d2 : nS;
+          if (i >= lo2 && i < hi2) {
+            ext3 += d2 < d01 ? d2 : d01;
+            pre3 += 1;
+          }
+        }
+        uint32_t incl = wave_incl_scan(w);
+        if (i < nS) Wp[i] = run + incl - w;
+        run += __shfl(incl, 63, 64);
+      }
+      wave_lds_sync();
+      if (lane == 0) Wp[nS] = run;
+      wave_lds_sync();
+      // row i of the masks: bit j set when L[j] is in out(L[i])
+      for (uint32_t q0 = 0; q0 < run; q0 += 64) {
+        uint32_t q = q0 + lane;
+        if (q < run) {
+          uint32_t i = lds_owner(Wp, nS, q);  // i < nS: Wp[nS] = run > q
+          uint32_t t = q - Wp[i];
+          uint32_t a2 = S[i], d2 = D[i], b2 = rp[a2];
+          uint32_t j;
+          bool found;
+          if (d2 < nS) {  // t < d2: out(a2)'s values against L
+            uint32_t a3 = col[b2 + t];
+            j = lds_lower(S, nS, a3);
+            found = j < nS && S[j] == a3;
+          } else {  // t < nS: L's values against out(a2)
+            j = t;
+            found = contains_u32(col, b2, b2 + d2, S[t]);
+          }
+          if (found) atomicOr(&M[i * W + (j >> 6)], 1ull << (j & 63));
+        }
+      }
+      wave_lds_sync();
+      // a lane per a2: its a3 in row i, then the a4 of both rows
+      for (uint32_t t = 0; t < nS; t += 64) {
+        uint32_t i = t + lane;
+        if (i >= nS || i < lo2 || i >= hi2) continue;
+        const uint32_t d2 = D[i];
+        const uint32_t m012 = d2 < d01 ? d2 : d01;
+        uint32_t lo3, hi3;
+        ineq_range(iq, 3, lt, le, i, 0, nS, lo3, hi3);
+        for (uint32_t w = 0; w < W; ++w) {
+          uint64_t bits = M[i * W + w] & range_bits(w, lo3, hi3);
+          while (bits) {
+            const uint32_t j = w * 64 + (uint32_t)__builtin_ctzll(bits);
+            bits &= bits - 1;
+            pre4 += 1;
+            ext4 += D[j] < m012 ? D[j] : m012;
+            uint32_t lo4, hi4;
+            ineq_range(iq, 4, lt, le, i, j, nS, lo4, hi4);
+            for (uint32_t w2 = 0; w2 < W; ++w2)
+              matches += (uint64_t)__popcll(M[i * W + w2] & M[j * W + w2] & range_bits(w2, lo4, hi4));
+          }
+        }
+      }
+    }
+  }
+  uint64_t v[7] = {matches, pre2, ext2, pre3, ext3, pre4, ext4};
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    uint64_t t = wave_sum(v[i]);
+    if (lane == 0 && t) atomicAdd(acc + i, (unsigned long long)t);
+  }
+}
+
+void clique5_count(gj_ctx* c, const Version& v, const uint32_t above[5], const uint32_t below[5],
+                   KernelTimer& timer, uint64_t out[7], uint32_t*& x0, uint32_t*& x1, uint64_t& n_left) {
+  const CsrDir& d = v.d[0];
+  // ctr: [0] seed claim, [1] overflow count, [2, 9) counters
+  unsigned long long* ctr = (unsigned long long*)ws_get(c, "c5_ctr", 9 * sizeof(unsigned long long));
+  uint32_t* ovf = (uint32_t*)ws_get(c, "c5_ovf", (v.m + 1) * sizeof(uint32_t));
+  GJ_HIP(hipMemsetAsync(ctr, 0, 9 * sizeof(unsigned long long), c->stream));
+  EdgeIneq5 iq;
+  for (int j = 0; j < 5; ++j) {
+    iq.above[j] = above[j];
+    iq.below[j] = below[j];
+  }
+  unsigned grid = (unsigned)c->num_cus * 3;  // 3 workgroups of 4 waves per CU (44 KiB of LDS each)
+  timer.start();
+  if (v.m) k_clique5<<<grid, kC5Waves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
+  timer.stop();
+  GJ_HIP(hipGetLastError());
+  unsigned long long h[9];
+  read_bytes(c, h, ctr, sizeof(h));
+  n_left = h[1];
+  for (int i = 0; i < 7; ++i) out[i] = h[2 + i];
+  x0 = x1 = nullptr;
+  if (n_left) {
+    x0 = (uint32_t*)ws_get(c, "c5_x0", n_left * sizeof(uint32_t));
+    x1 = (uint32_t*)ws_get(c, "c5_x1", n_left * sizeof(uint32_t));
+    k_gather_seeds<<<grid_for(n_left, kBlock, 1u << 14), kBlock, 0, c->stream>>>(ovf, n_left, d.row, d.col, x0, x1);
+    GJ_HIP(hipGetLastError());
+  }
+}
+
 // ---------------------------------------------------------------- diamond by 2-path counts
 // The diamond's matches from a0 are the pairs (a1, a2) of out(a0) with a
 // common out-neighbour a3, counted per a3: with k(a3) the number of 2-paths

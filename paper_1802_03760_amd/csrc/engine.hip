@@ -410,6 +410,36 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
     if (out_of(2, 0b011) && out_of(3, 0b111)) shape = 0;       // a2: a0, a1; a3: a0, a1, a2
     else if (out_of(2, 0b001) && out_of(3, 0b110)) shape = 1;  // a2: a0; a3: a1, a2
   }
+  // transitive 5-clique: every atom out of an earlier attribute
+  if (!collect && c->strategy != 1 && P.m == 5 && P.filters.empty() && !P.ntri && P.seed_fwd && lo == 0 &&
+      hi == v.m && out_of(2, 0b0011) && out_of(3, 0b0111) && out_of(4, 0b1111)) {
+    KernelTimer timer(c);
+    uint64_t o[7];
+    uint32_t *x0 = nullptr, *x1 = nullptr;
+    uint64_t left = 0;
+    clique5_count(c, v, P.above.data(), P.below.data(), timer, o, x0, x1, left);
+    gj_stats s{};
+    uint64_t mrest = 0;
+    if (left) {  // seeds whose common neighbourhood outgrew LDS
+      Runner R(c, P, V, false, false, std::max<uint64_t>(1, std::min<uint64_t>(c->seed_chunk, left)));
+      R.seed(x0, x1, nullptr, left);
+      int64_t ws = 0;
+      R.finish(mrest, ws);
+      s = R.st;
+    }
+    s.prefixes[2] += o[1];
+    s.extensions[2] += o[2];
+    s.prefixes[3] += o[3];
+    s.extensions[3] += o[4];
+    s.prefixes[4] += o[5];
+    s.extensions[4] += o[6];
+    s.matches = mrest + o[0];
+    s.prefixes[5] = s.matches;
+    s.kernel_ms += timer.total_ms();
+    s.kernel_launches += timer.launches();
+    *st = s;
+    return;
+  }
   // 4-cycle: a2 from out(a1), a3 from out(a2) and in(a0)
   auto is_bind = [&](const BindH& b, int col, int dir) { return b.col == col && b.dir == dir && b.col2 < 0; };
   bool cycle4 = !collect && c->strategy != 1 && P.m == 4 && P.filters.empty() && !P.has_ineq() && !P.ntri &&

@@ -220,3 +220,57 @@ def test_clique4_edge_grouped_kernel(gj, ctx):
             r = gj.count(cc, GG, gj.Query(cc, *q))
             assert (r["matches"], r["prefixes"], r["extensions"]) == \
                 (ref["matches"], ref["prefixes"], ref["extensions"]), q
+
+
+def test_clique5_edge_grouped_kernel(gj, ctx):
+    """Full transitive 5-clique counts run grouped by seed edge, with the
+    common neighbourhood's adjacency as bit masks in LDS; seeds whose common
+    neighbourhood exceeds 256 entries finish on the depth-first path.  Hub
+    pairs with 200 and 300 common neighbours (each joined to the next two,
+    so that 5-cliques exist) fall on both sides of that limit, over an R-MAT
+    background.  Then the degree-ordered form, random inequality sets, and
+    the symmetry-breaking set on the undirected form.  Counts and every
+    counter equal the oracle's and the generic path's (strategy 1)."""
+    from tests.test_gpu_sym import rand_less
+    s, d = [], []
+    base = 0
+    for k in (200, 300):
+        h0, h1 = base, base + 1
+        common = np.arange(base + 2, base + 2 + k, dtype=np.uint32)
+        s += [np.array([h0], np.uint32), np.full(k, h0, np.uint32), np.full(k, h1, np.uint32),
+              common[:-1], common[:-2]]
+        d += [np.array([h1], np.uint32), common, common, common[1:], common[2:]]
+        base += k + 2
+    rs, rd = synth.rmat_draws(11, seed=45)
+    s.append(rs + base)
+    d.append(rd + base)
+    src, dst = np.concatenate(s), np.concatenate(d)
+    n = base + (1 << 11)
+    c1 = gj.Context(0)
+    c1.set_option("strategy", 1)
+
+    def check(G, G1, O, q):
+        ref = oracle.run(O, q, threads=8)
+        for cc, GG in ((ctx, G), (c1, G1)):
+            r = gj.count(cc, GG, gj.Query(cc, *q))
+            assert (r["matches"], r["prefixes"], r["extensions"]) == \
+                (ref["matches"], ref["prefixes"], ref["extensions"]), q
+        return ref
+
+    G, G1, O = gj.Graph(ctx, src, dst, n), gj.Graph(c1, src, dst, n), oracle.Graph(n, src, dst)
+    ref = check(G, G1, O, Q.CLIQUE5)
+    assert ref["matches"] >= 198 + 298
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        check(G, G1, O, Q.with_less(Q.CLIQUE5, rand_less(rng, 5)))
+    # degree-ordered: the oracle renames the same way
+    Gd, Gd1 = gj.Graph(ctx, src, dst, n, degree_order=True), gj.Graph(c1, src, dst, n, degree_order=True)
+    ds, dd, _ = oracle.relabel_by_degree(n, src, dst)
+    check(Gd, Gd1, oracle.Graph(n, ds, dd), Q.CLIQUE5)
+    # undirected with the symmetry-breaking chain a0 < a1 < a2 < a3 < a4
+    u, v = oracle.symmetric_edges(n, src, dst)
+    Gu, Gu1, Ou = (gj.Graph(ctx, src, dst, n, undirected=True), gj.Graph(c1, src, dst, n, undirected=True),
+                   oracle.Graph(n, u, v))
+    less, aut = Q.SYM_LESS["clique5"]
+    refu = check(Gu, Gu1, Ou, Q.with_less(Q.CLIQUE5, less))
+    assert gj.count(ctx, Gu, gj.Query(ctx, *Q.CLIQUE5))["matches"] == aut * refu["matches"]
