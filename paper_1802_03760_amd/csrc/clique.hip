@@ -373,7 +373,8 @@ void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4]
 // then the sum over a2 = L[i] and a3 = L[j] in row i of |row i & row j|,
 // popcounts of a few words.  Inequalities between vertex ids become ranges
 // of positions in the sorted L.  Counters are the depth-first evaluation's,
-// as for the 4-clique; edges with |L| > kC5Cap go to the depth-first path.
+// as for the 4-clique; edges with |L| > kC5Cap take a second pass with a
+// workgroup per edge (k_clique5_wg), and beyond that the depth-first path.
 constexpr int kC5Waves = 4;
 constexpr uint32_t kC5Cap = 256;           // entries of L per wave
 constexpr uint32_t kC5Words = kC5Cap / 64;  // mask words per row at most
@@ -567,13 +568,148 @@ __global__ void __launch_bounds__(kC5Waves * 64) k_clique5(const uint32_t* __res
   }
 }
 
+// The seeds whose L outgrew a wave's share, again with a whole workgroup per
+// seed: up to 704 entries of L (11 mask words per row, 70 KiB of LDS),
+// compaction and offsets by workgroup scans, the probes over 256 lanes.
+// Seeds beyond that are appended to ovf for the depth-first path.
+constexpr uint32_t kC5CapWg = 704;
+constexpr uint32_t kC5WordsWg = (kC5CapWg + 63) / 64;
+
+__global__ void __launch_bounds__(kBlock) k_clique5_wg(const uint32_t* __restrict__ rp,
+                                                       const uint32_t* __restrict__ col,
+                                                       const uint32_t* __restrict__ row,
+                                                       const uint32_t* __restrict__ ids, uint64_t m,
+                                                       unsigned long long* __restrict__ claim,
+                                                       uint32_t* __restrict__ ovf,
+                                                       unsigned long long* __restrict__ acc, EdgeIneq5 iq) {
+  __shared__ uint32_t S[kC5CapWg];
+  __shared__ uint32_t D[kC5CapWg];
+  __shared__ uint32_t Wp[kC5CapWg + 1];
+  __shared__ unsigned long long M[kC5CapWg * kC5WordsWg];
+  __shared__ unsigned long long next;
+  const uint32_t tid = threadIdx.x;
+  uint64_t matches = 0, pre2 = 0, ext2 = 0, pre3 = 0, ext3 = 0, pre4 = 0, ext4 = 0;
+  for (;;) {
+    __syncthreads();  // the previous seed's reads are done
+    if (tid == 0) next = atomicAdd(claim, 1ull);
+    __syncthreads();
+    const unsigned long long k = next;
+    if (k >= m) break;
+    const uint64_t e = ids[k];
+    const uint32_t x0 = row[e], x1 = col[e];
+    if (((iq.above[1] & 1) && !(x1 > x0)) || ((iq.below[1] & 1) && !(x1 < x0))) continue;
+    const uint32_t b0 = rp[x0], d0 = rp[x0 + 1] - b0, b1 = rp[x1], d1 = rp[x1 + 1] - b1;
+    const uint32_t d01 = d0 < d1 ? d0 : d1;
+    uint32_t nS = 0;
+    {
+      const uint32_t sb = d0 <= d1 ? b0 : b1, gb = d0 <= d1 ? b1 : b0, gd = d0 <= d1 ? d1 : d0;
+      for (uint32_t t = 0; t < d01; t += kBlock) {
+        uint32_t i = t + tid;
+        uint32_t x = 0, hit = 0;
+        if (i < d01) {
+          x = col[sb + i];
+          hit = contains_u32(col, gb, gb + gd, x) ? 1u : 0u;
+        }
+        uint32_t tot = 0;
+        uint32_t pos = nS + block_excl_scan<kBlock>(hit, tot);
+        if (hit && pos < kC5CapWg) S[pos] = x;
+        nS += tot;
+      }
+    }
+    if (nS > kC5CapWg) {
+      if (tid == 0) ovf[atomicAdd(claim + 1, 1ull)] = (uint32_t)e;
+      continue;
+    }
+    if (tid == 0) {
+      ext2 += d01;
+      pre2 += 1;
+    }
+    if (nS == 0) continue;
+    __syncthreads();  // L is complete
+    const uint32_t W = (nS + 63) >> 6;
+    uint32_t lt[2], le[2];
+    lt[0] = lds_lower(S, nS, x0);
+    le[0] = lds_lower(S, nS, x0 + 1);
+    lt[1] = lds_lower(S, nS, x1);
+    le[1] = lds_lower(S, nS, x1 + 1);
+    uint32_t lo2, hi2;
+    ineq_range(iq, 2, lt, le, 0, 0, nS, lo2, hi2);
+    for (uint32_t i = tid; i < nS * W; i += kBlock) M[i] = 0;
+    uint32_t run = 0;
+    for (uint32_t t = 0; t < nS; t += kBlock) {
+      uint32_t i = t + tid;
+      uint32_t w = 0;
+      if (i < nS) {
+        uint32_t a2 = S[i];
+        uint32_t d2 = rp[a2 + 1] - rp[a2];
+        D[i] = d2;
+        w = d2 < nS ? d2 : nS;
+        if (i >= lo2 && i < hi2) {
+          ext3 += d2 < d01 ? d2 : d01;
+          pre3 += 1;
+        }
+      }
+      uint32_t tot = 0;
+      uint32_t ex = block_excl_scan<kBlock>(w, tot);
+      if (i < nS) Wp[i] = run + ex;
+      run += tot;
+    }
+    if (tid == 0) Wp[nS] = run;
+    __syncthreads();  // masks cleared, degrees and offsets written
+    for (uint32_t q = tid; q < run; q += kBlock) {
+      uint32_t i = lds_owner(Wp, nS, q);  // i < nS: Wp[nS] = run > q
+      uint32_t t = q - Wp[i];
+      uint32_t a2 = S[i], d2 = D[i], b2 = rp[a2];
+      uint32_t j;
+      bool found;
+      if (d2 < nS) {
+        uint32_t a3 = col[b2 + t];
+        j = lds_lower(S, nS, a3);
+        found = j < nS && S[j] == a3;
+      } else {
+        j = t;
+        found = contains_u32(col, b2, b2 + d2, S[t]);
+      }
+      if (found) atomicOr(&M[i * W + (j >> 6)], 1ull << (j & 63));
+    }
+    __syncthreads();  // masks complete
+    for (uint32_t i = tid; i < nS; i += kBlock) {
+      if (i < lo2 || i >= hi2) continue;
+      const uint32_t d2 = D[i];
+      const uint32_t m012 = d2 < d01 ? d2 : d01;
+      uint32_t lo3, hi3;
+      ineq_range(iq, 3, lt, le, i, 0, nS, lo3, hi3);
+      for (uint32_t w = 0; w < W; ++w) {
+        uint64_t bits = M[i * W + w] & range_bits(w, lo3, hi3);
+        while (bits) {
+          const uint32_t j = w * 64 + (uint32_t)__builtin_ctzll(bits);
+          bits &= bits - 1;
+          pre4 += 1;
+          ext4 += D[j] < m012 ? D[j] : m012;
+          uint32_t lo4, hi4;
+          ineq_range(iq, 4, lt, le, i, j, nS, lo4, hi4);
+          for (uint32_t w2 = 0; w2 < W; ++w2)
+            matches += (uint64_t)__popcll(M[i * W + w2] & M[j * W + w2] & range_bits(w2, lo4, hi4));
+        }
+      }
+    }
+  }
+  uint64_t v[7] = {matches, pre2, ext2, pre3, ext3, pre4, ext4};
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+    uint64_t t = block_sum<kBlock>(v[i]);
+    if (tid == 0 && t) atomicAdd(acc + i, (unsigned long long)t);
+  }
+}
+
 void clique5_count(gj_ctx* c, const Version& v, const uint32_t above[5], const uint32_t below[5],
                    KernelTimer& timer, uint64_t out[7], uint32_t*& x0, uint32_t*& x1, uint64_t& n_left) {
   const CsrDir& d = v.d[0];
-  // ctr: [0] seed claim, [1] overflow count, [2, 9) counters
-  unsigned long long* ctr = (unsigned long long*)ws_get(c, "c5_ctr", 9 * sizeof(unsigned long long));
+  // ctr: [0] seed claim, [1] overflow count, [2, 9) counters, [9] second-pass
+  // claim, [10] its overflow count
+  unsigned long long* ctr = (unsigned long long*)ws_get(c, "c5_ctr", 11 * sizeof(unsigned long long));
   uint32_t* ovf = (uint32_t*)ws_get(c, "c5_ovf", (v.m + 1) * sizeof(uint32_t));
-  GJ_HIP(hipMemsetAsync(ctr, 0, 9 * sizeof(unsigned long long), c->stream));
+  GJ_HIP(hipMemsetAsync(ctr, 0, 11 * sizeof(unsigned long long), c->stream));
   EdgeIneq5 iq;
   for (int j = 0; j < 5; ++j) {
     iq.above[j] = above[j];
@@ -584,15 +720,27 @@ void clique5_count(gj_ctx* c, const Version& v, const uint32_t above[5], const u
   if (v.m) k_clique5<<<grid, kC5Waves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
   timer.stop();
   GJ_HIP(hipGetLastError());
-  unsigned long long h[9];
+  unsigned long long n1 = 0;
+  read_bytes(c, &n1, ctr + 1, sizeof(n1));
+  const uint32_t* left = ovf;
+  if (n1) {  // larger L: a workgroup per seed
+    uint32_t* ovf2 = (uint32_t*)ws_get(c, "c5_ovf2", (n1 + 1) * sizeof(uint32_t));
+    unsigned grid2 = (unsigned)c->num_cus * 2;  // 2 workgroups per CU (70 KiB of LDS each)
+    timer.start();
+    k_clique5_wg<<<grid2, kBlock, 0, c->stream>>>(d.rp, d.col, d.row, ovf, n1, ctr + 9, ovf2, ctr + 2, iq);
+    timer.stop();
+    GJ_HIP(hipGetLastError());
+    left = ovf2;
+  }
+  unsigned long long h[11];
   read_bytes(c, h, ctr, sizeof(h));
-  n_left = h[1];
+  n_left = n1 ? h[10] : h[1];
   for (int i = 0; i < 7; ++i) out[i] = h[2 + i];
   x0 = x1 = nullptr;
   if (n_left) {
     x0 = (uint32_t*)ws_get(c, "c5_x0", n_left * sizeof(uint32_t));
     x1 = (uint32_t*)ws_get(c, "c5_x1", n_left * sizeof(uint32_t));
-    k_gather_seeds<<<grid_for(n_left, kBlock, 1u << 14), kBlock, 0, c->stream>>>(ovf, n_left, d.row, d.col, x0, x1);
+    k_gather_seeds<<<grid_for(n_left, kBlock, 1u << 14), kBlock, 0, c->stream>>>(left, n_left, d.row, d.col, x0, x1);
     GJ_HIP(hipGetLastError());
   }
 }

@@ -224,17 +224,17 @@ def test_clique4_edge_grouped_kernel(gj, ctx):
 
 def test_clique5_edge_grouped_kernel(gj, ctx):
     """Full transitive 5-clique counts run grouped by seed edge, with the
-    common neighbourhood's adjacency as bit masks in LDS; seeds whose common
-    neighbourhood exceeds 256 entries finish on the depth-first path.  Hub
-    pairs with 200 and 300 common neighbours (each joined to the next two,
-    so that 5-cliques exist) fall on both sides of that limit, over an R-MAT
+    common neighbourhood's adjacency as bit masks in LDS: a wave per seed up
+    to 256 common neighbours, a workgroup up to 704, the depth-first path
+    beyond.  Hub pairs with 200, 300 and 720 common neighbours (each joined
+    to the next two, so that 5-cliques exist) take the three, over an R-MAT
     background.  Then the degree-ordered form, random inequality sets, and
     the symmetry-breaking set on the undirected form.  Counts and every
     counter equal the oracle's and the generic path's (strategy 1)."""
     from tests.test_gpu_sym import rand_less
     s, d = [], []
     base = 0
-    for k in (200, 300):
+    for k in (200, 300, 720):
         h0, h1 = base, base + 1
         common = np.arange(base + 2, base + 2 + k, dtype=np.uint32)
         s += [np.array([h0], np.uint32), np.full(k, h0, np.uint32), np.full(k, h1, np.uint32),
@@ -259,7 +259,7 @@ def test_clique5_edge_grouped_kernel(gj, ctx):
 
     G, G1, O = gj.Graph(ctx, src, dst, n), gj.Graph(c1, src, dst, n), oracle.Graph(n, src, dst)
     ref = check(G, G1, O, Q.CLIQUE5)
-    assert ref["matches"] >= 198 + 298
+    assert ref["matches"] >= 198 + 298 + 718
     rng = np.random.default_rng(5)
     for _ in range(3):
         check(G, G1, O, Q.with_less(Q.CLIQUE5, rand_less(rng, 5)))
