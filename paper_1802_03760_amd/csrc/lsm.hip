@@ -195,16 +195,22 @@ __global__ void __launch_bounds__(kBlock) k_copy_rows(const uint32_t* __restrict
 }
 
 // ---------------------------------------------------------------- host
+// allocates whatever an earlier call did not (one that failed part-way
+// leaves the rest null, never a half-initialised map)
 static void lsm_alloc(gj_ctx* c, gj_graph* g) {
   LsmState& L = g->lsm;
-  if (L.map[0][0]) return;
   uint64_t bytes = (uint64_t)g->n * sizeof(uint64_t);
   for (int b = 0; b < 2; ++b)
     for (int d = 0; d < 2; ++d) {
-      L.map[b][d] = (uint64_t*)dev_alloc(bytes);
-      GJ_HIP(hipMemsetAsync(L.map[b][d], 0xFF, bytes, c->stream));
+      if (L.map[b][d]) continue;
+      uint64_t* p = (uint64_t*)dev_alloc(bytes);
+      hipError_t e = hipMemsetAsync(p, 0xFF, bytes, c->stream);
+      if (e != hipSuccess) dev_free(p);
+      GJ_HIP(e);
+      L.map[b][d] = p;
     }
-  for (int d = 0; d < 2; ++d) L.keys[d] = (uint32_t*)dev_alloc((uint64_t)g->n * sizeof(uint32_t));
+  for (int d = 0; d < 2; ++d)
+    if (!L.keys[d]) L.keys[d] = (uint32_t*)dev_alloc((uint64_t)g->n * sizeof(uint32_t));
 }
 
 void lsm_free(gj_graph* g) {
