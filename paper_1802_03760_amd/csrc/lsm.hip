@@ -365,6 +365,30 @@ void measure(gj_ctx* c, gj_graph* g, DirPlan (&P)[2]) {
   }
 }
 
+// the rows of both directions appended, and the next version's map written
+void write_rows(gj_ctx* c, gj_graph* g, const DirPlan (&P)[2], uint64_t k, LsmCommit& commit) {
+  LsmState& L = g->lsm;
+  Version& base = g->ver[g->cur];
+  const int nb = 1 - L.cur_map;
+  for (int d = 0; d < 2; ++d) {
+    const DirPlan& p = P[d];
+    uint64_t abase = base.m + L.used[d];
+    if (p.tot_old)
+      k_lsm_move<<<grid_for(p.tot_old, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+          p.ooff, p.nt, p.tot_old, p.olo, p.dlo, p.x, p.ins_scan, p.noff, abase, base.d[d].col);
+    k_lsm_ins<<<grid_for(k, kBlock, 1u << 16), kBlock, 0, c->stream>>>(p.x, p.g, k, p.hscan, p.dlo, p.olo, p.olen,
+                                                                      p.ins_scan, p.noff, abase, base.d[d].col);
+    if (L.nkeys[d])
+      k_lsm_copy_map<<<grid_for(L.nkeys[d], kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+          L.keys[d], L.nkeys[d], L.map[L.cur_map][d], L.map[nb][d]);
+    k_lsm_set_map<<<grid_for(p.nt, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
+        p.tv, p.nt, p.noff, p.nlen, abase, p.fresh, p.fscan, L.nkeys[d], L.map[nb][d], L.keys[d]);
+    GJ_HIP(hipGetLastError());
+    commit.used[d] = L.used[d] + p.tot_new;
+    commit.nkeys[d] = L.nkeys[d] + p.nfresh;
+  }
+}
+
 // Whether this update appends its rows: they fit the current slot's slack,
 // and they are at most an eighth of the edges (2^16 entries at least) per
 // direction.  A larger batch touches most of the heavy rows, so writing both
@@ -400,22 +424,11 @@ bool lsm_update(gj_ctx* c, gj_graph* g, const uint32_t* const (&r)[2], const uin
   LsmState& L = g->lsm;
   Version& base = g->ver[g->cur];
   const int nb = 1 - L.cur_map;
-  for (int d = 0; d < 2; ++d) {
-    DirPlan& p = P[d];
-    uint64_t abase = base.m + L.used[d];
-    if (p.tot_old)
-      k_lsm_move<<<grid_for(p.tot_old, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
-          p.ooff, p.nt, p.tot_old, p.olo, p.dlo, p.x, p.ins_scan, p.noff, abase, base.d[d].col);
-    k_lsm_ins<<<grid_for(k, kBlock, 1u << 16), kBlock, 0, c->stream>>>(p.x, p.g, k, p.hscan, p.dlo, p.olo, p.olen,
-                                                                      p.ins_scan, p.noff, abase, base.d[d].col);
-    if (L.nkeys[d])
-      k_lsm_copy_map<<<grid_for(L.nkeys[d], kBlock, 1u << 16), kBlock, 0, c->stream>>>(
-          L.keys[d], L.nkeys[d], L.map[L.cur_map][d], L.map[nb][d]);
-    k_lsm_set_map<<<grid_for(p.nt, kBlock, 1u << 16), kBlock, 0, c->stream>>>(
-        p.tv, p.nt, p.noff, p.nlen, abase, p.fresh, p.fscan, L.nkeys[d], L.map[nb][d], L.keys[d]);
-    GJ_HIP(hipGetLastError());
-    commit.used[d] = L.used[d] + p.tot_new;
-    commit.nkeys[d] = L.nkeys[d] + p.nfresh;
+  try {
+    write_rows(c, g, P, k, commit);
+  } catch (...) {
+    lsm_abort(c, g);  // the next map may be partly written
+    throw;
   }
   // every insert and delete of dE appears once per direction
   uint64_t ins = P[0].ins, del = k - P[0].ins;
