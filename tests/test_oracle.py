@@ -542,7 +542,8 @@ def test_tri_invalid():
 
 @pytest.mark.parametrize("n", [4, 7, 10])
 def test_counter_closed_forms(n):
-    """Per-stage counters beyond the first stage, from closed forms.
+    """Per-stage counters beyond the first stage, from closed forms (triangle,
+    4-clique, 5-clique, diamond, 4-cycle).
     Complete digraph K_n: every set has n - 1 values, so each stage proposes
     n - 1 per prefix; prefixes are the tuples of the shape's distinctness.
     Transitive tournament (i -> j iff i < j): out(v) = n - 1 - v, so the
@@ -553,6 +554,9 @@ def test_counter_closed_forms(n):
     assert r["prefixes"][2:4] == [n * k, n * k * (n - 2)] and r["extensions"][2] == n * k * k
     r = oracle.run(G, Q.CLIQUE4)
     assert r["prefixes"][3] == n * k * (n - 2) and r["extensions"][3] == n * k * (n - 2) * k
+    r = oracle.run(G, Q.CLIQUE5)
+    p4 = n * k * (n - 2) * (n - 3)
+    assert r["prefixes"][4] == p4 and r["extensions"][4] == p4 * k and r["matches"] == p4 * (n - 4)
     for q in (Q.DIAMOND, Q.CYCLE4):  # a2 may repeat a1 (diamond) or a0 (4-cycle)
         r = oracle.run(G, q)
         assert r["prefixes"][3] == n * k * k and r["extensions"][2] == n * k * k
@@ -563,3 +567,6 @@ def test_counter_closed_forms(n):
     r = oracle.run(T, Q.CLIQUE4)
     assert r["prefixes"][3] == math.comb(n, 3)
     assert r["extensions"][3] == sum(math.comb(z, 2) * (n - 1 - z) for z in range(n))
+    r = oracle.run(T, Q.CLIQUE5)  # increasing tuples; the largest bound vertex has the shortest out-list
+    assert r["prefixes"][4] == math.comb(n, 4) and r["matches"] == math.comb(n, 5)
+    assert r["extensions"][4] == sum(math.comb(z, 3) * (n - 1 - z) for z in range(n))
