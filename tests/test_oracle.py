@@ -123,6 +123,9 @@ def test_complete_digraph(n):
     assert oracle.run(G, Q.TRIANGLE)["matches"] == n * (n - 1) * (n - 2)
     assert oracle.run(G, Q.CYCLIC_TRIANGLE)["matches"] == n * (n - 1) * (n - 2)
     assert oracle.run(G, Q.CLIQUE4)["matches"] == n * (n - 1) * (n - 2) * (n - 3)
+    assert oracle.run(G, Q.CLIQUE5)["matches"] == n * (n - 1) * (n - 2) * (n - 3) * (n - 4)
+    # the house's a4 joins a1 and a2 only: any vertex but those two
+    assert oracle.run(G, Q.HOUSE)["matches"] == n * (n - 1) * (n - 2) * (n - 3) * (n - 2)
     assert oracle.run(G, Q.DIAMOND)["matches"] == (n - 1) ** 4 + (n - 1)
     assert oracle.run(G, Q.CYCLE4)["matches"] == (n - 1) ** 4 + (n - 1)
 
