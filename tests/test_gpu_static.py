@@ -98,6 +98,7 @@ def test_complete_digraph_closed_forms(gj, ctx):
     G = gj.Graph(ctx, src, dst, n)
     for q, want in [(Q.TRIANGLE, n * (n - 1) * (n - 2)), (Q.CLIQUE4, n * (n - 1) * (n - 2) * (n - 3)),
                     (Q.CLIQUE5, n * (n - 1) * (n - 2) * (n - 3) * (n - 4)),
+                    (Q.HOUSE, n * (n - 1) * (n - 2) * (n - 3) * (n - 2)),
                     (Q.DIAMOND, (n - 1) ** 4 + (n - 1)), (Q.CYCLE4, (n - 1) ** 4 + (n - 1))]:
         assert gj.count(ctx, G, gj.Query(ctx, *q))["matches"] == want
 
