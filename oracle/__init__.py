@@ -68,7 +68,9 @@ def _load():
         L.or_run_textbook.restype = vp
         L.or_run_textbook.argtypes = [vp, i32, vp, vp, i32, vp, vp, ip]
         L.or_delta.restype = vp
-        L.or_delta.argtypes = [vp, vp, vp, vp, u64, i32, vp, vp, i32, vp, vp, vp, i32, ip]
+        L.or_delta.argtypes = [vp, vp, vp, vp, u64, i32, vp, vp, i32, vp, vp, vp, i32, i32, i32, ip]
+        L.or_twopath.restype = i32
+        L.or_twopath.argtypes = [vp, i32, i32, vp]
         L.or_result_matches.restype = u64
         L.or_result_matches.argtypes = [vp]
         L.or_result_counters.argtypes = [vp, vp, vp]
@@ -157,7 +159,7 @@ class Graph:
         return int(a[0]), int(a[1])
 
 
-def _take(res, m, want_rows, want_signs=False):
+def _take(res, m, want_rows, want_signs=False, delta=False):
     L = _load()
     out = {"matches": int(L.or_result_matches(res))}
     pre = np.zeros(MAX_ATTRS + 1, dtype=np.uint64)
@@ -176,6 +178,7 @@ def _take(res, m, want_rows, want_signs=False):
         if n:
             L.or_result_signs(res, _p(sg))
         out["signs"] = sg
+    if delta:
         out["count_delta"] = int(L.or_result_count_delta(res))
         out["raw_emissions"] = int(L.or_result_raw_emissions(res))
     L.or_result_free(res)
@@ -225,28 +228,50 @@ def textbook(graph, query):
     return out
 
 
-def delta(graph, src, dst, sign, query=None):
-    """Applies the batch to `graph` in place; returns the query's delta."""
+def delta(graph, src, dst, sign, query=None, rows=True, threads=1):
+    """Applies the batch to `graph` in place; returns the query's delta.
+    rows=False keeps only sums: count_delta (the signed sum of the outputs of
+    every dQ_i), raw_emissions and the counters."""
     src = np.ascontiguousarray(src, dtype=np.uint32)
     dst = np.ascontiguousarray(dst, dtype=np.uint32)
     sign = np.ascontiguousarray(sign, dtype=np.int8)
     st = ctypes.c_int(0)
     if query is None:
         res = _load().or_delta(graph._h, _p(src), _p(dst), _p(sign), len(src),
-                               0, None, None, 0, None, None, None, 0, ctypes.byref(st))
+                               0, None, None, 0, None, None, None, 0, 0, threads, ctypes.byref(st))
         m = 0
     else:
         if len(query) > 4 and query[4]:
             raise OracleError("delta(): ternary atoms are not supported")
         m, s, d, k, o, lx, ly, nl = _query_arrays(query)
         res = _load().or_delta(graph._h, _p(src), _p(dst), _p(sign), len(src),
-                               m, _p(s), _p(d), k, _p(o), _p(lx), _p(ly), nl, ctypes.byref(st))
+                               m, _p(s), _p(d), k, _p(o), _p(lx), _p(ly), nl, int(rows), threads,
+                               ctypes.byref(st))
     if st.value != 0:
         raise OracleError("or_delta status %d" % st.value)
     if query is None:
         _load().or_result_free(res)
         return None
-    return _take(res, m, True, True)
+    return _take(res, m, rows, rows, delta=True)
+
+
+TWOPATH_KINDS = {"diamond": 0, "cycle4": 1}
+
+
+def twopath(graph, kind, threads=1):
+    """Counts of the diamond edge(a0,a1), edge(a0,a2), edge(a1,a3),
+    edge(a2,a3) (kind "diamond") or the 4-cycle a0 -> a1 -> a2 -> a3 -> a0
+    (kind "cycle4") by counting 2-paths, with the Generic Join counters of
+    the order a0, a1, a2, a3 summed from their definitions.  Returns
+    {"matches", "prefixes", "extensions"} shaped as run()'s."""
+    out = np.zeros(6, dtype=np.uint64)
+    st = _load().or_twopath(graph._h, TWOPATH_KINDS[kind], threads, _p(out))
+    if st != 0:
+        raise OracleError("or_twopath status %d" % st)
+    pre = [0] * (MAX_ATTRS + 1)
+    ext = [0] * (MAX_ATTRS + 1)
+    pre[2], ext[2], pre[3], ext[3], pre[4] = (int(x) for x in out[1:6])
+    return {"matches": int(out[0]), "prefixes": pre, "extensions": ext}
 
 
 def symmetric_edges(n, src, dst):

@@ -70,10 +70,8 @@ enum { OR_OK = 0, OR_EINVAL = 1, OR_EOVERFLOW = 4 };
 // Edge relation held as per-vertex sorted neighbour vectors (out and in).
 struct Graph {
   uint32_t n = 0;
+  uint64_t m = 0;  // number of edges
   std::vector<std::vector<uint32_t>> out, in;
-  // the edge set in (src, dst) order and in (dst, src) order; position in
-  // these is the "edge index" of the forward / reverse direction
-  std::vector<std::pair<uint32_t, uint32_t>> fwd_edges, rev_edges;
   uint64_t noop_inserts = 0, noop_deletes = 0, dropped_loops = 0;
 
   bool has(uint32_t u, uint32_t v) const {
@@ -84,17 +82,69 @@ struct Graph {
   void rebuild_lists(const std::vector<std::pair<uint32_t, uint32_t>>& s) {
     out.assign(n, {});
     in.assign(n, {});
-    fwd_edges = s;
-    rev_edges.clear();
-    rev_edges.reserve(s.size());
     for (auto& e : s) {
       out[e.first].push_back(e.second);
       in[e.second].push_back(e.first);
-      rev_edges.push_back({e.second, e.first});
     }
     for (auto& l : out) std::sort(l.begin(), l.end());
     for (auto& l : in) std::sort(l.begin(), l.end());
-    std::sort(rev_edges.begin(), rev_edges.end());
+    m = s.size();
+    stale = true;
+  }
+  // The edge set in (src, dst) order and in (dst, src) order; position in
+  // these is the "edge index" of the forward / reverse direction.  Read off
+  // the neighbour lists (already in that order) after every change.
+  const std::vector<std::pair<uint32_t, uint32_t>>& fwd_edges() const {
+    refresh();
+    return fwd_;
+  }
+  const std::vector<std::pair<uint32_t, uint32_t>>& rev_edges() const {
+    refresh();
+    return rev_;
+  }
+  void mark_changed() { stale = true; }
+
+ private:
+  mutable std::vector<std::pair<uint32_t, uint32_t>> fwd_, rev_;
+  mutable bool stale = true;
+  void refresh() const {
+    if (!stale) return;
+    fwd_.clear();
+    rev_.clear();
+    fwd_.reserve(m);
+    rev_.reserve(m);
+    for (uint32_t u = 0; u < n; ++u)
+      for (uint32_t v : out[u]) fwd_.push_back({u, v});
+    for (uint32_t v = 0; v < n; ++v)
+      for (uint32_t u : in[v]) rev_.push_back({v, u});
+    stale = false;
+  }
+};
+
+// One version of the relation for a delta query: the graph as it is, or the
+// graph with the neighbour lists of the vertices an update batch touches
+// replaced by their lists after the batch (`out_new`, `in_new`).
+struct VersionView {
+  const Graph* g = nullptr;
+  const std::map<uint32_t, std::vector<uint32_t>>* out_new = nullptr;
+  const std::map<uint32_t, std::vector<uint32_t>>* in_new = nullptr;
+  const std::vector<uint32_t>& out(uint32_t v) const {
+    if (out_new) {
+      auto it = out_new->find(v);
+      if (it != out_new->end()) return it->second;
+    }
+    return g->out[v];
+  }
+  const std::vector<uint32_t>& in(uint32_t v) const {
+    if (in_new) {
+      auto it = in_new->find(v);
+      if (it != in_new->end()) return it->second;
+    }
+    return g->in[v];
+  }
+  bool has(uint32_t u, uint32_t v) const {
+    const auto& l = out(u);
+    return std::binary_search(l.begin(), l.end(), v);
   }
 };
 
@@ -263,11 +313,11 @@ Plan make_plan(const Query& q) {
 // Which version of the relation an atom reads: for delta query dQ_i, atoms
 // before i read the new graph, atoms after i the old one (Sec. 3.3.1).
 struct Views {
-  const Graph* g_old;
-  const Graph* g_new;
-  int delta_atom;  // -1: every atom reads g_old
-  const Graph& of(int atom) const {
-    return (delta_atom >= 0 && atom < delta_atom) ? *g_new : *g_old;
+  VersionView v_old;
+  VersionView v_new;
+  int delta_atom;  // -1: every atom reads v_old
+  const VersionView& of(int atom) const {
+    return (delta_atom >= 0 && atom < delta_atom) ? v_new : v_old;
   }
 };
 
@@ -277,16 +327,16 @@ struct Views {
 const std::vector<uint32_t>& ext_list(const Views& v, const Binding& b, const std::vector<uint32_t>& prefix,
                                       std::vector<uint32_t>& scratch) {
   if (b.tri >= 0) {
-    const Graph& g = *v.g_old;
+    const VersionView& g = v.v_old;
     uint32_t x = prefix[b.col], y = prefix[b.col2];
     scratch.clear();
     if (g.has(x, y))
-      std::set_intersection(g.out[x].begin(), g.out[x].end(), g.out[y].begin(), g.out[y].end(),
+      std::set_intersection(g.out(x).begin(), g.out(x).end(), g.out(y).begin(), g.out(y).end(),
                             std::back_inserter(scratch));
     return scratch;
   }
-  const Graph& g = v.of(b.atom);
-  return b.out_dir ? g.out[prefix[b.col]] : g.in[prefix[b.col]];
+  const VersionView& g = v.of(b.atom);
+  return b.out_dir ? g.out(prefix[b.col]) : g.in(prefix[b.col]);
 }
 
 struct Counters {
@@ -397,8 +447,8 @@ bool pair_ok(const Query& q, const Views& v, int atom, uint32_t x0, uint32_t x1)
 void run_seeds(const Query& q, const Plan& plan, const Views& views,
                uint64_t lo, uint64_t hi, Counters& c, bool collect,
                std::vector<uint32_t>& rows, bool factorise) {
-  const Graph& g = views.of(plan.seed_atom);
-  const auto& E = plan.seed_fwd ? g.fwd_edges : g.rev_edges;
+  const Graph& g = *views.of(plan.seed_atom).g;
+  const auto& E = plan.seed_fwd ? g.fwd_edges() : g.rev_edges();
   std::vector<uint32_t> prefix;
   prefix.reserve(q.m);
   for (uint64_t k = lo; k < hi && k < E.size(); ++k) {
@@ -495,13 +545,14 @@ void* or_graph_new(uint32_t n, const uint32_t* src, const uint32_t* dst, uint64_
 
 void* or_graph_copy(const void* g) { return new Graph(*(const Graph*)g); }
 void or_graph_free(void* g) { delete (Graph*)g; }
-uint64_t or_graph_edges(const void* g) { return ((const Graph*)g)->fwd_edges.size(); }
+uint64_t or_graph_edges(const void* g) { return ((const Graph*)g)->m; }
 uint32_t or_graph_vertices(const void* g) { return ((const Graph*)g)->n; }
 void or_graph_edge_list(const void* gp, uint32_t* src, uint32_t* dst) {
   const Graph* g = (const Graph*)gp;
-  for (size_t i = 0; i < g->fwd_edges.size(); ++i) {
-    src[i] = g->fwd_edges[i].first;
-    dst[i] = g->fwd_edges[i].second;
+  const auto& E = g->fwd_edges();
+  for (size_t i = 0; i < E.size(); ++i) {
+    src[i] = E[i].first;
+    dst[i] = E[i].second;
   }
 }
 
@@ -529,8 +580,8 @@ void* or_run(const void* gp, int num_attrs, const uint8_t* as, const uint8_t* ad
     return nullptr;
   }
   Plan plan = make_plan(q);
-  Views views{g, g, -1};
-  const auto& E = plan.seed_fwd ? g->fwd_edges : g->rev_edges;
+  Views views{VersionView{g}, VersionView{g}, -1};
+  const auto& E = plan.seed_fwd ? g->fwd_edges() : g->rev_edges();
   uint64_t hi = std::min<uint64_t>(seed_hi, E.size());
   uint64_t lo = std::min<uint64_t>(seed_lo, hi);
   if (threads < 1) threads = 1;
@@ -617,15 +668,21 @@ void* or_run_textbook(const void* gp, int num_attrs, const uint8_t* as, const ui
 }
 
 // Applies a signed update batch to the graph (in place) and returns, for the
-// given query, the consolidated change of its output (Delta-GJ, Sec. 3.3.1).
+// given query, the change of its output (Delta-GJ, Sec. 3.3.1).
 // Normalisation: self-loops dropped, repeated rows collapse, an insertion of
 // a present edge and a deletion of an absent edge are no-ops (counted); a
 // batch that both inserts and deletes one edge is rejected (status EINVAL,
 // graph unchanged).  Pass num_atoms = 0 to only apply the batch.
+// want_rows != 0: the signed outputs of all dQ_i are consolidated per tuple
+// (weights summed, zeros dropped) into sorted rows with signs.  Otherwise
+// only their sums are kept: count_delta is the sum of the signed outputs
+// (consolidation regroups them and cannot change it) and raw_emissions their
+// number.  The seeds of each dQ_i are split over `threads` std::threads in
+// contiguous chunks; nothing depends on the thread count.
 void* or_delta(void* gp, const uint32_t* src, const uint32_t* dst, const int8_t* sign,
                uint64_t b, int num_attrs, const uint8_t* as, const uint8_t* ad,
                int num_atoms, const uint8_t* order, const uint8_t* lx, const uint8_t* ly,
-               int num_less, int* status) {
+               int num_less, int want_rows, int threads, int* status) {
   Graph* g = (Graph*)gp;
   Query q;
   bool have_query = num_atoms > 0;
@@ -655,17 +712,28 @@ void* or_delta(void* gp, const uint32_t* src, const uint32_t* dst, const int8_t*
     if (!g->has(e.first, e.second)) ++noop_d;
     else dE.push_back({e, -1});
   }
-  std::set<std::pair<uint32_t, uint32_t>> ss(g->fwd_edges.begin(), g->fwd_edges.end());
+  // the new version: every list dE touches, rewritten; the others shared
+  std::map<uint32_t, std::vector<uint32_t>> out_new, in_new;
   for (auto& x : dE) {
-    if (x.second > 0) ss.insert(x.first);
-    else ss.erase(x.first);
+    uint32_t u = x.first.first, v = x.first.second;
+    if (!out_new.count(u)) out_new[u] = g->out[u];
+    if (!in_new.count(v)) in_new[v] = g->in[v];
   }
-  std::vector<std::pair<uint32_t, uint32_t>> s(ss.begin(), ss.end());
-  Graph g_new;
-  g_new.n = g->n;
-  g_new.rebuild_lists(s);
+  for (auto& x : dE) {
+    uint32_t u = x.first.first, v = x.first.second;
+    std::vector<uint32_t>& o = out_new[u];
+    std::vector<uint32_t>& i = in_new[v];
+    if (x.second > 0) {
+      o.insert(std::lower_bound(o.begin(), o.end(), v), v);
+      i.insert(std::lower_bound(i.begin(), i.end(), u), u);
+    } else {
+      o.erase(std::lower_bound(o.begin(), o.end(), v));
+      i.erase(std::lower_bound(i.begin(), i.end(), u));
+    }
+  }
   Result* r = new Result();
   r->m = q.m;
+  if (threads < 1) threads = 1;
   if (have_query) {
     std::map<std::vector<uint32_t>, int64_t> acc;
     for (int i = 0; i < (int)q.atoms.size(); ++i) {
@@ -685,36 +753,182 @@ void* or_delta(void* gp, const uint32_t* src, const uint32_t* dst, const int8_t*
       }
       plan.seed_atom = i;
       plan.seed_fwd = true;
-      Views views{g, &g_new, i};
-      for (auto& x : dE) {
-        uint32_t x0 = x.first.first, x1 = x.first.second;
-        bool ok = true;
-        for (int f : plan.filters) ok = ok && pair_ok(qi, views, f, x0, x1);
-        std::vector<uint32_t> prefix = {x0}, rows;
-        if (!ok || !ineq_ok(plan, 1, prefix, x1)) continue;
-        prefix.push_back(x1);
+      Views views{VersionView{g}, VersionView{g, &out_new, &in_new}, i};
+      // per thread: counters, signed match sum, emissions, and (want_rows)
+      // the emitted rows with the weight of their seed
+      struct Part {
         Counters c;
-        extend(qi, plan, views, 2, prefix, c, true, rows);
-        r->c.merge(c);
-        for (size_t k = 0; k + q.m <= rows.size(); k += q.m) {
-          std::vector<uint32_t> t(rows.begin() + k, rows.begin() + k + q.m);
-          acc[t] += x.second;
-          ++r->raw_emissions;
+        int64_t wsum = 0;
+        uint64_t raw = 0;
+        std::vector<uint32_t> rows;
+        std::vector<int8_t> w;
+      };
+      int nt = (uint64_t)threads > dE.size() ? std::max<int>(1, (int)dE.size()) : threads;
+      std::vector<Part> parts(nt);
+      std::vector<std::thread> pool;
+      for (int t = 0; t < nt; ++t) {
+        uint64_t a = dE.size() * t / nt, e = dE.size() * (t + 1) / nt;
+        pool.emplace_back([&, t, a, e] {
+          Part& P = parts[t];
+          for (uint64_t s = a; s < e; ++s) {
+            const auto& x = dE[s];
+            uint32_t x0 = x.first.first, x1 = x.first.second;
+            bool ok = true;
+            for (int f : plan.filters) ok = ok && pair_ok(qi, views, f, x0, x1);
+            std::vector<uint32_t> prefix = {x0};
+            if (!ok || !ineq_ok(plan, 1, prefix, x1)) continue;
+            prefix.push_back(x1);
+            uint64_t before = P.c.matches;
+            size_t rbefore = P.rows.size();
+            extend(qi, plan, views, 2, prefix, P.c, want_rows != 0, P.rows);
+            uint64_t k = P.c.matches - before;
+            P.raw += k;
+            P.wsum += (int64_t)k * x.second;
+            if (want_rows) P.w.insert(P.w.end(), (P.rows.size() - rbefore) / q.m, (int8_t)x.second);
+          }
+        });
+      }
+      for (auto& th : pool) th.join();
+      for (Part& P : parts) {
+        r->c.merge(P.c);
+        r->raw_emissions += P.raw;
+        r->count_delta += P.wsum;
+        for (size_t k = 0; k < P.w.size(); ++k) {
+          std::vector<uint32_t> t(P.rows.begin() + k * q.m, P.rows.begin() + (k + 1) * q.m);
+          acc[t] += P.w[k];
         }
       }
     }
-    for (auto& kv : acc) {
-      if (kv.second == 0) continue;
-      r->rows.insert(r->rows.end(), kv.first.begin(), kv.first.end());
-      r->signs.push_back((int8_t)kv.second);
-      r->count_delta += kv.second;
+    if (want_rows) {
+      int64_t sum = 0;
+      for (auto& kv : acc) {
+        if (kv.second == 0) continue;
+        r->rows.insert(r->rows.end(), kv.first.begin(), kv.first.end());
+        r->signs.push_back((int8_t)kv.second);
+        sum += kv.second;
+      }
+      if (sum != r->count_delta) { *status = OR_EINVAL; delete r; return nullptr; }
     }
   }
-  g->rebuild_lists(s);
+  // commit the new version
+  for (auto& kv : out_new) g->out[kv.first].swap(kv.second);
+  for (auto& kv : in_new) g->in[kv.first].swap(kv.second);
+  for (auto& x : dE) g->m += x.second > 0 ? 1 : (uint64_t)-1;
+  g->mark_changed();
   g->noop_inserts += noop_i;
   g->noop_deletes += noop_d;
   *status = OR_OK;
   return r;
+}
+
+// Counts of two four-attribute queries by counting 2-paths, the reference
+// for graphs where Generic Join itself is too slow on the host:
+//  kind 0, the diamond edge(a0,a1), edge(a0,a2), edge(a1,a3), edge(a2,a3):
+//    with k(a0, a3) = |{a1 : a0 -> a1 -> a3}| the number of 2-paths, the
+//    matches are the pairs of 2-paths from a0 to a3 (a1 = a2 allowed, join
+//    semantics), so count = sum over a0, a3 of k(a0, a3)^2;
+//  kind 1, the 4-cycle edge(a0,a1), edge(a1,a2), edge(a2,a3), edge(a3,a0):
+//    a match is a 2-path a0 -> a1 -> a2 and a 2-path a2 -> a3 -> a0, so
+//    count = sum over a0, a2 of k(a0, a2) * k(a2, a0).
+// Also the per-stage counters of Generic Join in the order a0, a1, a2, a3
+// (edge-seeded form, Sec. 4.2), each summed from its definition:
+//  prefixes[2] = |E|;
+//  diamond:  a2 ranges over out(a0) alone, so extensions[2] = prefixes[3] =
+//            sum over edges (a0, a1) of |out(a0)|; a3 is proposed from the
+//            smaller of out(a1), out(a2): extensions[3] = sum over
+//            (a0, a1, a2) of min(|out(a1)|, |out(a2)|);
+//  4-cycle:  a2 ranges over out(a1): extensions[2] = prefixes[3] = sum over
+//            edges (a0, a1) of |out(a1)|; a3 from the smaller of out(a2) and
+//            in(a0): extensions[3] = sum over 2-paths (a0, a1, a2) of
+//            min(|out(a2)|, |in(a0)|);
+//  prefixes[4] = count.
+// out[0..5] = count, prefixes[2], extensions[2], prefixes[3], extensions[3],
+// prefixes[4].  Work is split over `threads` std::threads by vertex ranges.
+int or_twopath(const void* gp, int kind, int threads, uint64_t* out) {
+  const Graph* g = (const Graph*)gp;
+  if (kind != 0 && kind != 1) return OR_EINVAL;
+  if (threads < 1) threads = 1;
+  const uint32_t n = g->n;
+  std::vector<uint64_t> res(3 * threads, 0);
+  std::vector<int> ovf(threads, 0);
+  std::vector<std::thread> pool;
+  for (int t = 0; t < threads; ++t) {
+    pool.emplace_back([&, t] {
+      uint64_t count = 0, ext2 = 0, ext3 = 0;
+      bool over = false;
+      std::vector<uint32_t> k(n, 0), back(n, 0), seen;
+      std::vector<uint32_t> da, db;
+      for (uint64_t v = (uint64_t)n * t / threads; v < (uint64_t)n * (t + 1) / threads; ++v) {
+        const uint32_t a0 = (uint32_t)v;
+        // count: 2-paths from a0, by end vertex
+        seen.clear();
+        for (uint32_t a1 : g->out[a0])
+          for (uint32_t a2 : g->out[a1]) {
+            if (k[a2] == 0) seen.push_back(a2);
+            ++k[a2];
+          }
+        if (kind == 0) {
+          for (uint32_t e : seen) {
+            uint64_t sq = (uint64_t)k[e] * k[e];
+            over = over || __builtin_add_overflow(count, sq, &count);
+          }
+        } else {
+          // 2-paths into a0, by start vertex
+          for (uint32_t a3 : g->in[a0])
+            for (uint32_t a2 : g->in[a3]) ++back[a2];
+          for (uint32_t e : seen) {
+            uint64_t pr = (uint64_t)k[e] * back[e];
+            over = over || __builtin_add_overflow(count, pr, &count);
+          }
+          for (uint32_t a3 : g->in[a0])
+            for (uint32_t a2 : g->in[a3]) back[a2] = 0;
+        }
+        for (uint32_t e : seen) k[e] = 0;
+        // counters, grouped by vertex w = a0
+        const uint32_t w = a0;
+        if (kind == 0) {
+          // the seed edges (w, a1) each propose |out(w)| values of a2; the
+          // prefixes (w, a1, a2) range over out(w) x out(w)
+          uint64_t d0 = g->out[w].size();
+          ext2 += d0 * d0;
+          da.clear();
+          for (uint32_t a1 : g->out[w]) da.push_back((uint32_t)g->out[a1].size());
+          for (uint32_t x : da)
+            for (uint32_t y : da) ext3 += std::min(x, y);
+        } else {
+          // the prefixes (a0, a1, a2) are the 2-paths; here those whose middle
+          // vertex a1 is w: a0 ranges over in(w), a2 over out(w)
+          uint64_t di = g->in[w].size(), dout = g->out[w].size();
+          ext2 += di * dout;
+          da.clear();
+          db.clear();
+          for (uint32_t x : g->in[w]) da.push_back((uint32_t)g->in[x].size());
+          for (uint32_t y : g->out[w]) db.push_back((uint32_t)g->out[y].size());
+          for (uint32_t x : da)
+            for (uint32_t y : db) ext3 += std::min(x, y);
+        }
+      }
+      res[3 * t] = count;
+      res[3 * t + 1] = ext2;
+      res[3 * t + 2] = ext3;
+      ovf[t] = over ? 1 : 0;
+    });
+  }
+  for (auto& th : pool) th.join();
+  uint64_t count = 0, ext2 = 0, ext3 = 0;
+  bool over = false;
+  for (int t = 0; t < threads; ++t) {
+    over = over || ovf[t] || __builtin_add_overflow(count, res[3 * t], &count) ||
+           __builtin_add_overflow(ext2, res[3 * t + 1], &ext2) ||
+           __builtin_add_overflow(ext3, res[3 * t + 2], &ext3);
+  }
+  out[0] = count;
+  out[1] = g->m;
+  out[2] = ext2;
+  out[3] = ext2;
+  out[4] = ext3;
+  out[5] = count;
+  return over ? OR_EOVERFLOW : OR_OK;
 }
 
 uint64_t or_result_matches(const void* r) { return ((const Result*)r)->c.matches; }
