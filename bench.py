@@ -37,35 +37,53 @@ def algorithmic_bytes_stage(prefixes, extensions, j, k, write_next=0):
     return prefixes * (4 * j + 8 * k) + extensions * 4 * k + write_next * 4 * (j + 1)
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(src, dst, n, budget_s, threads):
     """The oracle as it stands on a bounded sample of the same workload: seed
-    edge slices spread evenly over the edge range."""
+    edge slices spread evenly over the edge range, on `threads` host threads,
+    then one thread on a sample of a quarter of the size (the single-core
+    figure of the paper's COST comparison, Sec. 5.2.1)."""
     import oracle
     t0 = time.time()
     G = oracle.Graph(n, src, dst)
     build_s = time.time() - t0
     E = G.num_edges
     nslices = 64
-    # calibrate on a small sample, then size slices to the budget
-    size = 256
-    ext = 0
-    el = 0.0
-    while True:
+
+    def sample(size, th):
         ext = 0
         t0 = time.time()
         for i in range(nslices):
             lo = (E * i) // nslices
-            r = oracle.run(G, TRIANGLE, seed_lo=lo, seed_hi=min(E, lo + size), threads=threads)
-            ext += r["extensions"][2]
-        el = time.time() - t0
+            ext += oracle.run(G, TRIANGLE, seed_lo=lo, seed_hi=min(E, lo + size), threads=th)["extensions"][2]
+        return ext, time.time() - t0
+
+    # calibrate on a small sample, then size slices to the budget
+    size = 256
+    while True:
+        ext, el = sample(size, threads)
         if el > budget_s / 2 or size * nslices >= E:
             break
         size = min(E // nslices + 1, int(size * max(2.0, min(16.0, budget_s / max(el, 1e-3)))))
+    size1 = max(1, size // (4 * max(1, threads // 4)))
+    ext1, el1 = sample(size1, 1)
     return {"value": ext / el, "unit": "extensions/s", "cores": threads, "kind": "oracle",
             "sample": "%d seed-edge slices of %d edges spread evenly over the %d edges "
                       "(%.2f%% of seeds), %d threads; oracle index build %.1f s not timed"
                       % (nslices, size, E, 100.0 * nslices * size / E, threads, build_s),
-            "seconds": round(el, 2), "extensions": ext}
+            "seconds": round(el, 2), "extensions": ext,
+            "hardware_threads": os.cpu_count(), "cpu_model": cpu_model(),
+            "single_thread": {"value": ext1 / el1, "unit": "extensions/s", "seconds": round(el1, 2),
+                              "sample": "%d slices of %d edges, 1 thread" % (nslices, size1)}}
 
 
 def batched_vs_plain(gj, ctx, G, nreq, seed, log, max_width=1000):
@@ -81,13 +99,16 @@ def batched_vs_plain(gj, ctx, G, nreq, seed, log, max_width=1000):
              "triangle": (3, [(0, 1), (1, 2), (0, 2)]),
              "4-cycle": (4, [(0, 1), (1, 2), (2, 3), (3, 0)])}
     qs = {k: gj.Query(ctx, *v) for k, v in kinds.items()}
+    ks = {"4-clique": {2: 2, 3: 3}, "diamond": {2: 1, 3: 2}, "triangle": {2: 2}, "4-cycle": {2: 1, 3: 2}}
     names = ["4-clique", "diamond", "4-clique", "diamond", "triangle", "4-cycle"]
     reqs = []
+    rnames = []
     for i in range(nreq):
         k = names[i % len(names)]
-        lo = int(rng.integers(E // 8, E))
+        lo = int(rng.integers(0, E))
         width = int(np.exp(rng.uniform(0, np.log(max_width))))
         reqs.append((qs[k], lo, min(E, lo + width)))
+        rnames.append(k)
     tune = gj.autotune(ctx, G, reqs)
     gj.run_batch(ctx, G, reqs)
     t0 = time.perf_counter()
@@ -100,14 +121,164 @@ def batched_vs_plain(gj, ctx, G, nreq, seed, log, max_width=1000):
     fallbacks = ctx.get_option("batch_fallbacks")
     assert all(b["extensions"] == p["extensions"] for b, p in zip(bst, plain))
     ext = sum(sum(p["extensions"]) for p in plain)
-    log("batched: %d requests, %d extensions: plain %.1f ms, batched %.1f ms (fallbacks %d)"
-        % (nreq, ext, tp * 1e3, tb * 1e3, ctx.get_option("batch_fallbacks")))
+    byt = sum(stage_bytes(p["prefixes"], p["extensions"], kinds[k][0], ks[k]) for p, k in zip(plain, rnames))
+    log("batched: %d requests, %d extensions: plain %.1f ms, batched %.1f ms (fallbacks %d); batched %.0f GB/s "
+        "algorithmic" % (nreq, ext, tp * 1e3, tb * 1e3, ctx.get_option("batch_fallbacks"), byt / tb / 1e9))
     return {"requests": nreq, "queries": "4-clique, diamond, triangle, 4-cycle seed slices (widths "
                                           "log-uniform in [1, %d] seed edges)" % max_width,
             "extensions": ext, "matches": int(sum(counts)),
             "plain_ms": tp * 1e3, "batched_ms": tb * 1e3,
             "plain_extensions_per_s": ext / tp, "batched_extensions_per_s": ext / tb,
-            "speedup": tp / tb, "tuning": tune, "fallbacks": fallbacks}
+            "speedup": tp / tb, "tuning": tune, "fallbacks": fallbacks,
+            "algorithmic_bytes": byt, "batched_gbs": byt / tb / 1e9, "batched_frac": byt / tb / 1e9 / HBM_PEAK_GBS,
+            "plain_gbs": byt / tp / 1e9}
+
+
+def stage_bytes(P, X, m, ks, final_written=False):
+    """Algorithmic bytes of a depth-first count from its per-stage counters:
+    stage j reads its prefixes and row pointers, each proposal and its probes
+    (4 B per binding atom), and writes the next frontier unless final."""
+    t = 0
+    for j in range(2, m):
+        t += algorithmic_bytes_stage(P[j], X[j], j, ks[j], P[j + 1] if j + 1 < m or final_written else 0)
+    return t
+
+
+def propose_leg(gj, ctx, G, log, nslices=48, width=3000):
+    """The generic per-candidate kernel (k_propose) alone: 4-clique and
+    diamond counts over seed slices spread evenly over the R-MAT-22 edge
+    range (the first at the hub rows), on the depth-first path.  Roofline of
+    the propose launches from the stage counters (GJ cost model) over their
+    summed HIP-event time."""
+    E = G.info(degrees=False)["edges"]
+    out = {}
+    for name, qd, ks in (("4-clique", (4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]), {2: 2, 3: 3}),
+                         ("diamond", (4, [(0, 1), (0, 2), (1, 3), (2, 3)]), {2: 1, 3: 2})):
+        q = gj.Query(ctx, *qd)
+        w = width if name == "4-clique" else width // 10
+        gj.count(ctx, G, q, E // 2, E // 2 + 10)
+        kms = 0.0
+        ext = 0
+        byt = 0
+        launches = 0
+        t0 = time.perf_counter()
+        for i in range(nslices):
+            lo = (E * i) // nslices
+            r = gj.count(ctx, G, q, lo, min(E, lo + w))
+            kms += r["kernel_ms"]
+            launches += r["kernel_launches"]
+            ext += sum(r["extensions"])
+            byt += stage_bytes(r["prefixes"], r["extensions"], 4, ks)
+        wall = time.perf_counter() - t0
+        gbs = byt / (kms * 1e-3) / 1e9
+        out[name] = {"slices": nslices, "width": w, "extensions": ext, "kernel_ms": kms, "wall_s": wall,
+                     "launches": launches, "extensions_per_s_kernel": ext / (kms * 1e-3),
+                     "extensions_per_s_wall": ext / wall, "algorithmic_bytes": byt,
+                     "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
+        log("k_propose, R-MAT-22 %s slices: %.2e ext in %.1f ms of propose kernels (%.2e ext/s, %.0f GB/s = "
+            "%.3f of HBM)" % (name, ext, kms, ext / (kms * 1e-3), gbs, gbs / HBM_PEAK_GBS))
+    return out
+
+
+def golden_counts():
+    """Stored oracle counts (tests/golden/full_counts.json, written from the
+    CPU oracle alone), to check the legs' results against."""
+    path = os.path.join(ROOT, "tests", "golden", "full_counts.json")
+    return json.load(open(path))["entries"] if os.path.exists(path) else {}
+
+
+def rmat20_triangle_leg(gj, log, nreq=256):
+    """Triangle count and full enumeration on R-MAT scale 20 (16.1M edges):
+    the plain path (one gj_run; the owner-grouped kernel counts), the generic
+    per-candidate kernel, the batched path (gj_run_batch over nreq seed
+    slices covering every seed edge, autotuned), and the sorted enumeration
+    of every match into device memory.  Counts equal the stored oracle
+    count."""
+    import numpy as np
+    import torch
+    import synth
+    src, dst = synth.rmat_draws(20, seed=0)
+    n = 1 << 20
+    c = gj.Context(0, torch.cuda.current_stream(), allocator="torch")
+    G = gj.Graph(c, src, dst, n)
+    E = G.info(degrees=False)["edges"]
+    q = gj.Query(c, *TRIANGLE)
+    out = {"edges": E}
+
+    def timed(f, reps=3):
+        f()
+        torch.cuda.synchronize()
+        best = 1e30
+        for _ in range(reps):
+            t = time.perf_counter()
+            r = f()
+            torch.cuda.synchronize()
+            best = min(best, time.perf_counter() - t)
+        return r, best
+
+    r, t = timed(lambda: gj.count(c, G, q))
+    ext, matches = r["extensions"][2], r["matches"]
+    out["plain_count"] = {"s": t, "extensions_per_s": ext / t, "matches_per_s": matches / t,
+                          "kernel": "k_owner_count"}
+    c.set_option("strategy", 1)
+    r1, t1 = timed(lambda: gj.count(c, G, q), 1)
+    c.set_option("strategy", 0)
+    out["generic_count"] = {"s": t1, "extensions_per_s": ext / t1, "kernel": "k_propose"}
+    bounds = [(E * i) // nreq for i in range(nreq + 1)]
+    reqs = [(q, bounds[i], bounds[i + 1]) for i in range(nreq)]
+    tune = gj.autotune(c, G, reqs)
+    (counts, _), tb = timed(lambda: gj.run_batch(c, G, reqs), 1)
+    out["batched_count"] = {"s": tb, "extensions_per_s": ext / tb, "requests": nreq, "tuning": tune,
+                            "fallbacks": c.get_option("batch_fallbacks")}
+    buf = torch.empty((matches, 3), dtype=torch.int32, device="cuda")
+    (st, rows), te = timed(lambda: gj.enumerate_rows(c, G, q, out=buf), 1)
+    out["enumerate"] = {"s": te, "matches_per_s": matches / te, "extensions_per_s": ext / te,
+                        "rows": int(st["matches"]), "bytes": int(buf.numel() * 4)}
+    sorted_ok = bool((buf[1:, 0] > buf[:-1, 0]).logical_or(
+        (buf[1:, 0] == buf[:-1, 0]).logical_and((buf[1:, 1] > buf[:-1, 1]).logical_or(
+            (buf[1:, 1] == buf[:-1, 1]).logical_and(buf[1:, 2] > buf[:-1, 2])))).all().item())
+    del buf, rows
+    gold = golden_counts().get("rmat20_triangle")
+    out["matches"], out["extensions"] = matches, ext
+    out["check"] = {"oracle_matches": gold["matches"] if gold else None,
+                    "equal": bool(gold and gold["matches"] == matches == sum(counts) == st["matches"]
+                                  and gold["extensions"][2] == ext),
+                    "rows_strictly_ascending": sorted_ok}
+    log("R-MAT-20 triangle: %d matches; plain %.2f ms, generic %.1f ms, batched (%d requests) %.1f ms, "
+        "enumeration %.1f ms; oracle equal %s" % (matches, t * 1e3, t1 * 1e3, nreq, tb * 1e3, te * 1e3,
+                                                 out["check"]["equal"]))
+    G.close()
+    c.close()
+    return out
+
+
+def rmat22_clique_diamond_leg(gj, ctx, G, log):
+    """Whole-graph 4-clique and diamond counts on the resident R-MAT-22 graph
+    (the default strategy: the edge-grouped kernels for the 4-clique, the
+    2-path kernel for the diamond), each checked against the stored oracle
+    count where the oracle has one."""
+    import torch
+    gold = golden_counts()
+    out = {}
+    for name, qd, gname in (("4-clique", (4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]), None),
+                            ("diamond", (4, [(0, 1), (0, 2), (1, 3), (2, 3)]), "rmat22_diamond")):
+        q = gj.Query(ctx, *qd)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = gj.count(ctx, G, q)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t
+        ext = sum(r["extensions"])
+        g = gold.get(gname) if gname else None
+        out[name] = {"matches": r["matches"], "extensions": ext, "s": el, "extensions_per_s": ext / el,
+                     "matches_per_s": r["matches"] / el, "kernel_ms": r["kernel_ms"],
+                     "kernel_launches": r["kernel_launches"],
+                     "oracle_equal": (g["matches"] == r["matches"] and g["extensions"] == r["extensions"])
+                     if g else None}
+        log("R-MAT-22 %s: %d matches, %.2e extensions in %.2f s (%.2e ext/s)%s"
+            % (name, r["matches"], ext, el, ext / el, "" if g is None else ", oracle equal %s"
+               % out[name]["oracle_equal"]))
+    return out
 
 
 def symmetry_breaking(gj, ctx, scale, log, full=False):
@@ -447,7 +618,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--scale", type=int, default=22)
-    ap.add_argument("--delta-batches", type=int, default=300)
+    ap.add_argument("--delta-batches", type=int, default=2000)
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--strategy", type=int, default=0)
@@ -459,7 +630,7 @@ def main():
     ap.add_argument("--serve-max-update", type=int, default=100000)
     ap.add_argument("--serve-skip", type=float, default=0.0,
                     help="fraction of the edge range (the hub rows) where no count slice starts")
-    ap.add_argument("--latency-batches", type=int, default=200)
+    ap.add_argument("--latency-batches", type=int, default=2000)
     ap.add_argument("--sym-scale", type=int, default=20,
                     help="R-MAT scale of the symmetry-breaking leg (0: skip)")
     ap.add_argument("--factor-scale", type=int, default=16,
@@ -470,6 +641,12 @@ def main():
                     help="R-MAT scale of the log-structured update leg (-1: --scale, 0: skip)")
     ap.add_argument("--sym-full", action="store_true",
                     help="also count 4-cliques with the plain query over the symmetric graph")
+    ap.add_argument("--rmat20-leg", type=int, default=1, help="the R-MAT-20 triangle leg (0: skip)")
+    ap.add_argument("--propose-leg", type=int, default=1,
+                    help="the generic propose kernel on 4-clique and diamond seed slices (0: skip)")
+    ap.add_argument("--clique-leg", type=int, default=1,
+                    help="whole-graph 4-clique and diamond counts on the benchmark graph (0: skip)")
+    ap.add_argument("--no-peaks", action="store_true", help="skip the copy / LDS bandwidth calibration")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of known "
                          "traffic that scales the HBM counters of a profiling run")
@@ -488,8 +665,12 @@ def main():
     log = lambda *a: print(*a, file=sys.stderr, flush=True)
     torch.cuda.init()
     stream = torch.cuda.current_stream()
-    ctx = gj.Context(0, stream)
+    # PyTorch supplies the stream and every device allocation of the library
+    ctx = gj.Context(0, stream, allocator="torch")
     ctx.set_option("strategy", args.strategy)
+    peaks = None if args.no_peaks else gj.measure_peaks(ctx)
+    if peaks:
+        log("measured peaks: device copy %.0f GB/s, LDS read %.0f GB/s" % (peaks["copy_gbs"], peaks["lds_gbs"]))
     if args.copy_calibration_mib:
         nb = args.copy_calibration_mib << 20
         a = torch.empty(nb, dtype=torch.uint8, device="cuda").fill_(1)
@@ -529,6 +710,7 @@ def main():
     kern_ms = sum(s["kernel_ms"] for s in stats) / args.steps
     launches = st["kernel_launches"]
     step_bytes = algorithmic_bytes_stage(st["prefixes"][2], ext, 2, 2)
+    lds_bytes = 16 * ext
     achieved = step_bytes / (kern_ms * 1e-3) / 1e9
     src_hash = hashlib.sha256(open(os.path.join(ROOT, "paper_1802_03760_amd", "csrc", "owner.hip"),
                                    "rb").read()).hexdigest()[:16]
@@ -536,6 +718,10 @@ def main():
                                             src_hash == MEASURED_TRAFFIC["owner.hip"]) else None
     log("triangle count: %d matches, %d extensions, %.2f ms/step, kernel %.2f ms (%d launches)"
         % (matches, ext, ms_step, kern_ms, launches))
+
+    cliques = rmat22_clique_diamond_leg(gj, ctx, G, log) if args.clique_leg else None
+    propose = propose_leg(gj, ctx, G, log) if args.propose_leg else None
+    rmat20 = rmat20_triangle_leg(gj, log) if args.rmat20_leg else None
 
     batched = None
     if args.batch_requests:
@@ -561,19 +747,28 @@ def main():
     fact = factorisation(gj, args.factor_scale, log) if args.factor_scale else None
     tri = triangle_index(gj, args.tri_scale, log) if args.tri_scale else None
 
-    # delta-batch latency: update stream on the same graph
+    # delta-batch latency: update stream on the same graph, every batch's
+    # count delta checked against the stored oracle values of the stream
     lat = []
     qd = [q]
     changed = 0
+    deltas = []
     for k, bs, bd, bg in synth.update_stream(args.scale, 0, 1, args.delta_batches, 1, 100000):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         r = gj.apply_updates(ctx, G, bs, bd, bg, qd)[0]
         lat.append((time.perf_counter() - t1) * 1e3)
         changed += abs(r["count_delta"])
+        deltas.append(r["count_delta"])
     lat = np.array(lat if lat else [float("nan")])
-    log("delta stream: %d batches, p50 %.2f ms, p99 %.2f ms" % (args.delta_batches, np.percentile(lat, 50),
-                                                             np.percentile(lat, 99)))
+    dgold = os.path.join(ROOT, "tests", "golden", "delta_stream_rmat22.json")
+    delta_check = None
+    if args.scale == 22 and os.path.exists(dgold):
+        gb = json.load(open(dgold))["batches"]
+        n_ok = sum(1 for k, d in enumerate(deltas) if k < len(gb) and gb[k][2] == d)
+        delta_check = {"batches_checked": min(len(deltas), len(gb)), "equal": n_ok}
+    log("delta stream: %d batches, p50 %.2f ms, p99 %.2f ms; oracle check %s"
+        % (args.delta_batches, np.percentile(lat, 50), np.percentile(lat, 99), delta_check))
 
     lsm = None
     ls = args.scale if args.lsm_scale < 0 else args.lsm_scale
@@ -613,16 +808,32 @@ def main():
         "matches": matches,
         "extensions": ext,
         "index_build_ms": build_ms,
-        "delta": {"batches": args.delta_batches, "sizes": "log-uniform [1, 100000], 10% deletions, seed 1",
+        "delta": {"batches": args.delta_batches, "samples": int(len(lat)),
+                  "sizes": "log-uniform [1, 100000], 10% deletions, seed 1",
                   "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                  "mean_ms": float(lat.mean()), "abs_count_changes": int(changed)},
+                  "mean_ms": float(lat.mean()), "abs_count_changes": int(changed), "oracle_check": delta_check},
         "roofline": {"bound": "hbm", "kernel": "k_owner_count" if launches == 1 else "k_propose",
                      "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": traffic, "launches_per_step": launches,
                      "avg_launch_ms": kern_ms / max(launches, 1),
-                     "algorithmic_bytes_per_step": step_bytes},
+                     "algorithmic_bytes_per_step": step_bytes,
+                     # HBM bytes the counters saw (FETCH_SIZE + WRITE_SIZE) over the same launch time
+                     "measured_hbm_gbs": traffic / (kern_ms * 1e-3) / 1e9 if traffic else None,
+                     "measured_hbm_frac": traffic / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS if traffic else None,
+                     "model_exceeds_measured": bool(traffic and step_bytes > traffic),
+                     "copy_peak_gbs": peaks["copy_gbs"] if peaks else None,
+                     "lds": {"achieved_gbs": lds_bytes / (kern_ms * 1e-3) / 1e9,
+                             "peak_gbs": peaks["lds_gbs"] if peaks else None,
+                             "frac": lds_bytes / (kern_ms * 1e-3) / 1e9 / peaks["lds_gbs"] if peaks else None,
+                             "bytes_per_step": lds_bytes,
+                             "model": "one 16-byte bucket read per proposal (table builds and overflow "
+                                      "walks not counted)"} if launches == 1 else None},
         "cpu_baseline": cpu,
+        "measured_peaks": peaks,
+        "rmat22_clique_diamond": cliques,
+        "propose_slices": propose,
+        "rmat20_triangle": rmat20,
         "batched": batched,
         "update_latency": latency,
         "serving": serving,

@@ -20,6 +20,7 @@
 #ifndef GJ_H
 #define GJ_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -43,10 +44,28 @@ typedef struct gj_ctx gj_ctx;
 typedef struct gj_graph gj_graph;
 typedef struct gj_query gj_query;
 
+/* Source of the library's device memory (graph indexes, frontiers,
+ * workspace).  alloc returns `bytes` of device memory on the current device,
+ * or NULL when none is left (the call then fails with GJ_ENOMEM); `stream`
+ * is the hipStream_t of the context that asks.  free returns a block from
+ * alloc; the library calls it only after that stream has finished with the
+ * block.  Both may be called from the threads of a server (gj_server_*) on
+ * the context, and from several contexts at once when they share the
+ * allocator.  `user` is passed through. */
+typedef struct {
+  void* (*alloc)(void* user, size_t bytes, void* stream);
+  void (*free)(void* user, void* ptr, void* stream);
+  void* user;
+} gj_allocator;
+
 /* Creates a context on HIP device `device`.  `hip_stream` is a hipStream_t to
- * issue work on (NULL: the library creates its own).  Internal buffers are
- * device allocations owned by the context and reused across calls. */
-gj_status gj_ctx_create(int device, void* hip_stream, gj_ctx** out);
+ * issue work on (NULL: the library creates its own).  `allocator` (copied;
+ * its callbacks must stay valid until the context and everything built on it
+ * are destroyed) supplies every device allocation of the context, its
+ * graphs and its servers; NULL uses hipMalloc / hipFree.  Internal buffers
+ * are owned by the context and reused across calls.  Errors: GJ_EDEVICE for
+ * a bad device, GJ_EINVAL for an allocator without both callbacks. */
+gj_status gj_ctx_create(int device, void* hip_stream, const gj_allocator* allocator, gj_ctx** out);
 /* Releases the context.  Servers and graphs built on it must be destroyed
  * first: gj_graph_destroy waits on the context's stream. */
 void gj_ctx_destroy(gj_ctx* ctx);
@@ -82,6 +101,11 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   dQ_i binds the last attribute by one atom on each seed
  *                   attribute (the triangle shapes) on the owner-grouped
  *                   kernel, unless "strategy" is 1
+ *   "owner_task_min"  owner-grouped kernel: least proposals per task; a
+ *                   unit (an owner's set and its partners) with more work is
+ *                   cut into tasks of partner ranges of at least this many
+ *                   proposals and at least 8 x the owner's set size (default
+ *                   2^20, >= 1)
  *   "propose_u"     candidates per lane whose membership searches the
  *                   generic propose kernel runs in lockstep: 1, 2 or 4
  *                   (default 4; at most 2 in stages with ternary atoms)
@@ -121,9 +145,10 @@ gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
 
 /* Reads an option (keys above, plus "batch_cap", the counters
  * "lsm_compactions" and "lsm_folds" of this context (see "lsm_updates"),
- * and the counter
- * "batch_fallbacks": gj_run_batch calls that fell back to the depth-first
- * path). */
+ * the counter "batch_fallbacks" (gj_run_batch calls that fell back to the
+ * depth-first path), and of the last owner-grouped launch on this context
+ * "owner_tasks" (its tasks) and "owner_split_units" (units cut into more
+ * than one task)). */
 gj_status gj_ctx_get_option(gj_ctx* ctx, const char* key, int64_t* value);
 
 /* ---------------------------------------------------------------- graphs */
@@ -429,6 +454,17 @@ void gj_server_destroy(gj_server* s);
  * GJ_EOVERFLOW if *n > cap (nothing copied). */
 gj_status gj_last_delta(gj_ctx* ctx, uint32_t q, uint32_t* rows, int8_t* signs,
                         uint64_t cap, int on_device, uint64_t* n);
+
+/* ---------------------------------------------------------------- calibration */
+
+/* Bandwidth peaks of ctx's device as measured by microbenchmark kernels, the
+ * reference beside the published peaks when kernels are reported against
+ * their roofline: *copy_gbs, a device-to-device copy of 2 GiB (bytes read +
+ * written per second, 16-byte vector accesses; takes 4 GiB of device memory
+ * through ctx's allocator for the call); *lds_gbs, 16-byte LDS reads at
+ * conflict-free addresses by every lane of every CU.  Best of five timed
+ * launches each.  Either pointer may be NULL to skip that measurement. */
+gj_status gj_measure_peaks(gj_ctx* ctx, double* copy_gbs, double* lds_gbs);
 
 #ifdef __cplusplus
 }

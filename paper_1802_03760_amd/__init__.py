@@ -33,7 +33,7 @@ EXPORTS = ["gj_ctx_create", "gj_ctx_destroy", "gj_last_error", "gj_ctx_set_optio
            "gj_last_delta", "gj_run_batch", "gj_autotune", "gj_server_create", "gj_server_submit_count",
            "gj_server_submit_update", "gj_server_wait", "gj_server_get_stats", "gj_server_destroy",
            "gj_server_set_option", "gj_query_register_ex", "gj_graph_vertex_ids", "gj_query_register_rel",
-           "gj_graph_index_triangles"]
+           "gj_graph_index_triangles", "gj_measure_peaks"]
 REQ_COUNT, REQ_UPDATE = 0, 1
 SERVER_MAX_QUERIES = 16
 
@@ -94,7 +94,16 @@ class Stats(ctypes.Structure):
 
 
 _vp, _u64, _u32, _i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
-_lib.gj_ctx_create.argtypes = [_i32, _vp, ctypes.POINTER(_vp)]
+# gj_allocator: device memory callbacks (include/gj.h)
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class AllocatorStruct(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("user", ctypes.c_void_p)]
+
+
+_lib.gj_ctx_create.argtypes = [_i32, _vp, ctypes.POINTER(AllocatorStruct), ctypes.POINTER(_vp)]
 _lib.gj_ctx_create.restype = _i32
 _lib.gj_ctx_destroy.argtypes = [_vp]
 _lib.gj_ctx_destroy.restype = None
@@ -129,6 +138,8 @@ _lib.gj_query_destroy.argtypes = [_vp]
 _lib.gj_query_destroy.restype = None
 _lib.gj_run.argtypes = [_vp, _vp, _vp, _i32, _u64, _u64, _vp, _u64, _i32, ctypes.POINTER(Stats)]
 _lib.gj_run.restype = _i32
+_lib.gj_measure_peaks.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.gj_measure_peaks.restype = _i32
 _lib.gj_apply_updates.argtypes = [_vp, _vp, _vp, _vp, _vp, _u64, _i32, ctypes.POINTER(_vp), _u32,
                                   _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp,
                                   ctypes.POINTER(Stats)]
@@ -166,10 +177,11 @@ class _Handle:
     collector frees a reference cycle it clears weak references first and
     then calls __del__ in no particular order.)"""
 
-    __slots__ = ("h", "destroy", "deps", "parents")
+    __slots__ = ("h", "destroy", "deps", "parents", "keep")
 
-    def __init__(self, h, destroy, parents=()):
+    def __init__(self, h, destroy, parents=(), keep=None):
         self.h, self.destroy, self.deps, self.parents = h, destroy, {}, []
+        self.keep = keep  # kept alive until the handle is destroyed (e.g. allocator callbacks)
         for p in parents:
             self.depend(p)
 
@@ -186,6 +198,7 @@ class _Handle:
             d.close()
         h, self.h = self.h, None
         self.destroy(h)
+        self.keep = None
         for p in self.parents:
             p.deps.pop(id(self), None)
         self.parents = []
@@ -251,19 +264,72 @@ def _ptr(x):
     return _np_ptr(x)
 
 
+class DeviceAllocator:
+    """Device memory source of a context (gj_allocator).  Subclasses define
+    alloc(nbytes, stream) -> device address (0 when out of memory) and
+    free(ptr, stream); the library calls free only after its stream has
+    finished with the memory.  Exceptions in a callback count as a failed
+    allocation (alloc) or are dropped (free)."""
+
+    def alloc(self, nbytes, stream):
+        raise NotImplementedError
+
+    def free(self, ptr, stream):
+        raise NotImplementedError
+
+    def struct(self):
+        if getattr(self, "_struct", None) is None:
+            def a(user, nbytes, stream):
+                try:
+                    return int(self.alloc(int(nbytes), stream or 0) or 0)
+                except Exception:
+                    return 0
+
+            def f(user, ptr, stream):
+                try:
+                    self.free(int(ptr), stream or 0)
+                except Exception:
+                    pass
+            self._cb = (ALLOC_FN(a), FREE_FN(f))
+            self._struct = AllocatorStruct(self._cb[0], self._cb[1], None)
+        return self._struct
+
+
+class TorchAllocator(DeviceAllocator):
+    """Device memory from PyTorch's caching allocator, on the library's
+    stream."""
+
+    def __init__(self, device=0):
+        import torch
+        self.torch = torch
+        self.device = device
+
+    def alloc(self, nbytes, stream):
+        return self.torch.cuda.caching_allocator_alloc(nbytes, self.device, int(stream))
+
+    def free(self, ptr, stream):
+        self.torch.cuda.caching_allocator_delete(ptr)
+
+
 class Context(_Owner):
     """gj_ctx on one HIP device; issues work on `stream` (a torch.cuda.Stream,
-    a raw hipStream_t int, or None for the library's own stream)."""
+    a raw hipStream_t int, or None for the library's own stream) and takes
+    device memory from `allocator` (a DeviceAllocator, "torch" for
+    PyTorch's caching allocator, or None for hipMalloc)."""
 
-    def __init__(self, device=0, stream=None):
+    def __init__(self, device=0, stream=None, allocator=None):
         h = _vp()
         raw = None
         if stream is not None:
             raw = stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
-        st = _lib.gj_ctx_create(device, _vp(raw) if raw else None, ctypes.byref(h))
+        if allocator == "torch":
+            allocator = TorchAllocator(device)
+        ap = ctypes.byref(allocator.struct()) if allocator is not None else None
+        st = _lib.gj_ctx_create(device, _vp(raw) if raw else None, ap, ctypes.byref(h))
         if st != GJ_OK:
             raise GJError(st, "gj_ctx_create(device=%d) failed" % device)
-        self._hd = _Handle(h, _lib.gj_ctx_destroy)
+        self.allocator = allocator
+        self._hd = _Handle(h, _lib.gj_ctx_destroy, keep=allocator)
         self.device = device
         _roots[id(self._hd)] = self._hd
 
@@ -486,6 +552,13 @@ def enumerate_rows(ctx, graph, query, seed_lo=0, seed_hi=(1 << 64) - 1, out=None
                     on_dev, ctypes.byref(st))
     ctx.check(s, "gj_run(enumerate)")
     return st.as_dict(), out[: st.matches]
+
+
+def measure_peaks(ctx):
+    """gj_measure_peaks: measured device-copy and LDS bandwidth (GB/s)."""
+    cp, lds = ctypes.c_double(), ctypes.c_double()
+    ctx.check(_lib.gj_measure_peaks(ctx._h, ctypes.byref(cp), ctypes.byref(lds)), "gj_measure_peaks")
+    return {"copy_gbs": cp.value, "lds_gbs": lds.value}
 
 
 def apply_updates(ctx, graph, src, dst, sign, queries, rows=False, cap=1 << 16):

@@ -11,9 +11,14 @@
 
 namespace gj {
 
-void* dev_alloc(size_t bytes) {
+void* dev_alloc(gj_ctx* c, size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 16;
+  if (c->alloc.alloc) {
+    p = c->alloc.alloc(c->alloc.user, bytes, (void*)c->stream);
+    if (!p) throw Error{GJ_ENOMEM, "allocator returned no memory for " + std::to_string(bytes) + " bytes"};
+    return p;
+  }
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     (void)hipGetLastError();
@@ -22,8 +27,15 @@ void* dev_alloc(size_t bytes) {
   return p;
 }
 
-void dev_free(void* p) {
-  if (p) (void)hipFree(p);
+void dev_free(gj_ctx* c, void* p) {
+  if (!p) return;
+  if (c->alloc.alloc) {
+    // the device is done with p before the allocator may hand it out again
+    (void)hipStreamSynchronize(c->stream);
+    c->alloc.free(c->alloc.user, p, (void*)c->stream);
+    return;
+  }
+  (void)hipFree(p);
 }
 
 // Named grow-only workspace buffers owned by the context.
@@ -33,11 +45,11 @@ void* ws_get(gj_ctx* c, const std::string& name, size_t bytes) {
   size_t want = bytes + bytes / 8 + 256;
   if (b.p) {
     GJ_HIP(hipStreamSynchronize(c->stream));
-    dev_free(b.p);
+    dev_free(c, b.p);
     b.p = nullptr;
     b.bytes = 0;
   }
-  b.p = dev_alloc(want);
+  b.p = dev_alloc(c, want);
   b.bytes = want;
   return b.p;
 }
@@ -124,14 +136,16 @@ static gj_status guarded(gj_ctx* c, F&& f) {
 
 extern "C" {
 
-gj_status gj_ctx_create(int device, void* hip_stream, gj_ctx** out) {
+gj_status gj_ctx_create(int device, void* hip_stream, const gj_allocator* allocator, gj_ctx** out) {
   if (!out) return GJ_EINVAL;
   *out = nullptr;
+  if (allocator && (!allocator->alloc || !allocator->free)) return GJ_EINVAL;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return GJ_EDEVICE;
   gj_ctx* c = new (std::nothrow) gj_ctx();
   if (!c) return GJ_ENOMEM;
   c->device = device;
+  if (allocator) c->alloc = *allocator;
   gj_status s = guarded(c, [&] {
     if (hip_stream) {
       c->stream = (hipStream_t)hip_stream;
@@ -157,7 +171,7 @@ void gj_ctx_destroy(gj_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   gj::batch_destroy(c);
-  for (auto& kv : c->ws) gj::dev_free(kv.second.p);
+  for (auto& kv : c->ws) gj::dev_free(c, kv.second.p);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -182,6 +196,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "delta_owner_min") {
       GJ_CHECK(value >= 0, GJ_EINVAL, "delta_owner_min must be >= 0");
       c->delta_owner_min = (uint64_t)value;
+    } else if (k == "owner_task_min") {
+      GJ_CHECK(value >= 1 && value <= (1ll << 40), GJ_EINVAL, "owner_task_min out of range");
+      c->owner_task_min = (uint64_t)value;
     } else if (k == "delta_fused") {
       GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "delta_fused must be 0 or 1");
       c->delta_fused = (int)value;
@@ -235,6 +252,9 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "lsm_max_patch") *value = (int64_t)c->lsm_max_patch;
     else if (k == "lsm_compactions") *value = (int64_t)c->lsm_compactions;
     else if (k == "lsm_folds") *value = (int64_t)c->lsm_folds;
+    else if (k == "owner_task_min") *value = (int64_t)c->owner_task_min;
+    else if (k == "owner_tasks") *value = (int64_t)c->owner_tasks;
+    else if (k == "owner_split_units") *value = (int64_t)c->owner_split_units;
     else throw Error{GJ_EINVAL, "unknown option " + k};
   });
 }
@@ -314,10 +334,10 @@ void gj_graph_destroy(gj_graph* g) {
     (void)hipSetDevice(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
   }
-  for (auto& v : g->ver) gj::version_free(v);
+  for (auto& v : g->ver) gj::version_free(g->ctx, v);
   gj::lsm_free(g);
   gj::tri_index_free(g);
-  gj::dev_free(g->old_of_new);
+  gj::dev_free(g->ctx, g->old_of_new);
   delete g;
 }
 
@@ -627,7 +647,7 @@ gj_status reserve_version(gj_ctx* c, gj_graph* g, int b, uint64_t cap) {
   return guarded(c, [&] {
     GJ_CHECK(b >= 0 && b < kMaxVersions && b != g->cur, GJ_EINVAL, "bad version slot");
     Version& v = g->ver[b];
-    version_alloc(v, g->n, cap);
+    version_alloc(c, v, g->n, cap);
     // write the slot once now (a fill kernel), so that whatever the first
     // access to fresh device memory costs is paid here, not by an update
     for (int d = 0; d < 2; ++d) {
@@ -648,6 +668,7 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->batch_cap = src->batch_cap;
   dst->delta_fused = src->delta_fused;
   dst->delta_owner_min = src->delta_owner_min;
+  dst->owner_task_min = src->owner_task_min;
   dst->factorise = src->factorise;
   dst->propose_u = src->propose_u;
   dst->batch_heavy = src->batch_heavy;

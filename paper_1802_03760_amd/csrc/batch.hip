@@ -439,6 +439,7 @@ struct BatchExec::Impl {
   hipGraphExec_t exec = nullptr;
   unsigned grid_cfg = 0;
   std::vector<void*> allocs;
+  gj_ctx* owner = nullptr;  // the context whose allocator holds allocs
 
   uint64_t stat_words() const { return (uint64_t)max_req * (2 + 2 * kStat); }
   unsigned long long* cnt() { return d_stat; }
@@ -446,14 +447,14 @@ struct BatchExec::Impl {
   unsigned long long* pre() { return d_stat + 2ull * max_req; }
   unsigned long long* ext() { return d_stat + 2ull * max_req + (uint64_t)max_req * kStat; }
   void* alloc(size_t b) {
-    void* p = dev_alloc(b);
+    void* p = dev_alloc(owner, b);
     allocs.push_back(p);
     return p;
   }
   ~Impl() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
-    for (void* p : allocs) dev_free(p);
+    for (void* p : allocs) dev_free(owner, p);
     if (h_stage) (void)hipHostFree(h_stage);
   }
 };
@@ -500,6 +501,7 @@ void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t
     delete p;
     p = new Impl;
     Impl& t = *p;
+    t.owner = c;
     t.max_req = mr;
     t.max_m = mm;
     t.cap = cap;

@@ -433,7 +433,7 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
     // upper bound of the new edge count: old + all of dE, with slack so that a
     // growing graph does not reallocate the spare version on every batch
     uint64_t need = cur_view.m + k;
-    if (need > nv.cap) version_alloc(nv, n, need + need / 16 + (1u << 20));
+    if (need > nv.cap) version_alloc(c, nv, n, need + need / 16 + (1u << 20));
     uint32_t* mx = (uint32_t*)ws_get(c, "maxdeg", 2 * sizeof(uint32_t));
     GJ_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(uint32_t), c->stream));
     for (int d = 0; d < 2; ++d) {
@@ -577,8 +577,8 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
     gj_stats acc{};
     int64_t cd = 0;
     uint64_t raw = 0;
-    uint32_t* all_rows = nullptr;
-    int8_t* all_signs = nullptr;
+    // every dQ_i's signed rows, concatenated (freed on every exit)
+    DevMem all_rows_m, all_signs_m;
     uint64_t all_n = 0, all_cap = 0;
     for (int i = 0; i < (int)q->atoms.size(); ++i) {
       PlanH P = make_plan(q, delta_order(q, i), i);
@@ -598,29 +598,31 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
       if (matches) {
         if (all_n + matches > all_cap) {
           uint64_t ncap = std::max<uint64_t>(all_n + matches, all_cap * 2);
-          uint32_t* nr = (uint32_t*)dev_alloc(ncap * q->m * sizeof(uint32_t));
-          int8_t* ns = (int8_t*)dev_alloc(ncap);
+          DevMem nr(c, ncap * q->m * sizeof(uint32_t));
+          DevMem ns(c, ncap);
           if (all_n) {
-            GJ_HIP(hipMemcpyAsync(nr, all_rows, all_n * q->m * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
-            GJ_HIP(hipMemcpyAsync(ns, all_signs, all_n, hipMemcpyDeviceToDevice, c->stream));
+            GJ_HIP(hipMemcpyAsync(nr.get(), all_rows_m.get(), all_n * q->m * sizeof(uint32_t),
+                                  hipMemcpyDeviceToDevice, c->stream));
+            GJ_HIP(hipMemcpyAsync(ns.get(), all_signs_m.get(), all_n, hipMemcpyDeviceToDevice, c->stream));
             GJ_HIP(hipStreamSynchronize(c->stream));
           }
-          dev_free(all_rows);
-          dev_free(all_signs);
-          all_rows = nr;
-          all_signs = ns;
+          all_rows_m = std::move(nr);
+          all_signs_m = std::move(ns);
           all_cap = ncap;
         }
-        GJ_HIP(hipMemcpyAsync(all_rows + all_n * q->m, R.rows, matches * q->m * sizeof(uint32_t),
+        GJ_HIP(hipMemcpyAsync(all_rows_m.as<uint32_t>() + all_n * q->m, R.rows, matches * q->m * sizeof(uint32_t),
                               hipMemcpyDeviceToDevice, c->stream));
-        GJ_HIP(hipMemcpyAsync(all_signs + all_n, R.rsign, matches, hipMemcpyDeviceToDevice, c->stream));
+        GJ_HIP(hipMemcpyAsync(all_signs_m.as<int8_t>() + all_n, R.rsign, matches, hipMemcpyDeviceToDevice,
+                              c->stream));
         GJ_HIP(hipStreamSynchronize(c->stream));
         all_n += matches;
       }
     }
     uint64_t nd = 0;
     if (want_rows) {
-      try {
+      uint32_t* all_rows = all_rows_m.as<uint32_t>();
+      int8_t* all_signs = all_signs_m.as<int8_t>();
+      {
         gj_ctx::LastDelta& ld = c->last_delta[qi];
         ld.kept = true;
         ld.m = q->m;
@@ -640,13 +642,7 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
           GJ_HIP(hipStreamSynchronize(c->stream));
           if (nd > ucap) overflow = true;
         }
-      } catch (...) {
-        dev_free(all_rows);
-        dev_free(all_signs);
-        throw;
       }
-      dev_free(all_rows);
-      dev_free(all_signs);
     }
     if (count_delta) count_delta[qi] = cd;
     if (n_delta) n_delta[qi] = nd;

@@ -203,8 +203,8 @@ Runner::Runner(gj_ctx* c_, const PlanH& P_, const Views& V_, bool weighted_, boo
 }
 
 Runner::~Runner() {
-  if (rows_owned) dev_free(rows);
-  if (signs_owned) dev_free(rsign);
+  if (rows_owned) dev_free(c, rows);
+  if (signs_owned) dev_free(c, rsign);
 }
 
 void Runner::use_rows(uint32_t* dev_rows, int8_t* dev_signs, uint64_t cap) {
@@ -228,17 +228,18 @@ void Runner::ensure_rows(uint64_t need) {
   uint64_t want = std::max<uint64_t>(need, rows_alloc * 2);
   want = std::min<uint64_t>(std::max<uint64_t>(want, 1024), rcap);
   if (want <= rows_alloc) return;
-  uint32_t* nr = (uint32_t*)dev_alloc(want * P.m * sizeof(uint32_t));
-  int8_t* ns = want_signs ? (int8_t*)dev_alloc(want) : nullptr;
+  DevMem nr(c, want * P.m * sizeof(uint32_t));
+  DevMem ns;
+  if (want_signs) ns = DevMem(c, want);
   if (rows_alloc) {
-    GJ_HIP(hipMemcpyAsync(nr, rows, rows_alloc * P.m * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
-    if (ns) GJ_HIP(hipMemcpyAsync(ns, rsign, rows_alloc, hipMemcpyDeviceToDevice, c->stream));
+    GJ_HIP(hipMemcpyAsync(nr.get(), rows, rows_alloc * P.m * sizeof(uint32_t), hipMemcpyDeviceToDevice, c->stream));
+    if (ns.get()) GJ_HIP(hipMemcpyAsync(ns.get(), rsign, rows_alloc, hipMemcpyDeviceToDevice, c->stream));
     GJ_HIP(hipStreamSynchronize(c->stream));
   }
-  dev_free(rows);
-  dev_free(rsign);
-  rows = nr;
-  rsign = ns;
+  dev_free(c, rows);
+  dev_free(c, rsign);
+  rows = (uint32_t*)nr.release();
+  rsign = (int8_t*)ns.release();
   rows_alloc = want;
 }
 

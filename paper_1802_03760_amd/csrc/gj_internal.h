@@ -135,6 +135,7 @@ struct gj_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  gj_allocator alloc{};     // device memory source (alloc == null: hipMalloc / hipFree)
   std::string err;
   uint64_t frontier_cap = 1ull << 25;
   uint64_t seed_chunk = 1ull << 25;
@@ -167,6 +168,9 @@ struct gj_ctx {
   uint64_t lsm_max_patch = 0;  // arena entries per direction before a compaction (0: the slot's slack)
   uint64_t lsm_compactions = 0;  // compactions run on this context
   uint64_t lsm_folds = 0;  // batches written as a new version while appended rows were pending
+  uint64_t owner_task_min = 1ull << 20;  // least proposals per owner task (owner-grouped kernel)
+  uint64_t owner_tasks = 0;        // tasks of the last owner-grouped launch
+  uint64_t owner_split_units = 0;  // owner units of that launch cut into more than one task
 };
 
 // Resident versions of a graph: ver[cur] is current; an update reads it and
@@ -213,8 +217,48 @@ class KernelTimer {
 };
 
 void* ws_get(gj_ctx* c, const std::string& name, size_t bytes);
-void dev_free(void* p);
-void* dev_alloc(size_t bytes);
+// Device memory through the context's allocator (hipMalloc / hipFree without
+// one).  dev_alloc throws GJ_ENOMEM on failure; dev_free(c, null) is a no-op.
+void dev_free(gj_ctx* c, void* p);
+void* dev_alloc(gj_ctx* c, size_t bytes);
+
+// Device memory owned by one scope, freed on every exit (errors included).
+class DevMem {
+ public:
+  DevMem() = default;
+  DevMem(gj_ctx* c, size_t bytes) : c_(c), p_(dev_alloc(c, bytes)) {}
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  DevMem(DevMem&& o) noexcept : c_(o.c_), p_(o.p_) { o.p_ = nullptr; }
+  DevMem& operator=(DevMem&& o) noexcept {
+    if (this != &o) {
+      reset();
+      c_ = o.c_;
+      p_ = o.p_;
+      o.p_ = nullptr;
+    }
+    return *this;
+  }
+  ~DevMem() { reset(); }
+  void reset() {
+    if (p_) dev_free(c_, p_);
+    p_ = nullptr;
+  }
+  template <class T>
+  T* as() const {
+    return (T*)p_;
+  }
+  void* get() const { return p_; }
+  void* release() {
+    void* p = p_;
+    p_ = nullptr;
+    return p;
+  }
+
+ private:
+  gj_ctx* c_ = nullptr;
+  void* p_ = nullptr;
+};
 uint64_t read_u64(gj_ctx* c, const void* dptr);
 void read_bytes(gj_ctx* c, void* host, const void* dptr, size_t bytes);
 // several device words, one synchronisation
@@ -251,8 +295,8 @@ void graph_build(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32_t* 
 // (both directions when `undirected`).  Sets g->old_of_new when renaming.
 void graph_build_sym(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32_t* d_dst, uint64_t m,
                      bool degree_order, bool undirected);
-void version_alloc(Version& v, uint32_t n, uint64_t cap);
-void version_free(Version& v);
+void version_alloc(gj_ctx* c, Version& v, uint32_t n, uint64_t cap);
+void version_free(gj_ctx* c, Version& v);
 // Log-structured updates: merge the rewritten rows into a compacted slot
 // (no-op when none are); release the maps.
 void graph_compact(gj_ctx* c, gj_graph* g);

@@ -86,27 +86,30 @@ __global__ void __launch_bounds__(kBlock) k_maxdeg(const uint32_t* __restrict__ 
   }
 }
 
-void version_alloc(Version& v, uint32_t n, uint64_t cap) {
+void version_alloc(gj_ctx* c, Version& v, uint32_t n, uint64_t cap) {
   if (cap < 1) cap = 1;
   for (int d = 0; d < 2; ++d) {
-    if (!v.d[d].rp) v.d[d].rp = (uint32_t*)dev_alloc(((uint64_t)n + 1) * sizeof(uint32_t));
+    if (!v.d[d].rp) v.d[d].rp = (uint32_t*)dev_alloc(c, ((uint64_t)n + 1) * sizeof(uint32_t));
     if (cap > v.cap) {
-      dev_free(v.d[d].col);
-      dev_free(v.d[d].row);
+      // a failure part-way leaves this direction without arrays and the
+      // slot's capacity at 0, so the next call allocates them again
+      dev_free(c, v.d[d].col);
+      dev_free(c, v.d[d].row);
       v.d[d].col = nullptr;
       v.d[d].row = nullptr;
-      v.d[d].col = (uint32_t*)dev_alloc(cap * sizeof(uint32_t));
-      v.d[d].row = (uint32_t*)dev_alloc(cap * sizeof(uint32_t));
+      if (d == 0) v.cap = 0;
+      v.d[d].col = (uint32_t*)dev_alloc(c, cap * sizeof(uint32_t));
+      v.d[d].row = (uint32_t*)dev_alloc(c, cap * sizeof(uint32_t));
     }
   }
   if (cap > v.cap) v.cap = cap;
 }
 
-void version_free(Version& v) {
+void version_free(gj_ctx* c, Version& v) {
   for (int d = 0; d < 2; ++d) {
-    dev_free(v.d[d].rp);
-    dev_free(v.d[d].col);
-    dev_free(v.d[d].row);
+    dev_free(c, v.d[d].rp);
+    dev_free(c, v.d[d].col);
+    dev_free(c, v.d[d].row);
     v.d[d] = CsrDir{};
   }
   v.cap = v.m = 0;
@@ -158,7 +161,7 @@ void graph_build(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32_t* 
   Version& v = g->ver[g->cur];
   // the same growth room as the versions updates write, so that no slot is
   // reallocated when updates come back round to it
-  version_alloc(v, n, mu + mu / 16 + (1ull << 20));
+  version_alloc(c, v, n, mu + mu / 16 + (1ull << 20));
   v.m = mu;
   if (m) k_compact_edges<<<gr, kBlock, 0, c->stream>>>(sorted, m, flags, off, v.d[0].row, v.d[0].col, other);
   uint64_t* other_alt = sorted;  // free for reuse now
@@ -219,13 +222,14 @@ void graph_build_sym(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32
   int bits = bits_for(n);
   uint64_t m2 = 2 * m;
   struct Temps {  // freed on every exit, errors included
+    gj_ctx* c;
     std::vector<void*> p;
     ~Temps() {
-      for (void* x : p) dev_free(x);
+      for (void* x : p) dev_free(c, x);
     }
-  } tmp;
+  } tmp{c, {}};
   auto alloc = [&](size_t bytes) {
-    void* p = dev_alloc(bytes ? bytes : 1);
+    void* p = dev_alloc(c, bytes ? bytes : 1);
     tmp.p.push_back(p);
     return p;
   };
@@ -260,7 +264,7 @@ void graph_build_sym(gj_ctx* c, gj_graph* g, const uint32_t* d_src, const uint32
     k_rowptr<<<gn, kBlock, 0, c->stream>>>(srow, ms, n, rp);
     k_degree_keys<<<gn, kBlock, 0, c->stream>>>(rp, n, vk);
     uint64_t* vs = sort_u64(c, vk, vk2, n, bits, bits);
-    g->old_of_new = (uint32_t*)dev_alloc((uint64_t)n * sizeof(uint32_t));
+    g->old_of_new = (uint32_t*)dev_alloc(c, (uint64_t)n * sizeof(uint32_t));
     k_rank_ids<<<gn, kBlock, 0, c->stream>>>(vs, n, g->old_of_new, new_of_old);
     uint32_t* osrc = (uint32_t*)alloc((ms + 1) * sizeof(uint32_t));
     uint32_t* odst = (uint32_t*)alloc((ms + 1) * sizeof(uint32_t));

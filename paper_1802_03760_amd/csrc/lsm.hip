@@ -203,21 +203,21 @@ static void lsm_alloc(gj_ctx* c, gj_graph* g) {
   for (int b = 0; b < 2; ++b)
     for (int d = 0; d < 2; ++d) {
       if (L.map[b][d]) continue;
-      uint64_t* p = (uint64_t*)dev_alloc(bytes);
+      uint64_t* p = (uint64_t*)dev_alloc(c, bytes);
       hipError_t e = hipMemsetAsync(p, 0xFF, bytes, c->stream);
-      if (e != hipSuccess) dev_free(p);
+      if (e != hipSuccess) dev_free(c, p);
       GJ_HIP(e);
       L.map[b][d] = p;
     }
   for (int d = 0; d < 2; ++d)
-    if (!L.keys[d]) L.keys[d] = (uint32_t*)dev_alloc((uint64_t)g->n * sizeof(uint32_t));
+    if (!L.keys[d]) L.keys[d] = (uint32_t*)dev_alloc(c, (uint64_t)g->n * sizeof(uint32_t));
 }
 
 void lsm_free(gj_graph* g) {
   LsmState& L = g->lsm;
   for (int b = 0; b < 2; ++b)
-    for (int d = 0; d < 2; ++d) dev_free(L.map[b][d]);
-  for (int d = 0; d < 2; ++d) dev_free(L.keys[d]);
+    for (int d = 0; d < 2; ++d) dev_free(g->ctx, L.map[b][d]);
+  for (int d = 0; d < 2; ++d) dev_free(g->ctx, L.keys[d]);
   L = LsmState{};
 }
 
@@ -262,7 +262,7 @@ void graph_compact(gj_ctx* c, gj_graph* g) {
   // entries per direction, reallocated only when less than half of that is
   // left (a graph that grows would otherwise reallocate at every compaction)
   uint64_t room = m / 2 + (1ull << 22);
-  if (m + room / 2 > nv.cap) version_alloc(nv, n, m + room);
+  if (m + room / 2 > nv.cap) version_alloc(c, nv, n, m + room);
   uint32_t* deg = (uint32_t*)ws_get(c, "lsm_deg", ((uint64_t)n + 1) * sizeof(uint32_t));
   for (int d = 0; d < 2; ++d) {
     const uint64_t* pm = L.map[L.cur_map][d];

@@ -77,7 +77,8 @@ __global__ void k_owner_vals(OwnerArgs a, uint32_t r, const uint32_t* __restrict
 
 // task count of every unit: work / task size, at most one task per partner
 __global__ void k_owner_units(OwnerArgs a, const uint64_t* __restrict__ wscan0, const uint64_t* __restrict__ wscan1,
-                              uint64_t tw_min, uint32_t* __restrict__ ntasks) {
+                              uint64_t tw_min, uint32_t* __restrict__ ntasks,
+                              unsigned long long* __restrict__ nsplit) {
   uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t u = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; u < 2ull * a.n; u += gs) {
     uint32_t v = (uint32_t)(u >> 1), r = (uint32_t)(u & 1);
@@ -95,6 +96,7 @@ __global__ void k_owner_units(OwnerArgs a, const uint64_t* __restrict__ wscan0, 
       nt = (uint32_t)(k < P ? k : P);
     }
     ntasks[u] = nt;
+    if (nt > 1) atomicAdd(nsplit, 1ull);
   }
 }
 
@@ -473,11 +475,12 @@ void owner_count(gj_ctx* c, const OwnerArgs& a, const uint32_t* seed_row, const 
   uint64_t units = 2ull * a.n;
   uint32_t* ntasks = (uint32_t*)ws_get(c, "own_nt", (units + 1) * sizeof(uint32_t));
   uint64_t* toff = (uint64_t*)ws_get(c, "own_toff", (units + 1) * sizeof(uint64_t));
-  unsigned long long* acc = (unsigned long long*)ws_get(c, "own_acc", 3 * sizeof(unsigned long long));
+  // acc: matches, extensions, signed sum, units split into several tasks
+  unsigned long long* acc = (unsigned long long*)ws_get(c, "own_acc", 4 * sizeof(unsigned long long));
   unsigned int* counter = (unsigned int*)ws_get(c, "own_ctr", sizeof(unsigned int));
-  GJ_HIP(hipMemsetAsync(acc, 0, 3 * sizeof(unsigned long long), c->stream));
+  GJ_HIP(hipMemsetAsync(acc, 0, 4 * sizeof(unsigned long long), c->stream));
   GJ_HIP(hipMemsetAsync(counter, 0, sizeof(unsigned int), c->stream));
-  const uint64_t tw_min = 1ull << 20;
+  const uint64_t tw_min = c->owner_task_min;
   uint32_t* vals = (uint32_t*)ws_get(c, "own_vals", (E + 1) * sizeof(uint32_t));
   uint64_t* wscan0 = (uint64_t*)ws_get(c, "own_ws0", (E + 1) * sizeof(uint64_t));
   uint64_t* wscan1 = (uint64_t*)ws_get(c, "own_ws1", (E + 1) * sizeof(uint64_t));
@@ -486,7 +489,8 @@ void owner_count(gj_ctx* c, const OwnerArgs& a, const uint32_t* seed_row, const 
   scan_u32_to_u64(c, vals, wscan0, E);
   if (E) k_owner_vals<<<ge, kBlock, 0, c->stream>>>(a, 1, t_row, t_col, E, vals);
   scan_u32_to_u64(c, vals, wscan1, E);
-  k_owner_units<<<grid_for(units, kBlock, 1u << 16), kBlock, 0, c->stream>>>(a, wscan0, wscan1, tw_min, ntasks);
+  k_owner_units<<<grid_for(units, kBlock, 1u << 16), kBlock, 0, c->stream>>>(a, wscan0, wscan1, tw_min, ntasks,
+                                                                             acc + 3);
   scan_u32_to_u64(c, ntasks, toff, units);
   uint64_t nt = read_u64(c, toff + units);
   GJ_CHECK(nt < (1ull << 32), GJ_EUNSUPPORTED, "too many owner tasks");
@@ -502,8 +506,10 @@ void owner_count(gj_ctx* c, const OwnerArgs& a, const uint32_t* seed_row, const 
     k_owner_count<false><<<grid, kOwnNT, 0, c->stream>>>(a, tasks, (uint32_t)nt, counter, seed_row, seed_col, E, acc);
   timer.stop();
   GJ_HIP(hipGetLastError());
-  unsigned long long h[3];
+  unsigned long long h[4];
   read_bytes(c, h, acc, sizeof(h));
+  c->owner_tasks = nt;
+  c->owner_split_units = h[3];
   matches = h[0];
   extensions = h[1];
   if (wsum) *wsum = a.sg0 ? (int64_t)h[2] : (int64_t)h[0];

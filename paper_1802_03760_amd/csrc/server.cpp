@@ -602,7 +602,7 @@ gj_status gj_server_create(gj_ctx* ctx, gj_graph* g, uint32_t max_batch, uint64_
   s->g = g;
   s->max_batch = max_batch;
   s->mem_budget = mem_budget_bytes;
-  gj_status st = gj_ctx_create(ctx->device, nullptr, &s->cctx);
+  gj_status st = gj_ctx_create(ctx->device, nullptr, ctx->alloc.alloc ? &ctx->alloc : nullptr, &s->cctx);
   if (st != GJ_OK) {
     delete s;
     return st;
@@ -640,7 +640,7 @@ static gj_status enqueue_req(gj_server* s, Req&& r, uint64_t* ticket) {
       // created now, so that only the lanes in use take hardware queues)
       for (int l = 0; l < s->heavy_lanes; ++l) {
         gj_ctx* c = nullptr;
-        gj_status st = gj_ctx_create(s->ctx->device, nullptr, &c);
+        gj_status st = gj_ctx_create(s->ctx->device, nullptr, s->ctx->alloc.alloc ? &s->ctx->alloc : nullptr, &c);
         if (st != GJ_OK) break;
         gj::copy_options(c, s->ctx);
         s->hctx.push_back(c);

@@ -24,8 +24,8 @@ __global__ void k_add_base(const uint64_t* __restrict__ scan, uint64_t k, uint64
 }
 
 void tri_index_free(gj_graph* g) {
-  dev_free(g->tri.rp);
-  dev_free(g->tri.col);
+  dev_free(g->ctx, g->tri.rp);
+  dev_free(g->ctx, g->tri.col);
   g->tri = TriIndex{};
 }
 
@@ -36,7 +36,7 @@ void tri_index_build(gj_ctx* c, gj_graph* g) {
   // owned by the graph from the start (freed by gj_graph_destroy or the next
   // build if this one fails); valid once version and slot are set at the end
   TriIndex& t = g->tri;
-  t.rp = (uint64_t*)dev_alloc((m + 1) * sizeof(uint64_t));
+  t.rp = (uint64_t*)dev_alloc(c, (m + 1) * sizeof(uint64_t));
   // third attribute bound by out(x) and out(y)
   StageDesc d;
   memset(&d, 0, sizeof(d));
@@ -81,7 +81,7 @@ void tri_index_build(gj_ctx* c, gj_graph* g) {
   }
   if (m == 0) GJ_HIP(hipMemsetAsync(t.rp, 0, sizeof(uint64_t), c->stream));
   t.size = base.back();
-  t.col = (uint32_t*)dev_alloc(std::max<uint64_t>(t.size, 1) * sizeof(uint32_t));
+  t.col = (uint32_t*)dev_alloc(c, std::max<uint64_t>(t.size, 1) * sizeof(uint32_t));
   // pass 2: the same proposals, survivors' values in candidate order
   size_t ci = 0;
   for (uint64_t s = 0; s < m; s += chunk, ++ci) {

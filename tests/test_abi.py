@@ -94,3 +94,19 @@ def test_release_order_in_a_collected_cycle():
         del c, g, q, s, o, objs
         gc.collect()
         _check_order(log)
+
+
+def test_device_memory_only_through_dev_alloc():
+    """Device memory is taken in one place, which uses the context's
+    allocator when one was given (gj_allocator); the only other device
+    buffer is the allocation-free path's static scratch array."""
+    csrc = os.path.join(ROOT, "paper_1802_03760_amd", "csrc")
+    sites = []
+    for f in sorted(os.listdir(csrc)):
+        t = open(os.path.join(csrc, f)).read()
+        for name in ("hipMalloc(", "hipMallocAsync(", "hipExtMallocWithFlags(", "hipMallocManaged("):
+            sites += [f] * t.count(name)
+    assert sites == ["api.hip"]
+    api = open(os.path.join(csrc, "api.hip")).read()
+    start = api.index("void* dev_alloc(gj_ctx* c, size_t bytes)")
+    assert api.index("hipMalloc(") > start and api.index("hipMalloc(") < api.index("void dev_free(")
