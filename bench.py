@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one k_owner_count launch on this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB device copy in the same
 # run; valid only for the kernel source it was measured on (sha256 prefix).
-MEASURED_TRAFFIC = {"owner.hip": "acc8f2abfea5e5bd", "bytes": 127.05e9 + 1.089e9}
+MEASURED_TRAFFIC = {"owner.hip": "908ac2248e19ea0d", "bytes": 127.18e9 + 1.087e9}
 TRIANGLE = (3, [(0, 1), (1, 2), (0, 2)], [0, 1, 2])
 
 
@@ -647,6 +647,9 @@ def main():
     ap.add_argument("--clique-leg", type=int, default=1,
                     help="whole-graph 4-clique and diamond counts on the benchmark graph (0: skip)")
     ap.add_argument("--no-peaks", action="store_true", help="skip the copy / LDS bandwidth calibration")
+    ap.add_argument("--hash-index", type=int, default=-1, help="option hash_index of the contexts (-1: default)")
+    ap.add_argument("--hash-min-degree", type=int, default=0, help="option hash_min_degree (0: default)")
+    ap.add_argument("--hash-build-work", type=int, default=-1, help="option hash_build_work (-1: default)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of known "
                          "traffic that scales the HBM counters of a profiling run")
@@ -668,6 +671,12 @@ def main():
     # PyTorch supplies the stream and every device allocation of the library
     ctx = gj.Context(0, stream, allocator="torch")
     ctx.set_option("strategy", args.strategy)
+    if args.hash_index >= 0:
+        ctx.set_option("hash_index", args.hash_index)
+    if args.hash_min_degree:
+        ctx.set_option("hash_min_degree", args.hash_min_degree)
+    if args.hash_build_work >= 0:
+        ctx.set_option("hash_build_work", args.hash_build_work)
     peaks = None if args.no_peaks else gj.measure_peaks(ctx)
     if peaks:
         log("measured peaks: device copy %.0f GB/s, LDS read %.0f GB/s" % (peaks["copy_gbs"], peaks["lds_gbs"]))

@@ -86,6 +86,9 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   extension sets of at most this size (default 8)
  *   "batch_waves_per_cu"  gj_run_batch: resident waves per CU of its
  *                   persistent grids, a multiple of 4 in [4, 128] (default 32)
+ *   "batch_claim_words"  gj_run_batch: words of 64 candidates a wave of the
+ *                   fused propose kernel claims from the device counter at a
+ *                   time, 1..4096 (default 16)
  *   "batch_cap"     gj_run_batch: prefixes per level (default 2^27)
  *   "batch_heavy"   gj_run_batch: requests whose estimated work (the
  *                   server's seed-work estimate) reaches this run on the
@@ -106,6 +109,25 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   cut into tasks of partner ranges of at least this many
  *                   proposals and at least 8 x the owner's set size (default
  *                   2^20, >= 1)
+ *   "hash_index"    membership tests of the generic propose kernels
+ *                   (Sec. 2.2: O(1) membership in an extension set): 1
+ *                   (default) gives a graph version a per-row open-addressing
+ *                   table (four-slot buckets at load <= 1/2) for every row of
+ *                   at least "hash_min_degree" entries in both directions
+ *                   (about 12 bytes per such entry and direction, plus 8 per
+ *                   vertex; kept until the version is rewritten or the graph
+ *                   destroyed) once the static reads of that version
+ *                   (gj_run, gj_run_batch, gj_autotune) have proposed
+ *                   "hash_build_work" candidates per edge, and then probes it
+ *                   instead of searching the row; the server and delta
+ *                   queries use tables built this way but build none; 2 also
+ *                   lets the server build them; 0 searches every row.
+ *                   Results are the same either way
+ *   "hash_min_degree"  rows of at least this many entries get a table
+ *                   (default 32, >= 1)
+ *   "hash_build_work"  candidates per edge that static reads of a version
+ *                   propose before its tables are built (default 16; 0: at
+ *                   the first read that tests membership)
  *   "propose_u"     candidates per lane whose membership searches the
  *                   generic propose kernel runs in lockstep: 1, 2 or 4
  *                   (default 4; at most 2 in stages with ternary atoms)
@@ -146,7 +168,8 @@ gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
 /* Reads an option (keys above, plus "batch_cap", the counters
  * "lsm_compactions" and "lsm_folds" of this context (see "lsm_updates"),
  * the counter "batch_fallbacks" (gj_run_batch calls that fell back to the
- * depth-first path), and of the last owner-grouped launch on this context
+ * depth-first path), "hash_builds" (membership indexes this context built),
+ * and of the last owner-grouped launch on this context
  * "owner_tasks" (its tasks) and "owner_split_units" (units cut into more
  * than one task)). */
 gj_status gj_ctx_get_option(gj_ctx* ctx, const char* key, int64_t* value);
@@ -342,16 +365,24 @@ gj_status gj_run_batch(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_q
 typedef struct {
   uint32_t batch_lin;          /* linear search below this extension-set size */
   uint32_t batch_waves_per_cu; /* waves per CU of the persistent grids */
-  double best_ms;              /* device time of the chosen configuration (-1: cached) */
+  uint32_t batch_claim_words;  /* words of 64 candidates a fused-propose wave claims at a time */
+  uint32_t hash_index;         /* membership tests: 1 per-row hash tables, 0 row searches */
+  uint32_t propose_u;          /* lockstep width of the depth-first propose kernel */
+  uint64_t batch_heavy;        /* work bound from which a request runs depth-first (0: all fused) */
+  double best_ms;              /* wall time of the chosen configuration (-1: cached) */
   int configs_tried;
   int from_cache;
 } gj_tuning;
 
-/* Times every candidate configuration of gj_run_batch on this batch, keeps the
- * fastest in ctx (options "batch_lin", "batch_waves_per_cu") and, if
- * cache_path is not NULL, records it in that JSON file keyed by graph size and
- * query set (a cached key is reused without timing).  All configurations
- * must agree on the counts (else GJ_EDEVICE).  out may be NULL. */
+/* Tunes gj_run_batch on this batch by coordinate descent: the options
+ * "hash_index" (0 or 1), "batch_lin" (0, 8, 32, 128), "batch_waves_per_cu"
+ * (16, 32, 64), "batch_claim_words" (4, 16, 64), "batch_heavy" (0, 2^22,
+ * 2^24, 2^26) and "propose_u" (1, 2, 4) in turn, each value timed (wall time
+ * of the whole call, best of two after a warm-up) with the others at their
+ * best so far.  Keeps the fastest in ctx and, if cache_path is not NULL,
+ * records it in that JSON file keyed by graph size and query set (a cached
+ * key is reused without timing).  All configurations must agree on the
+ * counts (else GJ_EDEVICE).  out may be NULL. */
 gj_status gj_autotune(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_query* const* qs,
                       const uint64_t* seed_lo, const uint64_t* seed_hi, const char* cache_path,
                       gj_tuning* out);

@@ -52,6 +52,8 @@ class TriAtom(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("batch_lin", ctypes.c_uint32), ("batch_waves_per_cu", ctypes.c_uint32),
+                ("batch_claim_words", ctypes.c_uint32), ("hash_index", ctypes.c_uint32),
+                ("propose_u", ctypes.c_uint32), ("batch_heavy", ctypes.c_uint64),
                 ("best_ms", ctypes.c_double), ("configs_tried", ctypes.c_int),
                 ("from_cache", ctypes.c_int)]
 
@@ -533,6 +535,8 @@ def autotune(ctx, graph, requests, cache_path=None):
                                cache_path.encode() if cache_path else None, ctypes.byref(out)),
               "gj_autotune")
     return {"batch_lin": out.batch_lin, "batch_waves_per_cu": out.batch_waves_per_cu,
+            "batch_claim_words": out.batch_claim_words, "hash_index": out.hash_index,
+            "propose_u": out.propose_u, "batch_heavy": out.batch_heavy,
             "best_ms": out.best_ms, "configs_tried": out.configs_tried, "from_cache": bool(out.from_cache)}
 
 

@@ -199,6 +199,15 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "owner_task_min") {
       GJ_CHECK(value >= 1 && value <= (1ll << 40), GJ_EINVAL, "owner_task_min out of range");
       c->owner_task_min = (uint64_t)value;
+    } else if (k == "hash_index") {
+      GJ_CHECK(value >= 0 && value <= 2, GJ_EINVAL, "hash_index must be 0, 1 or 2");
+      c->hash_index = (int)value;
+    } else if (k == "hash_min_degree") {
+      GJ_CHECK(value >= 1 && value <= (1ll << 31), GJ_EINVAL, "hash_min_degree out of range");
+      c->hash_min_degree = (uint32_t)value;
+    } else if (k == "hash_build_work") {
+      GJ_CHECK(value >= 0, GJ_EINVAL, "hash_build_work must be >= 0");
+      c->hash_build_work = (uint64_t)value;
     } else if (k == "delta_fused") {
       GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "delta_fused must be 0 or 1");
       c->delta_fused = (int)value;
@@ -223,6 +232,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "batch_lin") {
       GJ_CHECK(value >= 0 && value <= 4096, GJ_EINVAL, "batch_lin out of range");
       c->batch_lin = (uint32_t)value;
+    } else if (k == "batch_claim_words") {
+      GJ_CHECK(value >= 1 && value <= 4096, GJ_EINVAL, "batch_claim_words out of range");
+      c->batch_claim_words = (uint32_t)value;
     } else if (k == "batch_waves_per_cu") {
       GJ_CHECK(value >= 4 && value <= 128 && value % 4 == 0, GJ_EINVAL, "batch_waves_per_cu out of range");
       c->batch_waves_per_cu = (uint32_t)value;
@@ -242,6 +254,7 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "batch_cap") *value = (int64_t)c->batch_cap;
     else if (k == "batch_lin") *value = c->batch_lin;
     else if (k == "batch_waves_per_cu") *value = c->batch_waves_per_cu;
+    else if (k == "batch_claim_words") *value = c->batch_claim_words;
     else if (k == "batch_fallbacks") *value = (int64_t)c->batch_fallbacks;
     else if (k == "delta_fused") *value = c->delta_fused;
     else if (k == "delta_owner_min") *value = (int64_t)c->delta_owner_min;
@@ -253,6 +266,10 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "lsm_compactions") *value = (int64_t)c->lsm_compactions;
     else if (k == "lsm_folds") *value = (int64_t)c->lsm_folds;
     else if (k == "owner_task_min") *value = (int64_t)c->owner_task_min;
+    else if (k == "hash_index") *value = c->hash_index;
+    else if (k == "hash_min_degree") *value = c->hash_min_degree;
+    else if (k == "hash_build_work") *value = (int64_t)c->hash_build_work;
+    else if (k == "hash_builds") *value = (int64_t)c->hash_builds;
     else if (k == "owner_tasks") *value = (int64_t)c->owner_tasks;
     else if (k == "owner_split_units") *value = (int64_t)c->owner_split_units;
     else throw Error{GJ_EINVAL, "unknown option " + k};
@@ -334,7 +351,10 @@ void gj_graph_destroy(gj_graph* g) {
     (void)hipSetDevice(g->ctx->device);
     (void)hipStreamSynchronize(g->ctx->stream);
   }
-  for (auto& v : g->ver) gj::version_free(g->ctx, v);
+  for (auto& v : g->ver) {
+    gj::hash_free(g->ctx, v);
+    gj::version_free(g->ctx, v);
+  }
   gj::lsm_free(g);
   gj::tri_index_free(g);
   gj::dev_free(g->ctx, g->old_of_new);
@@ -569,7 +589,14 @@ void count_batch(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* co
       return;
     }
   }
+  hash_note_work(c, g, ver ? *ver : g->ver[g->cur], 0);
   count_fused(c, g, nreq, qs, seed_lo, seed_hi, counts, stats, ver);
+  if (stats) {
+    uint64_t W = 0;
+    for (uint32_t i = 0; i < nreq; ++i)
+      for (int j = 3; j <= GJ_MAX_ATTRS; ++j) W += stats[i].extensions[j];
+    hash_note_work(c, g, ver ? *ver : g->ver[g->cur], W);
+  }
 }
 
 // One fused run, or depth-first runs if a level outgrew the batch capacity.
@@ -596,6 +623,8 @@ gj_status count_on_versions(gj_ctx* c, const gj_graph* g, const Version* const* 
                             uint64_t* counts, gj_stats* stats) {
   return guarded(c, [&] {
     for (uint32_t i = 0; i < nreq; ++i) GJ_CHECK(qs[i] && vers[i], GJ_EINVAL, "null query or version");
+    for (uint32_t i = 0; i < nreq; ++i)
+      if (i == 0 || vers[i] != vers[i - 1]) hash_note_work(c, g, *vers[i], 0);
     if (nreq == 1) {
       // alone: the depth-first path, no fused-level overhead
       gj_stats st{};
@@ -648,6 +677,7 @@ gj_status reserve_version(gj_ctx* c, gj_graph* g, int b, uint64_t cap) {
     GJ_CHECK(b >= 0 && b < kMaxVersions && b != g->cur, GJ_EINVAL, "bad version slot");
     Version& v = g->ver[b];
     version_alloc(c, v, g->n, cap);
+    ++v.gen;
     // write the slot once now (a fill kernel), so that whatever the first
     // access to fresh device memory costs is paid here, not by an update
     for (int d = 0; d < 2; ++d) {
@@ -665,10 +695,14 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->strategy = src->strategy;
   dst->batch_lin = src->batch_lin;
   dst->batch_waves_per_cu = src->batch_waves_per_cu;
+  dst->batch_claim_words = src->batch_claim_words;
   dst->batch_cap = src->batch_cap;
   dst->delta_fused = src->delta_fused;
   dst->delta_owner_min = src->delta_owner_min;
   dst->owner_task_min = src->owner_task_min;
+  dst->hash_index = src->hash_index;
+  dst->hash_min_degree = src->hash_min_degree;
+  dst->hash_build_work = src->hash_build_work;
   dst->factorise = src->factorise;
   dst->propose_u = src->propose_u;
   dst->batch_heavy = src->batch_heavy;

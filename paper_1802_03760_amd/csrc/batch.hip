@@ -42,13 +42,13 @@ struct BReq {
 struct BHead {
   uint32_t nreq;
   uint32_t lin;        // tuned: linear search below this extension-set size
+  uint32_t claim_words;  // tuned: words (64 candidates each) a wave claims at a time
   uint64_t seeds;      // total seed edges over all requests
   unsigned long long nlev[GJ_MAX_ATTRS + 1];
   unsigned long long claim[GJ_MAX_ATTRS + 1];  // next unclaimed word chunk per level
   uint32_t overflow;
 };
 
-constexpr uint32_t kChunkWords = 16;  // 1024 candidates claimed at a time
 
 constexpr int kStat = GJ_MAX_ATTRS + 1;
 
@@ -247,19 +247,20 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
   const uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
   const uint64_t W = off[n];
   const uint32_t lin = H->lin;
+  const uint64_t claim = H->claim_words;
   const int lane = lane_id();
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
   const uint64_t nwords = (W + 63) >> 6;
   (void)nwaves;
   WaveAcc a_pre, a_cnt, a_ws;
-  // waves claim chunks of kChunkWords words from a device counter and walk
-  // each chunk galloping forward over the prefixes
+  // waves claim chunks of `claim` words from a device counter and walk each
+  // chunk galloping forward over the prefixes
   for (;;) {
     uint64_t cb = 0;
     if (lane == 0) cb = atomicAdd(&H->claim[j], 1ull);
-    cb = shfl_u64(cb, 0) * kChunkWords;
+    cb = shfl_u64(cb, 0) * claim;
     if (cb >= nwords) break;
-    uint64_t ce = cb + kChunkWords < nwords ? cb + kChunkWords : nwords;
+    uint64_t ce = cb + claim < nwords ? cb + claim : nwords;
     uint64_t plo = find_segment(off, 0, n, cb << 6);
   for (uint64_t wd = cb; wd < ce; ++wd) {
     uint64_t gf = wd << 6;
@@ -303,8 +304,13 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
         for (int a = 0; a < kMaxBind; ++a) {
           if (a < d.k && a != am && keep) {
             uint32_t u = F[(uint64_t)d.col[a] * cap + p], lo, hi;
-            row_range(d.rp[a], d.pm[a], u, lo, hi);
-            keep = member(d.adj[a], lo, hi, e, lin);
+            uint64_t dd = d.hd[a] ? d.hd[a][u] : 0ull;
+            if (dd) {
+              keep = hash_member(d.hs[a], dd, e);
+            } else {
+              row_range(d.rp[a], d.pm[a], u, lo, hi);
+              keep = member(d.adj[a], lo, hi, e, lin);
+            }
           }
         }
         fin = mc == (uint32_t)(j + 1);
@@ -555,6 +561,7 @@ void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t
   ho[nreq] = tot;
   hh->nreq = nreq;
   hh->lin = c->batch_lin;
+  hh->claim_words = c->batch_claim_words;
   hh->seeds = tot;
   GJ_HIP(hipMemcpyAsync(t.d_req, hr, sizeof(BReq) * nreq, hipMemcpyHostToDevice, c->stream));
   GJ_HIP(hipMemcpyAsync(t.d_roff, ho, sizeof(uint64_t) * (nreq + 1), hipMemcpyHostToDevice, c->stream));

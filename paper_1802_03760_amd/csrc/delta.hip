@@ -434,6 +434,7 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
     // growing graph does not reallocate the spare version on every batch
     uint64_t need = cur_view.m + k;
     if (need > nv.cap) version_alloc(c, nv, n, need + need / 16 + (1u << 20));
+    ++nv.gen;  // rewritten from here on: its membership index no longer holds
     uint32_t* mx = (uint32_t*)ws_get(c, "maxdeg", 2 * sizeof(uint32_t));
     GJ_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(uint32_t), c->stream));
     for (int d = 0; d < 2; ++d) {

@@ -51,6 +51,8 @@ struct Views {
   const Version* new_v;
   int delta_atom;  // -1: every atom reads old_v
   const TriIndex* tri = nullptr;  // for ternary atoms (static runs)
+  bool hash = true;               // membership indexes may be used where built
+  const gj_graph* graph = nullptr;  // static reads: the graph whose indexes may be built
   const Version& of(int atom) const {
     return (delta_atom >= 0 && atom < delta_atom) ? *new_v : *old_v;
   }

@@ -104,6 +104,10 @@ StageDesc stage_desc(const PlanH& P, const Views& V, int j) {
     d.rp[a] = v.d[b.dir].rp;
     d.adj[a] = v.d[b.dir].col;
     d.pm[a] = v.pmap[b.dir];
+    if (V.hash && !d.pm[a] && v.hash_gen == v.gen && v.h[b.dir].desc) {
+      d.hd[a] = v.h[b.dir].desc;
+      d.hs[a] = v.h[b.dir].slots;
+    }
   }
   if (d.ntri) {
     GJ_CHECK(V.tri && V.tri->rp, GJ_EINVAL, "ternary atom without a triangle index");
@@ -276,6 +280,10 @@ void Runner::stage(int j, uint64_t n) {
   uint64_t W = read_u64(c, l.off + n);
   st.extensions[j] += W;
   if (W == 0) return;
+  // a static read that tests membership counts its candidates towards the
+  // version's index, built once they pay for it
+  if (V.graph && d.k >= 2 && !d.hd[0] && !d.hd[1] && hash_note_work(c, V.graph, *V.old_v, W))
+    d = stage_desc(P, V, j);
   bool final = j + 1 == P.m;
   if (final && !collect) {
     timer.start();
@@ -492,6 +500,7 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
     return;
   }
   uint64_t seed_cap = std::max<uint64_t>(1, std::min<uint64_t>(c->seed_chunk, hi - lo));
+  V.graph = g;  // membership indexes are built on demand (Runner::stage)
   Runner R(c, P, V, false, collect, seed_cap);
   if (collect) {
     if (out_on_device)

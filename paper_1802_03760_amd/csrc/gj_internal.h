@@ -6,6 +6,7 @@
 #include <cstdint>
 #include <initializer_list>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -60,6 +61,10 @@ struct StageDesc {
   // rows rewritten by log-structured updates (row_range in prim.h); null:
   // every row of the atom's version is rp[v] .. rp[v + 1]
   const uint64_t* pm[kMaxBind];
+  // membership index of the atom's version and direction (hash.hip), or
+  // null: hd[a][v] describes row v's table in hs[a] (0: no table)
+  const uint64_t* hd[kMaxBind];
+  const uint32_t* hs[kMaxBind];
 };
 
 // Membership filters of the seed pairs (atoms over the first two attributes
@@ -93,10 +98,27 @@ struct CsrDir {
   uint32_t* row = nullptr;  // cap
 };
 
+// Membership index of one direction (hash.hip): per row a table of 2^b
+// four-slot buckets; desc[v] = first bucket << 8 | b, 0 for rows without one.
+struct HashDir {
+  uint64_t* desc = nullptr;
+  uint32_t* slots = nullptr;
+  uint64_t buckets_cap = 0;
+};
+
 struct Version {
   CsrDir d[2];  // 0 forward, 1 reverse
   uint64_t m = 0, cap = 0;
   uint32_t max_deg[2] = {0, 0};
+  // contents generation, advanced whenever the slot is written; the index
+  // h is valid while hash_gen == gen
+  uint64_t gen = 0;
+  uint64_t hash_gen = ~0ull;
+  uint32_t hash_min = 0;  // the least row size with a table in h
+  HashDir h[2];
+  // candidates proposed by static reads of the contents of generation
+  // work_gen (decides when an index pays for its build)
+  uint64_t probe_work = 0, work_gen = ~0ull;
   // Views written by a log-structured update only (never a graph's slot):
   // per direction and vertex, the row as arena offset | length << 32 when the
   // update path has rewritten it into the tail of col, ~0 when it is still
@@ -157,6 +179,7 @@ struct gj_ctx {
   gj::BatchExec* batch = nullptr;
   uint32_t batch_lin = 8;           // linear search below this extension-set size
   uint32_t batch_waves_per_cu = 32; // resident waves per CU of the persistent grids
+  uint32_t batch_claim_words = 16;  // words of 64 candidates a wave of the fused propose claims at a time
   uint64_t batch_cap = 1ull << 27;  // prefixes per level of the batched pipeline
   uint64_t batch_fallbacks = 0;     // batches rerun depth-first after a level overflow
   int delta_fused = 1;              // count-only delta queries through the fused pipeline
@@ -169,6 +192,11 @@ struct gj_ctx {
   uint64_t lsm_compactions = 0;  // compactions run on this context
   uint64_t lsm_folds = 0;  // batches written as a new version while appended rows were pending
   uint64_t owner_task_min = 1ull << 20;  // least proposals per owner task (owner-grouped kernel)
+  int hash_index = 1;      // 0: rows are searched; 1, 2: membership indexes are used where built
+  bool hash_build = true;  // this context builds missing indexes on static reads
+  uint32_t hash_min_degree = 32;  // rows of at least this many entries get a table
+  uint64_t hash_build_work = 16;  // build once reads of a version proposed this many candidates per edge
+  uint64_t hash_builds = 0;       // membership indexes built by this context
   uint64_t owner_tasks = 0;        // tasks of the last owner-grouped launch
   uint64_t owner_split_units = 0;  // owner units of that launch cut into more than one task
 };
@@ -188,6 +216,7 @@ struct gj_graph {
   int cur = 0;
   uint64_t version = 0;
   gj::LsmState lsm;
+  std::mutex hash_mu;  // one build of a version's membership index at a time
 };
 
 struct gj_query {
@@ -270,6 +299,15 @@ inline unsigned grid_for(uint64_t items, uint64_t per_block, unsigned cap = 1u <
   if (g > cap) g = cap;
   return (unsigned)g;
 }
+
+// hash.hip: the membership index of version v (both directions), built if
+// this context builds indexes and v's is missing or stale; freed with v
+void hash_ensure(gj_ctx* c, const gj_graph* g, const Version& v);
+// adds W proposed candidates to v's account and builds its index (as
+// hash_ensure) once the account reaches hash_build_work x its edges;
+// returns whether v's index is usable now
+bool hash_note_work(gj_ctx* c, const gj_graph* g, const Version& v, uint64_t W);
+void hash_free(gj_ctx* c, Version& v);
 
 // scan.hip: exclusive scans; out has n + 1 entries (out[n] = total)
 void scan_u32_to_u64(gj_ctx* c, const uint32_t* in, uint64_t* out, uint64_t n);

@@ -88,6 +88,7 @@ __global__ void __launch_bounds__(kBlock) k_maxdeg(const uint32_t* __restrict__ 
 
 void version_alloc(gj_ctx* c, Version& v, uint32_t n, uint64_t cap) {
   if (cap < 1) cap = 1;
+  ++v.gen;  // the slot is about to be rewritten
   for (int d = 0; d < 2; ++d) {
     if (!v.d[d].rp) v.d[d].rp = (uint32_t*)dev_alloc(c, ((uint64_t)n + 1) * sizeof(uint32_t));
     if (cap > v.cap) {
@@ -122,6 +123,7 @@ int bits_for(uint32_t n) {
 }
 
 void version_finish(gj_ctx* c, Version& v, uint32_t n, bool from_update) {
+  ++v.gen;
   uint32_t* mx = (uint32_t*)ws_get(c, "maxdeg", 2 * sizeof(uint32_t));
   if (!from_update) {
     GJ_HIP(hipMemsetAsync(mx, 0, 2 * sizeof(uint32_t), c->stream));

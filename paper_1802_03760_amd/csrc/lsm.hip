@@ -263,6 +263,7 @@ void graph_compact(gj_ctx* c, gj_graph* g) {
   // left (a graph that grows would otherwise reallocate at every compaction)
   uint64_t room = m / 2 + (1ull << 22);
   if (m + room / 2 > nv.cap) version_alloc(c, nv, n, m + room);
+  ++nv.gen;
   uint32_t* deg = (uint32_t*)ws_get(c, "lsm_deg", ((uint64_t)n + 1) * sizeof(uint32_t));
   for (int d = 0; d < 2; ++d) {
     const uint64_t* pm = L.map[L.cur_map][d];

@@ -162,6 +162,29 @@ __device__ __forceinline__ void row_range(const uint32_t* __restrict__ rp, const
   hi = b;
 }
 
+// ---------------------------------------------------------------- membership index
+// A row's table descriptor: first bucket << 8 | b for a table of 2^b
+// four-slot buckets; 0 = the row has no table.
+constexpr uint32_t kHashEmpty = 0xFFFFFFFFu;  // never a vertex id (ids < 2^32 - 1)
+
+// home bucket of x among 2^b (b >= 1): the top b bits of a multiplicative
+// hash
+__device__ __forceinline__ uint32_t hash_home(uint32_t x, uint32_t b) { return (x * 0x9E3779B1u) >> (32 - b); }
+
+// x in the row table `desc` (b > 0) of `slots`: buckets from the home bucket
+// on until x or a bucket with an empty slot (insertion never passes one)
+__device__ __forceinline__ bool hash_member(const uint32_t* __restrict__ slots, uint64_t desc, uint32_t x) {
+  const uint32_t b = (uint32_t)(desc & 0xFF), mask = (1u << b) - 1;
+  const uint64_t base = desc >> 8;
+  uint32_t h = hash_home(x, b);
+  for (;;) {
+    uint4 q = *(const uint4*)(slots + 4 * (base + h));
+    if (q.x == x || q.y == x || q.z == x || q.w == x) return true;
+    if (q.w == kHashEmpty) return false;
+    h = (h + 1) & mask;
+  }
+}
+
 // p in [lo, hi) with off[p] <= g < off[p+1]; requires off[lo] <= g < off[hi].
 __device__ __forceinline__ uint64_t find_segment(const uint64_t* __restrict__ off, uint64_t lo,
                                                  uint64_t hi, uint64_t g) {

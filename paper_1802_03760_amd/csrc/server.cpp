@@ -88,7 +88,7 @@ struct Active {
   uint64_t count = 0;
   int64_t start_ns = 0;
   gj_status status = GJ_OK;
-  bool busy = false;         // a heavy lane is running a chunk of it
+  int inflight = 0;          // chunks of it heavy lanes are running
 
   uint64_t nblocks() const { return cum.empty() ? 0 : cum.size() - 1; }
   uint64_t block_of(uint64_t seed) const { return (seed - lo) / bs; }
@@ -441,10 +441,15 @@ static void count_loop(gj_server* s) {
   s->cv_heavy.notify_all();
 }
 
-// Heavy lane `lane`: takes the oldest heavy request no other lane is running
-// (one whose version slot an update waits for first) and runs one chunk of
-// about heavy_work estimated work on the depth-first path; lanes run
-// concurrently with each other and with the light iterations.
+// Heavy lane `lane`: claims the next chunk of about heavy_work estimated
+// work of the oldest heavy request with seeds left (one whose version slot an
+// update waits for first) and runs it on the depth-first path.  Every free
+// lane claims chunks of that request until all its seeds are claimed, so the
+// oldest heavy request is served by all lanes at once (the stalls of one
+// lane's host-driven stages are filled by the others'); lanes run
+// concurrently with each other and with the light iterations.  Counts and
+// work are added under the lock; the request finishes when its last chunk
+// returns.
 static void heavy_loop(gj_server* s, int lane) {
   gj_ctx* c = s->hctx[lane];
   (void)hipSetDevice(c->device);
@@ -452,14 +457,14 @@ static void heavy_loop(gj_server* s, int lane) {
   for (;;) {
     uint64_t vno[kMaxVersions] = {};
     Active* pick = nullptr;
-    double W;
+    Chunk ch{};
     {
       std::unique_lock<std::mutex> lk(s->mu);
       s->cv_heavy.wait(lk, [&] {
         if (s->updating && s->update_priority) return false;  // updates first
         pick = nullptr;
         for (auto& a : s->heavy) {
-          if (a->busy) continue;
+          if (a->next >= a->hi) continue;  // every seed claimed
           if (!pick) pick = a.get();
           if (a->slot == s->want) {
             pick = a.get();
@@ -469,18 +474,34 @@ static void heavy_loop(gj_server* s, int lane) {
         return pick != nullptr || (s->light_done && s->heavy.empty());
       });
       if (!pick) break;  // the light thread has exited and every heavy request is done
-      pick->busy = true;
+      double W = (double)(s->heavy_work ? s->heavy_work : 4 * std::max<uint64_t>(s->iter_work, 1));
+      double used = 0;
+      ch = take(pick, W, used);
+      pick->next = ch.hi;  // claimed
+      ++pick->inflight;
+      if (!pick->start_ns) pick->start_ns = now_ns();
       vers[pick->slot] = s->g->ver[pick->slot];
       for (int b = 0; b < kMaxVersions; ++b) vno[b] = s->version_no[b];
-      W = (double)(s->heavy_work ? s->heavy_work : 4 * std::max<uint64_t>(s->iter_work, 1));
     }
-    double used = 0;
-    std::vector<Chunk> one{take(pick, W, used)};
-    run_chunks(s, c, one, vers);
+    const gj_query* q = pick->r.q;
+    const Version* cv = &vers[pick->slot];
+    uint64_t cnt = 0;
+    gj_stats st{};
+    gj_status status = count_on_versions(c, s->g, &cv, 1, &q, &ch.lo, &ch.hi, &cnt, &st);
     {
       std::lock_guard<std::mutex> lk(s->mu);
-      pick->busy = false;
-      if (pick->next >= pick->hi) {
+      --pick->inflight;
+      if (status != GJ_OK) {
+        pick->status = status;
+        pick->next = pick->hi;
+      } else {
+        pick->count += cnt;
+        double work = (double)st.prefixes[2];
+        for (int j = 0; j <= GJ_MAX_ATTRS; ++j) work += (double)st.extensions[j];
+        pick->est_done += (double)(pick->cum[ch.b1] - pick->cum[ch.b0]);
+        pick->work_done += work;
+      }
+      if (pick->next >= pick->hi && pick->inflight == 0) {
         gj_server_result res = count_result(*pick, vno[pick->slot], 1, now_ns());
         record(s, pick->r, res);
         release(s, pick->r.state);
@@ -608,6 +629,7 @@ gj_status gj_server_create(gj_ctx* ctx, gj_graph* g, uint32_t max_batch, uint64_
     return st;
   }
   gj::copy_options(s->cctx, ctx);
+  s->cctx->hash_build = ctx->hash_index >= 2;  // the server reads indexes built elsewhere unless asked
   s->cur = g->cur;
   for (int b = 0; b < kMaxVersions; ++b) {
     s->lo[b] = 1;  // empty
@@ -643,6 +665,7 @@ static gj_status enqueue_req(gj_server* s, Req&& r, uint64_t* ticket) {
         gj_status st = gj_ctx_create(s->ctx->device, nullptr, s->ctx->alloc.alloc ? &s->ctx->alloc : nullptr, &c);
         if (st != GJ_OK) break;
         gj::copy_options(c, s->ctx);
+        c->hash_build = s->ctx->hash_index >= 2;
         s->hctx.push_back(c);
       }
       if (s->hctx.empty()) return GJ_EDEVICE;

@@ -129,18 +129,29 @@ __device__ __forceinline__ Cand resolve(const uint32_t* __restrict__ F, uint64_t
       return c;
     }
   }
-  const uint32_t* rp = d.rp[0];
-  const uint32_t* adj = d.adj[0];
-  const uint64_t* pm = d.pm[0];
-  int col = d.col[0];
-#pragma unroll
-  for (int a = 1; a < kMaxBind; ++a) {
-    if (a == c.am) {
-      rp = d.rp[a];
-      adj = d.adj[a];
-      pm = d.pm[a];
-      col = d.col[a];
-    }
+  // the proposing atom's arrays by a switch on its (per-lane) index: a
+  // select loop over the atoms is turned into an indexed read of the kernel
+  // argument, which the compiler copies to private memory in every lane
+  const uint32_t* rp;
+  const uint32_t* adj;
+  const uint64_t* pm;
+  int col;
+  switch (c.am) {
+#define GJ_PICK(A)  \
+  case A:           \
+    rp = d.rp[A];   \
+    adj = d.adj[A]; \
+    pm = d.pm[A];   \
+    col = d.col[A]; \
+    break;
+    GJ_PICK(1) GJ_PICK(2) GJ_PICK(3) GJ_PICK(4) GJ_PICK(5) GJ_PICK(6) GJ_PICK(7)
+#undef GJ_PICK
+    default:
+      rp = d.rp[0];
+      adj = d.adj[0];
+      pm = d.pm[0];
+      col = d.col[0];
+      break;
   }
   uint32_t v = F[(uint64_t)col * stride + c.p], lo, hi;
   row_range(rp, pm, v, lo, hi);
@@ -161,6 +172,11 @@ __device__ __forceinline__ bool intersect_all(const uint32_t* __restrict__ F, ui
         continue;
       }
       uint32_t u = F[(uint64_t)d.col[a] * stride + c.p], lo, hi;
+      uint64_t dd = d.hd[a] ? d.hd[a][u] : 0ull;
+      if (dd) {
+        keep = hash_member(d.hs[a], dd, c.e);
+        continue;
+      }
       row_range(d.rp[a], d.pm[a], u, lo, hi);
       keep = contains_u32(d.adj[a], lo, hi, c.e);
     }
@@ -183,15 +199,54 @@ __device__ __forceinline__ void intersect_lockstep(const uint32_t* __restrict__ 
     if (a < d.k) {
       const uint32_t* arr = d.adj[a];
       uint32_t lo[U], hi[U], n[U];
+      uint64_t dd[U];
       bool act[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         act[u] = keep[u] && a != c[u].am;
         lo[u] = hi[u] = n[u] = 0;
+        dd[u] = 0;
         if (act[u]) {
           uint32_t x = F[(uint64_t)d.col[a] * stride + c[u].p];
-          row_range(d.rp[a], d.pm[a], x, lo[u], hi[u]);
-          n[u] = hi[u] - lo[u];
+          if (d.hd[a]) dd[u] = d.hd[a][x];
+          if (!dd[u]) {
+            row_range(d.rp[a], d.pm[a], x, lo[u], hi[u]);
+            n[u] = hi[u] - lo[u];
+          }
+        }
+      }
+      if (d.hd[a]) {
+        // rows with a table: probes in lockstep, one bucket load per step
+        uint32_t h[U];
+        bool pend[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          pend[u] = dd[u] != 0;
+          h[u] = pend[u] ? hash_home(c[u].e, (uint32_t)(dd[u] & 0xFF)) : 0u;
+        }
+        for (;;) {
+          bool any = false;
+#pragma unroll
+          for (int u = 0; u < U; ++u) any = any || pend[u];
+          if (!any) break;
+          uint4 q[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            q[u] = pend[u] ? *(const uint4*)(d.hs[a] + 4 * ((dd[u] >> 8) + h[u])) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (!pend[u]) continue;
+            const uint32_t e = c[u].e;
+            if (q[u].x == e || q[u].y == e || q[u].z == e || q[u].w == e) {
+              keep[u] = true;
+              pend[u] = false;
+            } else if (q[u].w == kHashEmpty) {
+              keep[u] = false;
+              pend[u] = false;
+            } else {
+              h[u] = (h[u] + 1) & ((1u << (uint32_t)(dd[u] & 0xFF)) - 1);
+            }
+          }
         }
       }
       for (;;) {
@@ -217,7 +272,7 @@ __device__ __forceinline__ void intersect_lockstep(const uint32_t* __restrict__ 
       }
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (act[u]) keep[u] = lo[u] < hi[u] && arr[lo[u]] == c[u].e;
+        if (act[u] && !dd[u]) keep[u] = lo[u] < hi[u] && arr[lo[u]] == c[u].e;
     }
   }
 }

@@ -1,9 +1,15 @@
-// Autotuner of the batched executor: times every candidate configuration on
-// the caller's own batch, keeps the fastest, and caches the choice in a small
-// JSON file keyed by the graph and the query set.  Every configuration must
-// produce the same counts; a difference is reported as a device error.
+// Autotuner of gj_run_batch: searches its parameters on the caller's own
+// batch -- the membership test (per-row hash tables or searches), the
+// linear-search threshold, the persistent grid (waves per CU), the candidate
+// chunk a wave claims at a time, the work bound from which a request leaves
+// the fused pipeline for the depth-first path, and the depth-first propose
+// kernel's lockstep width -- keeps the fastest, and caches the choice in a
+// small JSON file keyed by the graph and the query set.  Every configuration
+// must produce the same counts; a difference is reported as a device error.
 #include <algorithm>
+#include <chrono>
 #include <cstdio>
+#include <cstring>
 #include <fstream>
 #include <map>
 #include <sstream>
@@ -33,98 +39,148 @@ static std::string tune_key(const gj_graph* g, uint32_t nreq, const gj_query* co
   return k.str();
 }
 
-static std::map<std::string, std::pair<uint32_t, uint32_t>> read_cache(const char* path) {
-  std::map<std::string, std::pair<uint32_t, uint32_t>> m;
+// The tuned parameters, in the order they are searched.
+struct Params {
+  uint32_t lin, waves, claim, hash, propose_u;
+  uint64_t heavy;
+};
+
+static bool same(const Params& a, const Params& b) {
+  return a.lin == b.lin && a.waves == b.waves && a.claim == b.claim && a.hash == b.hash &&
+         a.propose_u == b.propose_u && a.heavy == b.heavy;
+}
+
+static Params current(const gj_ctx* c) {
+  return Params{c->batch_lin, c->batch_waves_per_cu, c->batch_claim_words, (uint32_t)(c->hash_index ? 1 : 0),
+                (uint32_t)c->propose_u, c->batch_heavy};
+}
+
+static void apply(gj_ctx* c, const Params& p) {
+  c->batch_lin = p.lin;
+  c->batch_waves_per_cu = p.waves;
+  c->batch_claim_words = p.claim;
+  c->hash_index = p.hash ? (c->hash_index ? c->hash_index : 1) : 0;
+  c->propose_u = (int)p.propose_u;
+  c->batch_heavy = p.heavy;
+}
+
+// one entry per line: "key": [lin, waves, claim, hash, propose_u, heavy],
+static std::map<std::string, Params> read_cache(const char* path) {
+  std::map<std::string, Params> m;
   if (!path) return m;
   std::ifstream f(path);
   std::string line;
-  // one entry per line: "key": [lin, waves],
   while (std::getline(f, line)) {
     size_t a = line.find('"'), b = line.find('"', a + 1), l = line.find('[', b), r = line.find(']', l);
     if (a == std::string::npos || b == std::string::npos || l == std::string::npos || r == std::string::npos)
       continue;
-    unsigned lin = 0, waves = 0;
-    if (sscanf(line.c_str() + l + 1, "%u , %u", &lin, &waves) == 2)
-      m[line.substr(a + 1, b - a - 1)] = {lin, waves};
+    unsigned lin = 0, waves = 0, claim = 0, hash = 0, pu = 0;
+    unsigned long long heavy = 0;
+    if (sscanf(line.c_str() + l + 1, "%u , %u , %u , %u , %u , %llu", &lin, &waves, &claim, &hash, &pu, &heavy) == 6)
+      m[line.substr(a + 1, b - a - 1)] = Params{lin, waves, claim, hash, pu, heavy};
   }
   return m;
 }
 
-static void write_cache(const char* path, const std::map<std::string, std::pair<uint32_t, uint32_t>>& m) {
+static void write_cache(const char* path, const std::map<std::string, Params>& m) {
   std::ofstream f(path);
   f << "{\n";
   size_t i = 0;
   for (auto& kv : m) {
-    f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
-      << (++i < m.size() ? "," : "") << "\n";
+    const Params& p = kv.second;
+    f << "  \"" << kv.first << "\": [" << p.lin << ", " << p.waves << ", " << p.claim << ", " << p.hash << ", "
+      << p.propose_u << ", " << p.heavy << "]" << (++i < m.size() ? "," : "") << "\n";
   }
   f << "}\n";
 }
 
+static void report(gj_tuning* out, const Params& p, double ms, int tried, int cached) {
+  if (!out) return;
+  out->batch_lin = p.lin;
+  out->batch_waves_per_cu = p.waves;
+  out->batch_claim_words = p.claim;
+  out->hash_index = p.hash;
+  out->propose_u = p.propose_u;
+  out->batch_heavy = p.heavy;
+  out->best_ms = ms;
+  out->configs_tried = tried;
+  out->from_cache = cached;
+}
+
+// Coordinate descent over the parameters of gj_run_batch on the caller's own
+// batch: each parameter in turn takes each of its candidate values with the
+// others held at their best so far, and keeps the fastest (wall time of the
+// whole call, best of two after a warm-up that also builds what the
+// configuration needs: captured pipeline, membership index).  Every
+// configuration must give the same counts.
 void autotune(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const* qs, const uint64_t* lo,
               const uint64_t* hi, const char* cache_path, gj_tuning* out) {
   std::string key = tune_key(g, nreq, qs);
   auto cache = read_cache(cache_path);
   auto it = cache.find(key);
   if (it != cache.end()) {
-    c->batch_lin = it->second.first;
-    c->batch_waves_per_cu = it->second.second;
-    if (out) {
-      out->batch_lin = c->batch_lin;
-      out->batch_waves_per_cu = c->batch_waves_per_cu;
-      out->best_ms = -1;
-      out->configs_tried = 0;
-      out->from_cache = 1;
-    }
+    apply(c, it->second);
+    report(out, it->second, -1, 0, 1);
     return;
   }
-  if (!c->batch) c->batch = new BatchExec();
-  const uint32_t lins[] = {0, 8, 32, 128};
-  const uint32_t waves[] = {16, 32, 64};
   std::vector<uint64_t> ref(nreq), cnt(nreq);
   std::vector<gj_stats> st(nreq);
-  double best = 1e300;
-  uint32_t best_lin = c->batch_lin, best_w = c->batch_waves_per_cu;
+  // configurations with the membership index have it from their warm-up on
+  const uint64_t build_work = c->hash_build_work;
+  struct Restore {
+    gj_ctx* c;
+    uint64_t w;
+    ~Restore() { c->hash_build_work = w; }
+  } restore{c, build_work};
+  c->hash_build_work = 0;
   bool have_ref = false;
   int tried = 0;
-  for (uint32_t w : waves) {
-    for (uint32_t l : lins) {
-      c->batch_lin = l;
-      c->batch_waves_per_cu = w;
-      bool ov = false;
-      c->batch->run(c, g, nreq, qs, lo, hi, cnt.data(), st.data(), ov);  // warm-up / capture
-      GJ_CHECK(!ov, GJ_EUNSUPPORTED, "autotune: batch exceeds the frontier capacity");
-      double t = 1e300;
-      for (int rep = 0; rep < 2; ++rep) {
-        c->batch->run(c, g, nreq, qs, lo, hi, cnt.data(), st.data(), ov);
-        t = std::min(t, st[0].kernel_ms);
-      }
-      if (!have_ref) {
-        ref = cnt;
-        have_ref = true;
-      }
-      GJ_CHECK(cnt == ref, GJ_EDEVICE, "autotune: configurations disagree on the counts");
-      ++tried;
-      if (t < best) {
-        best = t;
-        best_lin = l;
-        best_w = w;
+  auto time_one = [&](const Params& p) {
+    apply(c, p);
+    count_batch(c, g, nreq, qs, lo, hi, cnt.data(), st.data(), nullptr);  // warm-up
+    double t = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+      GJ_HIP(hipStreamSynchronize(c->stream));
+      auto t0 = std::chrono::steady_clock::now();
+      count_batch(c, g, nreq, qs, lo, hi, cnt.data(), st.data(), nullptr);
+      GJ_HIP(hipStreamSynchronize(c->stream));
+      t = std::min(t, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    }
+    if (!have_ref) {
+      ref = cnt;
+      have_ref = true;
+    }
+    GJ_CHECK(cnt == ref, GJ_EDEVICE, "autotune: configurations disagree on the counts");
+    ++tried;
+    return t;
+  };
+  Params best = current(c);
+  double best_ms = time_one(best);
+  auto sweep = [&](auto field, std::initializer_list<uint64_t> values) {
+    Params base = best;
+    for (uint64_t v : values) {
+      Params p = base;
+      field(p, v);
+      if (same(p, base)) continue;
+      double t = time_one(p);
+      if (t < best_ms) {
+        best_ms = t;
+        best = p;
       }
     }
-  }
-  c->batch_lin = best_lin;
-  c->batch_waves_per_cu = best_w;
+  };
+  sweep([](Params& p, uint64_t v) { p.hash = (uint32_t)v; }, {0, 1});
+  sweep([](Params& p, uint64_t v) { p.lin = (uint32_t)v; }, {0, 8, 32, 128});
+  sweep([](Params& p, uint64_t v) { p.waves = (uint32_t)v; }, {16, 32, 64});
+  sweep([](Params& p, uint64_t v) { p.claim = (uint32_t)v; }, {4, 16, 64});
+  sweep([](Params& p, uint64_t v) { p.heavy = v; }, {0, 1ull << 22, 1ull << 24, 1ull << 26});
+  sweep([](Params& p, uint64_t v) { p.propose_u = (uint32_t)v; }, {1, 2, 4});
+  apply(c, best);
   if (cache_path) {
-    cache[key] = {best_lin, best_w};
+    cache[key] = best;
     write_cache(cache_path, cache);
   }
-  if (out) {
-    out->batch_lin = best_lin;
-    out->batch_waves_per_cu = best_w;
-    out->best_ms = best;
-    out->configs_tried = tried;
-    out->from_cache = 0;
-  }
+  report(out, best, best_ms, tried, 0);
 }
 
 }  // namespace gj

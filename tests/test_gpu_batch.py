@@ -117,16 +117,38 @@ def test_autotune_and_cache(gj, tmp_path):
     reqs, _ = mixed_requests(gj, ctx, E, rng, 16)
     path = str(tmp_path / "tune.json")
     t = gj.autotune(ctx, G, reqs, path)
-    assert t["configs_tried"] == 12 and not t["from_cache"]
+    # the starting point, then each parameter's other values (coordinate descent)
+    assert 1 + 1 + 3 + 2 + 2 + 3 + 2 <= t["configs_tried"] <= 1 + 2 + 4 + 3 + 3 + 4 + 3 and not t["from_cache"]
     assert os.path.exists(path)
+    keys = ("batch_lin", "batch_waves_per_cu", "batch_claim_words", "hash_index", "propose_u", "batch_heavy")
+    opts = {k: ctx.get_option(k) for k in keys}
+    assert opts == {k: t[k] for k in keys}  # the context keeps the choice
     counts, _ = gj.run_batch(ctx, G, reqs)
     assert counts == [gj.count(ctx, G, q, lo, hi)["matches"] for q, lo, hi in reqs]
     ctx2 = gj.Context(0)
     G2 = gj.Graph(ctx2, src, dst, n)
     reqs2 = [(gj.Query(ctx2, q.num_attrs, q.atoms, q.order), lo, hi) for q, lo, hi in reqs]
     t2 = gj.autotune(ctx2, G2, reqs2, path)
-    assert t2["from_cache"] and (t2["batch_lin"], t2["batch_waves_per_cu"]) == (t["batch_lin"],
-                                                                             t["batch_waves_per_cu"])
+    assert t2["from_cache"] and all(t2[k] == t[k] for k in keys)
+    assert {k: ctx2.get_option(k) for k in keys} == opts
+
+
+@pytest.mark.parametrize("claim", [1, 3, 4096])
+def test_claim_sizes(gj, claim):
+    """Waves of the fused propose kernel claiming 1, 3 or 4096 words of
+    candidates at a time: counts and counters equal the depth-first path's."""
+    src, dst = synth.rmat_draws(12, seed=7)
+    n = 1 << 12
+    ctx = gj.Context(0)
+    ctx.set_option("batch_claim_words", claim)
+    ctx.set_option("batch_heavy", 0)
+    G = gj.Graph(ctx, src, dst, n)
+    E = G.info()["edges"]
+    reqs, _ = mixed_requests(gj, ctx, E, np.random.default_rng(claim), 24)
+    counts, stats = gj.run_batch(ctx, G, reqs)
+    for (q, lo, hi), c, st in zip(reqs, counts, stats):
+        r = gj.count(ctx, G, q, lo, hi)
+        assert c == r["matches"] and st["extensions"] == r["extensions"], (lo, hi)
 
 
 @pytest.mark.parametrize("heavy", [0, 1, 2000])
