@@ -325,6 +325,29 @@ gj_status gj_run(gj_ctx* ctx, const gj_graph* g, const gj_query* q, int mode,
                  uint64_t seed_lo, uint64_t seed_hi, uint32_t* out,
                  uint64_t out_cap_rows, int out_on_device, gj_stats* stats);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): gj_run in
+ * COUNT mode over seed edges [seed_lo, seed_hi) (clamped as gj_run), on the
+ * depth-first per-candidate path, with every workspace buffer (frontiers,
+ * minimum counts, scans, ballots, counters) taken from one static 64 MiB
+ * device array per GPU instead of an allocation; no hipMalloc, hipFree or
+ * allocating call is made.  frontier_cap is the batch bound B (Sec. 3.1.2):
+ * prefixes per frontier and proposals per batch; 0 takes the largest power
+ * of two whose buffers fit the array for this query (2^21 prefixes for two
+ * attributes, 2^20 for three or four, 2^19 for five or six, 2^18 for seven
+ * or eight); a larger value, or one below 64, is rejected with
+ * GJ_EINVAL and a message naming the maximum.  Counts and counters equal
+ * gj_run's (options "factorise" and "strategy" are ignored: it always
+ * enumerates on the generic kernels; stats->kernel_ms is 0, no timing
+ * events are created).  The array is shared by every call on that GPU and
+ * keeps the last call's contents; calls on one GPU are serialised by a lock
+ * in the library (a call returns once its kernels are done), so overlapping
+ * calls wait rather than race.  Errors: GJ_EINVAL for a graph with rows
+ * appended by log-structured updates that no static read has merged yet
+ * (merging allocates), or without the triangle index a ternary atom needs. */
+gj_status gj_count_noalloc(gj_ctx* ctx, const gj_graph* g, const gj_query* q, uint64_t seed_lo,
+                           uint64_t seed_hi, uint64_t frontier_cap, gj_stats* stats);
+
 /* Applies one signed update batch (sign +1 insert, -1 delete; host memory
  * unless on_device) as a new version of the graph, and returns for each of
  * the nq queries the change of its result (Delta-GJ, Sec. 3.3.1: the signed

@@ -33,7 +33,8 @@ EXPORTS = ["gj_ctx_create", "gj_ctx_destroy", "gj_last_error", "gj_ctx_set_optio
            "gj_last_delta", "gj_run_batch", "gj_autotune", "gj_server_create", "gj_server_submit_count",
            "gj_server_submit_update", "gj_server_wait", "gj_server_get_stats", "gj_server_destroy",
            "gj_server_set_option", "gj_query_register_ex", "gj_graph_vertex_ids", "gj_query_register_rel",
-           "gj_graph_index_triangles", "gj_measure_peaks"]
+           "gj_graph_index_triangles", "gj_count_noalloc",
+           "gj_measure_peaks"]
 REQ_COUNT, REQ_UPDATE = 0, 1
 SERVER_MAX_QUERIES = 16
 
@@ -142,6 +143,8 @@ _lib.gj_run.argtypes = [_vp, _vp, _vp, _i32, _u64, _u64, _vp, _u64, _i32, ctypes
 _lib.gj_run.restype = _i32
 _lib.gj_measure_peaks.argtypes = [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
 _lib.gj_measure_peaks.restype = _i32
+_lib.gj_count_noalloc.argtypes = [_vp, _vp, _vp, _u64, _u64, _u64, ctypes.POINTER(Stats)]
+_lib.gj_count_noalloc.restype = _i32
 _lib.gj_apply_updates.argtypes = [_vp, _vp, _vp, _vp, _vp, _u64, _i32, ctypes.POINTER(_vp), _u32,
                                   _vp, ctypes.POINTER(_vp), ctypes.POINTER(_vp), _vp, _vp,
                                   ctypes.POINTER(Stats)]
@@ -563,6 +566,16 @@ def measure_peaks(ctx):
     cp, lds = ctypes.c_double(), ctypes.c_double()
     ctx.check(_lib.gj_measure_peaks(ctx._h, ctypes.byref(cp), ctypes.byref(lds)), "gj_measure_peaks")
     return {"copy_gbs": cp.value, "lds_gbs": lds.value}
+
+
+def count_noalloc(ctx, graph, query, seed_lo=0, seed_hi=(1 << 64) - 1, frontier_cap=0):
+    """gj_count_noalloc: the count of gj_run on the depth-first path, every
+    workspace buffer taken from the library's static scratch (no device
+    allocation).  Returns the stats dict."""
+    st = Stats()
+    ctx.check(_lib.gj_count_noalloc(ctx._h, graph._h, query._h, seed_lo, seed_hi, frontier_cap,
+                                    ctypes.byref(st)), "gj_count_noalloc")
+    return st.as_dict()
 
 
 def apply_updates(ctx, graph, src, dst, sign, queries, rows=False, cap=1 << 16):

@@ -14,6 +14,7 @@ namespace gj {
 void* dev_alloc(gj_ctx* c, size_t bytes) {
   void* p = nullptr;
   if (bytes == 0) bytes = 16;
+  GJ_CHECK(!c->arena.on, GJ_EUNSUPPORTED, "device allocation requested inside the allocation-free path");
   if (c->alloc.alloc) {
     p = c->alloc.alloc(c->alloc.user, bytes, (void*)c->stream);
     if (!p) throw Error{GJ_ENOMEM, "allocator returned no memory for " + std::to_string(bytes) + " bytes"};
@@ -38,8 +39,24 @@ void dev_free(gj_ctx* c, void* p) {
   (void)hipFree(p);
 }
 
-// Named grow-only workspace buffers owned by the context.
+// Named grow-only workspace buffers owned by the context (or, inside the
+// allocation-free path, named pieces of its scratch, reserved once per call).
 void* ws_get(gj_ctx* c, const std::string& name, size_t bytes) {
+  if (c->arena.on) {
+    gj_ctx::Arena& A = c->arena;
+    auto it = A.named.find(name);
+    if (it != A.named.end()) {
+      GJ_CHECK(bytes <= it->second.bytes, GJ_EUNSUPPORTED,
+               "scratch piece " + name + " outgrew its reservation");
+      return it->second.p;
+    }
+    uint64_t at = (A.used + kArenaAlign - 1) & ~(kArenaAlign - 1);
+    GJ_CHECK(at + bytes <= A.size, GJ_EUNSUPPORTED,
+             "the " + std::to_string(A.size) + "-byte scratch cannot hold piece " + name);
+    A.used = at + bytes;
+    A.named[name] = DevBuf{A.base + at, bytes};
+    return A.base + at;
+  }
   DevBuf& b = c->ws[name];
   if (bytes <= b.bytes && b.p) return b.p;
   size_t want = bytes + bytes / 8 + 256;
@@ -76,6 +93,7 @@ void read_u64s(gj_ctx* c, std::initializer_list<const uint64_t*> ptrs, uint64_t*
 }
 
 void KernelTimer::start() {
+  if (c_->arena.on) return;  // the allocation-free path creates no events (launches still counted)
   if (c_->events.size() < 2 * (n_ + 1)) {
     for (int i = 0; i < 2; ++i) {
       hipEvent_t e;
@@ -87,12 +105,13 @@ void KernelTimer::start() {
 }
 
 void KernelTimer::stop() {
-  GJ_HIP(hipEventRecord(c_->events[2 * n_ + 1], c_->stream));
+  if (!c_->arena.on) GJ_HIP(hipEventRecord(c_->events[2 * n_ + 1], c_->stream));
   ++n_;
 }
 
 double KernelTimer::total_ms() {
   GJ_HIP(hipStreamSynchronize(c_->stream));
+  if (c_->arena.on) return 0.0;
   double t = 0;
   for (size_t i = 0; i < n_; ++i) {
     float ms = 0;
@@ -154,6 +173,7 @@ gj_status gj_ctx_create(int device, void* hip_stream, const gj_allocator* alloca
       c->own_stream = true;
     }
     GJ_HIP(hipHostMalloc(&c->pinned, 4096, hipHostMallocDefault));
+    (void)gj::scratch_ptr(device);  // the allocation-free entry point's scratch on this device
     hipDeviceProp_t prop;
     GJ_HIP(hipGetDeviceProperties(&prop, device));
     c->num_cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;

@@ -206,6 +206,23 @@ Runner::Runner(gj_ctx* c_, const PlanH& P_, const Views& V_, bool weighted_, boo
   seed_off = (uint64_t*)ws_get(c, "seed_off", (seed_cap + 1) * sizeof(uint64_t));
 }
 
+static uint64_t arena_piece(uint64_t b) { return (b + kArenaAlign - 1) & ~(kArenaAlign - 1); }
+
+// Mirrors the Runner constructor's buffers for a count-only, unweighted run.
+uint64_t runner_scratch_bytes(int m, uint64_t seed_cap, uint64_t fcap) {
+  uint64_t t = 0, words = fcap / 64 + 2;
+  for (int j = 2; j < m; ++j) {
+    uint64_t cap = j == 2 ? seed_cap : fcap;
+    t += arena_piece(cap * j * sizeof(uint32_t) + 16) + arena_piece(cap * sizeof(uint32_t) + 16) +
+         arena_piece(cap + 16) + arena_piece((cap + 1) * sizeof(uint64_t)) + arena_piece(words * sizeof(uint64_t)) +
+         arena_piece(words * sizeof(uint32_t)) + arena_piece((words + 1) * sizeof(uint64_t));
+  }
+  if (m == 2) t += arena_piece(seed_cap * 2 * sizeof(uint32_t) + 16);
+  t += arena_piece(4 * sizeof(unsigned long long)) + arena_piece((seed_cap + 1) * sizeof(uint32_t)) +
+       arena_piece((seed_cap + 1) * sizeof(uint64_t));
+  return t + scan_scratch_bytes(std::max(seed_cap, fcap) + 1);
+}
+
 Runner::~Runner() {
   if (rows_owned) dev_free(c, rows);
   if (signs_owned) dev_free(c, rsign);

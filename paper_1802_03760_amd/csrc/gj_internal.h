@@ -164,6 +164,14 @@ struct gj_ctx {
   int strategy = 0;
   int num_cus = 256;
   std::map<std::string, gj::DevBuf> ws;
+  // While `on`, ws_get hands out named pieces of [base, base + size) (the
+  // allocation-free entry point's scratch) and dev_alloc refuses to run.
+  struct Arena {
+    bool on = false;
+    uint8_t* base = nullptr;
+    uint64_t size = 0, used = 0;
+    std::map<std::string, gj::DevBuf> named;
+  } arena;
   void* pinned = nullptr;  // small pinned host staging (4 KiB)
   std::vector<hipEvent_t> events;  // pool for kernel timing (pairs)
   // consolidated delta rows of the last gj_apply_updates, per query position
@@ -308,6 +316,21 @@ void hash_ensure(gj_ctx* c, const gj_graph* g, const Version& v);
 // returns whether v's index is usable now
 bool hash_note_work(gj_ctx* c, const gj_graph* g, const Version& v, uint64_t W);
 void hash_free(gj_ctx* c, Version& v);
+
+// scan.hip: workspace bytes of the scans of up to n items, and their
+// reservation (so that later scans of at most n items take no new buffer)
+uint64_t scan_scratch_bytes(uint64_t n);
+void scan_reserve(gj_ctx* c, uint64_t n);
+// engine.hip: workspace bytes of a count-only, unweighted Runner (query of m
+// attributes, P_2 batches of seed_cap seeds, frontiers of fcap prefixes),
+// scans included, in pieces aligned as the arena aligns them
+uint64_t runner_scratch_bytes(int m, uint64_t seed_cap, uint64_t fcap);
+// noalloc.hip: the scratch array of this device (resolved once per device)
+// and the lock that keeps calls on one device from overlapping on it
+void* scratch_ptr(int device);
+uint64_t scratch_bytes();
+void scratch_lock(int device, bool lock);
+constexpr uint64_t kArenaAlign = 256;
 
 // scan.hip: exclusive scans; out has n + 1 entries (out[n] = total)
 void scan_u32_to_u64(gj_ctx* c, const uint32_t* in, uint64_t* out, uint64_t n);

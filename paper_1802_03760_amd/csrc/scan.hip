@@ -75,6 +75,30 @@ static void scan_impl(gj_ctx* c, const Tin* in, Tout* out, uint64_t n, int level
   GJ_HIP(hipGetLastError());
 }
 
+// The level buffers of a scan of n items (u64 tile sums, the widest any
+// scan here takes), as scan_impl names them.
+uint64_t scan_scratch_bytes(uint64_t n) {
+  uint64_t t = 0;
+  for (int level = 0; n > 0; ++level) {
+    uint64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb <= 1) break;
+    t += ((nb + 1) * sizeof(uint64_t) + kArenaAlign - 1) & ~(kArenaAlign - 1);
+    t += (nb * sizeof(uint64_t) + kArenaAlign - 1) & ~(kArenaAlign - 1);
+    n = nb;
+  }
+  return t;
+}
+
+void scan_reserve(gj_ctx* c, uint64_t n) {
+  for (int level = 0; n > 0; ++level) {
+    uint64_t nb = (n + kScanTile - 1) / kScanTile;
+    if (nb <= 1) break;
+    ws_get(c, "scan_off" + std::to_string(level), (nb + 1) * sizeof(uint64_t));
+    ws_get(c, "scan_part" + std::to_string(level), nb * sizeof(uint64_t));
+    n = nb;
+  }
+}
+
 void scan_u32_to_u64(gj_ctx* c, const uint32_t* in, uint64_t* out, uint64_t n) {
   scan_impl<uint32_t, uint64_t>(c, in, out, n, 0);
 }
