@@ -109,6 +109,8 @@ def batched_vs_plain(gj, ctx, G, nreq, seed, log, max_width=1000):
         width = int(np.exp(rng.uniform(0, np.log(max_width))))
         reqs.append((qs[k], lo, min(E, lo + width)))
         rnames.append(k)
+    keys = ("batch_lin", "batch_waves_per_cu", "batch_claim_words", "hash_index", "propose_u", "batch_heavy")
+    saved = {k: ctx.get_option(k) for k in keys}
     tune = gj.autotune(ctx, G, reqs)
     gj.run_batch(ctx, G, reqs)
     t0 = time.perf_counter()
@@ -119,6 +121,8 @@ def batched_vs_plain(gj, ctx, G, nreq, seed, log, max_width=1000):
     tp = time.perf_counter() - t0
     assert counts == [p["matches"] for p in plain]
     fallbacks = ctx.get_option("batch_fallbacks")
+    for k, v in saved.items():  # the tuning is for this mix, not for the legs that follow
+        ctx.set_option(k, v)
     assert all(b["extensions"] == p["extensions"] for b, p in zip(bst, plain))
     ext = sum(sum(p["extensions"]) for p in plain)
     byt = sum(stage_bytes(p["prefixes"], p["extensions"], kinds[k][0], ks[k]) for p, k in zip(plain, rnames))
@@ -149,9 +153,12 @@ def propose_leg(gj, ctx, G, log, nslices=48, width=3000):
     diamond counts over seed slices spread evenly over the R-MAT-22 edge
     range (the first at the hub rows), on the depth-first path.  Roofline of
     the propose launches from the stage counters (GJ cost model) over their
-    summed HIP-event time."""
+    summed HIP-event time.  The version's membership index is built by the
+    warm-up count (hash_build_work 0 for the leg), so every slice probes it."""
     E = G.info(degrees=False)["edges"]
     out = {}
+    saved = ctx.get_option("hash_build_work")
+    ctx.set_option("hash_build_work", 0)
     for name, qd, ks in (("4-clique", (4, [(0, 1), (0, 2), (0, 3), (1, 2), (1, 3), (2, 3)]), {2: 2, 3: 3}),
                          ("diamond", (4, [(0, 1), (0, 2), (1, 3), (2, 3)]), {2: 1, 3: 2})):
         q = gj.Query(ctx, *qd)
@@ -177,6 +184,7 @@ def propose_leg(gj, ctx, G, log, nslices=48, width=3000):
                      "achieved_gbs": gbs, "frac": gbs / HBM_PEAK_GBS}
         log("k_propose, R-MAT-22 %s slices: %.2e ext in %.1f ms of propose kernels (%.2e ext/s, %.0f GB/s = "
             "%.3f of HBM)" % (name, ext, kms, ext / (kms * 1e-3), gbs, gbs / HBM_PEAK_GBS))
+    ctx.set_option("hash_build_work", saved)
     return out
 
 

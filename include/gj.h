@@ -126,7 +126,7 @@ const char* gj_last_error(const gj_ctx* ctx);
  *   "hash_min_degree"  rows of at least this many entries get a table
  *                   (default 32, >= 1)
  *   "hash_build_work"  candidates per edge that static reads of a version
- *                   propose before its tables are built (default 16; 0: at
+ *                   propose before its tables are built (default 64; 0: at
  *                   the first read that tests membership)
  *   "propose_u"     candidates per lane whose membership searches the
  *                   generic propose kernel runs in lockstep: 1, 2 or 4
@@ -157,6 +157,10 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   gj_graph_index_triangles, gj_server_create.  Results
  *                   are the same either way.  0 (default) writes every
  *                   batch as a new version of both indexes
+ *   "lsm_fold_min"  with lsm_updates: a batch of at least this many distinct
+ *                   changes (default 8192; 0: every batch) is written as a
+ *                   new version of both indexes without first sizing the rows
+ *                   it touches (such a batch touches most heavy rows)
  *   "lsm_max_patch" with lsm_updates: at most this many appended entries
  *                   per direction (0, default: the slot's slack; a
  *                   compaction leaves m / 2 + 2^22 entries of it, and

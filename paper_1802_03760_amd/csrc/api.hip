@@ -246,6 +246,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "lsm_max_patch") {
       GJ_CHECK(value >= 0, GJ_EINVAL, "lsm_max_patch must be >= 0");
       c->lsm_max_patch = (uint64_t)value;
+    } else if (k == "lsm_fold_min") {
+      GJ_CHECK(value >= 0, GJ_EINVAL, "lsm_fold_min must be >= 0");
+      c->lsm_fold_min = (uint64_t)value;
     } else if (k == "batch_cap") {
       GJ_CHECK(value >= 64 && value <= (1ll << 32), GJ_EINVAL, "batch_cap out of range");
       c->batch_cap = (uint64_t)value;
@@ -285,6 +288,7 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "lsm_max_patch") *value = (int64_t)c->lsm_max_patch;
     else if (k == "lsm_compactions") *value = (int64_t)c->lsm_compactions;
     else if (k == "lsm_folds") *value = (int64_t)c->lsm_folds;
+    else if (k == "lsm_fold_min") *value = (int64_t)c->lsm_fold_min;
     else if (k == "owner_task_min") *value = (int64_t)c->owner_task_min;
     else if (k == "hash_index") *value = c->hash_index;
     else if (k == "hash_min_degree") *value = c->hash_min_degree;
@@ -728,6 +732,7 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->batch_heavy = src->batch_heavy;
   dst->lsm_updates = src->lsm_updates;
   dst->lsm_max_patch = src->lsm_max_patch;
+  dst->lsm_fold_min = src->lsm_fold_min;
 }
 
 gj_status settle(gj_ctx* c, const gj_graph* g) {

@@ -197,13 +197,14 @@ struct gj_ctx {
   int propose_u = 4;  // candidates per lane tested in lockstep by the generic propose kernel (1, 2, 4)
   int lsm_updates = 0;  // gj_apply_updates: append rewritten rows instead of rewriting both indexes
   uint64_t lsm_max_patch = 0;  // arena entries per direction before a compaction (0: the slot's slack)
+  uint64_t lsm_fold_min = 8192;  // batches of at least this many changes fold without sizing their rows
   uint64_t lsm_compactions = 0;  // compactions run on this context
   uint64_t lsm_folds = 0;  // batches written as a new version while appended rows were pending
   uint64_t owner_task_min = 1ull << 20;  // least proposals per owner task (owner-grouped kernel)
   int hash_index = 1;      // 0: rows are searched; 1, 2: membership indexes are used where built
   bool hash_build = true;  // this context builds missing indexes on static reads
   uint32_t hash_min_degree = 32;  // rows of at least this many entries get a table
-  uint64_t hash_build_work = 16;  // build once reads of a version proposed this many candidates per edge
+  uint64_t hash_build_work = 64;  // build once reads of a version proposed this many candidates per edge
   uint64_t hash_builds = 0;       // membership indexes built by this context
   uint64_t owner_tasks = 0;        // tasks of the last owner-grouped launch
   uint64_t owner_split_units = 0;  // owner units of that launch cut into more than one task

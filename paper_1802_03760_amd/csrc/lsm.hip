@@ -412,6 +412,9 @@ bool appends(const gj_ctx* c, const gj_graph* g, const DirPlan (&P)[2]) {
 
 bool lsm_update(gj_ctx* c, gj_graph* g, const uint32_t* const (&r)[2], const uint32_t* const (&x)[2],
                 const int8_t* const (&sg)[2], uint64_t k, Version& oldv, Version& newv, LsmCommit& commit) {
+  // a batch this large touches most heavy rows: it is written as a new
+  // version without sizing its rows first
+  if (k >= c->lsm_fold_min) return false;
   lsm_alloc(c, g);
   DirPlan P[2];
   for (int d = 0; d < 2; ++d) {

@@ -198,3 +198,31 @@ def test_lsm_option_off_mid_stream(gj):
     finally:
         srv.close()
     assert ctx.get_option("lsm_compactions") == 1
+
+
+@pytest.mark.parametrize("fold_min", [0, 40])
+def test_lsm_fold_min(gj, fold_min):
+    """lsm_fold_min: batches of at least that many distinct changes are
+    written as a new version of both indexes without sizing their rows (the
+    appended rows folded in); smaller ones append.  With 0 no batch appends.
+    Deltas, counters and the final index equal the oracle's."""
+    n = 60
+    rng = np.random.default_rng(9)
+    src = rng.integers(0, n, 500).astype(np.uint32)
+    dst = rng.integers(0, n, 500).astype(np.uint32)
+    ctx = lsm_ctx(gj)
+    ctx.set_option("lsm_fold_min", fold_min)
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle.Graph(n, src, dst)
+    qs_py = [Q.TRIANGLE, Q.CLIQUE4]
+    qs_gj = [gj.Query(ctx, *q) for q in qs_py]
+    for it in range(10):
+        b = 80 if it % 3 == 2 else int(rng.integers(1, 15))  # every third batch above 40 changes
+        check_step(gj, ctx, G, O, qs_py, qs_gj, *random_batch(rng, O, n, b))
+    folds = ctx.get_option("lsm_folds")
+    if fold_min == 0:
+        assert folds == 0  # nothing was ever appended
+    else:
+        assert folds >= 2  # the large batches after appended ones
+    assert ctx.get_option("lsm_compactions") == 0
+    final_checks(gj, ctx, G, O, qs_py, qs_gj)
