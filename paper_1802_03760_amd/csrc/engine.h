@@ -71,6 +71,9 @@ struct Level {
   uint64_t* mask = nullptr;
   uint32_t* wcnt = nullptr;
   uint64_t* woff = nullptr;
+  // per-prefix records of count-minimisation (StageDesc::pl, ent), or null
+  uint32_t* pl = nullptr;
+  uint64_t* ent = nullptr;
 };
 
 class Runner {
@@ -94,6 +97,7 @@ class Runner {
 
  private:
   void stage(int j, uint64_t n);
+  StageDesc desc(int j, int lvl);
   void factorised(int j0, uint64_t n);
   void ensure_rows(uint64_t need);
   Level L[GJ_MAX_ATTRS + 1];

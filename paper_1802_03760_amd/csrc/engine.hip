@@ -193,6 +193,12 @@ Runner::Runner(gj_ctx* c_, const PlanH& P_, const Views& V_, bool weighted_, boo
     l.mask = (uint64_t*)ws_get(c, t + "mask", words * sizeof(uint64_t));
     l.wcnt = (uint32_t*)ws_get(c, t + "wcnt", words * sizeof(uint32_t));
     l.woff = (uint64_t*)ws_get(c, t + "woff", (words + 1) * sizeof(uint64_t));
+    // the allocation-free count keeps to the frontier-only form (its batch
+    // bounds are sized without the records)
+    if (!c->arena.on && P.ntri == 0) {
+      l.pl = (uint32_t*)ws_get(c, t + "pl", l.cap * sizeof(uint32_t) + 16);
+      l.ent = (uint64_t*)ws_get(c, t + "ent", l.cap * P.bind[j].size() * sizeof(uint64_t) + 16);
+    }
   }
   if (P.m == 2) {
     Level& l = L[2];
@@ -291,16 +297,19 @@ void Runner::stage(int j, uint64_t n) {
     factorised(j, n);
     return;
   }
-  StageDesc d = stage_desc(P, V, j);
+  StageDesc d = desc(j, j);
   launch_count_min(c, l.F, l.cap, n, d, l.minc, l.mini);
   scan_u32_to_u64(c, l.minc, l.off, n);
   uint64_t W = read_u64(c, l.off + n);
   st.extensions[j] += W;
   if (W == 0) return;
   // a static read that tests membership counts its candidates towards the
-  // version's index, built once they pay for it
-  if (V.graph && d.k >= 2 && !d.hd[0] && !d.hd[1] && hash_note_work(c, V.graph, *V.old_v, W))
-    d = stage_desc(P, V, j);
+  // version's index, built once they pay for it (the records are written
+  // again to name the new tables; the counts do not change)
+  if (V.graph && d.k >= 2 && !d.hd[0] && !d.hd[1] && hash_note_work(c, V.graph, *V.old_v, W)) {
+    d = desc(j, j);
+    if (d.ent) launch_count_min(c, l.F, l.cap, n, d, l.minc, l.mini);
+  }
   bool final = j + 1 == P.m;
   if (final && !collect) {
     timer.start();
@@ -345,7 +354,7 @@ void Runner::factorised(int j0, uint64_t n) {
   uint32_t* cnt = (uint32_t*)ws_get(c, "fact_cnt", (uint64_t)T * l.cap * sizeof(uint32_t) + 16);
   bool zero = false;
   for (int t = j0; t < P.m; ++t) {
-    StageDesc d = stage_desc(P, V, t);  // its columns and inequalities all lie before j0
+    StageDesc d = desc(t, j0);  // its columns and inequalities all lie before j0
     launch_count_min(c, l.F, l.cap, n, d, l.minc, l.mini);
     scan_u32_to_u64(c, l.minc, l.off, n);
     uint64_t W = read_u64(c, l.off + n);
@@ -359,6 +368,23 @@ void Runner::factorised(int j0, uint64_t n) {
     timer.stop();
   }
   if (!zero) launch_factor_sum(c, cnt, l.cap, n, T, acc);
+}
+
+// Stage j's descriptor over the prefixes of level lvl, with that level's
+// record buffers when every binding atom is binary, the buffers hold one
+// record per atom, and every row it may read stays below 2^31 entries.
+StageDesc Runner::desc(int j, int lvl) {
+  StageDesc d = stage_desc(P, V, j);
+  const Level& l = L[lvl];
+  if (!l.ent || d.ntri || P.bind[j].size() > P.bind[lvl].size()) return d;
+  for (const BindH& b : P.bind[j]) {
+    const Version& v = V.of(b.atom);
+    if (v.max_deg[0] >= (1u << 30) || v.max_deg[1] >= (1u << 30)) return d;
+  }
+  d.pl = l.pl;
+  d.ent = l.ent;
+  d.es = l.cap;
+  return d;
 }
 
 // counts: acc[0] unsigned matches, acc[1] signed weight sum

@@ -65,7 +65,19 @@ struct StageDesc {
   // null: hd[a][v] describes row v's table in hs[a] (0: no table)
   const uint64_t* hd[kMaxBind];
   const uint32_t* hs[kMaxBind];
+  // Per-prefix records written by count-minimisation (the prefix's count and
+  // proposing index of Sec. 3.1, with where its sets live), or null: the
+  // stage kernels then resolve every candidate's rows from the frontier.
+  // pl[p]: start of the proposing atom's row in adj[mini[p]];
+  // ent[a * es + p] for the other atoms: the row's table descriptor (as
+  // hd), or kEntRange | length << 32 | start when it has none.  Binary atoms
+  // only (no ternary binding in the stage), rows below 2^31 entries.
+  uint32_t* pl;
+  uint64_t* ent;
+  uint64_t es;
 };
+
+constexpr uint64_t kEntRange = 1ull << 63;
 
 // Membership filters of the seed pairs (atoms over the first two attributes
 // other than the seed atom): keep (x0, x1) iff x[val] is in adj[rp[x[key]]..].

@@ -70,15 +70,20 @@ __device__ __forceinline__ uint32_t tri_set(const StageDesc& d, int a, const uin
 
 // ---------------------------------------------------------------- count-minimisation
 // min_c = smallest extension-set size over the binding atoms, min_i = its
-// binding index (ties: lowest, i.e. lowest atom index).
+// binding index (ties: lowest, i.e. lowest atom index).  With d.ent, also the
+// prefix's records: where the proposing row starts, and for every other atom
+// its table descriptor or row range, so that the propose and emit kernels
+// read one record per atom instead of the frontier, row pointers and maps.
 __global__ void k_count_min(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n, StageDesc d,
                             uint32_t* __restrict__ minc, uint8_t* __restrict__ mini) {
   uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
     uint32_t best = 0xFFFFFFFFu;
     int bi = 0;
+    uint32_t rlo[kMaxBind], rlen[kMaxBind], rv[kMaxBind];
 #pragma unroll
     for (int a = 0; a < kMaxBind; ++a) {
+      rlo[a] = rlen[a] = rv[a] = 0;
       if (a < d.k) {
         uint32_t c;
         if (d.col2[a] >= 0) {
@@ -88,6 +93,9 @@ __global__ void k_count_min(const uint32_t* __restrict__ F, uint64_t stride, uin
           uint32_t v = F[(uint64_t)d.col[a] * stride + p], lo, hi;
           row_range(d.rp[a], d.pm[a], v, lo, hi);
           c = hi - lo;
+          rlo[a] = lo;
+          rlen[a] = c;
+          rv[a] = v;
         }
         if (c < best) {
           best = c;
@@ -97,6 +105,24 @@ __global__ void k_count_min(const uint32_t* __restrict__ F, uint64_t stride, uin
     }
     minc[p] = best;
     mini[p] = (uint8_t)bi;
+    if (d.ent && best) {
+      uint32_t start = 0;
+#pragma unroll
+      for (int a = 0; a < kMaxBind; ++a) {
+        if (a >= d.k) continue;
+        if (a == bi) {
+          start = rlo[a];
+          continue;
+        }
+        uint64_t r = kEntRange | ((uint64_t)rlen[a] << 32) | rlo[a];
+        if (d.hd[a]) {
+          uint64_t dd = d.hd[a][rv[a]];
+          if (dd) r = dd;
+        }
+        d.ent[(uint64_t)a * d.es + p] = r;
+      }
+      d.pl[p] = start;
+    }
   }
 }
 
@@ -108,6 +134,7 @@ struct Cand {
   int am;
 };
 
+template <bool REC>
 __device__ __forceinline__ Cand resolve(const uint32_t* __restrict__ F, uint64_t stride,
                                         const uint64_t* __restrict__ off, const uint8_t* __restrict__ mini,
                                         const StageDesc& d, uint64_t plo, uint64_t phi, uint64_t g) {
@@ -115,6 +142,22 @@ __device__ __forceinline__ Cand resolve(const uint32_t* __restrict__ F, uint64_t
   c.p = find_segment(off, plo, phi, g);
   uint32_t k = (uint32_t)(g - off[c.p]);
   c.am = mini[c.p];
+  if (REC) {
+    const uint32_t* adj;
+    switch (c.am) {
+#define GJ_PICK(A) \
+  case A:          \
+    adj = d.adj[A]; \
+    break;
+      GJ_PICK(1) GJ_PICK(2) GJ_PICK(3) GJ_PICK(4) GJ_PICK(5) GJ_PICK(6) GJ_PICK(7)
+#undef GJ_PICK
+      default:
+        adj = d.adj[0];
+        break;
+    }
+    c.e = adj[d.pl[c.p] + k];
+    return c;
+  }
   if (d.ntri) {
     bool tri = false;
 #pragma unroll
@@ -159,6 +202,7 @@ __device__ __forceinline__ Cand resolve(const uint32_t* __restrict__ F, uint64_t
   return c;
 }
 
+template <bool REC>
 __device__ __forceinline__ bool intersect_all(const uint32_t* __restrict__ F, uint64_t stride, const StageDesc& d,
                                               const Cand& c) {
   bool keep = ineq_ok(F, stride, c.p, d.above, d.below, c.e);
@@ -169,6 +213,16 @@ __device__ __forceinline__ bool intersect_all(const uint32_t* __restrict__ F, ui
         uint64_t lo;
         uint32_t len = tri_set(d, a, F, stride, c.p, lo);
         keep = contains_u32(d.tcol + lo, 0, len, c.e);
+        continue;
+      }
+      if (REC) {
+        const uint64_t r = d.ent[(uint64_t)a * d.es + c.p];
+        if (r & kEntRange) {
+          const uint32_t lo = (uint32_t)r;
+          keep = contains_u32(d.adj[a], lo, lo + (uint32_t)((r >> 32) & 0x7FFFFFFFu), c.e);
+        } else {
+          keep = hash_member(d.hs[a], r, c.e);
+        }
         continue;
       }
       uint32_t u = F[(uint64_t)d.col[a] * stride + c.p], lo, hi;
@@ -188,7 +242,7 @@ __device__ __forceinline__ bool intersect_all(const uint32_t* __restrict__ F, ui
 // binary searches issues the U loads before any comparison, so a wave keeps
 // U dependent-load chains in flight instead of one (the searches are bound by
 // load latency, not bandwidth).  Binary bindings only.
-template <int U>
+template <int U, bool REC>
 __device__ __forceinline__ void intersect_lockstep(const uint32_t* __restrict__ F, uint64_t stride,
                                                    const StageDesc& d, const Cand (&c)[U], bool (&keep)[U]) {
 #pragma unroll
@@ -206,7 +260,17 @@ __device__ __forceinline__ void intersect_lockstep(const uint32_t* __restrict__ 
         act[u] = keep[u] && a != c[u].am;
         lo[u] = hi[u] = n[u] = 0;
         dd[u] = 0;
-        if (act[u]) {
+        if (REC) {
+          if (!act[u]) continue;
+          const uint64_t r = d.ent[(uint64_t)a * d.es + c[u].p];
+          if (r & kEntRange) {
+            lo[u] = (uint32_t)r;
+            n[u] = (uint32_t)((r >> 32) & 0x7FFFFFFFu);
+            hi[u] = lo[u] + n[u];
+          } else {
+            dd[u] = r;
+          }
+        } else if (act[u]) {
           uint32_t x = F[(uint64_t)d.col[a] * stride + c[u].p];
           if (d.hd[a]) dd[u] = d.hd[a][x];
           if (!dd[u]) {
@@ -284,7 +348,7 @@ __device__ __forceinline__ void intersect_lockstep(const uint32_t* __restrict__ 
 //         consecutive, so a wave adds once per prefix it touches).
 // A wave takes U words (64 candidates each) per step, one candidate of each
 // per lane, and tests their memberships in lockstep.
-template <int MODE, int U>
+template <int MODE, int U, bool REC>
 __global__ void __launch_bounds__(kBlock) k_propose(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n,
                                                     const uint64_t* __restrict__ off,
                                                     const uint8_t* __restrict__ mini, StageDesc d, uint64_t w0,
@@ -319,16 +383,16 @@ __global__ void __launch_bounds__(kBlock) k_propose(const uint32_t* __restrict__
       c[u].e = 0;
       c[u].am = 0;
       if (keep[u]) {
-        c[u] = resolve(F, stride, off, mini, d, plo, phi, g);
+        c[u] = resolve<REC>(F, stride, off, mini, d, plo, phi, g);
         pp[u] = c[u].p;
       }
     }
     if (U == 1 || d.ntri) {
 #pragma unroll
       for (int u = 0; u < U; ++u)
-        if (keep[u]) keep[u] = intersect_all(F, stride, d, c[u]);
+        if (keep[u]) keep[u] = intersect_all<REC>(F, stride, d, c[u]);
     } else {
-      intersect_lockstep<U>(F, stride, d, c, keep);
+      intersect_lockstep<U, REC>(F, stride, d, c, keep);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -372,7 +436,7 @@ __global__ void __launch_bounds__(kBlock) k_propose(const uint32_t* __restrict__
 // KIND 1: rows of map.m values in attribute order at rows[(obase+pos)*m],
 // signs to osign, only for obase + pos < ocap.
 // KIND 2: the new values only, at G[obase + pos] for obase + pos < ocap.
-template <int KIND>
+template <int KIND, bool REC>
 __global__ void __launch_bounds__(kBlock) k_emit(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n,
                                                  const uint64_t* __restrict__ off, const uint8_t* __restrict__ mini,
                                                  StageDesc d, uint64_t w0, uint64_t w1,
@@ -395,7 +459,7 @@ __global__ void __launch_bounds__(kBlock) k_emit(const uint32_t* __restrict__ F,
     plo = gallop_segment(off, plo, n, gf);
     phi = gallop_segment(off, plo, n, gl) + 1;
     if (!((b >> lane) & 1)) continue;
-    Cand c = resolve(F, stride, off, mini, d, plo, phi, gf + lane);
+    Cand c = resolve<REC>(F, stride, off, mini, d, plo, phi, gf + lane);
     uint64_t pos = woff[wd] + __popcll(b & lanemask_lt());
     if (KIND == 2) {
       if (obase + pos < ocap) G[obase + pos] = c.e;
@@ -471,10 +535,14 @@ void launch_propose(gj_ctx* c, int mode, const uint32_t* F, uint64_t stride, uin
   unsigned gr = propose_grid(c, words);
   // ternary bindings search one candidate at a time: wider steps only cost occupancy
   int u = d.ntri && c->propose_u > 2 ? 2 : c->propose_u;
-  switch (mode * 8 + u) {
-#define GJ_PROPOSE(M, U)                                                                                  \
-  case M * 8 + U:                                                                                        \
-    k_propose<M, U><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc); \
+  // with per-prefix records, instances without the frontier-resolution code
+  switch (mode * 16 + u * 2 + (d.ent ? 1 : 0)) {
+#define GJ_PROPOSE(M, U)                                                                                        \
+  case M * 16 + U * 2:                                                                                         \
+    k_propose<M, U, false><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc); \
+    break;                                                                                                     \
+  case M * 16 + U * 2 + 1:                                                                                     \
+    k_propose<M, U, true><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, wcnt, wt, acc);  \
     break;
     GJ_PROPOSE(0, 1) GJ_PROPOSE(0, 2) GJ_PROPOSE(0, 4)
     GJ_PROPOSE(1, 1) GJ_PROPOSE(1, 2) GJ_PROPOSE(1, 4)
@@ -512,12 +580,21 @@ void launch_emit(gj_ctx* c, bool final_rows, const uint32_t* F, uint64_t stride,
                  const RowMap& map, uint64_t obase, uint64_t ocap) {
   uint64_t words = (w1 - w0 + 63) >> 6;
   unsigned gr = propose_grid(c, words);
-  if (final_rows)
-    k_emit<1><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, wt, G, gstride, Gw,
-                                            map, obase, ocap);
-  else
-    k_emit<0><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, wt, G, gstride, Gw,
-                                            map, obase, ocap);
+#define GJ_EMIT(K, R)                                                                                       \
+  k_emit<K, R><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, wt, G, gstride, Gw, \
+                                             map, obase, ocap)
+  if (final_rows) {
+    if (d.ent)
+      GJ_EMIT(1, true);
+    else
+      GJ_EMIT(1, false);
+  } else {
+    if (d.ent)
+      GJ_EMIT(0, true);
+    else
+      GJ_EMIT(0, false);
+  }
+#undef GJ_EMIT
   GJ_HIP(hipGetLastError());
 }
 
@@ -527,8 +604,9 @@ void launch_emit_values(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t 
   uint64_t words = (w1 - w0 + 63) >> 6;
   unsigned gr = propose_grid(c, words);
   RowMap map{};
-  k_emit<2><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, nullptr, out, 0,
-                                          nullptr, map, obase, ocap);
+  GJ_CHECK(!d.ent, GJ_EINVAL, "per-prefix records with ternary bindings");
+  k_emit<2, false><<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, mini, d, w0, w1, mask, woff, nullptr, out, 0,
+                                                 nullptr, map, obase, ocap);
   GJ_HIP(hipGetLastError());
 }
 
