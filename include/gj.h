@@ -166,6 +166,32 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   compaction leaves m / 2 + 2^22 entries of it, and
  *                   reallocates the slot when less than half of that is
  *                   left)
+ *   "run_stage"     1 (default): the last stage of a count on the
+ *                   depth-first path (gj_run, depth-first delta queries,
+ *                   the server's heavy lanes), when its binary atoms split
+ *                   into at least one reading an earlier column and at most
+ *                   one reading the last bound column, is counted grouped
+ *                   by prefix runs: consecutive prefixes that agree on the
+ *                   columns the earlier atoms read share those atoms'
+ *                   extension sets, so one workgroup intersects them once
+ *                   into an LDS hash table (at most 24,576 values) and counts
+ *                   every prefix of the run against it (O(1) membership,
+ *                   Sec. 2.2).  Runs with a larger shared set, or too little
+ *                   work, stay with the per-candidate kernel.  0 always
+ *                   uses the per-candidate kernel; "strategy" 1 does too.
+ *                   Counts and counters are the same either way
+ *   "run_ratio"     run_stage: a prefix's own set is streamed through the
+ *                   table when it holds at most this many times the shared
+ *                   set's values, else the shared values are looked up in
+ *                   it (0..64, default 2)
+ *   "run_min_work"  run_stage: least count-minimised candidates of a run
+ *                   for it to be staged (default 256, >= 0); a staged run
+ *                   also needs at least twice its smallest shared set
+ *   "run_task_work" run_stage: a run's prefixes are cut into tasks of about
+ *                   this many candidates plus 8 per value the build reads
+ *                   (default 2^15, >= 1)
+ *   "run_stage_min" run_stage: least count-minimised candidates of a stage
+ *                   for it to take the run kernels (default 2^16, >= 0)
  * Returns GJ_EINVAL for an unknown key or out-of-range value. */
 gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
 
@@ -175,7 +201,12 @@ gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
  * depth-first path), "hash_builds" (membership indexes this context built),
  * and of the last owner-grouped launch on this context
  * "owner_tasks" (its tasks) and "owner_split_units" (units cut into more
- * than one task)). */
+ * than one task), and of the run kernels (see "run_stage") on this context
+ * "run_tasks", "run_tasks_big" (of them, tasks of the large-set shape),
+ * "run_w_staged", "run_w_large", "run_w_light" (count-minimised candidates
+ * of runs staged, with a shared set above the tables, with too little
+ * work), "run_units" (values tested), "run_builds" and "run_build_elems"
+ * (shared sets built, and the values they streamed)). */
 gj_status gj_ctx_get_option(gj_ctx* ctx, const char* key, int64_t* value);
 
 /* ---------------------------------------------------------------- graphs */

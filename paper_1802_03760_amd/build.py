@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgj.so")
 OBJ = os.path.join(os.path.dirname(HERE), "_build", "gj")
 SOURCES = ["api.hip", "scan.hip", "sort.hip", "graph.hip", "stage.hip", "engine.hip", "owner.hip",
-           "rows.hip", "delta.hip", "batch.hip", "sched.hip", "tri.hip", "clique.hip", "lsm.hip", "noalloc.hip", "calib.hip", "hash.hip", "tune.cpp", "server.cpp"]
+           "rows.hip", "delta.hip", "batch.hip", "sched.hip", "tri.hip", "clique.hip", "lsm.hip", "noalloc.hip", "calib.hip", "hash.hip", "run.hip", "tune.cpp", "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # no packed-FP32 instructions in device code

@@ -258,6 +258,21 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "batch_claim_words") {
       GJ_CHECK(value >= 1 && value <= 4096, GJ_EINVAL, "batch_claim_words out of range");
       c->batch_claim_words = (uint32_t)value;
+    } else if (k == "run_stage") {
+      GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "run_stage must be 0 or 1");
+      c->run_stage = (int)value;
+    } else if (k == "run_ratio") {
+      GJ_CHECK(value >= 0 && value <= 64, GJ_EINVAL, "run_ratio out of range");
+      c->run_ratio = (uint32_t)value;
+    } else if (k == "run_min_work") {
+      GJ_CHECK(value >= 0, GJ_EINVAL, "run_min_work must be >= 0");
+      c->run_min_work = (uint64_t)value;
+    } else if (k == "run_task_work") {
+      GJ_CHECK(value >= 1 && value <= (1ll << 40), GJ_EINVAL, "run_task_work out of range");
+      c->run_task_work = (uint64_t)value;
+    } else if (k == "run_stage_min") {
+      GJ_CHECK(value >= 0, GJ_EINVAL, "run_stage_min must be >= 0");
+      c->run_stage_min = (uint64_t)value;
     } else if (k == "batch_waves_per_cu") {
       GJ_CHECK(value >= 4 && value <= 128 && value % 4 == 0, GJ_EINVAL, "batch_waves_per_cu out of range");
       c->batch_waves_per_cu = (uint32_t)value;
@@ -294,6 +309,19 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "hash_min_degree") *value = c->hash_min_degree;
     else if (k == "hash_build_work") *value = (int64_t)c->hash_build_work;
     else if (k == "hash_builds") *value = (int64_t)c->hash_builds;
+    else if (k == "run_stage") *value = c->run_stage;
+    else if (k == "run_ratio") *value = c->run_ratio;
+    else if (k == "run_min_work") *value = (int64_t)c->run_min_work;
+    else if (k == "run_task_work") *value = (int64_t)c->run_task_work;
+    else if (k == "run_stage_min") *value = (int64_t)c->run_stage_min;
+    else if (k == "run_tasks") *value = (int64_t)c->run_tasks;
+    else if (k == "run_tasks_big") *value = (int64_t)c->run_tasks_big;
+    else if (k == "run_w_staged") *value = (int64_t)c->run_w_staged;
+    else if (k == "run_w_large") *value = (int64_t)c->run_w_large;
+    else if (k == "run_w_light") *value = (int64_t)c->run_w_light;
+    else if (k == "run_units") *value = (int64_t)c->run_units;
+    else if (k == "run_builds") *value = (int64_t)c->run_builds;
+    else if (k == "run_build_elems") *value = (int64_t)c->run_build_elems;
     else if (k == "owner_tasks") *value = (int64_t)c->owner_tasks;
     else if (k == "owner_split_units") *value = (int64_t)c->owner_split_units;
     else throw Error{GJ_EINVAL, "unknown option " + k};
@@ -733,6 +761,11 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->lsm_updates = src->lsm_updates;
   dst->lsm_max_patch = src->lsm_max_patch;
   dst->lsm_fold_min = src->lsm_fold_min;
+  dst->run_stage = src->run_stage;
+  dst->run_ratio = src->run_ratio;
+  dst->run_min_work = src->run_min_work;
+  dst->run_task_work = src->run_task_work;
+  dst->run_stage_min = src->run_stage_min;
 }
 
 gj_status settle(gj_ctx* c, const gj_graph* g) {

@@ -13,6 +13,7 @@
 #include "engine.h"
 #include "gj_internal.h"
 #include "owner.h"
+#include "run.h"
 
 namespace gj {
 
@@ -311,6 +312,19 @@ void Runner::stage(int j, uint64_t n) {
     if (d.ent) launch_count_min(c, l.F, l.cap, n, d, l.minc, l.mini);
   }
   bool final = j + 1 == P.m;
+  RunDesc rd;
+  if (final && !collect && c->run_stage && c->strategy != 1 && !c->arena.on && W >= c->run_stage_min && run_desc(d, rd)) {
+    // prefix runs sharing their old sets take the run kernels; the rest of
+    // the candidates the per-candidate kernel
+    uint64_t* off2 = (uint64_t*)ws_get(c, "run_off2", (l.cap + 1) * sizeof(uint64_t));
+    uint64_t W2 = run_count(c, l.F, l.cap, n, l.off, l.minc, d, rd, weighted ? l.Fw : nullptr, acc, off2, timer);
+    if (W2) {
+      timer.start();
+      launch_propose(c, weighted ? 2 : 1, l.F, l.cap, n, off2, l.mini, d, 0, W2, nullptr, nullptr, l.Fw, acc);
+      timer.stop();
+    }
+    return;
+  }
   if (final && !collect) {
     timer.start();
     launch_propose(c, weighted ? 2 : 1, l.F, l.cap, n, l.off, l.mini, d, 0, W, nullptr, nullptr, l.Fw, acc);

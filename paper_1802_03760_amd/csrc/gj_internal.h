@@ -218,6 +218,20 @@ struct gj_ctx {
   uint32_t hash_min_degree = 32;  // rows of at least this many entries get a table
   uint64_t hash_build_work = 64;  // build once reads of a version proposed this many candidates per edge
   uint64_t hash_builds = 0;       // membership indexes built by this context
+  int run_stage = 1;               // last-stage counts grouped by prefix runs where they apply
+  uint32_t run_ratio = 2;          // stream a new set through S's table up to this many times |S|
+  uint64_t run_min_work = 256;     // least count-minimised candidates of a staged run
+  uint64_t run_task_work = 1ull << 15;  // candidates per task of a staged run beyond its build
+  uint64_t run_stage_min = 1ull << 16;  // least candidates of a stage taken by the run kernels
+  uint64_t run_tasks = 0;          // tasks of the run kernels on this context
+  uint64_t run_tasks_big = 0;      // of those, tasks of the large-set shape
+  // count-minimised candidates of the stages offered to the run kernels: in
+  // staged runs, in runs whose shared set exceeds the table, in runs with too
+  // little work to repay a build
+  uint64_t run_w_staged = 0, run_w_large = 0, run_w_light = 0;
+  // work of the counting kernel: units (values tested), builds of a shared
+  // set, and the values those builds streamed
+  uint64_t run_units = 0, run_builds = 0, run_build_elems = 0;
   uint64_t owner_tasks = 0;        // tasks of the last owner-grouped launch
   uint64_t owner_split_units = 0;  // owner units of that launch cut into more than one task
 };

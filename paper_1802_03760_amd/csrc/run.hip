@@ -1,0 +1,616 @@
+// Last-stage counts grouped by prefix runs.
+//
+// The atoms binding attribute j split into new ones, whose other attribute
+// is the last bound column j-1, and old ones, which read earlier columns.
+// Consecutive prefixes of a frontier that agree on every column an old atom
+// reads (a run; frontiers are written in lexicographic order, so such
+// prefixes sit together) have the same old extension sets, hence the same
+// intersection S of them.  Generic Join's proposal and intersection for a
+// prefix p of the run (Sec. 2.2, Sec. 4.1) then reduce to |S & new set of p|
+// within p's inequality range.  One workgroup builds S once per run (or per
+// share of a long run) into an LDS hash table, so its membership tests are
+// O(1) LDS probes, and per prefix takes the cheaper side by the ratio of the
+// two sizes: the new set streamed from memory (coalesced) through the table
+// when it holds at most `run_ratio` x |S| values, else S's values probed
+// against the new set's own table or row.  A run's prefixes are cut into
+// tasks of about equal work (the balanced split of Sec. 3.4), claimed from a
+// device counter.  Runs whose S could outgrow the table, or whose work would
+// not repay the build, keep the per-candidate kernel: their counts of
+// candidates stay in a second candidate space, the staged runs' set to zero.
+#include <algorithm>
+#include <cstring>
+
+#include "gj_internal.h"
+#include "prim.h"
+#include "run.h"
+
+namespace gj {
+
+// Two workgroup shapes: small shared sets (at most 4,096 values, a 32 KiB
+// table and S's values in LDS, two workgroups of 512 threads per CU) and
+// large ones (at most 24,576 values, a 128 KiB table at load <= 3/4, S's
+// values in a per-workgroup global buffer, one workgroup of 1,024 threads per
+// CU).  Larger sets stay with the per-candidate kernel.
+template <bool BIG>
+struct RunShape;
+template <>
+struct RunShape<false> {
+  static constexpr int NT = 512;
+  static constexpr uint32_t CAP = 4096;
+  static constexpr int LOG_SLOTS = 13;
+};
+template <>
+struct RunShape<true> {
+  static constexpr int NT = 1024;
+  static constexpr uint32_t CAP = 24576;
+  static constexpr int LOG_SLOTS = 15;
+};
+constexpr uint32_t kRunCap = RunShape<false>::CAP;
+constexpr uint32_t kRunCapBig = RunShape<true>::CAP;
+constexpr uint32_t kRunChunk = 512;  // prefixes per chunk (one thread each)
+constexpr uint32_t kRunEmpty = 0xFFFFFFFFu;
+constexpr int kRunU = 2;                // units per thread per step, loads in flight together
+
+// ---------------------------------------------------------------- planning
+// head[p] = 1 where a run starts: p = 0, or a key column differs from p - 1.
+__global__ void k_run_heads(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n, int r,
+                            uint32_t* __restrict__ head) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
+    uint32_t h = p == 0;
+    for (int c = 0; c < r && !h; ++c) h = F[(uint64_t)c * stride + p] != F[(uint64_t)c * stride + p - 1];
+    head[p] = h;
+  }
+}
+
+// rs[run] = its first prefix; rs[runs] = n
+// (also clears the task counter of the counting kernel)
+__global__ void k_run_starts(const uint32_t* __restrict__ head, const uint64_t* __restrict__ hoff, uint64_t n,
+                             uint32_t* __restrict__ rs, unsigned int* __restrict__ counter) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  if (blockIdx.x == 0 && threadIdx.x < 16) counter[threadIdx.x] = 0;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
+    if (head[p]) rs[hoff[p]] = (uint32_t)p;
+    if (p + 1 == n) rs[hoff[n]] = (uint32_t)n;
+  }
+}
+
+// Row of binding atom a of the stage for value v (a a compile-time index in
+// every caller, so the descriptor's arrays are read without a private copy).
+__device__ __forceinline__ void atom_row(const StageDesc& d, int a, uint32_t v, uint32_t& lo, uint32_t& len) {
+  uint32_t hi;
+  row_range(d.rp[a], d.pm[a], v, lo, hi);
+  len = hi - lo;
+}
+
+// Per run (at its head): the size bound of S (smallest old set), the run's
+// candidates in the count-minimised space, whether it is staged, and its
+// number of tasks (tcnt[head]; 0 elsewhere and for unstaged runs).
+__global__ void k_run_plan(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n,
+                           const uint64_t* __restrict__ off, const uint32_t* __restrict__ head,
+                           const uint64_t* __restrict__ hoff, const uint32_t* __restrict__ rs, StageDesc d,
+                           RunDesc rd, uint32_t* __restrict__ tcnt, uint32_t* __restrict__ tcnt_big,
+                           uint8_t* __restrict__ staged, unsigned long long* __restrict__ wsum) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
+    uint32_t t = 0;
+    bool big = false;
+    if (head[p]) {
+      uint64_t rid = hoff[p];
+      uint64_t e = rs[rid + 1];
+      uint32_t B = 0xFFFFFFFFu;
+#pragma unroll
+      for (int a = 0; a < kMaxBind; ++a) {
+        if (a < d.k && ((rd.old_mask >> a) & 1)) {
+          uint32_t lo, len;
+          atom_row(d, a, F[(uint64_t)d.col[a] * stride + p], lo, len);
+          B = len < B ? len : B;
+        }
+      }
+      uint64_t W = off[e] - off[p];
+      bool st = B <= kRunCapBig && W >= rd.min_work && W >= 2ull * B;
+      big = B > kRunCap;
+      if (st) {
+        uint64_t per = rd.task_work + 8ull * B * (uint64_t)rd.nold;
+        uint64_t k = (W + per - 1) / per;
+        uint64_t kids = e - p;
+        t = (uint32_t)(k < 1 ? 1 : (k > kids ? kids : k));
+      }
+      staged[rid] = st ? 1 : 0;
+      // candidates by outcome: staged, shared set too large, too little work
+      atomicAdd(wsum + (st ? 0 : (B > kRunCapBig ? 1 : 2)), (unsigned long long)W);
+    }
+    tcnt[p] = big ? 0 : t;
+    tcnt_big[p] = big ? t : 0;
+  }
+}
+
+// The per-candidate kernel's counts: zero for prefixes of staged runs.
+__global__ void k_run_direct(const uint32_t* __restrict__ head, const uint64_t* __restrict__ hoff,
+                             const uint8_t* __restrict__ staged, uint64_t n, uint32_t* __restrict__ minc) {
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
+    uint64_t rid = hoff[p] + head[p] - 1;
+    if (staged[rid]) minc[p] = 0;
+  }
+}
+
+// ---------------------------------------------------------------- LDS table
+// Open addressing over buckets of four u32 slots (one 16-byte read each);
+// insertion fills the first empty slot from the home bucket on, so a bucket
+// with an empty last slot ends an unsuccessful search.
+__device__ __forceinline__ void run_insert(uint32_t* H, uint32_t x, int shift, uint32_t bmask) {
+  uint32_t b = (x * 0x9E3779B1u) >> shift;
+  for (;;) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (atomicCAS(&H[4 * b + k], kRunEmpty, x) == kRunEmpty) return;
+    b = (b + 1) & bmask;
+  }
+}
+
+__device__ __forceinline__ bool run_probe(const uint32_t* H, uint32_t x, int shift, uint32_t bmask) {
+  const uint4* B = reinterpret_cast<const uint4*>(H);
+  uint32_t b = (x * 0x9E3779B1u) >> shift;
+  for (;;) {
+    uint4 q = B[b];
+    if (min(min(q.x ^ x, q.y ^ x), min(q.z ^ x, q.w ^ x)) == 0u) return true;
+    if (q.w == kRunEmpty) return false;
+    b = (b + 1) & bmask;
+  }
+}
+
+// first i in [lo, hi) with a[i] >= x, else hi
+__device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* __restrict__ a, uint64_t lo, uint64_t hi,
+                                                    uint64_t x) {
+  uint64_t n = hi - lo;
+  while (n > 0) {
+    uint64_t half = n >> 1;
+    if (a[lo + half] < x) {
+      lo += half + 1;
+      n -= half + 1;
+    } else {
+      n = half;
+    }
+  }
+  return lo;
+}
+
+// last i in [0, n) with w[i] <= q (w ascending, w[0] = 0 <= q < w[n])
+__device__ __forceinline__ uint32_t run_owner(const uint32_t* w, uint32_t n, uint32_t q) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    uint32_t mid = (lo + hi) >> 1;
+    if (w[mid] <= q)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// x in the new atom's set of a prefix: its table (desc != 0) or its row
+__device__ __forceinline__ bool mem_member(const uint32_t* __restrict__ adj, const uint32_t* __restrict__ hs,
+                                           uint64_t desc, uint32_t lo, uint32_t len, uint32_t x) {
+  if (desc) return hash_member(hs, desc, x);
+  return contains_u32(adj, lo, lo + len, x);
+}
+
+// Membership of U values in the new sets of their prefixes, in lockstep
+// (each step issues the loads of every pending value before comparing):
+// want[u] asks for x[u] in the set with table descriptor desc[u] in hs, or,
+// without a table, in the sorted row adj[lo[u], lo[u] + len[u]).
+template <int U>
+__device__ __forceinline__ void member_lockstep(const uint32_t* __restrict__ adj, const uint32_t* __restrict__ hs,
+                                                const uint64_t (&desc)[U], const uint32_t (&lo)[U],
+                                                const uint32_t (&len)[U], const uint32_t (&x)[U],
+                                                const bool (&want)[U], bool (&hit)[U]) {
+  bool pend[U];
+  uint32_t h[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    pend[u] = want[u] && desc[u] != 0;
+    h[u] = pend[u] ? hash_home(x[u], (uint32_t)(desc[u] & 0xFF)) : 0u;
+  }
+  for (;;) {
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u) any = any || pend[u];
+    if (!any) break;
+    uint4 q[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      q[u] = pend[u] ? *(const uint4*)(hs + 4 * ((desc[u] >> 8) + h[u])) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (!pend[u]) continue;
+      const uint32_t e = x[u];
+      if (q[u].x == e || q[u].y == e || q[u].z == e || q[u].w == e) {
+        hit[u] = true;
+        pend[u] = false;
+      } else if (q[u].w == kHashEmpty) {
+        pend[u] = false;
+      } else {
+        h[u] = (h[u] + 1) & ((1u << (uint32_t)(desc[u] & 0xFF)) - 1);
+      }
+    }
+  }
+  uint32_t l[U], n[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    l[u] = lo[u];
+    n[u] = want[u] && desc[u] == 0 ? len[u] : 0u;
+  }
+  for (;;) {
+    bool any = false;
+#pragma unroll
+    for (int u = 0; u < U; ++u) any = any || n[u] > 0;
+    if (!any) break;
+    uint32_t v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = n[u] > 0 ? adj[l[u] + (n[u] >> 1)] : 0u;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (n[u] > 0) {
+        const uint32_t half = n[u] >> 1;
+        if (v[u] < x[u]) {
+          l[u] += half + 1;
+          n[u] -= half + 1;
+        } else {
+          n[u] = half;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u)
+    if (want[u] && desc[u] == 0) hit[u] = l[u] < lo[u] + len[u] && adj[l[u]] == x[u];
+}
+
+// ---------------------------------------------------------------- counting kernel
+template <bool SIGNED, bool BIG>
+__global__ void __launch_bounds__(RunShape<BIG>::NT) __attribute__((amdgpu_waves_per_eu(4))) k_run_count(const uint32_t* __restrict__ F, uint64_t stride,
+                                                                 uint64_t n, const uint64_t* __restrict__ off,
+                                                                 const uint64_t* __restrict__ hoff,
+                                                                 const uint32_t* __restrict__ rs,
+                                                                 const uint64_t* __restrict__ toff, StageDesc d,
+                                                                 RunDesc rd, const int8_t* __restrict__ wt,
+                                                                 uint32_t* __restrict__ sv_glob,
+                                                                 unsigned int* __restrict__ counter,
+                                                                 unsigned long long* __restrict__ acc,
+                                                                 unsigned long long* __restrict__ wsum) {
+  constexpr int kRunNT = RunShape<BIG>::NT;
+  constexpr int kRunLogSlots = RunShape<BIG>::LOG_SLOTS;
+  __shared__ __attribute__((aligned(16))) uint32_t H[1 << kRunLogSlots];
+  // S's values: in LDS (small shape) or this workgroup's global buffer
+  __shared__ uint32_t SvL[BIG ? 1 : RunShape<BIG>::CAP];
+  uint32_t* const SvG = sv_glob + (uint64_t)blockIdx.x * RunShape<BIG>::CAP;
+  __shared__ uint32_t coff[kRunChunk + 1];
+  __shared__ uint32_t clo[kRunChunk], clen[kRunChunk], clb[kRunChunk], cub[kRunChunk];
+  __shared__ uint64_t cdesc[kRunChunk];
+  __shared__ int8_t cw[kRunChunk];
+  __shared__ uint8_t cstream[kRunChunk];
+  __shared__ uint64_t s_cs, s_ce, s_head;
+  __shared__ uint32_t s_task, s_nS, s_small;
+  __shared__ uint32_t s_olo[kMaxBind], s_olen[kMaxBind];
+  __shared__ uint64_t s_odesc[kMaxBind];
+  const int tid = threadIdx.x;
+  const uint64_t ntask = toff[n];
+  // the new atom's arrays (the index is uniform over the launch)
+  const uint32_t* nrp = nullptr;
+  const uint32_t* nadj = nullptr;
+  const uint64_t* npm = nullptr;
+  const uint64_t* nhd = nullptr;
+  const uint32_t* nhs = nullptr;
+  int ncol = 0;
+  switch (rd.newa) {
+#define GJ_NEWA(A)     \
+  case A:              \
+    nrp = d.rp[A];     \
+    nadj = d.adj[A];   \
+    npm = d.pm[A];     \
+    nhd = d.hd[A];     \
+    nhs = d.hs[A];     \
+    ncol = d.col[A];   \
+    break;
+    GJ_NEWA(0) GJ_NEWA(1) GJ_NEWA(2) GJ_NEWA(3) GJ_NEWA(4) GJ_NEWA(5) GJ_NEWA(6) GJ_NEWA(7)
+#undef GJ_NEWA
+    default:
+      break;
+  }
+  uint64_t hits = 0, units = 0, builds = 0, belems = 0;
+  int64_t whits = 0;
+  uint64_t cached = ~0ull;  // head of the run whose S is in the table
+  uint32_t nS = 0;
+  int shift = 0;
+  uint32_t bmask = 0;
+  for (;;) {
+    if (tid == 0) {
+      uint32_t t = atomicAdd(counter, 1u);
+      s_task = t;
+      if (t < ntask) {
+        // the run (head prefix) of task t, its prefixes, and this task's share
+        // of them by equal parts of the run's candidates
+        uint64_t s = find_segment(toff, 0, n, t);
+        uint64_t e = rs[hoff[s] + 1];
+        uint64_t nt = toff[s + 1] - toff[s], i = t - toff[s];
+        uint64_t W = off[e] - off[s];
+        uint64_t q = W / nt, rm = W % nt;
+        uint64_t g0 = off[s] + q * i + rm * i / nt, g1 = off[s] + q * (i + 1) + rm * (i + 1) / nt;
+        s_cs = i == 0 ? s : lower_bound_u64(off, s, e, g0);
+        s_ce = i + 1 == nt ? e : lower_bound_u64(off, s, e, g1);
+        s_head = s;
+      }
+    }
+    __syncthreads();
+    if (s_task >= ntask) break;
+    const uint64_t head = s_head, cs = s_cs, ce = s_ce;
+    if (cs < ce && head != cached) {
+      // S = the intersection of the old sets of the run: the smallest one
+      // streamed, each value tested in the others (their tables or rows)
+      if (tid == 0) {
+        uint32_t best = 0xFFFFFFFFu;
+        int bi = 0;
+#pragma unroll
+        for (int a = 0; a < kMaxBind; ++a) {
+          if (a < d.k && ((rd.old_mask >> a) & 1)) {
+            uint32_t v = F[(uint64_t)d.col[a] * stride + head], lo, len;
+            atom_row(d, a, v, lo, len);
+            s_olo[a] = lo;
+            s_olen[a] = len;
+            s_odesc[a] = d.hd[a] ? d.hd[a][v] : 0ull;
+            if (len < best) {
+              best = len;
+              bi = a;
+            }
+          }
+        }
+        s_small = (uint32_t)bi;
+        s_nS = 0;
+      }
+      for (uint32_t k = tid; k < (1u << kRunLogSlots); k += kRunNT) H[k] = kRunEmpty;
+      __syncthreads();
+      const int small = (int)s_small;
+      const uint32_t slen = s_olen[small], slo = s_olo[small];
+      // table of 2^lg slots, lg >= log2(4 |S| bound) where it fits (load <= 1/4),
+      // else the whole table (load <= 1/2 small, <= 3/4 large)
+      int lg = 6;
+      while ((1u << lg) < 4 * slen && lg < kRunLogSlots) ++lg;
+      shift = 32 - (lg - 2);
+      bmask = (1u << (lg - 2)) - 1;
+      const uint32_t* sadj = d.adj[0];
+      switch (small) {
+#define GJ_SMALL(A)    \
+  case A:              \
+    sadj = d.adj[A];   \
+    break;
+        GJ_SMALL(1) GJ_SMALL(2) GJ_SMALL(3) GJ_SMALL(4) GJ_SMALL(5) GJ_SMALL(6) GJ_SMALL(7)
+#undef GJ_SMALL
+        default:
+          break;
+      }
+      for (uint32_t k0 = 0; k0 < slen; k0 += kRunNT) {
+        uint32_t k = k0 + tid;
+        bool in = k < slen;
+        uint32_t x = in ? sadj[slo + k] : 0u;
+#pragma unroll
+        for (int a = 0; a < kMaxBind; ++a) {
+          if (a < d.k && ((rd.old_mask >> a) & 1) && a != small && in)
+            in = mem_member(d.adj[a], d.hs[a], s_odesc[a], s_olo[a], s_olen[a], x);
+        }
+        uint64_t bal = __ballot(in);
+        uint32_t base = 0;
+        if (lane_id() == 0 && bal) base = atomicAdd(&s_nS, (uint32_t)__popcll(bal));
+        base = __shfl(base, 0, 64);
+        if (in) {
+          const uint32_t pos = base + (uint32_t)__popcll(bal & lanemask_lt());
+          if (BIG)
+            SvG[pos] = x;
+          else
+            SvL[pos] = x;
+          run_insert(H, x, shift, bmask);
+        }
+      }
+      if (BIG) __threadfence_block();  // S's values in memory are seen by the whole workgroup
+      __syncthreads();
+      nS = s_nS;
+      cached = head;
+      builds += 1;
+      belems += slen;
+    }
+    // the task's prefixes, kRunChunk at a time (none when S is empty)
+    for (uint64_t cb = cs; cb < ce && nS; cb += kRunChunk) {
+      const uint32_t cn = (uint32_t)(ce - cb < kRunChunk ? ce - cb : kRunChunk);
+      uint32_t u = 0;
+      if ((uint32_t)tid < cn) {
+        const uint64_t p = cb + tid;
+        uint32_t lb = 0, ub = 0xFFFFFFFFu;
+        if (d.above | d.below) {
+#pragma unroll
+          for (int c = 0; c < 8; ++c) {
+            if (((d.above | d.below) >> c) & 1) {
+              uint32_t o = F[(uint64_t)c * stride + p];
+              if ((d.above >> c) & 1) lb = max(lb, o + 1);
+              if ((d.below >> c) & 1) ub = min(ub, o);
+            }
+          }
+        }
+        uint32_t lo = 0, len = 0;
+        uint64_t desc = 0;
+        bool stream = false;
+        if (rd.newa >= 0) {
+          uint32_t v = F[(uint64_t)ncol * stride + p], hi;
+          row_range(nrp, npm, v, lo, hi);
+          len = hi - lo;
+          desc = nhd ? nhd[v] : 0ull;
+          stream = (uint64_t)len <= (uint64_t)rd.ratio * nS;
+          u = stream ? len : nS;
+        } else {
+          u = nS;
+        }
+        if (lb >= ub) u = 0;
+        clo[tid] = lo;
+        clen[tid] = len;
+        cdesc[tid] = desc;
+        clb[tid] = lb;
+        cub[tid] = ub;
+        cstream[tid] = stream ? 1 : 0;
+        if (SIGNED) cw[tid] = wt[p];
+      }
+      uint32_t total;
+      uint32_t ex = block_excl_scan<kRunNT, uint32_t>(u, total);
+      if ((uint32_t)tid < cn) coff[tid] = ex;
+      if (tid == 0) coff[cn] = total;
+      units += total;
+      __syncthreads();
+      // kRunU units per thread per step, their loads issued together: unit
+      // q = q0 + u * kRunNT + tid belongs to the prefix i whose range of the
+      // chunk's unit space holds it, at offset t within it
+      for (uint32_t q0 = 0; q0 < total; q0 += kRunNT * kRunU) {
+        uint32_t ci[kRunU], xv[kRunU], slo[kRunU], sln[kRunU];
+        uint64_t sds[kRunU];
+        bool act[kRunU], sm[kRunU], hit[kRunU];
+#pragma unroll
+        for (int u = 0; u < kRunU; ++u) {
+          const uint32_t q = q0 + u * kRunNT + tid;
+          act[u] = q < total;
+          const uint32_t i = act[u] ? run_owner(coff, cn, q) : 0u;
+          const uint32_t t = q - coff[i];
+          ci[u] = i;
+          sm[u] = act[u] && !cstream[i];
+          xv[u] = !act[u] ? 0u : (sm[u] ? (BIG ? SvG[t] : SvL[t]) : nadj[clo[i] + t]);
+        }
+        // streamed values: one LDS probe each
+#pragma unroll
+        for (int u = 0; u < kRunU; ++u) hit[u] = act[u] && !sm[u] && run_probe(H, xv[u], shift, bmask);
+        // S's values: membership in the prefix's new set in memory
+#pragma unroll
+        for (int u = 0; u < kRunU; ++u) {
+          const uint32_t i = ci[u];
+          slo[u] = clo[i];
+          sln[u] = clen[i];
+          sds[u] = cdesc[i];
+        }
+        if (rd.newa >= 0) {
+          member_lockstep<kRunU>(nadj, nhs, sds, slo, sln, xv, sm, hit);
+        } else {
+#pragma unroll
+          for (int u = 0; u < kRunU; ++u) hit[u] = hit[u] || sm[u];
+        }
+#pragma unroll
+        for (int u = 0; u < kRunU; ++u) {
+          const uint32_t i = ci[u];
+          if (act[u] && hit[u] && xv[u] >= clb[i] && xv[u] < cub[i]) {
+            ++hits;
+            if (SIGNED) whits += cw[i];
+          }
+        }
+      }
+      __syncthreads();  // the chunk's arrays are read before the next chunk writes them
+    }
+    __syncthreads();  // every thread has read this task's shared values before thread 0 claims the next
+  }
+  uint64_t tsum = block_sum<kRunNT>(hits);
+  if (tid == 0 && tsum) atomicAdd(acc, (unsigned long long)tsum);
+  if (tid == 0) {
+    atomicAdd(wsum + 3, (unsigned long long)units);
+    atomicAdd(wsum + 4, (unsigned long long)builds);
+    atomicAdd(wsum + 5, (unsigned long long)belems);
+  }
+  if (SIGNED) {
+    uint64_t s = block_sum<kRunNT>((uint64_t)whits);
+    if (tid == 0 && s) atomicAdd(acc + 1, (unsigned long long)s);
+  }
+}
+
+// ---------------------------------------------------------------- host
+bool run_desc(const StageDesc& d, RunDesc& rd) {
+  if (d.ntri || d.k < 1) return false;
+  memset(&rd, 0, sizeof(rd));
+  rd.newa = -1;
+  int r = 0;
+  for (int a = 0; a < d.k; ++a) {
+    if (d.col[a] == d.j - 1) {
+      if (rd.newa >= 0) return false;  // two new atoms: not handled here
+      rd.newa = a;
+    } else {
+      rd.old_mask |= 1u << a;
+      ++rd.nold;
+      r = std::max(r, d.col[a] + 1);
+    }
+  }
+  if (rd.nold == 0) return false;
+  rd.r = r;
+  return true;
+}
+
+uint64_t run_count(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const uint64_t* off, uint32_t* minc,
+                   const StageDesc& d, RunDesc rd, const int8_t* wt, unsigned long long* acc, uint64_t* off2,
+                   KernelTimer& timer) {
+  rd.ratio = c->run_ratio;
+  rd.min_work = c->run_min_work;
+  rd.task_work = c->run_task_work;
+  uint32_t* head = (uint32_t*)ws_get(c, "run_head", n * sizeof(uint32_t) + 16);
+  uint64_t* hoff = (uint64_t*)ws_get(c, "run_hoff", (n + 1) * sizeof(uint64_t));
+  uint32_t* rs = (uint32_t*)ws_get(c, "run_rs", (n + 1) * sizeof(uint32_t));
+  uint32_t* tcnt = (uint32_t*)ws_get(c, "run_tcnt", n * sizeof(uint32_t) + 16);
+  uint32_t* tcnt_big = (uint32_t*)ws_get(c, "run_tcnt_big", n * sizeof(uint32_t) + 16);
+  uint64_t* toff = (uint64_t*)ws_get(c, "run_toff", (n + 1) * sizeof(uint64_t));
+  uint64_t* toff_big = (uint64_t*)ws_get(c, "run_toff_big", (n + 1) * sizeof(uint64_t));
+  uint8_t* staged = (uint8_t*)ws_get(c, "run_staged", n + 16);
+  // two task counters, then 3 + 3 sums (all cleared by k_run_starts):
+  // candidates by plan outcome, and units, builds and built values of the
+  // counting kernels
+  unsigned int* counter = (unsigned int*)ws_get(c, "run_counter", 64);
+  unsigned long long* wsum = (unsigned long long*)(counter + 2);
+  unsigned gr = grid_for(n, kBlock, 1u << 16);
+  k_run_heads<<<gr, kBlock, 0, c->stream>>>(F, stride, n, rd.r, head);
+  scan_u32_to_u64(c, head, hoff, n);
+  k_run_starts<<<gr, kBlock, 0, c->stream>>>(head, hoff, n, rs, counter);
+  k_run_plan<<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, head, hoff, rs, d, rd, tcnt, tcnt_big, staged, wsum);
+  scan_u32_to_u64(c, tcnt, toff, n);
+  scan_u32_to_u64(c, tcnt_big, toff_big, n);
+  k_run_direct<<<gr, kBlock, 0, c->stream>>>(head, hoff, staged, n, minc);
+  scan_u32_to_u64(c, minc, off2, n);
+  GJ_HIP(hipGetLastError());
+  uint64_t h[3];
+  read_u64s(c, {off2 + n, toff + n, toff_big + n}, h);
+  if (h[1]) {
+    unsigned g = (unsigned)std::min<uint64_t>(h[1], (uint64_t)c->num_cus * 2);
+    timer.start();
+    if (wt)
+      k_run_count<true, false><<<g, RunShape<false>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff, d, rd, wt,
+                                                                         nullptr, counter, acc, wsum);
+    else
+      k_run_count<false, false><<<g, RunShape<false>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff, d, rd,
+                                                                          wt, nullptr, counter, acc, wsum);
+    timer.stop();
+    GJ_HIP(hipGetLastError());
+  }
+  if (h[2]) {
+    unsigned g = (unsigned)std::min<uint64_t>(h[2], (uint64_t)c->num_cus);
+    uint32_t* sv = (uint32_t*)ws_get(c, "run_sv", (uint64_t)g * kRunCapBig * sizeof(uint32_t));
+    timer.start();
+    if (wt)
+      k_run_count<true, true><<<g, RunShape<true>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff_big, d, rd,
+                                                                       wt, sv, counter + 1, acc, wsum);
+    else
+      k_run_count<false, true><<<g, RunShape<true>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff_big, d, rd,
+                                                                        wt, sv, counter + 1, acc, wsum);
+    timer.stop();
+    GJ_HIP(hipGetLastError());
+  }
+  uint64_t w[6];
+  read_bytes(c, w, wsum, sizeof(w));
+  c->run_w_staged += w[0];
+  c->run_w_large += w[1];
+  c->run_w_light += w[2];
+  c->run_units += w[3];
+  c->run_builds += w[4];
+  c->run_build_elems += w[5];
+  c->run_tasks += h[1] + h[2];
+  c->run_tasks_big += h[2];
+  return h[0];
+}
+
+}  // namespace gj
