@@ -166,9 +166,9 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   compaction leaves m / 2 + 2^22 entries of it, and
  *                   reallocates the slot when less than half of that is
  *                   left)
- *   "run_stage"     1 (default): the last stage of a count on the
- *                   depth-first path (gj_run, depth-first delta queries,
- *                   the server's heavy lanes), when its binary atoms split
+ *   "run_stage"     1 (default): the last stage of a static count on the
+ *                   depth-first path (gj_run, the server's heavy lanes,
+ *                   gj_run_batch's heavy requests), when its binary atoms split
  *                   into at least one reading an earlier column and at most
  *                   one reading the last bound column, is counted grouped
  *                   by prefix runs: consecutive prefixes that agree on the
@@ -185,13 +185,21 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   set's values, else the shared values are looked up in
  *                   it (0..64, default 2)
  *   "run_min_work"  run_stage: least count-minimised candidates of a run
- *                   for it to be staged (default 256, >= 0); a staged run
- *                   also needs at least twice its smallest shared set
+ *                   for it to be staged (default 256, >= 0)
+ *   "run_reuse"     run_stage: a staged run also has at least this many
+ *                   times as many candidates as its smallest shared set
+ *                   holds values (default 4, 1..1024)
  *   "run_task_work" run_stage: a run's prefixes are cut into tasks of about
  *                   this many candidates plus 8 per value the build reads
  *                   (default 2^15, >= 1)
  *   "run_stage_min" run_stage: least count-minimised candidates of a stage
- *                   for it to take the run kernels (default 2^16, >= 0)
+ *                   for it to take the run kernels (default 2^22, >= 0;
+ *                   a smaller stage takes the per-candidate kernel, which
+ *                   finishes it in about the time planning the runs takes)
+ *   "run_min_tasks" run_stage: a stage whose staged runs make fewer tasks
+ *                   than this (default 256, >= 0) is left whole to the
+ *                   per-candidate kernel (a workgroup works through a task
+ *                   alone, so a few tasks cannot occupy the device)
  * Returns GJ_EINVAL for an unknown key or out-of-range value. */
 gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
 
@@ -203,6 +211,8 @@ gj_status gj_ctx_set_option(gj_ctx* ctx, const char* key, int64_t value);
  * "owner_tasks" (its tasks) and "owner_split_units" (units cut into more
  * than one task), and of the run kernels (see "run_stage") on this context
  * "run_tasks", "run_tasks_big" (of them, tasks of the large-set shape),
+ * "run_declined" (stages planned by runs but left to the per-candidate
+ * kernel),
  * "run_w_staged", "run_w_large", "run_w_light" (count-minimised candidates
  * of runs staged, with a shared set above the tables, with too little
  * work), "run_units" (values tested), "run_builds" and "run_build_elems"

@@ -270,6 +270,12 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "run_task_work") {
       GJ_CHECK(value >= 1 && value <= (1ll << 40), GJ_EINVAL, "run_task_work out of range");
       c->run_task_work = (uint64_t)value;
+    } else if (k == "run_reuse") {
+      GJ_CHECK(value >= 1 && value <= 1024, GJ_EINVAL, "run_reuse out of range");
+      c->run_reuse = (uint32_t)value;
+    } else if (k == "run_min_tasks") {
+      GJ_CHECK(value >= 0, GJ_EINVAL, "run_min_tasks must be >= 0");
+      c->run_min_tasks = (uint64_t)value;
     } else if (k == "run_stage_min") {
       GJ_CHECK(value >= 0, GJ_EINVAL, "run_stage_min must be >= 0");
       c->run_stage_min = (uint64_t)value;
@@ -316,12 +322,18 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "run_stage_min") *value = (int64_t)c->run_stage_min;
     else if (k == "run_tasks") *value = (int64_t)c->run_tasks;
     else if (k == "run_tasks_big") *value = (int64_t)c->run_tasks_big;
-    else if (k == "run_w_staged") *value = (int64_t)c->run_w_staged;
-    else if (k == "run_w_large") *value = (int64_t)c->run_w_large;
-    else if (k == "run_w_light") *value = (int64_t)c->run_w_light;
-    else if (k == "run_units") *value = (int64_t)c->run_units;
-    else if (k == "run_builds") *value = (int64_t)c->run_builds;
-    else if (k == "run_build_elems") *value = (int64_t)c->run_build_elems;
+    else if (k == "run_declined") *value = (int64_t)c->run_declined;
+    else if (k == "run_min_tasks") *value = (int64_t)c->run_min_tasks;
+    else if (k == "run_reuse") *value = c->run_reuse;
+    else if (k == "run_w_staged" || k == "run_w_large" || k == "run_w_light" || k == "run_units" ||
+             k == "run_builds" || k == "run_build_elems") {
+      static const char* names[] = {"run_w_staged", "run_w_large", "run_w_light", "run_units", "run_builds",
+                                    "run_build_elems"};
+      uint64_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+      if (c->run_stats) gj::read_bytes(c, h, c->run_stats, sizeof(h));
+      for (int i = 0; i < 6; ++i)
+        if (k == names[i]) *value = (int64_t)h[i];
+    }
     else if (k == "owner_tasks") *value = (int64_t)c->owner_tasks;
     else if (k == "owner_split_units") *value = (int64_t)c->owner_split_units;
     else throw Error{GJ_EINVAL, "unknown option " + k};
@@ -766,6 +778,8 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->run_min_work = src->run_min_work;
   dst->run_task_work = src->run_task_work;
   dst->run_stage_min = src->run_stage_min;
+  dst->run_min_tasks = src->run_min_tasks;
+  dst->run_reuse = src->run_reuse;
 }
 
 gj_status settle(gj_ctx* c, const gj_graph* g) {

@@ -313,17 +313,23 @@ void Runner::stage(int j, uint64_t n) {
   }
   bool final = j + 1 == P.m;
   RunDesc rd;
-  if (final && !collect && c->run_stage && c->strategy != 1 && !c->arena.on && W >= c->run_stage_min && run_desc(d, rd)) {
+  // Static counts only: the seeds of a delta query are one batch of changes,
+  // whose prefixes rarely share a source, so its runs hold a few prefixes
+  // each and staging them was measured slower than the per-candidate kernel.
+  if (final && !collect && !weighted && c->run_stage && c->strategy != 1 && !c->arena.on &&
+      W >= c->run_stage_min && run_desc(d, rd)) {
     // prefix runs sharing their old sets take the run kernels; the rest of
     // the candidates the per-candidate kernel
     uint64_t* off2 = (uint64_t*)ws_get(c, "run_off2", (l.cap + 1) * sizeof(uint64_t));
-    uint64_t W2 = run_count(c, l.F, l.cap, n, l.off, l.minc, d, rd, weighted ? l.Fw : nullptr, acc, off2, timer);
-    if (W2) {
-      timer.start();
-      launch_propose(c, weighted ? 2 : 1, l.F, l.cap, n, off2, l.mini, d, 0, W2, nullptr, nullptr, l.Fw, acc);
-      timer.stop();
+    uint64_t W2 = 0;
+    if (run_count(c, l.F, l.cap, n, l.off, l.minc, d, rd, weighted ? l.Fw : nullptr, acc, off2, W2, timer)) {
+      if (W2) {
+        timer.start();
+        launch_propose(c, weighted ? 2 : 1, l.F, l.cap, n, off2, l.mini, d, 0, W2, nullptr, nullptr, l.Fw, acc);
+        timer.stop();
+      }
+      return;
     }
-    return;
   }
   if (final && !collect) {
     timer.start();

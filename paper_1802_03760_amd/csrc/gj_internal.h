@@ -222,16 +222,17 @@ struct gj_ctx {
   uint32_t run_ratio = 2;          // stream a new set through S's table up to this many times |S|
   uint64_t run_min_work = 256;     // least count-minimised candidates of a staged run
   uint64_t run_task_work = 1ull << 15;  // candidates per task of a staged run beyond its build
-  uint64_t run_stage_min = 1ull << 16;  // least candidates of a stage taken by the run kernels
+  uint64_t run_stage_min = 1ull << 22;  // least candidates of a stage taken by the run kernels
+  uint32_t run_reuse = 4;          // staged runs: candidates >= this x the shared set bound
+  uint64_t run_min_tasks = 256;    // fewer staged tasks in a stage: the per-candidate kernel takes it
   uint64_t run_tasks = 0;          // tasks of the run kernels on this context
   uint64_t run_tasks_big = 0;      // of those, tasks of the large-set shape
-  // count-minimised candidates of the stages offered to the run kernels: in
-  // staged runs, in runs whose shared set exceeds the table, in runs with too
-  // little work to repay a build
-  uint64_t run_w_staged = 0, run_w_large = 0, run_w_light = 0;
-  // work of the counting kernel: units (values tested), builds of a shared
-  // set, and the values those builds streamed
-  uint64_t run_units = 0, run_builds = 0, run_build_elems = 0;
+  uint64_t run_declined = 0;       // stages planned by runs but left to the per-candidate kernel
+  // device sums over the context's life (run.hip): count-minimised
+  // candidates of planned runs that were staged, whose shared set exceeds
+  // the tables, with too little work to repay a build; then the counting
+  // kernels' units (values tested), builds, and the values builds streamed
+  unsigned long long* run_stats = nullptr;
   uint64_t owner_tasks = 0;        // tasks of the last owner-grouped launch
   uint64_t owner_split_units = 0;  // owner units of that launch cut into more than one task
 };

@@ -68,7 +68,7 @@ __global__ void k_run_heads(const uint32_t* __restrict__ F, uint64_t stride, uin
 __global__ void k_run_starts(const uint32_t* __restrict__ head, const uint64_t* __restrict__ hoff, uint64_t n,
                              uint32_t* __restrict__ rs, unsigned int* __restrict__ counter) {
   uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
-  if (blockIdx.x == 0 && threadIdx.x < 16) counter[threadIdx.x] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 2) counter[threadIdx.x] = 0;
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
     if (head[p]) rs[hoff[p]] = (uint32_t)p;
     if (p + 1 == n) rs[hoff[n]] = (uint32_t)n;
@@ -92,6 +92,7 @@ __global__ void k_run_plan(const uint32_t* __restrict__ F, uint64_t stride, uint
                            RunDesc rd, uint32_t* __restrict__ tcnt, uint32_t* __restrict__ tcnt_big,
                            uint8_t* __restrict__ staged, unsigned long long* __restrict__ wsum) {
   uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t ws[3] = {0, 0, 0};
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
     uint32_t t = 0;
     bool big = false;
@@ -108,7 +109,7 @@ __global__ void k_run_plan(const uint32_t* __restrict__ F, uint64_t stride, uint
         }
       }
       uint64_t W = off[e] - off[p];
-      bool st = B <= kRunCapBig && W >= rd.min_work && W >= 2ull * B;
+      bool st = B <= kRunCapBig && W >= rd.min_work && W >= (uint64_t)rd.reuse * B;
       big = B > kRunCap;
       if (st) {
         uint64_t per = rd.task_work + 8ull * B * (uint64_t)rd.nold;
@@ -118,20 +119,26 @@ __global__ void k_run_plan(const uint32_t* __restrict__ F, uint64_t stride, uint
       }
       staged[rid] = st ? 1 : 0;
       // candidates by outcome: staged, shared set too large, too little work
-      atomicAdd(wsum + (st ? 0 : (B > kRunCapBig ? 1 : 2)), (unsigned long long)W);
+      ws[st ? 0 : (B > kRunCapBig ? 1 : 2)] += W;
     }
     tcnt[p] = big ? 0 : t;
     tcnt_big[p] = big ? t : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    uint64_t b = block_sum<kBlock>(ws[i]);
+    if (threadIdx.x == 0 && b) atomicAdd(wsum + i, (unsigned long long)b);
   }
 }
 
 // The per-candidate kernel's counts: zero for prefixes of staged runs.
 __global__ void k_run_direct(const uint32_t* __restrict__ head, const uint64_t* __restrict__ hoff,
-                             const uint8_t* __restrict__ staged, uint64_t n, uint32_t* __restrict__ minc) {
+                             const uint8_t* __restrict__ staged, uint64_t n, const uint32_t* __restrict__ minc,
+                             uint32_t* __restrict__ minc2) {
   uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
     uint64_t rid = hoff[p] + head[p] - 1;
-    if (staged[rid]) minc[p] = 0;
+    minc2[p] = staged[rid] ? 0u : minc[p];
   }
 }
 
@@ -544,25 +551,31 @@ bool run_desc(const StageDesc& d, RunDesc& rd) {
   return true;
 }
 
-uint64_t run_count(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const uint64_t* off, uint32_t* minc,
-                   const StageDesc& d, RunDesc rd, const int8_t* wt, unsigned long long* acc, uint64_t* off2,
-                   KernelTimer& timer) {
+bool run_count(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const uint64_t* off, const uint32_t* minc,
+               const StageDesc& d, RunDesc rd, const int8_t* wt, unsigned long long* acc, uint64_t* off2,
+               uint64_t& W2, KernelTimer& timer) {
   rd.ratio = c->run_ratio;
   rd.min_work = c->run_min_work;
   rd.task_work = c->run_task_work;
+  rd.reuse = c->run_reuse;
   uint32_t* head = (uint32_t*)ws_get(c, "run_head", n * sizeof(uint32_t) + 16);
   uint64_t* hoff = (uint64_t*)ws_get(c, "run_hoff", (n + 1) * sizeof(uint64_t));
   uint32_t* rs = (uint32_t*)ws_get(c, "run_rs", (n + 1) * sizeof(uint32_t));
   uint32_t* tcnt = (uint32_t*)ws_get(c, "run_tcnt", n * sizeof(uint32_t) + 16);
   uint32_t* tcnt_big = (uint32_t*)ws_get(c, "run_tcnt_big", n * sizeof(uint32_t) + 16);
+  uint32_t* minc2 = (uint32_t*)ws_get(c, "run_minc2", n * sizeof(uint32_t) + 16);
   uint64_t* toff = (uint64_t*)ws_get(c, "run_toff", (n + 1) * sizeof(uint64_t));
   uint64_t* toff_big = (uint64_t*)ws_get(c, "run_toff_big", (n + 1) * sizeof(uint64_t));
   uint8_t* staged = (uint8_t*)ws_get(c, "run_staged", n + 16);
-  // two task counters, then 3 + 3 sums (all cleared by k_run_starts):
-  // candidates by plan outcome, and units, builds and built values of the
-  // counting kernels
-  unsigned int* counter = (unsigned int*)ws_get(c, "run_counter", 64);
-  unsigned long long* wsum = (unsigned long long*)(counter + 2);
+  // two task counters (cleared by k_run_starts)
+  unsigned int* counter = (unsigned int*)ws_get(c, "run_counter", 16);
+  // context-lifetime sums: candidates by plan outcome, and units, builds and
+  // built values of the counting kernels (read by gj_ctx_get_option)
+  if (!c->run_stats) {
+    c->run_stats = (unsigned long long*)ws_get(c, "run_stats", 8 * sizeof(unsigned long long));
+    GJ_HIP(hipMemsetAsync(c->run_stats, 0, 8 * sizeof(unsigned long long), c->stream));
+  }
+  unsigned long long* wsum = c->run_stats;
   unsigned gr = grid_for(n, kBlock, 1u << 16);
   k_run_heads<<<gr, kBlock, 0, c->stream>>>(F, stride, n, rd.r, head);
   scan_u32_to_u64(c, head, hoff, n);
@@ -570,11 +583,19 @@ uint64_t run_count(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, co
   k_run_plan<<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, head, hoff, rs, d, rd, tcnt, tcnt_big, staged, wsum);
   scan_u32_to_u64(c, tcnt, toff, n);
   scan_u32_to_u64(c, tcnt_big, toff_big, n);
-  k_run_direct<<<gr, kBlock, 0, c->stream>>>(head, hoff, staged, n, minc);
-  scan_u32_to_u64(c, minc, off2, n);
+  k_run_direct<<<gr, kBlock, 0, c->stream>>>(head, hoff, staged, n, minc, minc2);
+  scan_u32_to_u64(c, minc2, off2, n);
   GJ_HIP(hipGetLastError());
   uint64_t h[3];
   read_u64s(c, {off2 + n, toff + n, toff_big + n}, h);
+  // too few tasks to occupy the device: a workgroup works through a task
+  // alone, so the per-candidate kernel, which spreads every candidate over
+  // the whole device, is faster for the stage
+  if (h[1] + h[2] < (uint64_t)c->run_min_tasks) {
+    c->run_declined += 1;
+    return false;
+  }
+  W2 = h[0];
   if (h[1]) {
     unsigned g = (unsigned)std::min<uint64_t>(h[1], (uint64_t)c->num_cus * 2);
     timer.start();
@@ -600,17 +621,9 @@ uint64_t run_count(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, co
     timer.stop();
     GJ_HIP(hipGetLastError());
   }
-  uint64_t w[6];
-  read_bytes(c, w, wsum, sizeof(w));
-  c->run_w_staged += w[0];
-  c->run_w_large += w[1];
-  c->run_w_light += w[2];
-  c->run_units += w[3];
-  c->run_builds += w[4];
-  c->run_build_elems += w[5];
   c->run_tasks += h[1] + h[2];
   c->run_tasks_big += h[2];
-  return h[0];
+  return true;
 }
 
 }  // namespace gj

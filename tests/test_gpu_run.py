@@ -23,6 +23,7 @@ def gj():
 def run_ctx(gj, task_work=1 << 15, ratio=8, min_work=0, hash_index=1):
     c = gj.Context(0)
     c.set_option("run_stage_min", 0)  # every last stage that can, however small
+    c.set_option("run_min_tasks", 0)  # and however few tasks it makes
     c.set_option("run_min_work", min_work)
     c.set_option("run_task_work", task_work)
     c.set_option("run_ratio", ratio)
@@ -103,6 +104,7 @@ def test_seed_slices_rmat(gj, hash_index):
     c = gj.Context(0)
     c.set_option("hash_index", hash_index)
     c.set_option("hash_build_work", 0)
+    c.set_option("run_min_tasks", 0)
     src, dst = synth.rmat_draws(14, seed=13)
     n = 1 << 14
     G, O = gj.Graph(c, src, dst, n), oracle.Graph(n, src, dst)
@@ -174,8 +176,10 @@ def test_sets_beyond_both_tables(gj):
 
 @pytest.mark.parametrize("task_work", [1, 1 << 15])
 def test_delta_depth_first(gj, task_work):
-    """Signed counts: delta queries on the depth-first path (weights carried
-    by the prefixes) equal the oracle's Delta-GJ batch by batch."""
+    """Delta queries on the depth-first path (signed weights carried by the
+    prefixes) keep the per-candidate kernel beside static counts that take
+    the run kernels on the same context: count deltas equal the oracle's
+    Delta-GJ batch by batch."""
     c = run_ctx(gj, task_work=task_work)
     c.set_option("delta_fused", 0)
     scale = 10
@@ -184,15 +188,17 @@ def test_delta_depth_first(gj, task_work):
     G, O = gj.Graph(c, src, dst, n), oracle.Graph(n, src, dst)
     qs = [Q.TRIANGLE, Q.CLIQUE4, Q.DIAMOND, Q.CYCLE4, Q.HOUSE]
     hs = [gj.Query(c, *q) for q in qs]
-    before = c.get_option("run_tasks")
     for k, bs, bd, bg in synth.update_stream(scale, 15, 16, 5, 1, 3000):
+        before = c.get_option("run_tasks")
         res = gj.apply_updates(c, G, bs, bd, bg, hs, rows=False)
+        assert c.get_option("run_tasks") == before
         for q, r in zip(qs, res):
             ref = oracle.delta(O.copy(), bs, bd, bg, q, rows=False, threads=8)
             assert r["count_delta"] == ref["count_delta"], (k, q, r["count_delta"], ref["count_delta"])
             assert r["stats"]["prefixes"] == ref["prefixes"] and r["stats"]["extensions"] == ref["extensions"]
         oracle.delta(O, bs, bd, bg)
-    assert c.get_option("run_tasks") > before
+        E = G.info()["edges"]
+        check(gj, c, G, O, Q.CLIQUE4, 0, E // 2)
 
 
 def test_off_equals_on(gj):
@@ -210,3 +216,17 @@ def test_off_equals_on(gj):
         a = gj.count(on, Gon, gj.Query(on, *q), 1, E)
         b = gj.count(off, Goff, gj.Query(off, *q), 1, E)
         assert (a["matches"], a["prefixes"], a["extensions"]) == (b["matches"], b["prefixes"], b["extensions"]), name
+
+
+def test_declined_stages(gj):
+    """A stage whose staged runs make fewer tasks than run_min_tasks is left
+    whole to the per-candidate kernel: counts and counters still equal the
+    oracle's, and the context counts the declined stages."""
+    c = run_ctx(gj)
+    c.set_option("run_min_tasks", 1 << 40)
+    src, dst = synth.rmat_draws(11, seed=19)
+    n = 1 << 11
+    G, O = gj.Graph(c, src, dst, n), oracle.Graph(n, src, dst)
+    for q in (Q.TRIANGLE, Q.CLIQUE4, Q.DIAMOND):
+        check(gj, c, G, O, q)
+    assert c.get_option("run_declined") > 0 and c.get_option("run_tasks") == 0
