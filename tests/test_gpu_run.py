@@ -100,11 +100,13 @@ def test_inequalities_and_symmetric(gj, name):
 @pytest.mark.parametrize("hash_index", [0, 1])
 def test_seed_slices_rmat(gj, hash_index):
     """Seed slices of an R-MAT-14 graph, hub rows included, at the default
-    thresholds (the run kernels take the large stages only)."""
+    run sizes and split (stage and task-count thresholds lowered so that the
+    run kernels take part at this scale)."""
     c = gj.Context(0)
     c.set_option("hash_index", hash_index)
     c.set_option("hash_build_work", 0)
     c.set_option("run_min_tasks", 0)
+    c.set_option("run_stage_min", 0)
     src, dst = synth.rmat_draws(14, seed=13)
     n = 1 << 14
     G, O = gj.Graph(c, src, dst, n), oracle.Graph(n, src, dst)
