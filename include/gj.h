@@ -98,6 +98,10 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   every query that asks for counts only as one fused
  *                   pipeline (as gj_run_batch, with signed seeds); 0 runs
  *                   each dQ_i on the depth-first path
+ *   "delta_lane_min"  a server's updates: batches with at least this many
+ *                   distinct changes (default 1024, >= 0) run their
+ *                   count-only dQ_i on the server's delta lanes (see
+ *                   gj_server_create)
  *   "delta_owner_min"  gj_apply_updates: batches with at least this many
  *                   distinct changes (default 2^17, >= 0) run the count-only
  *                   delta queries of three-attribute queries whose every
@@ -488,7 +492,11 @@ gj_status gj_autotune(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_qu
  * concurrently on the depth-first path, each lane taking the oldest heavy
  * request no other lane is running.  Requests whose version an update waits
  * for go first; with "update_priority" (default 1) no new heavy chunk starts
- * while an update batch is on the device (light iterations go on).  With iteration_work
+ * while an update batch is on the device (light iterations go on).  Updates
+ * run on ctx; the count-only delta queries of a batch with at least ctx's
+ * "delta_lane_min" distinct changes run depth-first side by side on ctx and
+ * "update_lanes" more contexts (default 2, created at the first request),
+ * one host thread each; smaller batches take ctx alone.  With iteration_work
  * 0 requests run whole, in arrival order, in the fused pipeline.  Results
  * equal gj_run / gj_apply_updates issued alone in submission order.
  * gj_server_create returns GJ_EDEVICE / GJ_ENOMEM if the light context or
@@ -523,8 +531,9 @@ gj_status gj_server_create(gj_ctx* ctx, gj_graph* g, uint32_t max_batch, uint64_
                            gj_server** out);
 /* Server options: "iteration_work" (>= 0), "heavy_work" (>= 0),
  * "update_priority" (0 or 1), "max_batch" (1..65536) at any time;
- * "versions" (2..8) and "heavy_lanes" (1..4) before the first request, else
- * GJ_EBUSY.  GJ_EINVAL for an unknown key or a value out of range. */
+ * "versions" (2..8), "heavy_lanes" (1..4) and "update_lanes" (0..4) before
+ * the first request, else GJ_EBUSY.  GJ_EINVAL for an unknown key or a value
+ * out of range. */
 gj_status gj_server_set_option(gj_server* s, const char* key, int64_t value);
 /* Queues a count of query q over seed edges [seed_lo, seed_hi) (as gj_run);
  * *ticket identifies the result.  The query must outlive the request. */

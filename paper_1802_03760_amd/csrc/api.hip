@@ -121,6 +121,16 @@ double KernelTimer::total_ms() {
   return t;
 }
 
+void read_u32s(gj_ctx* c, std::initializer_list<const uint32_t*> ptrs, uint32_t* host) {
+  GJ_CHECK(ptrs.size() * sizeof(uint32_t) <= 4096, GJ_EINVAL, "too many values to read");
+  uint32_t* st = (uint32_t*)c->pinned;
+  size_t i = 0;
+  for (const uint32_t* p : ptrs)
+    GJ_HIP(hipMemcpyAsync(st + i++, p, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  GJ_HIP(hipStreamSynchronize(c->stream));
+  memcpy(host, st, ptrs.size() * sizeof(uint32_t));
+}
+
 uint64_t read_u64(gj_ctx* c, const void* dptr) {
   uint64_t v = 0;
   read_bytes(c, &v, dptr, sizeof(v));
@@ -216,6 +226,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "delta_owner_min") {
       GJ_CHECK(value >= 0, GJ_EINVAL, "delta_owner_min must be >= 0");
       c->delta_owner_min = (uint64_t)value;
+    } else if (k == "delta_lane_min") {
+      GJ_CHECK(value >= 0, GJ_EINVAL, "delta_lane_min must be >= 0");
+      c->delta_lane_min = (uint64_t)value;
     } else if (k == "owner_task_min") {
       GJ_CHECK(value >= 1 && value <= (1ll << 40), GJ_EINVAL, "owner_task_min out of range");
       c->owner_task_min = (uint64_t)value;
@@ -302,6 +315,7 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "batch_fallbacks") *value = (int64_t)c->batch_fallbacks;
     else if (k == "delta_fused") *value = c->delta_fused;
     else if (k == "delta_owner_min") *value = (int64_t)c->delta_owner_min;
+    else if (k == "delta_lane_min") *value = (int64_t)c->delta_lane_min;
     else if (k == "factorise") *value = c->factorise;
     else if (k == "propose_u") *value = c->propose_u;
     else if (k == "batch_heavy") *value = (int64_t)c->batch_heavy;
@@ -728,11 +742,12 @@ gj_status count_on_versions(gj_ctx* c, const gj_graph* g, const Version* const* 
 }
 
 gj_status update_into(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst, const int8_t* sign,
-                      uint64_t b, const gj_query* const* qs, uint32_t nq, int64_t* count_delta, int target) {
+                      uint64_t b, const gj_query* const* qs, uint32_t nq, int64_t* count_delta, int target,
+                      const std::vector<gj_ctx*>* lanes) {
   return guarded(c, [&] {
     bool overflow = false;
     apply_updates(c, g, src, dst, sign, b, 0, qs, nq, count_delta, nullptr, nullptr, nullptr, nullptr, nullptr,
-                  overflow, target);
+                  overflow, target, lanes);
   });
 }
 
@@ -763,6 +778,7 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->batch_cap = src->batch_cap;
   dst->delta_fused = src->delta_fused;
   dst->delta_owner_min = src->delta_owner_min;
+  dst->delta_lane_min = src->delta_lane_min;
   dst->owner_task_min = src->owner_task_min;
   dst->hash_index = src->hash_index;
   dst->hash_min_degree = src->hash_min_degree;

@@ -15,6 +15,7 @@
 #include "gj_internal.h"
 #include "lsm.h"
 #include "owner.h"
+#include <thread>
 #include "prim.h"
 
 namespace gj {
@@ -27,7 +28,12 @@ __global__ void k_batch_keys(const uint32_t* __restrict__ src, const uint32_t* _
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < b; i += gs) {
     uint32_t s = src[i], d = dst[i];
     int8_t g = sign[i];
-    if (s >= n || d >= n || (g != 1 && g != -1)) atomicOr(bad, 1u);
+    if (s >= n || d >= n || (g != 1 && g != -1)) {
+      // the batch is rejected once the flag is read; until then the row
+      // stands in as the self-loop (0, 0), which no later kernel looks up
+      atomicOr(bad, 1u);
+      s = d = 0;
+    }
     keys[i] = ((uint64_t)s << 32) | d;
     vals[i] = g > 0 ? 1u : 0u;
   }
@@ -323,10 +329,23 @@ static void add_stats(gj_stats& a, const gj_stats& b) {
   a.kernel_launches += b.kernel_launches;
 }
 
+// One dQ_i of a count-only query on the depth-first path (signed sum of its
+// outputs and its counters), on context c.
+static void delta_count_one(gj_ctx* c, const gj_query* q, int i, const Version& ov, const Version& nv,
+                            const uint32_t* es, const uint32_t* ed, const int8_t* eg, uint64_t k, int64_t& ws,
+                            uint64_t& matches, gj_stats& st) {
+  PlanH P = make_plan(q, delta_order(q, i), i);
+  Views V{&ov, &nv, i};
+  Runner R(c, P, V, true, false, std::max<uint64_t>(1, std::min<uint64_t>(c->seed_chunk, k)));
+  R.seed(es, ed, eg, k);
+  R.finish(matches, ws);
+  st = R.st;
+}
+
 void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst, const int8_t* sign, uint64_t b,
                    int on_device, const gj_query* const* qs, uint32_t nq, int64_t* count_delta,
                    uint32_t* const* out_rows, int8_t* const* out_signs, const uint64_t* cap, uint64_t* n_delta,
-                   gj_stats* stats, bool& overflow, int target) {
+                   gj_stats* stats, bool& overflow, int target, const std::vector<gj_ctx*>* lanes) {
   overflow = false;
   uint32_t n = g->n;
   int bits = bits_for(n);
@@ -361,15 +380,14 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
   uint64_t* keys2 = (uint64_t*)ws_get(c, "ub_keys2", (b + 1) * sizeof(uint64_t));
   uint32_t* vals = (uint32_t*)ws_get(c, "ub_vals", (b + 1) * sizeof(uint32_t));
   uint32_t* vals2 = (uint32_t*)ws_get(c, "ub_vals2", (b + 1) * sizeof(uint32_t));
+  // counters of the classification (no-op inserts, no-op deletes,
+  // conflicts), then the flag of an invalid row; read with the number of
+  // changes in one synchronisation
   unsigned long long* cnt = (unsigned long long*)ws_get(c, "ub_cnt", 4 * sizeof(unsigned long long));
-  uint32_t* bad = (uint32_t*)ws_get(c, "ub_bad", sizeof(uint32_t));
+  uint32_t* bad = (uint32_t*)(cnt + 3);
   GJ_HIP(hipMemsetAsync(cnt, 0, 4 * sizeof(unsigned long long), c->stream));
-  GJ_HIP(hipMemsetAsync(bad, 0, sizeof(uint32_t), c->stream));
   unsigned gb = grid_for(b, kBlock, 1u << 16);
   if (b) k_batch_keys<<<gb, kBlock, 0, c->stream>>>(ds, dd, dg, b, n, keys, vals, bad);
-  uint32_t hbad = 0;
-  read_bytes(c, &hbad, bad, sizeof(hbad));
-  GJ_CHECK(!hbad, GJ_EINVAL, "update batch: vertex id >= num_vertices or sign not +-1");
   sort_kv_u64(c, keys, vals, keys2, vals2, b, bits, bits);
   uint32_t* flags = (uint32_t*)ws_get(c, "ub_flags", (b + 1) * sizeof(uint32_t));
   int8_t* dsign = (int8_t*)ws_get(c, "ub_dsign", b + 1);
@@ -385,10 +403,12 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
     k_batch_classify<<<gb, kBlock, 0, c->stream>>>(keys, vals, b, cur_view.d[0].rp, cur_view.d[0].col,
                                                    cur_view.pmap[0], flags, dsign, cnt);
   scan_u32_to_u64(c, flags, off, b);
-  unsigned long long hc[3];
-  read_bytes(c, hc, cnt, sizeof(hc));
+  uint64_t hc[5];
+  read_u64s(c, {(const uint64_t*)cnt, (const uint64_t*)cnt + 1, (const uint64_t*)cnt + 2, (const uint64_t*)cnt + 3,
+                off + b}, hc);
+  GJ_CHECK(!hc[3], GJ_EINVAL, "update batch: vertex id >= num_vertices or sign not +-1");
   GJ_CHECK(hc[2] == 0, GJ_EINVAL, "update batch inserts and deletes the same edge");
-  uint64_t k = read_u64(c, off + b);
+  uint64_t k = hc[4];
   // dE sorted by (src, dst) and by (dst, src)
   uint32_t* es = (uint32_t*)ws_get(c, "de_src", (k + 1) * sizeof(uint32_t));
   uint32_t* ed = (uint32_t*)ws_get(c, "de_dst", (k + 1) * sizeof(uint32_t));
@@ -447,10 +467,14 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
       }
       update_dir(c, n, bv.d[d], bv.m, rw, d ? rd : es, d ? rs : ed, d ? rg : eg, k, nv.d[d], d ? "r" : "f", mx + d);
     }
-    uint32_t newm = 0;
-    read_bytes(c, &newm, nv.d[0].rp + n, sizeof(newm));
-    nv.m = newm;
-    version_finish(c, nv, n, true);  // row pointers and largest degrees come from the update
+    // the new edge count and the largest degrees (written by the update), in
+    // one synchronisation
+    uint32_t h3[3];
+    read_u32s(c, {nv.d[0].rp + n, mx, mx + 1}, h3);
+    nv.m = h3[0];
+    ++nv.gen;  // written (as version_finish marks a slot)
+    nv.max_deg[0] = h3[1];
+    nv.max_deg[1] = h3[2];
   }
   const Version& ov = patched ? lsm_old : cur_view;
   const Version& nv = patched ? lsm_new : g->ver[target];
@@ -512,9 +536,85 @@ void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* 
       }
     }
   }
+  // With delta lanes (other contexts, each with its own stream), the
+  // count-only dQ_i of a large enough batch run depth-first side by side,
+  // one host thread per lane, instead of through the fused pipeline: their
+  // host-driven stages overlap and their kernels share the device.
+  const bool use_lanes = lanes && !lanes->empty() && k >= c->delta_lane_min;
+  if (use_lanes) {
+    struct Job {
+      uint32_t qi;
+      int i;
+      int64_t ws = 0;
+      uint64_t matches = 0;
+      gj_stats st{};
+    };
+    std::vector<Job> jobs;
+    for (uint32_t qi = 0; qi < nq; ++qi) {
+      bool want_rows = (out_rows && out_rows[qi]) || (out_signs && out_signs[qi]);
+      if (want_rows || done[qi]) continue;
+      for (int i = 0; i < (int)qs[qi]->atoms.size(); ++i) jobs.push_back(Job{qi, i});
+    }
+    if (!jobs.empty()) {
+      // the seeds and the new version are complete before other streams read them
+      GJ_HIP(hipStreamSynchronize(c->stream));
+      const size_t nw = std::min(jobs.size(), lanes->size() + 1);
+      std::vector<Error> errs(nw);
+      std::vector<char> failed(nw, 0);
+      auto work = [&](size_t w) {
+        gj_ctx* x = w == 0 ? c : (*lanes)[w - 1];
+        try {
+          if (w) GJ_HIP(hipSetDevice(x->device));
+          for (size_t j = w; j < jobs.size(); j += nw) {
+            Job& J = jobs[j];
+            delta_count_one(x, qs[J.qi], J.i, ov, nv, es, ed, eg, k, J.ws, J.matches, J.st);
+          }
+        } catch (const Error& e) {
+          errs[w] = e;
+          failed[w] = 1;
+        } catch (const std::exception& e) {
+          errs[w] = Error{GJ_EDEVICE, e.what()};
+          failed[w] = 1;
+        }
+      };
+      std::vector<std::thread> th;
+      try {
+        for (size_t w = 1; w < nw; ++w) th.emplace_back(work, w);
+      } catch (...) {
+        for (auto& t : th) t.join();
+        throw Error{GJ_ENOMEM, "cannot start a delta lane thread"};
+      }
+      work(0);
+      for (auto& t : th) t.join();
+      for (size_t w = 0; w < nw; ++w)
+        if (failed[w]) throw errs[w];
+      std::vector<gj_stats> acc(nq);
+      std::vector<int64_t> cd(nq, 0);
+      std::vector<uint64_t> raw(nq, 0);
+      for (const Job& J : jobs) {
+        add_stats(acc[J.qi], J.st);
+        cd[J.qi] += J.ws;
+        raw[J.qi] += J.matches;
+        done[J.qi] = 1;
+      }
+      for (const Job& J : jobs) {
+        const uint32_t qi = J.qi;
+        if (count_delta) count_delta[qi] = cd[qi];
+        if (n_delta) n_delta[qi] = 0;
+        if (stats) {
+          gj_stats a = acc[qi];
+          a.noop_inserts = hc[0];
+          a.noop_deletes = hc[1];
+          a.raw_emissions = raw[qi];
+          a.matches = raw[qi];
+          stats[qi] = a;
+        }
+      }
+    }
+  }
   // Queries that only need count deltas: every dQ_i of all of them runs as
   // one fused, graph-captured pipeline with signed seeds.
-  if (c->delta_fused) {
+  if (c->delta_fused && !use_lanes) {
     std::vector<gj::ReqSpec> specs;
     std::vector<uint32_t> owner;
     for (uint32_t qi = 0; qi < nq; ++qi) {

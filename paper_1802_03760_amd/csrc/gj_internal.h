@@ -204,6 +204,7 @@ struct gj_ctx {
   uint64_t batch_fallbacks = 0;     // batches rerun depth-first after a level overflow
   int delta_fused = 1;              // count-only delta queries through the fused pipeline
   uint64_t delta_owner_min = 1ull << 17;  // changes from which triangle-shaped deltas use the owner kernel
+  uint64_t delta_lane_min = 1024;  // changes from which a server's updates run their dQ_i on its delta lanes
   int factorise = 0;  // gj_run counts: trailing independent attributes as products
   uint64_t batch_heavy = 1ull << 24;  // gj_run_batch: estimated work from which a request runs depth-first
   int propose_u = 4;  // candidates per lane tested in lockstep by the generic propose kernel (1, 2, 4)
@@ -328,6 +329,7 @@ uint64_t read_u64(gj_ctx* c, const void* dptr);
 void read_bytes(gj_ctx* c, void* host, const void* dptr, size_t bytes);
 // several device words, one synchronisation
 void read_u64s(gj_ctx* c, std::initializer_list<const uint64_t*> ptrs, uint64_t* host);
+void read_u32s(gj_ctx* c, std::initializer_list<const uint32_t*> ptrs, uint32_t* host);
 
 inline unsigned grid_for(uint64_t items, uint64_t per_block, unsigned cap = 1u << 20) {
   uint64_t g = (items + per_block - 1) / per_block;
@@ -466,7 +468,8 @@ gj_status count_on_versions(gj_ctx* c, const gj_graph* g, const Version* const* 
 // api.hip: an update batch from host arrays written into version slot
 // `target`, count deltas only, as a status
 gj_status update_into(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst, const int8_t* sign,
-                      uint64_t b, const gj_query* const* qs, uint32_t nq, int64_t* count_delta, int target);
+                      uint64_t b, const gj_query* const* qs, uint32_t nq, int64_t* count_delta, int target,
+                      const std::vector<gj_ctx*>* lanes = nullptr);
 // api.hip: allocate version slot b with room for cap edges, as a status
 gj_status reserve_version(gj_ctx* c, gj_graph* g, int b, uint64_t cap);
 // api.hip: copy the tunable options of one context to another
@@ -482,10 +485,13 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
                 uint64_t hi, uint32_t* out, uint64_t cap, int out_on_device, gj_stats* st,
                 bool& overflow, const Version* ver = nullptr);
 // target: the version slot to write (-1: slot 1 - cur for cur < 2, else 0)
+// lanes: other contexts on the device on which the count-only dQ_i of a
+// batch of at least delta_lane_min changes run side by side (null: none)
 void apply_updates(gj_ctx* c, gj_graph* g, const uint32_t* src, const uint32_t* dst,
                    const int8_t* sign, uint64_t b, int on_device, const gj_query* const* qs,
                    uint32_t nq, int64_t* count_delta, uint32_t* const* rows,
                    int8_t* const* signs, const uint64_t* cap, uint64_t* n_delta,
-                   gj_stats* stats, bool& overflow, int target = -1);
+                   gj_stats* stats, bool& overflow, int target = -1,
+                   const std::vector<gj_ctx*>* lanes = nullptr);
 
 }  // namespace gj

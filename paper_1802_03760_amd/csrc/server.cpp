@@ -105,6 +105,7 @@ struct gj_server {
   gj_ctx* ctx = nullptr;   // updates: the caller's context
   gj_ctx* cctx = nullptr;  // light counts: internal context with its own stream
   std::vector<gj_ctx*> hctx;  // heavy lanes: one context and stream each
+  std::vector<gj_ctx*> uctx;  // delta lanes of the update thread: one context and stream each
   gj_graph* g = nullptr;
   uint32_t max_batch = 64;
   uint64_t mem_budget = 0;
@@ -122,6 +123,7 @@ struct gj_server {
   std::vector<std::unique_ptr<Active>> heavy;  // heavy requests, arrival order (under mu)
   bool light_done = false;                     // the light thread has exited
   int heavy_lanes = 3;                         // heavy requests run concurrently
+  int update_lanes = 2;                        // contexts beside ctx that run an update's dQ_i
   uint64_t heavy_work = 0;                     // estimated work per heavy chunk (0: 4 x iter_work)
   // version bookkeeping (under mu): state u = the graph after the first u
   // update requests; slot b holds states [lo[b], hi[b]] (empty if lo > hi)
@@ -556,7 +558,7 @@ static void update_loop(gj_server* s) {
     res.nq = (uint32_t)r.qs.size();
     int64_t cd[GJ_SERVER_MAX_QUERIES] = {0};
     res.status = update_into(s->ctx, s->g, r.src.data(), r.dst.data(), r.sign.data(), r.src.size(), r.qs.data(),
-                             (uint32_t)r.qs.size(), cd, target);
+                             (uint32_t)r.qs.size(), cd, target, &s->uctx);
     for (uint32_t i = 0; i < res.nq; ++i) res.count_delta[i] = cd[i];
     res.batch_size = 1;
     res.start_ns = start;
@@ -603,6 +605,7 @@ static void shutdown(gj_server* s) {
   if (s->update_worker.joinable()) s->update_worker.join();
   gj_ctx_destroy(s->cctx);
   for (gj_ctx* c : s->hctx) gj_ctx_destroy(c);
+  for (gj_ctx* c : s->uctx) gj_ctx_destroy(c);
   delete s;
 }
 
@@ -669,6 +672,14 @@ static gj_status enqueue_req(gj_server* s, Req&& r, uint64_t* ticket) {
         s->hctx.push_back(c);
       }
       if (s->hctx.empty()) return GJ_EDEVICE;
+      for (int l = 0; l < s->update_lanes; ++l) {
+        gj_ctx* c = nullptr;
+        if (gj_ctx_create(s->ctx->device, nullptr, s->ctx->alloc.alloc ? &s->ctx->alloc : nullptr, &c) != GJ_OK)
+          break;  // fewer lanes: the updates still run
+        gj::copy_options(c, s->ctx);
+        c->hash_build = false;
+        s->uctx.push_back(c);
+      }
       try {
         for (int l = 0; l < (int)s->hctx.size(); ++l) s->heavy_workers.emplace_back(gj::heavy_loop, s, l);
       } catch (...) {
@@ -732,6 +743,10 @@ gj_status gj_server_set_option(gj_server* s, const char* key, int64_t value) {
     if (value < 1 || value > 4) return GJ_EINVAL;
     if (s->started) return GJ_EBUSY;
     s->heavy_lanes = (int)value;
+  } else if (k == "update_lanes") {
+    if (value < 0 || value > 4) return GJ_EINVAL;
+    if (s->started) return GJ_EBUSY;
+    s->update_lanes = (int)value;
   } else if (k == "heavy_work") {
     if (value < 0) return GJ_EINVAL;
     s->heavy_work = (uint64_t)value;

@@ -198,3 +198,40 @@ def test_server_options(gj):
     srv.close()
     G.close()
     ctx.close()
+
+
+@pytest.mark.parametrize("lanes", [0, 1, 2, 4])
+def test_served_update_lanes(gj, lanes):
+    """Update batches whose count-only delta queries run side by side on the
+    server's delta lanes (delta_lane_min 0: every batch with a change),
+    between counts: every count delta equals the same batch applied alone,
+    and the oracle's, batch by batch."""
+    scale = 11
+    src, dst = synth.rmat_draws(scale, seed=51)
+    n = 1 << scale
+    ctx = gj.Context(0)
+    ctx.set_option("delta_lane_min", 0)
+    G = gj.Graph(ctx, src, dst, n)
+    qs = {k: gj.Query(ctx, *Q.ALL[k]) for k in Q.ALL}
+    E = G.info()["edges"]
+    srv = gj.Server(ctx, G, max_batch=16)
+    srv.set_option("update_lanes", lanes)
+    rng = np.random.default_rng(52)
+    submitted = []
+    upd_names = ["triangle", "clique4", "diamond", "cycle4", "house"]
+    for k, bs, bd, bg in synth.update_stream(scale, 51, 53, 5, 1, 2000):
+        for name, lo, hi in make_requests(rng, E, 6, ["triangle", "clique4", "diamond"]):
+            submitted.append((srv.submit_count(qs[name], lo, hi), ("count", name, lo, hi)))
+        submitted.append((srv.submit_update(bs, bd, bg, [qs[x] for x in upd_names]),
+                          ("update", bs, bd, bg, upd_names)))
+    results = {t: srv.wait(t, 120000) for t, _ in submitted}
+    srv.close()
+    replay_and_check(gj, src, dst, n, submitted, results)
+    O = oracle.Graph(n, src, dst)
+    for t, req in sorted(submitted, key=lambda x: x[0]):
+        if req[0] != "update":
+            continue
+        _, bs, bd, bg, names = req
+        want = [oracle.delta(O.copy(), bs, bd, bg, Q.ALL[x], rows=False, threads=8)["count_delta"] for x in names]
+        assert results[t]["count_delta"] == want, t
+        oracle.delta(O, bs, bd, bg)
