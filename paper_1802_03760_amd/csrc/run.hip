@@ -38,18 +38,19 @@ struct RunShape<false> {
   static constexpr int NT = 512;
   static constexpr uint32_t CAP = 4096;
   static constexpr int LOG_SLOTS = 13;
+  static constexpr int U = 2;  // windows per wave per step, their loads issued together
 };
 template <>
 struct RunShape<true> {
   static constexpr int NT = 1024;
   static constexpr uint32_t CAP = 24576;
   static constexpr int LOG_SLOTS = 15;
+  static constexpr int U = 1;
 };
 constexpr uint32_t kRunCap = RunShape<false>::CAP;
 constexpr uint32_t kRunCapBig = RunShape<true>::CAP;
 constexpr uint32_t kRunChunk = 512;  // prefixes per chunk (one thread each)
 constexpr uint32_t kRunEmpty = 0xFFFFFFFFu;
-constexpr int kRunU = 2;                // units per thread per step, loads in flight together
 
 // ---------------------------------------------------------------- planning
 // head[p] = 1 where a run starts: p = 0, or a key column differs from p - 1.
@@ -183,6 +184,38 @@ __device__ __forceinline__ uint64_t lower_bound_u64(const uint64_t* __restrict__
   return lo;
 }
 
+// Exclusive scan over a workgroup of NT threads with few live registers: a
+// scan in each wave, then the wave totals scanned by the first wave.  sh
+// holds NT / 64 + 1 values; the caller synchronises before reusing it.
+template <int NT>
+__device__ __forceinline__ uint64_t run_block_scan(uint64_t v, uint64_t& total, uint64_t* sh) {
+  constexpr int NW = NT / 64;
+  const int lane = lane_id(), wave = wave_id();
+  const uint64_t inc = wave_incl_scan(v);
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  if (wave == 0) {
+    const uint64_t x = lane < NW ? sh[lane] : 0ull;
+    const uint64_t xi = wave_incl_scan(x);
+    if (lane < NW) sh[lane] = xi - x;
+    if (lane == NW - 1) sh[NW] = xi;
+  }
+  __syncthreads();
+  total = sh[NW];
+  return sh[wave] + inc - v;
+}
+
+// OR of a 64-bit value over the wave
+__device__ __forceinline__ uint64_t wave_or(uint64_t v) {
+  uint32_t lo = (uint32_t)v, hi = (uint32_t)(v >> 32);
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    lo |= __shfl_xor(lo, o, 64);
+    hi |= __shfl_xor(hi, o, 64);
+  }
+  return ((uint64_t)hi << 32) | lo;
+}
+
 // last i in [0, n) with w[i] <= q (w ascending, w[0] = 0 <= q < w[n])
 __device__ __forceinline__ uint32_t run_owner(const uint32_t* w, uint32_t n, uint32_t q) {
   uint32_t lo = 0, hi = n;
@@ -287,17 +320,20 @@ __global__ void __launch_bounds__(RunShape<BIG>::NT) __attribute__((amdgpu_waves
                                                                  unsigned long long* __restrict__ acc,
                                                                  unsigned long long* __restrict__ wsum) {
   constexpr int kRunNT = RunShape<BIG>::NT;
+  constexpr int kRunU = RunShape<BIG>::U;
   constexpr int kRunLogSlots = RunShape<BIG>::LOG_SLOTS;
   __shared__ __attribute__((aligned(16))) uint32_t H[1 << kRunLogSlots];
   // S's values: in LDS (small shape) or this workgroup's global buffer
   __shared__ uint32_t SvL[BIG ? 1 : RunShape<BIG>::CAP];
   uint32_t* const SvG = sv_glob + (uint64_t)blockIdx.x * RunShape<BIG>::CAP;
+  // the chunk's prefixes with work: unit offsets; row start, length (top
+  // bit: streamed) and inequality range; table descriptor; weight
   __shared__ uint32_t coff[kRunChunk + 1];
-  __shared__ uint32_t clo[kRunChunk], clen[kRunChunk], clb[kRunChunk], cub[kRunChunk];
+  __shared__ uint4 cmeta[kRunChunk];
   __shared__ uint64_t cdesc[kRunChunk];
   __shared__ int8_t cw[kRunChunk];
-  __shared__ uint8_t cstream[kRunChunk];
   __shared__ uint64_t s_cs, s_ce, s_head;
+  __shared__ uint64_t s_scan[kRunNT / 64 + 1];
   __shared__ uint32_t s_task, s_nS, s_small;
   __shared__ uint32_t s_olo[kMaxBind], s_olen[kMaxBind];
   __shared__ uint64_t s_odesc[kMaxBind];
@@ -429,9 +465,12 @@ __global__ void __launch_bounds__(RunShape<BIG>::NT) __attribute__((amdgpu_waves
     for (uint64_t cb = cs; cb < ce && nS; cb += kRunChunk) {
       const uint32_t cn = (uint32_t)(ce - cb < kRunChunk ? ce - cb : kRunChunk);
       uint32_t u = 0;
+      uint32_t lo = 0, len = 0, lb = 0, ub = 0xFFFFFFFFu;
+      uint64_t desc = 0;
+      bool stream = false;
+      int8_t w8 = 1;
       if ((uint32_t)tid < cn) {
         const uint64_t p = cb + tid;
-        uint32_t lb = 0, ub = 0xFFFFFFFFu;
         if (d.above | d.below) {
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
@@ -442,9 +481,6 @@ __global__ void __launch_bounds__(RunShape<BIG>::NT) __attribute__((amdgpu_waves
             }
           }
         }
-        uint32_t lo = 0, len = 0;
-        uint64_t desc = 0;
-        bool stream = false;
         if (rd.newa >= 0) {
           uint32_t v = F[(uint64_t)ncol * stride + p], hi;
           row_range(nrp, npm, v, lo, hi);
@@ -456,60 +492,81 @@ __global__ void __launch_bounds__(RunShape<BIG>::NT) __attribute__((amdgpu_waves
           u = nS;
         }
         if (lb >= ub) u = 0;
-        clo[tid] = lo;
-        clen[tid] = len;
-        cdesc[tid] = desc;
-        clb[tid] = lb;
-        cub[tid] = ub;
-        cstream[tid] = stream ? 1 : 0;
-        if (SIGNED) cw[tid] = wt[p];
+        if (SIGNED) w8 = wt[p];
       }
-      uint32_t total;
-      uint32_t ex = block_excl_scan<kRunNT, uint32_t>(u, total);
-      if ((uint32_t)tid < cn) coff[tid] = ex;
-      if (tid == 0) coff[cn] = total;
+      // prefixes with work, compacted in order: their unit offsets (low
+      // half) and positions (high half) by one workgroup scan
+      uint64_t tot;
+      const uint64_t ex = run_block_scan<kRunNT>((uint64_t)u | ((uint64_t)(u != 0) << 32), tot, s_scan);
+      const uint32_t total = (uint32_t)tot, cnz = (uint32_t)(tot >> 32);
+      if (u) {
+        const uint32_t k = (uint32_t)(ex >> 32);
+        coff[k] = (uint32_t)ex;
+        cmeta[k] = make_uint4(lo, len | (stream ? 0x80000000u : 0u), lb, ub);
+        cdesc[k] = desc;
+        if (SIGNED) cw[k] = w8;
+      }
+      if (tid == 0) coff[cnz] = total;
       units += total;
       __syncthreads();
-      // kRunU units per thread per step, their loads issued together: unit
-      // q = q0 + u * kRunNT + tid belongs to the prefix i whose range of the
-      // chunk's unit space holds it, at offset t within it
-      for (uint32_t q0 = 0; q0 < total; q0 += kRunNT * kRunU) {
-        uint32_t ci[kRunU], xv[kRunU], slo[kRunU], sln[kRunU];
+      // Each wave walks a contiguous run of 64-unit windows of the chunk's
+      // unit space.  The prefix holding a window's first unit is carried from
+      // window to window: lane l reads where prefix i0 + 1 + l starts, the
+      // starts that fall in the window form a bit mask (every prefix has
+      // work, so at most 64 start there), and lane j's prefix is i0 plus
+      // the starts at or before j.  kRunU windows per step, their loads
+      // issued together.
+      constexpr uint32_t kWaves = kRunNT / 64;
+      const uint32_t lane = (uint32_t)lane_id();
+      const uint32_t nwin = (total + 63) >> 6;
+      const uint32_t per = (nwin + kWaves - 1) / kWaves;
+      const uint32_t wb = (uint32_t)wave_id() * per, we = min(nwin, wb + per);
+      uint32_t i0 = wb < we ? run_owner(coff, cnz, wb << 6) : 0u;
+      for (uint32_t wv = wb; wv < we; wv += kRunU) {
+        uint32_t ci[kRunU], xv[kRunU], slo[kRunU], sln[kRunU], lbv[kRunU], ubv[kRunU];
         uint64_t sds[kRunU];
         bool act[kRunU], sm[kRunU], hit[kRunU];
 #pragma unroll
-        for (int u = 0; u < kRunU; ++u) {
-          const uint32_t q = q0 + u * kRunNT + tid;
-          act[u] = q < total;
-          const uint32_t i = act[u] ? run_owner(coff, cn, q) : 0u;
-          const uint32_t t = q - coff[i];
-          ci[u] = i;
-          sm[u] = act[u] && !cstream[i];
-          xv[u] = !act[u] ? 0u : (sm[u] ? (BIG ? SvG[t] : SvL[t]) : nadj[clo[i] + t]);
+        for (int k = 0; k < kRunU; ++k) {
+          const uint32_t qw = (wv + k) << 6, q = qw + lane;
+          const bool wok = wv + k < we;
+          uint64_t bit = 0;
+          const uint32_t nb = i0 + 1 + lane;
+          if (wok && nb < cnz) {
+            const uint32_t b = coff[nb] - qw;
+            if (b < 64) bit = 1ull << b;
+          }
+          const uint64_t smask = wave_or(bit);
+          const uint32_t i = i0 + (uint32_t)__popcll(smask & ((2ull << lane) - 1));
+          i0 += (uint32_t)__popcll(smask);
+          act[k] = wok && q < total;
+          ci[k] = act[k] ? i : 0u;
+          const uint4 mt = cmeta[ci[k]];
+          const uint32_t t = q - coff[ci[k]];
+          sm[k] = act[k] && !(mt.y >> 31);
+          slo[k] = mt.x;
+          sln[k] = mt.y & 0x7FFFFFFFu;
+          lbv[k] = mt.z;
+          ubv[k] = mt.w;
+          xv[k] = !act[k] ? 0u : (sm[k] ? (BIG ? SvG[t] : SvL[t]) : nadj[mt.x + t]);
         }
         // streamed values: one LDS probe each
 #pragma unroll
-        for (int u = 0; u < kRunU; ++u) hit[u] = act[u] && !sm[u] && run_probe(H, xv[u], shift, bmask);
+        for (int k = 0; k < kRunU; ++k) hit[k] = act[k] && !sm[k] && run_probe(H, xv[k], shift, bmask);
         // S's values: membership in the prefix's new set in memory
-#pragma unroll
-        for (int u = 0; u < kRunU; ++u) {
-          const uint32_t i = ci[u];
-          slo[u] = clo[i];
-          sln[u] = clen[i];
-          sds[u] = cdesc[i];
-        }
         if (rd.newa >= 0) {
+#pragma unroll
+          for (int k = 0; k < kRunU; ++k) sds[k] = sm[k] ? cdesc[ci[k]] : 0ull;
           member_lockstep<kRunU>(nadj, nhs, sds, slo, sln, xv, sm, hit);
         } else {
 #pragma unroll
-          for (int u = 0; u < kRunU; ++u) hit[u] = hit[u] || sm[u];
+          for (int k = 0; k < kRunU; ++k) hit[k] = hit[k] || sm[k];
         }
 #pragma unroll
-        for (int u = 0; u < kRunU; ++u) {
-          const uint32_t i = ci[u];
-          if (act[u] && hit[u] && xv[u] >= clb[i] && xv[u] < cub[i]) {
+        for (int k = 0; k < kRunU; ++k) {
+          if (act[k] && hit[k] && xv[k] >= lbv[k] && xv[k] < ubv[k]) {
             ++hits;
-            if (SIGNED) whits += cw[i];
+            if (SIGNED) whits += cw[ci[k]];
           }
         }
       }
