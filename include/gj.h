@@ -488,7 +488,9 @@ gj_status gj_autotune(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_qu
  * x bytes per prefix) stays within mem_budget_bytes (0: no limit), in one
  * fused pipeline per iteration (a request alone runs the depth-first path).
  * Heavy requests are cut into chunks of about "heavy_work" estimated
- * extensions (0, the default: 4 x iteration_work) that the heavy lanes run
+ * extensions (0, the default: 64 x iteration_work, so that a chunk's last
+ * stage is large enough for the kernels that group prefix runs, see
+ * "run_stage") that the heavy lanes run
  * concurrently on the depth-first path, each lane taking the oldest heavy
  * request no other lane is running.  Requests whose version an update waits
  * for go first; with "update_priority" (default 1) no new heavy chunk starts

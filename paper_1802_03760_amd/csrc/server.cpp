@@ -124,7 +124,7 @@ struct gj_server {
   bool light_done = false;                     // the light thread has exited
   int heavy_lanes = 3;                         // heavy requests run concurrently
   int update_lanes = 2;                        // contexts beside ctx that run an update's dQ_i
-  uint64_t heavy_work = 0;                     // estimated work per heavy chunk (0: 4 x iter_work)
+  uint64_t heavy_work = 0;                     // estimated work per heavy chunk (0: 64 x iter_work)
   // version bookkeeping (under mu): state u = the graph after the first u
   // update requests; slot b holds states [lo[b], hi[b]] (empty if lo > hi)
   uint64_t submitted_updates = 0, applied = 0;
@@ -476,7 +476,7 @@ static void heavy_loop(gj_server* s, int lane) {
         return pick != nullptr || (s->light_done && s->heavy.empty());
       });
       if (!pick) break;  // the light thread has exited and every heavy request is done
-      double W = (double)(s->heavy_work ? s->heavy_work : 4 * std::max<uint64_t>(s->iter_work, 1));
+      double W = (double)(s->heavy_work ? s->heavy_work : 64 * std::max<uint64_t>(s->iter_work, 1));
       double used = 0;
       ch = take(pick, W, used);
       pick->next = ch.hi;  // claimed
