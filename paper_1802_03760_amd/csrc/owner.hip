@@ -278,6 +278,8 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
   __shared__ uint16_t wstart[kOwnNT];    // short window -> set holding its first element
   __shared__ int8_t psg[kOwnNT];         // sign of each partner's seed edge
   __shared__ uint32_t s_task, s_long;
+  __shared__ uint32_t s_scan[kOwnNT / 64 + 1];
+  __shared__ uint64_t s_sum[kOwnNT / 64 + 1];
   const int tid = threadIdx.x, lane = lane_id(), wave = wave_id();
   constexpr int nwaves = kOwnNT / 64;
   uint64_t hits = 0, ext = 0;
@@ -336,7 +338,7 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
         // one scan: long-partner count in the high half, short sizes in the low half
         bool is_long = s >= kLong;
         uint32_t total;
-        uint32_t pre = block_excl_scan<kOwnNT, uint32_t>(is_long ? (1u << 16) : s, total);
+        uint32_t pre = block_scan_lean<kOwnNT>(is_long ? (1u << 16) : s, total, s_scan);
         uint32_t nlong = total >> 16, short_total = total & 0xFFFFu;
         uint32_t kl = pre >> 16;
         if (is_long) {
@@ -456,14 +458,14 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
     }
   }
 
-  uint64_t th = block_sum<kOwnNT>(hits);
-  uint64_t te = block_sum<kOwnNT>(ext);
+  uint64_t th = block_sum_lean<kOwnNT>(hits, s_sum);
+  uint64_t te = block_sum_lean<kOwnNT>(ext, s_sum);
   if (tid == 0) {
     atomicAdd(acc, (unsigned long long)th);
     atomicAdd(acc + 1, (unsigned long long)te);
   }
   if (SIGNED) {
-    uint64_t ts = block_sum<kOwnNT>((uint64_t)shits);  // two's complement: the signed sum
+    uint64_t ts = block_sum_lean<kOwnNT>((uint64_t)shits, s_sum);  // two's complement: the signed sum
     if (tid == 0) atomicAdd(acc + 2, (unsigned long long)ts);
   }
 }

@@ -107,6 +107,28 @@ __device__ __forceinline__ T block_excl_scan(T v, T& total) {
   return before + inc - v;
 }
 
+// The same scan with few live registers: each wave scans, then the first
+// wave scans the wave totals (sh holds NT / 64 + 1 values).  For wide
+// workgroups, where the loop above keeps every wave total live at once.
+// Contains __syncthreads; the caller synchronises before reusing sh.
+template <int NT, typename T>
+__device__ __forceinline__ T block_scan_lean(T v, T& total, T* sh) {
+  constexpr int NW = NT / 64;
+  const int lane = lane_id(), wave = wave_id();
+  const T inc = wave_incl_scan(v);
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  if (wave == 0) {
+    const T x = lane < NW ? sh[lane] : (T)0;
+    const T xi = wave_incl_scan(x);
+    if (lane < NW) sh[lane] = xi - x;
+    if (lane == NW - 1) sh[NW] = xi;
+  }
+  __syncthreads();
+  total = sh[NW];
+  return sh[wave] + inc - v;
+}
+
 template <int NT>
 __device__ __forceinline__ uint64_t block_sum(uint64_t v) {
   __shared__ uint64_t wsum[NT / 64];
@@ -116,6 +138,25 @@ __device__ __forceinline__ uint64_t block_sum(uint64_t v) {
   uint64_t all = 0;
 #pragma unroll
   for (int w = 0; w < NT / 64; ++w) all += wsum[w];
+  __syncthreads();
+  return all;
+}
+
+// Workgroup sum with few live registers (see block_scan_lean); sh holds
+// NT / 64 + 1 values.  Contains __syncthreads.
+template <int NT>
+__device__ __forceinline__ uint64_t block_sum_lean(uint64_t v, uint64_t* sh) {
+  constexpr int NW = NT / 64;
+  const int lane = lane_id(), wave = wave_id();
+  v = wave_sum(v);
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  if (wave == 0) {
+    const uint64_t t = wave_sum(lane < NW ? sh[lane] : 0ull);
+    if (lane == 0) sh[NW] = t;
+  }
+  __syncthreads();
+  const uint64_t all = sh[NW];
   __syncthreads();
   return all;
 }
