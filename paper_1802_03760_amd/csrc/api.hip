@@ -431,6 +431,8 @@ void gj_graph_destroy(gj_graph* g) {
   }
   for (auto& v : g->ver) {
     gj::hash_free(g->ctx, v);
+    gj::dev_free(g->ctx, v.plan.tasks);
+    v.plan = gj::OwnerPlan{};
     gj::version_free(g->ctx, v);
   }
   gj::lsm_free(g);

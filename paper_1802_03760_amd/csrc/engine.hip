@@ -455,7 +455,18 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
                 v.d[dir].rp,   v.d[dir].col,   v.d[1 - dir].rp, v.d[1 - dir].col, g->n};
     KernelTimer timer(c);
     uint64_t matches = 0, ext = 0;
-    owner_count(c, a, v.d[dir].row, v.d[dir].col, v.d[1 - dir].row, v.d[1 - dir].col, v.m, timer, matches, ext);
+    if (!ver) {
+      // the graph's current slot keeps the plan (tasks by owner and partner
+      // range, a function of its degrees) for later counts of this version
+      gj_graph* gm = const_cast<gj_graph*>(g);
+      std::lock_guard<std::mutex> lk(gm->hash_mu);
+      Version& slot = gm->ver[gm->cur];
+      owner_count(c, a, v.d[dir].row, v.d[dir].col, v.d[1 - dir].row, v.d[1 - dir].col, v.m, timer, matches, ext,
+                  nullptr, &slot.plan, slot.gen, gm->ctx);
+    } else {
+      owner_count(c, a, v.d[dir].row, v.d[dir].col, v.d[1 - dir].row, v.d[1 - dir].col, v.m, timer, matches,
+                  ext);
+    }
     gj_stats s{};
     s.prefixes[2] = v.m;
     s.extensions[2] = ext;

@@ -118,6 +118,18 @@ struct HashDir {
   uint64_t buckets_cap = 0;
 };
 
+// The owner-grouped kernel's plan of a static count over one version: its
+// tasks (owner unit, partner range), a function of the version's degrees,
+// kept while gen matches the version's and the key (row-pointer arrays of the
+// atoms and seed indexes, the minimum task work) is the same.
+struct OwnerPlan {
+  uint32_t* tasks = nullptr;  // 3 x nt, device, allocated through the graph's context
+  uint64_t cap = 0;           // u32 entries allocated
+  uint64_t nt = 0, split_units = 0;
+  uint64_t gen = ~0ull, tw = 0;
+  const uint32_t* key[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
 struct Version {
   CsrDir d[2];  // 0 forward, 1 reverse
   uint64_t m = 0, cap = 0;
@@ -136,6 +148,8 @@ struct Version {
   // update path has rewritten it into the tail of col, ~0 when it is still
   // rp[v] .. rp[v + 1]; null when no row is rewritten.
   const uint64_t* pmap[2] = {nullptr, nullptr};
+  // only the graph's own slots fill it (copies of a Version never do)
+  OwnerPlan plan;
 };
 
 // Log-structured updates (the multi-version index of Sec. 4.3): between two

@@ -25,8 +25,12 @@ struct OwnerArgs {
 // matches with each edge's term times its sign.  seed_row/seed_col: the E
 // seed edges as (x0, x1) in seed-index order; t_row/t_col: the same edges in
 // transposed-index order as (x1, x0).
+// plan (with gen, the version's generation, and pc, the context that owns
+// the graph's memory): a static count's plan kept with the version, reused
+// while valid, else built and stored there; null: planned for this call only.
 void owner_count(gj_ctx* c, const OwnerArgs& a, const uint32_t* seed_row, const uint32_t* seed_col,
                  const uint32_t* t_row, const uint32_t* t_col, uint64_t E, KernelTimer& timer, uint64_t& matches,
-                 uint64_t& extensions, int64_t* wsum = nullptr);
+                 uint64_t& extensions, int64_t* wsum = nullptr, OwnerPlan* plan = nullptr, uint64_t gen = 0,
+                 gj_ctx* pc = nullptr);
 
 }  // namespace gj

@@ -21,7 +21,10 @@
 // the (prefix, range) balancing of Sec. 3.4 applied within the GPU.  Probe
 // sets larger than half the table are processed in id-range segments.  Edges
 // whose larger set is below kDMin go to a per-edge merge in the same launch.
+#include <algorithm>
+
 #include "gj_internal.h"
+
 #include "owner.h"
 #include "prim.h"
 
@@ -473,32 +476,68 @@ __global__ void __launch_bounds__(kOwnNT) __attribute__((amdgpu_waves_per_eu(8))
 // ---------------------------------------------------------------- host
 void owner_count(gj_ctx* c, const OwnerArgs& a, const uint32_t* seed_row, const uint32_t* seed_col,
                  const uint32_t* t_row, const uint32_t* t_col, uint64_t E, KernelTimer& timer, uint64_t& matches,
-                 uint64_t& extensions, int64_t* wsum) {
+                 uint64_t& extensions, int64_t* wsum, OwnerPlan* plan, uint64_t gen, gj_ctx* pc) {
   uint64_t units = 2ull * a.n;
-  uint32_t* ntasks = (uint32_t*)ws_get(c, "own_nt", (units + 1) * sizeof(uint32_t));
-  uint64_t* toff = (uint64_t*)ws_get(c, "own_toff", (units + 1) * sizeof(uint64_t));
   // acc: matches, extensions, signed sum, units split into several tasks
   unsigned long long* acc = (unsigned long long*)ws_get(c, "own_acc", 4 * sizeof(unsigned long long));
   unsigned int* counter = (unsigned int*)ws_get(c, "own_ctr", sizeof(unsigned int));
   GJ_HIP(hipMemsetAsync(acc, 0, 4 * sizeof(unsigned long long), c->stream));
   GJ_HIP(hipMemsetAsync(counter, 0, sizeof(unsigned int), c->stream));
   const uint64_t tw_min = c->owner_task_min;
-  uint32_t* vals = (uint32_t*)ws_get(c, "own_vals", (E + 1) * sizeof(uint32_t));
-  uint64_t* wscan0 = (uint64_t*)ws_get(c, "own_ws0", (E + 1) * sizeof(uint64_t));
-  uint64_t* wscan1 = (uint64_t*)ws_get(c, "own_ws1", (E + 1) * sizeof(uint64_t));
-  unsigned ge = grid_for(E, kBlock, 1u << 16);
-  if (E) k_owner_vals<<<ge, kBlock, 0, c->stream>>>(a, 0, seed_row, seed_col, E, vals);
-  scan_u32_to_u64(c, vals, wscan0, E);
-  if (E) k_owner_vals<<<ge, kBlock, 0, c->stream>>>(a, 1, t_row, t_col, E, vals);
-  scan_u32_to_u64(c, vals, wscan1, E);
-  k_owner_units<<<grid_for(units, kBlock, 1u << 16), kBlock, 0, c->stream>>>(a, wscan0, wscan1, tw_min, ntasks,
-                                                                             acc + 3);
-  scan_u32_to_u64(c, ntasks, toff, units);
-  uint64_t nt = read_u64(c, toff + units);
-  GJ_CHECK(nt < (1ull << 32), GJ_EUNSUPPORTED, "too many owner tasks");
-  uint32_t* tasks = (uint32_t*)ws_get(c, "own_tasks", (3 * nt + 3) * sizeof(uint32_t));
-  k_owner_tasks<<<grid_for(units, kBlock, 1u << 16), kBlock, 0, c->stream>>>(a, wscan0, wscan1, ntasks, toff, tasks);
-  GJ_HIP(hipGetLastError());
+  const uint32_t* key[4] = {a.rpA, a.rpB, a.rpS0, a.rpS1};
+  const bool reuse = plan && plan->tasks && plan->gen == gen && plan->tw == tw_min &&
+                     std::equal(key, key + 4, plan->key);
+  uint64_t nt = 0, split = 0;
+  const uint32_t* tasks = nullptr;
+  if (reuse) {
+    nt = plan->nt;
+    split = plan->split_units;
+    tasks = plan->tasks;
+  } else {
+    uint32_t* ntasks = (uint32_t*)ws_get(c, "own_nt", (units + 1) * sizeof(uint32_t));
+    uint64_t* toff = (uint64_t*)ws_get(c, "own_toff", (units + 1) * sizeof(uint64_t));
+    uint32_t* vals = (uint32_t*)ws_get(c, "own_vals", (E + 1) * sizeof(uint32_t));
+    uint64_t* wscan0 = (uint64_t*)ws_get(c, "own_ws0", (E + 1) * sizeof(uint64_t));
+    uint64_t* wscan1 = (uint64_t*)ws_get(c, "own_ws1", (E + 1) * sizeof(uint64_t));
+    unsigned ge = grid_for(E, kBlock, 1u << 16);
+    if (E) k_owner_vals<<<ge, kBlock, 0, c->stream>>>(a, 0, seed_row, seed_col, E, vals);
+    scan_u32_to_u64(c, vals, wscan0, E);
+    if (E) k_owner_vals<<<ge, kBlock, 0, c->stream>>>(a, 1, t_row, t_col, E, vals);
+    scan_u32_to_u64(c, vals, wscan1, E);
+    k_owner_units<<<grid_for(units, kBlock, 1u << 16), kBlock, 0, c->stream>>>(a, wscan0, wscan1, tw_min, ntasks,
+                                                                               acc + 3);
+    scan_u32_to_u64(c, ntasks, toff, units);
+    uint64_t h2[2];
+    read_u64s(c, {toff + units, (const uint64_t*)(acc + 3)}, h2);
+    nt = h2[0];
+    split = h2[1];
+    GJ_CHECK(nt < (1ull << 32), GJ_EUNSUPPORTED, "too many owner tasks");
+    uint32_t* tw = nullptr;
+    if (plan) {
+      // the plan is kept with the version: allocated through the graph's context
+      if (plan->cap < 3 * nt + 3) {
+        plan->gen = ~0ull;
+        dev_free(pc, plan->tasks);
+        plan->tasks = nullptr;
+        plan->cap = 0;
+        plan->tasks = (uint32_t*)dev_alloc(pc, (3 * nt + 3) * sizeof(uint32_t));
+        plan->cap = 3 * nt + 3;
+      }
+      tw = plan->tasks;
+    } else {
+      tw = (uint32_t*)ws_get(c, "own_tasks", (3 * nt + 3) * sizeof(uint32_t));
+    }
+    k_owner_tasks<<<grid_for(units, kBlock, 1u << 16), kBlock, 0, c->stream>>>(a, wscan0, wscan1, ntasks, toff, tw);
+    GJ_HIP(hipGetLastError());
+    tasks = tw;
+    if (plan) {
+      plan->nt = nt;
+      plan->split_units = split;
+      plan->tw = tw_min;
+      std::copy(key, key + 4, plan->key);
+      plan->gen = gen;
+    }
+  }
   unsigned grid = (unsigned)c->num_cus * 2;
   timer.start();
   GJ_CHECK((a.sg0 == nullptr) == (a.sg1 == nullptr), GJ_EINVAL, "owner kernel: signs for one order only");
@@ -508,10 +547,10 @@ void owner_count(gj_ctx* c, const OwnerArgs& a, const uint32_t* seed_row, const 
     k_owner_count<false><<<grid, kOwnNT, 0, c->stream>>>(a, tasks, (uint32_t)nt, counter, seed_row, seed_col, E, acc);
   timer.stop();
   GJ_HIP(hipGetLastError());
-  unsigned long long h[4];
+  unsigned long long h[3];
   read_bytes(c, h, acc, sizeof(h));
   c->owner_tasks = nt;
-  c->owner_split_units = h[3];
+  c->owner_split_units = split;
   matches = h[0];
   extensions = h[1];
   if (wsum) *wsum = a.sg0 ? (int64_t)h[2] : (int64_t)h[0];
