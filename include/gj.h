@@ -90,6 +90,13 @@ const char* gj_last_error(const gj_ctx* ctx);
  *                   fused propose kernel claims from the device counter at a
  *                   time, 1..4096 (default 16)
  *   "batch_cap"     gj_run_batch: prefixes per level (default 2^27)
+ *   "batch_run"     gj_run_batch: 1 (default) lets the fused pipeline's last
+ *                   stage of a static count take the run kernels of
+ *                   "run_stage" (with its run_ratio, run_min_work,
+ *                   run_reuse and run_task_work; levels of at most 2^25
+ *                   prefixes; the context's run_* sums count their work);
+ *                   0 keeps the per-candidate kernel there.  Counts and
+ *                   counters are the same either way
  *   "batch_heavy"   gj_run_batch: requests whose estimated work (the
  *                   server's seed-work estimate) reaches this run on the
  *                   depth-first path, the rest fused (default 2^24; 0: all

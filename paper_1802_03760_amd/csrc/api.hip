@@ -271,6 +271,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "batch_claim_words") {
       GJ_CHECK(value >= 1 && value <= 4096, GJ_EINVAL, "batch_claim_words out of range");
       c->batch_claim_words = (uint32_t)value;
+    } else if (k == "batch_run") {
+      GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "batch_run must be 0 or 1");
+      c->batch_run = (int)value;
     } else if (k == "run_stage") {
       GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "run_stage must be 0 or 1");
       c->run_stage = (int)value;
@@ -312,6 +315,7 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "batch_lin") *value = c->batch_lin;
     else if (k == "batch_waves_per_cu") *value = c->batch_waves_per_cu;
     else if (k == "batch_claim_words") *value = c->batch_claim_words;
+    else if (k == "batch_run") *value = c->batch_run;
     else if (k == "batch_fallbacks") *value = (int64_t)c->batch_fallbacks;
     else if (k == "delta_fused") *value = c->delta_fused;
     else if (k == "delta_owner_min") *value = (int64_t)c->delta_owner_min;
@@ -777,6 +781,7 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->batch_lin = src->batch_lin;
   dst->batch_waves_per_cu = src->batch_waves_per_cu;
   dst->batch_claim_words = src->batch_claim_words;
+  dst->batch_run = src->batch_run;
   dst->batch_cap = src->batch_cap;
   dst->delta_fused = src->delta_fused;
   dst->delta_owner_min = src->delta_owner_min;

@@ -24,33 +24,11 @@
 #include "engine.h"
 #include "gj_internal.h"
 #include "prim.h"
+#include "run.h"
 
 namespace gj {
 
-struct BReq {
-  uint32_t m;
-  uint32_t pad;
-  uint64_t seed_lo;
-  const uint32_t* seed_row;
-  const uint32_t* seed_col;
-  const int8_t* seed_w;  // signed seeds of a delta query, or null (+1)
-  SeedFilter filt;
-  StageDesc st[GJ_MAX_ATTRS];
-};
 
-// header of the device state: sizes and flags read by every kernel
-struct BHead {
-  uint32_t nreq;
-  uint32_t lin;        // tuned: linear search below this extension-set size
-  uint32_t claim_words;  // tuned: words (64 candidates each) a wave claims at a time
-  uint64_t seeds;      // total seed edges over all requests
-  unsigned long long nlev[GJ_MAX_ATTRS + 1];
-  unsigned long long claim[GJ_MAX_ATTRS + 1];  // next unclaimed word chunk per level
-  uint32_t overflow;
-};
-
-
-constexpr int kStat = GJ_MAX_ATTRS + 1;
 
 __device__ __forceinline__ bool member(const uint32_t* __restrict__ a, uint32_t lo, uint32_t hi, uint32_t x,
                                        uint32_t lin) {
@@ -237,7 +215,8 @@ __global__ void __launch_bounds__(kBlock) k_bt_count_min(const BReq* __restrict_
 __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ R, int j, BHead* __restrict__ H,
                                                        const uint32_t* __restrict__ F,
                                                        const uint32_t* __restrict__ rid, uint64_t cap,
-                                                       const uint64_t* __restrict__ off,
+                                                       const uint64_t* __restrict__ off_all,
+                                                       const uint64_t* __restrict__ off_left,
                                                        const uint8_t* __restrict__ mini, const int8_t* __restrict__ Fw,
                                                        uint32_t* __restrict__ G, uint32_t* __restrict__ grid_,
                                                        int8_t* __restrict__ Gw, uint64_t gcap,
@@ -245,6 +224,9 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
                                                        unsigned long long* __restrict__ pre,
                                                        unsigned long long* __restrict__ wsum) {
   const uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
+  // the candidates the run kernels left (staged runs' prefixes have none),
+  // where they took the level
+  const uint64_t* __restrict__ off = H->nrun[j] > 0 ? off_left : off_all;
   const uint64_t W = off[n];
   const uint32_t lin = H->lin;
   const uint64_t claim = H->claim_words;
@@ -347,9 +329,10 @@ constexpr int kBtTile = kBlock * 8;
 // size, so a small level costs a few tiles whatever the capacity.
 constexpr unsigned kScanGrid = 1024;
 
-__global__ void __launch_bounds__(kBlock) k_bt_scan_reduce(const uint32_t* __restrict__ in, const BHead* H, int j,
-                                                           uint64_t cap, uint64_t* __restrict__ part) {
-  uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
+__global__ void __launch_bounds__(kBlock) k_bt_scan_reduce(const uint32_t* __restrict__ in,
+                                                           const unsigned long long* __restrict__ np, uint64_t cap,
+                                                           uint64_t* __restrict__ part) {
+  uint64_t n = *np < cap ? *np : cap;
   uint64_t tiles = (n + kBtTile - 1) / kBtTile + 1;
   for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
     uint64_t base = t * kBtTile;
@@ -363,11 +346,12 @@ __global__ void __launch_bounds__(kBlock) k_bt_scan_reduce(const uint32_t* __res
   }
 }
 
-__global__ void __launch_bounds__(kBlock) k_bt_scan_down(const uint32_t* __restrict__ in, const BHead* H, int j,
-                                                         uint64_t cap, const uint64_t* __restrict__ part_off,
+__global__ void __launch_bounds__(kBlock) k_bt_scan_down(const uint32_t* __restrict__ in,
+                                                         const unsigned long long* __restrict__ np, uint64_t cap,
+                                                         const uint64_t* __restrict__ part_off,
                                                          uint64_t* __restrict__ out) {
   __shared__ uint64_t tile[kBtTile];
-  uint64_t n = H->nlev[j] < cap ? H->nlev[j] : cap;
+  uint64_t n = *np < cap ? *np : cap;
   uint64_t tiles = (n + kBtTile - 1) / kBtTile + 1;
   for (uint64_t t = blockIdx.x; t < tiles; t += gridDim.x) {
     uint64_t base = t * kBtTile;
@@ -397,9 +381,10 @@ __global__ void __launch_bounds__(kBlock) k_bt_scan_down(const uint32_t* __restr
 }
 
 // exclusive scan of the block sums of the live tiles, one workgroup
-__global__ void __launch_bounds__(kBlock) k_bt_scan_parts(const uint64_t* __restrict__ part, const BHead* H, int j,
-                                                          uint64_t cap, uint64_t* __restrict__ out) {
-  uint64_t nl = H->nlev[j] < cap ? H->nlev[j] : cap;
+__global__ void __launch_bounds__(kBlock) k_bt_scan_parts(const uint64_t* __restrict__ part,
+                                                          const unsigned long long* __restrict__ np, uint64_t cap,
+                                                          uint64_t* __restrict__ out) {
+  uint64_t nl = *np < cap ? *np : cap;
   uint64_t n = (nl + kBtTile - 1) / kBtTile + 1;
   uint64_t carry = 0;
   for (uint64_t base = 0; base < n; base += kBtTile) {
@@ -421,6 +406,18 @@ __global__ void __launch_bounds__(kBlock) k_bt_scan_parts(const uint64_t* __rest
   if (threadIdx.x == 0) out[n] = carry;
 }
 
+void bt_scan_n(hipStream_t st, const uint32_t* in, const unsigned long long* n, uint64_t cap, uint64_t* part,
+               uint64_t* part_off, uint64_t* out) {
+  k_bt_scan_reduce<<<kScanGrid, kBlock, 0, st>>>(in, n, cap, part);
+  k_bt_scan_parts<<<1, kBlock, 0, st>>>(part, n, cap, part_off);
+  k_bt_scan_down<<<kScanGrid, kBlock, 0, st>>>(in, n, cap, part_off, out);
+}
+
+void bt_scan(hipStream_t st, const uint32_t* in, const BHead* H, int j, uint64_t cap, uint64_t* part,
+             uint64_t* part_off, uint64_t* out) {
+  bt_scan_n(st, in, &H->nlev[j], cap, part, part_off, out);
+}
+
 // ---------------------------------------------------------------- executor
 struct BatchExec::Impl {
   uint32_t max_req = 0;
@@ -439,6 +436,11 @@ struct BatchExec::Impl {
   uint64_t* part = nullptr;
   uint64_t* part_off = nullptr;
   uint64_t nparts = 0;
+  // run kernels of the last stage (run.h), when captured into the pipeline:
+  // their buffers and the per-request, per-level split table
+  bool runs = false;
+  RunFusedBufs rb;
+  RunDesc* d_rdt = nullptr;
   void* h_stage = nullptr;  // pinned staging for the request table and results
   size_t h_stage_bytes = 0;
   hipGraph_t graph = nullptr;
@@ -448,6 +450,7 @@ struct BatchExec::Impl {
   gj_ctx* owner = nullptr;  // the context whose allocator holds allocs
 
   uint64_t stat_words() const { return (uint64_t)max_req * (2 + 2 * kStat); }
+  uint64_t rdt_entries() const { return (uint64_t)max_req * kStat; }
   unsigned long long* cnt() { return d_stat; }
   unsigned long long* wsum() { return d_stat + max_req; }
   unsigned long long* pre() { return d_stat + 2ull * max_req; }
@@ -478,11 +481,13 @@ static void enqueue(gj_ctx* c, BatchExec::Impl& s, unsigned grid) {
     // latency-bound, no dynamic claiming: oversubscribe (idle blocks exit at once)
     k_bt_count_min<<<grid_for(s.cap, kBlock * 4, 8192), kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j],
                                                                          s.cap, s.minc[j], s.mini[j], s.ext());
-    k_bt_scan_reduce<<<kScanGrid, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part);
-    k_bt_scan_parts<<<1, kBlock, 0, st>>>(s.part, s.d_head, j, s.cap, s.part_off);
-    k_bt_scan_down<<<kScanGrid, kBlock, 0, st>>>(s.minc[j], s.d_head, j, s.cap, s.part_off, s.off[j]);
+    bt_scan(st, s.minc[j], s.d_head, j, s.cap, s.part, s.part_off, s.off[j]);
+    if (s.runs)
+      run_fused_level(st, s.rb, s.d_req, s.d_rdt, s.d_head, j, s.F[j], s.rid[j], s.cap, s.off[j], s.minc[j], s.part,
+                      s.part_off, s.cnt(), s.pre(), s.wsum());
     bool last = j + 1 >= s.max_m;
-    k_bt_propose<<<grid, kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j], s.cap, s.off[j], s.mini[j], s.W[j],
+    k_bt_propose<<<grid, kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j], s.cap, s.off[j],
+                                         s.runs ? s.rb.off2 : s.off[j], s.mini[j], s.W[j],
                                          last ? nullptr : s.F[j + 1], last ? nullptr : s.rid[j + 1],
                                          last ? nullptr : s.W[j + 1], last ? 0 : s.cap, s.cnt(), s.pre(),
                                          s.wsum());
@@ -499,7 +504,9 @@ void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t
   uint64_t cap = c->batch_cap;
   unsigned grid = (unsigned)c->num_cus * (c->batch_waves_per_cu / 4 > 0 ? c->batch_waves_per_cu / 4 : 1);
   Impl& s = *p;
-  bool rebuild = nreq > s.max_req || max_m > s.max_m || cap != s.cap || grid != s.grid_cfg || !s.exec;
+  const bool runs = c->batch_run != 0;
+  bool rebuild = nreq > s.max_req || max_m > s.max_m || cap != s.cap || grid != s.grid_cfg || runs != s.runs ||
+                 !s.exec;
   if (rebuild) {
     uint32_t mr = std::max<uint32_t>(nreq, std::max<uint32_t>(s.max_req, 64));
     int mm = std::max(max_m, std::max(s.max_m, 3));
@@ -527,8 +534,17 @@ void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t
     t.nparts = (cap + kBtTile - 1) / kBtTile + 1;
     t.part = (uint64_t*)t.alloc(t.nparts * sizeof(uint64_t));
     t.part_off = (uint64_t*)t.alloc((t.nparts + 1) * sizeof(uint64_t));
+    t.runs = runs;
+    if (runs) {
+      // levels of up to 2^25 prefixes take the run kernels (larger ones keep
+      // the per-candidate kernel), so the buffers stay below 2 GB
+      const uint64_t rcap = std::min<uint64_t>(cap, 1ull << 25);
+      unsigned long long* stats = run_stats_get(c);  // cleared here, outside the capture
+      run_fused_carve(t.rb, t.alloc(run_fused_bytes(rcap, c->num_cus)), rcap, c->num_cus, stats);
+      t.d_rdt = (RunDesc*)t.alloc(sizeof(RunDesc) * t.rdt_entries());
+    }
     t.h_stage_bytes = sizeof(BHead) + sizeof(BReq) * mr + sizeof(uint64_t) * (mr + 1) +
-                      sizeof(unsigned long long) * t.stat_words();
+                      sizeof(unsigned long long) * t.stat_words() + sizeof(RunDesc) * t.rdt_entries();
     GJ_HIP(hipHostMalloc(&t.h_stage, t.h_stage_bytes, hipHostMallocDefault));
     // capture the level pipeline once; it reads every size from device memory
     GJ_HIP(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
@@ -559,6 +575,27 @@ void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t
     tot += r.len;
   }
   ho[nreq] = tot;
+  unsigned long long* res = (unsigned long long*)(ho + t.max_req + 1);
+  if (t.runs) {
+    // the split of each request's last stage where the run kernels can take
+    // it (static counts only; signed delta seeds keep the per-candidate kernel)
+    RunDesc* hd = (RunDesc*)(res + t.stat_words());
+    memset(hd, 0, sizeof(RunDesc) * (uint64_t)nreq * kStat);
+    for (uint32_t i = 0; i < nreq; ++i) {
+      const ReqSpec& r = specs[i];
+      const int j = r.P.m - 1;
+      RunDesc& rd = hd[(uint64_t)i * kStat + j];
+      if (j < 2 || r.w || !c->run_stage || c->strategy == 1 || !run_desc(hr[i].st[j], rd)) continue;
+      rd.ok = 1;
+      rd.ratio = c->run_ratio;
+      rd.min_work = c->run_min_work;
+      rd.task_work = c->run_task_work;
+      rd.reuse = c->run_reuse;
+      hh->runon[j] = 1;
+    }
+    GJ_HIP(hipMemcpyAsync(t.d_rdt, hd, sizeof(RunDesc) * (uint64_t)nreq * kStat, hipMemcpyHostToDevice,
+                          c->stream));
+  }
   hh->nreq = nreq;
   hh->lin = c->batch_lin;
   hh->claim_words = c->batch_claim_words;
@@ -570,7 +607,6 @@ void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t
   timer.start();
   GJ_HIP(hipGraphLaunch(t.exec, c->stream));
   timer.stop();
-  unsigned long long* res = (unsigned long long*)(ho + t.max_req + 1);
   GJ_HIP(hipMemcpyAsync(res, t.d_stat, t.stat_words() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                         c->stream));
   GJ_HIP(hipMemcpyAsync(hh, t.d_head, sizeof(BHead), hipMemcpyDeviceToHost, c->stream));

@@ -215,6 +215,7 @@ struct gj_ctx {
   uint32_t batch_waves_per_cu = 32; // resident waves per CU of the persistent grids
   uint32_t batch_claim_words = 16;  // words of 64 candidates a wave of the fused propose claims at a time
   uint64_t batch_cap = 1ull << 27;  // prefixes per level of the batched pipeline
+  int batch_run = 1;                 // the batched pipeline's last stages take the run kernels where they apply
   uint64_t batch_fallbacks = 0;     // batches rerun depth-first after a level overflow
   int delta_fused = 1;              // count-only delta queries through the fused pipeline
   uint64_t delta_owner_min = 1ull << 17;  // changes from which triangle-shaped deltas use the owner kernel

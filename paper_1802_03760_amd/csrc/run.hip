@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "batch.h"
 #include "gj_internal.h"
 #include "prim.h"
 #include "run.h"
@@ -66,8 +67,11 @@ __global__ void k_run_heads(const uint32_t* __restrict__ F, uint64_t stride, uin
 
 // rs[run] = its first prefix; rs[runs] = n
 // (also clears the task counter of the counting kernel)
-__global__ void k_run_starts(const uint32_t* __restrict__ head, const uint64_t* __restrict__ hoff, uint64_t n,
-                             uint32_t* __restrict__ rs, unsigned int* __restrict__ counter) {
+// (n: *np when np is not null)
+__global__ void k_run_starts(const uint32_t* __restrict__ head, const uint64_t* __restrict__ hoff, uint64_t n_arg,
+                             const unsigned long long* __restrict__ np, uint32_t* __restrict__ rs,
+                             unsigned int* __restrict__ counter) {
+  const uint64_t n = np ? *np : n_arg;
   uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
   if (blockIdx.x == 0 && threadIdx.x < 2) counter[threadIdx.x] = 0;
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
@@ -84,9 +88,46 @@ __device__ __forceinline__ void atom_row(const StageDesc& d, int a, uint32_t v, 
   len = hi - lo;
 }
 
-// Per run (at its head): the size bound of S (smallest old set), the run's
-// candidates in the count-minimised space, whether it is staged, and its
-// number of tasks (tcnt[head]; 0 elsewhere and for unstaged runs).
+// The plan of the run headed by prefix p (ending before prefix e): the size
+// bound of S (smallest old set), the run's candidates in the count-minimised
+// space, whether it is staged (st) and with which shape (big), its number of
+// tasks (t), and its candidates added to ws by outcome (staged, shared set
+// too large, too little work).
+__device__ __forceinline__ void run_plan_one(const uint32_t* __restrict__ F, uint64_t stride, uint64_t p, uint64_t e,
+                                             const uint64_t* __restrict__ off, const StageDesc& d, const RunDesc& rd,
+                                             bool& st, bool& big, uint32_t& t, uint64_t (&ws)[3]) {
+  uint32_t B = 0xFFFFFFFFu;
+#pragma unroll
+  for (int a = 0; a < kMaxBind; ++a) {
+    if (a < d.k && ((rd.old_mask >> a) & 1)) {
+      uint32_t lo, len;
+      atom_row(d, a, F[(uint64_t)d.col[a] * stride + p], lo, len);
+      B = len < B ? len : B;
+    }
+  }
+  uint64_t W = off[e] - off[p];
+  st = B <= kRunCapBig && W >= rd.min_work && W >= (uint64_t)rd.reuse * B;
+  big = B > kRunCap;
+  t = 0;
+  if (st) {
+    uint64_t per = rd.task_work + 8ull * B * (uint64_t)rd.nold;
+    uint64_t k = (W + per - 1) / per;
+    uint64_t kids = e - p;
+    t = (uint32_t)(k < 1 ? 1 : (k > kids ? kids : k));
+  }
+  ws[st ? 0 : (B > kRunCapBig ? 1 : 2)] += W;
+}
+
+__device__ __forceinline__ void run_plan_sums(const uint64_t (&ws)[3], unsigned long long* __restrict__ wsum) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    uint64_t b = block_sum<kBlock>(ws[i]);
+    if (threadIdx.x == 0 && b) atomicAdd(wsum + i, (unsigned long long)b);
+  }
+}
+
+// Per run (at its head): staged[run], and its number of tasks in the shape's
+// array (tcnt or tcnt_big at the head; 0 elsewhere and for unstaged runs).
 __global__ void k_run_plan(const uint32_t* __restrict__ F, uint64_t stride, uint64_t n,
                            const uint64_t* __restrict__ off, const uint32_t* __restrict__ head,
                            const uint64_t* __restrict__ hoff, const uint32_t* __restrict__ rs, StageDesc d,
@@ -96,46 +137,25 @@ __global__ void k_run_plan(const uint32_t* __restrict__ F, uint64_t stride, uint
   uint64_t ws[3] = {0, 0, 0};
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
     uint32_t t = 0;
-    bool big = false;
+    bool big = false, st = false;
     if (head[p]) {
-      uint64_t rid = hoff[p];
-      uint64_t e = rs[rid + 1];
-      uint32_t B = 0xFFFFFFFFu;
-#pragma unroll
-      for (int a = 0; a < kMaxBind; ++a) {
-        if (a < d.k && ((rd.old_mask >> a) & 1)) {
-          uint32_t lo, len;
-          atom_row(d, a, F[(uint64_t)d.col[a] * stride + p], lo, len);
-          B = len < B ? len : B;
-        }
-      }
-      uint64_t W = off[e] - off[p];
-      bool st = B <= kRunCapBig && W >= rd.min_work && W >= (uint64_t)rd.reuse * B;
-      big = B > kRunCap;
-      if (st) {
-        uint64_t per = rd.task_work + 8ull * B * (uint64_t)rd.nold;
-        uint64_t k = (W + per - 1) / per;
-        uint64_t kids = e - p;
-        t = (uint32_t)(k < 1 ? 1 : (k > kids ? kids : k));
-      }
-      staged[rid] = st ? 1 : 0;
-      // candidates by outcome: staged, shared set too large, too little work
-      ws[st ? 0 : (B > kRunCapBig ? 1 : 2)] += W;
+      uint64_t run = hoff[p];
+      run_plan_one(F, stride, p, rs[run + 1], off, d, rd, st, big, t, ws);
+      staged[run] = st ? 1 : 0;
     }
     tcnt[p] = big ? 0 : t;
     tcnt_big[p] = big ? t : 0;
   }
-#pragma unroll
-  for (int i = 0; i < 3; ++i) {
-    uint64_t b = block_sum<kBlock>(ws[i]);
-    if (threadIdx.x == 0 && b) atomicAdd(wsum + i, (unsigned long long)b);
-  }
+  run_plan_sums(ws, wsum);
 }
 
-// The per-candidate kernel's counts: zero for prefixes of staged runs.
+// The per-candidate kernel's counts: zero for prefixes of staged runs
+// (n: *np when np is not null).
 __global__ void k_run_direct(const uint32_t* __restrict__ head, const uint64_t* __restrict__ hoff,
-                             const uint8_t* __restrict__ staged, uint64_t n, const uint32_t* __restrict__ minc,
+                             const uint8_t* __restrict__ staged, uint64_t n_arg,
+                             const unsigned long long* __restrict__ np, const uint32_t* __restrict__ minc,
                              uint32_t* __restrict__ minc2) {
+  const uint64_t n = np ? *np : n_arg;
   uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
     uint64_t rid = hoff[p] + head[p] - 1;
@@ -308,17 +328,47 @@ __device__ __forceinline__ void member_lockstep(const uint32_t* __restrict__ adj
 }
 
 // ---------------------------------------------------------------- counting kernel
-template <bool SIGNED, bool BIG>
+// A task's stage and run split: the launch's own (one stage of one query),
+// or, in the fused pipeline (FUSED), those of the request its run belongs to.
+template <bool FUSED>
+__device__ __forceinline__ const StageDesc& task_desc(const StageDesc& own, const BReq* __restrict__ R, uint32_t r,
+                                                      int j) {
+  if constexpr (FUSED)
+    return R[r].st[j];
+  else
+    return own;
+}
+template <bool FUSED>
+__device__ __forceinline__ const RunDesc& task_split(const RunDesc& own, const RunDesc* __restrict__ RDt, uint32_t r,
+                                                     int j) {
+  if constexpr (FUSED)
+    return RDt[(uint64_t)r * kStat + j];
+  else
+    return own;
+}
+
+// FUSED: the level's live size is *np, a run's request is rid[head], and
+// each task adds its survivors to that request's match count fcnt, prefix
+// counter fpre of the next level and weight sum fws (static requests only:
+// weight 1); acc is not used.
+template <bool SIGNED, bool BIG, bool FUSED>
 __global__ void __launch_bounds__(RunShape<BIG>::NT) __attribute__((amdgpu_waves_per_eu(4))) k_run_count(const uint32_t* __restrict__ F, uint64_t stride,
-                                                                 uint64_t n, const uint64_t* __restrict__ off,
+                                                                 uint64_t n_arg, const uint64_t* __restrict__ off,
                                                                  const uint64_t* __restrict__ hoff,
                                                                  const uint32_t* __restrict__ rs,
-                                                                 const uint64_t* __restrict__ toff, StageDesc d,
-                                                                 RunDesc rd, const int8_t* __restrict__ wt,
+                                                                 const uint64_t* __restrict__ toff, StageDesc d_own,
+                                                                 RunDesc rd_own, const int8_t* __restrict__ wt,
                                                                  uint32_t* __restrict__ sv_glob,
                                                                  unsigned int* __restrict__ counter,
                                                                  unsigned long long* __restrict__ acc,
-                                                                 unsigned long long* __restrict__ wsum) {
+                                                                 unsigned long long* __restrict__ wsum,
+                                                                 const BReq* __restrict__ R, int jl,
+                                                                 const uint32_t* __restrict__ rid,
+                                                                 const RunDesc* __restrict__ RDt,
+                                                                 const unsigned long long* __restrict__ np,
+                                                                 unsigned long long* __restrict__ fcnt,
+                                                                 unsigned long long* __restrict__ fpre,
+                                                                 unsigned long long* __restrict__ fws) {
   constexpr int kRunNT = RunShape<BIG>::NT;
   constexpr int kRunU = RunShape<BIG>::U;
   constexpr int kRunLogSlots = RunShape<BIG>::LOG_SLOTS;
@@ -338,29 +388,8 @@ __global__ void __launch_bounds__(RunShape<BIG>::NT) __attribute__((amdgpu_waves
   __shared__ uint32_t s_olo[kMaxBind], s_olen[kMaxBind];
   __shared__ uint64_t s_odesc[kMaxBind];
   const int tid = threadIdx.x;
+  const uint64_t n = FUSED ? (uint64_t)*np : n_arg;
   const uint64_t ntask = toff[n];
-  // the new atom's arrays (the index is uniform over the launch)
-  const uint32_t* nrp = nullptr;
-  const uint32_t* nadj = nullptr;
-  const uint64_t* npm = nullptr;
-  const uint64_t* nhd = nullptr;
-  const uint32_t* nhs = nullptr;
-  int ncol = 0;
-  switch (rd.newa) {
-#define GJ_NEWA(A)     \
-  case A:              \
-    nrp = d.rp[A];     \
-    nadj = d.adj[A];   \
-    npm = d.pm[A];     \
-    nhd = d.hd[A];     \
-    nhs = d.hs[A];     \
-    ncol = d.col[A];   \
-    break;
-    GJ_NEWA(0) GJ_NEWA(1) GJ_NEWA(2) GJ_NEWA(3) GJ_NEWA(4) GJ_NEWA(5) GJ_NEWA(6) GJ_NEWA(7)
-#undef GJ_NEWA
-    default:
-      break;
-  }
   uint64_t hits = 0, units = 0, builds = 0, belems = 0;
   int64_t whits = 0;
   uint64_t cached = ~0ull;  // head of the run whose S is in the table
@@ -388,6 +417,31 @@ __global__ void __launch_bounds__(RunShape<BIG>::NT) __attribute__((amdgpu_waves
     __syncthreads();
     if (s_task >= ntask) break;
     const uint64_t head = s_head, cs = s_cs, ce = s_ce;
+    const uint32_t rq = FUSED ? __builtin_amdgcn_readfirstlane(rid[head]) : 0u;
+    const StageDesc& d = task_desc<FUSED>(d_own, R, rq, jl);
+    const RunDesc& rd = task_split<FUSED>(rd_own, RDt, rq, jl);
+    // the new atom's arrays (uniform over the task)
+    const uint32_t* nrp = nullptr;
+    const uint32_t* nadj = nullptr;
+    const uint64_t* npm = nullptr;
+    const uint64_t* nhd = nullptr;
+    const uint32_t* nhs = nullptr;
+    int ncol = 0;
+    switch (rd.newa) {
+#define GJ_NEWA(A)     \
+  case A:              \
+    nrp = d.rp[A];     \
+    nadj = d.adj[A];   \
+    npm = d.pm[A];     \
+    nhd = d.hd[A];     \
+    nhs = d.hs[A];     \
+    ncol = d.col[A];   \
+    break;
+      GJ_NEWA(0) GJ_NEWA(1) GJ_NEWA(2) GJ_NEWA(3) GJ_NEWA(4) GJ_NEWA(5) GJ_NEWA(6) GJ_NEWA(7)
+#undef GJ_NEWA
+      default:
+        break;
+    }
     if (cs < ce && head != cached) {
       // S = the intersection of the old sets of the run: the smallest one
       // streamed, each value tested in the others (their tables or rows)
@@ -572,10 +626,22 @@ __global__ void __launch_bounds__(RunShape<BIG>::NT) __attribute__((amdgpu_waves
       }
       __syncthreads();  // the chunk's arrays are read before the next chunk writes them
     }
+    if (FUSED) {
+      // the task's survivors to its request's counters
+      const uint64_t t = block_sum_lean<kRunNT>(hits, s_scan);
+      if (tid == 0 && t) {
+        atomicAdd(fcnt + rq, (unsigned long long)t);
+        atomicAdd(fpre + (uint64_t)rq * kStat + jl + 1, (unsigned long long)t);
+        atomicAdd(fws + rq, (unsigned long long)t);
+      }
+      hits = 0;
+    }
     __syncthreads();  // every thread has read this task's shared values before thread 0 claims the next
   }
-  uint64_t tsum = block_sum<kRunNT>(hits);
-  if (tid == 0 && tsum) atomicAdd(acc, (unsigned long long)tsum);
+  if (!FUSED) {
+    uint64_t tsum = block_sum<kRunNT>(hits);
+    if (tid == 0 && tsum) atomicAdd(acc, (unsigned long long)tsum);
+  }
   if (tid == 0) {
     atomicAdd(wsum + 3, (unsigned long long)units);
     atomicAdd(wsum + 4, (unsigned long long)builds);
@@ -608,6 +674,14 @@ bool run_desc(const StageDesc& d, RunDesc& rd) {
   return true;
 }
 
+unsigned long long* run_stats_get(gj_ctx* c) {
+  if (!c->run_stats) {
+    c->run_stats = (unsigned long long*)ws_get(c, "run_stats", 8 * sizeof(unsigned long long));
+    GJ_HIP(hipMemsetAsync(c->run_stats, 0, 8 * sizeof(unsigned long long), c->stream));
+  }
+  return c->run_stats;
+}
+
 bool run_count(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const uint64_t* off, const uint32_t* minc,
                const StageDesc& d, RunDesc rd, const int8_t* wt, unsigned long long* acc, uint64_t* off2,
                uint64_t& W2, KernelTimer& timer) {
@@ -628,19 +702,15 @@ bool run_count(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const 
   unsigned int* counter = (unsigned int*)ws_get(c, "run_counter", 16);
   // context-lifetime sums: candidates by plan outcome, and units, builds and
   // built values of the counting kernels (read by gj_ctx_get_option)
-  if (!c->run_stats) {
-    c->run_stats = (unsigned long long*)ws_get(c, "run_stats", 8 * sizeof(unsigned long long));
-    GJ_HIP(hipMemsetAsync(c->run_stats, 0, 8 * sizeof(unsigned long long), c->stream));
-  }
-  unsigned long long* wsum = c->run_stats;
+  unsigned long long* wsum = run_stats_get(c);
   unsigned gr = grid_for(n, kBlock, 1u << 16);
   k_run_heads<<<gr, kBlock, 0, c->stream>>>(F, stride, n, rd.r, head);
   scan_u32_to_u64(c, head, hoff, n);
-  k_run_starts<<<gr, kBlock, 0, c->stream>>>(head, hoff, n, rs, counter);
+  k_run_starts<<<gr, kBlock, 0, c->stream>>>(head, hoff, n, nullptr, rs, counter);
   k_run_plan<<<gr, kBlock, 0, c->stream>>>(F, stride, n, off, head, hoff, rs, d, rd, tcnt, tcnt_big, staged, wsum);
   scan_u32_to_u64(c, tcnt, toff, n);
   scan_u32_to_u64(c, tcnt_big, toff_big, n);
-  k_run_direct<<<gr, kBlock, 0, c->stream>>>(head, hoff, staged, n, minc, minc2);
+  k_run_direct<<<gr, kBlock, 0, c->stream>>>(head, hoff, staged, n, nullptr, minc, minc2);
   scan_u32_to_u64(c, minc2, off2, n);
   GJ_HIP(hipGetLastError());
   uint64_t h[3];
@@ -657,11 +727,11 @@ bool run_count(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const 
     unsigned g = (unsigned)std::min<uint64_t>(h[1], (uint64_t)c->num_cus * 2);
     timer.start();
     if (wt)
-      k_run_count<true, false><<<g, RunShape<false>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff, d, rd, wt,
-                                                                         nullptr, counter, acc, wsum);
+      k_run_count<true, false, false><<<g, RunShape<false>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff, d, rd, wt,
+                                                                         nullptr, counter, acc, wsum, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     else
-      k_run_count<false, false><<<g, RunShape<false>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff, d, rd,
-                                                                          wt, nullptr, counter, acc, wsum);
+      k_run_count<false, false, false><<<g, RunShape<false>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff, d, rd,
+                                                                          wt, nullptr, counter, acc, wsum, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     timer.stop();
     GJ_HIP(hipGetLastError());
   }
@@ -670,17 +740,147 @@ bool run_count(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const 
     uint32_t* sv = (uint32_t*)ws_get(c, "run_sv", (uint64_t)g * kRunCapBig * sizeof(uint32_t));
     timer.start();
     if (wt)
-      k_run_count<true, true><<<g, RunShape<true>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff_big, d, rd,
-                                                                       wt, sv, counter + 1, acc, wsum);
+      k_run_count<true, true, false><<<g, RunShape<true>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff_big, d, rd,
+                                                                       wt, sv, counter + 1, acc, wsum, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     else
-      k_run_count<false, true><<<g, RunShape<true>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff_big, d, rd,
-                                                                        wt, sv, counter + 1, acc, wsum);
+      k_run_count<false, true, false><<<g, RunShape<true>::NT, 0, c->stream>>>(F, stride, n, off, hoff, rs, toff_big, d, rd,
+                                                                        wt, sv, counter + 1, acc, wsum, nullptr, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     timer.stop();
     GJ_HIP(hipGetLastError());
   }
   c->run_tasks += h[1] + h[2];
   c->run_tasks_big += h[2];
   return true;
+}
+
+// ---------------------------------------------------------------- fused pipeline
+// Level j of the fused pipeline holds the prefixes of every request, each
+// tagged with its request (rid); a request's stage and run split come from
+// the request table R and the split table RDt (ok = 0: the request's
+// prefixes stay with the per-candidate kernel).  Every size is read from
+// device memory, so the launches below can be captured once and replayed.
+
+// the live size the run kernels take at level j: 0 where the host left the
+// level off or where it holds more than rcap prefixes (the run buffers' size)
+__global__ void k_runf_setn(BHead* __restrict__ H, int j, uint64_t cap, uint64_t rcap) {
+  if (threadIdx.x == 0) {
+    const uint64_t nl = H->nlev[j] < cap ? H->nlev[j] : cap;
+    H->nrun[j] = H->runon[j] && nl <= rcap ? nl : 0ull;
+  }
+}
+
+// head[p] = 1 where a run starts: a request's first prefix, or, for a
+// request that takes the run kernels, a key column that differs from p - 1
+// (a request left to the per-candidate kernel is one run per stretch)
+__global__ void k_runf_heads(const uint32_t* __restrict__ F, uint64_t stride, const unsigned long long* __restrict__ np,
+                             const uint32_t* __restrict__ rid, const RunDesc* __restrict__ RDt, int j,
+                             uint32_t* __restrict__ head) {
+  const uint64_t n = *np;
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
+    const uint32_t r = rid[p];
+    uint32_t h = p == 0 || rid[p - 1] != r;
+    if (!h) {
+      const RunDesc& rd = RDt[(uint64_t)r * kStat + j];
+      if (rd.ok)
+        for (int c = 0; c < rd.r && !h; ++c) h = F[(uint64_t)c * stride + p] != F[(uint64_t)c * stride + p - 1];
+    }
+    head[p] = h;
+  }
+}
+
+// k_run_plan over the level, each run planned with its request's stage
+__global__ void k_runf_plan(const uint32_t* __restrict__ F, uint64_t stride, const unsigned long long* __restrict__ np,
+                            const uint64_t* __restrict__ off, const uint32_t* __restrict__ head,
+                            const uint64_t* __restrict__ hoff, const uint32_t* __restrict__ rs,
+                            const BReq* __restrict__ R, const RunDesc* __restrict__ RDt,
+                            const uint32_t* __restrict__ rid, int j, uint32_t* __restrict__ tcnt,
+                            uint32_t* __restrict__ tcnt_big, uint8_t* __restrict__ staged,
+                            unsigned long long* __restrict__ wsum) {
+  const uint64_t n = *np;
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t ws[3] = {0, 0, 0};
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gs) {
+    uint32_t t = 0;
+    bool big = false, st = false;
+    if (head[p]) {
+      const uint64_t run = hoff[p];
+      const uint32_t r = rid[p];
+      const RunDesc& rd = RDt[(uint64_t)r * kStat + j];
+      if (rd.ok) run_plan_one(F, stride, p, rs[run + 1], off, R[r].st[j], rd, st, big, t, ws);
+      staged[run] = st ? 1 : 0;
+    }
+    tcnt[p] = big ? 0 : t;
+    tcnt_big[p] = big ? t : 0;
+  }
+  run_plan_sums(ws, wsum);
+}
+
+namespace {
+constexpr uint64_t kFusedAlign = 256;
+uint64_t fused_round(uint64_t b) { return (b + kFusedAlign - 1) / kFusedAlign * kFusedAlign; }
+}  // namespace
+
+uint64_t run_fused_bytes(uint64_t cap, int num_cus) {
+  const uint64_t n1 = cap + 1;
+  return 5 * fused_round(n1 * sizeof(uint32_t)) + 4 * fused_round(n1 * sizeof(uint64_t)) + fused_round(n1) +
+         fused_round(2 * sizeof(unsigned int)) + fused_round((uint64_t)num_cus * kRunCapBig * sizeof(uint32_t));
+}
+
+void run_fused_carve(RunFusedBufs& b, void* base, uint64_t cap, int num_cus, unsigned long long* stats) {
+  const uint64_t n1 = cap + 1;
+  char* q = (char*)base;
+  auto take = [&](uint64_t bytes) {
+    char* r = q;
+    q += fused_round(bytes);
+    return (void*)r;
+  };
+  b.cap = cap;
+  b.num_cus = num_cus;
+  b.head = (uint32_t*)take(n1 * sizeof(uint32_t));
+  b.rs = (uint32_t*)take(n1 * sizeof(uint32_t));
+  b.tcnt = (uint32_t*)take(n1 * sizeof(uint32_t));
+  b.tcnt_big = (uint32_t*)take(n1 * sizeof(uint32_t));
+  b.minc2 = (uint32_t*)take(n1 * sizeof(uint32_t));
+  b.hoff = (uint64_t*)take(n1 * sizeof(uint64_t));
+  b.toff = (uint64_t*)take(n1 * sizeof(uint64_t));
+  b.toff_big = (uint64_t*)take(n1 * sizeof(uint64_t));
+  b.off2 = (uint64_t*)take(n1 * sizeof(uint64_t));
+  b.staged = (uint8_t*)take(n1);
+  b.counter = (unsigned int*)take(2 * sizeof(unsigned int));
+  b.sv = (uint32_t*)take((uint64_t)num_cus * kRunCapBig * sizeof(uint32_t));
+  b.stats = stats;
+}
+
+void run_fused_level(hipStream_t st, const RunFusedBufs& b, const BReq* R, const RunDesc* RDt, BHead* H, int j,
+                     const uint32_t* F, const uint32_t* rid, uint64_t cap, const uint64_t* off,
+                     const uint32_t* minc, uint64_t* part, uint64_t* part_off, unsigned long long* cnt,
+                     unsigned long long* pre, unsigned long long* wsum) {
+  GJ_CHECK(b.cap <= cap, GJ_EINVAL, "run buffers larger than the level capacity");
+  const unsigned long long* np = &H->nrun[j];
+  const uint64_t rc = b.cap;
+  const unsigned gr = (unsigned)b.num_cus * 8;  // grid-stride over the live level
+  k_runf_setn<<<1, 64, 0, st>>>(H, j, cap, rc);
+  k_runf_heads<<<gr, kBlock, 0, st>>>(F, cap, np, rid, RDt, j, b.head);
+  bt_scan_n(st, b.head, np, rc, part, part_off, b.hoff);
+  k_run_starts<<<gr, kBlock, 0, st>>>(b.head, b.hoff, 0, np, b.rs, b.counter);
+  k_runf_plan<<<gr, kBlock, 0, st>>>(F, cap, np, off, b.head, b.hoff, b.rs, R, RDt, rid, j, b.tcnt, b.tcnt_big,
+                                     b.staged, b.stats);
+  bt_scan_n(st, b.tcnt, np, rc, part, part_off, b.toff);
+  bt_scan_n(st, b.tcnt_big, np, rc, part, part_off, b.toff_big);
+  k_run_direct<<<gr, kBlock, 0, st>>>(b.head, b.hoff, b.staged, 0, np, minc, b.minc2);
+  bt_scan_n(st, b.minc2, np, rc, part, part_off, b.off2);
+  const StageDesc d0{};
+  const RunDesc rd0{};
+  // a fixed grid (idle workgroups exit at once): two small-shape workgroups
+  // per CU, one large-shape one
+  k_run_count<false, false, true><<<(unsigned)b.num_cus * 2, RunShape<false>::NT, 0, st>>>(
+      F, cap, 0, off, b.hoff, b.rs, b.toff, d0, rd0, nullptr, nullptr, b.counter, nullptr, b.stats, R, j, rid, RDt,
+      np, cnt, pre, wsum);
+  k_run_count<false, true, true><<<(unsigned)b.num_cus, RunShape<true>::NT, 0, st>>>(
+      F, cap, 0, off, b.hoff, b.rs, b.toff_big, d0, rd0, nullptr, b.sv, b.counter + 1, nullptr, b.stats, R, j, rid,
+      RDt, np, cnt, pre, wsum);
+  GJ_HIP(hipGetLastError());
 }
 
 }  // namespace gj

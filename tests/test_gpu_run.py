@@ -232,3 +232,75 @@ def test_declined_stages(gj):
     for q in (Q.TRIANGLE, Q.CLIQUE4, Q.DIAMOND):
         check(gj, c, G, O, q)
     assert c.get_option("run_declined") > 0 and c.get_option("run_tasks") == 0
+
+
+def batch_requests(gj, c, E, rng, nreq, names, widths):
+    qs = {k: gj.Query(c, *Q.ALL[k]) for k in names}
+    reqs, specs = [], []
+    for i in range(nreq):
+        k = names[i % len(names)]
+        lo = 0 if i < len(names) else int(rng.integers(0, E))  # the first of each query at the hub rows
+        w = int(rng.choice(widths))
+        reqs.append((qs[k], lo, min(lo + w, E)))
+        specs.append((Q.ALL[k], lo, min(lo + w, E)))
+    return reqs, specs
+
+
+@pytest.mark.parametrize("task_work,ratio", [(1, 8), (1 << 15, 2), (64, 0)])
+def test_batched_pipeline_runs(gj, task_work, ratio):
+    """The fused pipeline's last stages grouped by runs (batch_run): every
+    request's count and counters equal the oracle's over three replays of
+    the captured pipeline with different request mixes (queries ending at
+    different levels share them), and the run kernels took part."""
+    c = run_ctx(gj, task_work, ratio)
+    c.set_option("run_reuse", 1)
+    c.set_option("batch_heavy", 0)  # every request fused
+    assert c.get_option("batch_run") == 1
+    src, dst = synth.rmat_draws(12, seed=31)
+    n = 1 << 12
+    G, O = gj.Graph(c, src, dst, n), oracle.Graph(n, src, dst)
+    E = O.num_edges
+    rng = np.random.default_rng(task_work + ratio)
+    names = ["clique4", "diamond", "triangle", "cycle4", "paper_diamond", "cyclic_triangle", "house"]
+    b0 = c.get_option("run_builds")
+    for rep in range(3):
+        reqs, specs = batch_requests(gj, c, E, rng, 24 + 5 * rep, names[rep:] + names[:rep], [0, 1, 40, 400, 2500])
+        counts, stats = gj.run_batch(c, G, reqs)
+        assert c.get_option("batch_fallbacks") == 0
+        for (q, lo, hi), cnt, st in zip(specs, counts, stats):
+            ref = oracle.run(O, q, seed_lo=lo, seed_hi=hi, threads=8)
+            assert (cnt, st["prefixes"], st["extensions"]) == (ref["matches"], ref["prefixes"], ref["extensions"]), \
+                (rep, q, lo, hi)
+    assert c.get_option("run_builds") > b0
+
+
+def test_batched_runs_off_equals_on(gj):
+    """batch_run 0 and 1 give the same counts and counters at the default
+    run sizes, with inequalities on the symmetric graph among the requests;
+    switching the option re-captures the pipeline."""
+    src, dst = synth.rmat_draws(13, seed=32)
+    n = 1 << 13
+    c = gj.Context(0)
+    c.set_option("batch_heavy", 0)
+    G = gj.Graph(c, src, dst, n)
+    Gu = gj.Graph(c, src, dst, n, undirected=True)
+    E = G.info()["edges"]
+    rng = np.random.default_rng(33)
+    reqs, _ = batch_requests(gj, c, E, rng, 30, ["clique4", "diamond", "triangle", "cycle4"], [100, 3000])
+    qs = [gj.Query(c, *Q.with_less(Q.ALL[k], Q.SYM_LESS[k][0])) for k in ("clique4", "triangle")]
+    Eu = Gu.info()["edges"]
+    ureqs = [(qs[i % 2], lo, lo + 3000) for i, lo in enumerate(range(0, Eu, Eu // 6))]
+    def key(out):
+        counts, stats = out
+        return counts, [(s["matches"], s["prefixes"], s["extensions"]) for s in stats]
+
+    res = {}
+    for on in (1, 0, 1):
+        c.set_option("batch_run", on)
+        a = key(gj.run_batch(c, G, reqs))
+        b = key(gj.run_batch(c, Gu, ureqs))
+        if on in res:
+            assert res[on] == (a, b)
+        res[on] = (a, b)
+    assert res[0] == res[1]
+    assert sum(res[1][0][0]) > 0 and sum(res[1][1][0]) > 0
