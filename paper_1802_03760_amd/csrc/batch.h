@@ -46,6 +46,10 @@ struct BHead {
   // the host), and the live size the run kernels take there (0 elsewhere)
   uint32_t runon[GJ_MAX_ATTRS + 1];
   unsigned long long nrun[GJ_MAX_ATTRS + 1];
+  // level j regrouped by parent prefix before its stage: its live size and
+  // that of level j - 1 (both 0 where it is not)
+  unsigned long long nreg[GJ_MAX_ATTRS + 1];
+  unsigned long long nregp[GJ_MAX_ATTRS + 1];
 };
 
 

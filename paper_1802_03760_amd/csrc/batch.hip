@@ -220,6 +220,7 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
                                                        const uint8_t* __restrict__ mini, const int8_t* __restrict__ Fw,
                                                        uint32_t* __restrict__ G, uint32_t* __restrict__ grid_,
                                                        int8_t* __restrict__ Gw, uint64_t gcap,
+                                                       uint32_t* __restrict__ par, uint64_t par_cap,
                                                        unsigned long long* __restrict__ cnt,
                                                        unsigned long long* __restrict__ pre,
                                                        unsigned long long* __restrict__ wsum) {
@@ -311,6 +312,7 @@ __global__ void __launch_bounds__(kBlock) k_bt_propose(const BReq* __restrict__ 
         G[(uint64_t)j * gcap + pos] = e;
         grid_[pos] = r;
         Gw[pos] = w;
+        if (pos < par_cap) par[pos] = (uint32_t)p;
       } else {
         atomicOr(&H->overflow, 1u);
       }
@@ -418,6 +420,109 @@ void bt_scan(hipStream_t st, const uint32_t* in, const BHead* H, int j, uint64_t
   bt_scan_n(st, in, &H->nlev[j], cap, part, part_off, out);
 }
 
+// ---------------------------------------------------------------- regrouping by parent
+// The fused propose kernel writes a level in the order its waves reserve
+// space, so the children of one prefix arrive in pieces of at most 64 (one
+// word of candidates each) spread over the level.  Before a level whose last
+// stage takes the run kernels, a counting sort by parent index puts the
+// children of every prefix side by side (in arbitrary order among
+// themselves), so the runs, whose key columns are all parent columns, come
+// whole.  Levels or parent levels above the buffers' size keep their order.
+
+__global__ void k_bt_reg_setn(BHead* __restrict__ H, int j, uint64_t cap, uint64_t rcap) {
+  if (threadIdx.x == 0) {
+    const uint64_t nc = H->nlev[j] < cap ? H->nlev[j] : cap;
+    const uint64_t np = H->nlev[j - 1] < cap ? H->nlev[j - 1] : cap;
+    const bool on = H->runon[j] && nc <= rcap && np <= rcap;
+    H->nreg[j] = on ? nc : 0ull;
+    H->nregp[j] = on ? np : 0ull;
+  }
+}
+
+__global__ void k_bt_reg_clear(uint32_t* __restrict__ hist, const unsigned long long* __restrict__ np) {
+  const uint64_t n = *np;
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) hist[i] = 0;
+}
+
+// children per parent: one atomic per distinct parent in a wave (a wave's
+// lanes hold a few pieces, each of one parent)
+__global__ void __launch_bounds__(kBlock) k_bt_reg_hist(const uint32_t* __restrict__ par,
+                                                        const unsigned long long* __restrict__ nc,
+                                                        uint32_t* __restrict__ hist) {
+  const uint64_t n = *nc;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t base = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; base < n;
+       base += nwaves * 64) {
+    const uint64_t i = base + lane_id();
+    const bool valid = i < n;
+    const uint32_t k = valid ? par[i] : 0u;
+    bool todo = valid;
+    while (__ballot(todo)) {
+      const uint32_t kc = first_pending(k, todo);
+      const bool mine = todo && k == kc;
+      const uint64_t mm = __ballot(mine);
+      if (lane_id() == __ffsll((unsigned long long)mm) - 1) atomicAdd(&hist[kc], (uint32_t)__popcll(mm));
+      todo = todo && !mine;
+    }
+  }
+}
+
+// Each child to its slot in its parent's range (poff[parent] + a slot taken
+// by counting the parent's histogram entry down, once per distinct parent in
+// a wave): columns, request and weight into the staging buffers.
+__global__ void __launch_bounds__(kBlock) k_bt_reg_scatter(const uint32_t* __restrict__ par,
+                                                           const unsigned long long* __restrict__ nc,
+                                                           uint32_t* __restrict__ hist,
+                                                           const uint64_t* __restrict__ poff, int j,
+                                                           const uint32_t* __restrict__ F, uint64_t cap,
+                                                           const uint32_t* __restrict__ rid,
+                                                           const int8_t* __restrict__ Fw,
+                                                           uint32_t* __restrict__ T, uint64_t rcap,
+                                                           uint32_t* __restrict__ trid, int8_t* __restrict__ tw) {
+  const uint64_t n = *nc;
+  const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  for (uint64_t base = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; base < n;
+       base += nwaves * 64) {
+    const uint64_t i = base + lane_id();
+    const bool valid = i < n;
+    const uint32_t k = valid ? par[i] : 0u;
+    uint32_t slot = 0;
+    bool todo = valid;
+    while (__ballot(todo)) {
+      const uint32_t kc = first_pending(k, todo);
+      const bool mine = todo && k == kc;
+      const uint64_t mm = __ballot(mine);
+      const int leader = __ffsll((unsigned long long)mm) - 1;
+      const uint32_t cntk = (uint32_t)__popcll(mm);
+      uint32_t top = 0;
+      if (lane_id() == leader) top = atomicSub(&hist[kc], cntk);
+      top = __shfl(top, leader, 64);
+      if (mine) slot = top - cntk + (uint32_t)__popcll(mm & lanemask_lt());
+      todo = todo && !mine;
+    }
+    if (valid) {
+      const uint64_t pos = poff[k] + slot;
+      for (int c = 0; c < j; ++c) T[(uint64_t)c * rcap + pos] = F[(uint64_t)c * cap + i];
+      trid[pos] = rid[i];
+      tw[pos] = Fw[i];
+    }
+  }
+}
+
+__global__ void k_bt_reg_copy(const unsigned long long* __restrict__ nc, int j, const uint32_t* __restrict__ T,
+                              uint64_t rcap, const uint32_t* __restrict__ trid, const int8_t* __restrict__ tw,
+                              uint32_t* __restrict__ F, uint64_t cap, uint32_t* __restrict__ rid,
+                              int8_t* __restrict__ Fw) {
+  const uint64_t n = *nc;
+  uint64_t gs = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gs) {
+    for (int c = 0; c < j; ++c) F[(uint64_t)c * cap + i] = T[(uint64_t)c * rcap + i];
+    rid[i] = trid[i];
+    Fw[i] = tw[i];
+  }
+}
+
 // ---------------------------------------------------------------- executor
 struct BatchExec::Impl {
   uint32_t max_req = 0;
@@ -441,6 +546,16 @@ struct BatchExec::Impl {
   bool runs = false;
   RunFusedBufs rb;
   RunDesc* d_rdt = nullptr;
+  // regrouping by parent (levels of at most rcap prefixes): the parent index
+  // of each prefix of the level being written, the per-parent histogram and
+  // offsets, and staging for the regrouped level (columns stride rcap)
+  uint64_t rcap = 0;
+  uint32_t* par = nullptr;
+  uint32_t* rg_hist = nullptr;
+  uint64_t* rg_off = nullptr;
+  uint32_t* rg_F = nullptr;
+  uint32_t* rg_rid = nullptr;
+  int8_t* rg_w = nullptr;
   void* h_stage = nullptr;  // pinned staging for the request table and results
   size_t h_stage_bytes = 0;
   hipGraph_t graph = nullptr;
@@ -478,6 +593,21 @@ static void enqueue(gj_ctx* c, BatchExec::Impl& s, unsigned grid) {
   k_bt_seed<<<grid, kBlock, 0, st>>>(s.d_req, s.d_roff, s.d_head, s.F[2], s.rid[2], s.W[2], s.cap, s.cnt(),
                                      s.pre(), s.wsum());
   for (int j = 2; j < s.max_m; ++j) {
+    if (s.runs && j >= 3) {
+      // children of one prefix side by side for the run kernels (a no-op
+      // where the host left level j off or it is too large)
+      const unsigned gr = (unsigned)c->num_cus * 8;
+      const unsigned long long* nc = &s.d_head->nreg[j];
+      const unsigned long long* np = &s.d_head->nregp[j];
+      k_bt_reg_setn<<<1, 64, 0, st>>>(s.d_head, j, s.cap, s.rcap);
+      k_bt_reg_clear<<<gr, kBlock, 0, st>>>(s.rg_hist, np);
+      k_bt_reg_hist<<<gr, kBlock, 0, st>>>(s.par, nc, s.rg_hist);
+      bt_scan_n(st, s.rg_hist, np, s.rcap, s.part, s.part_off, s.rg_off);
+      k_bt_reg_scatter<<<gr, kBlock, 0, st>>>(s.par, nc, s.rg_hist, s.rg_off, j, s.F[j], s.cap, s.rid[j], s.W[j],
+                                              s.rg_F, s.rcap, s.rg_rid, s.rg_w);
+      k_bt_reg_copy<<<gr, kBlock, 0, st>>>(nc, j, s.rg_F, s.rcap, s.rg_rid, s.rg_w, s.F[j], s.cap, s.rid[j],
+                                           s.W[j]);
+    }
     // latency-bound, no dynamic claiming: oversubscribe (idle blocks exit at once)
     k_bt_count_min<<<grid_for(s.cap, kBlock * 4, 8192), kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j],
                                                                          s.cap, s.minc[j], s.mini[j], s.ext());
@@ -489,8 +619,9 @@ static void enqueue(gj_ctx* c, BatchExec::Impl& s, unsigned grid) {
     k_bt_propose<<<grid, kBlock, 0, st>>>(s.d_req, j, s.d_head, s.F[j], s.rid[j], s.cap, s.off[j],
                                          s.runs ? s.rb.off2 : s.off[j], s.mini[j], s.W[j],
                                          last ? nullptr : s.F[j + 1], last ? nullptr : s.rid[j + 1],
-                                         last ? nullptr : s.W[j + 1], last ? 0 : s.cap, s.cnt(), s.pre(),
-                                         s.wsum());
+                                         last ? nullptr : s.W[j + 1], last ? 0 : s.cap,
+                                         last || !s.runs ? nullptr : s.par, last || !s.runs ? 0 : s.rcap, s.cnt(),
+                                         s.pre(), s.wsum());
   }
 }
 
@@ -542,6 +673,15 @@ void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t
       unsigned long long* stats = run_stats_get(c);  // cleared here, outside the capture
       run_fused_carve(t.rb, t.alloc(run_fused_bytes(rcap, c->num_cus)), rcap, c->num_cus, stats);
       t.d_rdt = (RunDesc*)t.alloc(sizeof(RunDesc) * t.rdt_entries());
+      t.rcap = rcap;
+      if (mm > 3) {
+        t.par = (uint32_t*)t.alloc(rcap * sizeof(uint32_t));
+        t.rg_hist = (uint32_t*)t.alloc((rcap + 1) * sizeof(uint32_t));
+        t.rg_off = (uint64_t*)t.alloc((rcap + 1) * sizeof(uint64_t));
+        t.rg_F = (uint32_t*)t.alloc(rcap * (mm - 1) * sizeof(uint32_t));
+        t.rg_rid = (uint32_t*)t.alloc(rcap * sizeof(uint32_t));
+        t.rg_w = (int8_t*)t.alloc(rcap);
+      }
     }
     t.h_stage_bytes = sizeof(BHead) + sizeof(BReq) * mr + sizeof(uint64_t) * (mr + 1) +
                       sizeof(unsigned long long) * t.stat_words() + sizeof(RunDesc) * t.rdt_entries();
