@@ -81,11 +81,67 @@ __device__ __forceinline__ bool ineq3(const EdgeIneq& q, int j, uint32_t v, uint
   return ok;
 }
 
+// The values [lb, ub) the inequalities allow at position j given prefix
+// columns c0, c1, c2 (ids are below 2^32 - 1, so ub = 2^32 - 1 bounds
+// nothing and c + 1 does not wrap).
+__device__ __forceinline__ void ineq_range3(const EdgeIneq& q, int j, uint32_t c0, uint32_t c1, uint32_t c2,
+                                            uint32_t& lb, uint32_t& ub) {
+  const uint32_t a = q.above[j], b = q.below[j];
+  lb = 0;
+  ub = 0xFFFFFFFFu;
+  if (a & 1) lb = max(lb, c0 + 1);
+  if (a & 2) lb = max(lb, c1 + 1);
+  if (a & 4) lb = max(lb, c2 + 1);
+  if (b & 1) ub = min(ub, c0);
+  if (b & 2) ub = min(ub, c1);
+  if (b & 4) ub = min(ub, c2);
+}
+
+// first i in [0, n) with a[i] >= x (a sorted, in LDS), else n
+__device__ __forceinline__ uint32_t lds_first_ge(const uint32_t* a, uint32_t n, uint32_t x) {
+  uint32_t lo = 0;
+  while (n > 0) {
+    const uint32_t half = n >> 1;
+    if (a[lo + half] < x) {
+      lo += half + 1;
+      n -= half + 1;
+    } else {
+      n = half;
+    }
+  }
+  return lo;
+}
+
+// With inequalities on a3 (INEQ): S and out(a2) are both sorted, so the
+// values a3 may take form one range of each, found by binary search per a2;
+// a2's work is the smaller range, and rel records which side it walks and
+// where that range starts (bit 31 set: out(a2) from its row start + the low
+// bits, probing S; clear: S from that index, probing out(a2)).  Counters
+// stay those of the whole sets (the depth-first evaluation's).
+__device__ __forceinline__ uint32_t a3_range(const uint32_t* __restrict__ col, uint32_t b2, uint32_t d2,
+                                             const uint32_t* S, uint32_t nS, uint32_t lb, uint32_t ub,
+                                             uint32_t& rel) {
+  if (lb >= ub) {
+    rel = 0;
+    return 0;
+  }
+  const uint32_t rl = lower_bound_u32(col, b2, b2 + d2, lb);
+  const uint32_t rh = ub == 0xFFFFFFFFu ? b2 + d2 : lower_bound_u32(col, rl, b2 + d2, ub);
+  const uint32_t sl = lds_first_ge(S, nS, lb);
+  const uint32_t sh = ub == 0xFFFFFFFFu ? nS : sl + lds_first_ge(S + sl, nS - sl, ub);
+  if (rh - rl < sh - sl) {
+    rel = 0x80000000u | (rl - b2);
+    return rh - rl;
+  }
+  rel = sl;
+  return sh - sl;
+}
+
 // SHAPE 0, the transitive 4-clique: S = L = out(a0) & out(a1) and a2 ranges
 // over L.  SHAPE 1, the diamond edge(a0,a1), edge(a0,a2), edge(a1,a3),
 // edge(a2,a3): S = out(a1) and a2 ranges over out(a0).  Either way a3 ranges
 // over S & out(a2), and S sits in the wave's LDS share.
-template <int SHAPE>
+template <int SHAPE, bool INEQ>
 __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restrict__ rp,
                                                          const uint32_t* __restrict__ col,
                                                          const uint32_t* __restrict__ row, uint64_t m,
@@ -94,9 +150,11 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
                                                          unsigned long long* __restrict__ acc, EdgeIneq iq) {
   __shared__ uint32_t Ls[kCqWaves][kCqCap];
   __shared__ uint32_t Ws[kCqWaves][kCqCap + 1];
+  __shared__ uint32_t Rs[kCqWaves][INEQ ? kCqCap : 1];  // per a2: the side and start of its a3 range
   const int lane = lane_id();
   uint32_t* S = Ls[wave_id()];
   uint32_t* Wp = Ws[wave_id()];
+  uint32_t* Rel = Rs[wave_id()];
   uint64_t matches = 0, pre2 = 0, pre3 = 0, ext2 = 0, ext3 = 0;
   for (;;) {
     unsigned long long base = 0;
@@ -155,8 +213,15 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
           if (i < cn) {
             uint32_t a2 = SHAPE == 0 ? S[c0 + i] : col[b0 + c0 + i];
             if (ineq3(iq, 2, a2, x0, x1, 0)) {
-              uint32_t d2 = rp[a2 + 1] - rp[a2];
-              w = d2 < nS ? d2 : nS;
+              uint32_t b2 = rp[a2], d2 = rp[a2 + 1] - b2;
+              if (INEQ) {
+                uint32_t lb, ub, rel;
+                ineq_range3(iq, 3, x0, x1, a2, lb, ub);
+                w = a3_range(col, b2, d2, S, nS, lb, ub, rel);
+                Rel[i] = rel;
+              } else {
+                w = d2 < nS ? d2 : nS;
+              }
               uint32_t lim = SHAPE == 0 ? d01 : d1;  // count-minimisation of the last stage
               ext3 += d2 < lim ? d2 : lim;
               pre3 += 1;
@@ -177,9 +242,17 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
             uint32_t t = q - Wp[i];
             uint32_t a2 = SHAPE == 0 ? S[c0 + i] : col[b0 + c0 + i];
             uint32_t b2 = rp[a2], d2 = rp[a2 + 1] - b2;
-            uint32_t a3 = d2 < nS ? col[b2 + t] : S[t];  // t < d2, or t < nS
-            found = d2 < nS ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
-            found = found && ineq3(iq, 3, a3, x0, x1, a2);
+            if (INEQ) {
+              const uint32_t rel = Rel[i];
+              const bool row_side = (rel >> 31) != 0;
+              uint32_t a3 = row_side ? col[b2 + (rel & 0x7FFFFFFFu) + t] : S[rel + t];
+              found = row_side ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
+              found = found && ineq3(iq, 3, a3, x0, x1, a2);
+            } else {
+              uint32_t a3 = d2 < nS ? col[b2 + t] : S[t];  // t < d2, or t < nS
+              found = d2 < nS ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
+              found = found && ineq3(iq, 3, a3, x0, x1, a2);
+            }
           }
           matches += found ? 1 : 0;
         }
@@ -208,7 +281,7 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
 constexpr uint32_t kCqCapWg = 16384;
 constexpr uint32_t kCqOffWg = 1024;
 
-template <int SHAPE>
+template <int SHAPE, bool INEQ>
 __global__ void __launch_bounds__(kBlock) k_edge4_wg(const uint32_t* __restrict__ rp,
                                                      const uint32_t* __restrict__ col,
                                                      const uint32_t* __restrict__ row, const uint32_t* __restrict__ ids,
@@ -217,6 +290,7 @@ __global__ void __launch_bounds__(kBlock) k_edge4_wg(const uint32_t* __restrict_
                                                      EdgeIneq iq) {
   __shared__ uint32_t S[kCqCapWg];
   __shared__ uint32_t Wp[kCqOffWg + 1];
+  __shared__ uint32_t Rel[INEQ ? kCqOffWg : 1];  // per a2: the side and start of its a3 range
   __shared__ unsigned long long next;
   const uint32_t tid = threadIdx.x;
   uint64_t matches = 0, pre2 = 0, pre3 = 0, ext2 = 0, ext3 = 0;
@@ -270,8 +344,15 @@ __global__ void __launch_bounds__(kBlock) k_edge4_wg(const uint32_t* __restrict_
         if (i < cn) {
           uint32_t a2 = SHAPE == 0 ? S[c0 + i] : col[b0 + c0 + i];
           if (ineq3(iq, 2, a2, x0, x1, 0)) {
-            uint32_t d2 = rp[a2 + 1] - rp[a2];
-            w = d2 < nS ? d2 : nS;
+            uint32_t b2 = rp[a2], d2 = rp[a2 + 1] - b2;
+            if (INEQ) {
+              uint32_t lb, ub, rel;
+              ineq_range3(iq, 3, x0, x1, a2, lb, ub);
+              w = a3_range(col, b2, d2, S, nS, lb, ub, rel);
+              Rel[i] = rel;
+            } else {
+              w = d2 < nS ? d2 : nS;
+            }
             uint32_t lim = SHAPE == 0 ? d01 : d1;
             ext3 += d2 < lim ? d2 : lim;
             pre3 += 1;
@@ -291,8 +372,17 @@ __global__ void __launch_bounds__(kBlock) k_edge4_wg(const uint32_t* __restrict_
           uint32_t t = q - Wp[i];
           uint32_t a2 = SHAPE == 0 ? S[c0 + i] : col[b0 + c0 + i];
           uint32_t b2 = rp[a2], d2 = rp[a2 + 1] - b2;
-          uint32_t a3 = d2 < nS ? col[b2 + t] : S[t];
-          bool found = d2 < nS ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
+          bool found;
+          uint32_t a3;
+          if (INEQ) {
+            const uint32_t rel = Rel[i];
+            const bool row_side = (rel >> 31) != 0;
+            a3 = row_side ? col[b2 + (rel & 0x7FFFFFFFu) + t] : S[rel + t];
+            found = row_side ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
+          } else {
+            a3 = d2 < nS ? col[b2 + t] : S[t];
+            found = d2 < nS ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
+          }
           matches += (found && ineq3(iq, 3, a3, x0, x1, a2)) ? 1 : 0;
         }
       }
@@ -329,12 +419,19 @@ void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4]
     iq.above[j] = above[j];
     iq.below[j] = below[j];
   }
-  unsigned grid = (unsigned)c->num_cus * 4;  // 4 workgroups of 4 waves per CU (32 KiB LDS each)
+  // inequalities on a3: its ranges in S and out(a2) narrowed per a2 (48 KiB
+  // of LDS per workgroup, so 3 per CU)
+  const bool ineq = (above[3] | below[3]) != 0;
+  unsigned grid = (unsigned)c->num_cus * (ineq ? 3 : 4);  // workgroups of 4 waves, 32 KiB of LDS each without
   timer.start();
-  if (v.m && shape == 0)
-    k_edge4<0><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
-  if (v.m && shape == 1)
-    k_edge4<1><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
+  if (v.m && shape == 0 && !ineq)
+    k_edge4<0, false><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
+  if (v.m && shape == 0 && ineq)
+    k_edge4<0, true><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
+  if (v.m && shape == 1 && !ineq)
+    k_edge4<1, false><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
+  if (v.m && shape == 1 && ineq)
+    k_edge4<1, true><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
   timer.stop();
   GJ_HIP(hipGetLastError());
   unsigned long long n1 = 0;
@@ -344,9 +441,12 @@ void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4]
   // the depth-first path for the diamond, whose overflowing seeds go there)
   if (n1 && shape == 0) {
     uint32_t* ovf2 = (uint32_t*)ws_get(c, "cq_ovf2", (n1 + 1) * sizeof(uint32_t));
-    unsigned grid2 = (unsigned)c->num_cus * 2;  // 2 workgroups per CU (68 KiB of LDS each)
+    unsigned grid2 = (unsigned)c->num_cus * 2;  // 2 workgroups per CU (68 KiB of LDS each, 72 KiB with INEQ)
     timer.start();
-    k_edge4_wg<0><<<grid2, kBlock, 0, c->stream>>>(d.rp, d.col, d.row, ovf, n1, ctr + 7, ovf2, ctr + 2, iq);
+    if (ineq)
+      k_edge4_wg<0, true><<<grid2, kBlock, 0, c->stream>>>(d.rp, d.col, d.row, ovf, n1, ctr + 7, ovf2, ctr + 2, iq);
+    else
+      k_edge4_wg<0, false><<<grid2, kBlock, 0, c->stream>>>(d.rp, d.col, d.row, ovf, n1, ctr + 7, ovf2, ctr + 2, iq);
     timer.stop();
     GJ_HIP(hipGetLastError());
     left = ovf2;

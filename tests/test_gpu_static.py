@@ -276,3 +276,47 @@ def test_clique5_edge_grouped_kernel(gj, ctx):
     less, aut = Q.SYM_LESS["clique5"]
     refu = check(Gu, Gu1, Ou, Q.with_less(Q.CLIQUE5, less))
     assert gj.count(ctx, Gu, gj.Query(ctx, *Q.CLIQUE5))["matches"] == aut * refu["matches"]
+
+
+def test_clique4_edge_grouped_inequalities(gj, ctx):
+    """The edge-grouped 4-clique and diamond kernels with inequalities on a3
+    (each a2's range of S and of its own row narrowed by binary search):
+    hub pairs with 300, 1,030 and 16,400 common neighbours (the wave, the
+    workgroup and the depth-first path) plus an R-MAT background, directed
+    with several inequality sets and undirected with the symmetry-breaking
+    order.  Counts and counters equal the oracle's and the generic path's."""
+    s, d = [], []
+    base = 0
+    for k in (300, 1030, 16400):
+        h0, h1 = base + k + 1, base  # one hub pair with the larger id first
+        common = np.arange(base + 2, base + 2 + k, dtype=np.uint32)[::-1].copy()
+        s += [np.array([h0], np.uint32), np.full(k, h0, np.uint32), np.full(k, h1, np.uint32), common[:-1],
+              common[1:]]
+        d += [np.array([h1], np.uint32), common, common, common[1:], common[:-1]]
+        base += k + 2
+    rs, rd = synth.rmat_draws(11, seed=45)
+    s.append(rs + base)
+    d.append(rd + base)
+    src, dst = np.concatenate(s), np.concatenate(d)
+    n = base + (1 << 11)
+    c1 = gj.Context(0)
+    c1.set_option("strategy", 1)
+    cases = [(Q.CLIQUE4, [(0, 1), (1, 2), (2, 3)]), (Q.CLIQUE4, [(2, 3)]), (Q.CLIQUE4, [(3, 2)]),
+             (Q.CLIQUE4, [(0, 3), (3, 1)]), (Q.CLIQUE4, [(3, 0), (2, 3)]),
+             (Q.DIAMOND, [(0, 3), (3, 2)])]  # the diamond's oracle run alone takes about 12 s here
+    G, O = gj.Graph(ctx, src, dst, n), oracle.Graph(n, src, dst)
+    G1 = gj.Graph(c1, src, dst, n)
+    for q, less in cases:
+        qq = Q.with_less(q, less)
+        ref = oracle.run(O, qq, threads=8)
+        for cc, GG in ((ctx, G), (c1, G1)):
+            r = gj.count(cc, GG, gj.Query(cc, *qq))
+            assert (r["matches"], r["prefixes"], r["extensions"]) == \
+                (ref["matches"], ref["prefixes"], ref["extensions"]), (q, less)
+    u, v = oracle.symmetric_edges(n, src, dst)
+    Gu, Ou = gj.Graph(ctx, src, dst, n, undirected=True), oracle.Graph(n, u, v)
+    qq = Q.with_less(Q.CLIQUE4, Q.SYM_LESS["clique4"][0])
+    ref = oracle.run(Ou, qq, threads=8)
+    assert ref["matches"] > 0
+    r = gj.count(ctx, Gu, gj.Query(ctx, *qq))
+    assert (r["matches"], r["prefixes"], r["extensions"]) == (ref["matches"], ref["prefixes"], ref["extensions"])
