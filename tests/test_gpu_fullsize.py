@@ -60,6 +60,9 @@ def test_rmat22_triangle_count(gj, rmat22, oracle22):
     assert full["prefixes"][2] == len(es) == G.info()["edges"]
     outd = np.bincount(es, minlength=n)
     assert full["extensions"][2] == int(np.minimum(outd[es], outd[ed]).sum())
+    # Generic Join's work bound (Sec. 2.2; Chiba-Nishizeki: 2 a(G) |E|)
+    E0 = len(es)
+    assert full["extensions"][2] <= 2 * int(np.ceil(np.sqrt(2 * E0 + n) / 2)) * E0
     # generic per-candidate kernel on the same graph
     gen = gj.Context(0)
     gen.set_option("strategy", 1)

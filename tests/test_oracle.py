@@ -190,6 +190,39 @@ def test_agm_bound_triangle():
     assert r["prefixes"][3] == r["matches"]
 
 
+def test_gj_work_bound_triangle():
+    """Generic Join's work on the triangle (Sec. 2.2): the count-minimised
+    proposals of stage 2 are the sum over seed edges of min(|out(a0)|,
+    |out(a1)|), at most the sum of the smaller undirected degree, which
+    Chiba and Nishizeki bound by 2 a(G) |E| with arboricity a(G) <=
+    ceil(sqrt(2|E| + n) / 2), so O(|E|^{3/2}).  Checked on a skewed R-MAT
+    graph, a hub with reciprocal arcs to 5,000 leaves that form a path, and
+    a complete digraph; on the hub graph the sum of the larger sets would
+    exceed the bound more than tenfold."""
+    graphs = []
+    s, d = synth.rmat_draws(12, seed=8)
+    graphs.append((1 << 12, s, d))
+    leaves = np.arange(1, 5001, dtype=np.uint32)
+    graphs.append((5001, np.concatenate([np.zeros(5000, np.uint32), leaves, leaves[:-1]]),
+                   np.concatenate([leaves, np.zeros(5000, np.uint32), leaves[1:]])))
+    k = 60
+    a, b = np.meshgrid(np.arange(k, dtype=np.uint32), np.arange(k, dtype=np.uint32))
+    graphs.append((k, a[a != b], b[a != b]))
+    for n, src, dst in graphs:
+        G = oracle.Graph(n, src, dst)
+        E = G.num_edges
+        r = oracle.run(G, Q.TRIANGLE, threads=4)
+        arb = int(np.ceil(np.sqrt(2 * E + n) / 2))
+        assert r["extensions"][2] <= 2 * arb * E, (n, E, r["extensions"][2])
+        assert r["extensions"][2] <= 2 * E ** 1.5 + 2 * E
+        # and the count-minimised sum is what it says: min, not max or sum
+        u = np.unique(np.stack([src, dst], 1)[src != dst], axis=0)
+        out = np.bincount(u[:, 0], minlength=n)
+        assert r["extensions"][2] == int(np.minimum(out[u[:, 0]], out[u[:, 1]]).sum())
+        if n == 5001:
+            assert int(np.maximum(out[u[:, 0]], out[u[:, 1]]).sum()) > 10 * 2 * arb * E
+
+
 # ---------------------------------------------------------------- orders, threads, slices
 def test_order_and_thread_independence():
     s, d = synth.rmat_draws(9, seed=4)
