@@ -137,6 +137,16 @@ __device__ __forceinline__ uint32_t a3_range(const uint32_t* __restrict__ col, u
   return sh - sl;
 }
 
+// x in out(v) = col[b, b + d): v's table in the membership index (hd/hs, the
+// version's forward direction; null when there is none) where the row has
+// one, else a binary search of the row.
+__device__ __forceinline__ bool row_member(const uint32_t* __restrict__ col, const uint64_t* __restrict__ hd,
+                                           const uint32_t* __restrict__ hs, uint32_t v, uint32_t b, uint32_t d,
+                                           uint32_t x) {
+  const uint64_t desc = hd ? hd[v] : 0ull;
+  return desc ? hash_member(hs, desc, x) : contains_u32(col, b, b + d, x);
+}
+
 // SHAPE 0, the transitive 4-clique: S = L = out(a0) & out(a1) and a2 ranges
 // over L.  SHAPE 1, the diamond edge(a0,a1), edge(a0,a2), edge(a1,a3),
 // edge(a2,a3): S = out(a1) and a2 ranges over out(a0).  Either way a3 ranges
@@ -147,7 +157,9 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
                                                          const uint32_t* __restrict__ row, uint64_t m,
                                                          unsigned long long* __restrict__ claim,
                                                          uint32_t* __restrict__ ovf,
-                                                         unsigned long long* __restrict__ acc, EdgeIneq iq) {
+                                                         unsigned long long* __restrict__ acc, EdgeIneq iq,
+                                                         const uint64_t* __restrict__ hd,
+                                                         const uint32_t* __restrict__ hs) {
   __shared__ uint32_t Ls[kCqWaves][kCqCap];
   __shared__ uint32_t Ws[kCqWaves][kCqCap + 1];
   __shared__ uint32_t Rs[kCqWaves][INEQ ? kCqCap : 1];  // per a2: the side and start of its a3 range
@@ -172,13 +184,14 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
       if (SHAPE == 0) {
         // L = out(x0) & out(x1): the shorter list proposes, in order
         const uint32_t sb = d0 <= d1 ? b0 : b1, gb = d0 <= d1 ? b1 : b0, gd = d0 <= d1 ? d1 : d0;
+        const uint32_t gv = d0 <= d1 ? x1 : x0;  // the longer row's vertex
         for (uint32_t t = 0; t < d01; t += 64) {
           uint32_t i = t + lane;
           uint32_t x = 0;
           bool hit = false;
           if (i < d01) {
             x = col[sb + i];
-            hit = contains_u32(col, gb, gb + gd, x);
+            hit = row_member(col, hd, hs, gv, gb, gd, x);
           }
           uint64_t bal = __ballot(hit);
           uint32_t pos = nS + (uint32_t)__popcll(bal & lanemask_lt());
@@ -246,11 +259,11 @@ __global__ void __launch_bounds__(kCqWaves * 64) k_edge4(const uint32_t* __restr
               const uint32_t rel = Rel[i];
               const bool row_side = (rel >> 31) != 0;
               uint32_t a3 = row_side ? col[b2 + (rel & 0x7FFFFFFFu) + t] : S[rel + t];
-              found = row_side ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
+              found = row_side ? lds_contains(S, nS, a3) : row_member(col, hd, hs, a2, b2, d2, a3);
               found = found && ineq3(iq, 3, a3, x0, x1, a2);
             } else {
               uint32_t a3 = d2 < nS ? col[b2 + t] : S[t];  // t < d2, or t < nS
-              found = d2 < nS ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
+              found = d2 < nS ? lds_contains(S, nS, a3) : row_member(col, hd, hs, a2, b2, d2, a3);
               found = found && ineq3(iq, 3, a3, x0, x1, a2);
             }
           }
@@ -287,7 +300,8 @@ __global__ void __launch_bounds__(kBlock) k_edge4_wg(const uint32_t* __restrict_
                                                      const uint32_t* __restrict__ row, const uint32_t* __restrict__ ids,
                                                      uint64_t m, unsigned long long* __restrict__ claim,
                                                      uint32_t* __restrict__ ovf, unsigned long long* __restrict__ acc,
-                                                     EdgeIneq iq) {
+                                                     EdgeIneq iq, const uint64_t* __restrict__ hd,
+                                                     const uint32_t* __restrict__ hs) {
   __shared__ uint32_t S[kCqCapWg];
   __shared__ uint32_t Wp[kCqOffWg + 1];
   __shared__ uint32_t Rel[INEQ ? kCqOffWg : 1];  // per a2: the side and start of its a3 range
@@ -308,12 +322,13 @@ __global__ void __launch_bounds__(kBlock) k_edge4_wg(const uint32_t* __restrict_
     uint32_t nS = 0;
     if (SHAPE == 0) {
       const uint32_t sb = d0 <= d1 ? b0 : b1, gb = d0 <= d1 ? b1 : b0, gd = d0 <= d1 ? d1 : d0;
+      const uint32_t gv = d0 <= d1 ? x1 : x0;  // the longer row's vertex
       for (uint32_t t = 0; t < d01; t += kBlock) {
         uint32_t i = t + tid;
         uint32_t x = 0, hit = 0;
         if (i < d01) {
           x = col[sb + i];
-          hit = contains_u32(col, gb, gb + gd, x) ? 1u : 0u;
+          hit = row_member(col, hd, hs, gv, gb, gd, x) ? 1u : 0u;
         }
         uint32_t tot = 0;
         uint32_t pos = nS + block_excl_scan<kBlock>(hit, tot);
@@ -378,10 +393,10 @@ __global__ void __launch_bounds__(kBlock) k_edge4_wg(const uint32_t* __restrict_
             const uint32_t rel = Rel[i];
             const bool row_side = (rel >> 31) != 0;
             a3 = row_side ? col[b2 + (rel & 0x7FFFFFFFu) + t] : S[rel + t];
-            found = row_side ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
+            found = row_side ? lds_contains(S, nS, a3) : row_member(col, hd, hs, a2, b2, d2, a3);
           } else {
             a3 = d2 < nS ? col[b2 + t] : S[t];
-            found = d2 < nS ? lds_contains(S, nS, a3) : contains_u32(col, b2, b2 + d2, a3);
+            found = d2 < nS ? lds_contains(S, nS, a3) : row_member(col, hd, hs, a2, b2, d2, a3);
           }
           matches += (found && ineq3(iq, 3, a3, x0, x1, a2)) ? 1 : 0;
         }
@@ -407,7 +422,8 @@ __global__ void k_gather_seeds(const uint32_t* __restrict__ ids, uint64_t k, con
 }
 
 void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4], const uint32_t below[4],
-                 KernelTimer& timer, uint64_t out[5], uint32_t*& x0, uint32_t*& x1, uint64_t& n_left) {
+                 const uint64_t* hd, const uint32_t* hs, KernelTimer& timer, uint64_t out[5], uint32_t*& x0,
+                 uint32_t*& x1, uint64_t& n_left) {
   const CsrDir& d = v.d[0];
   // ctr: [0] seed claim, [1] overflow count, [2, 7) counters, [7] second-pass
   // claim, [8] its overflow count
@@ -425,13 +441,13 @@ void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4]
   unsigned grid = (unsigned)c->num_cus * (ineq ? 3 : 4);  // workgroups of 4 waves, 32 KiB of LDS each without
   timer.start();
   if (v.m && shape == 0 && !ineq)
-    k_edge4<0, false><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
+    k_edge4<0, false><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq, hd, hs);
   if (v.m && shape == 0 && ineq)
-    k_edge4<0, true><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
+    k_edge4<0, true><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq, hd, hs);
   if (v.m && shape == 1 && !ineq)
-    k_edge4<1, false><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
+    k_edge4<1, false><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq, hd, hs);
   if (v.m && shape == 1 && ineq)
-    k_edge4<1, true><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
+    k_edge4<1, true><<<grid, kCqWaves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq, hd, hs);
   timer.stop();
   GJ_HIP(hipGetLastError());
   unsigned long long n1 = 0;
@@ -444,9 +460,9 @@ void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4]
     unsigned grid2 = (unsigned)c->num_cus * 2;  // 2 workgroups per CU (68 KiB of LDS each, 72 KiB with INEQ)
     timer.start();
     if (ineq)
-      k_edge4_wg<0, true><<<grid2, kBlock, 0, c->stream>>>(d.rp, d.col, d.row, ovf, n1, ctr + 7, ovf2, ctr + 2, iq);
+      k_edge4_wg<0, true><<<grid2, kBlock, 0, c->stream>>>(d.rp, d.col, d.row, ovf, n1, ctr + 7, ovf2, ctr + 2, iq, hd, hs);
     else
-      k_edge4_wg<0, false><<<grid2, kBlock, 0, c->stream>>>(d.rp, d.col, d.row, ovf, n1, ctr + 7, ovf2, ctr + 2, iq);
+      k_edge4_wg<0, false><<<grid2, kBlock, 0, c->stream>>>(d.rp, d.col, d.row, ovf, n1, ctr + 7, ovf2, ctr + 2, iq, hd, hs);
     timer.stop();
     GJ_HIP(hipGetLastError());
     left = ovf2;

@@ -552,7 +552,18 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
     uint64_t o[5];
     uint32_t *x0 = nullptr, *x1 = nullptr;
     uint64_t left = 0;
-    edge4_count(c, v, shape, P.above.data(), P.below.data(), timer, o, x0, x1, left);
+    // the membership index of the version (built here if missing: a whole
+    // count probes rows many times over), for the probes of rows in memory
+    const uint64_t* hd = nullptr;
+    const uint32_t* hs = nullptr;
+    if (c->hash_index && !v.pmap[0] && !v.pmap[1]) {
+      hash_ensure(c, g, v);
+      if (v.hash_gen == v.gen && v.h[0].desc) {
+        hd = v.h[0].desc;
+        hs = v.h[0].slots;
+      }
+    }
+    edge4_count(c, v, shape, P.above.data(), P.below.data(), hd, hs, timer, o, x0, x1, left);
     gj_stats s{};
     uint64_t mrest = 0;
     if (left) {  // seeds whose common neighbourhood outgrew LDS

@@ -427,8 +427,11 @@ void launch_emit_values(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t 
 // extensions[3], prefixes[2]} of the seeds it finished; the n_left others
 // (their fixed set too large for LDS) are left as seed pairs (x0[i], x1[i]) in
 // context workspace for the depth-first path.
+// hd/hs: the version's forward membership index (row tables for the probes
+// of rows in memory), or null.
 void edge4_count(gj_ctx* c, const Version& v, int shape, const uint32_t above[4], const uint32_t below[4],
-                 KernelTimer& timer, uint64_t out[5], uint32_t*& x0, uint32_t*& x1, uint64_t& n_left);
+                 const uint64_t* hd, const uint32_t* hs, KernelTimer& timer, uint64_t out[5], uint32_t*& x0,
+                 uint32_t*& x1, uint64_t& n_left);
 // clique.hip: the diamond over every forward edge of v by 2-path counts (no
 // inequalities): out = {matches, prefixes[3] = extensions[2], extensions[3]}.
 void diamond2p_count(gj_ctx* c, const Version& v, uint32_t n, KernelTimer& timer, uint64_t out[3]);
