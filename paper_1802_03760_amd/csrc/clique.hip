@@ -548,7 +548,8 @@ __global__ void __launch_bounds__(kC5Waves * 64) k_clique5(const uint32_t* __res
                                                            const uint32_t* __restrict__ row, uint64_t m,
                                                            unsigned long long* __restrict__ claim,
                                                            uint32_t* __restrict__ ovf,
-                                                           unsigned long long* __restrict__ acc, EdgeIneq5 iq) {
+                                                           unsigned long long* __restrict__ acc, EdgeIneq5 iq, const uint64_t* __restrict__ hd,
+                                                       const uint32_t* __restrict__ hs) {
   __shared__ uint32_t Ls[kC5Waves][kC5Cap];
   __shared__ uint32_t Ds[kC5Waves][kC5Cap];
   __shared__ uint32_t Ws[kC5Waves][kC5Cap + 1];
@@ -575,13 +576,14 @@ __global__ void __launch_bounds__(kC5Waves * 64) k_clique5(const uint32_t* __res
       uint32_t nS = 0;
       {
         const uint32_t sb = d0 <= d1 ? b0 : b1, gb = d0 <= d1 ? b1 : b0, gd = d0 <= d1 ? d1 : d0;
+        const uint32_t gv = d0 <= d1 ? x1 : x0;  // the longer row's vertex
         for (uint32_t t = 0; t < d01; t += 64) {
           uint32_t i = t + lane;
           uint32_t x = 0;
           bool hit = false;
           if (i < d01) {
             x = col[sb + i];
-            hit = contains_u32(col, gb, gb + gd, x);
+            hit = row_member(col, hd, hs, gv, gb, gd, x);
           }
           uint64_t bal = __ballot(hit);
           uint32_t pos = nS + (uint32_t)__popcll(bal & lanemask_lt());
@@ -646,7 +648,7 @@ __global__ void __launch_bounds__(kC5Waves * 64) k_clique5(const uint32_t* __res
             found = j < nS && S[j] == a3;
           } else {  // t < nS: L's values against out(a2)
             j = t;
-            found = contains_u32(col, b2, b2 + d2, S[t]);
+            found = row_member(col, hd, hs, a2, b2, d2, S[t]);
           }
           if (found) atomicOr(&M[i * W + (j >> 6)], 1ull << (j & 63));
         }
@@ -697,7 +699,8 @@ __global__ void __launch_bounds__(kBlock) k_clique5_wg(const uint32_t* __restric
                                                        const uint32_t* __restrict__ ids, uint64_t m,
                                                        unsigned long long* __restrict__ claim,
                                                        uint32_t* __restrict__ ovf,
-                                                       unsigned long long* __restrict__ acc, EdgeIneq5 iq) {
+                                                       unsigned long long* __restrict__ acc, EdgeIneq5 iq, const uint64_t* __restrict__ hd,
+                                                       const uint32_t* __restrict__ hs) {
   __shared__ uint32_t S[kC5CapWg];
   __shared__ uint32_t D[kC5CapWg];
   __shared__ uint32_t Wp[kC5CapWg + 1];
@@ -719,12 +722,13 @@ __global__ void __launch_bounds__(kBlock) k_clique5_wg(const uint32_t* __restric
     uint32_t nS = 0;
     {
       const uint32_t sb = d0 <= d1 ? b0 : b1, gb = d0 <= d1 ? b1 : b0, gd = d0 <= d1 ? d1 : d0;
+      const uint32_t gv = d0 <= d1 ? x1 : x0;  // the longer row's vertex
       for (uint32_t t = 0; t < d01; t += kBlock) {
         uint32_t i = t + tid;
         uint32_t x = 0, hit = 0;
         if (i < d01) {
           x = col[sb + i];
-          hit = contains_u32(col, gb, gb + gd, x) ? 1u : 0u;
+          hit = row_member(col, hd, hs, gv, gb, gd, x) ? 1u : 0u;
         }
         uint32_t tot = 0;
         uint32_t pos = nS + block_excl_scan<kBlock>(hit, tot);
@@ -784,7 +788,7 @@ __global__ void __launch_bounds__(kBlock) k_clique5_wg(const uint32_t* __restric
         found = j < nS && S[j] == a3;
       } else {
         j = t;
-        found = contains_u32(col, b2, b2 + d2, S[t]);
+        found = row_member(col, hd, hs, a2, b2, d2, S[t]);
       }
       if (found) atomicOr(&M[i * W + (j >> 6)], 1ull << (j & 63));
     }
@@ -819,7 +823,8 @@ __global__ void __launch_bounds__(kBlock) k_clique5_wg(const uint32_t* __restric
 }
 
 void clique5_count(gj_ctx* c, const Version& v, const uint32_t above[5], const uint32_t below[5],
-                   KernelTimer& timer, uint64_t out[7], uint32_t*& x0, uint32_t*& x1, uint64_t& n_left) {
+                   const uint64_t* hd, const uint32_t* hs, KernelTimer& timer, uint64_t out[7], uint32_t*& x0,
+                   uint32_t*& x1, uint64_t& n_left) {
   const CsrDir& d = v.d[0];
   // ctr: [0] seed claim, [1] overflow count, [2, 9) counters, [9] second-pass
   // claim, [10] its overflow count
@@ -833,7 +838,7 @@ void clique5_count(gj_ctx* c, const Version& v, const uint32_t above[5], const u
   }
   unsigned grid = (unsigned)c->num_cus * 3;  // 3 workgroups of 4 waves per CU (44 KiB of LDS each)
   timer.start();
-  if (v.m) k_clique5<<<grid, kC5Waves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq);
+  if (v.m) k_clique5<<<grid, kC5Waves * 64, 0, c->stream>>>(d.rp, d.col, d.row, v.m, ctr, ovf, ctr + 2, iq, hd, hs);
   timer.stop();
   GJ_HIP(hipGetLastError());
   unsigned long long n1 = 0;
@@ -843,7 +848,8 @@ void clique5_count(gj_ctx* c, const Version& v, const uint32_t above[5], const u
     uint32_t* ovf2 = (uint32_t*)ws_get(c, "c5_ovf2", (n1 + 1) * sizeof(uint32_t));
     unsigned grid2 = (unsigned)c->num_cus * 2;  // 2 workgroups per CU (70 KiB of LDS each)
     timer.start();
-    k_clique5_wg<<<grid2, kBlock, 0, c->stream>>>(d.rp, d.col, d.row, ovf, n1, ctr + 9, ovf2, ctr + 2, iq);
+    k_clique5_wg<<<grid2, kBlock, 0, c->stream>>>(d.rp, d.col, d.row, ovf, n1, ctr + 9, ovf2, ctr + 2, iq, hd,
+                                                  hs);
     timer.stop();
     GJ_HIP(hipGetLastError());
     left = ovf2;

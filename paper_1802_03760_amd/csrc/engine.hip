@@ -500,7 +500,16 @@ void run_static(gj_ctx* c, const gj_graph* g, const gj_query* q, int mode, uint6
     uint64_t o[7];
     uint32_t *x0 = nullptr, *x1 = nullptr;
     uint64_t left = 0;
-    clique5_count(c, v, P.above.data(), P.below.data(), timer, o, x0, x1, left);
+    const uint64_t* hd = nullptr;  // the version's membership index, as for the 4-clique below
+    const uint32_t* hs = nullptr;
+    if (c->hash_index && !v.pmap[0] && !v.pmap[1]) {
+      hash_ensure(c, g, v);
+      if (v.hash_gen == v.gen && v.h[0].desc) {
+        hd = v.h[0].desc;
+        hs = v.h[0].slots;
+      }
+    }
+    clique5_count(c, v, P.above.data(), P.below.data(), hd, hs, timer, o, x0, x1, left);
     gj_stats s{};
     uint64_t mrest = 0;
     if (left) {  // seeds whose common neighbourhood outgrew LDS

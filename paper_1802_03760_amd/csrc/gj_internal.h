@@ -440,7 +440,8 @@ void diamond2p_count(gj_ctx* c, const Version& v, uint32_t n, KernelTimer& timer
 // extensions[4] of the seeds it took; the others (x0, x1: n_left pairs, in
 // workspace) are left to the depth-first path
 void clique5_count(gj_ctx* c, const Version& v, const uint32_t above[5], const uint32_t below[5],
-                   KernelTimer& timer, uint64_t out[7], uint32_t*& x0, uint32_t*& x1, uint64_t& n_left);
+                   const uint64_t* hd, const uint32_t* hs, KernelTimer& timer, uint64_t out[7], uint32_t*& x0,
+                   uint32_t*& x1, uint64_t& n_left);
 // clique.hip: the 4-cycle a0 -> a1 -> a2 -> a3 -> a0 by forward and backward
 // 2-path counts (no inequalities): out = {matches, prefixes[3] =
 // extensions[2], extensions[3]}.
