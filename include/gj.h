@@ -539,7 +539,9 @@ typedef struct {
 gj_status gj_server_create(gj_ctx* ctx, gj_graph* g, uint32_t max_batch, uint64_t mem_budget_bytes,
                            gj_server** out);
 /* Server options: "iteration_work" (>= 0), "heavy_work" (>= 0),
- * "update_priority" (0 or 1), "max_batch" (1..65536) at any time;
+ * "update_priority" (0 or 1; 0 is experimental: under a mixed load of heavy
+ * counts and updates it has stalled served requests for seconds),
+ * "max_batch" (1..65536) at any time;
  * "versions" (2..8), "heavy_lanes" (1..4) and "update_lanes" (0..4) before
  * the first request, else GJ_EBUSY.  GJ_EINVAL for an unknown key or a value
  * out of range. */
