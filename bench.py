@@ -109,7 +109,8 @@ def batched_vs_plain(gj, ctx, G, nreq, seed, log, max_width=1000):
         width = int(np.exp(rng.uniform(0, np.log(max_width))))
         reqs.append((qs[k], lo, min(E, lo + width)))
         rnames.append(k)
-    keys = ("batch_lin", "batch_waves_per_cu", "batch_claim_words", "hash_index", "propose_u", "batch_heavy")
+    keys = ("batch_lin", "batch_waves_per_cu", "batch_claim_words", "hash_index", "propose_u", "batch_heavy",
+            "batch_run", "run_ratio")
     saved = {k: ctx.get_option(k) for k in keys}
     tune = gj.autotune(ctx, G, reqs)
     gj.run_batch(ctx, G, reqs)

@@ -451,12 +451,15 @@ typedef struct {
   double best_ms;              /* wall time of the chosen configuration (-1: cached) */
   int configs_tried;
   int from_cache;
+  uint32_t batch_run;          /* last stages grouped by prefix runs in the fused pipeline (0 or 1) */
+  uint32_t run_ratio;          /* runs stream a prefix's set up to this many times the shared set */
 } gj_tuning;
 
 /* Tunes gj_run_batch on this batch by coordinate descent: the options
  * "hash_index" (0 or 1), "batch_lin" (0, 8, 32, 128), "batch_waves_per_cu"
  * (16, 32, 64), "batch_claim_words" (4, 16, 64), "batch_heavy" (0, 2^22,
- * 2^24, 2^26) and "propose_u" (1, 2, 4) in turn, each value timed (wall time
+ * 2^24, 2^26), "propose_u" (1, 2, 4), and the intersection strategy of the
+ * last stages, "batch_run" (0, 1) and "run_ratio" (1, 2, 8), in turn, each value timed (wall time
  * of the whole call, best of two after a warm-up) with the others at their
  * best so far.  Keeps the fastest in ctx and, if cache_path is not NULL,
  * records it in that JSON file keyed by graph size and query set (a cached

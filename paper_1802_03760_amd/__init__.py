@@ -56,7 +56,7 @@ class Tuning(ctypes.Structure):
                 ("batch_claim_words", ctypes.c_uint32), ("hash_index", ctypes.c_uint32),
                 ("propose_u", ctypes.c_uint32), ("batch_heavy", ctypes.c_uint64),
                 ("best_ms", ctypes.c_double), ("configs_tried", ctypes.c_int),
-                ("from_cache", ctypes.c_int)]
+                ("from_cache", ctypes.c_int), ("batch_run", ctypes.c_uint32), ("run_ratio", ctypes.c_uint32)]
 
 
 class ServerResult(ctypes.Structure):
@@ -539,8 +539,9 @@ def autotune(ctx, graph, requests, cache_path=None):
               "gj_autotune")
     return {"batch_lin": out.batch_lin, "batch_waves_per_cu": out.batch_waves_per_cu,
             "batch_claim_words": out.batch_claim_words, "hash_index": out.hash_index,
-            "propose_u": out.propose_u, "batch_heavy": out.batch_heavy,
-            "best_ms": out.best_ms, "configs_tried": out.configs_tried, "from_cache": bool(out.from_cache)}
+            "propose_u": out.propose_u, "batch_heavy": out.batch_heavy, "batch_run": out.batch_run,
+            "run_ratio": out.run_ratio, "best_ms": out.best_ms, "configs_tried": out.configs_tried,
+            "from_cache": bool(out.from_cache)}
 
 
 def enumerate_rows(ctx, graph, query, seed_lo=0, seed_hi=(1 << 64) - 1, out=None, cap=None):

@@ -2,8 +2,11 @@
 // batch -- the membership test (per-row hash tables or searches), the
 // linear-search threshold, the persistent grid (waves per CU), the candidate
 // chunk a wave claims at a time, the work bound from which a request leaves
-// the fused pipeline for the depth-first path, and the depth-first propose
-// kernel's lockstep width -- keeps the fastest, and caches the choice in a
+// the fused pipeline for the depth-first path, the depth-first propose
+// kernel's lockstep width, and the intersection strategy of the last stages
+// (grouped by prefix runs in the fused pipeline or not, and the size ratio
+// at which a run streams a prefix's set rather than probing it) -- keeps the
+// fastest, and caches the choice in a
 // small JSON file keyed by the graph and the query set.  Every configuration
 // must produce the same counts; a difference is reported as a device error.
 #include <algorithm>
@@ -43,16 +46,18 @@ static std::string tune_key(const gj_graph* g, uint32_t nreq, const gj_query* co
 struct Params {
   uint32_t lin, waves, claim, hash, propose_u;
   uint64_t heavy;
+  uint32_t batch_run, run_ratio;
 };
 
 static bool same(const Params& a, const Params& b) {
   return a.lin == b.lin && a.waves == b.waves && a.claim == b.claim && a.hash == b.hash &&
-         a.propose_u == b.propose_u && a.heavy == b.heavy;
+         a.propose_u == b.propose_u && a.heavy == b.heavy && a.batch_run == b.batch_run &&
+         a.run_ratio == b.run_ratio;
 }
 
 static Params current(const gj_ctx* c) {
   return Params{c->batch_lin, c->batch_waves_per_cu, c->batch_claim_words, (uint32_t)(c->hash_index ? 1 : 0),
-                (uint32_t)c->propose_u, c->batch_heavy};
+                (uint32_t)c->propose_u, c->batch_heavy, (uint32_t)c->batch_run, c->run_ratio};
 }
 
 static void apply(gj_ctx* c, const Params& p) {
@@ -62,9 +67,13 @@ static void apply(gj_ctx* c, const Params& p) {
   c->hash_index = p.hash ? (c->hash_index ? c->hash_index : 1) : 0;
   c->propose_u = (int)p.propose_u;
   c->batch_heavy = p.heavy;
+  c->batch_run = (int)p.batch_run;
+  c->run_ratio = p.run_ratio;
 }
 
-// one entry per line: "key": [lin, waves, claim, hash, propose_u, heavy],
+// one entry per line: "key": [lin, waves, claim, hash, propose_u, heavy,
+// batch_run, run_ratio], (entries of the first six only keep the defaults
+// of the last two)
 static std::map<std::string, Params> read_cache(const char* path) {
   std::map<std::string, Params> m;
   if (!path) return m;
@@ -74,10 +83,12 @@ static std::map<std::string, Params> read_cache(const char* path) {
     size_t a = line.find('"'), b = line.find('"', a + 1), l = line.find('[', b), r = line.find(']', l);
     if (a == std::string::npos || b == std::string::npos || l == std::string::npos || r == std::string::npos)
       continue;
-    unsigned lin = 0, waves = 0, claim = 0, hash = 0, pu = 0;
+    unsigned lin = 0, waves = 0, claim = 0, hash = 0, pu = 0, brun = 1, ratio = 2;
     unsigned long long heavy = 0;
-    if (sscanf(line.c_str() + l + 1, "%u , %u , %u , %u , %u , %llu", &lin, &waves, &claim, &hash, &pu, &heavy) == 6)
-      m[line.substr(a + 1, b - a - 1)] = Params{lin, waves, claim, hash, pu, heavy};
+    const int got = sscanf(line.c_str() + l + 1, "%u , %u , %u , %u , %u , %llu , %u , %u", &lin, &waves, &claim,
+                           &hash, &pu, &heavy, &brun, &ratio);
+    if (got == 6 || got == 8)
+      m[line.substr(a + 1, b - a - 1)] = Params{lin, waves, claim, hash, pu, heavy, brun, ratio};
   }
   return m;
 }
@@ -89,7 +100,8 @@ static void write_cache(const char* path, const std::map<std::string, Params>& m
   for (auto& kv : m) {
     const Params& p = kv.second;
     f << "  \"" << kv.first << "\": [" << p.lin << ", " << p.waves << ", " << p.claim << ", " << p.hash << ", "
-      << p.propose_u << ", " << p.heavy << "]" << (++i < m.size() ? "," : "") << "\n";
+      << p.propose_u << ", " << p.heavy << ", " << p.batch_run << ", " << p.run_ratio << "]"
+      << (++i < m.size() ? "," : "") << "\n";
   }
   f << "}\n";
 }
@@ -102,6 +114,8 @@ static void report(gj_tuning* out, const Params& p, double ms, int tried, int ca
   out->hash_index = p.hash;
   out->propose_u = p.propose_u;
   out->batch_heavy = p.heavy;
+  out->batch_run = p.batch_run;
+  out->run_ratio = p.run_ratio;
   out->best_ms = ms;
   out->configs_tried = tried;
   out->from_cache = cached;
@@ -175,6 +189,8 @@ void autotune(gj_ctx* c, const gj_graph* g, uint32_t nreq, const gj_query* const
   sweep([](Params& p, uint64_t v) { p.claim = (uint32_t)v; }, {4, 16, 64});
   sweep([](Params& p, uint64_t v) { p.heavy = v; }, {0, 1ull << 22, 1ull << 24, 1ull << 26});
   sweep([](Params& p, uint64_t v) { p.propose_u = (uint32_t)v; }, {1, 2, 4});
+  sweep([](Params& p, uint64_t v) { p.batch_run = (uint32_t)v; }, {0, 1});
+  sweep([](Params& p, uint64_t v) { p.run_ratio = (uint32_t)v; }, {1, 2, 8});
   apply(c, best);
   if (cache_path) {
     cache[key] = best;

@@ -118,9 +118,11 @@ def test_autotune_and_cache(gj, tmp_path):
     path = str(tmp_path / "tune.json")
     t = gj.autotune(ctx, G, reqs, path)
     # the starting point, then each parameter's other values (coordinate descent)
-    assert 1 + 1 + 3 + 2 + 2 + 3 + 2 <= t["configs_tried"] <= 1 + 2 + 4 + 3 + 3 + 4 + 3 and not t["from_cache"]
+    assert 1 + 1 + 3 + 2 + 2 + 3 + 2 + 1 + 2 <= t["configs_tried"] <= 1 + 2 + 4 + 3 + 3 + 4 + 3 + 2 + 3 \
+        and not t["from_cache"]
     assert os.path.exists(path)
-    keys = ("batch_lin", "batch_waves_per_cu", "batch_claim_words", "hash_index", "propose_u", "batch_heavy")
+    keys = ("batch_lin", "batch_waves_per_cu", "batch_claim_words", "hash_index", "propose_u", "batch_heavy",
+            "batch_run", "run_ratio")
     opts = {k: ctx.get_option(k) for k in keys}
     assert opts == {k: t[k] for k in keys}  # the context keeps the choice
     counts, _ = gj.run_batch(ctx, G, reqs)
