@@ -102,7 +102,37 @@ __global__ void k_bt_head_reset(BHead* h) {
   }
 }
 
-// P_2 of every request: seed g of the concatenated seed space -> request r
+// P_2 of every request: seed g of the concatenated seed space -> request r.
+// A wave takes blocks of kSeedBlock consecutive seeds: it first counts the
+// block's survivors, reserves their slots with one atomic, then writes them
+// in seed order, so the prefixes of a run (seeds sharing x0) stay together
+// across a block instead of being cut every 64 seeds.
+constexpr uint32_t kSeedSub = 16;               // 64-seed steps per block
+constexpr uint64_t kSeedBlock = 64 * kSeedSub;  // seeds per block
+
+// The seed's request, values, weight, and whether it is in P_2 (keep) and
+// ends its query there (fin).
+__device__ __forceinline__ void seed_at(const BReq* __restrict__ R, const uint64_t* __restrict__ roff,
+                                        uint32_t nreq, uint64_t g, uint32_t& r, uint32_t& x0, uint32_t& x1,
+                                        int8_t& w, bool& keep, bool& fin) {
+  r = (uint32_t)find_segment(roff, 0, nreq, g);
+  const BReq& q = R[r];
+  const uint64_t e = q.seed_lo + (g - roff[r]);
+  x0 = q.seed_row[e];
+  x1 = q.seed_col[e];
+  w = q.seed_w ? q.seed_w[e] : (int8_t)1;
+  keep = true;
+  const uint32_t x[2] = {x0, x1};
+  for (int a = 0; a < q.filt.n && keep; ++a) {
+    const uint32_t key = x[q.filt.key[a]], val = x[q.filt.val[a]];
+    uint32_t lo, hi;
+    row_range(q.filt.rp[a], q.filt.pm[a], key, lo, hi);
+    keep = contains_u32(q.filt.adj[a], lo, hi, val);
+  }
+  keep = keep && seed_ineq_ok(q.filt.above, q.filt.below, x0, x1);
+  fin = q.m == 2;
+}
+
 __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, const uint64_t* __restrict__ roff,
                                                     BHead* __restrict__ H, uint32_t* __restrict__ F,
                                                     uint32_t* __restrict__ rid, int8_t* __restrict__ Fw, uint64_t cap,
@@ -112,47 +142,51 @@ __global__ void __launch_bounds__(kBlock) k_bt_seed(const BReq* __restrict__ R, 
   const uint32_t nreq = H->nreq;
   const uint64_t total = H->seeds;
   const uint64_t nwaves = ((uint64_t)gridDim.x * blockDim.x) >> 6;
+  const int lane = lane_id();
   WaveAcc a_pre, a_cnt, a_ws;
-  for (uint64_t base = (((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6) << 6; base < total;
-       base += nwaves * 64) {
-    uint64_t g = base + lane_id();
-    bool valid = g < total;
-    uint32_t r = 0;
-    bool keep = false, fin = false;
-    uint32_t x0 = 0, x1 = 0;
-    int8_t w = 1;
-    if (valid) {
-      r = (uint32_t)find_segment(roff, 0, nreq, g);
-      const BReq& q = R[r];
-      uint64_t e = q.seed_lo + (g - roff[r]);
-      x0 = q.seed_row[e];
-      x1 = q.seed_col[e];
-      if (q.seed_w) w = q.seed_w[e];
-      keep = true;
-      uint32_t x[2] = {x0, x1};
-      for (int a = 0; a < q.filt.n && keep; ++a) {
-        uint32_t key = x[q.filt.key[a]], val = x[q.filt.val[a]];
-        uint32_t lo, hi;
-        row_range(q.filt.rp[a], q.filt.pm[a], key, lo, hi);
-        keep = contains_u32(q.filt.adj[a], lo, hi, val);
-      }
-      keep = keep && seed_ineq_ok(q.filt.above, q.filt.below, x0, x1);
-      fin = q.m == 2;
+  for (uint64_t blk = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; blk * kSeedBlock < total;
+       blk += nwaves) {
+    const uint64_t b0 = blk * kSeedBlock;
+    // pass 1: counters, and the block's survivors that go on to level 3
+    uint32_t nstore = 0;
+    for (uint32_t k = 0; k < kSeedSub; ++k) {
+      const uint64_t g = b0 + (uint64_t)k * 64 + lane;
+      const bool valid = g < total;
+      uint32_t r = 0, x0 = 0, x1 = 0;
+      int8_t w = 1;
+      bool keep = false, fin = false;
+      if (valid) seed_at(R, roff, nreq, g, r, x0, x1, w, keep, fin);
+      a_pre.add(pre, r * kStat + 2, 1, valid && keep, true);
+      a_cnt.add(cnt, r, 1, valid && keep && fin, true);
+      a_ws.add(wsum, r, (uint64_t)(int64_t)w, valid && keep && fin, false);
+      nstore += (uint32_t)__popcll(__ballot(valid && keep && !fin));
     }
-    a_pre.add(pre, r * kStat + 2, 1, valid && keep, true);
-    a_cnt.add(cnt, r, 1, valid && keep && fin, true);
-    a_ws.add(wsum, r, (uint64_t)(int64_t)w, valid && keep && fin, false);
-    bool store = valid && keep && !fin;
-    uint64_t pos = wave_reserve(&H->nlev[2], store);
-    if (store) {
-      if (pos < cap) {
-        F[pos] = x0;
-        F[cap + pos] = x1;
-        rid[pos] = r;
-        Fw[pos] = w;
-      } else {
-        atomicOr(&H->overflow, 1u);
+    if (nstore == 0) continue;
+    uint64_t base = 0;
+    if (lane == 0) base = atomicAdd(&H->nlev[2], (unsigned long long)nstore);
+    base = shfl_u64(base, 0);
+    // pass 2: the survivors in seed order
+    for (uint32_t k = 0; k < kSeedSub; ++k) {
+      const uint64_t g = b0 + (uint64_t)k * 64 + lane;
+      const bool valid = g < total;
+      uint32_t r = 0, x0 = 0, x1 = 0;
+      int8_t w = 1;
+      bool keep = false, fin = false;
+      if (valid) seed_at(R, roff, nreq, g, r, x0, x1, w, keep, fin);
+      const bool store = valid && keep && !fin;
+      const uint64_t bal = __ballot(store);
+      if (store) {
+        const uint64_t pos = base + (uint64_t)__popcll(bal & lanemask_lt());
+        if (pos < cap) {
+          F[pos] = x0;
+          F[cap + pos] = x1;
+          rid[pos] = r;
+          Fw[pos] = w;
+        } else {
+          atomicOr(&H->overflow, 1u);
+        }
       }
+      base += (uint64_t)__popcll(bal);
     }
   }
   a_pre.flush(pre);
