@@ -669,7 +669,18 @@ void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t
   uint64_t cap = c->batch_cap;
   unsigned grid = (unsigned)c->num_cus * (c->batch_waves_per_cu / 4 > 0 ? c->batch_waves_per_cu / 4 : 1);
   Impl& s = *p;
-  const bool runs = c->batch_run != 0;
+  // the run kernels enter the captured pipeline once a batch has a request
+  // whose last stage they can take (static counts; a context that only runs
+  // signed delta batches never allocates their buffers), and stay
+  auto groupable = [&](const ReqSpec& r) {
+    RunDesc rd;
+    return !r.w && r.P.m >= 3 && c->run_stage && c->strategy != 1 && run_desc(stage_desc(r.P, r.V, r.P.m - 1), rd);
+  };
+  bool runs = false;
+  if (c->batch_run) {
+    runs = s.runs;
+    for (uint32_t i = 0; i < nreq && !runs; ++i) runs = groupable(specs[i]);
+  }
   bool rebuild = nreq > s.max_req || max_m > s.max_m || cap != s.cap || grid != s.grid_cfg || runs != s.runs ||
                  !s.exec;
   if (rebuild) {
