@@ -872,9 +872,10 @@ void clique5_count(gj_ctx* c, const Version& v, const uint32_t above[5], const u
 // common out-neighbour a3, counted per a3: with k(a3) the number of 2-paths
 // a0 -> a1 -> a3, a0 contributes the sum of k(a3)^2 (a1 = a2 included, as
 // the join allows).  One workgroup per a0 counts its 2-path endpoints with
-// atomics in a private dense array of n counters, then walks the same
-// 2-paths again taking each count with an exchange to zero (the first visit
-// of an endpoint gets k, later ones 0), which leaves the array clear.  The
+// atomics in a private dense array of n counters, noting each endpoint at its
+// first visit in a private list, then takes each listed endpoint's count
+// with an exchange to zero, which leaves the array clear (one atomic per
+// distinct endpoint instead of a second walk of every 2-path).  The
 // counters are the depth-first evaluation's: extensions[2] = prefixes[3] =
 // sum of d0^2 (a2 is proposed from out(a0) alone), extensions[3] = the sum
 // over (a1, a2) in out(a0)^2 of min(d(a1), d(a2)), from tiles of the
@@ -884,18 +885,24 @@ constexpr uint32_t kDgOff = 1024;   // a1 per offsets chunk
 
 __global__ void __launch_bounds__(kBlock) k_diamond2p(const uint32_t* __restrict__ rp,
                                                       const uint32_t* __restrict__ col, uint32_t n,
-                                                      unsigned int* __restrict__ cnt_all, uint64_t cnt_stride,
-                                                      unsigned long long* __restrict__ claim,
+                                                      unsigned int* __restrict__ cnt_all, uint32_t* __restrict__ list_all,
+                                                      uint64_t cnt_stride, unsigned long long* __restrict__ claim,
                                                       unsigned long long* __restrict__ acc) {
   __shared__ uint32_t DA[kDgTile], DB[kDgTile];
   __shared__ uint32_t Wp[kDgOff + 1];
   __shared__ unsigned long long next;
+  __shared__ uint32_t s_nl;  // endpoints listed for this a0
   unsigned int* cnt = cnt_all + (uint64_t)blockIdx.x * cnt_stride;
+  uint32_t* list = list_all + (uint64_t)blockIdx.x * cnt_stride;
   const uint32_t tid = threadIdx.x;
+  const int lane = lane_id();
   uint64_t matches = 0, sq = 0, ext3 = 0;
   for (;;) {
     __syncthreads();
-    if (tid == 0) next = atomicAdd(claim, 1ull);
+    if (tid == 0) {
+      next = atomicAdd(claim, 1ull);
+      s_nl = 0;
+    }
     __syncthreads();
     const unsigned long long a0 = next;
     if (a0 >= n) break;
@@ -929,40 +936,50 @@ __global__ void __launch_bounds__(kBlock) k_diamond2p(const uint32_t* __restrict
         }
       }
     }
-    // the 2-paths, twice: counting, then taking the counts back to zero
-    for (int pass = 0; pass < 2; ++pass) {
-      for (uint32_t c0 = 0; c0 < d0; c0 += kDgOff) {
-        const uint32_t cn = d0 - c0 < kDgOff ? d0 - c0 : kDgOff;
-        uint32_t run = 0;
-        for (uint32_t t = 0; t < cn; t += kBlock) {
-          uint32_t i = t + tid, w = 0;
-          if (i < cn) {
-            uint32_t a1 = col[b0 + c0 + i];
-            w = rp[a1 + 1] - rp[a1];
-          }
-          uint32_t tot = 0;
-          uint32_t ex = block_excl_scan<kBlock>(w, tot);
-          if (i < cn) Wp[i] = run + ex;
-          run += tot;
+    // the 2-paths: count their endpoints, listing each at its first visit
+    for (uint32_t c0 = 0; c0 < d0; c0 += kDgOff) {
+      const uint32_t cn = d0 - c0 < kDgOff ? d0 - c0 : kDgOff;
+      uint32_t run = 0;
+      for (uint32_t t = 0; t < cn; t += kBlock) {
+        uint32_t i = t + tid, w = 0;
+        if (i < cn) {
+          uint32_t a1 = col[b0 + c0 + i];
+          w = rp[a1 + 1] - rp[a1];
         }
-        if (tid == 0) Wp[cn] = run;
-        __syncthreads();
-        for (uint32_t q = tid; q < run; q += kBlock) {
+        uint32_t tot = 0;
+        uint32_t ex = block_excl_scan<kBlock>(w, tot);
+        if (i < cn) Wp[i] = run + ex;
+        run += tot;
+      }
+      if (tid == 0) Wp[cn] = run;
+      __syncthreads();
+      for (uint32_t q0 = 0; q0 < run; q0 += kBlock) {  // the whole wave takes every step
+        const uint32_t q = q0 + tid;
+        uint32_t a3 = 0;
+        bool first = false;
+        if (q < run) {
           uint32_t i = lds_owner(Wp, cn, q);  // i < cn: Wp[cn] = run > q
           uint32_t a1 = col[b0 + c0 + i];
-          uint32_t a3 = col[rp[a1] + (q - Wp[i])];
-          if (pass == 0) {
-            atomicAdd(cnt + a3, 1u);
-          } else {
-            uint64_t k = atomicExch(cnt + a3, 0u);
-            matches += k * k;
-          }
+          a3 = col[rp[a1] + (q - Wp[i])];
+          first = atomicAdd(cnt + a3, 1u) == 0u;
         }
-        __syncthreads();
+        const uint64_t fm = __ballot(first);
+        if (fm) {
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&s_nl, (uint32_t)__popcll(fm));
+          base = __shfl(base, 0, 64);
+          if (first) list[base + (uint32_t)__popcll(fm & lanemask_lt())] = a3;
+        }
       }
-      // every count of this a0 is in before any is taken back
-      __threadfence();
       __syncthreads();
+    }
+    // every count and list entry of this a0 is in before any is taken back
+    __threadfence();
+    __syncthreads();
+    const uint32_t nl = s_nl;
+    for (uint32_t i = tid; i < nl; i += kBlock) {
+      const uint64_t k = atomicExch(cnt + list[i], 0u);
+      matches += k * k;
     }
   }
   uint64_t v[3] = {matches, sq, ext3};
@@ -975,15 +992,17 @@ __global__ void __launch_bounds__(kBlock) k_diamond2p(const uint32_t* __restrict
 
 void diamond2p_count(gj_ctx* c, const Version& v, uint32_t n, KernelTimer& timer, uint64_t out[3]) {
   const CsrDir& d = v.d[0];
-  // one dense counter array per workgroup, at most 16 GiB in all
+  // one dense counter array and one endpoint list per workgroup, at most
+  // 16 GiB in all
   uint64_t per = ((uint64_t)n + 63) / 64 * 64;
-  uint64_t wgs = std::min<uint64_t>((uint64_t)c->num_cus * 2, std::max<uint64_t>(1, (16ull << 30) / (per * 4)));
+  uint64_t wgs = std::min<uint64_t>((uint64_t)c->num_cus * 2, std::max<uint64_t>(1, (16ull << 30) / (per * 8)));
   unsigned int* cnt = (unsigned int*)ws_get(c, "dg_cnt", wgs * per * sizeof(unsigned int));
+  uint32_t* list = (uint32_t*)ws_get(c, "dg_list", wgs * per * sizeof(uint32_t));
   unsigned long long* ctr = (unsigned long long*)ws_get(c, "dg_ctr", 4 * sizeof(unsigned long long));
   GJ_HIP(hipMemsetAsync(cnt, 0, wgs * per * sizeof(unsigned int), c->stream));
   GJ_HIP(hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), c->stream));
   timer.start();
-  k_diamond2p<<<(unsigned)wgs, kBlock, 0, c->stream>>>(d.rp, d.col, n, cnt, per, ctr, ctr + 1);
+  k_diamond2p<<<(unsigned)wgs, kBlock, 0, c->stream>>>(d.rp, d.col, n, cnt, list, per, ctr, ctr + 1);
   timer.stop();
   GJ_HIP(hipGetLastError());
   unsigned long long h[4];
