@@ -200,6 +200,11 @@ const char* gj_last_error(const gj_ctx* ctx);
  *   "run_reuse"     run_stage: a staged run also has at least this many
  *                   times as many candidates as its smallest shared set
  *                   holds values (default 4, 1..1024)
+ *   "run_big"       run_stage: 1 (default) stages shared sets of up to
+ *                   24,576 values in the large workgroup shape (a whole CU's
+ *                   LDS); 0 stages only those of up to 4,096 (the server's
+ *                   light lane, whose kernels share the device with other
+ *                   lanes)
  *   "run_task_work" run_stage: a run's prefixes are cut into tasks of about
  *                   this many candidates plus 8 per value the build reads
  *                   (default 2^15, >= 1)

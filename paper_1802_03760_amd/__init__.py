@@ -503,7 +503,8 @@ class Server(_Owner):
         return {"kind": r.kind, "status": r.status, "count": int(r.count),
                 "count_delta": [int(r.count_delta[i]) for i in range(r.nq)], "version": int(r.version),
                 "batch_size": int(r.batch_size), "latency_ms": (r.done_ns - r.submit_ns) * 1e-6,
-                "queue_ms": (r.start_ns - r.submit_ns) * 1e-6, "service_ms": (r.done_ns - r.start_ns) * 1e-6}
+                "queue_ms": (r.start_ns - r.submit_ns) * 1e-6, "service_ms": (r.done_ns - r.start_ns) * 1e-6,
+                "submit_ns": int(r.submit_ns), "start_ns": int(r.start_ns), "done_ns": int(r.done_ns)}
 
     def stats(self):
         s = ServerStats()

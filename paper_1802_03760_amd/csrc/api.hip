@@ -1,5 +1,6 @@
 // C ABI of libgj.so (declared in include/gj.h): argument checks, device
 // memory, error reporting.  The computation lives in the other sources.
+#include <algorithm>
 #include <chrono>
 #include <cstring>
 #include <new>
@@ -60,6 +61,19 @@ void* ws_get(gj_ctx* c, const std::string& name, size_t bytes) {
   DevBuf& b = c->ws[name];
   if (bytes <= b.bytes && b.p) return b.p;
   size_t want = bytes + bytes / 8 + 256;
+  if (b.p && b.bytes <= kWsRetireMax) {
+    // A small buffer that grows is retired, not freed: freeing synchronises
+    // the device (every stream, other threads' included), which would stall
+    // a server's other lanes behind this context's growth.  Growth at least
+    // doubles, so the retired buffers of a name total at most its final
+    // size; they are freed with the context.
+    want = std::max<size_t>(want, 2 * b.bytes);
+    void* np = dev_alloc(c, want);
+    c->ws_retired.push_back(b.p);
+    b.p = np;
+    b.bytes = want;
+    return b.p;
+  }
   if (b.p) {
     GJ_HIP(hipStreamSynchronize(c->stream));
     dev_free(c, b.p);
@@ -202,6 +216,7 @@ void gj_ctx_destroy(gj_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   gj::batch_destroy(c);
   for (auto& kv : c->ws) gj::dev_free(c, kv.second.p);
+  for (void* p : c->ws_retired) gj::dev_free(c, p);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -271,6 +286,9 @@ gj_status gj_ctx_set_option(gj_ctx* c, const char* key, int64_t value) {
     } else if (k == "batch_claim_words") {
       GJ_CHECK(value >= 1 && value <= 4096, GJ_EINVAL, "batch_claim_words out of range");
       c->batch_claim_words = (uint32_t)value;
+    } else if (k == "run_big") {
+      GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "run_big must be 0 or 1");
+      c->run_big = (int)value;
     } else if (k == "batch_run") {
       GJ_CHECK(value == 0 || value == 1, GJ_EINVAL, "batch_run must be 0 or 1");
       c->batch_run = (int)value;
@@ -316,6 +334,7 @@ gj_status gj_ctx_get_option(gj_ctx* c, const char* key, int64_t* value) {
     else if (k == "batch_waves_per_cu") *value = c->batch_waves_per_cu;
     else if (k == "batch_claim_words") *value = c->batch_claim_words;
     else if (k == "batch_run") *value = c->batch_run;
+    else if (k == "run_big") *value = c->run_big;
     else if (k == "batch_fallbacks") *value = (int64_t)c->batch_fallbacks;
     else if (k == "delta_fused") *value = c->delta_fused;
     else if (k == "delta_owner_min") *value = (int64_t)c->delta_owner_min;
@@ -782,6 +801,7 @@ void copy_options(gj_ctx* dst, const gj_ctx* src) {
   dst->batch_waves_per_cu = src->batch_waves_per_cu;
   dst->batch_claim_words = src->batch_claim_words;
   dst->batch_run = src->batch_run;
+  dst->run_big = src->run_big;
   dst->batch_cap = src->batch_cap;
   dst->delta_fused = src->delta_fused;
   dst->delta_owner_min = src->delta_owner_min;

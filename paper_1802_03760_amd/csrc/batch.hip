@@ -604,9 +604,11 @@ struct BatchExec::Impl {
   unsigned long long* wsum() { return d_stat + max_req; }
   unsigned long long* pre() { return d_stat + 2ull * max_req; }
   unsigned long long* ext() { return d_stat + 2ull * max_req + (uint64_t)max_req * kStat; }
+  std::vector<size_t> alloc_bytes;
   void* alloc(size_t b) {
     void* p = dev_alloc(owner, b);
     allocs.push_back(p);
+    alloc_bytes.push_back(b);
     return p;
   }
   ~Impl() {
@@ -728,6 +730,11 @@ void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t
         t.rg_w = (int8_t*)t.alloc(rcap);
       }
     }
+    // touch every buffer once now (a fill at copy speed, outside the
+    // capture), so that the first use of freshly mapped device memory is
+    // paid at the build, not in a replay
+    for (size_t i = 0; i < t.allocs.size(); ++i)
+      GJ_HIP(hipMemsetAsync(t.allocs[i], 0, t.alloc_bytes[i], c->stream));
     t.h_stage_bytes = sizeof(BHead) + sizeof(BReq) * mr + sizeof(uint64_t) * (mr + 1) +
                       sizeof(unsigned long long) * t.stat_words() + sizeof(RunDesc) * t.rdt_entries();
     GJ_HIP(hipHostMalloc(&t.h_stage, t.h_stage_bytes, hipHostMallocDefault));
@@ -776,6 +783,7 @@ void BatchExec::run_specs(gj_ctx* c, const std::vector<ReqSpec>& specs, uint64_t
       rd.min_work = c->run_min_work;
       rd.task_work = c->run_task_work;
       rd.reuse = c->run_reuse;
+      rd.big = c->run_big ? 1u : 0u;
       hh->runon[j] = 1;
     }
     GJ_HIP(hipMemcpyAsync(t.d_rdt, hd, sizeof(RunDesc) * (uint64_t)nreq * kStat, hipMemcpyHostToDevice,

@@ -190,6 +190,9 @@ struct gj_ctx {
   int strategy = 0;
   int num_cus = 256;
   std::map<std::string, gj::DevBuf> ws;
+  // workspace buffers replaced by larger ones (ws_get), kept until the
+  // context is destroyed
+  std::vector<void*> ws_retired;
   // While `on`, ws_get hands out named pieces of [base, base + size) (the
   // allocation-free entry point's scratch) and dev_alloc refuses to run.
   struct Arena {
@@ -240,6 +243,7 @@ struct gj_ctx {
   uint64_t run_task_work = 1ull << 15;  // candidates per task of a staged run beyond its build
   uint64_t run_stage_min = 1ull << 22;  // least candidates of a stage taken by the run kernels
   uint32_t run_reuse = 4;          // staged runs: candidates >= this x the shared set bound
+  int run_big = 1;                 // 0: shared sets beyond the small shape's table are not staged
   uint64_t run_min_tasks = 256;    // fewer staged tasks in a stage: the per-candidate kernel takes it
   uint64_t run_tasks = 0;          // tasks of the run kernels on this context
   uint64_t run_tasks_big = 0;      // of those, tasks of the large-set shape
@@ -297,6 +301,8 @@ class KernelTimer {
   size_t n_ = 0;
 };
 
+// workspace buffers up to this size are retired rather than freed when they grow
+constexpr size_t kWsRetireMax = 256ull << 20;
 void* ws_get(gj_ctx* c, const std::string& name, size_t bytes);
 // Device memory through the context's allocator (hipMalloc / hipFree without
 // one).  dev_alloc throws GJ_ENOMEM on failure; dev_free(c, null) is a no-op.

@@ -18,6 +18,7 @@ struct RunDesc {
   uint64_t min_work;   // staged runs: at least this many count-minimised candidates
   uint64_t task_work;  // candidates per task beyond the build's share
   uint32_t reuse;      // staged runs: candidates at least this many times the shared set bound
+  uint32_t big;        // 0: runs whose shared set needs the large shape are not staged
 };
 
 // Whether stage d can run grouped by prefix runs (binary atoms only, at least

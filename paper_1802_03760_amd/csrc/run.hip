@@ -106,7 +106,7 @@ __device__ __forceinline__ void run_plan_one(const uint32_t* __restrict__ F, uin
     }
   }
   uint64_t W = off[e] - off[p];
-  st = B <= kRunCapBig && W >= rd.min_work && W >= (uint64_t)rd.reuse * B;
+  st = B <= (rd.big ? kRunCapBig : kRunCap) && W >= rd.min_work && W >= (uint64_t)rd.reuse * B;
   big = B > kRunCap;
   t = 0;
   if (st) {
@@ -689,6 +689,7 @@ bool run_count(gj_ctx* c, const uint32_t* F, uint64_t stride, uint64_t n, const 
   rd.min_work = c->run_min_work;
   rd.task_work = c->run_task_work;
   rd.reuse = c->run_reuse;
+  rd.big = c->run_big ? 1u : 0u;
   uint32_t* head = (uint32_t*)ws_get(c, "run_head", n * sizeof(uint32_t) + 16);
   uint64_t* hoff = (uint64_t*)ws_get(c, "run_hoff", (n + 1) * sizeof(uint64_t));
   uint32_t* rs = (uint32_t*)ws_get(c, "run_rs", (n + 1) * sizeof(uint32_t));

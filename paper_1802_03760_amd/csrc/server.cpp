@@ -122,6 +122,7 @@ struct gj_server {
   std::vector<std::thread> heavy_workers;
   std::vector<std::unique_ptr<Active>> heavy;  // heavy requests, arrival order (under mu)
   bool light_done = false;                     // the light thread has exited
+  bool light_warm = false;                     // the light lane's fused pipeline is built
   int heavy_lanes = 3;                         // heavy requests run concurrently
   int update_lanes = 2;                        // contexts beside ctx that run an update's dQ_i
   uint64_t heavy_work = 0;                     // estimated work per heavy chunk (0: 64 x iter_work)
@@ -359,8 +360,42 @@ static void snapshot(const gj_server* s, const std::vector<std::unique_ptr<Activ
 
 // Light thread: admission, estimates, and the fused iterations of light
 // requests; heavy requests go to the heavy thread.
+// Builds the light lane's fused pipeline before any request: a batch of two
+// empty 4-clique slices allocates and captures it (level arrays, run
+// buffers), so that the first light iteration does not pay for device
+// allocations of several GB while the other lanes run.  Larger queries
+// rebuild it later.  Best effort: a failure leaves the build to the first
+// iteration.
+// Builds c's fused pipeline for queries of up to m attributes (3 or 4) with
+// a batch of two empty slices.
+static void warm_pipeline(gj_server* s, gj_ctx* c, uint32_t m) {
+  const gj_atom atoms[6] = {{0, 1}, {0, 2}, {1, 2}, {0, 3}, {1, 3}, {2, 3}};
+  const uint8_t order[4] = {0, 1, 2, 3};
+  gj_query* q = nullptr;
+  if (gj_query_register(c, m, atoms, m == 3 ? 3 : 6, order, &q) == GJ_OK) {
+    Version v = s->g->ver[s->cur];
+    const Version* vs[2] = {&v, &v};
+    const gj_query* qs[2] = {q, q};
+    uint64_t lo[2] = {0, 0}, hi[2] = {0, 0}, cnt[2] = {0, 0};
+    gj_stats st[2];
+    (void)count_on_versions(c, s->g, vs, 2, qs, lo, hi, cnt, st);
+    (void)hipStreamSynchronize(c->stream);
+    gj_query_destroy(q);
+  }
+}
+
+static void warm_light(gj_server* s) {
+  warm_pipeline(s, s->cctx, 4);
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->light_warm = true;
+  }
+  s->cv_update.notify_all();
+}
+
 static void count_loop(gj_server* s) {
   (void)hipSetDevice(s->cctx->device);
+  warm_light(s);
   std::vector<std::unique_ptr<Active>> active;  // arrival order
   Version vers[kMaxVersions];
   for (;;) {
@@ -527,7 +562,18 @@ static void update_loop(gj_server* s) {
   // no update pays for their allocation.
   {
     std::unique_lock<std::mutex> lk(s->mu);
-    s->cv_update.wait(lk, [&] { return s->started || s->stop; });
+    // the light lane's pipeline is built before the first update is served,
+    // so a caller that waits for an update has the server warm
+    s->cv_update.wait(lk, [&] { return (s->started && s->light_warm) || s->stop; });
+  }
+  // the fused pipeline of the count-only delta queries, likewise, before the
+  // first update needs it (without the run kernels, which signed delta
+  // seeds never take)
+  if (s->ctx->delta_fused) {
+    const int br = s->ctx->batch_run;
+    s->ctx->batch_run = 0;
+    warm_pipeline(s, s->ctx, 3);
+    s->ctx->batch_run = br;
   }
   {
     const Version& cv = s->g->ver[s->g->cur];
@@ -633,6 +679,16 @@ gj_status gj_server_create(gj_ctx* ctx, gj_graph* g, uint32_t max_batch, uint64_
   }
   gj::copy_options(s->cctx, ctx);
   s->cctx->hash_build = ctx->hash_index >= 2;  // the server reads indexes built elsewhere unless asked
+  // The light lane's fused iterations stage runs in the small shape only: a
+  // large-shape workgroup needs a whole CU's LDS, which the heavy lanes'
+  // kernels rarely leave free, and waiting for one stalled the iteration
+  // (and work queued behind it) for seconds.
+  s->cctx->run_big = 0;
+  // Its iterations are bounded by iteration_work, so levels of 2^24
+  // prefixes suffice (an overflow reruns the iteration depth-first); the
+  // pipeline's buffers scale with this capacity, and every GB of them costs
+  // about 0.1 s to allocate.
+  s->cctx->batch_cap = std::min<uint64_t>(s->cctx->batch_cap, 1ull << 24);
   s->cur = g->cur;
   for (int b = 0; b < kMaxVersions; ++b) {
     s->lo[b] = 1;  // empty
