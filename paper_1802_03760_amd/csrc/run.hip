@@ -40,6 +40,7 @@ struct RunShape<false> {
   static constexpr uint32_t CAP = 4096;
   static constexpr int LOG_SLOTS = 13;
   static constexpr int U = 2;  // windows per wave per step, their loads issued together
+  static constexpr int UF = 3;  // the same in the fused form (fewer live registers elsewhere)
 };
 template <>
 struct RunShape<true> {
@@ -47,6 +48,7 @@ struct RunShape<true> {
   static constexpr uint32_t CAP = 24576;
   static constexpr int LOG_SLOTS = 15;
   static constexpr int U = 1;
+  static constexpr int UF = 1;
 };
 constexpr uint32_t kRunCap = RunShape<false>::CAP;
 constexpr uint32_t kRunCapBig = RunShape<true>::CAP;
@@ -370,7 +372,7 @@ __global__ void __launch_bounds__(RunShape<BIG>::NT) __attribute__((amdgpu_waves
                                                                  unsigned long long* __restrict__ fpre,
                                                                  unsigned long long* __restrict__ fws) {
   constexpr int kRunNT = RunShape<BIG>::NT;
-  constexpr int kRunU = RunShape<BIG>::U;
+  constexpr int kRunU = FUSED ? RunShape<BIG>::UF : RunShape<BIG>::U;
   constexpr int kRunLogSlots = RunShape<BIG>::LOG_SLOTS;
   __shared__ __attribute__((aligned(16))) uint32_t H[1 << kRunLogSlots];
   // S's values: in LDS (small shape) or this workgroup's global buffer
