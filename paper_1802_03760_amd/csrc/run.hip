@@ -48,7 +48,7 @@ struct RunShape<true> {
   static constexpr uint32_t CAP = 24576;
   static constexpr int LOG_SLOTS = 15;
   static constexpr int U = 1;
-  static constexpr int UF = 1;
+  static constexpr int UF = 2;
 };
 constexpr uint32_t kRunCap = RunShape<false>::CAP;
 constexpr uint32_t kRunCapBig = RunShape<true>::CAP;
