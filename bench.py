@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM traffic of one k_owner_count launch on this workload, from two rocprofv3
 # --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by a 1 GiB device copy in the same
 # run; valid only for the kernel source it was measured on (sha256 prefix).
-MEASURED_TRAFFIC = {"owner.hip": "407f8e26f445ba99", "bytes": 126.26e9 + 1.003e9}
+MEASURED_TRAFFIC = {"owner.hip": "eefc393fc46fda14", "bytes": 126.29e9 + 1.003e9}
 TRIANGLE = (3, [(0, 1), (1, 2), (0, 2)], [0, 1, 2])
 
 
