@@ -304,3 +304,40 @@ def test_batched_runs_off_equals_on(gj):
         res[on] = (a, b)
     assert res[0] == res[1]
     assert sum(res[1][0][0]) > 0 and sum(res[1][1][0]) > 0
+
+
+def test_small_shape_only(gj):
+    """run_big 0 (the server's light lane): runs whose shared set needs the
+    large shape stay with the per-candidate kernel, the rest are staged in
+    the small shape; counts and counters equal the oracle's on the depth-first
+    path and in the fused pipeline, and the large shape takes no task."""
+    rng = np.random.default_rng(21)
+    n = 9000
+    src, dst = [], []
+    for h, k in ((0, 5000), (1, 4500)):
+        nb = rng.choice(np.arange(2, n), k, replace=False)
+        src += [h] * k
+        dst += list(nb)
+    src += [0, 1]
+    dst += [1, 0]
+    s2, d2 = synth.rmat_draws(12, seed=22)
+    src = np.concatenate([np.array(src, np.uint32), s2 % n]).astype(np.uint32)
+    dst = np.concatenate([np.array(dst, np.uint32), d2 % n]).astype(np.uint32)
+    c = run_ctx(gj, task_work=4096)
+    c.set_option("run_big", 0)
+    assert c.get_option("run_big") == 0
+    c.set_option("batch_heavy", 0)
+    G, O = gj.Graph(c, src, dst, n), oracle.Graph(n, src, dst)
+    big0, t0 = c.get_option("run_tasks_big"), c.get_option("run_tasks")
+    for q in (Q.TRIANGLE, Q.CLIQUE4, Q.DIAMOND):
+        check(gj, c, G, O, q)
+    assert c.get_option("run_tasks") > t0 and c.get_option("run_tasks_big") == big0
+    E = O.num_edges
+    qs = {k: gj.Query(c, *Q.ALL[k]) for k in ("clique4", "diamond", "triangle")}
+    reqs = [(qs[k], lo, min(E, lo + 3000)) for k in qs for lo in (0, E // 2)]
+    counts, stats = gj.run_batch(c, G, reqs)
+    for (qh, lo, hi), (k, _), cnt, st in zip(reqs, [(k, 0) for k in qs for _ in (0, 1)], counts, stats):
+        ref = oracle.run(O, Q.ALL[k], seed_lo=lo, seed_hi=hi, threads=8)
+        assert (cnt, st["prefixes"], st["extensions"]) == (ref["matches"], ref["prefixes"], ref["extensions"]), (k, lo)
+    with pytest.raises(gj.GJError):
+        c.set_option("run_big", 2)
