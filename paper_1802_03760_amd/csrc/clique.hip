@@ -1015,9 +1015,10 @@ void diamond2p_count(gj_ctx* c, const Version& v, uint32_t n, KernelTimer& timer
 // matches from a0 pair each forward 2-path a0 -> a1 -> a2 with each backward
 // one a2 -> a3 -> a0 of the same a2, so a0 contributes the sum over a2 of
 // k(a2) k'(a2) (forward times backward 2-path counts).  One workgroup per a0
-// adds the forward 2-paths' endpoints into its private counters, walks the
-// backward 2-paths (through the reverse index) summing the counters they
-// reach, and walks the forward ones again to clear them.  Counters as the
+// adds the forward 2-paths' endpoints into its private counters (listing
+// each endpoint at its first visit), walks the backward 2-paths (through
+// the reverse index) summing the counters they reach, and clears the listed
+// endpoints.  Counters as the
 // depth-first evaluation: extensions[2] = prefixes[3] = the forward 2-paths
 // (a2 is proposed from out(a1) alone), extensions[3] = the sum over them of
 // min(|out(a2)|, |in(a0)|).
@@ -1058,24 +1059,29 @@ __global__ void __launch_bounds__(kBlock) k_cycle4_2p(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ colf,
                                                       const uint32_t* __restrict__ rpr,
                                                       const uint32_t* __restrict__ colr, uint32_t n,
-                                                      unsigned int* __restrict__ cnt_all, uint64_t cnt_stride,
-                                                      unsigned long long* __restrict__ claim,
+                                                      unsigned int* __restrict__ cnt_all, uint32_t* __restrict__ list_all,
+                                                      uint64_t cnt_stride, unsigned long long* __restrict__ claim,
                                                       unsigned long long* __restrict__ acc) {
   __shared__ uint32_t Wp[kDgOff + 1];
   __shared__ unsigned long long next;
+  __shared__ uint32_t s_nl;  // forward endpoints listed for this a0
   unsigned int* cnt = cnt_all + (uint64_t)blockIdx.x * cnt_stride;
+  uint32_t* list = list_all + (uint64_t)blockIdx.x * cnt_stride;
   const uint32_t tid = threadIdx.x;
   uint64_t matches = 0, paths = 0, ext3 = 0;
   for (;;) {
     __syncthreads();
-    if (tid == 0) next = atomicAdd(claim, 1ull);
+    if (tid == 0) {
+      next = atomicAdd(claim, 1ull);
+      s_nl = 0;
+    }
     __syncthreads();
     const unsigned long long a0 = next;
     if (a0 >= n) break;
     const uint32_t bo = rpf[a0], dout = rpf[a0 + 1] - bo, bi = rpr[a0], din = rpr[a0 + 1] - bi;
     if (dout == 0) continue;
     walk_2paths(colf, bo, dout, rpf, colf, Wp, [&](uint32_t, uint32_t a2) {
-      atomicAdd(cnt + a2, 1u);
+      if (atomicAdd(cnt + a2, 1u) == 0u) list[atomicAdd(&s_nl, 1u)] = a2;  // first visit: listed
       uint32_t d2 = rpf[a2 + 1] - rpf[a2];
       ext3 += d2 < din ? d2 : din;
       paths += 1;
@@ -1087,9 +1093,10 @@ __global__ void __launch_bounds__(kBlock) k_cycle4_2p(const uint32_t* __restrict
         matches += __hip_atomic_load(cnt + a2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);  // at L2
       });
     __syncthreads();
-    walk_2paths(colf, bo, dout, rpf, colf, Wp, [&](uint32_t, uint32_t a2) {
-      __hip_atomic_store(cnt + a2, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    });
+    // clear the listed endpoints (one store each instead of a third walk)
+    const uint32_t nl = s_nl;
+    for (uint32_t i = tid; i < nl; i += kBlock)
+      __hip_atomic_store(cnt + list[i], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __threadfence();
     __syncthreads();
   }
@@ -1103,14 +1110,16 @@ __global__ void __launch_bounds__(kBlock) k_cycle4_2p(const uint32_t* __restrict
 
 void cycle4_2p_count(gj_ctx* c, const Version& v, uint32_t n, KernelTimer& timer, uint64_t out[3]) {
   uint64_t per = ((uint64_t)n + 63) / 64 * 64;
-  uint64_t wgs = std::min<uint64_t>((uint64_t)c->num_cus * 2, std::max<uint64_t>(1, (16ull << 30) / (per * 4)));
+  // one counter array and one endpoint list per workgroup, at most 16 GiB in all
+  uint64_t wgs = std::min<uint64_t>((uint64_t)c->num_cus * 2, std::max<uint64_t>(1, (16ull << 30) / (per * 8)));
   unsigned int* cnt = (unsigned int*)ws_get(c, "dg_cnt", wgs * per * sizeof(unsigned int));
+  uint32_t* list = (uint32_t*)ws_get(c, "dg_list", wgs * per * sizeof(uint32_t));
   unsigned long long* ctr = (unsigned long long*)ws_get(c, "dg_ctr", 4 * sizeof(unsigned long long));
   GJ_HIP(hipMemsetAsync(cnt, 0, wgs * per * sizeof(unsigned int), c->stream));
   GJ_HIP(hipMemsetAsync(ctr, 0, 4 * sizeof(unsigned long long), c->stream));
   timer.start();
-  k_cycle4_2p<<<(unsigned)wgs, kBlock, 0, c->stream>>>(v.d[0].rp, v.d[0].col, v.d[1].rp, v.d[1].col, n, cnt, per,
-                                                        ctr, ctr + 1);
+  k_cycle4_2p<<<(unsigned)wgs, kBlock, 0, c->stream>>>(v.d[0].rp, v.d[0].col, v.d[1].rp, v.d[1].col, n, cnt, list,
+                                                        per, ctr, ctr + 1);
   timer.stop();
   GJ_HIP(hipGetLastError());
   unsigned long long h[4];
