@@ -108,6 +108,38 @@ def test_rmat22_four_clique_and_diamond_slices(gj, rmat22, oracle22):
     ctx.close()
 
 
+@pytest.mark.timeout(900)
+def test_rmat20_full_sorted_enumeration(gj):
+    """Every row of the R-MAT-20 triangle enumeration (570,418,567 sorted
+    rows) against the oracle's, element by element, in 64 seed slices that
+    cover the whole edge range; the slices' rows are each sorted and follow
+    one another in order, so their concatenation is the full sorted
+    enumeration, and its length is the whole count."""
+    src, dst = synth.rmat_draws(20, seed=0)
+    n = 1 << 20
+    ctx = gj.Context(0)
+    G = gj.Graph(ctx, src, dst, n)
+    O = oracle.Graph(n, src, dst)
+    E = O.num_edges
+    q = gj.Query(ctx, *Q.TRIANGLE)
+    full = gj.count(ctx, G, q)["matches"]
+    total, prev = 0, None
+    for i in range(64):
+        lo, hi = E * i // 64, E * (i + 1) // 64
+        ref = oracle.run(O, Q.TRIANGLE, collect=True, seed_lo=lo, seed_hi=hi, threads=16)
+        st, rows = gj.enumerate_rows(ctx, G, q, lo, hi)
+        assert st["matches"] == ref["matches"] and np.array_equal(rows, ref["rows"]), (i, lo, hi)
+        if len(rows):
+            if prev is not None:
+                assert tuple(prev) < tuple(rows[0]), i  # slices follow one another in sorted order
+            prev = rows[-1].copy()
+        total += st["matches"]
+        del ref, rows
+    assert total == full == 570418567
+    G.close()
+    ctx.close()
+
+
 def test_rmat20_enumerate_slices(gj):
     """R-MAT scale 20 triangle count and enumeration (sorted rows) on
     sampled seed slices; the full count through both kernels."""
