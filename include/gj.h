@@ -516,6 +516,12 @@ gj_status gj_autotune(gj_ctx* ctx, const gj_graph* g, uint32_t nreq, const gj_qu
  * one host thread each; smaller batches take ctx alone.  With iteration_work
  * 0 requests run whole, in arrival order, in the fused pipeline.  Results
  * equal gj_run / gj_apply_updates issued alone in submission order.
+ * Start-up: the light context's fused pipeline (levels of at most 2^24
+ * prefixes, last stages grouped by runs in the small shape only, see
+ * "run_big") is built as soon as the server is created, and ctx's delta
+ * pipeline before the first update is served, so a caller that submits and
+ * waits for an empty update batch before timing has every large allocation
+ * behind it.
  * gj_server_create returns GJ_EDEVICE / GJ_ENOMEM if the light context or
  * the threads cannot be created; the first submit returns GJ_EDEVICE if no
  * heavy lane can be created. */
